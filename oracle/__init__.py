@@ -1,0 +1,374 @@
+"""Plain FP64 CPU oracle for the hybrid symplectic N-body step of Grimm &
+Stadel, "The GENGA Code" (arXiv:1404.2324).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this package.  It shares no
+code with the GPU library: the arithmetic lives in ``genga_oracle.c``
+(compiled with gcc, -ffp-contract=off), this module only marshals numpy
+arrays.
+
+Parity status (see the C source for the passage each routine follows):
+  changeover K, kick, Sun kick, Kepler drift, Hermite test, grouping,
+  energy / angular momentum, tangent-linear model: pinned by closed forms,
+  invariants and brute force in ``tests/test_oracle_pins.py``.
+  BS sequence / error norm / tolerance, the Hill-radius reading and the
+  strictness of the encounter threshold: parity unpinned against the paper
+  (readings), pinned only by the physics invariants.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "genga_oracle.c")
+_LIB = os.path.join(_HERE, "libgenga_oracle.so")
+
+GO_OK, GO_EINVAL, GO_EOVERFLOW, GO_EKEPLER, GO_EBS, GO_EADJ_ENCOUNTER = 0, -1, -3, -4, -5, -6
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/libgenga_oracle.so``."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd, cwd=_HERE)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_double), ("m0", ctypes.c_double),
+                ("dt", ctypes.c_double), ("n1", ctypes.c_double),
+                ("n2", ctypes.c_double), ("pf", ctypes.c_double),
+                ("bs_tol", ctypes.c_double), ("bs_max_depth", ctypes.c_int),
+                ("kepler_max_iter", ctypes.c_int),
+                ("encounter_free", ctypes.c_int), ("pad_", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "steps", "n_cand", "n_enc", "n_miss", "n_groups", "max_group",
+        "bs_substeps", "enc_total", "miss_total", "kepler_iter_max",
+        "tp_enc", "tp_enc_total")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+def params(G=1.0, m0=1.0, dt=0.01 * 2 * np.pi, n1=3.0, n2=0.4, pf=3.0,
+           bs_tol=1e-13, bs_max_depth=20, kepler_max_iter=40,
+           encounter_free=0) -> Params:
+    return Params(G, m0, dt, n1, n2, pf, bs_tol, bs_max_depth, kepler_max_iter,
+                  encounter_free, 0)
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_U8 = ctypes.POINTER(ctypes.c_uint8)
+_P = ctypes.POINTER(Params)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        i64, i32 = ctypes.c_int64, ctypes.c_int
+        sig = {
+            "go_changeover": (None, [ctypes.c_double, _D, _D]),
+            "go_rcrit": (None, [_P, i32, _D, _D, _D, _D]),
+            "go_accel": (None, [_P, i32, _D, _D, _D, _D]),
+            "go_sun_drift": (None, [_P, i32, _D, _D, _D, ctypes.c_double]),
+            "go_kepler": (i32, [ctypes.c_double, _D, _D, ctypes.c_double, _D, _D,
+                                i32, ctypes.POINTER(ctypes.c_int)]),
+            "go_stumpff": (None, [ctypes.c_double, _D]),
+            "go_hermite_dmin2": (ctypes.c_double, [ctypes.c_double, _D, _D, _D, _D]),
+            "go_groups": (i32, [i32, i32, _I32, _I32]),
+            "go_bs_group": (i32, [_P, i32, _D, _D, _D, _D, ctypes.c_double,
+                                  ctypes.POINTER(i64)]),
+            "go_energy": (None, [_P, i32, _D, _D, _D, _D, _D]),
+            "go_helio_to_dem": (None, [_P, i32, _D, _D]),
+            "go_dem_to_helio": (None, [_P, i32, _D, _D]),
+            "go_massive_init": (i32, [_P, i32, _D, _D, _D, _D, _U8]),
+            "go_massive_step": (i32, [_P, i32, _D, _D, _D, _D, _U8, i64,
+                                      ctypes.POINTER(Stats), i32, _I32, _D, _D,
+                                      ctypes.POINTER(ctypes.c_int)]),
+            "go_tp_init": (i32, [_P, i32, _D, _D, _D, _D, _U8, i64, _D, _D, _U8]),
+            "go_tp_step": (i32, [_P, i32, _D, _D, _D, _D, _U8, i64, _D, _D, _U8,
+                                 i64, ctypes.POINTER(Stats)]),
+            "go_free_step": (i32, [_P, i32, _D, _D, _D, i64]),
+            "go_free_tlm": (i32, [_P, i32, _D, _D, _D, _D, _D, _D, i64, _D, _D,
+                                  _D, _D]),
+            "go_free_adjoint": (i32, [_P, i32, _D, _D, _D, i64, _D, _D, _D, _D,
+                                      _D]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _check(code, what):
+    if code != GO_OK:
+        raise OracleError(code, what)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: oracle error {code}")
+        self.code = code
+
+
+# ---------------------------------------------------------------- blocks ---
+def changeover(y: float):
+    K, dK = ctypes.c_double(), ctypes.c_double()
+    lib().go_changeover(float(y), ctypes.byref(K), ctypes.byref(dK))
+    return K.value, dK.value
+
+
+def rcrit(p: Params, m, x, v):
+    m, x, v = _f64(m), _f64(x, (-1, 3)), _f64(v, (-1, 3))
+    rc = np.zeros(len(m))
+    lib().go_rcrit(ctypes.byref(p), len(m), _d(m), _d(x), _d(v), _d(rc))
+    return rc
+
+
+def accel(p: Params, m, x, rc=None):
+    m, x = _f64(m), _f64(x, (-1, 3))
+    rc = np.zeros(len(m)) if rc is None else _f64(rc)
+    acc = np.zeros_like(x)
+    lib().go_accel(ctypes.byref(p), len(m), _d(m), _d(x), _d(rc), _d(acc))
+    return acc
+
+
+def sun_drift(p: Params, m, x, v, h):
+    m, v = _f64(m), _f64(v, (-1, 3))
+    x = _f64(x, (-1, 3)).copy()
+    lib().go_sun_drift(ctypes.byref(p), len(m), _d(m), _d(x), _d(v), float(h))
+    return x
+
+
+def kepler(mu, x0, v0, dt, max_iter=40):
+    x0, v0 = _f64(x0, (3,)), _f64(v0, (3,))
+    x, v = np.zeros(3), np.zeros(3)
+    it = ctypes.c_int()
+    code = lib().go_kepler(float(mu), _d(x0), _d(v0), float(dt), _d(x), _d(v),
+                           int(max_iter), ctypes.byref(it))
+    _check(code, "kepler")
+    return x, v, it.value
+
+
+def stumpff(z):
+    c = np.zeros(4)
+    lib().go_stumpff(float(z), _d(c))
+    return c
+
+
+def hermite_dmin2(dt, dx0, dv0, dx1, dv1):
+    a = [_f64(t, (3,)) for t in (dx0, dv0, dx1, dv1)]
+    return lib().go_hermite_dmin2(float(dt), *[_d(t) for t in a])
+
+
+def groups(n, pairs):
+    pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    label = np.zeros(n, dtype=np.int32)
+    ng = lib().go_groups(int(n), len(pairs), pairs.ctypes.data_as(_I32),
+                         label.ctypes.data_as(_I32))
+    return ng, label
+
+
+def bs_group(p: Params, m, rc, x, v, H):
+    m, rc = _f64(m), _f64(rc)
+    x, v = _f64(x, (-1, 3)).copy(), _f64(v, (-1, 3)).copy()
+    sub = ctypes.c_int64()
+    code = lib().go_bs_group(ctypes.byref(p), len(m), _d(m), _d(rc), _d(x), _d(v),
+                             float(H), ctypes.byref(sub))
+    _check(code, "bs_group")
+    return x, v, sub.value
+
+
+def energy(p: Params, m, x, v):
+    m, x, v = _f64(m), _f64(x, (-1, 3)), _f64(v, (-1, 3))
+    E = ctypes.c_double()
+    L = np.zeros(3)
+    lib().go_energy(ctypes.byref(p), len(m), _d(m), _d(x), _d(v), ctypes.byref(E), _d(L))
+    return E.value, L
+
+
+def helio_to_dem(p: Params, m, u):
+    m, v = _f64(m), _f64(u, (-1, 3)).copy()
+    lib().go_helio_to_dem(ctypes.byref(p), len(m), _d(m), _d(v))
+    return v
+
+
+def dem_to_helio(p: Params, m, v):
+    m, u = _f64(m), _f64(v, (-1, 3)).copy()
+    lib().go_dem_to_helio(ctypes.byref(p), len(m), _d(m), _d(u))
+    return u
+
+
+# ------------------------------------------------------------ main mode ---
+class MassiveSim:
+    """One planetary system in main mode; state in democratic coordinates."""
+
+    def __init__(self, p: Params, m, x, v, coords="dem"):
+        self.p = p
+        self.m = _f64(m).copy()
+        self.x = _f64(x, (-1, 3)).copy()
+        v = _f64(v, (-1, 3)).copy()
+        if coords == "helio":
+            v = helio_to_dem(p, self.m, v)
+        self.v = v
+        n = len(self.m)
+        self.rc = np.zeros(n)
+        self.cand = np.zeros((n, n), dtype=np.uint8)
+        _check(lib().go_massive_init(ctypes.byref(p), n, _d(self.m), _d(self.x),
+                                     _d(self.v), _d(self.rc),
+                                     self.cand.ctypes.data_as(_U8)), "massive_init")
+        self.stats = Stats()
+        self.enc = np.zeros((0, 2), dtype=np.int32)
+        self.enc_d2 = np.zeros(0)
+        self.enc_rc2 = np.zeros(0)
+
+    @property
+    def n(self):
+        return len(self.m)
+
+    def candidates(self):
+        i, j = np.nonzero(self.cand)
+        return np.stack([i, j], 1).astype(np.int32)
+
+    def step(self, nsteps=1, enc_cap=None):
+        n = self.n
+        cap = n * (n - 1) // 2 if enc_cap is None else enc_cap
+        ij = np.zeros((max(cap, 1), 2), dtype=np.int32)
+        d2 = np.zeros(max(cap, 1))
+        rc2 = np.zeros(max(cap, 1))
+        ne = ctypes.c_int()
+        st = Stats()
+        code = lib().go_massive_step(ctypes.byref(self.p), n, _d(self.m), _d(self.x),
+                                     _d(self.v), _d(self.rc),
+                                     self.cand.ctypes.data_as(_U8), int(nsteps),
+                                     ctypes.byref(st), int(cap),
+                                     ij.ctypes.data_as(_I32), _d(d2), _d(rc2),
+                                     ctypes.byref(ne))
+        self.stats = st
+        k = min(ne.value, cap)
+        self.enc, self.enc_d2, self.enc_rc2 = ij[:k].copy(), d2[:k].copy(), rc2[:k].copy()
+        _check(code, "massive_step")
+        return st.as_dict()
+
+    def energy(self):
+        return energy(self.p, self.m, self.x, self.v)
+
+    def helio_v(self):
+        return dem_to_helio(self.p, self.m, self.v)
+
+
+# --------------------------------------------------- test-particle mode ---
+class TPSim:
+    """Main-mode massive bodies plus massless test particles."""
+
+    def __init__(self, p: Params, m, x, v, xt, vt, coords="dem"):
+        self.p = p
+        self.m = _f64(m).copy()
+        self.x = _f64(x, (-1, 3)).copy()
+        v = _f64(v, (-1, 3)).copy()
+        vt = _f64(vt, (-1, 3)).copy()
+        if coords == "helio":
+            # barycentric shift of the massive bodies applies to the particles
+            u = v.copy()
+            v = helio_to_dem(p, self.m, u)
+            vt = vt + (v[0] - u[0])
+        self.v = v
+        self.xt = _f64(xt, (-1, 3)).copy()
+        self.vt = vt
+        nm, ntp = len(self.m), len(self.xt)
+        self.rc = np.zeros(nm)
+        self.cand = np.zeros((nm, nm), dtype=np.uint8)
+        self.cand_tp = np.zeros((ntp, nm), dtype=np.uint8)
+        _check(lib().go_tp_init(ctypes.byref(p), nm, _d(self.m), _d(self.x), _d(self.v),
+                                _d(self.rc), self.cand.ctypes.data_as(_U8), ntp,
+                                _d(self.xt), _d(self.vt),
+                                self.cand_tp.ctypes.data_as(_U8)), "tp_init")
+        self.stats = Stats()
+
+    def step(self, nsteps=1):
+        st = Stats()
+        code = lib().go_tp_step(ctypes.byref(self.p), len(self.m), _d(self.m), _d(self.x),
+                                _d(self.v), _d(self.rc), self.cand.ctypes.data_as(_U8),
+                                len(self.xt), _d(self.xt), _d(self.vt),
+                                self.cand_tp.ctypes.data_as(_U8), int(nsteps),
+                                ctypes.byref(st))
+        self.stats = st
+        _check(code, "tp_step")
+        return st.as_dict()
+
+
+# ------------------------------------------------------------- batched ---
+def batched_run(p: Params, offsets, m0s, m, x, v, nsteps):
+    """Independent systems, each run as its own main-mode system with its own
+    central mass (the multi-simulation mode of Sec. 3.4)."""
+    x = _f64(x, (-1, 3)).copy()
+    v = _f64(v, (-1, 3)).copy()
+    m = _f64(m)
+    stats = []
+    for s in range(len(offsets) - 1):
+        a, b = int(offsets[s]), int(offsets[s + 1])
+        q = Params.from_buffer_copy(p)
+        q.m0 = float(m0s[s])
+        sim = MassiveSim(q, m[a:b], x[a:b], v[a:b])
+        stats.append(sim.step(nsteps))
+        x[a:b], v[a:b] = sim.x, sim.v
+    return x, v, stats
+
+
+# ------------------------------------------- encounter-free map + adjoint ---
+def free_step(p: Params, m, x, v, nsteps):
+    m = _f64(m)
+    x, v = _f64(x, (-1, 3)).copy(), _f64(v, (-1, 3)).copy()
+    _check(lib().go_free_step(ctypes.byref(p), len(m), _d(m), _d(x), _d(v), int(nsteps)),
+           "free_step")
+    return x, v
+
+
+def free_tlm(p: Params, m, x0, v0, dm, dx0, dv0, nsteps):
+    m, dm = _f64(m), _f64(dm)
+    x0, v0 = _f64(x0, (-1, 3)), _f64(v0, (-1, 3))
+    dx0, dv0 = _f64(dx0, (-1, 3)), _f64(dv0, (-1, 3))
+    xT, vT = np.zeros_like(x0), np.zeros_like(v0)
+    dxT, dvT = np.zeros_like(x0), np.zeros_like(v0)
+    _check(lib().go_free_tlm(ctypes.byref(p), len(m), _d(m), _d(x0), _d(v0), _d(dm),
+                             _d(dx0), _d(dv0), int(nsteps), _d(xT), _d(vT), _d(dxT),
+                             _d(dvT)), "free_tlm")
+    return xT, vT, dxT, dvT
+
+
+def free_adjoint(p: Params, m, x0, v0, nsteps, gxT, gvT):
+    m = _f64(m)
+    x0, v0 = _f64(x0, (-1, 3)), _f64(v0, (-1, 3))
+    gxT, gvT = _f64(gxT, (-1, 3)), _f64(gvT, (-1, 3))
+    gx0, gv0, gm = np.zeros_like(x0), np.zeros_like(v0), np.zeros_like(m)
+    _check(lib().go_free_adjoint(ctypes.byref(p), len(m), _d(m), _d(x0), _d(v0),
+                                 int(nsteps), _d(gxT), _d(gvT), _d(gx0), _d(gv0),
+                                 _d(gm)), "free_adjoint")
+    return gx0, gv0, gm

@@ -1,0 +1,51 @@
+"""Mutation check of the oracle's pins: each case plants one plausible
+mistake (a dropped term, a wrong sign, a wrong index or factor) in a copy of
+the oracle source, builds it on the CPU and runs the pins against it.  Every
+mutant must fail at least one pin."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = {
+    "hermite_a_sign": ("3.0 * dt * (Pd0 + Pd1)", "3.0 * dt * (Pd0 - Pd1)"),
+    "drop_Kprime": ("f = K / (r2 * r) - dK / r2;", "f = K / (r2 * r);"),
+    "kprime_sign": ("f = K / (r2 * r) - dK / r2;", "f = K / (r2 * r) + dK / r2;"),
+    "ha_kprime_sign": ("f = (1.0 - K) / (q2 * q) + dK / q2;", "f = (1.0 - K) / (q2 * q) - dK / q2;"),
+    "sun_sign": ("x[3 * i + k] += h * P[k] / p->m0;", "x[3 * i + k] -= h * P[k] / p->m0;"),
+    "stumpff_c3": ("double n3 = 0.25 * (c2 + c0 * c3);", "double n3 = 0.25 * (c2 + c1 * c3);"),
+    "kepler_gdot": ("double gd = 1.0 - mu * G[2] / r;", "double gd = 1.0 - mu * G[2] / r0;"),
+    "rcrit_hill": ("cbrt(m[i] / (3.0 * p->m0))", "cbrt(m[i] / (p->m0))"),
+    "y_scale": ("double y = (r - 0.1 * rcij) / (0.9 * rcij);", "double y = (r - 0.1 * rcij) / (rcij);"),
+    "mmid_smoothing": ("yout[k] = 0.5 * (ym[k] + yn[k] + hs * d[k]);",
+                       "yout[k] = 0.5 * (ym[k] + yn[k] + 2.0 * hs * d[k]);"),
+    "neville_h2": ("double den = ratio * ratio - 1.0;", "double den = ratio - 1.0;"),
+    "tlm_kick": ("3.0 * d[k] * ddot * ir3 / r2", "2.0 * d[k] * ddot * ir3 / r2"),
+    "tlm_dbeta": ("- 2.0 * dot3(v0, dv0);", "- 2.0 * dot3(x0, dv0);"),
+    "helio_dem_mass": ("v[3 * i + k] -= S[k] / (p->m0 + M);", "v[3 * i + k] -= S[k] / (p->m0);"),
+    "groups_max_label": ("int l = label[a] < label[b] ? label[a] : label[b];",
+                         "int l = label[a] > label[b] ? label[a] : label[b];"),
+    "energy_sun_term": ("*E = kin + dot3(P, P) / (2.0 * p->m0) + pot;", "*E = kin + pot;"),
+    "precheck_factor": ("cand[(size_t)i * n + j] = r < p->pf * rcij;", "cand[(size_t)i * n + j] = r < rcij;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    a, b = MUTANTS[name]
+    src = open(os.path.join(ROOT, "oracle", "genga_oracle.c")).read()
+    assert a in src, "mutation pattern no longer present in the oracle"
+    pkg = tmp_path / "oracle"
+    shutil.copytree(os.path.join(ROOT, "oracle"), pkg,
+                    ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    (pkg / "genga_oracle.c").write_text(src.replace(a, b, 1))
+    code = ("import sys; sys.path.insert(0, %r); sys.path.insert(1, %r); import pytest; "
+            "sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', %r]))"
+            % (str(tmp_path), ROOT, os.path.join(ROOT, "tests", "test_oracle_pins.py")))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       cwd=str(tmp_path), timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"

@@ -1,0 +1,567 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix:
+closed forms, invariants, special cases and brute force on tiny inputs.
+Each test names the passage it pins.  No GPU is involved."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1404_2324_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+LD = np.longdouble
+
+
+def _rot(rng):
+    q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    return q
+
+
+# ------------------------------------------------- changeover, Eq. (4)-(5) ---
+def test_changeover_golden_values():
+    rows = np.loadtxt(os.path.join(GOLDEN, "changeover_values.txt"))
+    for y, K, dK in rows:
+        k, d = O.changeover(y)
+        assert k == pytest.approx(K, abs=1e-15)
+        assert d == pytest.approx(dK, abs=1e-15)
+
+
+def test_changeover_symmetry_and_derivative():
+    for y in np.linspace(0.001, 0.999, 97):
+        k1, d1 = O.changeover(y)
+        k2, _ = O.changeover(1.0 - y)
+        assert k1 + k2 == pytest.approx(1.0, abs=4.5e-16)
+        h = 1e-6
+        fd = (O.changeover(y + h)[0] - O.changeover(y - h)[0]) / (2 * h)
+        assert d1 == pytest.approx(fd, rel=1e-7, abs=1e-9)
+    # smooth joins at both ends
+    assert O.changeover(1e-9)[1] < 1e-8 and O.changeover(1 - 1e-9)[1] < 1e-8
+
+
+# ------------------------------------------------- critical radius, Eq. (6) ---
+def test_rcrit_hill_and_velocity_terms():
+    p = O.params(n1=3.0, n2=0.4, dt=0.1)
+    # circular orbit at r = 2: a = 2, v = sqrt(1/2)
+    m = np.array([3e-6, 0.0])
+    x = np.array([[2.0, 0, 0], [0, 2.0, 0]])
+    v = np.array([[0, np.sqrt(0.5), 0], [-np.sqrt(0.5), 0, 0]])
+    rc = O.rcrit(p, m, x, v)
+    rh = 2.0 * (3e-6 / 3.0) ** (1 / 3)
+    assert rc[0] == pytest.approx(max(3 * rh, 0.4 * 0.1 * np.sqrt(0.5)), rel=1e-14)
+    assert rc[1] == pytest.approx(0.4 * 0.1 * np.sqrt(0.5), rel=1e-14)  # m = 0
+    # unbound orbit: Hill term from the heliocentric distance
+    v2 = np.array([[0, 2.0, 0]])
+    rc2 = O.rcrit(O.params(n1=3, n2=0.0, dt=0.1), m[:1], x[:1], v2)
+    assert rc2[0] == pytest.approx(3 * 2.0 * (1e-6) ** (1 / 3), rel=1e-14)
+
+
+# ------------------------------------------------------- kick, Eq. (2) -------
+def _HB(m, x, rc, G=1.0):
+    """Eq. (2) evaluated directly (extended precision)."""
+    n = len(m)
+    H = LD(0)
+    for i in range(n):
+        for j in range(i + 1, n):
+            d = x[j].astype(LD) - x[i].astype(LD)
+            r = np.sqrt(np.sum(d * d))
+            rcij = max(rc[i], rc[j])
+            y = float((r - LD(0.1) * rcij) / (LD(0.9) * rcij))
+            K = O.changeover(y)[0]
+            H -= LD(G) * LD(m[i]) * LD(m[j]) * LD(K) / r
+    return H
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_kick_is_gradient_of_HB(seed):
+    """The kick must be -grad(H_B)/m_i including the K' term (reading of
+    Sec. 2.1): central differences of Eq. (2)."""
+    rng = np.random.default_rng(seed)
+    n = 6
+    m = rng.uniform(1e-6, 1e-4, n)
+    x = rng.uniform(-0.05, 0.05, (n, 3)) + np.array([1.0, 0, 0])
+    rc = rng.uniform(0.02, 0.06, n)  # many pairs inside the changeover band
+    p = O.params()
+    acc = O.accel(p, m, x, rc)
+    h = 1e-7
+    for i in range(n):
+        for k in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            g = (_HB(m, xp, rc) - _HB(m, xm, rc)) / LD(2 * h)
+            assert acc[i, k] == pytest.approx(float(-g / LD(m[i])), rel=2e-6, abs=1e-9)
+
+
+def test_kick_newtonian_bruteforce_and_momentum():
+    rng = np.random.default_rng(7)
+    for n in (2, 3, 5, 8):
+        m = rng.uniform(1e-7, 1e-3, n)
+        x = rng.uniform(-2, 2, (n, 3))
+        p = O.params(encounter_free=1)
+        acc = O.accel(p, m, x)
+        ref = np.zeros((n, 3), dtype=LD)
+        for i in range(n):
+            for j in range(n):
+                if i != j:
+                    d = x[j].astype(LD) - x[i].astype(LD)
+                    r = np.sqrt(np.sum(d * d))
+                    ref[i] += LD(m[j]) * d / (r * r * r)
+        np.testing.assert_allclose(acc, ref.astype(np.float64), rtol=1e-14, atol=0)
+        # sum_i m_i a_i = 0 (Newton's third law, every pair antisymmetric)
+        tot = (m[:, None] * acc).sum(0)
+        assert np.abs(tot).max() <= 1e-15 * np.abs(m[:, None] * acc).max()
+        # with changeover radii the antisymmetry holds as well
+        rc = rng.uniform(0.1, 3.0, n)
+        acc2 = O.accel(O.params(), m, x, rc)
+        tot2 = (m[:, None] * acc2).sum(0)
+        assert np.abs(tot2).max() <= 1e-14 * max(np.abs(m[:, None] * acc2).max(), 1e-300)
+
+
+def test_kick_far_pairs_are_newtonian():
+    """K = 1 beyond r_crit: with small radii the kick equals the Newtonian sum."""
+    rng = np.random.default_rng(3)
+    m = rng.uniform(1e-7, 1e-5, 5)
+    x = rng.uniform(-2, 2, (5, 3))
+    a1 = O.accel(O.params(), m, x, np.full(5, 1e-3))
+    a2 = O.accel(O.params(encounter_free=1), m, x)
+    np.testing.assert_array_equal(a1, a2)
+
+
+# ------------------------------------------------------ Sun kick, Eq. (3) ----
+def test_sun_drift_linear_and_keeps_L():
+    rng = np.random.default_rng(4)
+    n = 7
+    m = rng.uniform(1e-6, 1e-3, n)
+    x = rng.uniform(-2, 2, (n, 3))
+    v = rng.uniform(-1, 1, (n, 3))
+    p = O.params()
+    h = 0.037
+    x2 = O.sun_drift(p, m, x, v, h)
+    P = (m[:, None] * v).sum(0)
+    np.testing.assert_allclose(x2, x + h * P, rtol=0, atol=4e-16 * np.abs(x).max())
+    L1 = (m[:, None] * np.cross(x, v)).sum(0)
+    L2 = (m[:, None] * np.cross(x2, v)).sum(0)
+    np.testing.assert_allclose(L2, L1, rtol=0, atol=1e-15 * np.abs(L1).max())
+
+
+# ------------------------------------------------ Kepler drift, Eq. (9) ------
+def _stumpff_closed(z):
+    if 0 < abs(z) < 1e-3:  # Taylor to z^3: the trigonometric forms cancel
+        return np.array([1 - z / 2 + z * z / 24 - z ** 3 / 720, 1 - z / 6 + z * z / 120 - z ** 3 / 5040,
+                         0.5 - z / 24 + z * z / 720 - z ** 3 / 40320,
+                         1 / 6 - z / 120 + z * z / 5040 - z ** 3 / 362880])
+    if z > 0:
+        s = np.sqrt(z)
+        return np.array([np.cos(s), np.sin(s) / s, (1 - np.cos(s)) / z, (s - np.sin(s)) / (z * s)])
+    if z < 0:
+        s = np.sqrt(-z)
+        return np.array([np.cosh(s), np.sinh(s) / s, (np.cosh(s) - 1) / (-z), (np.sinh(s) - s) / (-z * s)])
+    return np.array([1.0, 1.0, 0.5, 1.0 / 6.0])
+
+
+@pytest.mark.parametrize("z", [-50.0, -3.0, -0.5, -0.05, 0.0, 1e-6, 0.05, 0.3, 2.0, 9.0, 30.0])
+def test_stumpff_closed_forms(z):
+    c = O.stumpff(z)
+    ref = _stumpff_closed(z)
+    tol = 1e-13 if abs(z) > 0.01 else 1e-15
+    np.testing.assert_allclose(c, ref, rtol=tol * (1 + abs(z)), atol=1e-15)
+
+
+def _kepler_closed(mu, a, e, t):
+    """Closed-form two-body orbit in the perifocal plane, time t after
+    pericentre, in extended precision.  Elliptic: E - e sin E = M;
+    hyperbolic (a > 0 as |a|): e sinh H - H = M."""
+    mu, a, e, t = LD(mu), LD(a), LD(e), LD(t)
+    n = np.sqrt(mu / (a * a * a))
+    M = n * t
+    if e < 1:
+        E = M if e < 0.8 else LD(np.pi)
+        for _ in range(100):
+            E = E - (E - e * np.sin(E) - M) / (1 - e * np.cos(E))
+        sq = np.sqrt(1 - e * e)
+        den = 1 - e * np.cos(E)
+        x = np.array([a * (np.cos(E) - e), a * sq * np.sin(E), LD(0)])
+        v = np.array([-a * n * np.sin(E) / den, a * n * sq * np.cos(E) / den, LD(0)])
+    else:
+        H = np.arcsinh(M / e)
+        for _ in range(200):
+            H = H - (e * np.sinh(H) - H - M) / (e * np.cosh(H) - 1)
+        sq = np.sqrt(e * e - 1)
+        den = e * np.cosh(H) - 1
+        x = np.array([a * (e - np.cosh(H)), a * sq * np.sinh(H), LD(0)])
+        v = np.array([-a * n * np.sinh(H) / den, a * n * sq * np.cosh(H) / den, LD(0)])
+    return x, v
+
+
+@pytest.mark.parametrize("a,e", [(1.0, 0.0), (1.0, 0.05), (0.7, 0.3), (2.0, 0.9),
+                                 (1.0, 0.999), (1.0, 1.001), (0.5, 1.5), (3.0, 4.0)])
+@pytest.mark.parametrize("dt", [0.0628, -0.0628, 0.5, 3.0])
+def test_kepler_drift_closed_form(a, e, dt):
+    mu = 1.0
+    rng = np.random.default_rng(int(1000 * a + 100 * e))
+    R = _rot(rng)
+    t0 = 0.3
+    x0, v0 = _kepler_closed(mu, a, e, t0)
+    x1, v1 = _kepler_closed(mu, a, e, t0 + dt)
+    x0 = R @ x0.astype(np.float64)
+    v0 = R @ v0.astype(np.float64)
+    xr = R @ x1.astype(np.float64)
+    vr = R @ v1.astype(np.float64)
+    x, v, it = O.kepler(mu, x0, v0, dt)
+    scale = max(np.linalg.norm(xr), 1.0)
+    np.testing.assert_allclose(x, xr, rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(v, vr, rtol=0, atol=1e-12 * max(np.linalg.norm(vr), 1.0))
+
+
+def test_kepler_invariants_and_reversibility():
+    rng = np.random.default_rng(11)
+    mu = 1.0
+    for _ in range(50):
+        x0 = rng.uniform(-2, 2, 3)
+        v0 = rng.uniform(-1, 1, 3) * np.sqrt(mu / np.linalg.norm(x0))
+        dt = rng.uniform(-0.5, 0.5)
+        x, v, it = O.kepler(mu, x0, v0, dt)
+        assert it <= 8
+        E0 = 0.5 * v0 @ v0 - mu / np.linalg.norm(x0)
+        E1 = 0.5 * v @ v - mu / np.linalg.norm(x)
+        assert E1 == pytest.approx(E0, rel=1e-13, abs=1e-14)
+        np.testing.assert_allclose(np.cross(x, v), np.cross(x0, v0), rtol=0, atol=1e-14)
+        xb, vb, _ = O.kepler(mu, x, v, -dt)
+        np.testing.assert_allclose(xb, x0, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(vb, v0, rtol=0, atol=1e-13)
+        # composition: drift(t1 + t2) = drift(t2) o drift(t1)
+        xa, va, _ = O.kepler(mu, x0, v0, 0.3 * dt)
+        xc, vc, _ = O.kepler(mu, xa, va, 0.7 * dt)
+        np.testing.assert_allclose(xc, x, rtol=0, atol=1e-13)
+
+
+def test_kepler_symplectic_jacobian():
+    """f gdot - fdot g = 1 is equivalent to the drift being symplectic: the
+    numerical Jacobian J satisfies J^T Omega J = Omega."""
+    rng = np.random.default_rng(5)
+    mu = 1.0
+    x0 = np.array([0.9, 0.2, 0.05])
+    v0 = np.array([-0.15, 1.05, 0.02])
+    dt = 0.7
+    z0 = np.concatenate([x0, v0])
+    J = np.zeros((6, 6))
+    h = 1e-6
+    for k in range(6):
+        zp, zm = z0.copy(), z0.copy()
+        zp[k] += h
+        zm[k] -= h
+        a = np.concatenate(O.kepler(mu, zp[:3], zp[3:], dt)[:2])
+        b = np.concatenate(O.kepler(mu, zm[:3], zm[3:], dt)[:2])
+        J[:, k] = (a - b) / (2 * h)
+    Om = np.block([[np.zeros((3, 3)), np.eye(3)], [-np.eye(3), np.zeros((3, 3))]])
+    np.testing.assert_allclose(J.T @ Om @ J, Om, atol=1e-8)
+
+
+# -------------------------------------------- encounter test, Eq. (10)-(12) --
+def test_hermite_golden_straight_line():
+    with open(os.path.join(GOLDEN, "hermite_straight_line.txt")) as f:
+        rows = [list(map(float, l.split())) for l in f if l.strip() and not l.startswith("#")]
+    for r in rows:
+        dt, dx0, dv, want = r[0], np.array(r[1:4]), np.array(r[4:7]), r[7]
+        dx1 = dx0 + dv * dt
+        got = O.hermite_dmin2(dt, dx0, dv, dx1, dv)
+        assert got == pytest.approx(want, abs=1e-14)
+
+
+def test_hermite_straight_line_random():
+    rng = np.random.default_rng(8)
+    for _ in range(200):
+        dt = rng.uniform(0.01, 1)
+        dx0 = rng.standard_normal(3)
+        dv = rng.standard_normal(3) * rng.uniform(0.1, 5) / dt
+        dx1 = dx0 + dv * dt
+        ts = -(dx0 @ dv) / (dv @ dv) / dt
+        if 0 < ts < 1:
+            want = dx0 @ dx0 - (dx0 @ dv) ** 2 / (dv @ dv)
+        else:
+            want = min(dx0 @ dx0, dx1 @ dx1)
+        got = O.hermite_dmin2(dt, dx0, dv, dx1, dv)
+        assert got == pytest.approx(want, rel=1e-9, abs=1e-14)
+
+
+def _hermite_P(t, dt, P0, P1, Pd0, Pd1):
+    """Eq. (10) as printed."""
+    return (P0 * (1 + 2 * t) * (1 - t) ** 2 + P1 * t ** 2 * (3 - 2 * t)
+            + Pd0 * t * (1 - t) ** 2 * dt + Pd1 * t ** 2 * (t - 1) * dt)
+
+
+def test_hermite_matches_dense_minimum_of_eq10():
+    """Brute-force minimum of the printed cubic over a dense grid; this pins
+    the corrected coefficient a of Eq. (11) (with the printed sign the
+    stationary points are wrong and the test fails)."""
+    rng = np.random.default_rng(9)
+    t = np.linspace(0, 1, 200001)
+    for _ in range(300):
+        dt = rng.uniform(0.01, 1)
+        dx0, dv0, dx1, dv1 = (rng.standard_normal(3) for _ in range(4))
+        P0, P1 = dx0 @ dx0, dx1 @ dx1
+        Pd0, Pd1 = 2 * dx0 @ dv0, 2 * dx1 @ dv1
+        dense = _hermite_P(t, dt, P0, P1, Pd0, Pd1).min()
+        got = O.hermite_dmin2(dt, dx0, dv0, dx1, dv1)
+        assert got <= dense + 1e-12 * max(1, abs(dense))
+        assert got >= dense - 1e-8 * max(1, abs(P0) + abs(P1))
+
+
+# --------------------------------------------------- grouping, App. A --------
+def test_groups_match_bfs_components():
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    rng = np.random.default_rng(10)
+    for trial in range(50):
+        n = int(rng.integers(2, 60))
+        npairs = int(rng.integers(1, 2 * n))
+        pairs = rng.integers(0, n, (npairs, 2))
+        pairs = pairs[pairs[:, 0] != pairs[:, 1]]
+        if len(pairs) == 0:
+            continue
+        pairs = np.sort(pairs, 1)
+        ng, label = O.groups(n, pairs)
+        A = coo_matrix((np.ones(len(pairs)), (pairs[:, 0], pairs[:, 1])), shape=(n, n))
+        _, comp = connected_components(A, directed=False)
+        inpair = np.zeros(n, bool)
+        inpair[pairs.ravel()] = True
+        for i in range(n):
+            if not inpair[i]:
+                assert label[i] == -1
+            else:
+                members = np.nonzero((comp == comp[i]) & inpair)[0]
+                assert label[i] == members.min()
+        assert ng == len({comp[i] for i in range(n) if inpair[i]})
+
+
+def test_groups_paper_figure_example_chain():
+    # a chain A-B, B-C makes one group even without an A-C pair (Sec. 5)
+    ng, label = O.groups(8, [[1, 4], [4, 7], [2, 3], [5, 6], [3, 6]])
+    assert ng == 2
+    assert list(label) == [-1, 1, 2, 2, 1, 2, 2, 1]
+
+
+# ----------------------------------------------- BS direct integration -------
+def test_bs_reproduces_kepler_outside_changeover():
+    """With every pair beyond r_crit the group's H_A is pure Kepler motion of
+    each body around the fixed star."""
+    p = O.params(bs_tol=1e-13)
+    m = np.array([1e-6, 2e-6])
+    x = np.array([[1.0, 0.0, 0.0], [0.0, 1.2, 0.01]])
+    v = np.array([[0.0, 1.0, 0.0], [-0.9, 0.0, 0.0]])
+    rc = np.array([1e-3, 1e-3])
+    H = 0.3
+    xb, vb, sub = O.bs_group(p, m, rc, x, v, H)
+    for i in range(2):
+        xk, vk, _ = O.kepler(1.0, x[i], v[i], H)
+        np.testing.assert_allclose(xb[i], xk, rtol=0, atol=3e-13)
+        np.testing.assert_allclose(vb[i], vk, rtol=0, atol=3e-13)
+
+
+def _HA(p, m, rc, x, v):
+    H = 0.0
+    n = len(m)
+    for i in range(n):
+        H += 0.5 * m[i] * v[i] @ v[i] - p.G * p.m0 * m[i] / np.linalg.norm(x[i])
+        for j in range(i + 1, n):
+            r = np.linalg.norm(x[j] - x[i])
+            rcij = max(rc[i], rc[j])
+            K = O.changeover((r - 0.1 * rcij) / (0.9 * rcij))[0]
+            H -= p.G * m[i] * m[j] * (1 - K) / r
+    return H
+
+
+def test_bs_deep_encounter_conserves_HA_and_converges():
+    p = O.params(bs_tol=1e-13)
+    m = np.array([3e-6, 3e-6, 1e-6])
+    x = np.array([[1.0, 0.0, 0.0], [1.0, 0.004, 0.0], [1.0, -0.006, 0.001]])
+    v = np.array([[0.0, 1.0, 0.0], [0.02, 1.0, 0.0], [-0.01, 1.0, 0.003]])
+    rc = np.array([0.05, 0.05, 0.05])
+    E0 = _HA(p, m, rc, x, v)
+    xb, vb, sub = O.bs_group(p, m, rc, x, v, 0.0628)
+    E1 = _HA(p, m, rc, xb, vb)
+    assert abs((E1 - E0) / E0) < 1e-11
+    # tighter tolerance agrees to about the tolerance
+    xb2, vb2, sub2 = O.bs_group(O.params(bs_tol=1e-15), m, rc, x, v, 0.0628)
+    assert sub2 >= sub
+    np.testing.assert_allclose(xb, xb2, rtol=0, atol=1e-11)
+    # angular momentum of the group (central pair forces + fixed star)
+    L0 = (m[:, None] * np.cross(x, v)).sum(0)
+    L1 = (m[:, None] * np.cross(xb, vb)).sum(0)
+    np.testing.assert_allclose(L1, L0, rtol=0, atol=1e-13 * np.abs(L0).max())
+
+
+def test_bs_depth_exhaustion_is_an_error():
+    p = O.params(bs_tol=-1.0, bs_max_depth=3)  # no column can ever be accepted
+    m = np.array([1e-6, 1e-6])
+    x = np.array([[1.0, 0.0, 0.0], [1.0, 0.01, 0.0]])
+    v = np.array([[0.0, 1.0, 0.0], [0.0, 1.0, 0.0]])
+    with pytest.raises(O.OracleError) as ei:
+        O.bs_group(p, m, np.array([0.05, 0.05]), x, v, 0.0628)
+    assert ei.value.code == O.GO_EBS
+
+
+# ------------------------------------- energy, coordinates, conservation -----
+def test_energy_two_body_by_hand():
+    p = O.params()
+    m = np.array([1e-3, 2e-3])
+    x = np.array([[1.0, 0, 0], [0, 2.0, 0]])
+    v = np.array([[0, 1.0, 0], [-0.5, 0, 0]])
+    E, L = O.energy(p, m, x, v)
+    P = m[0] * v[0] + m[1] * v[1]
+    want = (0.5 * 1e-3 * 1.0 + 0.5 * 2e-3 * 0.25 + P @ P / 2
+            - 1e-3 / 1.0 - 2e-3 / 2.0 - 2e-6 / np.sqrt(5.0))
+    assert E == pytest.approx(want, rel=1e-15)
+    np.testing.assert_allclose(L, [0, 0, 1e-3 * 1.0 + 2e-3 * (0 - 2.0 * -0.5)], rtol=1e-15)
+
+
+def test_helio_democratic_round_trip():
+    p = O.params()
+    rng = np.random.default_rng(12)
+    m = rng.uniform(1e-7, 1e-3, 9)
+    u = rng.standard_normal((9, 3))
+    v = O.helio_to_dem(p, m, u)
+    # democratic velocities are barycentric: the star carries -sum m v
+    np.testing.assert_allclose(O.dem_to_helio(p, m, v), u, rtol=0, atol=1e-15)
+
+
+def _two_body(mu, a, e, t):
+    x, v = _kepler_closed(mu, a, e, t)
+    return x.astype(np.float64), v.astype(np.float64)
+
+
+def test_second_order_convergence_two_body():
+    """Star + one planet: the exact relative orbit is Kepler with
+    mu = G (m0 + m).  The split step (Eq. 7) is second order: halving tau
+    divides the error at a fixed time by 4."""
+    m1 = 1e-3
+    mu = 1.0 + m1
+    a, e = 1.0, 0.1
+    x0, u0 = _two_body(mu, a, e, 0.0)
+    T = 2.0
+    errs = []
+    for nst in (50, 100, 200):
+        p = O.params(dt=T / nst, encounter_free=1)
+        v0 = O.helio_to_dem(p, [m1], u0[None])
+        x, v = O.free_step(p, [m1], x0[None], v0, nst)
+        xr, _ = _two_body(mu, a, e, T)
+        errs.append(np.linalg.norm(x[0] - xr))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.6 < r1 < 4.4 and 3.6 < r2 < 4.4
+
+
+def test_encounter_free_reversible_and_conserves_L():
+    s = W.plain_n16()
+    p = O.params(encounter_free=1)
+    v = O.helio_to_dem(p, s.m, s.u)
+    x1, v1 = O.free_step(p, s.m, s.x, v, 50)
+    E0, L0 = O.energy(p, s.m, s.x, v)
+    E1, L1 = O.energy(p, s.m, x1, v1)
+    np.testing.assert_allclose(L1, L0, rtol=0, atol=1e-14 * np.abs(L0).max())
+    assert abs((E1 - E0) / E0) < 1e-7
+    pb = O.params(encounter_free=1, dt=-p.dt)
+    x2, v2 = O.free_step(pb, s.m, x1, v1, 50)
+    np.testing.assert_allclose(x2, s.x, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(v2, v, rtol=0, atol=1e-13)
+
+
+def test_massless_body_follows_exact_kepler():
+    """A lone massless body: no pair force, P = 0, so the step is the exact
+    Kepler flow."""
+    a, e = 1.3, 0.2
+    x0, u0 = _two_body(1.0, a, e, 0.1)
+    p = O.params()
+    sim = O.MassiveSim(p, [0.0], x0[None], u0[None])
+    sim.step(20)
+    xr, vr = _two_body(1.0, a, e, 0.1 + 20 * p.dt)
+    np.testing.assert_allclose(sim.x[0], xr, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(sim.v[0], vr, rtol=0, atol=1e-13)
+
+
+def test_plain_n16_energy_bounded_and_L_conserved():
+    s = W.plain_n16()
+    p = O.params()
+    sim = O.MassiveSim(p, s.m, s.x, s.u, coords="helio")
+    E0, L0 = sim.energy()
+    errs = []
+    enc = 0
+    for _ in range(10):
+        st = sim.step(100)
+        enc += st["enc_total"]
+        assert st["miss_total"] == 0
+        E, L = sim.energy()
+        errs.append(abs((E - E0) / E0))
+        np.testing.assert_allclose(L, L0, rtol=0, atol=1e-13 * np.abs(L0).max())
+    assert enc > 0  # the workload exercises the encounter path
+    assert max(errs) < 1e-8
+
+
+def test_precheck_candidates_and_counts():
+    s = W.planetesimals(256, seed_index=2)
+    p = O.params()
+    sim = O.MassiveSim(p, s.m, s.x, s.u, coords="helio")
+    i, j = np.nonzero(sim.cand)
+    assert np.all(i < j)
+    r = np.linalg.norm(sim.x[j] - sim.x[i], axis=1)
+    rcij = np.maximum(sim.rc[i], sim.rc[j])
+    assert np.all(r < 3 * rcij)
+    st = sim.step(5)
+    assert st["miss_total"] == 0
+    # confirmed encounters are a subset of candidates of that step
+    for a, b in sim.enc:
+        assert a < b
+
+
+# ------------------------------------------------- test-particle mode --------
+def test_tp_mode_equals_massive_path_with_zero_masses():
+    planets, xt, ut = W.test_particles(ntp=40, nplanets=3, seed_index=3)
+    p = O.params()
+    tp = O.TPSim(p, planets.m, planets.x, planets.u, xt, ut, coords="helio")
+    m_all = np.concatenate([planets.m, np.zeros(len(xt))])
+    v_all = np.concatenate([tp.v, tp.vt])
+    x_all = np.concatenate([tp.x, tp.xt])
+    ms = O.MassiveSim(p, m_all, x_all, v_all)
+    for _ in range(4):
+        tp.step(5)
+        ms.step(5)
+        np.testing.assert_allclose(ms.x[:3], tp.x, rtol=0, atol=1e-11)
+        np.testing.assert_allclose(ms.x[3:], tp.xt, rtol=0, atol=1e-11)
+        np.testing.assert_allclose(ms.v[3:], tp.vt, rtol=0, atol=1e-11)
+
+
+# ----------------------------------------------- tangent-linear, adjoint -----
+def _adj_system():
+    m, x, u = W.adjoint_systems(nsys=1, nplanets=4, seed_index=5)
+    p = O.params(encounter_free=1)
+    v = O.helio_to_dem(p, m[0], u[0])
+    return p, m[0], x[0], v
+
+
+def test_tlm_matches_central_differences():
+    p, m, x, v = _adj_system()
+    rng = np.random.default_rng(13)
+    dx = rng.standard_normal(x.shape)
+    dv = rng.standard_normal(v.shape)
+    dm = rng.standard_normal(m.shape) * m
+    nst = 100
+    _, _, dxT, dvT = O.free_tlm(p, m, x, v, dm, dx, dv, nst)
+    h = 1e-6
+    xp, vp = O.free_step(p, m + h * dm, x + h * dx, v + h * dv, nst)
+    xm, vm = O.free_step(p, m - h * dm, x - h * dx, v - h * dv, nst)
+    np.testing.assert_allclose(dxT, (xp - xm) / (2 * h), rtol=0, atol=2e-6 * np.abs(dxT).max())
+    np.testing.assert_allclose(dvT, (vp - vm) / (2 * h), rtol=0, atol=2e-6 * np.abs(dvT).max())
+
+
+def test_adjoint_dot_product_with_tlm():
+    p, m, x, v = _adj_system()
+    rng = np.random.default_rng(14)
+    dx, dv = rng.standard_normal(x.shape), rng.standard_normal(v.shape)
+    dm = rng.standard_normal(m.shape)
+    lx, lv = rng.standard_normal(x.shape), rng.standard_normal(v.shape)
+    nst = 30
+    _, _, dxT, dvT = O.free_tlm(p, m, x, v, dm, dx, dv, nst)
+    gx, gv, gm = O.free_adjoint(p, m, x, v, nst, lx, lv)
+    lhs = np.sum(dxT * lx) + np.sum(dvT * lv)
+    rhs = np.sum(dx * gx) + np.sum(dv * gv) + np.sum(dm * gm)
+    assert lhs == pytest.approx(rhs, rel=1e-12)
