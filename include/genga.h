@@ -1,0 +1,206 @@
+/*
+ * genga.h -- C ABI of the MI355X (gfx950) implementation of the hybrid
+ * symplectic N-body step of Grimm & Stadel, "The GENGA Code: Gravitational
+ * Encounters in N-body simulations with GPU Acceleration" (arXiv:1404.2324).
+ *
+ * The problem (Sec. 1, Sec. 3): bodies of mass m_i with positions x_i and
+ * velocities v_i orbit a central mass m0.  One step of length tau is the
+ * second-order composition of Eq. (7) of the Hamiltonian split Eqs. (1)-(3):
+ * an opening kick of the perturbing part H_B (pair terms weighted by the
+ * changeover function K of Eqs. 4-5), a Sun kick of H_C, a Kepler drift of
+ * H_A (Eq. 9), the close-encounter search (Eqs. 10-12), grouping (App. A),
+ * direct Bulirsch-Stoer integration of each group (Sec. 3.2.6), a second Sun
+ * kick and a closing kick with the prechecker (Sec. 2.2).
+ *
+ * Conventions shared by every call
+ *   - All floating point is IEEE double (FP64).
+ *   - Position / velocity arrays are n x 3, row-major (x0 y0 z0 x1 ...).
+ *   - "d_" pointers are device (HBM) pointers, "h_" pointers host pointers.
+ *   - The caller owns all memory: state arrays, the workspace and outputs.
+ *     The library owns only the opaque context; it never frees caller
+ *     memory.  Device pointers handed to genga_init must outlive the context
+ *     only when named so below (the workspace); state arrays are copied.
+ *   - Work is enqueued on the caller's HIP stream (NULL = default stream).
+ *     Only the calls documented as synchronising wait for the device.
+ *   - Return value: GENGA_OK (0), or a negative GENGA_E* code.  Errors the
+ *     device detects inside a step (non-convergence, overflow) are latched in
+ *     a device status word and returned by the next synchronising call.
+ */
+#ifndef GENGA_H
+#define GENGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct genga_ctx genga_ctx;
+
+/* Integration parameters.  Defaults (genga_params_default) follow Sec. 2.1:
+ * n1 = 3, n2 = 0.4; prechecker factor 3 (Sec. 2.2).  The Bulirsch-Stoer
+ * tolerance, depth and the Kepler iteration cap are this library's choices. */
+typedef struct genga_params {
+    double G;               /* gravitational constant                      */
+    double m0;              /* central mass (main and test-particle mode)  */
+    double dt;              /* time step tau (may be negative)              */
+    double n1, n2;          /* critical-radius factors of Eq. (6)          */
+    double pf;              /* prechecker enlargement of r_crit             */
+    double bs_tol;          /* BS relative tolerance per body               */
+    int32_t bs_max_depth;   /* max halvings of a BS substep                 */
+    int32_t kepler_max_iter;/* cap of the universal Kepler iteration        */
+    int32_t encounter_free; /* 1: K == 1 (the MVS map); no encounter work   */
+    int32_t cand_per_body;  /* candidate partners stored per body           */
+    int32_t enc_cap;        /* capacity of the encounter list               */
+    int32_t reserved;
+} genga_params;
+
+typedef struct genga_stats_s {
+    int64_t steps;          /* steps taken since init                       */
+    int32_t n_cand;         /* candidate pairs entering the last step       */
+    int32_t n_enc;          /* confirmed encounter pairs of the last step   */
+    int32_t n_groups;       /* encounter groups of the last step            */
+    int32_t max_group;      /* members of the largest group, last step      */
+    int32_t kepler_iter_max;/* most Kepler iterations any drift needed      */
+    int32_t tp_enc;         /* test-particle encounters of the last step    */
+    int64_t bs_substeps;    /* accepted BS substeps since init              */
+    int64_t enc_total;      /* encounters since init                        */
+    int64_t full_kicks;     /* opening kicks that could not reuse the cache */
+    int64_t tp_enc_total;
+    uint32_t flags;         /* latched device error bits                    */
+    uint32_t reserved;
+} genga_stats_t;
+
+enum { GENGA_MASSIVE = 0, GENGA_TEST = 1, GENGA_BATCH = 2 };
+enum { GENGA_HELIO = 0, GENGA_DEMOCRATIC = 1 };
+enum {
+    GENGA_OK = 0,
+    GENGA_EINVAL = -1,      /* bad argument, NaN/Inf input, size limit      */
+    GENGA_EHIP = -2,        /* a HIP runtime call failed                    */
+    GENGA_EOVERFLOW = -3,   /* candidate / encounter list capacity exceeded */
+    GENGA_EKEPLER = -4,     /* universal Kepler iteration did not converge  */
+    GENGA_EBS = -5,         /* Bulirsch-Stoer depth exhausted               */
+    GENGA_EADJ_ENCOUNTER = -6,
+    GENGA_ENOMEM = -7,      /* workspace smaller than genga_workspace_bytes */
+    GENGA_EGROUP = -8       /* encounter group larger than supported        */
+};
+
+/* Fill *p with the defaults: G = 1, m0 = 1, dt = 2 pi / 100, n1 = 3,
+ * n2 = 0.4 (Sec. 2.1), pf = 3 (Sec. 2.2), bs_tol = 1e-13, bs_max_depth =
+ * 20, kepler_max_iter = 40, encounter_free = 0, cand_per_body = 32,
+ * enc_cap = 2048. */
+void genga_params_default(genga_params *p);
+
+/* Device workspace (bytes) a context of this shape needs.  Main mode:
+ * n_massive <= 4096 bodies (the paper's main mode holds up to 2048,
+ * Sec. 3).  Returns 0 for an unsupported shape. */
+size_t genga_workspace_bytes(int mode, const genga_params *p, int n_massive,
+                             int64_t n_test, int n_sys, int64_t n_bodies);
+
+/* Create a context and load the initial state (Sec. 2.2: the first opening
+ * kick is prepared here, from the initial positions).
+ *   mode        GENGA_MASSIVE (main mode).
+ *   d_m         n_massive masses (device, read once).
+ *   d_x, d_v    n_massive x 3 positions and velocities (device, read once).
+ *               coords_in = GENGA_HELIO: heliocentric positions and
+ *               velocities, converted to democratic coordinates (heliocentric
+ *               positions, barycentric velocities, Sec. 2.1);
+ *               GENGA_DEMOCRATIC: already democratic.
+ *   d_workspace at least genga_workspace_bytes bytes of device memory, 256-B
+ *               aligned, owned by the caller, used until genga_destroy.
+ *   stream      hipStream_t of the caller (NULL = default stream).
+ * Synchronises once (validation of the input).  Errors: EINVAL (shape, NaN
+ * or Inf in the input, non-positive m0), ENOMEM (workspace too small), EHIP.
+ * n_test, n_sys, d_offsets, d_m0 are reserved for the other modes; pass 0 /
+ * NULL in main mode. */
+int genga_init(genga_ctx **ctx, int mode, const genga_params *p,
+               int n_massive, int64_t n_test, int n_sys,
+               const int32_t *d_offsets, const double *d_m0,
+               const double *d_m, const double *d_x, const double *d_v,
+               int coords_in, void *d_workspace, size_t ws_bytes,
+               void *stream);
+
+/* Advance nsteps steps of Eq. (7), following the step recipe of Sec. 2.2:
+ * opening kick (reusing the closing kick's accelerations for non-candidate
+ * pairs, Sec. 3.2.3), Sun kick, Kepler drift, encounter search, grouping,
+ * BS integration of groups, Sun kick, closing kick with the prechecker.
+ * Asynchronous on the context's stream (replays a captured HIP graph);
+ * errors latch in the device status.  nsteps >= 0. */
+int genga_step(genga_ctx *ctx, int64_t nsteps);
+
+/* Wait for the context's stream and return the latched device status as a
+ * GENGA_E* code (GENGA_OK when clean).  Synchronising. */
+int genga_sync(genga_ctx *ctx);
+
+/* Write the current state to d_x, d_v (n x 3, device, caller-owned) in
+ * GENGA_HELIO or GENGA_DEMOCRATIC coordinates.  Synchronising; returns the
+ * latched status. */
+int genga_get_state(genga_ctx *ctx, double *d_x, double *d_v, int coords_out);
+
+/* Replace the state (same shape) and prepare the next opening kick as
+ * genga_init does.  Synchronising. */
+int genga_set_state(genga_ctx *ctx, const double *d_x, const double *d_v,
+                    int coords_in);
+
+/* Total energy E = H_A + H_B + H_C of Eqs. (1)-(3) (K summed out:
+ * sum m v^2/2 + |P|^2/2m0 - sum G m0 m_i/r_i - sum_{i<j} G m_i m_j/r_ij) and
+ * angular momentum L = sum m_i x_i x v_i of each system, written to d_E
+ * (n_sys doubles) and d_L (3 n_sys doubles), device, asynchronous.  The
+ * relative energy error of Sec. 4.1 is |(E_t - E_0)/E_0|. */
+int genga_energy(genga_ctx *ctx, double *d_E, double *d_L);
+
+/* Confirmed close-encounter pairs of the last step (the Encounter kernel
+ * output, Sec. 3.2.4): i < j body indices in h_ij (2 per pair), the Hermite
+ * minimum squared separation in h_dmin2 and r_crit,ij^2 in h_rc2 (either
+ * may be NULL), sorted by (i, j).  *h_n receives the count; if it exceeds cap,
+ * cap pairs are written and GENGA_EOVERFLOW is returned.  Synchronising. */
+int genga_encounters(genga_ctx *ctx, int32_t *h_ij, double *h_dmin2,
+                     double *h_rc2, int cap, int *h_n);
+
+/* Prechecker candidates entering the next step (Sec. 2.2): pairs i < j with
+ * r_ij < pf r_crit,ij at the end of the last closing kick, sorted, as in
+ * genga_encounters.  Synchronising. */
+int genga_candidates(genga_ctx *ctx, int32_t *h_ij, int cap, int *h_n);
+
+/* Counters of the run (h_stats host).  Synchronising. */
+int genga_stats(genga_ctx *ctx, genga_stats_t *h_stats);
+
+/* Message for a GENGA_E* code (static storage). */
+const char *genga_strerror(int code);
+
+/* Release the context (not the caller's memory).  Synchronising. */
+int genga_destroy(genga_ctx *ctx);
+
+/* ---- component operations (same kernels' building blocks) ------------- */
+
+/* Acceleration of the perturbing part H_B (the kick of Eq. 7, Sec. 3.2.3):
+ * a_i = sum_{j != i} G m_j [K/r^3 - K'(r)/r^2] (x_j - x_i) with
+ * r_crit,ij = max(d_rc[i], d_rc[j]); encounter_free gives K = 1.
+ * d_m (n), d_x (n x 3), d_rc (n) in; d_acc (n x 3) out; all device.
+ * Uses the context-free workspace of genga_accel_workspace_bytes(n).
+ * Asynchronous.  Errors: EINVAL, ENOMEM, EHIP. */
+size_t genga_accel_workspace_bytes(int n);
+int genga_accel(const genga_params *p, int n, const double *d_m,
+                const double *d_x, const double *d_rc, double *d_acc,
+                void *d_workspace, size_t ws_bytes, void *stream);
+
+/* Kepler drift of n independent bodies for dt about mu (Eq. 9, universal
+ * variables).  d_x0, d_v0 in, d_x, d_v out (n x 3, device; may alias the
+ * inputs).  d_iters (n ints, device, may be NULL) receives the iteration
+ * count, negative when the iteration did not converge.  Asynchronous. */
+int genga_kepler(double mu, int64_t n, const double *d_x0, const double *d_v0,
+                 double dt, double *d_x, double *d_v, int max_iter,
+                 int32_t *d_iters, void *stream);
+
+/* Hermite close-encounter minimum of Eqs. (10)-(12) for n pairs.  d_q holds
+ * 12 doubles per pair (dx0, dv0, dx1, dv1: relative position and velocity at
+ * the start and the end of the step); d_out receives the minimum squared
+ * separation per pair.  Device pointers, asynchronous. */
+int genga_hermite(int64_t n, double dt, const double *d_q, double *d_out,
+                  void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GENGA_H */

@@ -149,7 +149,7 @@ void go_sun_drift(const go_params *p, int n, const double *m, double *x,
  *   c3(4z) = (c2 + c0 c3)/4.                                               */
 void go_stumpff(double z, double c[4]) {
     int nq = 0;
-    while (fabs(z) >= 0.1) {
+    while (fabs(z) >= 0.1 && nq < 64) { /* bounded for non-finite z */
         z *= 0.25;
         ++nq;
     }

@@ -1,0 +1,215 @@
+// Device-side FP64 building blocks of the hybrid symplectic step
+// (Grimm & Stadel, "The GENGA Code", arXiv:1404.2324), written for gfx950.
+// Included by every kernel translation unit of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace genga {
+
+constexpr double kTiny = 2.2250738585072014e-308;  // smallest normal double
+
+// ---- wave helpers (wave64) -------------------------------------------------
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  int2 p = *reinterpret_cast<int2*>(&v);
+  int lo = __builtin_amdgcn_readlane(p.x, lane);
+  int hi = __builtin_amdgcn_readlane(p.y, lane);
+  int2 q = make_int2(lo, hi);
+  return *reinterpret_cast<double*>(&q);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ---- changeover function, Eq. (4)-(5) ---------------------------------------
+// K(y) = 0 (y <= 0), y^2/(2y^2-2y+1) (0<y<1), 1 (y >= 1),
+// y = (r - 0.1 rc) / (0.9 rc); returns K and dK/dr.  rc <= 0: no changeover.
+__device__ __forceinline__ void changeover(double r, double rc, double& K,
+                                           double& dKdr) {
+  if (!(rc > 0.0)) {
+    K = 1.0;
+    dKdr = 0.0;
+    return;
+  }
+  const double inv = 1.0 / (0.9 * rc);
+  const double y = (r - 0.1 * rc) * inv;
+  if (y <= 0.0) {
+    K = 0.0;
+    dKdr = 0.0;
+  } else if (y >= 1.0) {
+    K = 1.0;
+    dKdr = 0.0;
+  } else {
+    const double D = 2.0 * y * y - 2.0 * y + 1.0;
+    const double iD = 1.0 / D;
+    K = y * y * iD;
+    dKdr = 2.0 * y * (1.0 - y) * iD * iD * inv;
+  }
+}
+
+// ---- critical radius, Eq. (6) ----------------------------------------------
+// rc = max(n1 R_H, n2 |dt| |v|); R_H = a (m / 3 m0)^(1/3) with the osculating
+// semi-major axis about mu = G m0 (heliocentric distance when unbound).
+__device__ __forceinline__ double rcrit(double x, double y, double z, double vx,
+                                        double vy, double vz, double m,
+                                        double mu, double m0, double n1,
+                                        double n2, double absdt) {
+  const double r = sqrt(x * x + y * y + z * z);
+  const double vv = vx * vx + vy * vy + vz * vz;
+  const double inva = 2.0 / r - vv / mu;
+  const double a = inva > 0.0 ? 1.0 / inva : r;
+  const double rh = a * cbrt(m / (3.0 * m0));
+  return fmax(n1 * rh, n2 * absdt * sqrt(vv));
+}
+
+// ---- Stumpff functions ------------------------------------------------------
+// c_k(z) = sum_n (-z)^n/(k+2n)!.  Horner series of c2, c3 for |z| < 0.1
+// (eight terms leave < 1e-20); larger |z| is quartered first and rebuilt with
+// c0(4z)=2c0^2-1, c1(4z)=c0 c1, c2(4z)=c1^2/2, c3(4z)=(c2+c0 c3)/4.
+__device__ __forceinline__ void stumpff(double z, double& c0, double& c1,
+                                        double& c2, double& c3) {
+  int nq = 0;
+  while (fabs(z) >= 0.1 && nq < 64) {  // bounded: an infinite z must not spin
+    z *= 0.25;
+    ++nq;
+  }
+  c2 = 1.0 / 2.0 +
+       z * (-1.0 / 24.0 +
+            z * (1.0 / 720.0 +
+                 z * (-1.0 / 40320.0 +
+                      z * (1.0 / 3628800.0 +
+                           z * (-1.0 / 479001600.0 +
+                                z * (1.0 / 87178291200.0 +
+                                     z * (-1.0 / 20922789888000.0)))))));
+  c3 = 1.0 / 6.0 +
+       z * (-1.0 / 120.0 +
+            z * (1.0 / 5040.0 +
+                 z * (-1.0 / 362880.0 +
+                      z * (1.0 / 39916800.0 +
+                           z * (-1.0 / 6227020800.0 +
+                                z * (1.0 / 1307674368000.0 +
+                                     z * (-1.0 / 355687428096000.0)))))));
+  c0 = 1.0 - z * c2;
+  c1 = 1.0 - z * c3;
+  for (int q = 0; q < nq; ++q) {
+    const double a0 = 2.0 * c0 * c0 - 1.0;
+    const double a1 = c0 * c1;
+    const double a2 = 0.5 * c1 * c1;
+    const double a3 = 0.25 * (c2 + c0 * c3);
+    c0 = a0;
+    c1 = a1;
+    c2 = a2;
+    c3 = a3;
+  }
+}
+
+// ---- Kepler drift in universal variables, Eq. (9) ---------------------------
+// x = f x0 + g v0, v = fdot x0 + gdot v0 about mu = G m0.  The universal Kepler
+// equation F(s) = r0 G1 + eta0 G2 + mu G3 - dt = 0 (G_k = s^k c_k(beta s^2),
+// beta = 2 mu/r0 - v0^2) is solved by the Laguerre-Conway iteration of order
+// 5 from s = dt/r0 until |ds| <= 2^-50 |s|.  Returns the iteration count, or
+// a negative count when max_iter was reached without convergence.
+__device__ __forceinline__ int kepler_drift(double mu, double dt, double& x,
+                                            double& y, double& z, double& vx,
+                                            double& vy, double& vz,
+                                            int max_iter) {
+  const double r0 = sqrt(x * x + y * y + z * z);
+  const double eta0 = x * vx + y * vy + z * vz;
+  const double beta = 2.0 * mu / r0 - (vx * vx + vy * vy + vz * vz);
+  const double zeta0 = mu - beta * r0;
+  double s = dt / r0;
+  int it = 1;
+  bool ok = false;
+  for (; it <= max_iter; ++it) {
+    double c0, c1, c2, c3;
+    stumpff(beta * s * s, c0, c1, c2, c3);
+    const double G1 = s * c1, G2 = s * s * c2, G3 = s * s * s * c3;
+    const double F = r0 * G1 + eta0 * G2 + mu * G3 - dt;
+    const double Fp = r0 + eta0 * G1 + zeta0 * G2;
+    const double Fpp = eta0 * c0 + zeta0 * G1;
+    const double disc = 16.0 * Fp * Fp - 20.0 * F * Fpp;
+    const double sq = sqrt(fabs(disc));
+    const double ds = -5.0 * F / (Fp + copysign(sq, Fp));
+    s += ds;
+    if (fabs(ds) <= 0x1p-50 * fabs(s)) {
+      ok = true;
+      break;
+    }
+  }
+  double c0, c1, c2, c3;
+  stumpff(beta * s * s, c0, c1, c2, c3);
+  const double G1 = s * c1, G2 = s * s * c2, G3 = s * s * s * c3;
+  const double r = r0 + eta0 * G1 + zeta0 * G2;
+  const double f = 1.0 - mu * G2 / r0;
+  const double g = dt - mu * G3;
+  const double fd = -mu * G1 / (r * r0);
+  const double gd = 1.0 - mu * G2 / r;
+  const double nx = f * x + g * vx, ny = f * y + g * vy, nz = f * z + g * vz;
+  const double nvx = fd * x + gd * vx, nvy = fd * y + gd * vy,
+               nvz = fd * z + gd * vz;
+  x = nx;
+  y = ny;
+  z = nz;
+  vx = nvx;
+  vy = nvy;
+  vz = nvz;
+  return ok ? it : -max_iter;
+}
+
+// ---- close-encounter test, Eqs. (10)-(12) -----------------------------------
+// Minimum over t in [0,1] of the cubic Hermite interpolant of the squared
+// separation; the stationary points solve a t^2 + b t + c = 0 with
+// a = 6(P0-P1) + 3 dt (Pd0+Pd1) (derivative of Eq. 10; the printed sign of
+// the Pd1 term is a typo), b = 6(P1-P0) - 2 dt (2 Pd0 + Pd1), c = dt Pd0.
+__device__ __forceinline__ double hermite_P(double t, double dt, double P0,
+                                            double P1, double Pd0, double Pd1) {
+  const double u = 1.0 - t;
+  return P0 * (1.0 + 2.0 * t) * u * u + P1 * t * t * (3.0 - 2.0 * t) +
+         Pd0 * dt * t * u * u - Pd1 * dt * t * t * u;
+}
+
+__device__ __forceinline__ double hermite_dmin2(double dt, double dx0,
+                                                double dy0, double dz0,
+                                                double dvx0, double dvy0,
+                                                double dvz0, double dx1,
+                                                double dy1, double dz1,
+                                                double dvx1, double dvy1,
+                                                double dvz1) {
+  const double P0 = dx0 * dx0 + dy0 * dy0 + dz0 * dz0;
+  const double P1 = dx1 * dx1 + dy1 * dy1 + dz1 * dz1;
+  const double Pd0 = 2.0 * (dx0 * dvx0 + dy0 * dvy0 + dz0 * dvz0);
+  const double Pd1 = 2.0 * (dx1 * dvx1 + dy1 * dvy1 + dz1 * dvz1);
+  const double a = 6.0 * (P0 - P1) + 3.0 * dt * (Pd0 + Pd1);
+  const double b = 6.0 * (P1 - P0) - 2.0 * dt * (2.0 * Pd0 + Pd1);
+  const double c = dt * Pd0;
+  double best = fmin(P0, P1);
+  double t1 = -1.0, t2 = -1.0;
+  if (a != 0.0) {
+    const double disc = b * b - 4.0 * a * c;
+    if (disc >= 0.0) {
+      const double q = -0.5 * (b + copysign(sqrt(disc), b));
+      t1 = q / a;
+      if (q != 0.0) t2 = c / q;
+    }
+  } else if (b != 0.0) {
+    t1 = -c / b;
+  }
+  if (t1 > 0.0 && t1 < 1.0) best = fmin(best, hermite_P(t1, dt, P0, P1, Pd0, Pd1));
+  if (t2 > 0.0 && t2 < 1.0) best = fmin(best, hermite_P(t2, dt, P0, P1, Pd0, Pd1));
+  return best;
+}
+
+}  // namespace genga

@@ -1,0 +1,370 @@
+// C ABI of the library (include/genga.h): context, workspace validation,
+// HIP-graph capture of the step, status reporting.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "genga_impl.h"
+
+using namespace genga;
+
+namespace {
+
+constexpr int kGraphSteps = 16;  // steps per captured graph
+
+int status_from_flags(unsigned f) {
+  if (f & F_KEPLER) return GENGA_EKEPLER;
+  if (f & F_BS) return GENGA_EBS;
+  if (f & (F_CAND_OVF | F_ENC_OVF | F_TP_OVF)) return GENGA_EOVERFLOW;
+  if (f & F_GROUP) return GENGA_EGROUP;
+  return GENGA_OK;
+}
+
+bool params_ok(const genga_params* p) {
+  if (!p) return false;
+  const double v[] = {p->G, p->m0, p->dt, p->n1, p->n2, p->pf, p->bs_tol};
+  for (double d : v)
+    if (!std::isfinite(d)) return false;
+  return p->G > 0.0 && p->m0 > 0.0 && p->dt != 0.0 && p->n1 >= 0.0 && p->n2 >= 0.0 &&
+         p->pf >= 1.0 && p->bs_max_depth >= 0 && p->bs_max_depth <= 40 &&
+         p->kepler_max_iter >= 1 && p->cand_per_body >= 1 && p->enc_cap >= 1;
+}
+
+int max_bodies(const genga_params* p) { return p->encounter_free ? 65536 : kGroupMaxN; }
+
+}  // namespace
+
+struct genga_ctx {
+  int mode = GENGA_MASSIVE;
+  genga_params p{};
+  StepConsts c{};
+  MassiveWs w{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t g_many = nullptr;
+  hipGraphExec_t g_one = nullptr;
+  int64_t steps = 0;
+};
+
+#define HIPCHK(expr)                          \
+  do {                                        \
+    if ((expr) != hipSuccess) return GENGA_EHIP; \
+  } while (0)
+
+static int capture(genga_ctx* ctx, int nsteps, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < nsteps && e == hipSuccess; ++k) e = massive_step(ctx->w, ctx->c, ctx->cap);
+  hipError_t e2 = hipStreamEndCapture(ctx->cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return GENGA_EHIP;
+  }
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e == hipSuccess ? GENGA_OK : GENGA_EHIP;
+}
+
+static int read_status(genga_ctx* ctx, DevStat* hs) {
+  HIPCHK(hipMemcpyAsync(hs, ctx->w.st, sizeof(DevStat), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return GENGA_OK;
+}
+
+static int load_state(genga_ctx* ctx, const double* d_m, const double* d_x, const double* d_v,
+                      int coords_in) {
+  const int n = ctx->w.n;
+  HIPCHK(hipMemsetAsync(ctx->w.flag_in, 0, sizeof(int), ctx->stream));
+  if (d_m) HIPCHK(validate_finite(d_m, n, ctx->w.flag_in, ctx->stream));
+  HIPCHK(validate_finite(d_x, 3 * (int64_t)n, ctx->w.flag_in, ctx->stream));
+  HIPCHK(validate_finite(d_v, 3 * (int64_t)n, ctx->w.flag_in, ctx->stream));
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, ctx->w.flag_in, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (bad) return GENGA_EINVAL;
+  const double* m = d_m;
+  HIPCHK(massive_pack(ctx->w, ctx->c, m, d_x, d_v, coords_in, ctx->stream));
+  HIPCHK(massive_prime(ctx->w, ctx->c, ctx->stream));
+  return GENGA_OK;
+}
+
+extern "C" {
+
+void genga_params_default(genga_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->G = 1.0;
+  p->m0 = 1.0;
+  p->dt = 0.02 * M_PI;
+  p->n1 = 3.0;
+  p->n2 = 0.4;
+  p->pf = 3.0;
+  p->bs_tol = 1e-13;
+  p->bs_max_depth = 20;
+  p->kepler_max_iter = 40;
+  p->encounter_free = 0;
+  p->cand_per_body = 32;
+  p->enc_cap = 2048;
+}
+
+size_t genga_workspace_bytes(int mode, const genga_params* p, int n_massive, int64_t n_test,
+                             int n_sys, int64_t n_bodies) {
+  (void)n_test;
+  (void)n_sys;
+  (void)n_bodies;
+  if (!params_ok(p) || mode != GENGA_MASSIVE) return 0;
+  if (n_massive < 1 || n_massive > max_bodies(p)) return 0;
+  return massive_ws_bytes(n_massive, *p);
+}
+
+int genga_init(genga_ctx** out, int mode, const genga_params* p, int n_massive, int64_t n_test,
+               int n_sys, const int32_t* d_offsets, const double* d_m0, const double* d_m,
+               const double* d_x, const double* d_v, int coords_in, void* d_workspace,
+               size_t ws_bytes, void* stream) {
+  (void)n_test;
+  (void)n_sys;
+  (void)d_offsets;
+  (void)d_m0;
+  if (!out) return GENGA_EINVAL;
+  *out = nullptr;
+  if (mode != GENGA_MASSIVE || !params_ok(p)) return GENGA_EINVAL;
+  if (n_massive < 1 || n_massive > max_bodies(p)) return GENGA_EINVAL;
+  if (!d_m || !d_x || !d_v || !d_workspace) return GENGA_EINVAL;
+  if (coords_in != GENGA_HELIO && coords_in != GENGA_DEMOCRATIC) return GENGA_EINVAL;
+  if (((uintptr_t)d_workspace & 255u) != 0) return GENGA_EINVAL;
+  const size_t need = massive_ws_bytes(n_massive, *p);
+  if (ws_bytes < need) return GENGA_ENOMEM;
+  genga_ctx* ctx = new (std::nothrow) genga_ctx();
+  if (!ctx) return GENGA_ENOMEM;
+  ctx->mode = mode;
+  ctx->p = *p;
+  ctx->c = make_consts(*p);
+  ctx->stream = (hipStream_t)stream;
+  massive_carve(ctx->w, n_massive, *p, d_workspace);
+  int rc = GENGA_OK;
+  if (hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) rc = GENGA_EHIP;
+  if (rc == GENGA_OK && hipMemsetAsync(ctx->w.st, 0, sizeof(DevStat), ctx->stream) != hipSuccess)
+    rc = GENGA_EHIP;
+  if (rc == GENGA_OK) rc = load_state(ctx, d_m, d_x, d_v, coords_in);
+  if (rc == GENGA_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = GENGA_EHIP;
+  if (rc != GENGA_OK) {
+    genga_destroy(ctx);
+    return rc;
+  }
+  *out = ctx;
+  return GENGA_OK;
+}
+
+int genga_step(genga_ctx* ctx, int64_t nsteps) {
+  if (!ctx || nsteps < 0) return GENGA_EINVAL;
+  if (nsteps == 0) return GENGA_OK;
+  if (nsteps >= kGraphSteps && !ctx->g_many) {
+    int r = capture(ctx, kGraphSteps, &ctx->g_many);
+    if (r != GENGA_OK) return r;
+  }
+  if (nsteps % kGraphSteps && !ctx->g_one) {
+    int r = capture(ctx, 1, &ctx->g_one);
+    if (r != GENGA_OK) return r;
+  }
+  for (int64_t k = 0; k < nsteps / kGraphSteps; ++k) HIPCHK(hipGraphLaunch(ctx->g_many, ctx->stream));
+  for (int64_t k = 0; k < nsteps % kGraphSteps; ++k) HIPCHK(hipGraphLaunch(ctx->g_one, ctx->stream));
+  ctx->steps += nsteps;
+  return GENGA_OK;
+}
+
+int genga_sync(genga_ctx* ctx) {
+  if (!ctx) return GENGA_EINVAL;
+  DevStat hs;
+  int r = read_status(ctx, &hs);
+  if (r != GENGA_OK) return r;
+  return status_from_flags(hs.flags);
+}
+
+int genga_get_state(genga_ctx* ctx, double* d_x, double* d_v, int coords_out) {
+  if (!ctx || !d_x || !d_v) return GENGA_EINVAL;
+  if (coords_out != GENGA_HELIO && coords_out != GENGA_DEMOCRATIC) return GENGA_EINVAL;
+  HIPCHK(massive_unpack(ctx->w, ctx->c, d_x, d_v, coords_out, ctx->stream));
+  return genga_sync(ctx);
+}
+
+int genga_set_state(genga_ctx* ctx, const double* d_x, const double* d_v, int coords_in) {
+  if (!ctx || !d_x || !d_v) return GENGA_EINVAL;
+  if (coords_in != GENGA_HELIO && coords_in != GENGA_DEMOCRATIC) return GENGA_EINVAL;
+  // masses stay: the pre-drift scratch holds them while the state is repacked
+  double* dm = reinterpret_cast<double*>(ctx->w.xpre);
+  HIPCHK(massive_masses(ctx->w, dm, ctx->stream));
+  int r = load_state(ctx, dm, d_x, d_v, coords_in);
+  if (r != GENGA_OK) return r;
+  return genga_sync(ctx);
+}
+
+int genga_energy(genga_ctx* ctx, double* d_E, double* d_L) {
+  if (!ctx || !d_E || !d_L) return GENGA_EINVAL;
+  HIPCHK(massive_energy(ctx->w, ctx->c, d_E, d_L, ctx->stream));
+  return GENGA_OK;
+}
+
+int genga_encounters(genga_ctx* ctx, int32_t* h_ij, double* h_dmin2, double* h_rc2, int cap,
+                     int* h_n) {
+  if (!ctx || !h_n || cap < 0 || (cap > 0 && !h_ij)) return GENGA_EINVAL;
+  DevStat hs;
+  int r = read_status(ctx, &hs);
+  if (r != GENGA_OK) return r;
+  const int n = ctx->p.encounter_free || ctx->steps == 0 ? 0 : hs.nenc;
+  const int have = std::min(n, ctx->w.enc_cap);
+  std::vector<int2> ij(have);
+  std::vector<double> d2(have), rc2(have);
+  if (have > 0) {
+    HIPCHK(hipMemcpyAsync(ij.data(), ctx->w.encij, have * sizeof(int2), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipMemcpyAsync(d2.data(), ctx->w.encd2, have * sizeof(double), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipMemcpyAsync(rc2.data(), ctx->w.encrc2, have * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  std::vector<int> idx(have);
+  for (int k = 0; k < have; ++k) idx[k] = k;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+    return ij[a].x != ij[b].x ? ij[a].x < ij[b].x : ij[a].y < ij[b].y;
+  });
+  const int wr = std::min(have, cap);
+  for (int k = 0; k < wr; ++k) {
+    h_ij[2 * k] = ij[idx[k]].x;
+    h_ij[2 * k + 1] = ij[idx[k]].y;
+    if (h_dmin2) h_dmin2[k] = d2[idx[k]];
+    if (h_rc2) h_rc2[k] = rc2[idx[k]];
+  }
+  *h_n = n;
+  if (n > cap || n > ctx->w.enc_cap) return GENGA_EOVERFLOW;
+  return status_from_flags(hs.flags);
+}
+
+int genga_candidates(genga_ctx* ctx, int32_t* h_ij, int cap, int* h_n) {
+  if (!ctx || !h_n || cap < 0 || (cap > 0 && !h_ij)) return GENGA_EINVAL;
+  DevStat hs;
+  int r = read_status(ctx, &hs);
+  if (r != GENGA_OK) return r;
+  const int n = ctx->w.n, cpb = ctx->w.cpb;
+  std::vector<int> cnt(n), tab((size_t)n * cpb);
+  HIPCHK(hipMemcpyAsync(cnt.data(), ctx->w.ccnt, n * sizeof(int), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipMemcpyAsync(tab.data(), ctx->w.ctab, (size_t)n * cpb * sizeof(int),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::vector<std::pair<int, int>> pairs;
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < std::min(cnt[i], cpb); ++k)
+      if (tab[(size_t)i * cpb + k] > i) pairs.emplace_back(i, tab[(size_t)i * cpb + k]);
+  std::sort(pairs.begin(), pairs.end());
+  const int np = (int)pairs.size();
+  for (int k = 0; k < std::min(np, cap); ++k) {
+    h_ij[2 * k] = pairs[k].first;
+    h_ij[2 * k + 1] = pairs[k].second;
+  }
+  *h_n = np;
+  if (np > cap) return GENGA_EOVERFLOW;
+  return status_from_flags(hs.flags);
+}
+
+int genga_stats(genga_ctx* ctx, genga_stats_t* s) {
+  if (!ctx || !s) return GENGA_EINVAL;
+  DevStat hs;
+  int r = read_status(ctx, &hs);
+  if (r != GENGA_OK) return r;
+  std::memset(s, 0, sizeof(*s));
+  s->steps = ctx->steps;
+  const bool any = ctx->steps > 0 && !ctx->p.encounter_free;
+  s->n_cand = any ? hs.ncand : 0;
+  s->n_enc = any ? hs.nenc : 0;
+  s->n_groups = any ? hs.ngroups : 0;
+  s->max_group = any ? hs.maxg : 0;
+  s->kepler_iter_max = hs.kep_itmax;
+  s->tp_enc = hs.tp_enc;
+  s->bs_substeps = (int64_t)hs.bs_sub;
+  s->enc_total = (int64_t)hs.enc_total;
+  s->full_kicks = (int64_t)hs.fullkicks;
+  s->tp_enc_total = (int64_t)hs.tp_enc_total;
+  s->flags = hs.flags;
+  return status_from_flags(hs.flags);
+}
+
+const char* genga_strerror(int code) {
+  switch (code) {
+    case GENGA_OK: return "ok";
+    case GENGA_EINVAL: return "invalid argument";
+    case GENGA_EHIP: return "HIP runtime error";
+    case GENGA_EOVERFLOW: return "list capacity exceeded";
+    case GENGA_EKEPLER: return "Kepler iteration did not converge";
+    case GENGA_EBS: return "Bulirsch-Stoer depth exhausted";
+    case GENGA_EADJ_ENCOUNTER: return "pair inside the critical radius in the encounter-free adjoint";
+    case GENGA_ENOMEM: return "workspace too small";
+    case GENGA_EGROUP: return "encounter group too large";
+    default: return "unknown error";
+  }
+}
+
+int genga_destroy(genga_ctx* ctx) {
+  if (!ctx) return GENGA_EINVAL;
+  if (ctx->stream || ctx->cap) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->g_many) (void)hipGraphExecDestroy(ctx->g_many);
+  if (ctx->g_one) (void)hipGraphExecDestroy(ctx->g_one);
+  if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+  delete ctx;
+  return GENGA_OK;
+}
+
+size_t genga_accel_workspace_bytes(int n) {
+  if (n < 1 || n > 65536) return 0;
+  genga_params p;
+  genga_params_default(&p);
+  p.cand_per_body = 1;
+  p.enc_cap = 1;
+  return massive_ws_bytes(n, p);
+}
+
+int genga_accel(const genga_params* p, int n, const double* d_m, const double* d_x,
+                const double* d_rc, double* d_acc, void* d_workspace, size_t ws_bytes,
+                void* stream) {
+  if (!params_ok(p) || n < 1 || n > 65536 || !d_m || !d_x || !d_acc || !d_workspace)
+    return GENGA_EINVAL;
+  if (!p->encounter_free && !d_rc) return GENGA_EINVAL;
+  if (((uintptr_t)d_workspace & 255u) != 0) return GENGA_EINVAL;
+  genga_params q = *p;
+  q.cand_per_body = 1;
+  q.enc_cap = 1;
+  if (ws_bytes < massive_ws_bytes(n, q)) return GENGA_ENOMEM;
+  MassiveWs w;
+  massive_carve(w, n, q, d_workspace);
+  StepConsts c = make_consts(q);
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(massive_pack(w, c, d_m, d_x, d_x, GENGA_DEMOCRATIC, s));
+  HIPCHK(hipMemsetAsync(w.tilecnt, 0, (size_t)w.nitile * sizeof(unsigned), s));
+  HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStat), s));
+  if (!q.encounter_free)
+    HIPCHK(hipMemcpyAsync(w.rc_cur, d_rc, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(thresholds_from_radii(w, c, s));
+  HIPCHK(massive_accel(w, c, d_acc, s));
+  return GENGA_OK;
+}
+
+int genga_kepler(double mu, int64_t n, const double* d_x0, const double* d_v0, double dt,
+                 double* d_x, double* d_v, int max_iter, int32_t* d_iters, void* stream) {
+  if (n < 0 || !(mu > 0.0) || !std::isfinite(dt) || max_iter < 1) return GENGA_EINVAL;
+  if (n > 0 && (!d_x0 || !d_v0 || !d_x || !d_v)) return GENGA_EINVAL;
+  HIPCHK(op_kepler(mu, n, d_x0, d_v0, dt, d_x, d_v, max_iter, d_iters, (hipStream_t)stream));
+  return GENGA_OK;
+}
+
+int genga_hermite(int64_t n, double dt, const double* d_q, double* d_out, void* stream) {
+  if (n < 0 || !std::isfinite(dt)) return GENGA_EINVAL;
+  if (n > 0 && (!d_q || !d_out)) return GENGA_EINVAL;
+  HIPCHK(op_hermite(n, dt, d_q, d_out, (hipStream_t)stream));
+  return GENGA_OK;
+}
+
+}  // extern "C"

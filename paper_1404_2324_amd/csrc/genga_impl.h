@@ -1,0 +1,111 @@
+// Internal declarations of the GENGA MI355X library: device-resident status
+// words, the per-mode workspace views and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/genga.h"
+
+namespace genga {
+
+// latched error bits of the device status word
+enum : unsigned {
+  F_KEPLER = 1u,       // Kepler iteration did not converge
+  F_BS = 2u,           // Bulirsch-Stoer depth exhausted
+  F_CAND_OVF = 4u,     // per-body candidate table full
+  F_ENC_OVF = 8u,      // encounter list full
+  F_GROUP = 16u,       // group larger than the in-wave BS limit
+  F_TP_OVF = 32u,      // more massive bodies than the test-particle mask holds
+};
+// control bits
+enum : unsigned { C_FULLKICK = 1u };
+
+struct DevStat {
+  unsigned flags;      // latched errors
+  unsigned ctl;        // control bits, consumed inside a step
+  int nenc;            // confirmed encounters of the last step
+  int ngroups;         // groups of the last step
+  int maxg;            // largest group of the last step
+  int ncand;           // candidate pairs (i<j) entering the last step
+  int kep_itmax;       // largest Kepler iteration count seen
+  int tp_enc;          // test-particle encounters of the last step
+  unsigned long long bs_sub;     // accepted BS substeps (cumulative)
+  unsigned long long enc_total;  // encounters (cumulative)
+  unsigned long long fullkicks;  // opening kicks recomputed in full
+  unsigned long long tp_enc_total;
+};
+
+constexpr int kBsMaxGroup = 64;        // members per in-wave BS group
+constexpr int kGroupMaxN = 2048;       // bodies the one-workgroup grouping holds
+constexpr int kEncLds = 2048;          // encounter pairs grouped in LDS
+constexpr int kKickWaves = 8;          // waves per kick workgroup
+constexpr int kKickIpl = 1;            // i-bodies per lane in the kick
+constexpr int kVecBlock = 256;         // threads of the per-body kernels
+
+// Views into the caller's workspace for main mode (also the massive part of
+// test-particle mode).  Bodies are padded to np (a multiple of 256).
+struct MassiveWs {
+  int n, np, njb, jb_len, nitile, nblk;
+  int cpb;              // candidate slots per body
+  int enc_cap;
+  double4* xm;          // x, y, z, m          (democratic: heliocentric x)
+  double4* vv;          // vx, vy, vz, 0       (barycentric v)
+  double4* xpre;        // pre-drift x
+  double4* vpre;        // pre-drift v
+  double4* afar;        // acceleration of non-candidate pairs (x G)
+  double4* part;        // kick partials [njb][np][2]
+  double* rc_cur;       // radii of the current step
+  double* rc_next;      // radii for the next step
+  double* thr;          // max((pf rc)^2, tiny): candidate threshold
+  double* partP;        // momentum partials [nblk][4]
+  double* red;          // scratch for reductions (energy, conversions)
+  int* ccnt;            // candidates per body
+  int* ctab;            // candidate partners [np][cpb]
+  unsigned* tilecnt;    // kick last-block counters [nitile]
+  int2* encij;          // encounter pairs of the last step
+  double* encd2;
+  double* encrc2;
+  int* goff;            // group offsets [np+1]
+  int* gmem;            // group members [np]
+  int* flag_in;         // input validation flag
+  DevStat* st;
+};
+
+struct StepConsts {
+  double G, m0, mu, dt, h, n1, n2, pf, pf2, bs_tol;
+  int bs_max_depth, kepler_max_iter, encounter_free;
+};
+
+StepConsts make_consts(const genga_params& p);
+
+// ---- main-mode launchers (massive.hip) --------------------------------------
+size_t massive_ws_bytes(int n, const genga_params& p);
+size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base);
+hipError_t validate_finite(const double* a, int64_t cnt, int* dbad,
+                           hipStream_t s);
+hipError_t massive_pack(const MassiveWs& w, const StepConsts& c,
+                        const double* m, const double* x, const double* v,
+                        int coords_in, hipStream_t s);
+hipError_t massive_unpack(const MassiveWs& w, const StepConsts& c, double* x,
+                          double* v, int coords_out, hipStream_t s);
+hipError_t massive_prime(const MassiveWs& w, const StepConsts& c,
+                         hipStream_t s);
+hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s);
+hipError_t massive_energy(const MassiveWs& w, const StepConsts& c, double* dE,
+                          double* dL, hipStream_t s);
+hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, double* acc,
+                         hipStream_t s);
+hipError_t thresholds_from_radii(const MassiveWs& w, const StepConsts& c,
+                                 hipStream_t s);
+hipError_t massive_masses(const MassiveWs& w, double* m, hipStream_t s);
+
+// ---- single-operation kernels for component checks (ops.hip) ---------------
+hipError_t op_kepler(double mu, int64_t n, const double* x0, const double* v0,
+                     double dt, double* x, double* v, int max_iter, int* iters,
+                     hipStream_t s);
+hipError_t op_hermite(int64_t n, double dt, const double* q, double* out,
+                      hipStream_t s);
+
+}  // namespace genga

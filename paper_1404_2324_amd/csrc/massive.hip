@@ -1,0 +1,1200 @@
+// Main-mode kernels of the hybrid symplectic step (Grimm & Stadel,
+// arXiv:1404.2324, Sec. 2.2 step recipe and Sec. 3.2 kernels), for gfx950.
+//
+// One step is six launches on one stream (captured once into a HIP graph):
+//   k_kick_open  opening kick: cached non-candidate acceleration + candidate
+//                pairs recomputed with the new radii (KickA/KickB, Sec 3.2.3)
+//   k_drift      Sun kick tau/2 (Eq. 3) + pre-drift copy + Kepler drift (Eq. 9)
+//   k_enc_group  Hermite test of the candidates (Eqs. 10-12) with ballot
+//                compaction, then equivalence classes in LDS (App. A)
+//   k_bs         Bulirsch-Stoer integration of H_A per group, one wave each
+//   k_sun2       Sun kick tau/2 and reset of the candidate table
+//   k_kick       closing kick: all pairs, prechecker, next radii (Eq. 6)
+#include <climits>
+
+#include "device_math.h"
+#include "genga_impl.h"
+
+namespace genga {
+
+namespace {
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+__device__ __forceinline__ unsigned lanemask_count(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// Deterministic sum over a block of NT threads; every thread gets the total.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  constexpr int NW = NT / 64;
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) t += sh[k];
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+struct KickArgs {
+  const double4* __restrict__ xm;
+  const double* __restrict__ thr;
+  const double* __restrict__ rc;
+  double4* __restrict__ part;
+  unsigned* __restrict__ tilecnt;
+  int* __restrict__ ccnt;
+  int* __restrict__ ctab;
+  double4* __restrict__ vv;
+  double4* __restrict__ afar;
+  double* __restrict__ rc_next;
+  double* __restrict__ acc_out;
+  DevStat* __restrict__ st;
+  int n, np, jb_len, cpb;
+  int encounter_free;
+  double G, h, m0, mu, n1, n2, absdt, pf;
+};
+
+enum { KICK_CLOSE = 0, KICK_INIT = 1, KICK_ACC = 2 };
+
+// All-pairs kick of H_B (Eq. 2 gradient) with the prechecker.
+// Grid (ceil(n/64), njb); a workgroup holds 64 i-bodies (one per lane) and a
+// j-range split over its waves.  j-data is wave-uniform and read through the
+// scalar cache into SGPRs; the FP64 pair loop runs on the VALU.  Pairs with
+// r^2 < max((pf rc_i)^2, (pf rc_j)^2) are candidates: their K-weighted term is
+// summed apart ("near") and appended to the per-body candidate table; all
+// other pairs have K = 1 and form the reusable "far" sum.  The per-j-block
+// partials are combined in a fixed order by the last workgroup of each i-tile.
+template <int MODE>
+__global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a) {
+  constexpr int W = kKickWaves;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int i = blockIdx.x * 64 + lane;
+  const bool iv = i < a.n;
+  double xi = 0.0, yi = 0.0, zi = 0.0, ti = kTiny;
+  if (iv) {
+    const double4 p = a.xm[i];
+    xi = p.x;
+    yi = p.y;
+    zi = p.z;
+    ti = a.thr[i];
+  }
+  const int jb = blockIdx.y;
+  const int j0 = jb * a.jb_len;
+  const int j1 = min(a.n, j0 + a.jb_len);
+  const int wl = (max(0, j1 - j0) + W - 1) / W;
+  const int js = j0 + wave * wl;
+  const int je = min(j1, js + wl);
+
+  double fx = 0.0, fy = 0.0, fz = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
+#pragma unroll 4
+  for (int j = js; j < je; ++j) {
+    const double4 pj = a.xm[j];
+    const double tj = a.thr[j];
+    const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r = sqrt(r2);
+    const double s = pj.w / (r2 * r);
+    const bool cand = r2 < fmax(ti, tj);
+    const double sf = cand ? 0.0 : s;
+    fx += sf * dx;
+    fy += sf * dy;
+    fz += sf * dz;
+    if (__builtin_expect(cand, 0)) {
+      if (iv && j != i) {
+        double K = 1.0, dK = 0.0;
+        if (!a.encounter_free) changeover(r, fmax(a.rc[i], a.rc[j]), K, dK);
+        const double sn = pj.w * (K / (r2 * r) - dK / r2);
+        nx += sn * dx;
+        ny += sn * dy;
+        nz += sn * dz;
+        if (MODE != KICK_ACC && !a.encounter_free) {
+          const int slot = atomicAdd(&a.ccnt[i], 1);
+          if (slot < a.cpb)
+            a.ctab[(size_t)i * a.cpb + slot] = j;
+          else
+            atomicOr(&a.st->flags, F_CAND_OVF);
+        }
+      }
+    }
+  }
+
+  __shared__ double sh[W][6][64];
+  sh[wave][0][lane] = fx;
+  sh[wave][1][lane] = fy;
+  sh[wave][2][lane] = fz;
+  sh[wave][3][lane] = nx;
+  sh[wave][4][lane] = ny;
+  sh[wave][5][lane] = nz;
+  __syncthreads();
+  if (threadIdx.x < 6 * 64) {
+    const int c = threadIdx.x >> 6;
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) t += sh[w][c][lane];
+    sh[0][c][lane] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64 && iv) {
+    double4* q = &a.part[((size_t)jb * a.np + i) * 2];
+    q[0] = make_double4(sh[0][0][lane], sh[0][1][lane], sh[0][2][lane], 0.0);
+    q[1] = make_double4(sh[0][3][lane], sh[0][4][lane], sh[0][5][lane], 0.0);
+  }
+  __threadfence();
+  __syncthreads();
+  __shared__ int s_last;
+  if (threadIdx.x == 0) {
+    const unsigned old = atomicAdd(&a.tilecnt[blockIdx.x], 1u);
+    s_last = (old == gridDim.y - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (threadIdx.x == 0) a.tilecnt[blockIdx.x] = 0u;
+  if (threadIdx.x >= 64 || !iv) return;
+
+  double S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0;
+  for (int b = 0; b < (int)gridDim.y; ++b) {
+    const double4* q = &a.part[((size_t)b * a.np + i) * 2];
+    const double4 f = q[0];
+    const double4 g = q[1];
+    S0 += f.x;
+    S1 += f.y;
+    S2 += f.z;
+    S3 += g.x;
+    S4 += g.y;
+    S5 += g.z;
+  }
+  const double G = a.G;
+  if (MODE == KICK_ACC) {
+    a.acc_out[3 * (size_t)i + 0] = G * (S0 + S3);
+    a.acc_out[3 * (size_t)i + 1] = G * (S1 + S4);
+    a.acc_out[3 * (size_t)i + 2] = G * (S2 + S5);
+    return;
+  }
+  a.afar[i] = make_double4(G * S0, G * S1, G * S2, 0.0);
+  if (MODE == KICK_INIT) {
+    a.rc_next[i] = a.rc[i];
+    return;
+  }
+  double4 v = a.vv[i];
+  v.x += a.h * (G * (S0 + S3));
+  v.y += a.h * (G * (S1 + S4));
+  v.z += a.h * (G * (S2 + S5));
+  a.vv[i] = v;
+  const double4 p = a.xm[i];
+  const double rcn =
+      rcrit(p.x, p.y, p.z, v.x, v.y, v.z, p.w, a.mu, a.m0, a.n1, a.n2, a.absdt);
+  a.rc_next[i] = rcn;
+  if (!a.encounter_free && rcn > a.pf * a.rc[i]) atomicOr(&a.st->ctl, C_FULLKICK);
+}
+
+// ---------------------------------------------------------------------------
+struct OpenArgs {
+  const double4* __restrict__ xm;
+  double4* __restrict__ vv;
+  const double4* __restrict__ afar;
+  const double* __restrict__ rc_next;
+  double* __restrict__ rc_cur;
+  double* __restrict__ thr;
+  const int* __restrict__ ccnt;
+  const int* __restrict__ ctab;
+  double* __restrict__ partP;
+  DevStat* __restrict__ st;
+  int n, cpb, encounter_free;
+  double G, h, pf2;
+};
+
+__device__ __forceinline__ void pair_hb(double xi, double yi, double zi,
+                                        double rci, const double4 pj,
+                                        double rcj, int enc_free, double& ax,
+                                        double& ay, double& az) {
+  const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double r = sqrt(r2);
+  double K = 1.0, dK = 0.0;
+  if (!enc_free) changeover(r, fmax(rci, rcj), K, dK);
+  const double s = pj.w * (K / (r2 * r) - dK / r2);
+  ax += s * dx;
+  ay += s * dy;
+  az += s * dz;
+}
+
+// Opening kick (KickA/KickB, Sec. 3.2.3): the closing kick's non-candidate
+// sum is reused; candidate pairs are recomputed with this step's radii in
+// ascending partner order.  When some radius grew beyond pf times the radius
+// that formed the candidate table the reuse is not exact and the full pair
+// sum is taken instead.  Also installs the step's radii and thresholds and
+// leaves per-block momentum partials for the Sun kick.
+__global__ __launch_bounds__(kVecBlock) void k_kick_open(OpenArgs a) {
+  __shared__ double sh[kVecBlock / 64];
+  const int i = blockIdx.x * kVecBlock + threadIdx.x;
+  const bool iv = i < a.n;
+  const bool full = (__builtin_amdgcn_readfirstlane(a.st->ctl) & C_FULLKICK) != 0;
+  double m = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
+  if (iv) {
+    const double4 p = a.xm[i];
+    const double rci = a.rc_next[i];
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    if (full) {
+      for (int j = 0; j < a.n; ++j)
+        if (j != i) pair_hb(p.x, p.y, p.z, rci, a.xm[j], a.rc_next[j], a.encounter_free, ax, ay, az);
+      ax *= a.G;
+      ay *= a.G;
+      az *= a.G;
+    } else {
+      const double4 af = a.afar[i];
+      const int cnt = min(a.ccnt[i], a.cpb);
+      const int* row = a.ctab + (size_t)i * a.cpb;
+      double cx = 0.0, cy = 0.0, cz = 0.0;
+      int prev = -1;
+      for (int t = 0; t < cnt; ++t) {
+        int jm = INT_MAX;
+        for (int u = 0; u < cnt; ++u) {
+          const int j = row[u];
+          jm = (j > prev && j < jm) ? j : jm;
+        }
+        if (jm == INT_MAX) break;
+        prev = jm;
+        pair_hb(p.x, p.y, p.z, rci, a.xm[jm], a.rc_next[jm], a.encounter_free, cx, cy, cz);
+      }
+      ax = af.x + a.G * cx;
+      ay = af.y + a.G * cy;
+      az = af.z + a.G * cz;
+    }
+    double4 v = a.vv[i];
+    v.x += a.h * ax;
+    v.y += a.h * ay;
+    v.z += a.h * az;
+    a.vv[i] = v;
+    a.rc_cur[i] = rci;
+    a.thr[i] = a.encounter_free ? kTiny : fmax(a.pf2 * rci * rci, kTiny);
+    m = p.w;
+    vx = v.x;
+    vy = v.y;
+    vz = v.z;
+  }
+  const double Px = block_sum<kVecBlock>(m * vx, sh);
+  const double Py = block_sum<kVecBlock>(m * vy, sh);
+  const double Pz = block_sum<kVecBlock>(m * vz, sh);
+  if (threadIdx.x == 0) {
+    a.partP[4 * blockIdx.x + 0] = Px;
+    a.partP[4 * blockIdx.x + 1] = Py;
+    a.partP[4 * blockIdx.x + 2] = Pz;
+    if (full && blockIdx.x == 0) atomicAdd(&a.st->fullkicks, 1ull);
+  }
+}
+
+// ---------------------------------------------------------------------------
+struct DriftArgs {
+  double4* __restrict__ xm;
+  double4* __restrict__ vv;
+  double4* __restrict__ xpre;
+  double4* __restrict__ vpre;
+  const double* __restrict__ partP;
+  DevStat* __restrict__ st;
+  int n, nblk, max_iter;
+  double h, m0, mu, dt;
+};
+
+// Sun kick tau/2 (H_C flow: x += tau/2 P/m0, Eq. 3) with P summed from the
+// opening kick's block partials, copy of the pre-drift state, Kepler drift.
+__global__ __launch_bounds__(kVecBlock) void k_drift(DriftArgs a) {
+  double Px = 0.0, Py = 0.0, Pz = 0.0;
+  for (int b = 0; b < a.nblk; ++b) {
+    Px += a.partP[4 * b + 0];
+    Py += a.partP[4 * b + 1];
+    Pz += a.partP[4 * b + 2];
+  }
+  const int i = blockIdx.x * kVecBlock + threadIdx.x;
+  int it = 0;
+  if (i < a.n) {
+    const double4 p = a.xm[i];
+    const double4 q = a.vv[i];
+    double x = p.x + a.h * Px / a.m0;
+    double y = p.y + a.h * Py / a.m0;
+    double z = p.z + a.h * Pz / a.m0;
+    double vx = q.x, vy = q.y, vz = q.z;
+    a.xpre[i] = make_double4(x, y, z, 0.0);
+    a.vpre[i] = q;
+    it = kepler_drift(a.mu, a.dt, x, y, z, vx, vy, vz, a.max_iter);
+    if (it < 0) atomicOr(&a.st->flags, F_KEPLER);
+    a.xm[i] = make_double4(x, y, z, p.w);
+    a.vv[i] = make_double4(vx, vy, vz, 0.0);
+  }
+  const int itm = wave_max_i(abs(it));
+  if ((threadIdx.x & 63) == 0 && itm > 0) atomicMax(&a.st->kep_itmax, itm);
+}
+
+// ---------------------------------------------------------------------------
+struct EncArgs {
+  const double4* __restrict__ xm;
+  const double4* __restrict__ vv;
+  const double4* __restrict__ xpre;
+  const double4* __restrict__ vpre;
+  const double* __restrict__ rc;
+  const int* __restrict__ ccnt;
+  const int* __restrict__ ctab;
+  int2* __restrict__ encij;
+  double* __restrict__ encd2;
+  double* __restrict__ encrc2;
+  int* __restrict__ goff;
+  int* __restrict__ gmem;
+  DevStat* __restrict__ st;
+  int n, cpb, enc_cap;
+  double dt;
+};
+
+constexpr int kEncThreads = 1024;
+
+// Exclusive scan over a block of 1024 threads; returns the prefix and puts the
+// total in *total.
+__device__ __forceinline__ int block_excl_scan(int v, int* shw, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  __syncthreads();
+  if (lane == 63) shw[w] = incl;
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int k = 0; k < kEncThreads / 64; ++k) {
+    if (k < w) base += shw[k];
+    tot += shw[k];
+  }
+  *total = tot;
+  return base + incl - v;
+}
+
+// Encounter search (Sec. 3.2.4) over the prechecker's candidates, then the
+// equivalence classes of the encounter pairs (App. A): LINK starts as the
+// identity, every pair lowers both ends to the smaller link (LDS atomic
+// min), links are shortened by LINK[i] = LINK[LINK[i]], and both sweeps
+// repeat until nothing changes.  Groups are numbered by their smallest
+// member; offsets and members go to global memory for the BS kernel.
+__global__ __launch_bounds__(kEncThreads) void k_enc_group(EncArgs a) {
+  __shared__ int link[kGroupMaxN];
+  __shared__ int gid[kGroupMaxN];
+  __shared__ int2 pr[kEncLds];
+  __shared__ int gsz[kGroupMaxN / 2 + 1];
+  __shared__ int gof[kGroupMaxN / 2 + 1];
+  __shared__ unsigned char inp[kGroupMaxN];
+  __shared__ int shw[kEncThreads / 64];
+  __shared__ int s_ne, s_changed;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int n = a.n;
+  if (tid == 0) s_ne = 0;
+  for (int i = tid; i < n; i += kEncThreads) {
+    link[i] = i;
+    inp[i] = 0;
+  }
+  __syncthreads();
+
+  int ncl = 0;
+  for (int base = 0; base < n; base += kEncThreads) {
+    const int i = base + tid;
+    const int cnt = i < n ? min(a.ccnt[i], a.cpb) : 0;
+    for (int k = 0; k < cnt; ++k) {
+      const int j = a.ctab[(size_t)i * a.cpb + k];
+      bool enc = false;
+      double d2 = 0.0, rc2 = 0.0;
+      if (j > i) {
+        ++ncl;
+        const double4 xi0 = a.xpre[i], xj0 = a.xpre[j], vi0 = a.vpre[i], vj0 = a.vpre[j];
+        const double4 xi1 = a.xm[i], xj1 = a.xm[j], vi1 = a.vv[i], vj1 = a.vv[j];
+        d2 = hermite_dmin2(a.dt, xj0.x - xi0.x, xj0.y - xi0.y, xj0.z - xi0.z,
+                           vj0.x - vi0.x, vj0.y - vi0.y, vj0.z - vi0.z,
+                           xj1.x - xi1.x, xj1.y - xi1.y, xj1.z - xi1.z,
+                           vj1.x - vi1.x, vj1.y - vi1.y, vj1.z - vi1.z);
+        const double rcij = fmax(a.rc[i], a.rc[j]);
+        rc2 = rcij * rcij;
+        enc = d2 < rc2;
+      }
+      // ballot compaction: one LDS atomic per wave and iteration
+      const unsigned long long act = __ballot(1);
+      const unsigned long long msk = __ballot(enc);
+      const int leader = __ffsll((long long)act) - 1;
+      int b0 = 0;
+      if (lane == leader && msk) b0 = atomicAdd(&s_ne, __popcll(msk));
+      b0 = __shfl(b0, leader, 64);
+      if (enc) {
+        const int pos = b0 + (int)lanemask_count(msk);
+        if (pos < kEncLds) pr[pos] = make_int2(i, j);
+        if (pos < a.enc_cap) {
+          a.encij[pos] = make_int2(i, j);
+          a.encd2[pos] = d2;
+          a.encrc2[pos] = rc2;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int ne_all = s_ne;
+  const int ne = min(ne_all, kEncLds);
+  for (int e = tid; e < ne; e += kEncThreads) {
+    inp[pr[e].x] = 1;
+    inp[pr[e].y] = 1;
+  }
+  // equivalence classes
+  while (true) {
+    if (tid == 0) s_changed = 0;
+    __syncthreads();
+    bool ch = false;
+    for (int e = tid; e < ne; e += kEncThreads) {
+      const int p1 = pr[e].x, p2 = pr[e].y;
+      const int l1 = link[p1], l2 = link[p2];
+      if (l1 != l2) {
+        atomicMin(&link[p1], l2);
+        atomicMin(&link[p2], l1);
+        ch = true;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += kEncThreads) {
+      const int l = link[i];
+      const int ll = link[l];
+      if (ll < l) {
+        atomicMin(&link[i], ll);
+        ch = true;
+      }
+    }
+    if (ch) s_changed = 1;
+    __syncthreads();
+    if (!s_changed) break;
+    __syncthreads();
+  }
+  // consecutive group ids in order of the smallest member
+  constexpr int PER = kGroupMaxN / kEncThreads;
+  int cntr = 0;
+  for (int k = 0; k < PER; ++k) {
+    const int i = tid * PER + k;
+    if (i < n && inp[i] && link[i] == i) ++cntr;
+  }
+  int ng = 0;
+  int off = block_excl_scan(cntr, shw, &ng);
+  for (int k = 0; k < PER; ++k) {
+    const int i = tid * PER + k;
+    if (i < n && inp[i] && link[i] == i) gid[i] = off++;
+  }
+  for (int g = tid; g <= ng; g += kEncThreads) gsz[g] = 0;
+  __syncthreads();
+  for (int i = tid; i < n; i += kEncThreads)
+    if (inp[i]) atomicAdd(&gsz[gid[link[i]]], 1);
+  __syncthreads();
+  // offsets: exclusive scan of the sizes
+  constexpr int GPER = (kGroupMaxN / 2 + kEncThreads - 1) / kEncThreads;
+  int loc = 0, mx = 0;
+  for (int k = 0; k < GPER; ++k) {
+    const int g = tid * GPER + k;
+    if (g < ng) {
+      loc += gsz[g];
+      mx = max(mx, gsz[g]);
+    }
+  }
+  int tot = 0;
+  int o2 = block_excl_scan(loc, shw, &tot);
+  for (int k = 0; k < GPER; ++k) {
+    const int g = tid * GPER + k;
+    if (g < ng) {
+      gof[g] = o2;
+      a.goff[g] = o2;
+      o2 += gsz[g];
+    }
+  }
+  if (tid == 0) a.goff[ng] = tot;
+  mx = wave_max_i(mx);
+  __syncthreads();
+  if (lane == 0) shw[tid >> 6] = mx;
+  for (int g = tid; g < ng; g += kEncThreads) gsz[g] = 0;
+  __syncthreads();
+  if (tid == 0) {
+    int m2 = 0;
+    for (int k = 0; k < kEncThreads / 64; ++k) m2 = max(m2, shw[k]);
+    a.st->maxg = m2;
+    a.st->ngroups = ng;
+    a.st->nenc = ne_all;
+    a.st->enc_total += (unsigned long long)ne_all;
+    if (ne_all > kEncLds || ne_all > a.enc_cap) atomicOr(&a.st->flags, F_ENC_OVF);
+  }
+  for (int i = tid; i < n; i += kEncThreads) {
+    if (inp[i]) {
+      const int g = gid[link[i]];
+      const int pos = gof[g] + atomicAdd(&gsz[g], 1);
+      a.gmem[pos] = i;
+    }
+  }
+  // candidate count for the statistics
+  __syncthreads();
+  int tc = 0;
+  const int csum = block_excl_scan(ncl, shw, &tc);
+  (void)csum;
+  if (tid == 0) a.st->ncand = tc;
+}
+
+// ---------------------------------------------------------------------------
+struct BsArgs {
+  double4* __restrict__ xm;
+  double4* __restrict__ vv;
+  const double4* __restrict__ xpre;
+  const double4* __restrict__ vpre;
+  const double* __restrict__ rc;
+  const int* __restrict__ goff;
+  const int* __restrict__ gmem;
+  DevStat* __restrict__ st;
+  double G, Gm0, dt, tol;
+  int max_depth;
+};
+
+constexpr int kBsCols = 8;
+constexpr int kBsMaxAttempts = 1 << 16;  // substep attempts per group and step
+
+// dv/dt of H_A for the lane's body: the fixed star plus the (1-K) part of the
+// group's pair terms (Eq. 1 gradient); other members' data by lane reads.
+__device__ __forceinline__ void ha_accel(int sz, int lane, double x, double y,
+                                         double z, double m, double rc,
+                                         double G, double Gm0, double& ax,
+                                         double& ay, double& az) {
+  const double r2 = x * x + y * y + z * z;
+  const double r = sqrt(r2);
+  const double fs = -Gm0 / (r2 * r);
+  ax = fs * x;
+  ay = fs * y;
+  az = fs * z;
+  for (int j = 0; j < sz; ++j) {
+    const double xj = readlane_d(x, j), yj = readlane_d(y, j), zj = readlane_d(z, j);
+    const double mj = readlane_d(m, j), rcj = readlane_d(rc, j);
+    if (j != lane) {
+      const double dx = xj - x, dy = yj - y, dz = zj - z;
+      const double q2 = dx * dx + dy * dy + dz * dz;
+      const double q = sqrt(q2);
+      double K, dK;
+      changeover(q, fmax(rc, rcj), K, dK);
+      const double s = G * mj * ((1.0 - K) / (q2 * q) + dK / q2);
+      ax += s * dx;
+      ay += s * dy;
+      az += s * dz;
+    }
+  }
+}
+
+// Gragg's modified midpoint rule over H with nsub substeps (one wave, one
+// body per lane).
+__device__ void mmid(int sz, int lane, const double y0[6], double H, int nsub,
+                     double m, double rc, double G, double Gm0, double out[6]) {
+  const double hs = H / nsub;
+  double ym[6], yn[6], d[6];
+  ha_accel(sz, lane, y0[0], y0[1], y0[2], m, rc, G, Gm0, d[3], d[4], d[5]);
+  d[0] = y0[3];
+  d[1] = y0[4];
+  d[2] = y0[5];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    ym[c] = y0[c];
+    yn[c] = y0[c] + hs * d[c];
+  }
+  for (int s = 1; s < nsub; ++s) {
+    ha_accel(sz, lane, yn[0], yn[1], yn[2], m, rc, G, Gm0, d[3], d[4], d[5]);
+    d[0] = yn[3];
+    d[1] = yn[4];
+    d[2] = yn[5];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double t = ym[c] + 2.0 * hs * d[c];
+      ym[c] = yn[c];
+      yn[c] = t;
+    }
+  }
+  ha_accel(sz, lane, yn[0], yn[1], yn[2], m, rc, G, Gm0, d[3], d[4], d[5]);
+  d[0] = yn[3];
+  d[1] = yn[4];
+  d[2] = yn[5];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) out[c] = 0.5 * (ym[c] + yn[c] + hs * d[c]);
+}
+
+__device__ __forceinline__ double relerr3(const double* A, const double* B) {
+  const double d0 = A[0] - B[0], d1 = A[1] - B[1], d2 = A[2] - B[2];
+  const double num = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  const double den = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+  return den > 0.0 ? num / den : num;
+}
+
+// One BS attempt over H: columns n_k = 2k (k = 1..8), Aitken-Neville
+// extrapolation in h^2 kept in LDS (R[col][comp][lane]), accepted at the first
+// column k >= 2 whose per-body relative error (max over the group) is within
+// tol.  Returns true and the extrapolated state in y on success.
+__device__ bool bs_attempt(int sz, int lane, double y[6], double H, double m,
+                           double rc, double G, double Gm0, double tol,
+                           double (*R)[6][64]) {
+  for (int k = 0; k < kBsCols; ++k) {
+    const int nk = 2 * (k + 1);
+    double t[6];
+    mmid(sz, lane, y, H, nk, m, rc, G, Gm0, t);
+    for (int j = 1; j <= k; ++j) {
+      const double ratio = (double)nk / (double)(2 * (k - j + 1));
+      const double den = ratio * ratio - 1.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double u = t[c] + (t[c] - R[j - 1][c][lane]) / den;
+        R[j - 1][c][lane] = t[c];
+        t[c] = u;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) R[k][c][lane] = t[c];
+    if (k >= 1) {
+      double A[6], B[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        A[c] = R[k][c][lane];
+        B[c] = R[k - 1][c][lane];
+      }
+      double e = fmax(relerr3(A, B), relerr3(A + 3, B + 3));
+      if (lane >= sz) e = 0.0;
+      e = wave_max(e);
+      if (e <= tol) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) y[c] = A[c];
+        return true;
+      }
+    }
+  }
+  return false;
+}
+
+// Binary refinement over [0, H]: a failed substep is halved; after finishing
+// both halves of a node the next sibling is tried at the node's length.
+__device__ int bs_integrate(int sz, int lane, double y[6], double H, double m,
+                            double rc, double G, double Gm0, double tol,
+                            int D, double (*R)[6][64], long long* nsub) {
+  long long pos = 0;
+  const long long total = 1ll << D;
+  int d = 0;
+  int attempts = 0;
+  while (pos < total) {
+    if (++attempts > kBsMaxAttempts) return -1;
+    double yt[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) yt[c] = y[c];
+    if (bs_attempt(sz, lane, yt, ldexp(H, -d), m, rc, G, Gm0, tol, R)) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) y[c] = yt[c];
+      ++*nsub;
+      pos += 1ll << (D - d);
+      while (d > 0 && (pos % (1ll << (D - d + 1))) == 0) --d;
+    } else {
+      ++d;
+      if (d > D) return -1;
+    }
+  }
+  return 0;
+}
+
+// One wave per encounter group (grid-stride over the device-side count):
+// members sorted ascending, state reset to the pre-drift copy, H_A integrated
+// over tau by BS, result written back.
+__global__ __launch_bounds__(64) void k_bs(BsArgs a) {
+  __shared__ double R[kBsCols][6][64];
+  __shared__ int mem[64];
+  const int lane = threadIdx.x;
+  const int ng = __builtin_amdgcn_readfirstlane(a.st->ngroups);
+  long long nsub = 0;
+  for (int g = blockIdx.x; g < ng; g += gridDim.x) {
+    const int o = a.goff[g];
+    const int sz = a.goff[g + 1] - o;
+    if (sz > kBsMaxGroup) {
+      if (lane == 0) atomicOr(&a.st->flags, F_GROUP);
+      continue;
+    }
+    const int my = lane < sz ? a.gmem[o + lane] : INT_MAX;
+    int rank = 0;
+    for (int q = 0; q < sz; ++q) rank += (__builtin_amdgcn_readlane(my, q) < my) ? 1 : 0;
+    __syncthreads();
+    if (lane < sz) mem[rank] = my;
+    __syncthreads();
+    const int b = lane < sz ? mem[lane] : -1;
+    double y[6] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double m = 0.0, rc = 0.0;
+    if (b >= 0) {
+      const double4 p = a.xpre[b], q = a.vpre[b];
+      y[0] = p.x;
+      y[1] = p.y;
+      y[2] = p.z;
+      y[3] = q.x;
+      y[4] = q.y;
+      y[5] = q.z;
+      m = a.xm[b].w;
+      rc = a.rc[b];
+    }
+    const int r = bs_integrate(sz, lane, y, a.dt, m, rc, a.G, a.Gm0, a.tol,
+                               a.max_depth, R, &nsub);
+    if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
+    if (b >= 0) {
+      a.xm[b] = make_double4(y[0], y[1], y[2], m);
+      a.vv[b] = make_double4(y[3], y[4], y[5], 0.0);
+    }
+  }
+  if (lane == 0 && nsub > 0) atomicAdd(&a.st->bs_sub, (unsigned long long)nsub);
+}
+
+// ---------------------------------------------------------------------------
+// Second Sun kick of the step (one workgroup): P from the current velocities,
+// x += tau/2 P/m0; clears the candidate counters and the control word for the
+// closing kick.
+__global__ __launch_bounds__(1024) void k_sun2(double4* __restrict__ xm,
+                                               const double4* __restrict__ vv,
+                                               int* __restrict__ ccnt,
+                                               DevStat* __restrict__ st, int n,
+                                               double h, double m0) {
+  __shared__ double sh[16];
+  double px = 0.0, py = 0.0, pz = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    const double m = xm[i].w;
+    const double4 v = vv[i];
+    px += m * v.x;
+    py += m * v.y;
+    pz += m * v.z;
+  }
+  const double Px = block_sum<1024>(px, sh);
+  const double Py = block_sum<1024>(py, sh);
+  const double Pz = block_sum<1024>(pz, sh);
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    double4 p = xm[i];
+    p.x += h * Px / m0;
+    p.y += h * Py / m0;
+    p.z += h * Pz / m0;
+    xm[i] = p;
+    ccnt[i] = 0;
+  }
+  if (threadIdx.x == 0) st->ctl = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// packing, coordinates, radii, energy
+
+// P = sum m v and M = sum m over n bodies given as n x 3 (src3) or double4.
+__global__ __launch_bounds__(1024) void k_momentum(const double* __restrict__ m,
+                                                   const double* __restrict__ v3,
+                                                   const double4* __restrict__ xm,
+                                                   const double4* __restrict__ vv,
+                                                   int n, double* __restrict__ out) {
+  __shared__ double sh[16];
+  double px = 0.0, py = 0.0, pz = 0.0, mm = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    double mi, vx, vy, vz;
+    if (v3) {
+      mi = m[i];
+      vx = v3[3 * i];
+      vy = v3[3 * i + 1];
+      vz = v3[3 * i + 2];
+    } else {
+      mi = xm[i].w;
+      vx = vv[i].x;
+      vy = vv[i].y;
+      vz = vv[i].z;
+    }
+    px += mi * vx;
+    py += mi * vy;
+    pz += mi * vz;
+    mm += mi;
+  }
+  const double Px = block_sum<1024>(px, sh);
+  const double Py = block_sum<1024>(py, sh);
+  const double Pz = block_sum<1024>(pz, sh);
+  const double M = block_sum<1024>(mm, sh);
+  if (threadIdx.x == 0) {
+    out[0] = Px;
+    out[1] = Py;
+    out[2] = Pz;
+    out[3] = M;
+  }
+}
+
+// Heliocentric velocities become barycentric: v = u - sum m u / (m0 + sum m).
+__global__ void k_pack(const double* __restrict__ m, const double* __restrict__ x,
+                       const double* __restrict__ v, const double* __restrict__ mom,
+                       double4* __restrict__ xm, double4* __restrict__ vv, int n,
+                       int np, int helio, double m0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  if (i >= n) {
+    xm[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+    vv[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+    return;
+  }
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  if (helio) {
+    const double den = m0 + mom[3];
+    sx = mom[0] / den;
+    sy = mom[1] / den;
+    sz = mom[2] / den;
+  }
+  xm[i] = make_double4(x[3 * i], x[3 * i + 1], x[3 * i + 2], m[i]);
+  vv[i] = make_double4(v[3 * i] - sx, v[3 * i + 1] - sy, v[3 * i + 2] - sz, 0.0);
+}
+
+// Barycentric velocities back to heliocentric: u = v + sum m v / m0.
+__global__ void k_unpack(const double4* __restrict__ xm, const double4* __restrict__ vv,
+                         const double* __restrict__ mom, double* __restrict__ x,
+                         double* __restrict__ v, int n, int helio, double m0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  if (helio) {
+    sx = mom[0] / m0;
+    sy = mom[1] / m0;
+    sz = mom[2] / m0;
+  }
+  const double4 p = xm[i], q = vv[i];
+  x[3 * i] = p.x;
+  x[3 * i + 1] = p.y;
+  x[3 * i + 2] = p.z;
+  v[3 * i] = q.x + sx;
+  v[3 * i + 1] = q.y + sy;
+  v[3 * i + 2] = q.z + sz;
+}
+
+// Radii of the first step (Eq. 6), thresholds, empty candidate table.
+__global__ void k_rcrit_init(const double4* __restrict__ xm, const double4* __restrict__ vv,
+                             double* __restrict__ rc, double* __restrict__ thr,
+                             int* __restrict__ ccnt, int n, double mu, double m0,
+                             double n1, double n2, double absdt, double pf2,
+                             int enc_free) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 p = xm[i], q = vv[i];
+  const double r = rcrit(p.x, p.y, p.z, q.x, q.y, q.z, p.w, mu, m0, n1, n2, absdt);
+  rc[i] = r;
+  thr[i] = enc_free ? kTiny : fmax(pf2 * r * r, kTiny);
+  ccnt[i] = 0;
+}
+
+// Per-body energy terms and angular momentum; rows[8 i + k]:
+// kinetic, -G m0 m/r, -1/2 G m sum_j m_j/r_ij, m v (3), m x x v (3) -> 9 terms
+__global__ void k_energy_rows(const double4* __restrict__ xm, const double4* __restrict__ vv,
+                              int n, double G, double m0, double* __restrict__ rows) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 p = xm[i], q = vv[i];
+  double pp = 0.0;
+  for (int j = 0; j < n; ++j) {
+    if (j == i) continue;
+    const double4 pj = xm[j];
+    const double dx = pj.x - p.x, dy = pj.y - p.y, dz = pj.z - p.z;
+    pp += pj.w / sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  double* r = rows + 9 * (size_t)i;
+  r[0] = 0.5 * p.w * (q.x * q.x + q.y * q.y + q.z * q.z);
+  r[1] = -G * m0 * p.w / sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
+  r[2] = -0.5 * G * p.w * pp;
+  r[3] = p.w * q.x;
+  r[4] = p.w * q.y;
+  r[5] = p.w * q.z;
+  r[6] = p.w * (p.y * q.z - p.z * q.y);
+  r[7] = p.w * (p.z * q.x - p.x * q.z);
+  r[8] = p.w * (p.x * q.y - p.y * q.x);
+}
+
+__global__ __launch_bounds__(1024) void k_energy_final(const double* __restrict__ rows,
+                                                       int n, double m0,
+                                                       double* __restrict__ E,
+                                                       double* __restrict__ L) {
+  __shared__ double sh[16];
+  double t[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) t[k] = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) t[k] += rows[9 * (size_t)i + k];
+  double s[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) s[k] = block_sum<1024>(t[k], sh);
+  if (threadIdx.x == 0) {
+    E[0] = s[0] + (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]) / (2.0 * m0) + s[1] + s[2];
+    L[0] = s[6];
+    L[1] = s[7];
+    L[2] = s[8];
+  }
+}
+
+// Candidate thresholds from given radii: max((pf rc)^2, tiny).
+__global__ void k_thresholds(const double* __restrict__ rc, double* __restrict__ thr,
+                             int* __restrict__ ccnt, int n, double pf2, int enc_free) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  thr[i] = enc_free ? kTiny : fmax(pf2 * rc[i] * rc[i], kTiny);
+  ccnt[i] = 0;
+}
+
+// Masses out of the packed state.
+__global__ void k_masses(const double4* __restrict__ xm, double* __restrict__ m, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) m[i] = xm[i].w;
+}
+
+// Every input value finite?  Sets *bad when not.
+__global__ void k_validate(const double* __restrict__ a, int64_t cnt, int* __restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt && !isfinite(a[i])) atomicOr(bad, 1);
+}
+
+KickArgs kick_args(const MassiveWs& w, const StepConsts& c) {
+  KickArgs a;
+  a.xm = w.xm;
+  a.thr = w.thr;
+  a.rc = w.rc_cur;
+  a.part = w.part;
+  a.tilecnt = w.tilecnt;
+  a.ccnt = w.ccnt;
+  a.ctab = w.ctab;
+  a.vv = w.vv;
+  a.afar = w.afar;
+  a.rc_next = w.rc_next;
+  a.acc_out = nullptr;
+  a.st = w.st;
+  a.n = w.n;
+  a.np = w.np;
+  a.jb_len = w.jb_len;
+  a.cpb = w.cpb;
+  a.encounter_free = c.encounter_free;
+  a.G = c.G;
+  a.h = c.h;
+  a.m0 = c.m0;
+  a.mu = c.mu;
+  a.n1 = c.n1;
+  a.n2 = c.n2;
+  a.absdt = fabs(c.dt);
+  a.pf = c.pf;
+  return a;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+StepConsts make_consts(const genga_params& p) {
+  StepConsts c;
+  c.G = p.G;
+  c.m0 = p.m0;
+  c.mu = p.G * p.m0;
+  c.dt = p.dt;
+  c.h = 0.5 * p.dt;
+  c.n1 = p.n1;
+  c.n2 = p.n2;
+  c.pf = p.pf;
+  c.pf2 = p.pf * p.pf;
+  c.bs_tol = p.bs_tol;
+  c.bs_max_depth = p.bs_max_depth;
+  c.kepler_max_iter = p.kepler_max_iter;
+  c.encounter_free = p.encounter_free;
+  return c;
+}
+
+static void kick_shape(int n, int& nitile, int& njb, int& jb_len) {
+  nitile = ceil_div(n, 64);
+  const int by_target = ceil_div(512, nitile);
+  const int by_len = ceil_div(n, kKickWaves * 16);
+  njb = std::max(1, std::min(by_target, by_len));
+  jb_len = ceil_div(n, njb);
+  njb = ceil_div(n, jb_len);
+}
+
+size_t massive_ws_bytes(int n, const genga_params& p) {
+  if (n < 1) return 0;
+  MassiveWs w;
+  return massive_carve(w, n, p, nullptr);
+}
+
+// Lay the main-mode arrays out in the workspace starting at base (nullptr:
+// only size the layout).  Returns the bytes used.
+size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base) {
+  w.n = n;
+  w.np = ceil_div(n, 256) * 256;
+  kick_shape(n, w.nitile, w.njb, w.jb_len);
+  w.nblk = ceil_div(n, kVecBlock);
+  w.cpb = p.cand_per_body;
+  w.enc_cap = p.enc_cap;
+  const size_t np = (size_t)w.np;
+  size_t off = 0;
+  auto take = [&](size_t sz) -> void* {
+    const size_t o = off;
+    off += align256(sz);
+    return base ? (void*)((char*)base + o) : nullptr;
+  };
+  w.xm = (double4*)take(np * sizeof(double4));
+  w.vv = (double4*)take(np * sizeof(double4));
+  w.xpre = (double4*)take(np * sizeof(double4));
+  w.vpre = (double4*)take(np * sizeof(double4));
+  w.afar = (double4*)take(np * sizeof(double4));
+  w.part = (double4*)take((size_t)w.njb * np * 2 * sizeof(double4));
+  w.rc_cur = (double*)take(np * sizeof(double));
+  w.rc_next = (double*)take(np * sizeof(double));
+  w.thr = (double*)take(np * sizeof(double));
+  w.partP = (double*)take((size_t)w.nblk * 4 * sizeof(double));
+  w.red = (double*)take(std::max<size_t>(np * 9, 64) * sizeof(double));
+  w.ccnt = (int*)take(np * sizeof(int));
+  w.ctab = (int*)take(np * (size_t)std::max(1, w.cpb) * sizeof(int));
+  w.tilecnt = (unsigned*)take((size_t)w.nitile * sizeof(unsigned));
+  w.encij = (int2*)take((size_t)std::max(1, w.enc_cap) * sizeof(int2));
+  w.encd2 = (double*)take((size_t)std::max(1, w.enc_cap) * sizeof(double));
+  w.encrc2 = (double*)take((size_t)std::max(1, w.enc_cap) * sizeof(double));
+  w.goff = (int*)take((np + 1) * sizeof(int));
+  w.gmem = (int*)take(np * sizeof(int));
+  w.flag_in = (int*)take(sizeof(int));
+  w.st = (DevStat*)take(sizeof(DevStat));
+  return off;
+}
+
+hipError_t massive_pack(const MassiveWs& w, const StepConsts& c, const double* m,
+                        const double* x, const double* v, int coords_in,
+                        hipStream_t s) {
+  const int helio = coords_in == GENGA_HELIO;
+  if (helio) hipLaunchKernelGGL(k_momentum, dim3(1), dim3(1024), 0, s, m, v, nullptr, nullptr, w.n, w.red);
+  hipLaunchKernelGGL(k_pack, dim3(ceil_div(w.np, 256)), dim3(256), 0, s, m, x, v, w.red,
+                     w.xm, w.vv, w.n, w.np, helio, c.m0);
+  return hipGetLastError();
+}
+
+hipError_t massive_unpack(const MassiveWs& w, const StepConsts& c, double* x,
+                          double* v, int coords_out, hipStream_t s) {
+  const int helio = coords_out == GENGA_HELIO;
+  if (helio)
+    hipLaunchKernelGGL(k_momentum, dim3(1), dim3(1024), 0, s, nullptr, nullptr, w.xm, w.vv, w.n, w.red);
+  hipLaunchKernelGGL(k_unpack, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xm, w.vv, w.red,
+                     x, v, w.n, helio, c.m0);
+  return hipGetLastError();
+}
+
+hipError_t massive_prime(const MassiveWs& w, const StepConsts& c, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(w.tilecnt, 0, (size_t)w.nitile * sizeof(unsigned), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rcrit_init, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xm, w.vv,
+                     w.rc_cur, w.thr, w.ccnt, w.n, c.mu, c.m0, c.n1, c.n2, fabs(c.dt),
+                     c.pf2, c.encounter_free);
+  KickArgs a = kick_args(w, c);
+  hipLaunchKernelGGL(k_kick<KICK_INIT>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, double* acc,
+                         hipStream_t s) {
+  KickArgs a = kick_args(w, c);
+  a.acc_out = acc;
+  hipLaunchKernelGGL(k_kick<KICK_ACC>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s) {
+  OpenArgs o;
+  o.xm = w.xm;
+  o.vv = w.vv;
+  o.afar = w.afar;
+  o.rc_next = w.rc_next;
+  o.rc_cur = w.rc_cur;
+  o.thr = w.thr;
+  o.ccnt = w.ccnt;
+  o.ctab = w.ctab;
+  o.partP = w.partP;
+  o.st = w.st;
+  o.n = w.n;
+  o.cpb = w.cpb;
+  o.encounter_free = c.encounter_free;
+  o.G = c.G;
+  o.h = c.h;
+  o.pf2 = c.pf2;
+  hipLaunchKernelGGL(k_kick_open, dim3(w.nblk), dim3(kVecBlock), 0, s, o);
+
+  DriftArgs d;
+  d.xm = w.xm;
+  d.vv = w.vv;
+  d.xpre = w.xpre;
+  d.vpre = w.vpre;
+  d.partP = w.partP;
+  d.st = w.st;
+  d.n = w.n;
+  d.nblk = w.nblk;
+  d.max_iter = c.kepler_max_iter;
+  d.h = c.h;
+  d.m0 = c.m0;
+  d.mu = c.mu;
+  d.dt = c.dt;
+  hipLaunchKernelGGL(k_drift, dim3(w.nblk), dim3(kVecBlock), 0, s, d);
+
+  if (!c.encounter_free) {
+    EncArgs e;
+    e.xm = w.xm;
+    e.vv = w.vv;
+    e.xpre = w.xpre;
+    e.vpre = w.vpre;
+    e.rc = w.rc_cur;
+    e.ccnt = w.ccnt;
+    e.ctab = w.ctab;
+    e.encij = w.encij;
+    e.encd2 = w.encd2;
+    e.encrc2 = w.encrc2;
+    e.goff = w.goff;
+    e.gmem = w.gmem;
+    e.st = w.st;
+    e.n = w.n;
+    e.cpb = w.cpb;
+    e.enc_cap = w.enc_cap;
+    e.dt = c.dt;
+    hipLaunchKernelGGL(k_enc_group, dim3(1), dim3(kEncThreads), 0, s, e);
+
+    BsArgs b;
+    b.xm = w.xm;
+    b.vv = w.vv;
+    b.xpre = w.xpre;
+    b.vpre = w.vpre;
+    b.rc = w.rc_cur;
+    b.goff = w.goff;
+    b.gmem = w.gmem;
+    b.st = w.st;
+    b.G = c.G;
+    b.Gm0 = c.mu;
+    b.dt = c.dt;
+    b.tol = c.bs_tol;
+    b.max_depth = c.bs_max_depth;
+    hipLaunchKernelGGL(k_bs, dim3(std::max(1, std::min(256, w.n / 2))), dim3(64), 0, s, b);
+  }
+  hipLaunchKernelGGL(k_sun2, dim3(1), dim3(1024), 0, s, w.xm, w.vv, w.ccnt, w.st, w.n, c.h, c.m0);
+
+  KickArgs a = kick_args(w, c);
+  hipLaunchKernelGGL(k_kick<KICK_CLOSE>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t massive_energy(const MassiveWs& w, const StepConsts& c, double* dE,
+                          double* dL, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_rows, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xm, w.vv,
+                     w.n, c.G, c.m0, w.red);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(1024), 0, s, w.red, w.n, c.m0, dE, dL);
+  return hipGetLastError();
+}
+
+hipError_t validate_finite(const double* a, int64_t cnt, int* dbad, hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_validate, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, a, cnt, dbad);
+  return hipGetLastError();
+}
+
+hipError_t thresholds_from_radii(const MassiveWs& w, const StepConsts& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_thresholds, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.rc_cur, w.thr,
+                     w.ccnt, w.n, c.pf2, c.encounter_free);
+  return hipGetLastError();
+}
+
+hipError_t massive_masses(const MassiveWs& w, double* m, hipStream_t s) {
+  hipLaunchKernelGGL(k_masses, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xm, m, w.n);
+  return hipGetLastError();
+}
+
+}  // namespace genga

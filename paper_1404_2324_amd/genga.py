@@ -1,0 +1,258 @@
+"""ctypes binding of the C ABI in ``include/genga.h``.
+
+Argument marshalling only: every step of the integration runs in the gfx950
+kernels of ``libgenga.so``.  PyTorch supplies device memory and the stream.
+If the library is missing this module raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgenga.so")
+
+GENGA_MASSIVE, GENGA_TEST, GENGA_BATCH = 0, 1, 2
+GENGA_HELIO, GENGA_DEMOCRATIC = 0, 1
+OK, EINVAL, EHIP, EOVERFLOW, EKEPLER, EBS, EADJ_ENCOUNTER, ENOMEM, EGROUP = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+
+
+class GengaError(RuntimeError):
+    def __init__(self, code, what):
+        msg = lib().genga_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_double), ("m0", ctypes.c_double), ("dt", ctypes.c_double),
+                ("n1", ctypes.c_double), ("n2", ctypes.c_double), ("pf", ctypes.c_double),
+                ("bs_tol", ctypes.c_double), ("bs_max_depth", ctypes.c_int32),
+                ("kepler_max_iter", ctypes.c_int32), ("encounter_free", ctypes.c_int32),
+                ("cand_per_body", ctypes.c_int32), ("enc_cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("n_cand", ctypes.c_int32),
+                ("n_enc", ctypes.c_int32), ("n_groups", ctypes.c_int32),
+                ("max_group", ctypes.c_int32), ("kepler_iter_max", ctypes.c_int32),
+                ("tp_enc", ctypes.c_int32), ("bs_substeps", ctypes.c_int64),
+                ("enc_total", ctypes.c_int64), ("full_kicks", ctypes.c_int64),
+                ("tp_enc_total", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+
+
+# every symbol the header declares, with its ctypes signature
+_vp, _i32, _i64, _d, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+_PP = ctypes.POINTER(Params)
+SIGNATURES = {
+    "genga_params_default": (None, [_PP]),
+    "genga_workspace_bytes": (_sz, [_i32, _PP, _i32, _i64, _i32, _i64]),
+    "genga_init": (_i32, [ctypes.POINTER(_vp), _i32, _PP, _i32, _i64, _i32, _vp, _vp, _vp, _vp,
+                          _vp, _i32, _vp, _sz, _vp]),
+    "genga_step": (_i32, [_vp, _i64]),
+    "genga_sync": (_i32, [_vp]),
+    "genga_get_state": (_i32, [_vp, _vp, _vp, _i32]),
+    "genga_set_state": (_i32, [_vp, _vp, _vp, _i32]),
+    "genga_energy": (_i32, [_vp, _vp, _vp]),
+    "genga_encounters": (_i32, [_vp, _vp, _vp, _vp, _i32, ctypes.POINTER(_i32)]),
+    "genga_candidates": (_i32, [_vp, _vp, _i32, ctypes.POINTER(_i32)]),
+    "genga_stats": (_i32, [_vp, ctypes.POINTER(Stats)]),
+    "genga_strerror": (ctypes.c_char_p, [_i32]),
+    "genga_destroy": (_i32, [_vp]),
+    "genga_accel_workspace_bytes": (_sz, [_i32]),
+    "genga_accel": (_i32, [_PP, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "genga_kepler": (_i32, [_d, _i64, _vp, _vp, _d, _vp, _vp, _i32, _vp, _vp]),
+    "genga_hermite": (_i32, [_i64, _d, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libgenga.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code, what):
+    if code != OK:
+        raise GengaError(code, what)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(a, device, dtype=torch.float64):
+    t = torch.as_tensor(a, dtype=dtype)
+    return t.to(device).contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().genga_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+class Simulation:
+    """Main-mode system on one GPU.  State stays in the library's workspace;
+    ``state()`` returns fresh device tensors."""
+
+    def __init__(self, m, x, v, params: Params | None = None, coords: str = "helio",
+                 device="cuda", stream=None):
+        self.p = params if params is not None else default_params()
+        self.device = torch.device(device)
+        self.stream = stream
+        m = _dev(m, self.device)
+        x = _dev(x, self.device).reshape(-1, 3)
+        v = _dev(v, self.device).reshape(-1, 3)
+        self.n = int(m.numel())
+        nbytes = lib().genga_workspace_bytes(GENGA_MASSIVE, ctypes.byref(self.p), self.n, 0, 0, 0)
+        if nbytes == 0:
+            raise GengaError(EINVAL, "genga_workspace_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._ctx = ctypes.c_void_p()
+        code = lib().genga_init(ctypes.byref(self._ctx), GENGA_MASSIVE, ctypes.byref(self.p),
+                                self.n, 0, 0, None, None, _ptr(m), _ptr(x), _ptr(v),
+                                GENGA_HELIO if coords == "helio" else GENGA_DEMOCRATIC,
+                                _ptr(self.ws), nbytes, _stream(stream))
+        _check(code, "genga_init")
+
+    def step(self, nsteps: int = 1):
+        _check(lib().genga_step(self._ctx, int(nsteps)), "genga_step")
+
+    def sync(self):
+        return lib().genga_sync(self._ctx)
+
+    def check(self):
+        _check(self.sync(), "device status")
+
+    def state(self, coords: str = "dem"):
+        x = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
+        v = torch.empty_like(x)
+        code = lib().genga_get_state(self._ctx, _ptr(x), _ptr(v),
+                                     GENGA_HELIO if coords == "helio" else GENGA_DEMOCRATIC)
+        _check(code, "genga_get_state")
+        return x, v
+
+    def set_state(self, x, v, coords: str = "dem"):
+        x = _dev(x, self.device).reshape(-1, 3)
+        v = _dev(v, self.device).reshape(-1, 3)
+        code = lib().genga_set_state(self._ctx, _ptr(x), _ptr(v),
+                                     GENGA_HELIO if coords == "helio" else GENGA_DEMOCRATIC)
+        _check(code, "genga_set_state")
+
+    def energy(self):
+        E = torch.empty(1, dtype=torch.float64, device=self.device)
+        L = torch.empty(3, dtype=torch.float64, device=self.device)
+        _check(lib().genga_energy(self._ctx, _ptr(E), _ptr(L)), "genga_energy")
+        torch.cuda.synchronize(self.device)
+        return float(E[0]), L.cpu().numpy()
+
+    def encounters(self):
+        n = ctypes.c_int()
+        code = lib().genga_encounters(self._ctx, None, None, None, 0, ctypes.byref(n))
+        if code not in (OK, EOVERFLOW):
+            _check(code, "genga_encounters")
+        cap = max(n.value, 1)
+        ij = np.zeros((cap, 2), dtype=np.int32)
+        d2 = np.zeros(cap)
+        rc2 = np.zeros(cap)
+        code = lib().genga_encounters(self._ctx, ij.ctypes.data_as(_vp), d2.ctypes.data_as(_vp),
+                                      rc2.ctypes.data_as(_vp), cap, ctypes.byref(n))
+        _check(code, "genga_encounters")
+        k = n.value
+        return ij[:k], d2[:k], rc2[:k]
+
+    def candidates(self):
+        n = ctypes.c_int()
+        code = lib().genga_candidates(self._ctx, None, 0, ctypes.byref(n))
+        if code not in (OK, EOVERFLOW):
+            _check(code, "genga_candidates")
+        cap = max(n.value, 1)
+        ij = np.zeros((cap, 2), dtype=np.int32)
+        _check(lib().genga_candidates(self._ctx, ij.ctypes.data_as(_vp), cap, ctypes.byref(n)),
+               "genga_candidates")
+        return ij[:n.value]
+
+    def stats(self, check: bool = True):
+        s = Stats()
+        code = lib().genga_stats(self._ctx, ctypes.byref(s))
+        if check:
+            _check(code, "genga_stats")
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().genga_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def accel(params: Params, m, x, rc=None, device="cuda", stream=None):
+    """H_B acceleration of every body (the kick's pair sum)."""
+    dev = torch.device(device)
+    m = _dev(m, dev)
+    x = _dev(x, dev).reshape(-1, 3)
+    n = int(m.numel())
+    rct = _dev(rc, dev) if rc is not None else None
+    out = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    nb = lib().genga_accel_workspace_bytes(n)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    _check(lib().genga_accel(ctypes.byref(params), n, _ptr(m), _ptr(x), _ptr(rct), _ptr(out),
+                             _ptr(ws), nb, _stream(stream)), "genga_accel")
+    return out
+
+
+def kepler(mu, x0, v0, dt, max_iter=40, device="cuda", stream=None):
+    """Kepler drift of independent bodies; returns x, v, iteration counts."""
+    dev = torch.device(device)
+    x0 = _dev(x0, dev).reshape(-1, 3)
+    v0 = _dev(v0, dev).reshape(-1, 3)
+    n = x0.shape[0]
+    x = torch.empty_like(x0)
+    v = torch.empty_like(v0)
+    it = torch.empty(n, dtype=torch.int32, device=dev)
+    _check(lib().genga_kepler(float(mu), n, _ptr(x0), _ptr(v0), float(dt), _ptr(x), _ptr(v),
+                              int(max_iter), _ptr(it), _stream(stream)), "genga_kepler")
+    return x, v, it
+
+
+def hermite(dt, q, device="cuda", stream=None):
+    """Hermite minimum squared separation for rows (dx0, dv0, dx1, dv1)."""
+    dev = torch.device(device)
+    q = _dev(q, dev).reshape(-1, 12)
+    out = torch.empty(q.shape[0], dtype=torch.float64, device=dev)
+    _check(lib().genga_hermite(q.shape[0], float(dt), _ptr(q), _ptr(out), _stream(stream)),
+           "genga_hermite")
+    return out

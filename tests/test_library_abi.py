@@ -1,0 +1,79 @@
+"""Host-side checks of the C ABI (no GPU needed): the built library loads,
+exports every function include/genga.h declares, and its host-only calls
+(defaults, workspace sizing, messages) behave as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "genga.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(genga_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_1404_2324_amd import genga
+    return genga
+
+
+def test_library_exports_every_declared_symbol(G):
+    L = G.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(L, name), f"{name} declared in genga.h but not exported"
+        assert name in G.SIGNATURES, f"{name} has no binding signature"
+
+
+def test_struct_layouts_match_header(G):
+    # genga_params: 7 doubles + 6 int32 = 80 bytes; stats: 8+6*4+4*8+8 = 96
+    assert ctypes.sizeof(G.Params) == 80
+    assert ctypes.sizeof(G.Stats) == 8 + 6 * 4 + 4 * 8 + 8
+
+
+def test_default_params(G):
+    p = G.default_params()
+    assert p.G == 1.0 and p.m0 == 1.0
+    assert p.n1 == 3.0 and p.n2 == 0.4 and p.pf == 3.0
+    assert abs(p.dt - 0.02 * 3.141592653589793) < 1e-16
+    assert p.bs_tol == 1e-13 and p.bs_max_depth == 20 and p.kepler_max_iter == 40
+
+
+def test_workspace_sizing_and_limits(G):
+    L = G.lib()
+    p = G.default_params()
+    b16 = L.genga_workspace_bytes(G.GENGA_MASSIVE, ctypes.byref(p), 16, 0, 0, 0)
+    b2k = L.genga_workspace_bytes(G.GENGA_MASSIVE, ctypes.byref(p), 2048, 0, 0, 0)
+    assert 0 < b16 < b2k
+    assert b2k < 64 << 20
+    # encounter mode is limited by the one-workgroup grouping
+    assert L.genga_workspace_bytes(G.GENGA_MASSIVE, ctypes.byref(p), 2049, 0, 0, 0) == 0
+    assert L.genga_workspace_bytes(G.GENGA_MASSIVE, ctypes.byref(p), 0, 0, 0, 0) == 0
+    q = G.default_params(encounter_free=1)
+    assert L.genga_workspace_bytes(G.GENGA_MASSIVE, ctypes.byref(q), 16384, 0, 0, 0) > 0
+    bad = G.default_params(pf=0.5)
+    assert L.genga_workspace_bytes(G.GENGA_MASSIVE, ctypes.byref(bad), 16, 0, 0, 0) == 0
+    bad = G.default_params(m0=-1.0)
+    assert L.genga_workspace_bytes(G.GENGA_MASSIVE, ctypes.byref(bad), 16, 0, 0, 0) == 0
+
+
+def test_argument_errors_without_device(G):
+    L = G.lib()
+    assert L.genga_step(None, 1) == G.EINVAL
+    assert L.genga_sync(None) == G.EINVAL
+    assert L.genga_destroy(None) == G.EINVAL
+    ctx = ctypes.c_void_p()
+    p = G.default_params()
+    # null arrays are rejected before any device work
+    assert L.genga_init(ctypes.byref(ctx), G.GENGA_MASSIVE, ctypes.byref(p), 16, 0, 0, None,
+                        None, None, None, None, G.GENGA_HELIO, None, 0, None) == G.EINVAL
+    for code in (G.OK, G.EINVAL, G.EHIP, G.EOVERFLOW, G.EKEPLER, G.EBS, G.ENOMEM, G.EGROUP):
+        assert L.genga_strerror(code)
