@@ -1,0 +1,177 @@
+"""Benchmark of the hybrid symplectic step on one MI355X.
+
+Workload: the 2048-planetesimal disk (masses dN/dm ~ m^-2 on [1e-9, 1e-7],
+a ~ U(0.5, 4), e ~ Ray(0.02), i ~ Ray(0.01), dt = 0.01 orbit, n1 = 3,
+n2 = 0.4), FP64, with encounters resolved by Bulirsch-Stoer per group.
+
+value = N (N - 1) x steps / wall time of the whole steps (every step runs one
+all-pairs kick plus the opening kick, Sun kicks, drift, encounter search,
+grouping and BS): whole-step pair-interaction throughput with the state
+resident in HBM.  The roofline entry covers the pair-kick kernel, timed live
+with HIP events on the stream it runs on.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128)
+HBM_PEAK_GBS = 8000.0
+FLOPS_PER_PAIR = 18              # 3 sub, 5 for r^2, sqrt, r^2 r, div, m/r^3, 3 FMA
+N_BODIES = 2048
+
+
+def _kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("device_math.h", "massive.hip", "genga_impl.h"):
+        with open(os.path.join(ROOT, "paper_1404_2324_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_per_launch():
+    """HBM bytes per kick launch from the committed counter summary, or None
+    when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "kick_n2048_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != _kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(s, gp, budget_s: float = 15.0):
+    import oracle as O
+    op = O.params(G=gp.G, m0=gp.m0, dt=gp.dt, n1=gp.n1, n2=gp.n2, pf=gp.pf,
+                  bs_tol=gp.bs_tol, bs_max_depth=gp.bs_max_depth,
+                  kepler_max_iter=gp.kepler_max_iter)
+    sim = O.MassiveSim(op, s.m, s.x, s.u, coords="helio")
+    cores = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp:
+        cores = min(cores, int(omp))
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and steps < 400:
+        sim.step(1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    n = len(s.m)
+    return {"value": n * (n - 1) * steps / dt, "unit": "pair interactions/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"first {steps} steps of the same 2048-body workload "
+                      f"({dt:.1f} s; the oracle recomputes every pair in both half kicks "
+                      f"and Hermite-tests every pair)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=32)
+    ap.add_argument("--kick-reps", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed region run one 256 MiB device copy (counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(the systems here shard with no exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1404_2324_amd import genga as G
+    from paper_1404_2324_amd import workloads as W
+
+    s = W.planetesimals(N_BODIES)
+    gp = G.default_params()
+    sim = G.Simulation(s.m, s.x, s.u, gp, coords="helio")
+    n = sim.n
+    stream = torch.cuda.current_stream()
+
+    sim.step(args.warmup)
+    sim.check()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    status = sim.sync()
+    if status != G.OK:
+        raise G.GengaError(status, "device status after the timed steps")
+    gpu_ms = e0.elapsed_time(e1)
+    sec = gpu_ms / 1e3
+    st = sim.stats()
+
+    # live timing of the pair-kick kernel (same pair loop, acceleration out)
+    acc = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    for _ in range(10):
+        sim.accel_state(acc)
+    torch.cuda.synchronize()
+    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k0.record(stream)
+    for _ in range(args.kick_reps):
+        sim.accel_state(acc)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    kick_s = k0.elapsed_time(k1) / 1e3 / args.kick_reps
+
+    if args.calib_copy:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    pairs = n * (n - 1)
+    flops = FLOPS_PER_PAIR * pairs
+    achieved = flops / kick_s / 1e12
+    traffic = _traffic_per_launch()
+    out = {
+        "metric": "FP64 pair interactions/s",
+        "value": pairs * args.steps / sec,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": gpu_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "planetesimals_n2048", "n_bodies": n, "dt": gp.dt,
+                   "n1": gp.n1, "n2": gp.n2, "bs_tol": gp.bs_tol,
+                   "host_wall_s": wall},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": traffic,
+                     "kernel": "k_kick (pair kick, acceleration mode)",
+                     "kernel_us": kick_s * 1e6,
+                     "flops_per_pair": FLOPS_PER_PAIR,
+                     "kick_pair_rate": pairs / kick_s},
+        "stats": {k: st[k] for k in ("n_cand", "n_enc", "n_groups", "max_group",
+                                      "kepler_iter_max", "bs_substeps", "enc_total",
+                                      "full_kicks")},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(s, gp)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

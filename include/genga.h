@@ -93,8 +93,9 @@ enum {
 void genga_params_default(genga_params *p);
 
 /* Device workspace (bytes) a context of this shape needs.  Main mode:
- * n_massive <= 4096 bodies (the paper's main mode holds up to 2048,
- * Sec. 3).  Returns 0 for an unsupported shape. */
+ * n_massive <= 2048 bodies with encounters (the paper's main-mode limit,
+ * Sec. 3), <= 65536 with encounter_free.  Returns 0 for an unsupported
+ * shape or invalid parameters. */
 size_t genga_workspace_bytes(int mode, const genga_params *p, int n_massive,
                              int64_t n_test, int n_sys, int64_t n_bodies);
 
@@ -149,6 +150,11 @@ int genga_set_state(genga_ctx *ctx, const double *d_x, const double *d_v,
  * (n_sys doubles) and d_L (3 n_sys doubles), device, asynchronous.  The
  * relative energy error of Sec. 4.1 is |(E_t - E_0)/E_0|. */
 int genga_energy(genga_ctx *ctx, double *d_E, double *d_L);
+
+/* H_B acceleration (the kick's pair sum, Sec. 3.2.3) of the current state
+ * with this step's critical radii, written to d_acc (n x 3, device).  Only
+ * the pair kernel runs; the state is not changed.  Asynchronous. */
+int genga_accel_state(genga_ctx *ctx, double *d_acc);
 
 /* Confirmed close-encounter pairs of the last step (the Encounter kernel
  * output, Sec. 3.2.4): i < j body indices in h_ij (2 per pair), the Hermite

@@ -208,7 +208,9 @@ static void stumpff45(double z, const double c[4], double *c4, double *c5) {
  *   F(s) = r0 G1 + eta0 G2 + mu G3 - dt = 0,  F' = r = r0 + eta0 G1 + zeta0 G2,
  *   F'' = eta0 G0 + zeta0 G1
  * is solved by the Laguerre-Conway iteration (order 5) from s = dt / r0 until
- * |ds| <= 2^-50 |s|.  Then f = 1 - mu G2/r0, g = dt - mu G3,
+ * |ds| <= 2^-50 |s|, or until |F| is within 2^-48 of the sum of the magnitudes
+ * of its terms (the residual is rounding noise; strongly hyperbolic orbits
+ * over long steps end there).  Reading: the paper gives no stopping rule.  Then f = 1 - mu G2/r0, g = dt - mu G3,
  * fdot = -mu G1/(r r0), gdot = 1 - mu G2/r.
  * Reading: universal variables replace the paper's fallback to BS for
  * unbound or non-converging orbits; non-convergence is an error.
@@ -233,6 +235,12 @@ static int kepler_solve(double mu, double r0, double eta0, double beta,
         double G[4];
         gk_at(s, beta, G);
         double F = r0 * G[1] + eta0 * G[2] + mu * G[3] - dt;
+        /* residual at the rounding level of its own terms: s cannot improve */
+        double Fscale = fabs(r0 * G[1]) + fabs(eta0 * G[2]) + fabs(mu * G[3]) + fabs(dt);
+        if (fabs(F) <= ldexp(Fscale, -48)) {
+            ok = 1;
+            break;
+        }
         double Fp = r0 + eta0 * G[1] + zeta0 * G[2];
         double Fpp = eta0 * G[0] + zeta0 * G[1];
         const double nl = 5.0;

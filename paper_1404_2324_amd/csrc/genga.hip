@@ -208,6 +208,12 @@ int genga_energy(genga_ctx* ctx, double* d_E, double* d_L) {
   return GENGA_OK;
 }
 
+int genga_accel_state(genga_ctx* ctx, double* d_acc) {
+  if (!ctx || !d_acc) return GENGA_EINVAL;
+  HIPCHK(massive_accel(ctx->w, ctx->c, d_acc, ctx->stream));
+  return GENGA_OK;
+}
+
 int genga_encounters(genga_ctx* ctx, int32_t* h_ij, double* h_dmin2, double* h_rc2, int cap,
                      int* h_n) {
   if (!ctx || !h_n || cap < 0 || (cap > 0 && !h_ij)) return GENGA_EINVAL;
@@ -343,7 +349,6 @@ int genga_accel(const genga_params* p, int n, const double* d_m, const double* d
   StepConsts c = make_consts(q);
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(massive_pack(w, c, d_m, d_x, d_x, GENGA_DEMOCRATIC, s));
-  HIPCHK(hipMemsetAsync(w.tilecnt, 0, (size_t)w.nitile * sizeof(unsigned), s));
   HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStat), s));
   if (!q.encounter_free)
     HIPCHK(hipMemcpyAsync(w.rc_cur, d_rc, n * sizeof(double), hipMemcpyDeviceToDevice, s));

@@ -63,7 +63,6 @@ struct MassiveWs {
   double* red;          // scratch for reductions (energy, conversions)
   int* ccnt;            // candidates per body
   int* ctab;            // candidate partners [np][cpb]
-  unsigned* tilecnt;    // kick last-block counters [nitile]
   int2* encij;          // encounter pairs of the last step
   double* encd2;
   double* encrc2;

@@ -1,7 +1,7 @@
 // Main-mode kernels of the hybrid symplectic step (Grimm & Stadel,
 // arXiv:1404.2324, Sec. 2.2 step recipe and Sec. 3.2 kernels), for gfx950.
 //
-// One step is six launches on one stream (captured once into a HIP graph):
+// One step is seven launches on one stream (captured once into a HIP graph):
 //   k_kick_open  opening kick: cached non-candidate acceleration + candidate
 //                pairs recomputed with the new radii (KickA/KickB, Sec 3.2.3)
 //   k_drift      Sun kick tau/2 (Eq. 3) + pre-drift copy + Kepler drift (Eq. 9)
@@ -9,7 +9,8 @@
 //                compaction, then equivalence classes in LDS (App. A)
 //   k_bs         Bulirsch-Stoer integration of H_A per group, one wave each
 //   k_sun2       Sun kick tau/2 and reset of the candidate table
-//   k_kick       closing kick: all pairs, prechecker, next radii (Eq. 6)
+//   k_kick       closing kick: all pairs and the prechecker, per j-block
+//   k_kick_finish  fixed-order sum of the partials, v += tau/2 a, next radii
 #include <climits>
 
 #include "device_math.h"
@@ -48,7 +49,6 @@ struct KickArgs {
   const double* __restrict__ thr;
   const double* __restrict__ rc;
   double4* __restrict__ part;
-  unsigned* __restrict__ tilecnt;
   int* __restrict__ ccnt;
   int* __restrict__ ctab;
   double4* __restrict__ vv;
@@ -69,8 +69,10 @@ enum { KICK_CLOSE = 0, KICK_INIT = 1, KICK_ACC = 2 };
 // scalar cache into SGPRs; the FP64 pair loop runs on the VALU.  Pairs with
 // r^2 < max((pf rc_i)^2, (pf rc_j)^2) are candidates: their K-weighted term is
 // summed apart ("near") and appended to the per-body candidate table; all
-// other pairs have K = 1 and form the reusable "far" sum.  The per-j-block
-// partials are combined in a fixed order by the last workgroup of each i-tile.
+// other pairs have K = 1 and form the reusable "far" sum.  Each workgroup
+// writes its j-block partials; k_kick_finish combines them in a fixed order
+// (a kernel boundary instead of a device-scope fence per workgroup, which
+// costs an L2 write-back on this multi-XCD part).
 template <int MODE>
 __global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a) {
   constexpr int W = kKickWaves;
@@ -100,8 +102,9 @@ __global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a) {
     const double tj = a.thr[j];
     const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
     const double r2 = dx * dx + dy * dy + dz * dz;
-    const double r = sqrt(r2);
-    const double s = pj.w / (r2 * r);
+    const double ir = rsqrt_nr(r2);
+    const double ir2 = ir * ir;
+    const double s = pj.w * (ir2 * ir);
     const bool cand = r2 < fmax(ti, tj);
     const double sf = cand ? 0.0 : s;
     fx += sf * dx;
@@ -110,8 +113,8 @@ __global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a) {
     if (__builtin_expect(cand, 0)) {
       if (iv && j != i) {
         double K = 1.0, dK = 0.0;
-        if (!a.encounter_free) changeover(r, fmax(a.rc[i], a.rc[j]), K, dK);
-        const double sn = pj.w * (K / (r2 * r) - dK / r2);
+        if (!a.encounter_free) changeover(r2 * ir, fmax(a.rc[i], a.rc[j]), K, dK);
+        const double sn = pj.w * (K * ir2 * ir - dK * ir2);
         nx += sn * dx;
         ny += sn * dy;
         nz += sn * dz;
@@ -147,21 +150,19 @@ __global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a) {
     q[0] = make_double4(sh[0][0][lane], sh[0][1][lane], sh[0][2][lane], 0.0);
     q[1] = make_double4(sh[0][3][lane], sh[0][4][lane], sh[0][5][lane], 0.0);
   }
-  __threadfence();
-  __syncthreads();
-  __shared__ int s_last;
-  if (threadIdx.x == 0) {
-    const unsigned old = atomicAdd(&a.tilecnt[blockIdx.x], 1u);
-    s_last = (old == gridDim.y - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  if (threadIdx.x == 0) a.tilecnt[blockIdx.x] = 0u;
-  if (threadIdx.x >= 64 || !iv) return;
+}
 
+// Closing-kick epilogue, one lane per body: the j-block partials are summed
+// in a fixed order; the far part is kept for the next opening kick.
+//   CLOSE: v += tau/2 a, next radii (Eq. 6) and the reuse check
+//   INIT:  far part only (first step's opening kick)
+//   ACC:   acceleration out
+template <int MODE>
+__global__ __launch_bounds__(kVecBlock) void k_kick_finish(KickArgs a, int njb) {
+  const int i = blockIdx.x * kVecBlock + threadIdx.x;
+  if (i >= a.n) return;
   double S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0;
-  for (int b = 0; b < (int)gridDim.y; ++b) {
+  for (int b = 0; b < njb; ++b) {
     const double4* q = &a.part[((size_t)b * a.np + i) * 2];
     const double4 f = q[0];
     const double4 g = q[1];
@@ -218,10 +219,11 @@ __device__ __forceinline__ void pair_hb(double xi, double yi, double zi,
                                         double& ay, double& az) {
   const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
   const double r2 = dx * dx + dy * dy + dz * dz;
-  const double r = sqrt(r2);
+  const double ir = rsqrt_nr(r2);
+  const double ir2 = ir * ir;
   double K = 1.0, dK = 0.0;
-  if (!enc_free) changeover(r, fmax(rci, rcj), K, dK);
-  const double s = pj.w * (K / (r2 * r) - dK / r2);
+  if (!enc_free) changeover(r2 * ir, fmax(rci, rcj), K, dK);
+  const double s = pj.w * (K * ir2 * ir - dK * ir2);
   ax += s * dx;
   ay += s * dy;
   az += s * dz;
@@ -564,8 +566,8 @@ __device__ __forceinline__ void ha_accel(int sz, int lane, double x, double y,
                                          double G, double Gm0, double& ax,
                                          double& ay, double& az) {
   const double r2 = x * x + y * y + z * z;
-  const double r = sqrt(r2);
-  const double fs = -Gm0 / (r2 * r);
+  const double ir = rsqrt_nr(r2);
+  const double fs = -Gm0 * (ir * ir * ir);
   ax = fs * x;
   ay = fs * y;
   az = fs * z;
@@ -575,10 +577,11 @@ __device__ __forceinline__ void ha_accel(int sz, int lane, double x, double y,
     if (j != lane) {
       const double dx = xj - x, dy = yj - y, dz = zj - z;
       const double q2 = dx * dx + dy * dy + dz * dz;
-      const double q = sqrt(q2);
+      const double iq = rsqrt_nr(q2);
+      const double iq2 = iq * iq;
       double K, dK;
-      changeover(q, fmax(rc, rcj), K, dK);
-      const double s = G * mj * ((1.0 - K) / (q2 * q) + dK / q2);
+      changeover(q2 * iq, fmax(rc, rcj), K, dK);
+      const double s = G * mj * ((1.0 - K) * iq2 * iq + dK * iq2);
       ax += s * dx;
       ay += s * dy;
       az += s * dz;
@@ -588,7 +591,7 @@ __device__ __forceinline__ void ha_accel(int sz, int lane, double x, double y,
 
 // Gragg's modified midpoint rule over H with nsub substeps (one wave, one
 // body per lane).
-__device__ void mmid(int sz, int lane, const double y0[6], double H, int nsub,
+__device__ __forceinline__ void mmid(int sz, int lane, const double y0[6], double H, int nsub,
                      double m, double rc, double G, double Gm0, double out[6]) {
   const double hs = H / nsub;
   double ym[6], yn[6], d[6];
@@ -632,7 +635,7 @@ __device__ __forceinline__ double relerr3(const double* A, const double* B) {
 // extrapolation in h^2 kept in LDS (R[col][comp][lane]), accepted at the first
 // column k >= 2 whose per-body relative error (max over the group) is within
 // tol.  Returns true and the extrapolated state in y on success.
-__device__ bool bs_attempt(int sz, int lane, double y[6], double H, double m,
+__device__ __forceinline__ bool bs_attempt(int sz, int lane, double y[6], double H, double m,
                            double rc, double G, double Gm0, double tol,
                            double (*R)[6][64]) {
   for (int k = 0; k < kBsCols; ++k) {
@@ -673,7 +676,7 @@ __device__ bool bs_attempt(int sz, int lane, double y[6], double H, double m,
 
 // Binary refinement over [0, H]: a failed substep is halved; after finishing
 // both halves of a node the next sibling is tried at the node's length.
-__device__ int bs_integrate(int sz, int lane, double y[6], double H, double m,
+__device__ __forceinline__ int bs_integrate(int sz, int lane, double y[6], double H, double m,
                             double rc, double G, double Gm0, double tol,
                             int D, double (*R)[6][64], long long* nsub) {
   long long pos = 0;
@@ -699,9 +702,236 @@ __device__ int bs_integrate(int sz, int lane, double y[6], double H, double m,
   return 0;
 }
 
+// ---- groups of up to 8 members: all columns, and several depths, at once ----
+// A wave of 64 lanes holds S = 8/P speculative refinement depths x 8 columns
+// x P member slots (P = 2, 4 or 8 >= group size):
+//   lane = s (8 P) + c P + b,  s = depth slot, c = column, b = member.
+// Column c integrates the modified midpoint rule with n_c = 2 (c + 1)
+// substeps; members exchange positions by lane shuffles.  Slot s attempts
+// the substep of length H / 2^s from the same start: exactly the attempts the
+// sequential scheme makes after s failures (the first half of each halving).
+// The Aitken-Neville tableau is built across the columns (T[c][j] needs
+// T[c-1][j-1] from lane - P); column k is tested when it completes (after
+// 2 k + 3 force evaluations), and each slot keeps its first column within
+// tolerance.  The result is the first accepted slot in sequential order, so
+// the substeps taken equal those of one-at-a-time evaluation.
+constexpr int kBsPar = 8;
+
+template <int P>
+struct ParBody {
+  int lane[P];     // lane of partner q (member (b + q) mod sz), q >= 1
+  double m[P];     // partner mass
+  double rcij[P];  // pair radius max(rc_b, rc_j)
+  double i09[P];   // 1 / (0.9 rc_ij), 0 when rc_ij = 0
+};
+
+template <int P>
+__device__ __forceinline__ void ha_accel_par(int sz, double x, double y, double z,
+                                             const ParBody<P>& Q, double G,
+                                             double Gm0, double& ax, double& ay,
+                                             double& az) {
+  const double r2 = x * x + y * y + z * z;
+  const double ir = rsqrt_nr(r2);
+  const double fs = -Gm0 * (ir * ir * ir);
+  ax = fs * x;
+  ay = fs * y;
+  az = fs * z;
+#pragma unroll
+  for (int q = 1; q < P; ++q) {
+    if (q >= sz) break;
+    const double xj = __shfl(x, Q.lane[q], 64);
+    const double yj = __shfl(y, Q.lane[q], 64);
+    const double zj = __shfl(z, Q.lane[q], 64);
+    const double dx = xj - x, dy = yj - y, dz = zj - z;
+    const double q2 = dx * dx + dy * dy + dz * dz;
+    const double iq = rsqrt_nr(q2);
+    const double iq2 = iq * iq;
+    double K = 1.0, dK = 0.0;
+    if (Q.rcij[q] > 0.0) changeover_clamped(q2 * iq, Q.rcij[q], Q.i09[q], K, dK);
+    const double sc = G * Q.m[q] * ((1.0 - K) * iq2 * iq + dK * iq2);
+    ax += sc * dx;
+    ay += sc * dy;
+    az += sc * dz;
+  }
+}
+
+// One speculative round: returns the accepted depth offset (0..S-1), with the
+// accepted state in y, or -1 when every slot failed.
+template <int P>
+__device__ __forceinline__ int bs_round_par(int sz, double y[6], double H, const ParBody<P>& Q,
+                            double G, double Gm0, double tol) {
+  constexpr int S = kBsPar / P;
+  const int lane = threadIdx.x & 63;
+  const int s = lane / (kBsPar * P);
+  const int c = (lane / P) % kBsPar;
+  const int b = lane % P;
+  const int nsub = 2 * (c + 1);
+  const double hs = ldexp(H, -s) / nsub;
+  double ym[6], yn[6], T0[6], yacc[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    ym[q] = y[q];
+    yn[q] = y[q];
+    T0[q] = y[q];
+    yacc[q] = y[q];
+  }
+  bool acc = false;  // this slot has accepted a column
+  for (int e = 0; e <= 2 * kBsCols; ++e) {
+    double d[6];
+    ha_accel_par<P>(sz, yn[0], yn[1], yn[2], Q, G, Gm0, d[3], d[4], d[5]);
+    d[0] = yn[3];
+    d[1] = yn[4];
+    d[2] = yn[5];
+    if (e == 0) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) yn[q] = ym[q] + hs * d[q];
+    } else if (e < nsub) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const double t = ym[q] + 2.0 * hs * d[q];
+        ym[q] = yn[q];
+        yn[q] = t;
+      }
+    } else if (e == nsub) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) T0[q] = 0.5 * (ym[q] + yn[q] + hs * d[q]);
+    }
+    if (e >= 4 && (e & 1) == 0) {
+      const int k = e / 2 - 1;  // column completed by this evaluation
+      double cur[6], diag[6], sub[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        cur[q] = T0[q];
+        diag[q] = T0[q];
+        sub[q] = T0[q];
+      }
+      for (int j = 1; j <= k; ++j) {
+        double nb[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) nb[q] = __shfl(cur[q], lane - (c >= 1 ? P : 0), 64);
+        if (j <= c) {
+          const double ratio = (double)(2 * (c + 1)) / (double)(2 * (c - j + 1));
+          const double den = ratio * ratio - 1.0;
+#pragma unroll
+          for (int q = 0; q < 6; ++q) {
+            if (j == c) sub[q] = cur[q];
+            cur[q] = cur[q] + (cur[q] - nb[q]) / den;
+            if (j == c) diag[q] = cur[q];
+          }
+        }
+      }
+      double err = 0.0;
+      if (c == k && b < sz) err = fmax(relerr3(diag, sub), relerr3(diag + 3, sub + 3));
+#pragma unroll
+      for (int o = 1; o < P; o <<= 1) err = fmax(err, __shfl_xor(err, o, 64));
+      // err of column k of this lane's slot, from lane (s, k, b)
+      const double ek = __shfl(err, s * kBsPar * P + k * P, 64);
+      const bool now = !acc && ek <= tol;
+      double got[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) got[q] = __shfl(diag[q], s * kBsPar * P + k * P + b, 64);
+      if (now) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) yacc[q] = got[q];
+        acc = true;
+      }
+      // slot 0 decided: nothing can precede it
+      if (__ballot(acc && lane == 0) != 0ull) break;
+    }
+  }
+  // first accepted slot in sequential order
+  const unsigned long long am = __ballot(acc && c == 0 && b == 0);
+  if (am == 0ull) return -1;
+  const int sacc = (__ffsll((long long)am) - 1) / (kBsPar * P);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) y[q] = __shfl(yacc[q], sacc * kBsPar * P + b, 64);
+  (void)S;
+  return sacc;
+}
+
+// Binary refinement over [0, H] with speculative depths: a round at depth d
+// also tries d+1..d+S-1 on the first halves, which is where the sequential
+// scheme goes after failures.
+template <int P>
+__device__ __forceinline__ int bs_integrate_par(int sz, double y[6], double H, const ParBody<P>& Q,
+                                double G, double Gm0, double tol, int D,
+                                long long* nsub) {
+  constexpr int S = kBsPar / P;
+  long long pos = 0;
+  const long long total = 1ll << D;
+  int d = 0;
+  int attempts = 0;
+  while (pos < total) {
+    if (++attempts > kBsMaxAttempts) return -1;
+    const int smax = min(S, D - d + 1);  // never beyond the depth limit
+    double yt[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) yt[q] = y[q];
+    int sa = bs_round_par<P>(sz, yt, ldexp(H, -d), Q, G, Gm0, tol);
+    if (sa >= smax) sa = -1;
+    if (sa >= 0) {
+      d += sa;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) y[q] = yt[q];
+      ++*nsub;
+      pos += 1ll << (D - d);
+      while (d > 0 && (pos % (1ll << (D - d + 1))) == 0) --d;
+    } else {
+      d += smax;
+      if (d > D) return -1;
+    }
+  }
+  return 0;
+}
+
+template <int P>
+__device__ __forceinline__ int bs_group_par(const BsArgs& a, int sz, const int* mem, long long* nsub) {
+  const int lane = threadIdx.x & 63;
+  const int b = lane % P;
+  const int id = b < sz ? mem[b] : -1;
+  double y[6] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double rcb = 0.0;
+  if (id >= 0) {
+    const double4 p = a.xpre[id], q = a.vpre[id];
+    y[0] = p.x;
+    y[1] = p.y;
+    y[2] = p.z;
+    y[3] = q.x;
+    y[4] = q.y;
+    y[5] = q.z;
+    rcb = a.rc[id];
+  }
+  ParBody<P> Q;
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    int j = b + q;
+    j = j >= sz ? j - sz : j;
+    j = j >= sz ? j - sz : j;  // dummy slots (b >= sz) wrap twice at most
+    Q.lane[q] = lane - b + j;
+    Q.m[q] = 0.0;
+    Q.rcij[q] = 0.0;
+    Q.i09[q] = 0.0;
+    if (q < sz) {
+      const int idj = mem[j];
+      Q.m[q] = a.xm[idj].w;
+      Q.rcij[q] = fmax(rcb, a.rc[idj]);
+      Q.i09[q] = Q.rcij[q] > 0.0 ? 1.0 / (0.9 * Q.rcij[q]) : 0.0;
+    }
+  }
+  const int r = bs_integrate_par<P>(sz, y, a.dt, Q, a.G, a.Gm0, a.tol, a.max_depth, nsub);
+  if (lane < P && id >= 0) {
+    const double m = a.xm[id].w;
+    a.xm[id] = make_double4(y[0], y[1], y[2], m);
+    a.vv[id] = make_double4(y[3], y[4], y[5], 0.0);
+  }
+  return r;
+}
+
 // One wave per encounter group (grid-stride over the device-side count):
 // members sorted ascending, state reset to the pre-drift copy, H_A integrated
-// over tau by BS, result written back.
+// over tau by BS, result written back.  Groups of up to 8 members take the
+// all-columns path with speculative depths, larger ones (up to 64) one lane
+// per member with the columns in sequence.
 __global__ __launch_bounds__(64) void k_bs(BsArgs a) {
   __shared__ double R[kBsCols][6][64];
   __shared__ int mem[64];
@@ -721,27 +951,39 @@ __global__ __launch_bounds__(64) void k_bs(BsArgs a) {
     __syncthreads();
     if (lane < sz) mem[rank] = my;
     __syncthreads();
-    const int b = lane < sz ? mem[lane] : -1;
-    double y[6] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    double m = 0.0, rc = 0.0;
-    if (b >= 0) {
-      const double4 p = a.xpre[b], q = a.vpre[b];
-      y[0] = p.x;
-      y[1] = p.y;
-      y[2] = p.z;
-      y[3] = q.x;
-      y[4] = q.y;
-      y[5] = q.z;
-      m = a.xm[b].w;
-      rc = a.rc[b];
+    if (sz <= kBsPar) {
+      int r;
+      if (sz <= 2)
+        r = bs_group_par<2>(a, sz, mem, &nsub);
+      else if (sz <= 4)
+        r = bs_group_par<4>(a, sz, mem, &nsub);
+      else
+        r = bs_group_par<8>(a, sz, mem, &nsub);
+      if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
+    } else {
+      const int bb = lane < sz ? mem[lane] : -1;
+      double y[6] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      double m = 0.0, rc = 0.0;
+      if (bb >= 0) {
+        const double4 p = a.xpre[bb], q = a.vpre[bb];
+        y[0] = p.x;
+        y[1] = p.y;
+        y[2] = p.z;
+        y[3] = q.x;
+        y[4] = q.y;
+        y[5] = q.z;
+        m = a.xm[bb].w;
+        rc = a.rc[bb];
+      }
+      const int r = bs_integrate(sz, lane, y, a.dt, m, rc, a.G, a.Gm0, a.tol,
+                                 a.max_depth, R, &nsub);
+      if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
+      if (bb >= 0) {
+        a.xm[bb] = make_double4(y[0], y[1], y[2], m);
+        a.vv[bb] = make_double4(y[3], y[4], y[5], 0.0);
+      }
     }
-    const int r = bs_integrate(sz, lane, y, a.dt, m, rc, a.G, a.Gm0, a.tol,
-                               a.max_depth, R, &nsub);
-    if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
-    if (b >= 0) {
-      a.xm[b] = make_double4(y[0], y[1], y[2], m);
-      a.vv[b] = make_double4(y[3], y[4], y[5], 0.0);
-    }
+    __syncthreads();
   }
   if (lane == 0 && nsub > 0) atomicAdd(&a.st->bs_sub, (unsigned long long)nsub);
 }
@@ -904,7 +1146,7 @@ __global__ void k_energy_rows(const double4* __restrict__ xm, const double4* __r
   r[8] = p.w * (p.x * q.y - p.y * q.x);
 }
 
-__global__ __launch_bounds__(1024) void k_energy_final(const double* __restrict__ rows,
+__global__ __launch_bounds__(256) void k_energy_final(const double* __restrict__ rows,
                                                        int n, double m0,
                                                        double* __restrict__ E,
                                                        double* __restrict__ L) {
@@ -912,12 +1154,12 @@ __global__ __launch_bounds__(1024) void k_energy_final(const double* __restrict_
   double t[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) t[k] = 0.0;
-  for (int i = threadIdx.x; i < n; i += 1024)
+  for (int i = threadIdx.x; i < n; i += 256)
 #pragma unroll
     for (int k = 0; k < 9; ++k) t[k] += rows[9 * (size_t)i + k];
   double s[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) s[k] = block_sum<1024>(t[k], sh);
+  for (int k = 0; k < 9; ++k) s[k] = block_sum<256>(t[k], sh);
   if (threadIdx.x == 0) {
     E[0] = s[0] + (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]) / (2.0 * m0) + s[1] + s[2];
     L[0] = s[6];
@@ -953,7 +1195,6 @@ KickArgs kick_args(const MassiveWs& w, const StepConsts& c) {
   a.thr = w.thr;
   a.rc = w.rc_cur;
   a.part = w.part;
-  a.tilecnt = w.tilecnt;
   a.ccnt = w.ccnt;
   a.ctab = w.ctab;
   a.vv = w.vv;
@@ -1042,7 +1283,6 @@ size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base) {
   w.red = (double*)take(std::max<size_t>(np * 9, 64) * sizeof(double));
   w.ccnt = (int*)take(np * sizeof(int));
   w.ctab = (int*)take(np * (size_t)std::max(1, w.cpb) * sizeof(int));
-  w.tilecnt = (unsigned*)take((size_t)w.nitile * sizeof(unsigned));
   w.encij = (int2*)take((size_t)std::max(1, w.enc_cap) * sizeof(int2));
   w.encd2 = (double*)take((size_t)std::max(1, w.enc_cap) * sizeof(double));
   w.encrc2 = (double*)take((size_t)std::max(1, w.enc_cap) * sizeof(double));
@@ -1074,13 +1314,12 @@ hipError_t massive_unpack(const MassiveWs& w, const StepConsts& c, double* x,
 }
 
 hipError_t massive_prime(const MassiveWs& w, const StepConsts& c, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(w.tilecnt, 0, (size_t)w.nitile * sizeof(unsigned), s);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_rcrit_init, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xm, w.vv,
                      w.rc_cur, w.thr, w.ccnt, w.n, c.mu, c.m0, c.n1, c.n2, fabs(c.dt),
                      c.pf2, c.encounter_free);
   KickArgs a = kick_args(w, c);
   hipLaunchKernelGGL(k_kick<KICK_INIT>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
+  hipLaunchKernelGGL(k_kick_finish<KICK_INIT>, dim3(w.nblk), dim3(kVecBlock), 0, s, a, w.njb);
   return hipGetLastError();
 }
 
@@ -1089,6 +1328,7 @@ hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, double* acc,
   KickArgs a = kick_args(w, c);
   a.acc_out = acc;
   hipLaunchKernelGGL(k_kick<KICK_ACC>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
+  hipLaunchKernelGGL(k_kick_finish<KICK_ACC>, dim3(w.nblk), dim3(kVecBlock), 0, s, a, w.njb);
   return hipGetLastError();
 }
 
@@ -1169,6 +1409,7 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s) 
 
   KickArgs a = kick_args(w, c);
   hipLaunchKernelGGL(k_kick<KICK_CLOSE>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
+  hipLaunchKernelGGL(k_kick_finish<KICK_CLOSE>, dim3(w.nblk), dim3(kVecBlock), 0, s, a, w.njb);
   return hipGetLastError();
 }
 
@@ -1176,7 +1417,7 @@ hipError_t massive_energy(const MassiveWs& w, const StepConsts& c, double* dE,
                           double* dL, hipStream_t s) {
   hipLaunchKernelGGL(k_energy_rows, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xm, w.vv,
                      w.n, c.G, c.m0, w.red);
-  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(1024), 0, s, w.red, w.n, c.m0, dE, dL);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, w.red, w.n, c.m0, dE, dL);
   return hipGetLastError();
 }
 

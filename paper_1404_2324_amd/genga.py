@@ -63,6 +63,7 @@ SIGNATURES = {
     "genga_get_state": (_i32, [_vp, _vp, _vp, _i32]),
     "genga_set_state": (_i32, [_vp, _vp, _vp, _i32]),
     "genga_energy": (_i32, [_vp, _vp, _vp]),
+    "genga_accel_state": (_i32, [_vp, _vp]),
     "genga_encounters": (_i32, [_vp, _vp, _vp, _vp, _i32, ctypes.POINTER(_i32)]),
     "genga_candidates": (_i32, [_vp, _vp, _i32, ctypes.POINTER(_i32)]),
     "genga_stats": (_i32, [_vp, ctypes.POINTER(Stats)]),
@@ -173,6 +174,13 @@ class Simulation:
         _check(lib().genga_energy(self._ctx, _ptr(E), _ptr(L)), "genga_energy")
         torch.cuda.synchronize(self.device)
         return float(E[0]), L.cpu().numpy()
+
+    def accel_state(self, out=None):
+        """H_B acceleration of the current state (pair kernel only)."""
+        if out is None:
+            out = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
+        _check(lib().genga_accel_state(self._ctx, _ptr(out)), "genga_accel_state")
+        return out
 
     def encounters(self):
         n = ctypes.c_int()
