@@ -80,7 +80,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=32)
-    ap.add_argument("--kick-reps", type=int, default=200)
+    ap.add_argument("--kick-steps", type=int, default=64,
+                    help="steps run launch by launch to time the pair kernel")
+    ap.add_argument("--big-n", type=int, default=16384,
+                    help="bodies of the encounter-free kick capability run (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed region run one 256 MiB device copy (counter scale)")
@@ -118,18 +121,23 @@ def main():
     sec = gpu_ms / 1e3
     st = sim.stats()
 
-    # live timing of the pair-kick kernel (same pair loop, acceleration out)
-    acc = torch.empty((n, 3), dtype=torch.float64, device="cuda")
-    for _ in range(10):
-        sim.accel_state(acc)
-    torch.cuda.synchronize()
-    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    k0.record(stream)
-    for _ in range(args.kick_reps):
-        sim.accel_state(acc)
-    k1.record(stream)
-    torch.cuda.synchronize()
-    kick_s = k0.elapsed_time(k1) / 1e3 / args.kick_reps
+    # live timing of the closing-kick pair kernel inside real steps (launched
+    # one by one with HIP events around it on the context's stream)
+    kick_us = sim.step_profiled(args.kick_steps)
+    kick_s = kick_us * 1e-6
+
+    # capability of the same pair kernel at a size that fills the chip
+    big = None
+    if args.big_n > 0:
+        sb = W.planetesimals(args.big_n, seed_index=2)
+        simb = G.Simulation(sb.m, sb.x, sb.u, G.default_params(encounter_free=1), coords="helio")
+        simb.step(2)
+        big_us = simb.step_profiled(8)
+        nb = args.big_n
+        big = {"n_bodies": nb, "kernel_us": big_us,
+               "pair_rate": nb * (nb - 1) / (big_us * 1e-6),
+               "tflops": FLOPS_PER_PAIR * nb * (nb - 1) / (big_us * 1e-6) / 1e12}
+        simb.close()
 
     if args.calib_copy:
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
@@ -160,10 +168,11 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic,
-                     "kernel": "k_kick (pair kick, acceleration mode)",
+                     "kernel": "k_kick<0> (closing-kick pair kernel)",
                      "kernel_us": kick_s * 1e6,
                      "flops_per_pair": FLOPS_PER_PAIR,
-                     "kick_pair_rate": pairs / kick_s},
+                     "kick_pair_rate": pairs / kick_s,
+                     "large_n": big},
         "stats": {k: st[k] for k in ("n_cand", "n_enc", "n_groups", "max_group",
                                       "kepler_iter_max", "bs_substeps", "enc_total",
                                       "full_kicks")},

@@ -130,6 +130,13 @@ int genga_init(genga_ctx **ctx, int mode, const genga_params *p,
  * errors latch in the device status.  nsteps >= 0. */
 int genga_step(genga_ctx *ctx, int64_t nsteps);
 
+/* Measurement form of genga_step: the same nsteps steps launched one kernel
+ * at a time (no graph), with HIP events recorded on the context's stream
+ * around each closing-kick pair kernel; *h_kick_us receives that kernel's
+ * average duration in microseconds.  Synchronising; returns the latched
+ * status. */
+int genga_step_profiled(genga_ctx *ctx, int64_t nsteps, double *h_kick_us);
+
 /* Wait for the context's stream and return the latched device status as a
  * GENGA_E* code (GENGA_OK when clean).  Synchronising. */
 int genga_sync(genga_ctx *ctx);

@@ -176,6 +176,31 @@ int genga_step(genga_ctx* ctx, int64_t nsteps) {
   return GENGA_OK;
 }
 
+int genga_step_profiled(genga_ctx* ctx, int64_t nsteps, double* h_kick_us) {
+  if (!ctx || nsteps < 1 || !h_kick_us) return GENGA_EINVAL;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return GENGA_EHIP;
+  }
+  double tot = 0.0;
+  int rc = GENGA_OK;
+  for (int64_t k = 0; k < nsteps && rc == GENGA_OK; ++k) {
+    float ms = 0.0f;
+    if (massive_step(ctx->w, ctx->c, ctx->stream, e0, e1) != hipSuccess ||
+        hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      rc = GENGA_EHIP;
+    tot += ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != GENGA_OK) return rc;
+  ctx->steps += nsteps;
+  *h_kick_us = tot * 1e3 / (double)nsteps;
+  return genga_sync(ctx);
+}
+
 int genga_sync(genga_ctx* ctx) {
   if (!ctx) return GENGA_EINVAL;
   DevStat hs;

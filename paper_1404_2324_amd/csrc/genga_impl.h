@@ -35,6 +35,7 @@ struct DevStat {
   unsigned long long enc_total;  // encounters (cumulative)
   unsigned long long fullkicks;  // opening kicks recomputed in full
   unsigned long long tp_enc_total;
+  double P2[4];        // momentum for the second Sun kick of the step
 };
 
 constexpr int kBsMaxGroup = 64;        // members per in-wave BS group
@@ -59,7 +60,9 @@ struct MassiveWs {
   double* rc_cur;       // radii of the current step
   double* rc_next;      // radii for the next step
   double* thr;          // max((pf rc)^2, tiny): candidate threshold
-  double* partP;        // momentum partials [nblk][4]
+  double* partP;        // momentum partials after the opening kick [nblk][4]
+  double* partP2;       // momentum partials after the drift [nblk][4]
+  double* dP;           // momentum change of each BS group [np/2+1][4]
   double* red;          // scratch for reductions (energy, conversions)
   int* ccnt;            // candidates per body
   int* ctab;            // candidate partners [np][cpb]
@@ -91,7 +94,9 @@ hipError_t massive_unpack(const MassiveWs& w, const StepConsts& c, double* x,
                           double* v, int coords_out, hipStream_t s);
 hipError_t massive_prime(const MassiveWs& w, const StepConsts& c,
                          hipStream_t s);
-hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s);
+// ev0/ev1 (may be null) are recorded around the closing-kick pair kernel.
+hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t massive_energy(const MassiveWs& w, const StepConsts& c, double* dE,
                           double* dL, hipStream_t s);
 hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, double* acc,

@@ -2,15 +2,17 @@
 // arXiv:1404.2324, Sec. 2.2 step recipe and Sec. 3.2 kernels), for gfx950.
 //
 // One step is seven launches on one stream (captured once into a HIP graph):
-//   k_kick_open  opening kick: cached non-candidate acceleration + candidate
-//                pairs recomputed with the new radii (KickA/KickB, Sec 3.2.3)
-//   k_drift      Sun kick tau/2 (Eq. 3) + pre-drift copy + Kepler drift (Eq. 9)
-//   k_enc_group  Hermite test of the candidates (Eqs. 10-12) with ballot
-//                compaction, then equivalence classes in LDS (App. A)
-//   k_bs         Bulirsch-Stoer integration of H_A per group, one wave each
-//   k_sun2       Sun kick tau/2 and reset of the candidate table
-//   k_kick       closing kick: all pairs and the prechecker, per j-block
-//   k_kick_finish  fixed-order sum of the partials, v += tau/2 a, next radii
+//   k_kick_open    opening kick: cached non-candidate acceleration + candidate
+//                  pairs recomputed with the new radii (KickA/KickB, Sec 3.2.3)
+//   k_drift        Sun kick tau/2 (Eq. 3) + pre-drift copy + Kepler drift
+//                  (Eq. 9) + momentum partials for the second Sun kick
+//   k_encounter    Hermite test of every candidate (Eqs. 10-12), ballot
+//                  compaction of the confirmed pairs
+//   k_group        equivalence classes of the pairs in LDS (App. A)
+//   k_bs           Bulirsch-Stoer integration of H_A per group, one wave each
+//   k_kick         closing kick: all pairs and the prechecker, per j-block
+//   k_kick_finish  fixed-order sum of the partials, second Sun kick tau/2,
+//                  v += tau/2 a, next radii
 #include <climits>
 
 #include "device_math.h"
@@ -45,7 +47,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // ---------------------------------------------------------------------------
 struct KickArgs {
-  const double4* __restrict__ xm;
+  const double4* __restrict__ xm;     // read by the pair kernel
+  double4* __restrict__ xm_rw;        // same array, updated by the finish
   const double* __restrict__ thr;
   const double* __restrict__ rc;
   double4* __restrict__ part;
@@ -55,8 +58,10 @@ struct KickArgs {
   double4* __restrict__ afar;
   double* __restrict__ rc_next;
   double* __restrict__ acc_out;
+  const double* __restrict__ partP2;  // momentum partials after the drift
+  const double* __restrict__ dP;      // momentum change of each BS group
   DevStat* __restrict__ st;
-  int n, np, jb_len, cpb;
+  int n, np, jb_len, cpb, nblk;
   int encounter_free;
   double G, h, m0, mu, n1, n2, absdt, pf;
 };
@@ -129,6 +134,30 @@ __global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a) {
     }
   }
 
+  if (MODE == KICK_CLOSE && blockIdx.x == 0 && blockIdx.y == 0 && wave == 0) {
+    // momentum after the drift and BS for the second Sun kick: drift partials
+    // plus each group's change, strided over the lanes, then a butterfly
+    double px = 0.0, py = 0.0, pz = 0.0;
+    for (int b = lane; b < a.nblk; b += 64) {
+      px += a.partP2[4 * b + 0];
+      py += a.partP2[4 * b + 1];
+      pz += a.partP2[4 * b + 2];
+    }
+    const int ng = a.encounter_free ? 0 : a.st->ngroups;
+    for (int g = lane; g < ng; g += 64) {
+      px += a.dP[4 * g + 0];
+      py += a.dP[4 * g + 1];
+      pz += a.dP[4 * g + 2];
+    }
+    px = wave_sum(px);
+    py = wave_sum(py);
+    pz = wave_sum(pz);
+    if (lane == 0) {
+      a.st->P2[0] = px;
+      a.st->P2[1] = py;
+      a.st->P2[2] = pz;
+    }
+  }
   __shared__ double sh[W][6][64];
   sh[wave][0][lane] = fx;
   sh[wave][1][lane] = fy;
@@ -152,27 +181,45 @@ __global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a) {
   }
 }
 
-// Closing-kick epilogue, one lane per body: the j-block partials are summed
-// in a fixed order; the far part is kept for the next opening kick.
-//   CLOSE: v += tau/2 a, next radii (Eq. 6) and the reuse check
+// Closing-kick epilogue, four lanes per body: the j-block partials are summed
+// in a fixed order (strided per lane, then a butterfly over the four lanes);
+// the far part is kept for the next opening kick.
+//   CLOSE: second Sun kick of the step (x += tau/2 P/m0 with P assembled by
+//          the pair kernel from the drift's momentum partials and each BS
+//          group's momentum change; the pair kernel only needs relative
+//          positions, so the shift can follow it), v += tau/2 a, next radii
+//          (Eq. 6) and the reuse check
 //   INIT:  far part only (first step's opening kick)
 //   ACC:   acceleration out
 template <int MODE>
 __global__ __launch_bounds__(kVecBlock) void k_kick_finish(KickArgs a, int njb) {
-  const int i = blockIdx.x * kVecBlock + threadIdx.x;
-  if (i >= a.n) return;
+  const int t = blockIdx.x * kVecBlock + threadIdx.x;
+  const int i = t >> 2, sub = t & 3;
+  const bool iv = i < a.n;
   double S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0;
-  for (int b = 0; b < njb; ++b) {
-    const double4* q = &a.part[((size_t)b * a.np + i) * 2];
-    const double4 f = q[0];
-    const double4 g = q[1];
-    S0 += f.x;
-    S1 += f.y;
-    S2 += f.z;
-    S3 += g.x;
-    S4 += g.y;
-    S5 += g.z;
+  if (iv) {
+    for (int b = sub; b < njb; b += 4) {
+      const double4* q = &a.part[((size_t)b * a.np + i) * 2];
+      const double4 f = q[0];
+      const double4 g = q[1];
+      S0 += f.x;
+      S1 += f.y;
+      S2 += f.z;
+      S3 += g.x;
+      S4 += g.y;
+      S5 += g.z;
+    }
   }
+#pragma unroll
+  for (int o = 1; o < 4; o <<= 1) {
+    S0 += __shfl_xor(S0, o, 64);
+    S1 += __shfl_xor(S1, o, 64);
+    S2 += __shfl_xor(S2, o, 64);
+    S3 += __shfl_xor(S3, o, 64);
+    S4 += __shfl_xor(S4, o, 64);
+    S5 += __shfl_xor(S5, o, 64);
+  }
+  if (!iv || sub != 0) return;
   const double G = a.G;
   if (MODE == KICK_ACC) {
     a.acc_out[3 * (size_t)i + 0] = G * (S0 + S3);
@@ -185,12 +232,17 @@ __global__ __launch_bounds__(kVecBlock) void k_kick_finish(KickArgs a, int njb) 
     a.rc_next[i] = a.rc[i];
     return;
   }
+  const double Px = a.st->P2[0], Py = a.st->P2[1], Pz = a.st->P2[2];
+  double4 p = a.xm_rw[i];
+  p.x += a.h * Px / a.m0;
+  p.y += a.h * Py / a.m0;
+  p.z += a.h * Pz / a.m0;
+  a.xm_rw[i] = p;
   double4 v = a.vv[i];
   v.x += a.h * (G * (S0 + S3));
   v.y += a.h * (G * (S1 + S4));
   v.z += a.h * (G * (S2 + S5));
   a.vv[i] = v;
-  const double4 p = a.xm[i];
   const double rcn =
       rcrit(p.x, p.y, p.z, v.x, v.y, v.z, p.w, a.mu, a.m0, a.n1, a.n2, a.absdt);
   a.rc_next[i] = rcn;
@@ -256,16 +308,44 @@ __global__ __launch_bounds__(kVecBlock) void k_kick_open(OpenArgs a) {
       const int cnt = min(a.ccnt[i], a.cpb);
       const int* row = a.ctab + (size_t)i * a.cpb;
       double cx = 0.0, cy = 0.0, cz = 0.0;
-      int prev = -1;
-      for (int t = 0; t < cnt; ++t) {
-        int jm = INT_MAX;
-        for (int u = 0; u < cnt; ++u) {
-          const int j = row[u];
-          jm = (j > prev && j < jm) ? j : jm;
+      // up to 8 partners loaded at once and put in ascending order by a
+      // sorting network; longer rows continue with an ordered scan
+      constexpr int kPre = 8;
+      int jj[kPre];
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) jj[u] = u < cnt ? row[u] : INT_MAX;
+#pragma unroll
+      for (int p1 = 0; p1 < kPre; ++p1)
+#pragma unroll
+        for (int p2 = (p1 & 1); p2 + 1 < kPre; p2 += 2) {
+          const int lo = min(jj[p2], jj[p2 + 1]), hi = max(jj[p2], jj[p2 + 1]);
+          jj[p2] = lo;
+          jj[p2 + 1] = hi;
         }
-        if (jm == INT_MAX) break;
-        prev = jm;
-        pair_hb(p.x, p.y, p.z, rci, a.xm[jm], a.rc_next[jm], a.encounter_free, cx, cy, cz);
+      int prev = -1;
+      if (cnt <= kPre) {
+        double4 pj[kPre];
+        double rj[kPre];
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+          const int jl = u < cnt ? jj[u] : i;  // padded slots read a valid index
+          pj[u] = a.xm[jl];
+          rj[u] = a.rc_next[jl];
+        }
+#pragma unroll
+        for (int u = 0; u < kPre; ++u)
+          if (u < cnt) pair_hb(p.x, p.y, p.z, rci, pj[u], rj[u], a.encounter_free, cx, cy, cz);
+      } else {
+        for (int t = 0; t < cnt; ++t) {
+          int jm = INT_MAX;
+          for (int u = 0; u < cnt; ++u) {
+            const int j = row[u];
+            jm = (j > prev && j < jm) ? j : jm;
+          }
+          if (jm == INT_MAX) break;
+          prev = jm;
+          pair_hb(p.x, p.y, p.z, rci, a.xm[jm], a.rc_next[jm], a.encounter_free, cx, cy, cz);
+        }
       }
       ax = af.x + a.G * cx;
       ay = af.y + a.G * cy;
@@ -301,14 +381,18 @@ struct DriftArgs {
   double4* __restrict__ xpre;
   double4* __restrict__ vpre;
   const double* __restrict__ partP;
+  double* __restrict__ partP2;
   DevStat* __restrict__ st;
   int n, nblk, max_iter;
   double h, m0, mu, dt;
 };
 
 // Sun kick tau/2 (H_C flow: x += tau/2 P/m0, Eq. 3) with P summed from the
-// opening kick's block partials, copy of the pre-drift state, Kepler drift.
+// opening kick's block partials, copy of the pre-drift state, Kepler drift;
+// leaves the momentum partials of the drifted velocities for the second Sun
+// kick and resets the step's encounter counters and control word.
 __global__ __launch_bounds__(kVecBlock) void k_drift(DriftArgs a) {
+  __shared__ double sh[kVecBlock / 64];
   double Px = 0.0, Py = 0.0, Pz = 0.0;
   for (int b = 0; b < a.nblk; ++b) {
     Px += a.partP[4 * b + 0];
@@ -317,22 +401,41 @@ __global__ __launch_bounds__(kVecBlock) void k_drift(DriftArgs a) {
   }
   const int i = blockIdx.x * kVecBlock + threadIdx.x;
   int it = 0;
+  double m = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
   if (i < a.n) {
     const double4 p = a.xm[i];
     const double4 q = a.vv[i];
     double x = p.x + a.h * Px / a.m0;
     double y = p.y + a.h * Py / a.m0;
     double z = p.z + a.h * Pz / a.m0;
-    double vx = q.x, vy = q.y, vz = q.z;
+    vx = q.x;
+    vy = q.y;
+    vz = q.z;
     a.xpre[i] = make_double4(x, y, z, 0.0);
     a.vpre[i] = q;
     it = kepler_drift(a.mu, a.dt, x, y, z, vx, vy, vz, a.max_iter);
     if (it < 0) atomicOr(&a.st->flags, F_KEPLER);
     a.xm[i] = make_double4(x, y, z, p.w);
     a.vv[i] = make_double4(vx, vy, vz, 0.0);
+    m = p.w;
   }
   const int itm = wave_max_i(abs(it));
   if ((threadIdx.x & 63) == 0 && itm > 0) atomicMax(&a.st->kep_itmax, itm);
+  const double Qx = block_sum<kVecBlock>(m * vx, sh);
+  const double Qy = block_sum<kVecBlock>(m * vy, sh);
+  const double Qz = block_sum<kVecBlock>(m * vz, sh);
+  if (threadIdx.x == 0) {
+    a.partP2[4 * blockIdx.x + 0] = Qx;
+    a.partP2[4 * blockIdx.x + 1] = Qy;
+    a.partP2[4 * blockIdx.x + 2] = Qz;
+    if (blockIdx.x == 0) {
+      a.st->nenc = 0;
+      a.st->ncand = 0;
+      a.st->ngroups = 0;
+      a.st->maxg = 0;
+      a.st->ctl = 0u;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -342,7 +445,7 @@ struct EncArgs {
   const double4* __restrict__ xpre;
   const double4* __restrict__ vpre;
   const double* __restrict__ rc;
-  const int* __restrict__ ccnt;
+  int* __restrict__ ccnt;
   const int* __restrict__ ctab;
   int2* __restrict__ encij;
   double* __restrict__ encd2;
@@ -377,13 +480,57 @@ __device__ __forceinline__ int block_excl_scan(int v, int* shw, int* total) {
   return base + incl - v;
 }
 
-// Encounter search (Sec. 3.2.4) over the prechecker's candidates, then the
-// equivalence classes of the encounter pairs (App. A): LINK starts as the
-// identity, every pair lowers both ends to the smaller link (LDS atomic
-// min), links are shortened by LINK[i] = LINK[LINK[i]], and both sweeps
-// repeat until nothing changes.  Groups are numbered by their smallest
-// member; offsets and members go to global memory for the BS kernel.
-__global__ __launch_bounds__(kEncThreads) void k_enc_group(EncArgs a) {
+// Encounter search (Sec. 3.2.4): one lane per candidate slot (body i, slot
+// k) over all workgroups, so the candidates' loads overlap across the chip.
+// The Hermite minimum of Eqs. (10)-(12) is taken for pairs i < j; confirmed
+// pairs are appended with a ballot compaction (one atomic per wave).
+__global__ __launch_bounds__(kVecBlock) void k_encounter(EncArgs a) {
+  const int t = blockIdx.x * kVecBlock + threadIdx.x;
+  const int i = t / a.cpb, k = t - i * a.cpb;
+  const int lane = threadIdx.x & 63;
+  bool cand = false, enc = false;
+  int j = -1;
+  double d2 = 0.0, rc2 = 0.0;
+  if (i < a.n && k < min(a.ccnt[i], a.cpb)) {
+    j = a.ctab[(size_t)i * a.cpb + k];
+    if (j > i) {
+      cand = true;
+      const double4 xi0 = a.xpre[i], xj0 = a.xpre[j], vi0 = a.vpre[i], vj0 = a.vpre[j];
+      const double4 xi1 = a.xm[i], xj1 = a.xm[j], vi1 = a.vv[i], vj1 = a.vv[j];
+      d2 = hermite_dmin2(a.dt, xj0.x - xi0.x, xj0.y - xi0.y, xj0.z - xi0.z,
+                         vj0.x - vi0.x, vj0.y - vi0.y, vj0.z - vi0.z,
+                         xj1.x - xi1.x, xj1.y - xi1.y, xj1.z - xi1.z,
+                         vj1.x - vi1.x, vj1.y - vi1.y, vj1.z - vi1.z);
+      const double rcij = fmax(a.rc[i], a.rc[j]);
+      rc2 = rcij * rcij;
+      enc = d2 < rc2;
+    }
+  }
+  const unsigned long long cm = __ballot(cand);
+  const unsigned long long msk = __ballot(enc);
+  int b0 = 0;
+  if (lane == 0) {
+    if (cm) atomicAdd(&a.st->ncand, __popcll(cm));
+    if (msk) b0 = atomicAdd(&a.st->nenc, __popcll(msk));
+  }
+  b0 = __shfl(b0, 0, 64);
+  if (enc) {
+    const int pos = b0 + (int)lanemask_count(msk);
+    if (pos < a.enc_cap) {
+      a.encij[pos] = make_int2(i, j);
+      a.encd2[pos] = d2;
+      a.encrc2[pos] = rc2;
+    }
+  }
+}
+
+// Equivalence classes of the encounter pairs (App. A), one workgroup: LINK
+// starts as the identity, every pair lowers both ends to the smaller link
+// (LDS atomic min), links are shortened by LINK[i] = LINK[LINK[i]], and both
+// sweeps repeat until nothing changes.  Groups are numbered by their smallest
+// member; offsets and members go to global memory for the BS kernel.  Also
+// clears the candidate table for the closing kick.
+__global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
   __shared__ int link[kGroupMaxN];
   __shared__ int gid[kGroupMaxN];
   __shared__ int2 pr[kEncLds];
@@ -391,57 +538,18 @@ __global__ __launch_bounds__(kEncThreads) void k_enc_group(EncArgs a) {
   __shared__ int gof[kGroupMaxN / 2 + 1];
   __shared__ unsigned char inp[kGroupMaxN];
   __shared__ int shw[kEncThreads / 64];
-  __shared__ int s_ne, s_changed;
+  __shared__ int s_changed;
   const int tid = threadIdx.x, lane = tid & 63;
   const int n = a.n;
-  if (tid == 0) s_ne = 0;
+  const int ne_all = a.st->nenc;
+  const int ne = min(min(ne_all, kEncLds), a.enc_cap);
   for (int i = tid; i < n; i += kEncThreads) {
     link[i] = i;
     inp[i] = 0;
   }
+  for (int e = tid; e < ne; e += kEncThreads) pr[e] = a.encij[e];
   __syncthreads();
-
-  int ncl = 0;
-  for (int base = 0; base < n; base += kEncThreads) {
-    const int i = base + tid;
-    const int cnt = i < n ? min(a.ccnt[i], a.cpb) : 0;
-    for (int k = 0; k < cnt; ++k) {
-      const int j = a.ctab[(size_t)i * a.cpb + k];
-      bool enc = false;
-      double d2 = 0.0, rc2 = 0.0;
-      if (j > i) {
-        ++ncl;
-        const double4 xi0 = a.xpre[i], xj0 = a.xpre[j], vi0 = a.vpre[i], vj0 = a.vpre[j];
-        const double4 xi1 = a.xm[i], xj1 = a.xm[j], vi1 = a.vv[i], vj1 = a.vv[j];
-        d2 = hermite_dmin2(a.dt, xj0.x - xi0.x, xj0.y - xi0.y, xj0.z - xi0.z,
-                           vj0.x - vi0.x, vj0.y - vi0.y, vj0.z - vi0.z,
-                           xj1.x - xi1.x, xj1.y - xi1.y, xj1.z - xi1.z,
-                           vj1.x - vi1.x, vj1.y - vi1.y, vj1.z - vi1.z);
-        const double rcij = fmax(a.rc[i], a.rc[j]);
-        rc2 = rcij * rcij;
-        enc = d2 < rc2;
-      }
-      // ballot compaction: one LDS atomic per wave and iteration
-      const unsigned long long act = __ballot(1);
-      const unsigned long long msk = __ballot(enc);
-      const int leader = __ffsll((long long)act) - 1;
-      int b0 = 0;
-      if (lane == leader && msk) b0 = atomicAdd(&s_ne, __popcll(msk));
-      b0 = __shfl(b0, leader, 64);
-      if (enc) {
-        const int pos = b0 + (int)lanemask_count(msk);
-        if (pos < kEncLds) pr[pos] = make_int2(i, j);
-        if (pos < a.enc_cap) {
-          a.encij[pos] = make_int2(i, j);
-          a.encd2[pos] = d2;
-          a.encrc2[pos] = rc2;
-        }
-      }
-    }
-  }
-  __syncthreads();
-  const int ne_all = s_ne;
-  const int ne = min(ne_all, kEncLds);
+  for (int i = tid; i < n; i += kEncThreads) a.ccnt[i] = 0;
   for (int e = tid; e < ne; e += kEncThreads) {
     inp[pr[e].x] = 1;
     inp[pr[e].y] = 1;
@@ -523,7 +631,6 @@ __global__ __launch_bounds__(kEncThreads) void k_enc_group(EncArgs a) {
     for (int k = 0; k < kEncThreads / 64; ++k) m2 = max(m2, shw[k]);
     a.st->maxg = m2;
     a.st->ngroups = ng;
-    a.st->nenc = ne_all;
     a.st->enc_total += (unsigned long long)ne_all;
     if (ne_all > kEncLds || ne_all > a.enc_cap) atomicOr(&a.st->flags, F_ENC_OVF);
   }
@@ -534,18 +641,13 @@ __global__ __launch_bounds__(kEncThreads) void k_enc_group(EncArgs a) {
       a.gmem[pos] = i;
     }
   }
-  // candidate count for the statistics
-  __syncthreads();
-  int tc = 0;
-  const int csum = block_excl_scan(ncl, shw, &tc);
-  (void)csum;
-  if (tid == 0) a.st->ncand = tc;
 }
 
 // ---------------------------------------------------------------------------
 struct BsArgs {
   double4* __restrict__ xm;
   double4* __restrict__ vv;
+  double* __restrict__ dP;
   const double4* __restrict__ xpre;
   const double4* __restrict__ vpre;
   const double* __restrict__ rc;
@@ -884,8 +986,12 @@ __device__ __forceinline__ int bs_integrate_par(int sz, double y[6], double H, c
   return 0;
 }
 
+// Integrates one group of sz <= P members; returns the BS status and, per
+// member lane, the member's momentum change m (v_BS - v_drift).
 template <int P>
-__device__ __forceinline__ int bs_group_par(const BsArgs& a, int sz, const int* mem, long long* nsub) {
+__device__ __forceinline__ int bs_group_par(const BsArgs& a, int sz, const int* mem,
+                                            long long* nsub, double& dpx, double& dpy,
+                                            double& dpz) {
   const int lane = threadIdx.x & 63;
   const int b = lane % P;
   const int id = b < sz ? mem[b] : -1;
@@ -919,8 +1025,13 @@ __device__ __forceinline__ int bs_group_par(const BsArgs& a, int sz, const int* 
     }
   }
   const int r = bs_integrate_par<P>(sz, y, a.dt, Q, a.G, a.Gm0, a.tol, a.max_depth, nsub);
+  dpx = dpy = dpz = 0.0;
   if (lane < P && id >= 0) {
     const double m = a.xm[id].w;
+    const double4 vo = a.vv[id];
+    dpx = m * (y[3] - vo.x);
+    dpy = m * (y[4] - vo.y);
+    dpz = m * (y[5] - vo.z);
     a.xm[id] = make_double4(y[0], y[1], y[2], m);
     a.vv[id] = make_double4(y[3], y[4], y[5], 0.0);
   }
@@ -951,14 +1062,15 @@ __global__ __launch_bounds__(64) void k_bs(BsArgs a) {
     __syncthreads();
     if (lane < sz) mem[rank] = my;
     __syncthreads();
+    double dpx = 0.0, dpy = 0.0, dpz = 0.0;
     if (sz <= kBsPar) {
       int r;
       if (sz <= 2)
-        r = bs_group_par<2>(a, sz, mem, &nsub);
+        r = bs_group_par<2>(a, sz, mem, &nsub, dpx, dpy, dpz);
       else if (sz <= 4)
-        r = bs_group_par<4>(a, sz, mem, &nsub);
+        r = bs_group_par<4>(a, sz, mem, &nsub, dpx, dpy, dpz);
       else
-        r = bs_group_par<8>(a, sz, mem, &nsub);
+        r = bs_group_par<8>(a, sz, mem, &nsub, dpx, dpy, dpz);
       if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
     } else {
       const int bb = lane < sz ? mem[lane] : -1;
@@ -979,45 +1091,26 @@ __global__ __launch_bounds__(64) void k_bs(BsArgs a) {
                                  a.max_depth, R, &nsub);
       if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
       if (bb >= 0) {
+        const double4 vo = a.vv[bb];
+        dpx = m * (y[3] - vo.x);
+        dpy = m * (y[4] - vo.y);
+        dpz = m * (y[5] - vo.z);
         a.xm[bb] = make_double4(y[0], y[1], y[2], m);
         a.vv[bb] = make_double4(y[3], y[4], y[5], 0.0);
       }
     }
+    // the group's momentum change for the second Sun kick (fixed lane order)
+    dpx = wave_sum(dpx);
+    dpy = wave_sum(dpy);
+    dpz = wave_sum(dpz);
+    if (lane == 0) {
+      a.dP[4 * g + 0] = dpx;
+      a.dP[4 * g + 1] = dpy;
+      a.dP[4 * g + 2] = dpz;
+    }
     __syncthreads();
   }
   if (lane == 0 && nsub > 0) atomicAdd(&a.st->bs_sub, (unsigned long long)nsub);
-}
-
-// ---------------------------------------------------------------------------
-// Second Sun kick of the step (one workgroup): P from the current velocities,
-// x += tau/2 P/m0; clears the candidate counters and the control word for the
-// closing kick.
-__global__ __launch_bounds__(1024) void k_sun2(double4* __restrict__ xm,
-                                               const double4* __restrict__ vv,
-                                               int* __restrict__ ccnt,
-                                               DevStat* __restrict__ st, int n,
-                                               double h, double m0) {
-  __shared__ double sh[16];
-  double px = 0.0, py = 0.0, pz = 0.0;
-  for (int i = threadIdx.x; i < n; i += 1024) {
-    const double m = xm[i].w;
-    const double4 v = vv[i];
-    px += m * v.x;
-    py += m * v.y;
-    pz += m * v.z;
-  }
-  const double Px = block_sum<1024>(px, sh);
-  const double Py = block_sum<1024>(py, sh);
-  const double Pz = block_sum<1024>(pz, sh);
-  for (int i = threadIdx.x; i < n; i += 1024) {
-    double4 p = xm[i];
-    p.x += h * Px / m0;
-    p.y += h * Py / m0;
-    p.z += h * Pz / m0;
-    xm[i] = p;
-    ccnt[i] = 0;
-  }
-  if (threadIdx.x == 0) st->ctl = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1192,6 +1285,7 @@ __global__ void k_validate(const double* __restrict__ a, int64_t cnt, int* __res
 KickArgs kick_args(const MassiveWs& w, const StepConsts& c) {
   KickArgs a;
   a.xm = w.xm;
+  a.xm_rw = w.xm;
   a.thr = w.thr;
   a.rc = w.rc_cur;
   a.part = w.part;
@@ -1201,11 +1295,14 @@ KickArgs kick_args(const MassiveWs& w, const StepConsts& c) {
   a.afar = w.afar;
   a.rc_next = w.rc_next;
   a.acc_out = nullptr;
+  a.partP2 = w.partP2;
+  a.dP = w.dP;
   a.st = w.st;
   a.n = w.n;
   a.np = w.np;
   a.jb_len = w.jb_len;
   a.cpb = w.cpb;
+  a.nblk = w.nblk;
   a.encounter_free = c.encounter_free;
   a.G = c.G;
   a.h = c.h;
@@ -1280,6 +1377,8 @@ size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base) {
   w.rc_next = (double*)take(np * sizeof(double));
   w.thr = (double*)take(np * sizeof(double));
   w.partP = (double*)take((size_t)w.nblk * 4 * sizeof(double));
+  w.partP2 = (double*)take((size_t)w.nblk * 4 * sizeof(double));
+  w.dP = (double*)take((np / 2 + 1) * 4 * sizeof(double));
   w.red = (double*)take(std::max<size_t>(np * 9, 64) * sizeof(double));
   w.ccnt = (int*)take(np * sizeof(int));
   w.ctab = (int*)take(np * (size_t)std::max(1, w.cpb) * sizeof(int));
@@ -1319,7 +1418,7 @@ hipError_t massive_prime(const MassiveWs& w, const StepConsts& c, hipStream_t s)
                      c.pf2, c.encounter_free);
   KickArgs a = kick_args(w, c);
   hipLaunchKernelGGL(k_kick<KICK_INIT>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
-  hipLaunchKernelGGL(k_kick_finish<KICK_INIT>, dim3(w.nblk), dim3(kVecBlock), 0, s, a, w.njb);
+  hipLaunchKernelGGL(k_kick_finish<KICK_INIT>, dim3(ceil_div(4 * w.n, kVecBlock)), dim3(kVecBlock), 0, s, a, w.njb);
   return hipGetLastError();
 }
 
@@ -1328,11 +1427,12 @@ hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, double* acc,
   KickArgs a = kick_args(w, c);
   a.acc_out = acc;
   hipLaunchKernelGGL(k_kick<KICK_ACC>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
-  hipLaunchKernelGGL(k_kick_finish<KICK_ACC>, dim3(w.nblk), dim3(kVecBlock), 0, s, a, w.njb);
+  hipLaunchKernelGGL(k_kick_finish<KICK_ACC>, dim3(ceil_div(4 * w.n, kVecBlock)), dim3(kVecBlock), 0, s, a, w.njb);
   return hipGetLastError();
 }
 
-hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s) {
+hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
+                        hipEvent_t ev0, hipEvent_t ev1) {
   OpenArgs o;
   o.xm = w.xm;
   o.vv = w.vv;
@@ -1358,6 +1458,7 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s) 
   d.xpre = w.xpre;
   d.vpre = w.vpre;
   d.partP = w.partP;
+  d.partP2 = w.partP2;
   d.st = w.st;
   d.n = w.n;
   d.nblk = w.nblk;
@@ -1387,11 +1488,14 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s) 
     e.cpb = w.cpb;
     e.enc_cap = w.enc_cap;
     e.dt = c.dt;
-    hipLaunchKernelGGL(k_enc_group, dim3(1), dim3(kEncThreads), 0, s, e);
+    hipLaunchKernelGGL(k_encounter, dim3(ceil_div(w.n * w.cpb, kVecBlock)), dim3(kVecBlock), 0,
+                       s, e);
+    hipLaunchKernelGGL(k_group, dim3(1), dim3(kEncThreads), 0, s, e);
 
     BsArgs b;
     b.xm = w.xm;
     b.vv = w.vv;
+    b.dP = w.dP;
     b.xpre = w.xpre;
     b.vpre = w.vpre;
     b.rc = w.rc_cur;
@@ -1405,11 +1509,12 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s) 
     b.max_depth = c.bs_max_depth;
     hipLaunchKernelGGL(k_bs, dim3(std::max(1, std::min(256, w.n / 2))), dim3(64), 0, s, b);
   }
-  hipLaunchKernelGGL(k_sun2, dim3(1), dim3(1024), 0, s, w.xm, w.vv, w.ccnt, w.st, w.n, c.h, c.m0);
 
   KickArgs a = kick_args(w, c);
+  if (ev0) hipEventRecord(ev0, s);
   hipLaunchKernelGGL(k_kick<KICK_CLOSE>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
-  hipLaunchKernelGGL(k_kick_finish<KICK_CLOSE>, dim3(w.nblk), dim3(kVecBlock), 0, s, a, w.njb);
+  if (ev1) hipEventRecord(ev1, s);
+  hipLaunchKernelGGL(k_kick_finish<KICK_CLOSE>, dim3(ceil_div(4 * w.n, kVecBlock)), dim3(kVecBlock), 0, s, a, w.njb);
   return hipGetLastError();
 }
 

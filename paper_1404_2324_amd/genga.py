@@ -60,6 +60,7 @@ SIGNATURES = {
                           _vp, _i32, _vp, _sz, _vp]),
     "genga_step": (_i32, [_vp, _i64]),
     "genga_sync": (_i32, [_vp]),
+    "genga_step_profiled": (_i32, [_vp, _i64, ctypes.POINTER(ctypes.c_double)]),
     "genga_get_state": (_i32, [_vp, _vp, _vp, _i32]),
     "genga_set_state": (_i32, [_vp, _vp, _vp, _i32]),
     "genga_energy": (_i32, [_vp, _vp, _vp]),
@@ -146,6 +147,14 @@ class Simulation:
 
     def step(self, nsteps: int = 1):
         _check(lib().genga_step(self._ctx, int(nsteps)), "genga_step")
+
+    def step_profiled(self, nsteps: int):
+        """Run nsteps steps launch by launch; returns the closing-kick pair
+        kernel's average duration in microseconds (HIP events)."""
+        us = ctypes.c_double()
+        _check(lib().genga_step_profiled(self._ctx, int(nsteps), ctypes.byref(us)),
+               "genga_step_profiled")
+        return us.value
 
     def sync(self):
         return lib().genga_sync(self._ctx)
