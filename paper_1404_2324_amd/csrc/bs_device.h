@@ -1,0 +1,374 @@
+// Device code of the Bulirsch-Stoer integration of H_A (Eq. 1) for one
+// close-encounter group (Sec. 3.2.6), shared by the main-mode and the
+// test-particle kernels.  One wave integrates one group.
+#pragma once
+
+#include "device_math.h"
+
+namespace genga {
+
+constexpr int kBsCols = 8;
+constexpr int kBsMaxAttempts = 1 << 16;  // substep attempts per group and step
+
+// dv/dt of H_A for the lane's body: the fixed star plus the (1-K) part of the
+// group's pair terms (Eq. 1 gradient); other members' data by lane reads.
+__device__ __forceinline__ void ha_accel(int sz, int lane, double x, double y,
+                                         double z, double m, double rc,
+                                         double G, double Gm0, double& ax,
+                                         double& ay, double& az) {
+  const double r2 = x * x + y * y + z * z;
+  const double ir = rsqrt_nr(r2);
+  const double fs = -Gm0 * (ir * ir * ir);
+  ax = fs * x;
+  ay = fs * y;
+  az = fs * z;
+  for (int j = 0; j < sz; ++j) {
+    const double xj = readlane_d(x, j), yj = readlane_d(y, j), zj = readlane_d(z, j);
+    const double mj = readlane_d(m, j), rcj = readlane_d(rc, j);
+    if (j != lane) {
+      const double dx = xj - x, dy = yj - y, dz = zj - z;
+      const double q2 = dx * dx + dy * dy + dz * dz;
+      const double iq = rsqrt_nr(q2);
+      const double iq2 = iq * iq;
+      double K, dK;
+      changeover(q2 * iq, fmax(rc, rcj), K, dK);
+      const double s = G * mj * ((1.0 - K) * iq2 * iq + dK * iq2);
+      ax += s * dx;
+      ay += s * dy;
+      az += s * dz;
+    }
+  }
+}
+
+// Gragg's modified midpoint rule over H with nsub substeps (one wave, one
+// body per lane).
+__device__ __forceinline__ void mmid(int sz, int lane, const double y0[6], double H, int nsub,
+                     double m, double rc, double G, double Gm0, double out[6]) {
+  const double hs = H / nsub;
+  double ym[6], yn[6], d[6];
+  ha_accel(sz, lane, y0[0], y0[1], y0[2], m, rc, G, Gm0, d[3], d[4], d[5]);
+  d[0] = y0[3];
+  d[1] = y0[4];
+  d[2] = y0[5];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    ym[c] = y0[c];
+    yn[c] = y0[c] + hs * d[c];
+  }
+  for (int s = 1; s < nsub; ++s) {
+    ha_accel(sz, lane, yn[0], yn[1], yn[2], m, rc, G, Gm0, d[3], d[4], d[5]);
+    d[0] = yn[3];
+    d[1] = yn[4];
+    d[2] = yn[5];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double t = ym[c] + 2.0 * hs * d[c];
+      ym[c] = yn[c];
+      yn[c] = t;
+    }
+  }
+  ha_accel(sz, lane, yn[0], yn[1], yn[2], m, rc, G, Gm0, d[3], d[4], d[5]);
+  d[0] = yn[3];
+  d[1] = yn[4];
+  d[2] = yn[5];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) out[c] = 0.5 * (ym[c] + yn[c] + hs * d[c]);
+}
+
+__device__ __forceinline__ double relerr3(const double* A, const double* B) {
+  const double d0 = A[0] - B[0], d1 = A[1] - B[1], d2 = A[2] - B[2];
+  const double num = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  const double den = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+  return den > 0.0 ? num / den : num;
+}
+
+// One BS attempt over H: columns n_k = 2k (k = 1..8), Aitken-Neville
+// extrapolation in h^2 kept in LDS (R[col][comp][lane]), accepted at the first
+// column k >= 2 whose per-body relative error (max over the group) is within
+// tol.  Returns true and the extrapolated state in y on success.
+__device__ __forceinline__ bool bs_attempt(int sz, int lane, double y[6], double H, double m,
+                           double rc, double G, double Gm0, double tol,
+                           double (*R)[6][64]) {
+  for (int k = 0; k < kBsCols; ++k) {
+    const int nk = 2 * (k + 1);
+    double t[6];
+    mmid(sz, lane, y, H, nk, m, rc, G, Gm0, t);
+    for (int j = 1; j <= k; ++j) {
+      const double ratio = (double)nk / (double)(2 * (k - j + 1));
+      const double den = ratio * ratio - 1.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double u = t[c] + (t[c] - R[j - 1][c][lane]) / den;
+        R[j - 1][c][lane] = t[c];
+        t[c] = u;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) R[k][c][lane] = t[c];
+    if (k >= 1) {
+      double A[6], B[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        A[c] = R[k][c][lane];
+        B[c] = R[k - 1][c][lane];
+      }
+      double e = fmax(relerr3(A, B), relerr3(A + 3, B + 3));
+      if (lane >= sz) e = 0.0;
+      e = wave_max(e);
+      if (e <= tol) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) y[c] = A[c];
+        return true;
+      }
+    }
+  }
+  return false;
+}
+
+// Binary refinement over [0, H]: a failed substep is halved; after finishing
+// both halves of a node the next sibling is tried at the node's length.
+__device__ __forceinline__ int bs_integrate(int sz, int lane, double y[6], double H, double m,
+                            double rc, double G, double Gm0, double tol,
+                            int D, double (*R)[6][64], long long* nsub) {
+  long long pos = 0;
+  const long long total = 1ll << D;
+  int d = 0;
+  int attempts = 0;
+  while (pos < total) {
+    if (++attempts > kBsMaxAttempts) return -1;
+    double yt[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) yt[c] = y[c];
+    if (bs_attempt(sz, lane, yt, ldexp(H, -d), m, rc, G, Gm0, tol, R)) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) y[c] = yt[c];
+      ++*nsub;
+      pos += 1ll << (D - d);
+      while (d > 0 && (pos % (1ll << (D - d + 1))) == 0) --d;
+    } else {
+      ++d;
+      if (d > D) return -1;
+    }
+  }
+  return 0;
+}
+
+// ---- groups of up to 8 members: all columns, and several depths, at once ----
+// A wave of 64 lanes holds S = 8/P speculative refinement depths x 8 columns
+// x P member slots (P = 2, 4 or 8 >= group size):
+//   lane = s (8 P) + c P + b,  s = depth slot, c = column, b = member.
+// Column c integrates the modified midpoint rule with n_c = 2 (c + 1)
+// substeps; members exchange positions by lane shuffles.  Slot s attempts
+// the substep of length H / 2^s from the same start: exactly the attempts the
+// sequential scheme makes after s failures (the first half of each halving).
+// The Aitken-Neville tableau is built across the columns (T[c][j] needs
+// T[c-1][j-1] from lane - P); column k is tested when it completes (after
+// 2 k + 3 force evaluations), and each slot keeps its first column within
+// tolerance.  The result is the first accepted slot in sequential order, so
+// the substeps taken equal those of one-at-a-time evaluation.
+// TP: member 0 is a massless test particle and the other members feel only
+// the star (a test-particle encounter, Sec. 3.3).
+constexpr int kBsPar = 8;
+
+template <int P>
+struct ParBody {
+  int lane[P];     // lane of partner q (member (b + q) mod sz), q >= 1
+  double m[P];     // partner mass
+  double rcij[P];  // pair radius max(rc_b, rc_j)
+  double i09[P];   // 1 / (0.9 rc_ij), 0 when rc_ij = 0
+};
+
+template <int P, bool TP>
+__device__ __forceinline__ void ha_accel_par(int sz, int b, double x, double y,
+                                             double z, const ParBody<P>& Q,
+                                             double G, double Gm0, double& ax,
+                                             double& ay, double& az) {
+  const double r2 = x * x + y * y + z * z;
+  const double ir = rsqrt_nr(r2);
+  const double fs = -Gm0 * (ir * ir * ir);
+  ax = fs * x;
+  ay = fs * y;
+  az = fs * z;
+  const int np = (TP && b != 0) ? 1 : sz;  // planets in a particle's group: star only
+#pragma unroll
+  for (int q = 1; q < P; ++q) {
+    if (q >= sz) break;
+    const double xj = __shfl(x, Q.lane[q], 64);
+    const double yj = __shfl(y, Q.lane[q], 64);
+    const double zj = __shfl(z, Q.lane[q], 64);
+    if (q < np) {
+      const double dx = xj - x, dy = yj - y, dz = zj - z;
+      const double q2 = dx * dx + dy * dy + dz * dz;
+      const double iq = rsqrt_nr(q2);
+      const double iq2 = iq * iq;
+      double K = 1.0, dK = 0.0;
+      if (Q.rcij[q] > 0.0) changeover_clamped(q2 * iq, Q.rcij[q], Q.i09[q], K, dK);
+      const double sc = G * Q.m[q] * ((1.0 - K) * iq2 * iq + dK * iq2);
+      ax += sc * dx;
+      ay += sc * dy;
+      az += sc * dz;
+    }
+  }
+}
+
+// One speculative round: returns the accepted depth offset (0..S-1), with the
+// accepted state in y, or -1 when every slot failed.
+template <int P, bool TP>
+__device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
+                                            const ParBody<P>& Q, double G,
+                                            double Gm0, double tol) {
+  const int lane = threadIdx.x & 63;
+  const int s = lane / (kBsPar * P);
+  const int c = (lane / P) % kBsPar;
+  const int b = lane % P;
+  const int nsub = 2 * (c + 1);
+  const double hs = ldexp(H, -s) / nsub;
+  double ym[6], yn[6], T0[6], yacc[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    ym[q] = y[q];
+    yn[q] = y[q];
+    T0[q] = y[q];
+    yacc[q] = y[q];
+  }
+  bool acc = false;  // this slot has accepted a column
+  for (int e = 0; e <= 2 * kBsCols; ++e) {
+    double d[6];
+    ha_accel_par<P, TP>(sz, b, yn[0], yn[1], yn[2], Q, G, Gm0, d[3], d[4], d[5]);
+    d[0] = yn[3];
+    d[1] = yn[4];
+    d[2] = yn[5];
+    if (e == 0) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) yn[q] = ym[q] + hs * d[q];
+    } else if (e < nsub) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const double t = ym[q] + 2.0 * hs * d[q];
+        ym[q] = yn[q];
+        yn[q] = t;
+      }
+    } else if (e == nsub) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) T0[q] = 0.5 * (ym[q] + yn[q] + hs * d[q]);
+    }
+    if (e >= 4 && (e & 1) == 0) {
+      const int k = e / 2 - 1;  // column completed by this evaluation
+      double cur[6], diag[6], sub[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        cur[q] = T0[q];
+        diag[q] = T0[q];
+        sub[q] = T0[q];
+      }
+      for (int j = 1; j <= k; ++j) {
+        double nb[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) nb[q] = __shfl(cur[q], lane - (c >= 1 ? P : 0), 64);
+        if (j <= c) {
+          const double ratio = (double)(2 * (c + 1)) / (double)(2 * (c - j + 1));
+          const double den = ratio * ratio - 1.0;
+#pragma unroll
+          for (int q = 0; q < 6; ++q) {
+            if (j == c) sub[q] = cur[q];
+            cur[q] = cur[q] + (cur[q] - nb[q]) / den;
+            if (j == c) diag[q] = cur[q];
+          }
+        }
+      }
+      double err = 0.0;
+      if (c == k && b < sz) err = fmax(relerr3(diag, sub), relerr3(diag + 3, sub + 3));
+#pragma unroll
+      for (int o = 1; o < P; o <<= 1) err = fmax(err, __shfl_xor(err, o, 64));
+      // err of column k of this lane's slot, from lane (s, k, 0)
+      const double ek = __shfl(err, s * kBsPar * P + k * P, 64);
+      const bool now = !acc && ek <= tol;
+      double got[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) got[q] = __shfl(diag[q], s * kBsPar * P + k * P + b, 64);
+      if (now) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) yacc[q] = got[q];
+        acc = true;
+      }
+      // slot 0 decided: nothing can precede it
+      if (__ballot(acc && lane == 0) != 0ull) break;
+    }
+  }
+  // first accepted slot in sequential order
+  const unsigned long long am = __ballot(acc && c == 0 && b == 0);
+  if (am == 0ull) return -1;
+  const int sacc = (__ffsll((long long)am) - 1) / (kBsPar * P);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) y[q] = __shfl(yacc[q], sacc * kBsPar * P + b, 64);
+  return sacc;
+}
+
+// Binary refinement over [0, H] with speculative depths: a round at depth d
+// also tries d+1..d+S-1 on the first halves, which is where the sequential
+// scheme goes after failures.
+template <int P, bool TP>
+__device__ __forceinline__ int bs_integrate_par(int sz, double y[6], double H,
+                                                const ParBody<P>& Q, double G,
+                                                double Gm0, double tol, int D,
+                                                long long* nsub) {
+  constexpr int S = kBsPar / P;
+  long long pos = 0;
+  const long long total = 1ll << D;
+  int d = 0;
+  int attempts = 0;
+  while (pos < total) {
+    if (++attempts > kBsMaxAttempts) return -1;
+    const int smax = min(S, D - d + 1);  // never beyond the depth limit
+    double yt[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) yt[q] = y[q];
+    int sa = bs_round_par<P, TP>(sz, yt, ldexp(H, -d), Q, G, Gm0, tol);
+    if (sa >= smax) sa = -1;
+    if (sa >= 0) {
+      d += sa;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) y[q] = yt[q];
+      ++*nsub;
+      pos += 1ll << (D - d);
+      while (d > 0 && (pos % (1ll << (D - d + 1))) == 0) --d;
+    } else {
+      d += smax;
+      if (d > D) return -1;
+    }
+  }
+  return 0;
+}
+
+// One group of sz <= P members over H.  Lane member b = lane % P holds the
+// member's start state in y (dummy state for b >= sz); mm[] and mrc[] (any
+// memory) give every member's mass and critical radius.  On return y holds
+// member b's state after H in every lane.
+template <int P, bool TP>
+__device__ __forceinline__ int bs_group(int sz, double y[6], const double* mm,
+                                        const double* mrc, double H, double G,
+                                        double Gm0, double tol, int D,
+                                        long long* nsub) {
+  const int lane = threadIdx.x & 63;
+  const int b = lane % P;
+  const double rcb = b < sz ? mrc[b] : 0.0;
+  ParBody<P> Q;
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    int j = b + q;
+    j = j >= sz ? j - sz : j;
+    j = j >= sz ? j - sz : j;  // dummy slots (b >= sz) wrap twice at most
+    Q.lane[q] = lane - b + j;
+    Q.m[q] = 0.0;
+    Q.rcij[q] = 0.0;
+    Q.i09[q] = 0.0;
+    if (q < sz) {
+      Q.m[q] = mm[j];
+      Q.rcij[q] = fmax(rcb, mrc[j]);
+      Q.i09[q] = Q.rcij[q] > 0.0 ? 1.0 / (0.9 * Q.rcij[q]) : 0.0;
+    }
+  }
+  return bs_integrate_par<P, TP>(sz, y, H, Q, G, Gm0, tol, D, nsub);
+}
+
+}  // namespace genga

@@ -35,6 +35,25 @@ bool params_ok(const genga_params* p) {
 
 int max_bodies(const genga_params* p) { return p->encounter_free ? 65536 : kGroupMaxN; }
 
+constexpr int kTpMaxPlanets = 32;          // one bit per planet in a particle's mask
+constexpr int64_t kTpMaxParticles = 1ll << 30;
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool shape_ok(int mode, const genga_params* p, int nm, int64_t ntp) {
+  if (mode == GENGA_MASSIVE) return nm >= 1 && nm <= max_bodies(p) && ntp == 0;
+  if (mode == GENGA_TEST) return nm >= 1 && nm <= kTpMaxPlanets && ntp >= 0 && ntp <= kTpMaxParticles;
+  return false;
+}
+
+size_t ws_bytes(int mode, const genga_params& p, int nm, int64_t ntp) {
+  if (mode == GENGA_TEST) {
+    TpWs t;
+    return align256(massive_ws_bytes(nm, p, true)) + tp_carve(t, ntp, nullptr);
+  }
+  return massive_ws_bytes(nm, p, false);
+}
+
 }  // namespace
 
 struct genga_ctx {
@@ -42,6 +61,7 @@ struct genga_ctx {
   genga_params p{};
   StepConsts c{};
   MassiveWs w{};
+  TpWs t{};
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
   hipGraphExec_t g_many = nullptr;
@@ -58,7 +78,10 @@ static int capture(genga_ctx* ctx, int nsteps, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int k = 0; k < nsteps && e == hipSuccess; ++k) e = massive_step(ctx->w, ctx->c, ctx->cap);
+  for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
+    e = massive_step(ctx->w, ctx->c, ctx->cap);
+    if (e == hipSuccess && ctx->mode == GENGA_TEST) e = tp_step(ctx->w, ctx->t, ctx->c, ctx->cap);
+  }
   hipError_t e2 = hipStreamEndCapture(ctx->cap, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
@@ -78,17 +101,19 @@ static int read_status(genga_ctx* ctx, DevStat* hs) {
 static int load_state(genga_ctx* ctx, const double* d_m, const double* d_x, const double* d_v,
                       int coords_in) {
   const int n = ctx->w.n;
+  const int64_t rows = n + (ctx->mode == GENGA_TEST ? ctx->t.ntp : 0);
   HIPCHK(hipMemsetAsync(ctx->w.flag_in, 0, sizeof(int), ctx->stream));
   if (d_m) HIPCHK(validate_finite(d_m, n, ctx->w.flag_in, ctx->stream));
-  HIPCHK(validate_finite(d_x, 3 * (int64_t)n, ctx->w.flag_in, ctx->stream));
-  HIPCHK(validate_finite(d_v, 3 * (int64_t)n, ctx->w.flag_in, ctx->stream));
+  HIPCHK(validate_finite(d_x, 3 * rows, ctx->w.flag_in, ctx->stream));
+  HIPCHK(validate_finite(d_v, 3 * rows, ctx->w.flag_in, ctx->stream));
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, ctx->w.flag_in, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (bad) return GENGA_EINVAL;
-  const double* m = d_m;
-  HIPCHK(massive_pack(ctx->w, ctx->c, m, d_x, d_v, coords_in, ctx->stream));
+  HIPCHK(massive_pack(ctx->w, ctx->c, d_m, d_x, d_v, coords_in, ctx->stream));
+  if (ctx->mode == GENGA_TEST) HIPCHK(tp_pack(ctx->w, ctx->t, ctx->c, d_x, d_v, coords_in, ctx->stream));
   HIPCHK(massive_prime(ctx->w, ctx->c, ctx->stream));
+  if (ctx->mode == GENGA_TEST) HIPCHK(tp_prime(ctx->w, ctx->t, ctx->c, ctx->stream));
   return GENGA_OK;
 }
 
@@ -116,35 +141,35 @@ size_t genga_workspace_bytes(int mode, const genga_params* p, int n_massive, int
   (void)n_test;
   (void)n_sys;
   (void)n_bodies;
-  if (!params_ok(p) || mode != GENGA_MASSIVE) return 0;
-  if (n_massive < 1 || n_massive > max_bodies(p)) return 0;
-  return massive_ws_bytes(n_massive, *p);
+  if (!params_ok(p) || !shape_ok(mode, p, n_massive, n_test)) return 0;
+  return ws_bytes(mode, *p, n_massive, n_test);
 }
 
 int genga_init(genga_ctx** out, int mode, const genga_params* p, int n_massive, int64_t n_test,
                int n_sys, const int32_t* d_offsets, const double* d_m0, const double* d_m,
                const double* d_x, const double* d_v, int coords_in, void* d_workspace,
-               size_t ws_bytes, void* stream) {
+               size_t ws_bytes_in, void* stream) {
   (void)n_test;
   (void)n_sys;
   (void)d_offsets;
   (void)d_m0;
   if (!out) return GENGA_EINVAL;
   *out = nullptr;
-  if (mode != GENGA_MASSIVE || !params_ok(p)) return GENGA_EINVAL;
-  if (n_massive < 1 || n_massive > max_bodies(p)) return GENGA_EINVAL;
+  if (!params_ok(p) || !shape_ok(mode, p, n_massive, n_test)) return GENGA_EINVAL;
   if (!d_m || !d_x || !d_v || !d_workspace) return GENGA_EINVAL;
   if (coords_in != GENGA_HELIO && coords_in != GENGA_DEMOCRATIC) return GENGA_EINVAL;
   if (((uintptr_t)d_workspace & 255u) != 0) return GENGA_EINVAL;
-  const size_t need = massive_ws_bytes(n_massive, *p);
-  if (ws_bytes < need) return GENGA_ENOMEM;
+  const size_t need = ws_bytes(mode, *p, n_massive, n_test);
+  if (ws_bytes_in < need) return GENGA_ENOMEM;
   genga_ctx* ctx = new (std::nothrow) genga_ctx();
   if (!ctx) return GENGA_ENOMEM;
   ctx->mode = mode;
   ctx->p = *p;
   ctx->c = make_consts(*p);
   ctx->stream = (hipStream_t)stream;
-  massive_carve(ctx->w, n_massive, *p, d_workspace);
+  const bool tp = mode == GENGA_TEST;
+  const size_t moff = align256(massive_carve(ctx->w, n_massive, *p, d_workspace, tp));
+  if (tp) tp_carve(ctx->t, n_test, (char*)d_workspace + moff);
   int rc = GENGA_OK;
   if (hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) rc = GENGA_EHIP;
   if (rc == GENGA_OK && hipMemsetAsync(ctx->w.st, 0, sizeof(DevStat), ctx->stream) != hipSuccess)
@@ -189,6 +214,7 @@ int genga_step_profiled(genga_ctx* ctx, int64_t nsteps, double* h_kick_us) {
   for (int64_t k = 0; k < nsteps && rc == GENGA_OK; ++k) {
     float ms = 0.0f;
     if (massive_step(ctx->w, ctx->c, ctx->stream, e0, e1) != hipSuccess ||
+        (ctx->mode == GENGA_TEST && tp_step(ctx->w, ctx->t, ctx->c, ctx->stream) != hipSuccess) ||
         hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
       rc = GENGA_EHIP;
     tot += ms;
@@ -213,6 +239,7 @@ int genga_get_state(genga_ctx* ctx, double* d_x, double* d_v, int coords_out) {
   if (!ctx || !d_x || !d_v) return GENGA_EINVAL;
   if (coords_out != GENGA_HELIO && coords_out != GENGA_DEMOCRATIC) return GENGA_EINVAL;
   HIPCHK(massive_unpack(ctx->w, ctx->c, d_x, d_v, coords_out, ctx->stream));
+  if (ctx->mode == GENGA_TEST) HIPCHK(tp_unpack(ctx->w, ctx->t, ctx->c, d_x, d_v, coords_out, ctx->stream));
   return genga_sync(ctx);
 }
 

@@ -31,6 +31,7 @@ struct DevStat {
   int ncand;           // candidate pairs (i<j) entering the last step
   int kep_itmax;       // largest Kepler iteration count seen
   int tp_enc;          // test-particle encounters of the last step
+  unsigned tp_nbs;     // particles listed for BS in the current step
   unsigned long long bs_sub;     // accepted BS substeps (cumulative)
   unsigned long long enc_total;  // encounters (cumulative)
   unsigned long long fullkicks;  // opening kicks recomputed in full
@@ -72,7 +73,22 @@ struct MassiveWs {
   int* goff;            // group offsets [np+1]
   int* gmem;            // group members [np]
   int* flag_in;         // input validation flag
+  double4* xstart;      // positions at the start of the step (test-particle mode)
+  double4* xpost;       // state after the drift, before BS (test-particle mode)
+  double4* vpost;
   DevStat* st;
+};
+
+// Test-particle state and the per-step list of particles needing BS.
+struct TpWs {
+  int64_t ntp;
+  double* x;            // [3][ntp]
+  double* v;            // [3][ntp]
+  unsigned* mask;       // candidate planets per particle
+  int* bs_idx;          // listed particles
+  unsigned* bs_mask;    // their encounter planets
+  double* bs_rct;       // their critical radii
+  double* bs_y;         // their pre-drift state [6][ntp]
 };
 
 struct StepConsts {
@@ -83,8 +99,9 @@ struct StepConsts {
 StepConsts make_consts(const genga_params& p);
 
 // ---- main-mode launchers (massive.hip) --------------------------------------
-size_t massive_ws_bytes(int n, const genga_params& p);
-size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base);
+size_t massive_ws_bytes(int n, const genga_params& p, bool snap = false);
+size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base,
+                     bool snap = false);
 hipError_t validate_finite(const double* a, int64_t cnt, int* dbad,
                            hipStream_t s);
 hipError_t massive_pack(const MassiveWs& w, const StepConsts& c,
@@ -104,6 +121,17 @@ hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, double* acc,
 hipError_t thresholds_from_radii(const MassiveWs& w, const StepConsts& c,
                                  hipStream_t s);
 hipError_t massive_masses(const MassiveWs& w, double* m, hipStream_t s);
+
+// ---- test-particle mode (tp.hip) --------------------------------------------
+size_t tp_carve(TpWs& t, int64_t ntp, void* base);
+hipError_t tp_pack(const MassiveWs& w, const TpWs& t, const StepConsts& c,
+                   const double* x, const double* v, int coords_in, hipStream_t s);
+hipError_t tp_unpack(const MassiveWs& w, const TpWs& t, const StepConsts& c,
+                     double* x, double* v, int coords_out, hipStream_t s);
+hipError_t tp_prime(const MassiveWs& w, const TpWs& t, const StepConsts& c,
+                    hipStream_t s);
+hipError_t tp_step(const MassiveWs& w, const TpWs& t, const StepConsts& c,
+                   hipStream_t s);
 
 // ---- single-operation kernels for component checks (ops.hip) ---------------
 hipError_t op_kepler(double mu, int64_t n, const double* x0, const double* v0,

@@ -273,3 +273,35 @@ def hermite(dt, q, device="cuda", stream=None):
     _check(lib().genga_hermite(q.shape[0], float(dt), _ptr(q), _ptr(out), _stream(stream)),
            "genga_hermite")
     return out
+
+
+class TestParticleSimulation(Simulation):
+    """Test-particle mode: up to 32 massive bodies plus massless particles
+    (row order: massive bodies first, then particles)."""
+
+    def __init__(self, m, x, v, xt, vt, params: Params | None = None, coords: str = "helio",
+                 device="cuda", stream=None):
+        self.p = params if params is not None else default_params()
+        self.device = torch.device(device)
+        self.stream = stream
+        m = _dev(m, self.device)
+        self.nm = int(m.numel())
+        xa = torch.cat([_dev(x, self.device).reshape(-1, 3), _dev(xt, self.device).reshape(-1, 3)])
+        va = torch.cat([_dev(v, self.device).reshape(-1, 3), _dev(vt, self.device).reshape(-1, 3)])
+        self.ntp = xa.shape[0] - self.nm
+        self.n = xa.shape[0]
+        nbytes = lib().genga_workspace_bytes(GENGA_TEST, ctypes.byref(self.p), self.nm, self.ntp, 0, 0)
+        if nbytes == 0:
+            raise GengaError(EINVAL, "genga_workspace_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._ctx = ctypes.c_void_p()
+        code = lib().genga_init(ctypes.byref(self._ctx), GENGA_TEST, ctypes.byref(self.p), self.nm,
+                                self.ntp, 0, None, None, _ptr(m), _ptr(xa.contiguous()),
+                                _ptr(va.contiguous()),
+                                GENGA_HELIO if coords == "helio" else GENGA_DEMOCRATIC,
+                                _ptr(self.ws), nbytes, _stream(stream))
+        _check(code, "genga_init")
+
+    def split_state(self, coords: str = "dem"):
+        x, v = self.state(coords)
+        return x[:self.nm], v[:self.nm], x[self.nm:], v[self.nm:]
