@@ -75,6 +75,37 @@ def cpu_baseline(s, gp, budget_s: float = 15.0):
                       f"and Hermite-tests every pair)"}
 
 
+TP_BYTES = 104  # per particle-step: x, v read and written (96 B) + the 32-bit mask both ways
+
+
+def tp_measure(G, W, torch, steps: int, ntp: int = 1_000_000):
+    """Test-particle mode: 8 planets and 10^6 particles (Sec. 3.3), with
+    physical radii (bulk density 2 g/cm^3, particles 10 km): particles that
+    hit a planet are removed."""
+    planets, xt, ut = W.test_particles(ntp=ntp)
+    sim = G.TestParticleSimulation(planets.m, planets.x, planets.u, xt, ut, G.default_params(),
+                                   coords="helio", radii=W.tp_radii(planets.m, ntp))
+    sim.step(4)
+    sim.check()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sim.check()
+    sec = e0.elapsed_time(e1) / 1e3
+    st = sim.stats()
+    sim.close()
+    return {"workload": f"tp_8p_{ntp}", "steps": steps, "ms_per_step": sec * 1e3 / steps,
+            "tp_steps_per_s": ntp * steps / sec,
+            "algorithmic_GBps": TP_BYTES * ntp * steps / sec / 1e9,
+            "hbm_frac": TP_BYTES * ntp * steps / sec / 1e9 / HBM_PEAK_GBS,
+            "tp_enc_last_step": st["tp_enc"], "bs_substeps": st["bs_substeps"],
+            "removed": st["tp_removed"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +116,8 @@ def main():
     ap.add_argument("--big-n", type=int, default=16384,
                     help="bodies of the encounter-free kick capability run (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tp-steps", type=int, default=100,
+                    help="steps of the 10^6-particle run reported under extra (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed region run one 256 MiB device copy (counter scale)")
     args = ap.parse_args()
@@ -139,6 +172,10 @@ def main():
                "tflops": FLOPS_PER_PAIR * nb * (nb - 1) / (big_us * 1e-6) / 1e12}
         simb.close()
 
+    extra = {}
+    if args.tp_steps > 0:
+        extra["test_particles"] = tp_measure(G, W, torch, args.tp_steps)
+
     if args.calib_copy:
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
@@ -177,6 +214,8 @@ def main():
                                       "kepler_iter_max", "bs_substeps", "enc_total",
                                       "full_kicks")},
     }
+    if extra:
+        out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, gp)
     print(json.dumps(out), flush=True)

@@ -68,6 +68,7 @@ typedef struct genga_stats_s {
     int64_t enc_total;      /* encounters since init                        */
     int64_t full_kicks;     /* opening kicks that could not reuse the cache */
     int64_t tp_enc_total;
+    int64_t tp_removed;     /* test particles removed by collisions         */
     uint32_t flags;         /* latched device error bits                    */
     uint32_t reserved;
 } genga_stats_t;
@@ -94,27 +95,32 @@ void genga_params_default(genga_params *p);
 
 /* Device workspace (bytes) a context of this shape needs.  Main mode:
  * n_massive <= 2048 bodies with encounters (the paper's main-mode limit,
- * Sec. 3), <= 65536 with encounter_free.  Returns 0 for an unsupported
- * shape or invalid parameters. */
+ * Sec. 3), <= 65536 with encounter_free, n_test = 0.  Test-particle mode:
+ * 1 <= n_massive <= 32 (Sec. 3.3), 0 <= n_test <= 2^30.  Returns 0 for an
+ * unsupported shape or invalid parameters. */
 size_t genga_workspace_bytes(int mode, const genga_params *p, int n_massive,
                              int64_t n_test, int n_sys, int64_t n_bodies);
 
 /* Create a context and load the initial state (Sec. 2.2: the first opening
  * kick is prepared here, from the initial positions).
- *   mode        GENGA_MASSIVE (main mode).
+ *   mode        GENGA_MASSIVE (main mode) or GENGA_TEST (test-particle mode,
+ *               Sec. 3.3: n_massive bodies take the main-mode step and n_test
+ *               massless particles feel them, but nothing else).
  *   d_m         n_massive masses (device, read once).
- *   d_x, d_v    n_massive x 3 positions and velocities (device, read once).
- *               coords_in = GENGA_HELIO: heliocentric positions and
- *               velocities, converted to democratic coordinates (heliocentric
- *               positions, barycentric velocities, Sec. 2.1);
- *               GENGA_DEMOCRATIC: already democratic.
+ *   d_x, d_v    (n_massive + n_test) x 3 positions and velocities (device,
+ *               read once): the massive bodies' rows first, then the
+ *               particles'.  coords_in = GENGA_HELIO: heliocentric positions
+ *               and velocities, converted to democratic coordinates
+ *               (heliocentric positions, barycentric velocities, Sec. 2.1,
+ *               with the massive bodies' momentum); GENGA_DEMOCRATIC:
+ *               already democratic.  A particle row of six NaN is a removed
+ *               particle.
  *   d_workspace at least genga_workspace_bytes bytes of device memory, 256-B
  *               aligned, owned by the caller, used until genga_destroy.
  *   stream      hipStream_t of the caller (NULL = default stream).
  * Synchronises once (validation of the input).  Errors: EINVAL (shape, NaN
  * or Inf in the input, non-positive m0), ENOMEM (workspace too small), EHIP.
- * n_test, n_sys, d_offsets, d_m0 are reserved for the other modes; pass 0 /
- * NULL in main mode. */
+ * n_sys, d_offsets, d_m0 are reserved for the batched mode; pass 0 / NULL. */
 int genga_init(genga_ctx **ctx, int mode, const genga_params *p,
                int n_massive, int64_t n_test, int n_sys,
                const int32_t *d_offsets, const double *d_m0,
@@ -131,10 +137,10 @@ int genga_init(genga_ctx **ctx, int mode, const genga_params *p,
 int genga_step(genga_ctx *ctx, int64_t nsteps);
 
 /* Measurement form of genga_step: the same nsteps steps launched one kernel
- * at a time (no graph), with HIP events recorded on the context's stream
- * around each closing-kick pair kernel; *h_kick_us receives that kernel's
- * average duration in microseconds.  Synchronising; returns the latched
- * status. */
+ * at a time (no graph) on the context's stream, the closing-kick pair kernel
+ * through hipExtLaunchKernel with two HIP events that take its dispatch's
+ * start and end timestamps; *h_kick_us receives that kernel's average
+ * duration in microseconds.  Synchronising; returns the latched status. */
 int genga_step_profiled(genga_ctx *ctx, int64_t nsteps, double *h_kick_us);
 
 /* Wait for the context's stream and return the latched device status as a
@@ -175,6 +181,29 @@ int genga_encounters(genga_ctx *ctx, int32_t *h_ij, double *h_dmin2,
  * r_ij < pf r_crit,ij at the end of the last closing kick, sorted, as in
  * genga_encounters.  Synchronising. */
 int genga_candidates(genga_ctx *ctx, int32_t *h_ij, int cap, int *h_n);
+
+/* Test-particle mode: physical radii (Sec. 3.2.7, Sec. 3.3), device array of
+ * n_massive + n_test values (planets first), copied.  From the next step on,
+ * a particle whose separation from a planet, Hermite-interpolated over a
+ * Bulirsch-Stoer substep of its encounter (Eqs. 10-12 over that substep),
+ * falls below the sum of their radii is removed: its x and v become NaN,
+ * later steps skip it, and a report is kept (genga_collisions).  Radii start
+ * at 0 (no collisions).  A particle only meets this test inside an encounter,
+ * so radii should stay below the critical radii.  Synchronising.  Errors:
+ * EINVAL (other mode, negative or non-finite radius; the radii are then
+ * reset to 0), EHIP. */
+int genga_set_radii(genga_ctx *ctx, const double *d_radii);
+
+/* Reports of the particles removed since init, sorted by (step, particle):
+ * particle index among the particles (h_tp), massive-body index (h_planet),
+ * step index since init (h_step), part of that step covered before the BS
+ * substep of the collision (h_frac, a multiple of 2^-bs_max_depth), and the
+ * particle's democratic state at the start of that substep (h_xv, 6 per
+ * report: x then v).  Host arrays of cap entries; *h_n receives the count;
+ * GENGA_EOVERFLOW when it exceeds cap (cap reports written).  Synchronising. */
+int genga_collisions(genga_ctx *ctx, int64_t *h_tp, int32_t *h_planet,
+                     int64_t *h_step, double *h_frac, double *h_xv,
+                     int64_t cap, int64_t *h_n);
 
 /* Counters of the run (h_stats host).  Synchronising. */
 int genga_stats(genga_ctx *ctx, genga_stats_t *h_stats);

@@ -53,7 +53,7 @@ class Stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "steps", "n_cand", "n_enc", "n_miss", "n_groups", "max_group",
         "bs_substeps", "enc_total", "miss_total", "kepler_iter_max",
-        "tp_enc", "tp_enc_total")]
+        "tp_enc", "tp_enc_total", "tp_removed")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -69,6 +69,7 @@ def params(G=1.0, m0=1.0, dt=0.01 * 2 * np.pi, n1=3.0, n2=0.4, pf=3.0,
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
 _I32 = ctypes.POINTER(ctypes.c_int32)
+_I64 = ctypes.POINTER(ctypes.c_int64)
 _U8 = ctypes.POINTER(ctypes.c_uint8)
 _P = ctypes.POINTER(Params)
 
@@ -101,7 +102,8 @@ def lib():
                                       ctypes.POINTER(ctypes.c_int)]),
             "go_tp_init": (i32, [_P, i32, _D, _D, _D, _D, _U8, i64, _D, _D, _U8]),
             "go_tp_step": (i32, [_P, i32, _D, _D, _D, _D, _U8, i64, _D, _D, _U8,
-                                 i64, ctypes.POINTER(Stats)]),
+                                 i64, ctypes.POINTER(Stats), _D, i64, _I32, _I64, _D,
+                                 _D]),
             "go_free_step": (i32, [_P, i32, _D, _D, _D, i64]),
             "go_free_tlm": (i32, [_P, i32, _D, _D, _D, _D, _D, _D, i64, _D, _D,
                                   _D, _D]),
@@ -286,9 +288,12 @@ class MassiveSim:
 
 # --------------------------------------------------- test-particle mode ---
 class TPSim:
-    """Main-mode massive bodies plus massless test particles."""
+    """Main-mode massive bodies plus massless test particles.  radii (optional,
+    nm + ntp values, planets first) enables collisions: a removed particle's
+    x and v become NaN and coll_planet / coll_step / coll_frac / coll_xv hold
+    its report (coll_planet = -1 while it is present)."""
 
-    def __init__(self, p: Params, m, x, v, xt, vt, coords="dem"):
+    def __init__(self, p: Params, m, x, v, xt, vt, coords="dem", radii=None):
         self.p = p
         self.m = _f64(m).copy()
         self.x = _f64(x, (-1, 3)).copy()
@@ -303,6 +308,14 @@ class TPSim:
         self.xt = _f64(xt, (-1, 3)).copy()
         self.vt = vt
         nm, ntp = len(self.m), len(self.xt)
+        self.rad = None if radii is None else _f64(radii).copy()
+        if self.rad is not None and self.rad.shape != (nm + ntp,):
+            raise ValueError("radii: nm + ntp values")
+        self.coll_planet = np.full(ntp, -1, dtype=np.int32)
+        self.coll_step = np.zeros(ntp, dtype=np.int64)
+        self.coll_frac = np.zeros(ntp)
+        self.coll_xv = np.zeros((ntp, 6))
+        self.nstep = 0
         self.rc = np.zeros(nm)
         self.cand = np.zeros((nm, nm), dtype=np.uint8)
         self.cand_tp = np.zeros((ntp, nm), dtype=np.uint8)
@@ -314,14 +327,23 @@ class TPSim:
 
     def step(self, nsteps=1):
         st = Stats()
+        rad = None if self.rad is None else _d(self.rad)
         code = lib().go_tp_step(ctypes.byref(self.p), len(self.m), _d(self.m), _d(self.x),
                                 _d(self.v), _d(self.rc), self.cand.ctypes.data_as(_U8),
                                 len(self.xt), _d(self.xt), _d(self.vt),
                                 self.cand_tp.ctypes.data_as(_U8), int(nsteps),
-                                ctypes.byref(st))
+                                ctypes.byref(st), rad, self.nstep,
+                                self.coll_planet.ctypes.data_as(_I32),
+                                self.coll_step.ctypes.data_as(_I64), _d(self.coll_frac),
+                                _d(self.coll_xv))
         self.stats = st
+        self.nstep += int(st.steps)
         _check(code, "tp_step")
         return st.as_dict()
+
+    def removed(self):
+        """Indices of the removed particles, ascending."""
+        return np.nonzero(self.coll_planet >= 0)[0]
 
 
 # ------------------------------------------------------------- batched ---

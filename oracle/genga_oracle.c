@@ -384,8 +384,14 @@ int go_groups(int n, int npairs, const int32_t *ij, int32_t *label) {
  * unpinned against the paper; pinned by Kepler agreement and the group's
  * conserved H_A).
  * tp_mode: body 0 is a massless test particle; only it feels the pair
- * terms, the other members (planets) feel only the star (Sec. 3.3).        */
+ * terms, the other members (planets) feel only the star (Sec. 3.3).
+ * rad (tp_mode only, may be NULL): physical radii of the members.  After each
+ * accepted substep the particle's separation from every planet member is
+ * tested over the substep with the Hermite rule of Eqs. (10)-(12) applied to
+ * that substep; below the sum of the radii the integration stops at the
+ * start of the substep (a collision, Sec. 3.2.7 and Sec. 3.3).              */
 #define BS_KMAX 8
+#define BS_COLLIDED 1
 
 typedef struct {
     const go_params *p;
@@ -393,6 +399,7 @@ typedef struct {
     const double *m;
     const double *rc;
     int tp_mode;
+    const double *rad;
 } ha_sys;
 
 static void ha_deriv(const ha_sys *s, const double *y, double *dy) {
@@ -494,7 +501,28 @@ static int bs_attempt(const ha_sys *s, const double *y0, double H, double *yout,
     return 0;
 }
 
-static int bs_integrate(const ha_sys *s, double *y, double H, int64_t *substeps) {
+/* Lowest planet member the particle (member 0) comes closer to than the sum
+ * of their radii during the substep y0 -> y1 of length h, or 0 for none.  */
+static int tp_collision(const ha_sys *s, const double *y0, const double *y1, double h) {
+    for (int j = 1; j < s->ng; ++j) {
+        double dx0[3], dv0[3], dx1[3], dv1[3];
+        for (int k = 0; k < 3; ++k) {
+            dx0[k] = y0[6 * j + k] - y0[k];
+            dv0[k] = y0[6 * j + 3 + k] - y0[3 + k];
+            dx1[k] = y1[6 * j + k] - y1[k];
+            dv1[k] = y1[6 * j + 3 + k] - y1[3 + k];
+        }
+        double R = s->rad[0] + s->rad[j];
+        if (go_hermite_dmin2(h, dx0, dv0, dx1, dv1) < R * R) return j;
+    }
+    return 0;
+}
+
+/* Returns GO_OK, GO_EBS, GO_EINVAL, or BS_COLLIDED with *coll_member (the
+ * planet member) and *coll_frac (the fraction of H covered before the
+ * substep in which the collision happens; y is the state there).           */
+static int bs_integrate(const ha_sys *s, double *y, double H, int64_t *substeps,
+                        int *coll_member, double *coll_frac) {
     int dim = 6 * s->ng;
     int D = s->p->bs_max_depth;
     if (D < 0 || D > 40) return GO_EINVAL;
@@ -512,6 +540,15 @@ static int bs_integrate(const ha_sys *s, double *y, double H, int64_t *substeps)
     while (pos < total) {
         double h = ldexp(H, -d);
         if (bs_attempt(s, y, h, ynew, T, w)) {
+            if (s->tp_mode && s->rad) {
+                int j = tp_collision(s, y, ynew, h);
+                if (j > 0) {
+                    *coll_member = j;
+                    *coll_frac = ldexp((double)pos, -D);
+                    rcode = BS_COLLIDED;
+                    break;
+                }
+            }
             memcpy(y, ynew, sizeof(double) * dim);
             if (substeps) ++*substeps;
             pos += (int64_t)1 << (D - d);
@@ -538,8 +575,10 @@ int go_bs_group(const go_params *p, int ng, const double *m, const double *rc,
             y[6 * i + k] = x[3 * i + k];
             y[6 * i + 3 + k] = v[3 * i + k];
         }
-    ha_sys s = {p, ng, m, rc, 0};
-    int rcode = bs_integrate(&s, y, H, substeps);
+    ha_sys s = {p, ng, m, rc, 0, NULL};
+    int cm = 0;
+    double cf = 0.0;
+    int rcode = bs_integrate(&s, y, H, substeps, &cm, &cf);
     for (int i = 0; i < ng; ++i)
         for (int k = 0; k < 3; ++k) {
             x[3 * i + k] = y[6 * i + k];
@@ -895,8 +934,11 @@ int go_tp_init(const go_params *p, int nm, const double *m, const double *x,
 
 int go_tp_step(const go_params *p, int nm, const double *m, double *x,
                double *v, double *rc, uint8_t *cand, int64_t ntp, double *xt,
-               double *vt, uint8_t *cand_tp, int64_t nsteps, go_stats *st) {
+               double *vt, uint8_t *cand_tp, int64_t nsteps, go_stats *st,
+               const double *rad, int64_t step0, int32_t *coll_planet,
+               int64_t *coll_step, double *coll_frac, double *coll_xv) {
     if (nm < 1 || nm > 64 || ntp < 0 || nsteps < 0) return GO_EINVAL;
+    if (rad && (!coll_planet || !coll_step || !coll_frac || !coll_xv)) return GO_EINVAL;
     go_stats local;
     if (!st) st = &local;
     memset(st, 0, sizeof(*st));
@@ -1009,13 +1051,14 @@ int go_tp_step(const go_params *p, int nm, const double *m, double *x,
         if (!p->encounter_free) precheck(p, nm, x, rc, cand);
 
         /* the test particles, each on its own (they do not interact) */
-        int64_t tpenc = 0, bssub = 0;
+        int64_t tpenc = 0, bssub = 0, nrem = 0;
         int bad = 0;
         int64_t itmx = 0;
-#pragma omp parallel for schedule(dynamic, 256) reduction(+ : tpenc, bssub) \
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : tpenc, bssub, nrem) \
     reduction(| : bad) reduction(max : itmx)
         for (int64_t k = 0; k < ntp; ++k) {
             double *xk = V3(xt, k), *vk = V3(vt, k);
+            if (isnan(xk[0])) continue; /* removed earlier */
             double rct = tp_rcrit(p, vk);
             double a[3];
             tp_accel(p, nm, m, x0, rc, xk, rct, a);
@@ -1051,8 +1094,10 @@ int go_tp_step(const go_params *p, int nm, const double *m, double *x,
                         ym[q] = xkm[q];
                         ym[3 + q] = vkm[q];
                     }
+                    double radg[65];
                     mg[0] = 0.0;
                     rg[0] = rct;
+                    radg[0] = rad ? rad[nm + k] : 0.0;
                     for (int t = 0; t < ns; ++t) {
                         int j = sel[t];
                         for (int q = 0; q < 3; ++q) {
@@ -1061,11 +1106,26 @@ int go_tp_step(const go_params *p, int nm, const double *m, double *x,
                         }
                         mg[t + 1] = m[j];
                         rg[t + 1] = rc[j];
+                        radg[t + 1] = rad ? rad[j] : 0.0;
                     }
-                    ha_sys hs = {p, ngp, mg, rg, 1};
+                    ha_sys hs = {p, ngp, mg, rg, 1, rad ? radg : NULL};
                     int64_t sub = 0;
-                    if (bs_integrate(&hs, ym, p->dt, &sub) != GO_OK) bad = 2;
+                    int cm = 0;
+                    double cf = 0.0;
+                    int rb = bs_integrate(&hs, ym, p->dt, &sub, &cm, &cf);
                     bssub += sub;
+                    if (rb == BS_COLLIDED) {
+                        /* removed: report the state before the colliding substep */
+                        coll_planet[k] = sel[cm - 1];
+                        coll_step[k] = step0 + s;
+                        coll_frac[k] = cf;
+                        for (int q = 0; q < 6; ++q) coll_xv[6 * k + q] = ym[q];
+                        for (int q = 0; q < 3; ++q) xk[q] = vk[q] = NAN;
+                        memset(&cand_tp[(size_t)k * nm], 0, (size_t)nm);
+                        ++nrem;
+                        continue;
+                    }
+                    if (rb != GO_OK) bad = 2;
                     for (int q = 0; q < 3; ++q) {
                         xk[q] = ym[q];
                         vk[q] = ym[3 + q];
@@ -1080,6 +1140,7 @@ int go_tp_step(const go_params *p, int nm, const double *m, double *x,
         }
         st->tp_enc = tpenc;
         st->tp_enc_total += tpenc;
+        st->tp_removed += nrem;
         st->bs_substeps += bssub;
         if (itmx > st->kepler_iter_max) st->kepler_iter_max = itmx;
         if (bad) {

@@ -49,6 +49,7 @@ typedef struct {
     int64_t kepler_iter_max;/* largest Kepler iteration count of the call */
     int64_t tp_enc;         /* test-particle encounters of the last step   */
     int64_t tp_enc_total;
+    int64_t tp_removed;     /* test particles removed by collisions (call) */
 } go_stats;
 
 enum {
@@ -94,9 +95,20 @@ int go_massive_step(const go_params *p, int n, const double *m, double *x,
 int go_tp_init(const go_params *p, int nm, const double *m, const double *x,
                const double *v, double *rc, uint8_t *cand, int64_t ntp,
                const double *xt, const double *vt, uint8_t *cand_tp);
+/* rad: NULL (no collisions) or nm + ntp physical radii, planets first.
+ * step0: steps taken before this call (for the collision reports).
+ * A particle closer to a planet than the sum of their radii at any time of a
+ * BS substep (Hermite interpolation over the substep, the encounter rule of
+ * Sec. 2.2) is removed (Sec. 3.3): its report gets the planet index, the step
+ * index, the fraction of the step at the start of that substep and the
+ * particle's state there (democratic coordinates, x then v); xt and vt of a
+ * removed particle become NaN and later steps skip it.  coll_planet holds -1
+ * for particles still present.  The report arrays may be NULL when rad is. */
 int go_tp_step(const go_params *p, int nm, const double *m, double *x,
                double *v, double *rc, uint8_t *cand, int64_t ntp, double *xt,
-               double *vt, uint8_t *cand_tp, int64_t nsteps, go_stats *st);
+               double *vt, uint8_t *cand_tp, int64_t nsteps, go_stats *st,
+               const double *rad, int64_t step0, int32_t *coll_planet,
+               int64_t *coll_step, double *coll_frac, double *coll_xv);
 
 /* ---- encounter-free map, tangent-linear model and adjoint ---------------- */
 int go_free_step(const go_params *p, int n, const double *m, double *x,

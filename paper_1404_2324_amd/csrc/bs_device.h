@@ -307,12 +307,23 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
 // Binary refinement over [0, H] with speculative depths: a round at depth d
 // also tries d+1..d+S-1 on the first halves, which is where the sequential
 // scheme goes after failures.
+// Test-particle groups (TP) with R2 >= 0 in some lane: after each accepted
+// substep, lane b (a planet member) tests its separation from member 0 over
+// the substep with the Hermite rule; below sqrt(R2) (the sum of the radii)
+// the integration stops at the start of that substep and returns 1, with the
+// lowest such member in *cb and the covered part of [0, H] in *cpos (units of
+// H / 2^D).  Returns 0 when H is covered, -1 when the depth is exhausted.
 template <int P, bool TP>
 __device__ __forceinline__ int bs_integrate_par(int sz, double y[6], double H,
                                                 const ParBody<P>& Q, double G,
                                                 double Gm0, double tol, int D,
-                                                long long* nsub) {
+                                                long long* nsub, double R2 = -1.0,
+                                                int* cb = nullptr,
+                                                long long* cpos = nullptr) {
   constexpr int S = kBsPar / P;
+  const int lane = threadIdx.x & 63;
+  const int b = lane % P;
+  const bool coll = TP && __ballot(R2 >= 0.0) != 0ull;
   long long pos = 0;
   const long long total = 1ll << D;
   int d = 0;
@@ -327,6 +338,24 @@ __device__ __forceinline__ int bs_integrate_par(int sz, double y[6], double H,
     if (sa >= smax) sa = -1;
     if (sa >= 0) {
       d += sa;
+      if (coll) {
+        const int l0 = lane - b;
+        double o[6], e[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          o[q] = y[q] - __shfl(y[q], l0, 64);
+          e[q] = yt[q] - __shfl(yt[q], l0, 64);
+        }
+        const double d2 = hermite_dmin2(ldexp(H, -d), o[0], o[1], o[2], o[3], o[4], o[5],
+                                        e[0], e[1], e[2], e[3], e[4], e[5]);
+        const bool hit = b >= 1 && b < sz && R2 >= 0.0 && d2 < R2;
+        const unsigned long long hm = __ballot(hit) & ((1ull << P) - 1ull);
+        if (hm != 0ull) {
+          *cb = __ffsll((long long)hm) - 1;
+          *cpos = pos;
+          return 1;
+        }
+      }
 #pragma unroll
       for (int q = 0; q < 6; ++q) y[q] = yt[q];
       ++*nsub;
@@ -348,7 +377,8 @@ template <int P, bool TP>
 __device__ __forceinline__ int bs_group(int sz, double y[6], const double* mm,
                                         const double* mrc, double H, double G,
                                         double Gm0, double tol, int D,
-                                        long long* nsub) {
+                                        long long* nsub, double R2 = -1.0,
+                                        int* cb = nullptr, long long* cpos = nullptr) {
   const int lane = threadIdx.x & 63;
   const int b = lane % P;
   const double rcb = b < sz ? mrc[b] : 0.0;
@@ -368,7 +398,7 @@ __device__ __forceinline__ int bs_group(int sz, double y[6], const double* mm,
       Q.i09[q] = Q.rcij[q] > 0.0 ? 1.0 / (0.9 * Q.rcij[q]) : 0.0;
     }
   }
-  return bs_integrate_par<P, TP>(sz, y, H, Q, G, Gm0, tol, D, nsub);
+  return bs_integrate_par<P, TP>(sz, y, H, Q, G, Gm0, tol, D, nsub, R2, cb, cpos);
 }
 
 }  // namespace genga

@@ -35,7 +35,6 @@ bool params_ok(const genga_params* p) {
 
 int max_bodies(const genga_params* p) { return p->encounter_free ? 65536 : kGroupMaxN; }
 
-constexpr int kTpMaxPlanets = 32;          // one bit per planet in a particle's mask
 constexpr int64_t kTpMaxParticles = 1ll << 30;
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -104,8 +103,11 @@ static int load_state(genga_ctx* ctx, const double* d_m, const double* d_x, cons
   const int64_t rows = n + (ctx->mode == GENGA_TEST ? ctx->t.ntp : 0);
   HIPCHK(hipMemsetAsync(ctx->w.flag_in, 0, sizeof(int), ctx->stream));
   if (d_m) HIPCHK(validate_finite(d_m, n, ctx->w.flag_in, ctx->stream));
-  HIPCHK(validate_finite(d_x, 3 * rows, ctx->w.flag_in, ctx->stream));
-  HIPCHK(validate_finite(d_v, 3 * rows, ctx->w.flag_in, ctx->stream));
+  // massive rows finite; test-particle rows finite or all NaN (removed)
+  HIPCHK(validate_finite(d_x, 3 * (int64_t)n, ctx->w.flag_in, ctx->stream));
+  HIPCHK(validate_finite(d_v, 3 * (int64_t)n, ctx->w.flag_in, ctx->stream));
+  if (ctx->mode == GENGA_TEST)
+    HIPCHK(tp_validate(ctx->t, n, d_x, d_v, ctx->w.flag_in, ctx->stream));
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, ctx->w.flag_in, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -173,6 +175,10 @@ int genga_init(genga_ctx** out, int mode, const genga_params* p, int n_massive, 
   int rc = GENGA_OK;
   if (hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) rc = GENGA_EHIP;
   if (rc == GENGA_OK && hipMemsetAsync(ctx->w.st, 0, sizeof(DevStat), ctx->stream) != hipSuccess)
+    rc = GENGA_EHIP;
+  if (rc == GENGA_OK && tp &&
+      hipMemsetAsync(ctx->t.rad, 0, (kTpMaxPlanets + std::max<int64_t>(n_test, 1)) * sizeof(double),
+                     ctx->stream) != hipSuccess)
     rc = GENGA_EHIP;
   if (rc == GENGA_OK) rc = load_state(ctx, d_m, d_x, d_v, coords_in);
   if (rc == GENGA_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = GENGA_EHIP;
@@ -347,7 +353,59 @@ int genga_stats(genga_ctx* ctx, genga_stats_t* s) {
   s->enc_total = (int64_t)hs.enc_total;
   s->full_kicks = (int64_t)hs.fullkicks;
   s->tp_enc_total = (int64_t)hs.tp_enc_total;
+  s->tp_removed = (int64_t)hs.tp_removed;
   s->flags = hs.flags;
+  return status_from_flags(hs.flags);
+}
+
+int genga_set_radii(genga_ctx* ctx, const double* d_radii) {
+  if (!ctx || !d_radii || ctx->mode != GENGA_TEST) return GENGA_EINVAL;
+  HIPCHK(hipMemsetAsync(ctx->w.flag_in, 0, sizeof(int), ctx->stream));
+  HIPCHK(tp_set_radii(ctx->t, ctx->w.n, d_radii, ctx->w.flag_in, ctx->stream));
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, ctx->w.flag_in, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (bad) {
+    // leave no partial set behind: back to no collisions
+    HIPCHK(hipMemsetAsync(ctx->t.rad, 0,
+                          (kTpMaxPlanets + std::max<int64_t>(ctx->t.ntp, 1)) * sizeof(double),
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return GENGA_EINVAL;
+  }
+  return GENGA_OK;
+}
+
+int genga_collisions(genga_ctx* ctx, int64_t* h_tp, int32_t* h_planet, int64_t* h_step,
+                     double* h_frac, double* h_xv, int64_t cap, int64_t* h_n) {
+  if (!ctx || !h_n || cap < 0 || ctx->mode != GENGA_TEST) return GENGA_EINVAL;
+  if (cap > 0 && (!h_tp || !h_planet || !h_step || !h_frac || !h_xv)) return GENGA_EINVAL;
+  DevStat hs;
+  int r = read_status(ctx, &hs);
+  if (r != GENGA_OK) return r;
+  // one slot per particle: more removals than particles (particles brought
+  // back by genga_set_state and removed again) lose the later reports
+  const int64_t total = (int64_t)hs.tp_removed;
+  const int64_t n = std::min<int64_t>(total, ctx->t.ntp);
+  std::vector<CollRec> recs((size_t)n);
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(recs.data(), ctx->t.coll, (size_t)n * sizeof(CollRec),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  std::sort(recs.begin(), recs.end(), [](const CollRec& a, const CollRec& b) {
+    return a.step != b.step ? a.step < b.step : a.tp < b.tp;
+  });
+  const int64_t wr = std::min(n, cap);
+  for (int64_t k = 0; k < wr; ++k) {
+    h_tp[k] = recs[k].tp;
+    h_planet[k] = recs[k].planet;
+    h_step[k] = recs[k].step;
+    h_frac[k] = recs[k].frac;
+    for (int q = 0; q < 6; ++q) h_xv[6 * k + q] = recs[k].xv[q];
+  }
+  *h_n = total;
+  if (total > cap || total > n) return GENGA_EOVERFLOW;
   return status_from_flags(hs.flags);
 }
 

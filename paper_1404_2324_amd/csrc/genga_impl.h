@@ -36,7 +36,19 @@ struct DevStat {
   unsigned long long enc_total;  // encounters (cumulative)
   unsigned long long fullkicks;  // opening kicks recomputed in full
   unsigned long long tp_enc_total;
+  unsigned long long nstep;      // steps begun since init
+  unsigned long long tp_removed; // test particles removed by collisions
   double P2[4];        // momentum for the second Sun kick of the step
+};
+
+// Report of a test particle removed by a collision with a planet.
+struct CollRec {
+  long long tp;        // particle index (0-based among the particles)
+  long long step;      // step index since init
+  int planet;          // massive-body index
+  int pad;
+  double frac;         // part of the step covered before the colliding substep
+  double xv[6];        // the particle's democratic state there
 };
 
 constexpr int kBsMaxGroup = 64;        // members per in-wave BS group
@@ -89,7 +101,11 @@ struct TpWs {
   unsigned* bs_mask;    // their encounter planets
   double* bs_rct;       // their critical radii
   double* bs_y;         // their pre-drift state [6][ntp]
+  double* rad;          // physical radii: planets [32], then particles [ntp]
+  CollRec* coll;        // collision reports, one slot per particle
 };
+
+constexpr int kTpMaxPlanets = 32;
 
 struct StepConsts {
   double G, m0, mu, dt, h, n1, n2, pf, pf2, bs_tol;
@@ -111,7 +127,8 @@ hipError_t massive_unpack(const MassiveWs& w, const StepConsts& c, double* x,
                           double* v, int coords_out, hipStream_t s);
 hipError_t massive_prime(const MassiveWs& w, const StepConsts& c,
                          hipStream_t s);
-// ev0/ev1 (may be null) are recorded around the closing-kick pair kernel.
+// When ev0 and ev1 are both given they take the start and end timestamps of
+// the closing-kick pair kernel's dispatch.
 hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t massive_energy(const MassiveWs& w, const StepConsts& c, double* dE,
@@ -132,6 +149,13 @@ hipError_t tp_prime(const MassiveWs& w, const TpWs& t, const StepConsts& c,
                     hipStream_t s);
 hipError_t tp_step(const MassiveWs& w, const TpWs& t, const StepConsts& c,
                    hipStream_t s);
+// Test-particle rows [nm, nm + ntp) of x and v: finite, or all NaN (removed);
+// anything else sets *dbad.
+hipError_t tp_validate(const TpWs& t, int nm, const double* x, const double* v, int* dbad,
+                       hipStream_t s);
+// Copies nm + ntp radii (planets first) into the workspace; negative or
+// non-finite values set *dbad.
+hipError_t tp_set_radii(const TpWs& t, int nm, const double* r, int* dbad, hipStream_t s);
 
 // ---- single-operation kernels for component checks (ops.hip) ---------------
 hipError_t op_kepler(double mu, int64_t n, const double* x0, const double* v0,

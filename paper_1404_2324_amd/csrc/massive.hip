@@ -13,6 +13,8 @@
 //   k_kick         closing kick: all pairs and the prechecker, per j-block
 //   k_kick_finish  fixed-order sum of the partials, second Sun kick tau/2,
 //                  v += tau/2 a, next radii
+#include <hip/hip_ext.h>
+
 #include <climits>
 
 #include "bs_device.h"
@@ -445,6 +447,7 @@ __global__ __launch_bounds__(kVecBlock) void k_drift(DriftArgs a) {
       a.st->ctl = 0u;
       a.st->tp_nbs = 0u;
       a.st->tp_enc = 0;
+      a.st->nstep += 1ull;
     }
   }
 }
@@ -1189,9 +1192,12 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
   }
 
   KickArgs a = kick_args(w, c);
-  if (ev0) hipEventRecord(ev0, s);
-  hipLaunchKernelGGL(k_kick<KICK_CLOSE>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
-  if (ev1) hipEventRecord(ev1, s);
+  if (ev0 && ev1)
+    // the events take the dispatch's own start and end timestamps
+    hipExtLaunchKernelGGL(k_kick<KICK_CLOSE>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s,
+                          ev0, ev1, 0, a);
+  else
+    hipLaunchKernelGGL(k_kick<KICK_CLOSE>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
   hipLaunchKernelGGL(k_kick_finish<KICK_CLOSE>, dim3(ceil_div(4 * w.n, kVecBlock)), dim3(kVecBlock), 0, s, a, w.njb);
   return hipGetLastError();
 }

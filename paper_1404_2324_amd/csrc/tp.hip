@@ -8,9 +8,12 @@
 //              candidate mask); the others are compacted into a list
 //   k_tp_bs    one wave per listed particle: BS of the particle with the
 //              planets it encounters (planets feel only the star there), then
-//              the rest of its step
+//              the rest of its step; a particle that comes closer to a planet
+//              than the sum of their physical radii during a BS substep is
+//              removed there and reported (Sec. 3.3)
 // Particle state is stored as SoA (x[3][ntp], v[3][ntp]) plus a 32-bit
-// candidate mask: 52 bytes read and written per particle and step.
+// candidate mask: 52 bytes read and written per particle and step.  A removed
+// particle's x and v are NaN; every kernel skips it.
 #include <algorithm>
 #include <climits>
 
@@ -45,6 +48,8 @@ struct TpArgs {
   unsigned* __restrict__ bs_mask;     // their encounter planets
   double* __restrict__ bs_rct;        // their radii
   double* __restrict__ bs_y;          // their pre-drift state [6][cap]
+  const double* __restrict__ rad;     // radii: planets [32], particles [ntp]
+  CollRec* __restrict__ coll;         // removal reports
   int64_t ntp, cap;
   int nm, nblk, enc_free, max_iter;
   double G, h, m0, mu, dt, absdt, n2, pf2, tol;
@@ -122,8 +127,10 @@ __global__ __launch_bounds__(256) void k_tp_main(TpArgs a) {
   unsigned emask = 0u;
   double xm0 = 0, ym0 = 0, zm0 = 0, vxm = 0, vym = 0, vzm = 0, rct = 0;
   int it = 0;
-  if (k < a.ntp) {
-    double x = a.x[k], y = a.x[a.ntp + k], z = a.x[2 * a.ntp + k];
+  double x = 0.0;
+  if (k < a.ntp) x = a.x[k];
+  if (k < a.ntp && !isnan(x)) {
+    double y = a.x[a.ntp + k], z = a.x[2 * a.ntp + k];
     double vx = a.v[k], vy = a.v[a.ntp + k], vz = a.v[2 * a.ntp + k];
     const unsigned cmask = a.mask[k];
     rct = a.n2 * a.absdt * sqrt(vx * vx + vy * vy + vz * vz);
@@ -193,12 +200,16 @@ __global__ __launch_bounds__(256) void k_tp_main(TpArgs a) {
 
 // One wave per listed particle: its group is the particle (member 0) and the
 // planets it encounters in ascending order, started from the pre-drift state.
+// rtp: the particle's physical radius; a planet member with a nonzero sum
+// of radii gets the collision test.
 template <int P>
 __device__ __forceinline__ int tp_group(const TpArgs& a, int64_t e, int sz, unsigned em,
-                                        const double* mm, const double* mrc, long long* nsub,
-                                        double y[6]) {
+                                        const double* mm, const double* mrc, double rtp,
+                                        long long* nsub, double y[6], int* cb,
+                                        long long* cpos) {
   const int lane = threadIdx.x & 63;
   const int b = lane % P;
+  double R2 = -1.0;
   y[0] = 1.0;
   y[1] = y[2] = y[3] = y[4] = y[5] = 0.0;
   if (b == 0) {
@@ -216,8 +227,36 @@ __device__ __forceinline__ int tp_group(const TpArgs& a, int64_t e, int sz, unsi
     y[3] = q.x;
     y[4] = q.y;
     y[5] = q.z;
+    const double R = rtp + a.rad[j];
+    if (R > 0.0) R2 = R * R;
   }
-  return bs_group<P, true>(sz, y, mm, mrc, a.dt, a.G, a.mu, a.tol, a.max_depth, nsub);
+  return bs_group<P, true>(sz, y, mm, mrc, a.dt, a.G, a.mu, a.tol, a.max_depth, nsub, R2, cb,
+                           cpos);
+}
+
+// Removal of listed particle e after a collision with its member cb, at the
+// start of the substep that covers [cpos, ...) of the step (units 2^-D).
+__device__ void tp_remove(const TpArgs& a, int64_t e, unsigned em, int cb, long long cpos,
+                          const double y[6]) {
+  const int64_t k = a.bs_idx[e];
+  unsigned mm2 = em;
+  for (int t = 1; t < cb; ++t) mm2 &= mm2 - 1u;
+  const unsigned long long slot = atomicAdd(&a.st->tp_removed, 1ull);
+  if ((int64_t)slot < a.ntp) {
+    CollRec r;
+    r.tp = k;
+    r.step = (long long)a.st->nstep - 1;
+    r.planet = __ffs(mm2) - 1;
+    r.pad = 0;
+    r.frac = ldexp((double)cpos, -a.max_depth);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) r.xv[q] = y[q];
+    a.coll[slot] = r;
+  }
+  const double nan = __builtin_nan("");
+  a.x[k] = a.x[a.ntp + k] = a.x[2 * a.ntp + k] = nan;
+  a.v[k] = a.v[a.ntp + k] = a.v[2 * a.ntp + k] = nan;
+  a.mask[k] = 0u;
 }
 
 __global__ __launch_bounds__(64) void k_tp_bs(TpArgs a) {
@@ -248,16 +287,21 @@ __global__ __launch_bounds__(64) void k_tp_bs(TpArgs a) {
     }
     __syncthreads();
     double y[6];
-    int r;
+    const double rtp = a.rad[kTpMaxPlanets + a.bs_idx[e]];
+    int r, cb = 0;
+    long long cpos = 0;
     if (sz <= 2)
-      r = tp_group<2>(a, e, sz, em, mm, mrc, &nsub, y);
+      r = tp_group<2>(a, e, sz, em, mm, mrc, rtp, &nsub, y, &cb, &cpos);
     else if (sz <= 4)
-      r = tp_group<4>(a, e, sz, em, mm, mrc, &nsub, y);
+      r = tp_group<4>(a, e, sz, em, mm, mrc, rtp, &nsub, y, &cb, &cpos);
     else
-      r = tp_group<8>(a, e, sz, em, mm, mrc, &nsub, y);
-    if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
-    if (lane == 0)
+      r = tp_group<8>(a, e, sz, em, mm, mrc, rtp, &nsub, y, &cb, &cpos);
+    if (r < 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
+    if (r == 1) {
+      if (lane == 0) tp_remove(a, e, em, cb, cpos, y);
+    } else if (lane == 0) {
       tp_finish(a, a.bs_idx[e], y[0], y[1], y[2], y[3], y[4], y[5], rct, P2x, P2y, P2z);
+    }
   }
   if (lane == 0 && nsub > 0) atomicAdd(&a.st->bs_sub, (unsigned long long)nsub);
 }
@@ -326,6 +370,33 @@ __global__ void k_tp_prime(TpArgs a) {
   a.mask[k] = msk;
 }
 
+// Test-particle rows of the caller's state: each row is finite, or all six
+// values are NaN (a removed particle).
+__global__ void k_tp_validate(const double* __restrict__ x, const double* __restrict__ v,
+                              int64_t ntp, int nm, int* __restrict__ bad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ntp) return;
+  const int64_t r = nm + k;
+  int fin = 0, nan = 0;
+  for (int q = 0; q < 3; ++q) {
+    const double a = x[3 * r + q], b = v[3 * r + q];
+    fin += isfinite(a) + isfinite(b);
+    nan += isnan(a) + isnan(b);
+  }
+  if (fin != 6 && nan != 6) atomicOr(bad, 1);
+}
+
+__global__ void k_tp_radii(const double* __restrict__ r, double* __restrict__ rad, int64_t ntp,
+                           int nm, int* __restrict__ bad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < kTpMaxPlanets) rad[k] = k < nm ? r[k] : 0.0;
+  if (k < ntp) rad[kTpMaxPlanets + k] = r[nm + k];
+  if (k < nm + ntp) {
+    const double q = r[k];
+    if (!(q >= 0.0) || !isfinite(q)) atomicOr(bad, 1);
+  }
+}
+
 TpArgs tp_args(const MassiveWs& w, const TpWs& t, const StepConsts& c) {
   TpArgs a;
   a.x = t.x;
@@ -344,6 +415,8 @@ TpArgs tp_args(const MassiveWs& w, const TpWs& t, const StepConsts& c) {
   a.bs_mask = t.bs_mask;
   a.bs_rct = t.bs_rct;
   a.bs_y = t.bs_y;
+  a.rad = t.rad;
+  a.coll = t.coll;
   a.ntp = t.ntp;
   a.cap = t.ntp;
   a.nm = w.n;
@@ -381,7 +454,24 @@ size_t tp_carve(TpWs& t, int64_t ntp, void* base) {
   t.bs_mask = (unsigned*)take(n * sizeof(unsigned));
   t.bs_rct = (double*)take(n * sizeof(double));
   t.bs_y = (double*)take(6 * n * sizeof(double));
+  t.rad = (double*)take((kTpMaxPlanets + n) * sizeof(double));
+  t.coll = (CollRec*)take(n * sizeof(CollRec));
   return off;
+}
+
+hipError_t tp_validate(const TpWs& t, int nm, const double* x, const double* v, int* dbad,
+                       hipStream_t s) {
+  if (t.ntp <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tp_validate, dim3(ceil_div64(t.ntp, 256)), dim3(256), 0, s, x, v, t.ntp,
+                     nm, dbad);
+  return hipGetLastError();
+}
+
+hipError_t tp_set_radii(const TpWs& t, int nm, const double* r, int* dbad, hipStream_t s) {
+  const int64_t n = std::max<int64_t>(t.ntp + nm, kTpMaxPlanets);
+  hipLaunchKernelGGL(k_tp_radii, dim3(ceil_div64(n, 256)), dim3(256), 0, s, r, t.rad, t.ntp, nm,
+                     dbad);
+  return hipGetLastError();
 }
 
 hipError_t tp_pack(const MassiveWs& w, const TpWs& t, const StepConsts& c, const double* x,

@@ -43,7 +43,8 @@ class Stats(ctypes.Structure):
                 ("max_group", ctypes.c_int32), ("kepler_iter_max", ctypes.c_int32),
                 ("tp_enc", ctypes.c_int32), ("bs_substeps", ctypes.c_int64),
                 ("enc_total", ctypes.c_int64), ("full_kicks", ctypes.c_int64),
-                ("tp_enc_total", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("tp_enc_total", ctypes.c_int64), ("tp_removed", ctypes.c_int64),
+                ("flags", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32)]
 
     def as_dict(self):
@@ -68,6 +69,8 @@ SIGNATURES = {
     "genga_encounters": (_i32, [_vp, _vp, _vp, _vp, _i32, ctypes.POINTER(_i32)]),
     "genga_candidates": (_i32, [_vp, _vp, _i32, ctypes.POINTER(_i32)]),
     "genga_stats": (_i32, [_vp, ctypes.POINTER(Stats)]),
+    "genga_set_radii": (_i32, [_vp, _vp]),
+    "genga_collisions": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64)]),
     "genga_strerror": (ctypes.c_char_p, [_i32]),
     "genga_destroy": (_i32, [_vp]),
     "genga_accel_workspace_bytes": (_sz, [_i32]),
@@ -277,10 +280,11 @@ def hermite(dt, q, device="cuda", stream=None):
 
 class TestParticleSimulation(Simulation):
     """Test-particle mode: up to 32 massive bodies plus massless particles
-    (row order: massive bodies first, then particles)."""
+    (row order: massive bodies first, then particles).  radii (optional,
+    n_massive + n_test values) turns on removal by collision."""
 
     def __init__(self, m, x, v, xt, vt, params: Params | None = None, coords: str = "helio",
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, radii=None):
         self.p = params if params is not None else default_params()
         self.device = torch.device(device)
         self.stream = stream
@@ -301,6 +305,33 @@ class TestParticleSimulation(Simulation):
                                 GENGA_HELIO if coords == "helio" else GENGA_DEMOCRATIC,
                                 _ptr(self.ws), nbytes, _stream(stream))
         _check(code, "genga_init")
+        if radii is not None:
+            self.set_radii(radii)
+
+    def set_radii(self, radii):
+        r = _dev(radii, self.device).reshape(-1).contiguous()
+        if r.numel() != self.n:
+            raise ValueError("radii: n_massive + n_test values")
+        _check(lib().genga_set_radii(self._ctx, _ptr(r)), "genga_set_radii")
+
+    def collisions(self):
+        """Removal reports since init, sorted by (step, particle): a dict of
+        numpy arrays tp, planet, step, frac and xv (n x 6, democratic)."""
+        n = ctypes.c_int64()
+        code = lib().genga_collisions(self._ctx, None, None, None, None, None, 0, ctypes.byref(n))
+        if code not in (OK, EOVERFLOW):
+            _check(code, "genga_collisions")
+        k = int(n.value)
+        tp = np.zeros(k, dtype=np.int64)
+        pl = np.zeros(k, dtype=np.int32)
+        stp = np.zeros(k, dtype=np.int64)
+        fr = np.zeros(k)
+        xv = np.zeros((k, 6))
+        if k:
+            _check(lib().genga_collisions(self._ctx, tp.ctypes.data, pl.ctypes.data, stp.ctypes.data,
+                                          fr.ctypes.data, xv.ctypes.data, k, ctypes.byref(n)),
+                   "genga_collisions")
+        return {"tp": tp, "planet": pl, "step": stp, "frac": fr, "xv": xv}
 
     def split_state(self, coords: str = "dem"):
         x, v = self.state(coords)

@@ -141,6 +141,39 @@ def test_particles(ntp: int = 1_000_000, nplanets: int = 8, seed_index: int = 3)
     return planets, xt, ut
 
 
+MSUN_G = 1.98847e33
+AU_CM = 1.495978707e13
+
+
+def tp_radii(m, ntp: int, rho_cgs: float = 2.0, r_tp_km: float = 10.0):
+    """Physical radii for test-particle mode, planets first: a planet of mass
+    m (solar masses) gets the radius of a sphere of bulk density rho_cgs
+    (g/cm^3); every particle gets r_tp_km.  Lengths in AU."""
+    m = np.asarray(m, dtype=np.float64)
+    rp = np.cbrt(3.0 * m * MSUN_G / (4.0 * np.pi * rho_cgs)) / AU_CM
+    return np.concatenate([rp, np.full(ntp, r_tp_km * 1e5 / AU_CM)])
+
+
+def tp_flybys(planets: System, radii, n: int, seed_index: int = 6, d0: float = 0.02,
+              bmax: float = 4.0):
+    """Test particles aimed at the planets (particle k at planet k mod nm):
+    heliocentric start d0 before the planet along a random direction, offset
+    sideways by an impact parameter b ~ U(0, bmax) x the planet's radius,
+    relative speed ~ U(0.2, 1).  Returns (xt, ut)."""
+    rng = rng_for(seed_index)
+    nm = len(planets.m)
+    j = np.arange(n) % nm
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    e = np.cross(d, rng.standard_normal((n, 3)))
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    b = rng.uniform(0.0, bmax, n) * np.asarray(radii)[j]
+    s = rng.uniform(0.2, 1.0, n)
+    xt = planets.x[j] - d0 * d + b[:, None] * e
+    ut = planets.u[j] + s[:, None] * d
+    return xt, ut
+
+
 def batched(nsys: int = 4096, seed_index: int = 4, nmin: int = 2, nmax: int = 32):
     """Independent systems with N ~ U{nmin..nmax} bodies, masses
     log-uniform in [1e-8, 1e-4], a ~ U(0.3, 3), e, i ~ Ray(0.02).

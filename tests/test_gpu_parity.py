@@ -290,6 +290,23 @@ def test_determinism_two_runs():
     assert np.array_equal(outs[0][2], outs[1][2])
 
 
+def test_profiled_steps_match_graph_steps():
+    """The measurement path (kernels launched one by one, the pair kernel
+    timed by its own dispatch timestamps) computes the same steps bit for bit."""
+    s = W.planetesimals(2048)
+    gp = _gparams()
+    a = G.Simulation(s.m, s.x, s.u, gp, coords="helio")
+    b = G.Simulation(s.m, s.x, s.u, gp, coords="helio")
+    a.step(12)
+    us = b.step_profiled(12)
+    _say("profiled pair kernel us", us)
+    assert 0.0 < us < 1e5
+    xa, va = a.state()
+    xb, vb = b.state()
+    assert torch.equal(xa, xb) and torch.equal(va, vb)
+    assert a.stats()["steps"] == b.stats()["steps"] == 12
+
+
 # ----------------------------------------------------------- error paths --
 def test_nan_input_rejected():
     s = W.plain_n16()

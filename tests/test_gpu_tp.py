@@ -102,3 +102,145 @@ def test_tp_encounter_free_equals_massive_free():
     orc = O.TPSim(_op(gp), planets.m, planets.x, planets.u, xt, ut, coords="helio")
     orc.step(20)
     assert _rel(xg, orc.xt).max() < REL
+
+
+def _coll_parity(sim, orc, ntp, tol):
+    """Removal reports and surviving states of the GPU run against the
+    oracle's.  Unique and compared exactly: which particles are removed, by
+    which planet, in which step.  The part of the step at which a collision is
+    reported is resolved to the BS substep, and where the two sides take an
+    accept/reject decision on different sides of the tolerance (their forces
+    differ in the last bits) the substep partition differs: it must agree for
+    most reports and stay within a few of the finest substeps otherwise
+    (the oracle's own runs under 1-ulp input changes differ the same way)."""
+    rep = sim.collisions()
+    gone_o = orc.removed()
+    _say("removed gpu", len(rep["tp"]), "oracle", len(gone_o))
+    order = np.argsort(rep["tp"], kind="stable")
+    np.testing.assert_array_equal(rep["tp"][order], gone_o)
+    np.testing.assert_array_equal(rep["planet"][order], orc.coll_planet[gone_o])
+    np.testing.assert_array_equal(rep["step"][order], orc.coll_step[gone_o])
+    fg, fo = rep["frac"][order], orc.coll_frac[gone_o]
+    same = fg == fo
+    _say("frac equal", int(same.sum()), "gpu earlier", int((fg < fo).sum()),
+         "gpu later", int((fg > fo).sum()), "max |dfrac|", float(np.abs(fg - fo).max(initial=0)))
+    assert same.sum() >= 0.8 * len(gone_o)
+    assert np.abs(fg - fo).max(initial=0) <= 2.0**-8
+    if len(gone_o):
+        xg_r, xo_r = rep["xv"][order], orc.coll_xv[gone_o]
+        dx = _rel(xg_r[same, :3], xo_r[same, :3]).max(initial=0)
+        dv = _rel(xg_r[same, 3:], xo_r[same, 3:]).max(initial=0)
+        _say("reports with equal frac: max rel x", dx, "v", dv)
+        assert dx < tol and dv < tol
+    _, _, xg, vg = [t.cpu().numpy() for t in sim.split_state(coords="dem")]
+    alive = np.setdiff1d(np.arange(ntp), gone_o)
+    assert np.all(np.isnan(xg[gone_o])) and np.all(np.isnan(vg[gone_o]))
+    assert np.all(np.isfinite(xg[alive]))
+    return xg, vg, alive
+
+
+def _flyby_inputs(n_bg=2000, n_fly=2000):
+    """The workload's planets and particles plus particles aimed at the
+    planets inside 4 planet radii; physical radii (bulk density 2 g/cm^3)."""
+    planets, xt, ut = W.test_particles(ntp=n_bg, seed_index=3)
+    xf, uf = W.tp_flybys(planets, W.tp_radii(planets.m, 0), n_fly)
+    xt, ut = np.concatenate([xt, xf]), np.concatenate([ut, uf])
+    return planets, xt, ut, W.tp_radii(planets.m, len(xt))
+
+
+# Passages within a few planet radii amplify differences: the BS tolerance
+# (1e-13 of the heliocentric |x|) is ~1e-10 of the particle-planet distance
+# there.  The oracle itself, rerun with the particles' inputs moved by 1 ulp,
+# spreads by up to 4e-10 (relative) on the survivors of these passages after
+# 12 steps; the bound below leaves a factor 25 over that.
+DEEP_TOL = 1e-8
+
+
+def test_tp_collisions_match_oracle():
+    """Sec. 3.3 removal: about 900 of 4000 particles hit a planet in 12 steps."""
+    planets, xt, ut, rad = _flyby_inputs()
+    ntp = len(xt)
+    gp = G.default_params()
+    sim = G.TestParticleSimulation(planets.m, planets.x, planets.u, xt, ut, gp, coords="helio",
+                                   radii=rad)
+    orc = O.TPSim(_op(gp), planets.m, planets.x, planets.u, xt, ut, coords="helio", radii=rad)
+    sub_o = 0
+    for _ in range(3):
+        sim.step(4)
+        sub_o += orc.step(4)["bs_substeps"]
+    sim.check()
+    st = sim.stats()
+    _say("bs substeps gpu", st["bs_substeps"], "oracle", sub_o)
+    assert abs(st["bs_substeps"] - sub_o) <= 0.01 * sub_o
+    assert st["tp_removed"] == len(orc.removed()) > 500
+    xg, vg, alive = _coll_parity(sim, orc, ntp, DEEP_TOL)
+    ex, ev = _rel(xg[alive], orc.xt[alive]), _rel(vg[alive], orc.vt[alive])
+    _say("survivors max rel x", ex.max(), "v", ev.max(), "beyond 1e-12:", int((ex > 1e-12).sum()))
+    assert ex.max() < DEEP_TOL and ev.max() < DEEP_TOL
+    # the background particles (no aimed passage) hold the 1e-12 bar
+    bg = alive[alive < 2000]
+    assert ex[: len(bg)].max() < REL and ev[: len(bg)].max() < REL
+
+
+def test_tp_million_with_radii_sampled_and_all_removals():
+    """The 10^6-particle workload with its physical radii for 10 steps: every
+    removal matches the oracle's (which follows all particles), and the
+    survivors match on a sample."""
+    planets, xt, ut = W.test_particles(ntp=1_000_000, seed_index=3)
+    rad = W.tp_radii(planets.m, len(xt))
+    gp = G.default_params()
+    sim = G.TestParticleSimulation(planets.m, planets.x, planets.u, xt, ut, gp, coords="helio",
+                                   radii=rad)
+    sim.step(10)
+    sim.check()
+    orc = O.TPSim(_op(gp), planets.m, planets.x, planets.u, xt, ut, coords="helio", radii=rad)
+    orc.step(10)
+    rep = sim.collisions()
+    gone_o = orc.removed()
+    _say("1e6 removals gpu", len(rep["tp"]), "oracle", len(gone_o))
+    np.testing.assert_array_equal(np.sort(rep["tp"]), gone_o)
+    _, _, xg, vg = [t.cpu().numpy() for t in sim.split_state(coords="dem")]
+    sel = np.setdiff1d(np.arange(0, 1_000_000, 499), gone_o)
+    assert _rel(xg[sel], orc.xt[sel]).max() < REL and _rel(vg[sel], orc.vt[sel]).max() < REL
+
+
+def test_tp_radii_errors_and_removed_rows_round_trip():
+    planets, xt, ut, rad = _flyby_inputs(1000, 500)
+    gp = G.default_params()
+    sim = G.TestParticleSimulation(planets.m, planets.x, planets.u, xt, ut, gp, coords="helio")
+    bad = rad.copy()
+    bad[3] = -1.0
+    with pytest.raises(G.GengaError) as ei:
+        sim.set_radii(bad)
+    assert ei.value.code == G.EINVAL
+    sim.set_radii(rad)
+    sim.step(4)
+    sim.check()
+    gone = sim.collisions()["tp"]
+    assert len(gone) > 0
+    # a removed particle's row is six NaN; set_state takes it back as removed
+    x, v = sim.state("dem")
+    sim2 = G.TestParticleSimulation(planets.m, planets.x, planets.u, xt, ut, gp, coords="helio")
+    sim2.set_state(x, v, coords="dem")
+    x2, v2 = sim2.state("dem")
+    assert torch_equal_nan(x, x2) and torch_equal_nan(v, v2)
+    sim2.step(2)
+    sim2.check()
+    x3, _ = sim2.state("dem")
+    assert bool(x3[planets.m.size + gone].isnan().all())
+    # a half-NaN particle row is rejected
+    x[planets.m.size, 0] = float("nan")
+    x[planets.m.size + gone[0]] = 0.5
+    with pytest.raises(G.GengaError):
+        sim2.set_state(x, v, coords="dem")
+    # main mode has no radii
+    import torch
+    ms = G.Simulation(planets.m, planets.x, planets.u, gp, coords="helio")
+    r = torch.zeros(planets.m.size, dtype=torch.float64, device="cuda")
+    assert G.lib().genga_set_radii(ms._ctx, r.data_ptr()) == G.EINVAL
+    ms.close()
+
+
+def torch_equal_nan(a, b):
+    import torch
+    return bool(torch.equal(torch.nan_to_num(a, nan=1e300), torch.nan_to_num(b, nan=1e300)))

@@ -33,10 +33,26 @@ def test_library_exports_every_declared_symbol(G):
         assert name in G.SIGNATURES, f"{name} has no binding signature"
 
 
-def test_struct_layouts_match_header(G):
-    # genga_params: 7 doubles + 6 int32 = 80 bytes; stats: 8+6*4+4*8+8 = 96
-    assert ctypes.sizeof(G.Params) == 80
-    assert ctypes.sizeof(G.Stats) == 8 + 6 * 4 + 4 * 8 + 8
+def test_struct_layouts_match_header(G, tmp_path):
+    """The binding's structs have the C compiler's size and field offsets."""
+    import subprocess
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "genga.h"', "int main(void) {"]
+    for cname, cls in (("genga_params", G.Params), ("genga_stats_t", G.Stats)):
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for cname, cls in (("genga_params", G.Params), ("genga_stats_t", G.Stats)):
+        assert int(out[cname]) == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(out[f"{cname}.{f}"]) == getattr(cls, f).offset, f"{cname}.{f}"
 
 
 def test_default_params(G):

@@ -31,6 +31,14 @@ MUTANTS = {
                          "int l = label[a] > label[b] ? label[a] : label[b];"),
     "energy_sun_term": ("*E = kin + dot3(P, P) / (2.0 * p->m0) + pot;", "*E = kin + pot;"),
     "precheck_factor": ("cand[(size_t)i * n + j] = r < p->pf * rcij;", "cand[(size_t)i * n + j] = r < rcij;"),
+    "coll_particle_radius": ("double R = s->rad[0] + s->rad[j];", "double R = s->rad[j];"),
+    "coll_end_points_only": ("if (go_hermite_dmin2(h, dx0, dv0, dx1, dv1) < R * R) return j;",
+                             "if (dot3(dx1, dx1) < R * R) return j;"),
+    "coll_report_after": ("                    rcode = BS_COLLIDED;\n",
+                          "                    memcpy(y, ynew, sizeof(double) * dim);\n"
+                          "                    rcode = BS_COLLIDED;\n"),
+    "coll_frac_after": ("*coll_frac = ldexp((double)pos, -D);",
+                        "*coll_frac = ldexp((double)(pos + ((int64_t)1 << (D - d))), -D);"),
 }
 
 
@@ -46,6 +54,9 @@ def test_pins_catch_mutant(name, tmp_path):
     code = ("import sys; sys.path.insert(0, %r); sys.path.insert(1, %r); import pytest; "
             "sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', %r]))"
             % (str(tmp_path), ROOT, os.path.join(ROOT, "tests", "test_oracle_pins.py")))
+    # the pins are small: one OpenMP thread keeps parallel test workers from
+    # oversubscribing the cores
+    env = dict(os.environ, OMP_NUM_THREADS="1", OMP_WAIT_POLICY="passive")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
-                       cwd=str(tmp_path), timeout=600)
+                       cwd=str(tmp_path), timeout=600, env=env)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"

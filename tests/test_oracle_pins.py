@@ -530,6 +530,106 @@ def test_tp_mode_equals_massive_path_with_zero_masses():
         np.testing.assert_allclose(ms.v[3:], tp.vt, rtol=0, atol=1e-11)
 
 
+def _pericentre(mu, r, v):
+    """Closest approach of the two-body relative orbit (textbook)."""
+    E = 0.5 * v @ v - mu / np.linalg.norm(r)
+    h2 = np.cross(r, v) @ np.cross(r, v)
+    e = np.sqrt(max(0.0, 1.0 + 2.0 * E * h2 / mu**2))
+    return h2 / (mu * (1.0 + e))
+
+
+def _flyby_setup(bs, vrel=2.0, start=0.03, mp=1e-3):
+    """One planet on a circular orbit at a = 1; massless particles passing it
+    at impact parameters bs with relative speed vrel (heliocentric input)."""
+    xp = np.array([[1.0, 0.0, 0.0]])
+    up = np.array([[0.0, np.sqrt(1.0 + mp), 0.0]])
+    xt = np.array([[1.0 - start, b, 0.0] for b in bs])
+    ut = np.array([[vrel, np.sqrt(1.0 + mp), 0.0] for _ in bs])
+    q = np.array([_pericentre(mp, xt[k] - xp[0], ut[k] - up[0]) for k in range(len(bs))])
+    return np.array([mp]), xp, up, xt, ut, q
+
+
+def test_tp_collision_removes_iff_closest_approach_below_radii():
+    """Sec. 3.3 (a particle hitting a planet is removed and reported) with the
+    collision condition of Sec. 3.2.7 (separation below the sum of the radii):
+    removal happens exactly for the passages whose two-body closest approach
+    lies inside the sum of the radii, whichever of the two radii carries it."""
+    bs = [0.002, 0.003, 0.004, 0.006, 0.008, 0.012]
+    m, xp, up, xt, ut, q = _flyby_setup(bs)
+    rp = 0.3 * q.min()
+    f = np.array([0.8, 1.25, 0.8, 1.25, 1.25, 0.8])
+    rt = f * q - rp            # particle radii carry the rest of the sum
+    p = O.params()
+    sim = O.TPSim(p, m, xp, up, xt, ut, coords="helio", radii=np.concatenate([[rp], rt]))
+    states = []
+    for _ in range(3):
+        states.append((sim.x.copy(), sim.v.copy()))
+        sim.step(1)
+    gone = sim.removed()
+    np.testing.assert_array_equal(gone, np.nonzero(f > 1.0)[0])
+    assert sim.stats.tp_removed == 0  # the last step removed nothing
+    assert np.all(sim.coll_planet[gone] == 0)
+    assert np.all(np.isnan(sim.xt[gone])) and np.all(np.isnan(sim.vt[gone]))
+    kept = np.nonzero(f < 1.0)[0]
+    assert np.all(np.isfinite(sim.xt[kept]))
+    D = p.bs_max_depth
+    for k in gone:
+        s, fr = int(sim.coll_step[k]), float(sim.coll_frac[k])
+        assert 0 <= s < 3 and 0.0 <= fr < 1.0 and (fr * 2**D) == int(fr * 2**D)
+        # the planet at the reported time: opening kick (no other massive
+        # body) and Sun kick, then the star-only flow over frac * tau
+        x0, v0 = states[s]
+        xpre = x0[0] + 0.5 * p.dt * m[0] * v0[0] / p.m0
+        xpl, vpl, _ = O.kepler(p.G * p.m0, xpre, v0[0], fr * p.dt)
+        r = sim.coll_xv[k, :3] - xpl
+        w = sim.coll_xv[k, 3:] - vpl
+        R = rp + rt[k]
+        # the report is the state just before the collision: still outside
+        # the sum of the radii, inbound, on a path that dips inside it
+        assert np.linalg.norm(r) > R
+        assert r @ w < 0.0
+        assert _pericentre(m[0], r, w) < R
+
+
+def test_tp_collision_inside_one_substep():
+    """The collision test covers the whole BS substep, as the encounter test
+    covers the whole step (Eqs. 10-12): a planet of negligible mass does not
+    bend the particle's path, BS takes the step in one substep, and a passage
+    that enters and leaves the sum of the radii between the substep's end
+    points is still found, with the report at the start of a substep."""
+    bs = [0.002, 0.002]
+    m, xp, up, xt, ut, q = _flyby_setup(bs, mp=1e-12, start=0.06, vrel=6.0)
+    np.testing.assert_allclose(q, 0.002, rtol=1e-6)   # a straight line
+    p = O.params()
+    sim = O.TPSim(p, m, xp, up, xt, ut, coords="helio", radii=[0.0, 0.003, 0.0015])
+    sim.step(1)
+    # a few substeps per particle, none shorter than tau/16: the particle
+    # crosses 0.024 AU per such substep, the chord inside the radii is 0.0045
+    assert sim.stats.tp_enc == 2 and sim.stats.bs_substeps <= 8
+    np.testing.assert_array_equal(sim.removed(), [0])
+    assert sim.coll_step[0] == 0 and (16 * sim.coll_frac[0]) % 1.0 == 0.0
+
+
+def test_tp_removed_particle_leaves_the_others_unchanged():
+    """Particles do not interact (Sec. 3.3): removing one changes nothing for
+    the others, and zero radii change nothing at all."""
+    bs = [0.003, 0.02]
+    m, xp, up, xt, ut, q = _flyby_setup(bs)
+    p = O.params()
+    a = O.TPSim(p, m, xp, up, xt, ut, coords="helio", radii=[0.0, 2 * q[0], 0.0])
+    b = O.TPSim(p, m, xp, up, xt[1:], ut[1:], coords="helio")
+    c = O.TPSim(p, m, xp, up, xt, ut, coords="helio", radii=[0.0, 0.0, 0.0])
+    d = O.TPSim(p, m, xp, up, xt, ut, coords="helio")
+    for sim in (a, b, c, d):
+        sim.step(6)
+    np.testing.assert_array_equal(a.removed(), [0])
+    np.testing.assert_array_equal(a.xt[1], b.xt[0])
+    np.testing.assert_array_equal(a.vt[1], b.vt[0])
+    np.testing.assert_array_equal(c.xt, d.xt)
+    np.testing.assert_array_equal(c.vt, d.vt)
+    assert len(c.removed()) == 0
+
+
 # ----------------------------------------------- tangent-linear, adjoint -----
 def _adj_system():
     m, x, u = W.adjoint_systems(nsys=1, nplanets=4, seed_index=5)
