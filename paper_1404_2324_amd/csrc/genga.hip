@@ -177,8 +177,9 @@ int genga_init(genga_ctx** out, int mode, const genga_params* p, int n_massive, 
   if (rc == GENGA_OK && hipMemsetAsync(ctx->w.st, 0, sizeof(DevStat), ctx->stream) != hipSuccess)
     rc = GENGA_EHIP;
   if (rc == GENGA_OK && tp &&
-      hipMemsetAsync(ctx->t.rad, 0, (kTpMaxPlanets + std::max<int64_t>(n_test, 1)) * sizeof(double),
-                     ctx->stream) != hipSuccess)
+      (hipMemsetAsync(ctx->t.rad, 0, (kTpMaxPlanets + std::max<int64_t>(n_test, 1)) * sizeof(double),
+                      ctx->stream) != hipSuccess ||
+       hipMemsetAsync(ctx->t.cum, 0, ctx->t.cum_bytes, ctx->stream) != hipSuccess))
     rc = GENGA_EHIP;
   if (rc == GENGA_OK) rc = load_state(ctx, d_m, d_x, d_v, coords_in);
   if (rc == GENGA_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = GENGA_EHIP;
@@ -347,12 +348,14 @@ int genga_stats(genga_ctx* ctx, genga_stats_t* s) {
   s->n_enc = any ? hs.nenc : 0;
   s->n_groups = any ? hs.ngroups : 0;
   s->max_group = any ? hs.maxg : 0;
-  s->kepler_iter_max = hs.kep_itmax;
-  s->tp_enc = hs.tp_enc;
-  s->bs_substeps = (int64_t)hs.bs_sub;
+  TpCounters tc = {0, 0, 0, 0};
+  if (ctx->mode == GENGA_TEST) HIPCHK(tp_read_counters(ctx->t, &tc, ctx->stream));
+  s->kepler_iter_max = std::max(hs.kep_itmax, tc.kit);
+  s->tp_enc = ctx->steps > 0 && !ctx->p.encounter_free ? (int32_t)tc.enc : 0;
+  s->bs_substeps = (int64_t)(hs.bs_sub + tc.sub);
   s->enc_total = (int64_t)hs.enc_total;
   s->full_kicks = (int64_t)hs.fullkicks;
-  s->tp_enc_total = (int64_t)hs.tp_enc_total;
+  s->tp_enc_total = (int64_t)tc.enc_total;
   s->tp_removed = (int64_t)hs.tp_removed;
   s->flags = hs.flags;
   return status_from_flags(hs.flags);

@@ -30,12 +30,9 @@ struct DevStat {
   int maxg;            // largest group of the last step
   int ncand;           // candidate pairs (i<j) entering the last step
   int kep_itmax;       // largest Kepler iteration count seen
-  int tp_enc;          // test-particle encounters of the last step
-  unsigned tp_nbs;     // particles listed for BS in the current step
   unsigned long long bs_sub;     // accepted BS substeps (cumulative)
   unsigned long long enc_total;  // encounters (cumulative)
   unsigned long long fullkicks;  // opening kicks recomputed in full
-  unsigned long long tp_enc_total;
   unsigned long long nstep;      // steps begun since init
   unsigned long long tp_removed; // test particles removed by collisions
   double P2[4];        // momentum for the second Sun kick of the step
@@ -103,9 +100,29 @@ struct TpWs {
   double* bs_y;         // their pre-drift state [6][ntp]
   double* rad;          // physical radii: planets [32], then particles [ntp]
   CollRec* coll;        // collision reports, one slot per particle
+  int64_t nb, cap;      // 256-particle blocks; list capacity nb * 256
+  int* blk_cnt;         // listed particles per block (this step)
+  int* blk_off;         // their prefix sum [nb + 1]
+  int* blk_enc;         // encounters per block (this step)
+  unsigned long long* blk_enc_tot;  // encounters per block since init
+  int* blk_kit;         // largest Kepler iteration count per block
+  unsigned long long* sub;          // accepted BS substeps per workgroup / wave
+  double* pl;           // planets' whole-step BS table
+  void* cum;            // the cumulative counters above, cleared at init
+  size_t cum_bytes;
 };
 
 constexpr int kTpMaxPlanets = 32;
+constexpr int kTpBs1Grid = 512;    // workgroups of the whole-step BS attempt
+constexpr int kTpBsGrid = 2048;    // waves of the refinement path
+constexpr int kTpSubSlots = kTpBs1Grid + kTpBsGrid;
+
+struct TpCounters {
+  long long enc;                 // encounters of the last step
+  unsigned long long enc_total;  // since init
+  int kit;                       // largest Kepler iteration count
+  unsigned long long sub;        // accepted BS substeps since init
+};
 
 struct StepConsts {
   double G, m0, mu, dt, h, n1, n2, pf, pf2, bs_tol;
@@ -149,6 +166,8 @@ hipError_t tp_prime(const MassiveWs& w, const TpWs& t, const StepConsts& c,
                     hipStream_t s);
 hipError_t tp_step(const MassiveWs& w, const TpWs& t, const StepConsts& c,
                    hipStream_t s);
+// Sums the per-block counters (synchronising).
+hipError_t tp_read_counters(const TpWs& t, TpCounters* h, hipStream_t s);
 // Test-particle rows [nm, nm + ntp) of x and v: finite, or all NaN (removed);
 // anything else sets *dbad.
 hipError_t tp_validate(const TpWs& t, int nm, const double* x, const double* v, int* dbad,

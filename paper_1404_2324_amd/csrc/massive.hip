@@ -445,8 +445,6 @@ __global__ __launch_bounds__(kVecBlock) void k_drift(DriftArgs a) {
       a.st->ngroups = 0;
       a.st->maxg = 0;
       a.st->ctl = 0u;
-      a.st->tp_nbs = 0u;
-      a.st->tp_enc = 0;
       a.st->nstep += 1ull;
     }
   }

@@ -6,16 +6,26 @@
 //              particle's candidate planets; particles without an encounter
 //              finish the step here (second Sun kick, closing kick, new
 //              candidate mask); the others are compacted into a list
-//   k_tp_bs    one wave per listed particle: BS of the particle with the
-//              planets it encounters (planets feel only the star there), then
-//              the rest of its step; a particle that comes closer to a planet
-//              than the sum of their physical radii during a BS substep is
-//              removed there and reported (Sec. 3.3)
+//   k_tp_scan  offsets of each block's listed particles (one workgroup)
+//   k_tp_plan  a planet's Gragg sequences and extrapolation over the whole
+//              step (it feels only the star inside a particle's group), the
+//              same for every particle that meets it
+//   k_tp_bs1   one lane per particle meeting one planet: the BS attempt over
+//              the whole step with the planet taken from that table; most
+//              passages end here
+//   k_tp_bs    one wave per remaining particle: BS of the particle with the
+//              planets it encounters (planets feel only the star there) with
+//              binary refinement, then the rest of its step
+// A particle that comes closer to a planet than the sum of their physical
+// radii during a BS substep is removed there and reported (Sec. 3.3).
+// Counters are kept per block or wave (no same-address atomics on the step
+// path) and summed when read.
 // Particle state is stored as SoA (x[3][ntp], v[3][ntp]) plus a 32-bit
 // candidate mask: 52 bytes read and written per particle and step.  A removed
 // particle's x and v are NaN; every kernel skips it.
 #include <algorithm>
 #include <climits>
+#include <vector>
 
 #include "bs_device.h"
 #include "device_math.h"
@@ -25,6 +35,8 @@ namespace genga {
 namespace {
 
 inline int ceil_div64(int64_t a, int b) { return (int)((a + b - 1) / b); }
+
+
 
 __device__ __forceinline__ unsigned lanemask_count_tp(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
@@ -50,7 +62,14 @@ struct TpArgs {
   double* __restrict__ bs_y;          // their pre-drift state [6][cap]
   const double* __restrict__ rad;     // radii: planets [32], particles [ntp]
   CollRec* __restrict__ coll;         // removal reports
-  int64_t ntp, cap;
+  int* __restrict__ blk_cnt;          // listed particles of each 256-particle block
+  int* __restrict__ blk_off;          // their exclusive prefix sum [nb + 1]
+  int* __restrict__ blk_enc;          // encounters of each block, last step
+  unsigned long long* __restrict__ blk_enc_tot;
+  int* __restrict__ blk_kit;          // largest Kepler iteration count per block
+  unsigned long long* __restrict__ sub;  // accepted BS substeps per block / wave
+  double* __restrict__ pl;            // planets' full-step BS table
+  int64_t ntp, cap, nb;
   int nm, nblk, enc_free, max_iter;
   double G, h, m0, mu, dt, absdt, n2, pf2, tol;
   int max_depth;
@@ -168,34 +187,78 @@ __global__ __launch_bounds__(256) void k_tp_main(TpArgs a) {
       tp_finish(a, k, x, y, z, vx, vy, vz, rct, P2x, P2y, P2z);
     }
   }
-  const int itm = wave_max_i(abs(it));
-  if (lane == 0 && itm > 0) atomicMax(&a.st->kep_itmax, itm);
-  // ballot compaction of the particles with an encounter
+  // block-level compaction of the particles with an encounter into this
+  // block's region of the list, and block counters
+  __shared__ int s_cnt[4], s_enc[4], s_kit[4];
+  const int w = threadIdx.x >> 6;
   const unsigned long long lm = __ballot(listed);
-  int base = 0;
-  if (lane == 0 && lm) base = (int)atomicAdd(&a.st->tp_nbs, (unsigned)__popcll(lm));
-  base = __shfl(base, 0, 64);
-  const int ne = listed ? __popc(emask) : 0;
-  int nen = ne;
+  int nen = listed ? __popc(emask) : 0;
   for (int o = 32; o > 0; o >>= 1) nen += __shfl_xor(nen, o, 64);
-  if (lane == 0 && nen) {
-    atomicAdd(&a.st->tp_enc, nen);
-    atomicAdd(&a.st->tp_enc_total, (unsigned long long)nen);
+  const int itm = wave_max_i(abs(it));
+  if (lane == 0) {
+    s_cnt[w] = __popcll(lm);
+    s_enc[w] = nen;
+    s_kit[w] = itm;
+  }
+  __syncthreads();
+  int base = 0;
+  for (int q = 0; q < w; ++q) base += s_cnt[q];
+  if (threadIdx.x == 0) {
+    const int b = blockIdx.x;
+    a.blk_cnt[b] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    const int ne = s_enc[0] + s_enc[1] + s_enc[2] + s_enc[3];
+    a.blk_enc[b] = ne;
+    a.blk_enc_tot[b] += (unsigned long long)ne;
+    a.blk_kit[b] = max(a.blk_kit[b], max(max(s_kit[0], s_kit[1]), max(s_kit[2], s_kit[3])));
   }
   if (listed) {
-    const int64_t pos = base + (int)lanemask_count_tp(lm);
-    if (pos < a.cap) {
-      a.bs_idx[pos] = (int)k;
-      a.bs_mask[pos] = emask;
-      a.bs_rct[pos] = rct;
-      a.bs_y[pos] = xm0;
-      a.bs_y[a.cap + pos] = ym0;
-      a.bs_y[2 * a.cap + pos] = zm0;
-      a.bs_y[3 * a.cap + pos] = vxm;
-      a.bs_y[4 * a.cap + pos] = vym;
-      a.bs_y[5 * a.cap + pos] = vzm;
-    }
+    const int64_t pos = (int64_t)blockIdx.x * 256 + base + (int)lanemask_count_tp(lm);
+    a.bs_idx[pos] = (int)k;
+    a.bs_mask[pos] = emask;
+    a.bs_rct[pos] = rct;
+    a.bs_y[pos] = xm0;
+    a.bs_y[a.cap + pos] = ym0;
+    a.bs_y[2 * a.cap + pos] = zm0;
+    a.bs_y[3 * a.cap + pos] = vxm;
+    a.bs_y[4 * a.cap + pos] = vym;
+    a.bs_y[5 * a.cap + pos] = vzm;
   }
+}
+
+// Exclusive prefix sum of the blocks' list counts (one workgroup of 1024).
+__global__ __launch_bounds__(1024) void k_tp_scan(TpArgs a) {
+  __shared__ int sh[1024];
+  const int t = threadIdx.x;
+  const int64_t chunk = (a.nb + 1023) / 1024;
+  const int64_t lo = min(a.nb, t * chunk), hi = min(a.nb, lo + chunk);
+  int sum = 0;
+  for (int64_t b = lo; b < hi; ++b) sum += a.blk_cnt[b];
+  sh[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = t >= o ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  int run = sh[t] - sum;
+  for (int64_t b = lo; b < hi; ++b) {
+    a.blk_off[b] = run;
+    run += a.blk_cnt[b];
+  }
+  if (t == 1023) a.blk_off[a.nb] = sh[1023];
+}
+
+// List entry of the d-th listed particle: the block whose region holds it
+// (largest b with blk_off[b] <= d), then the slot inside the region.
+__device__ __forceinline__ int64_t tp_entry(const TpArgs& a, int64_t d) {
+  int64_t lo = 0, hi = a.nb;  // blk_off[lo] <= d < blk_off[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a.blk_off[mid] <= d) lo = mid;
+    else hi = mid;
+  }
+  return lo * 256 + (d - a.blk_off[lo]);
 }
 
 // One wave per listed particle: its group is the particle (member 0) and the
@@ -259,14 +322,245 @@ __device__ void tp_remove(const TpArgs& a, int64_t e, unsigned em, int cb, long 
   a.mask[k] = 0u;
 }
 
+// ---- the whole-step BS attempt of a particle meeting one planet -------------
+// Table per planet j (kPlStride doubles): the planet's positions after each
+// midpoint substep of column k (k = 0..7, n_k = 2(k+1) substeps, column k at
+// offset 3 k (k+1)), then its extrapolated state T[k][k] (6 per column), then
+// its error estimate per column.
+constexpr int kPlPos = 3 * 72;
+constexpr int kPlDiag = kPlPos;
+constexpr int kPlErr = kPlDiag + 48;
+constexpr int kPlStride = kPlErr + 8;
+
+// Star-only derivative of a planet's state.
+__device__ __forceinline__ void star_acc(double Gm0, double x, double y, double z, double& ax,
+                                         double& ay, double& az) {
+  const double ir = rsqrt_nr(x * x + y * y + z * z);
+  const double fs = -Gm0 * (ir * ir * ir);
+  ax = fs * x;
+  ay = fs * y;
+  az = fs * z;
+}
+
+// One thread per (planet, column): the planet's Gragg sequence over the whole
+// step from its pre-drift state; then one thread per planet extrapolates.
+__global__ __launch_bounds__(256) void k_tp_plan(TpArgs a) {
+  __shared__ double sT0[kTpMaxPlanets * 8][6];
+  const int j = threadIdx.x >> 3, k = threadIdx.x & 7;
+  if (j < a.nm) {
+    const double4 p = a.ppre[j], q = a.vpre[j];
+    const double y0[6] = {p.x, p.y, p.z, q.x, q.y, q.z};
+    const int n = 2 * (k + 1);
+    const double hs = a.dt / n;
+    double ym[6], yn[6], d[6];
+    star_acc(a.mu, y0[0], y0[1], y0[2], d[3], d[4], d[5]);
+    d[0] = y0[3];
+    d[1] = y0[4];
+    d[2] = y0[5];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      ym[c] = y0[c];
+      yn[c] = y0[c] + hs * d[c];
+    }
+    double* pos = a.pl + (size_t)j * kPlStride + 3 * k * (k + 1);
+    for (int m = 1; m <= n; ++m) {
+      pos[3 * (m - 1) + 0] = yn[0];
+      pos[3 * (m - 1) + 1] = yn[1];
+      pos[3 * (m - 1) + 2] = yn[2];
+      star_acc(a.mu, yn[0], yn[1], yn[2], d[3], d[4], d[5]);
+      d[0] = yn[3];
+      d[1] = yn[4];
+      d[2] = yn[5];
+      if (m < n) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const double t = ym[c] + 2.0 * hs * d[c];
+          ym[c] = yn[c];
+          yn[c] = t;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sT0[threadIdx.x][c] = 0.5 * (ym[c] + yn[c] + hs * d[c]);
+  }
+  __syncthreads();
+  if (threadIdx.x < a.nm) {
+    const int jj = threadIdx.x;
+    double R[8][6];
+    double* tab = a.pl + (size_t)jj * kPlStride;
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      double cur[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) cur[c] = sT0[jj * 8 + kk][c];
+#pragma unroll
+      for (int jn = 1; jn <= kk; ++jn) {
+        const double ratio = (double)(2 * (kk + 1)) / (double)(2 * (kk - jn + 1));
+        const double den = ratio * ratio - 1.0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const double old = R[jn - 1][c];
+          R[jn - 1][c] = cur[c];
+          cur[c] = cur[c] + (cur[c] - old) / den;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        R[kk][c] = cur[c];
+        tab[kPlDiag + 6 * kk + c] = cur[c];
+      }
+      tab[kPlErr + kk] =
+          kk == 0 ? 0.0 : fmax(relerr3(R[kk], R[kk - 1]), relerr3(R[kk] + 3, R[kk - 1] + 3));
+    }
+  }
+}
+
+// Particle derivative in its group with planet position (qx, qy, qz).
+struct PairK {
+  double Gm, rcij, i09;
+};
+__device__ __forceinline__ void tp_pair_acc(double Gm0, const PairK& Q, double x, double y,
+                                            double z, double qx, double qy, double qz,
+                                            double& ax, double& ay, double& az) {
+  const double ir = rsqrt_nr(x * x + y * y + z * z);
+  const double fs = -Gm0 * (ir * ir * ir);
+  ax = fs * x;
+  ay = fs * y;
+  az = fs * z;
+  const double dx = qx - x, dy = qy - y, dz = qz - z;
+  const double q2 = dx * dx + dy * dy + dz * dz;
+  const double iq = rsqrt_nr(q2);
+  const double iq2 = iq * iq;
+  double K = 1.0, dK = 0.0;
+  if (Q.rcij > 0.0) changeover_clamped(q2 * iq, Q.rcij, Q.i09, K, dK);
+  const double sc = Q.Gm * ((1.0 - K) * iq2 * iq + dK * iq2);
+  ax += sc * dx;
+  ay += sc * dy;
+  az += sc * dz;
+}
+
+__global__ __launch_bounds__(256) void k_tp_bs1(TpArgs a) {
+  const int64_t nl = a.blk_off[a.nb];
+  const double P2x = a.st->P2[0], P2y = a.st->P2[1], P2z = a.st->P2[2];
+  unsigned long long nsub = 0;
+  for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < nl;
+       d += (int64_t)gridDim.x * 256) {
+    const int64_t e = tp_entry(a, d);
+    const unsigned em = a.bs_mask[e];
+    if (__popc(em) != 1) continue;  // several planets: the wave path
+    const int j = __ffs(em) - 1;
+    const double rct = a.bs_rct[e];
+    PairK Q;
+    Q.Gm = a.G * a.px0[j].w;
+    Q.rcij = fmax(rct, a.rc[j]);
+    Q.i09 = Q.rcij > 0.0 ? 1.0 / (0.9 * Q.rcij) : 0.0;
+    const double* tab = a.pl + (size_t)j * kPlStride;
+    const double4 pp = a.ppre[j];
+    double y0[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) y0[c] = a.bs_y[c * a.cap + e];
+    double f0[6];
+    tp_pair_acc(a.mu, Q, y0[0], y0[1], y0[2], pp.x, pp.y, pp.z, f0[3], f0[4], f0[5]);
+    f0[0] = y0[3];
+    f0[1] = y0[4];
+    f0[2] = y0[5];
+    double R[8][6];
+    int kacc = -1;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (kacc < 0) {
+        const int n = 2 * (k + 1);
+        const double hs = a.dt / n;
+        double ym[6], yn[6], dd[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          ym[c] = y0[c];
+          yn[c] = y0[c] + hs * f0[c];
+        }
+        const double* pos = tab + 3 * k * (k + 1);
+        for (int m = 1; m <= n; ++m) {
+          tp_pair_acc(a.mu, Q, yn[0], yn[1], yn[2], pos[3 * (m - 1)], pos[3 * (m - 1) + 1],
+                      pos[3 * (m - 1) + 2], dd[3], dd[4], dd[5]);
+          dd[0] = yn[3];
+          dd[1] = yn[4];
+          dd[2] = yn[5];
+          if (m < n) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+              const double t = ym[c] + 2.0 * hs * dd[c];
+              ym[c] = yn[c];
+              yn[c] = t;
+            }
+          }
+        }
+        double cur[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) cur[c] = 0.5 * (ym[c] + yn[c] + hs * dd[c]);
+#pragma unroll
+        for (int jn = 1; jn <= k; ++jn) {
+          const double ratio = (double)(2 * (k + 1)) / (double)(2 * (k - jn + 1));
+          const double den = ratio * ratio - 1.0;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            const double old = R[jn - 1][c];
+            R[jn - 1][c] = cur[c];
+            cur[c] = cur[c] + (cur[c] - old) / den;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) R[k][c] = cur[c];
+        if (k >= 1) {
+          const double err = fmax(fmax(relerr3(R[k], R[k - 1]), relerr3(R[k] + 3, R[k - 1] + 3)),
+                                  tab[kPlErr + k]);
+          if (err <= a.tol) kacc = k;
+        }
+      }
+    }
+    if (kacc < 0) continue;  // refinement needed: the wave path
+    double y1[6];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k == kacc) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) y1[c] = R[k][c];
+      }
+    ++nsub;
+    const int64_t ip = a.bs_idx[e];
+    const double Rs = a.rad[kTpMaxPlanets + ip] + a.rad[j];
+    bool hit = false;
+    if (Rs > 0.0) {
+      const double4 pv = a.vpre[j];
+      const double* q1 = tab + kPlDiag + 6 * kacc;
+      const double d2 = hermite_dmin2(a.dt, pp.x - y0[0], pp.y - y0[1], pp.z - y0[2],
+                                      pv.x - y0[3], pv.y - y0[4], pv.z - y0[5],
+                                      q1[0] - y1[0], q1[1] - y1[1], q1[2] - y1[2],
+                                      q1[3] - y1[3], q1[4] - y1[4], q1[5] - y1[5]);
+      hit = d2 < Rs * Rs;
+    }
+    if (hit) {
+      tp_remove(a, e, em, 1, 0, y0);
+    } else {
+      tp_finish(a, ip, y1[0], y1[1], y1[2], y1[3], y1[4], y1[5], rct, P2x, P2y, P2z);
+    }
+    a.bs_mask[e] = 0u;  // done
+  }
+  for (int o = 32; o > 0; o >>= 1) nsub += __shfl_xor(nsub, o, 64);
+  __shared__ unsigned long long s_sub[4];
+  if ((threadIdx.x & 63) == 0) s_sub[threadIdx.x >> 6] = nsub;
+  __syncthreads();
+  if (threadIdx.x == 0) a.sub[blockIdx.x] += s_sub[0] + s_sub[1] + s_sub[2] + s_sub[3];
+}
+
 __global__ __launch_bounds__(64) void k_tp_bs(TpArgs a) {
   __shared__ double mm[kBsPar], mrc[kBsPar];
   const int lane = threadIdx.x;
-  const int64_t nl = __builtin_amdgcn_readfirstlane((int)min((int64_t)a.st->tp_nbs, a.cap));
+  const int64_t nl = a.blk_off[a.nb];
   long long nsub = 0;
   const double P2x = a.st->P2[0], P2y = a.st->P2[1], P2z = a.st->P2[2];
-  for (int64_t e = blockIdx.x; e < nl; e += gridDim.x) {
+  for (int64_t d = blockIdx.x; d < nl; d += gridDim.x) {
+    const int64_t e = tp_entry(a, d);
     const unsigned em = a.bs_mask[e];
+    if (em == 0u) continue;  // finished by the whole-step attempt
     const int sz = 1 + __popc(em);
     const double rct = a.bs_rct[e];
     if (sz > kBsPar) {
@@ -303,7 +597,7 @@ __global__ __launch_bounds__(64) void k_tp_bs(TpArgs a) {
       tp_finish(a, a.bs_idx[e], y[0], y[1], y[2], y[3], y[4], y[5], rct, P2x, P2y, P2z);
     }
   }
-  if (lane == 0 && nsub > 0) atomicAdd(&a.st->bs_sub, (unsigned long long)nsub);
+  if (lane == 0 && nsub > 0) a.sub[kTpBs1Grid + blockIdx.x] += (unsigned long long)nsub;
 }
 
 // Rows [nm, nm + ntp) of the caller's n x 3 arrays into SoA; heliocentric
@@ -417,8 +711,16 @@ TpArgs tp_args(const MassiveWs& w, const TpWs& t, const StepConsts& c) {
   a.bs_y = t.bs_y;
   a.rad = t.rad;
   a.coll = t.coll;
+  a.blk_cnt = t.blk_cnt;
+  a.blk_off = t.blk_off;
+  a.blk_enc = t.blk_enc;
+  a.blk_enc_tot = t.blk_enc_tot;
+  a.blk_kit = t.blk_kit;
+  a.sub = t.sub;
+  a.pl = t.pl;
   a.ntp = t.ntp;
-  a.cap = t.ntp;
+  a.cap = t.cap;
+  a.nb = t.nb;
   a.nm = w.n;
   a.nblk = w.nblk;
   a.enc_free = c.encounter_free;
@@ -440,7 +742,10 @@ TpArgs tp_args(const MassiveWs& w, const TpWs& t, const StepConsts& c) {
 
 size_t tp_carve(TpWs& t, int64_t ntp, void* base) {
   t.ntp = ntp;
+  t.nb = std::max<int64_t>((ntp + 255) / 256, 1);
+  t.cap = t.nb * 256;  // one 256-entry region of the list per block
   const size_t n = (size_t)std::max<int64_t>(ntp, 1);
+  const size_t nc = (size_t)t.cap, nb = (size_t)t.nb;
   size_t off = 0;
   auto take = [&](size_t sz) -> void* {
     const size_t o = off;
@@ -450,13 +755,52 @@ size_t tp_carve(TpWs& t, int64_t ntp, void* base) {
   t.x = (double*)take(3 * n * sizeof(double));
   t.v = (double*)take(3 * n * sizeof(double));
   t.mask = (unsigned*)take(n * sizeof(unsigned));
-  t.bs_idx = (int*)take(n * sizeof(int));
-  t.bs_mask = (unsigned*)take(n * sizeof(unsigned));
-  t.bs_rct = (double*)take(n * sizeof(double));
-  t.bs_y = (double*)take(6 * n * sizeof(double));
+  t.bs_idx = (int*)take(nc * sizeof(int));
+  t.bs_mask = (unsigned*)take(nc * sizeof(unsigned));
+  t.bs_rct = (double*)take(nc * sizeof(double));
+  t.bs_y = (double*)take(6 * nc * sizeof(double));
   t.rad = (double*)take((kTpMaxPlanets + n) * sizeof(double));
   t.coll = (CollRec*)take(n * sizeof(CollRec));
+  t.blk_cnt = (int*)take(nb * sizeof(int));
+  t.blk_off = (int*)take((nb + 1) * sizeof(int));
+  t.blk_enc = (int*)take(nb * sizeof(int));
+  // cumulative counters, cleared at init: enc totals, Kepler maxima, substeps
+  t.cum = base ? (char*)base + off : nullptr;
+  const size_t cum0 = off;
+  t.blk_enc_tot = (unsigned long long*)take(nb * sizeof(unsigned long long));
+  t.blk_kit = (int*)take(nb * sizeof(int));
+  t.sub = (unsigned long long*)take(kTpSubSlots * sizeof(unsigned long long));
+  t.cum_bytes = off - cum0;
+  t.pl = (double*)take((size_t)kTpMaxPlanets * kPlStride * sizeof(double));
   return off;
+}
+
+hipError_t tp_read_counters(const TpWs& t, TpCounters* h, hipStream_t s) {
+  h->enc = 0;
+  h->enc_total = 0;
+  h->kit = 0;
+  h->sub = 0;
+  if (t.ntp <= 0) return hipSuccess;
+  std::vector<int> enc(t.nb), kit(t.nb);
+  std::vector<unsigned long long> tot(t.nb), sub(kTpSubSlots);
+  hipError_t e = hipMemcpyAsync(enc.data(), t.blk_enc, t.nb * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(kit.data(), t.blk_kit, t.nb * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(tot.data(), t.blk_enc_tot, t.nb * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sub.data(), t.sub, kTpSubSlots * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  for (int64_t b = 0; b < t.nb; ++b) {
+    h->enc += enc[b];
+    h->enc_total += tot[b];
+    h->kit = std::max(h->kit, kit[b]);
+  }
+  for (int q = 0; q < kTpSubSlots; ++q) h->sub += sub[q];
+  return hipSuccess;
 }
 
 hipError_t tp_validate(const TpWs& t, int nm, const double* x, const double* v, int* dbad,
@@ -500,9 +844,13 @@ hipError_t tp_prime(const MassiveWs& w, const TpWs& t, const StepConsts& c, hipS
 hipError_t tp_step(const MassiveWs& w, const TpWs& t, const StepConsts& c, hipStream_t s) {
   if (t.ntp <= 0) return hipSuccess;
   TpArgs a = tp_args(w, t, c);
-  hipLaunchKernelGGL(k_tp_main, dim3(ceil_div64(t.ntp, 256)), dim3(256), 0, s, a);
-  if (!c.encounter_free)
-    hipLaunchKernelGGL(k_tp_bs, dim3(2048), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_tp_main, dim3((unsigned)t.nb), dim3(256), 0, s, a);
+  if (!c.encounter_free) {
+    hipLaunchKernelGGL(k_tp_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_tp_plan, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_tp_bs1, dim3(kTpBs1Grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_tp_bs, dim3(kTpBsGrid), dim3(64), 0, s, a);
+  }
   return hipGetLastError();
 }
 
