@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -106,6 +108,98 @@ def tp_measure(G, W, torch, steps: int, ntp: int = 1_000_000):
             "removed": st["tp_removed"]}
 
 
+def batch_measure(G, W, torch, steps: int, cpu: bool):
+    """Batched mode: 4096 independent systems of 2..32 bodies (Sec. 3.4), all
+    steps in one captured launch; the tuner's table comes from init."""
+    off, m0s, m, x, u = W.batched()
+    sim = G.BatchedSimulation(off, m0s, m, x, u, G.default_params())
+    times, choice = sim.tune(4)
+    sim.step(2)
+    sim.check()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sim.check()
+    sec = e0.elapsed_time(e1) / 1e3
+    st = sim.stats()
+    sim.close()
+    nsys = len(off) - 1
+    sizes = np.diff(off)
+    out = {"workload": f"batched_{nsys}_systems_2_32", "systems": nsys, "bodies": int(off[-1]),
+           "steps": steps, "launches": 1, "ms_per_step": sec * 1e3 / steps,
+           "system_steps_per_s": nsys * steps / sec,
+           "pair_interactions_per_s": float((sizes * (sizes - 1)).sum()) * steps / sec,
+           "tuner": {"choice": choice, "us_per_variant_4_steps": times},
+           "enc_total": st["enc_total"], "bs_substeps": st["bs_substeps"],
+           "max_group_last_step": st["max_group"]}
+    if cpu:  # CPU baseline leg: the oracle on a sample of the same systems
+        import oracle as O
+        t0 = time.perf_counter()
+        ns, nst = 64, 20
+        v = np.concatenate([O.helio_to_dem(O.params(), m[off[k]:off[k + 1]], u[off[k]:off[k + 1]])
+                            for k in range(ns)])
+        O.batched_run(O.params(), off[:ns + 1], m0s[:ns], m[:off[ns]], x[:off[ns]], v, nst)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"system_steps_per_s": ns * nst / dt, "sample": f"first {ns} systems x {nst} steps",
+                             "cores": 1}
+    return out
+
+
+def adjoint_measure(G, W, torch, steps: int, ckpt: int = 32):
+    """Adjoint of the encounter-free map: 1024 systems x 8 planets, a
+    checkpoint every 32 steps.  Ratio = backward (segment recompute + VJP)
+    over the plain forward of the same packed kernel (one checkpoint)."""
+    m, x, u = W.adjoint_systems()
+    nsys = m.shape[0]
+    off = np.arange(0, 8 * nsys + 1, 8, dtype=np.int32)
+    gp = G.default_params(encounter_free=1)
+    sim = G.BatchedSimulation(off, np.ones(nsys), m.reshape(-1), x.reshape(-1, 3),
+                              u.reshape(-1, 3), gp, coords="helio")
+    xd, vd = sim.state("dem")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    rng = np.random.default_rng(1)
+    gx = torch.tensor(rng.standard_normal((8 * nsys, 3)), device="cuda")
+    gv = torch.zeros_like(gx)
+    sim.adj_forward(steps, steps)            # warm-up, one checkpoint
+    sim.set_state(xd, vd, coords="dem")
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    sim.adj_forward(steps, steps)            # plain forward (same kernel)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    sim.set_state(xd, vd, coords="dem")
+    torch.cuda.synchronize()
+    ev[2].record(stream)
+    sim.adj_forward(steps, ckpt)             # forward keeping checkpoints
+    ev[3].record(stream)
+    sim.adj_backward(gx, gv)                 # recompute + VJP
+    ev[4].record(stream)
+    torch.cuda.synchronize()
+    sim.check()
+    sim.set_state(xd, vd, coords="dem")
+    torch.cuda.synchronize()
+    ev[5].record(stream)
+    sim.step(steps)                          # the general batched kernel, same work
+    ev[6].record(stream)
+    torch.cuda.synchronize()
+    sim.check()
+    fwd = ev[0].elapsed_time(ev[1])
+    fck = ev[2].elapsed_time(ev[3])
+    bwd = ev[3].elapsed_time(ev[4])
+    gen = ev[5].elapsed_time(ev[6])
+    sim.close()
+    return {"workload": f"adjoint_{nsys}x8_encounter_free", "steps": steps, "ckpt_every": ckpt,
+            "forward_ms": fwd, "forward_ckpt_ms": fck, "backward_ms": bwd,
+            "adjoint_forward_ratio": bwd / fwd, "forward_plus_backward_ratio": (fck + bwd) / fwd,
+            "general_batched_kernel_ms": gen,
+            "system_steps_per_s_forward": nsys * steps / (fwd / 1e3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +212,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tp-steps", type=int, default=100,
                     help="steps of the 10^6-particle run reported under extra (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=1000,
+                    help="steps of the 4096-system batched run reported under extra (0: skip)")
+    ap.add_argument("--adj-steps", type=int, default=1000,
+                    help="steps of the 1024 x 8 adjoint run reported under extra (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed region run one 256 MiB device copy (counter scale)")
     args = ap.parse_args()
@@ -175,6 +273,10 @@ def main():
     extra = {}
     if args.tp_steps > 0:
         extra["test_particles"] = tp_measure(G, W, torch, args.tp_steps)
+    if args.batch_steps > 0:
+        extra["batched"] = batch_measure(G, W, torch, args.batch_steps, not args.no_cpu)
+    if args.adj_steps > 0:
+        extra["adjoint"] = adjoint_measure(G, W, torch, args.adj_steps)
 
     if args.calib_copy:
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")

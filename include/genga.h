@@ -82,7 +82,7 @@ enum {
     GENGA_EOVERFLOW = -3,   /* candidate / encounter list capacity exceeded */
     GENGA_EKEPLER = -4,     /* universal Kepler iteration did not converge  */
     GENGA_EBS = -5,         /* Bulirsch-Stoer depth exhausted               */
-    GENGA_EADJ_ENCOUNTER = -6,
+    GENGA_EADJ_ENCOUNTER = -6, /* pair inside r_crit in the K = 1 adjoint map */
     GENGA_ENOMEM = -7,      /* workspace smaller than genga_workspace_bytes */
     GENGA_EGROUP = -8       /* encounter group larger than supported        */
 };
@@ -96,16 +96,24 @@ void genga_params_default(genga_params *p);
 /* Device workspace (bytes) a context of this shape needs.  Main mode:
  * n_massive <= 2048 bodies with encounters (the paper's main-mode limit,
  * Sec. 3), <= 65536 with encounter_free, n_test = 0.  Test-particle mode:
- * 1 <= n_massive <= 32 (Sec. 3.3), 0 <= n_test <= 2^30.  Returns 0 for an
- * unsupported shape or invalid parameters. */
+ * 1 <= n_massive <= 32 (Sec. 3.3), 0 <= n_test <= 2^30.  Batched mode:
+ * 1 <= n_sys <= 2^24 systems of 1..64 bodies, n_bodies in all (n_massive and
+ * n_test unused).  Returns 0 for an unsupported shape or invalid parameters. */
 size_t genga_workspace_bytes(int mode, const genga_params *p, int n_massive,
                              int64_t n_test, int n_sys, int64_t n_bodies);
 
 /* Create a context and load the initial state (Sec. 2.2: the first opening
  * kick is prepared here, from the initial positions).
- *   mode        GENGA_MASSIVE (main mode) or GENGA_TEST (test-particle mode,
+ *   mode        GENGA_MASSIVE (main mode), GENGA_TEST (test-particle mode,
  *               Sec. 3.3: n_massive bodies take the main-mode step and n_test
- *               massless particles feel them, but nothing else).
+ *               massless particles feel them, but nothing else) or
+ *               GENGA_BATCH (Sec. 3.4: n_sys independent systems, each with
+ *               its own central mass; system s holds rows
+ *               [d_offsets[s], d_offsets[s+1]) of every array).
+ *   d_offsets   batched mode: n_sys + 1 int32 (device, read once): 0, then
+ *               increasing, each system 1..64 bodies.
+ *   d_m0        batched mode: n_sys central masses (device, read once), or
+ *               NULL for p->m0 everywhere.
  *   d_m         n_massive masses (device, read once).
  *   d_x, d_v    (n_massive + n_test) x 3 positions and velocities (device,
  *               read once): the massive bodies' rows first, then the
@@ -118,9 +126,11 @@ size_t genga_workspace_bytes(int mode, const genga_params *p, int n_massive,
  *   d_workspace at least genga_workspace_bytes bytes of device memory, 256-B
  *               aligned, owned by the caller, used until genga_destroy.
  *   stream      hipStream_t of the caller (NULL = default stream).
- * Synchronises once (validation of the input).  Errors: EINVAL (shape, NaN
- * or Inf in the input, non-positive m0), ENOMEM (workspace too small), EHIP.
- * n_sys, d_offsets, d_m0 are reserved for the batched mode; pass 0 / NULL. */
+ * Synchronises (validation of the input; batched mode also runs the tuner
+ * of genga_tune for 4 steps on a copy of the state).  Errors: EINVAL (shape,
+ * NaN or Inf in the input, non-positive m0, bad offsets), ENOMEM (workspace
+ * too small), EHIP.  n_sys, d_offsets, d_m0 are for the batched mode only;
+ * pass 0 / NULL otherwise; n_massive and n_test are 0 in batched mode. */
 int genga_init(genga_ctx **ctx, int mode, const genga_params *p,
                int n_massive, int64_t n_test, int n_sys,
                const int32_t *d_offsets, const double *d_m0,
@@ -170,9 +180,10 @@ int genga_energy(genga_ctx *ctx, double *d_E, double *d_L);
 int genga_accel_state(genga_ctx *ctx, double *d_acc);
 
 /* Confirmed close-encounter pairs of the last step (the Encounter kernel
- * output, Sec. 3.2.4): i < j body indices in h_ij (2 per pair), the Hermite
- * minimum squared separation in h_dmin2 and r_crit,ij^2 in h_rc2 (either
- * may be NULL), sorted by (i, j).  *h_n receives the count; if it exceeds cap,
+ * output, Sec. 3.2.4): i < j body indices in h_ij (2 per pair; rows of the
+ * whole state in batched mode), the Hermite minimum squared separation in
+ * h_dmin2 and r_crit,ij^2 in h_rc2 (either may be NULL; NaN in batched
+ * mode), sorted by (i, j).  *h_n receives the count; if it exceeds cap,
  * cap pairs are written and GENGA_EOVERFLOW is returned.  Synchronising. */
 int genga_encounters(genga_ctx *ctx, int32_t *h_ij, double *h_dmin2,
                      double *h_rc2, int cap, int *h_n);
@@ -204,6 +215,46 @@ int genga_set_radii(genga_ctx *ctx, const double *d_radii);
 int genga_collisions(genga_ctx *ctx, int64_t *h_tp, int32_t *h_planet,
                      int64_t *h_step, double *h_frac, double *h_xv,
                      int64_t cap, int64_t *h_n);
+
+/* Batched mode: time each kernel variant (register budget per wave: 1, 2 or
+ * 4 waves per SIMD; systems handed out in index order or largest first) for
+ * nsteps steps on a copy of the current state, with HIP events on the
+ * context's stream, and keep the fastest for later steps.  h_us (host, cap
+ * doubles) receives each variant's time in microseconds, *h_n the number of
+ * variants (6), *h_choice the variant kept.  The state is not advanced.
+ * Synchronising.  Errors: EINVAL (other mode), EOVERFLOW (cap < 6), EHIP. */
+int genga_tune(genga_ctx *ctx, int nsteps, double *h_us, int cap, int *h_n,
+               int *h_choice);
+
+/* Description of tuner variant v (static storage). */
+const char *genga_tune_variant(int v);
+
+/* ---- reverse-mode gradient of the encounter-free map ----------------------
+ * For a batched context created with encounter_free = 1: the map with K = 1
+ * (the MVS map in democratic coordinates, Sec. 2.1; kick tau/2, Sun kick
+ * tau/2, Kepler drift tau, Sun kick tau/2, kick tau/2).  The paper has no
+ * adjoint; this one differentiates that map exactly (up to rounding). */
+
+/* Bytes of the caller's buffer for nsteps steps with a checkpoint every
+ * ckpt_every steps (the checkpoints plus one segment's tape); 0 when the
+ * context is not a batched encounter-free one or the arguments are invalid. */
+size_t genga_adj_buffer_bytes(genga_ctx *ctx, int64_t nsteps, int ckpt_every);
+
+/* Advance every system nsteps steps of the encounter-free map, keeping the
+ * state every ckpt_every steps in d_buffer (device, 256-B aligned, caller-
+ * owned, at least genga_adj_buffer_bytes; it must stay untouched until the
+ * matching genga_adj_backward).  Asynchronous.  A pair that comes inside its
+ * critical radius (Eq. 6) latches GENGA_EADJ_ENCOUNTER (the hybrid method
+ * would no longer use K = 1 there).  Errors: EINVAL, ENOMEM, EHIP. */
+int genga_adj_forward(genga_ctx *ctx, int64_t nsteps, int ckpt_every,
+                      void *d_buffer, size_t buffer_bytes);
+
+/* Gradients through the last genga_adj_forward: given dL/dx_T and dL/dv_T
+ * (device, rows x 3, democratic coordinates) write dL/dx_0, dL/dv_0 (rows x
+ * 3) and dL/dm (rows) of the state before it.  Recomputes each segment from
+ * its checkpoint (the state is not changed).  Asynchronous. */
+int genga_adj_backward(genga_ctx *ctx, const double *d_gxT, const double *d_gvT,
+                       double *d_gx0, double *d_gv0, double *d_gm);
 
 /* Counters of the run (h_stats host).  Synchronising. */
 int genga_stats(genga_ctx *ctx, genga_stats_t *h_stats);

@@ -1,0 +1,566 @@
+// Batched independent systems (Sec. 3.4): each system has its own central
+// mass and 1..64 bodies; systems never interact.  One wave integrates one
+// system, one lane per body, and runs every requested step inside a single
+// launch with the state held in registers (the method's step of Sec. 2.2,
+// as in main mode, with each system's own central mass):
+//   radii (Eq. 6), opening kick (Eq. 2 gradient, every pair), Sun kick,
+//   Kepler drift (Eq. 9), Hermite test of the prechecker's candidates
+//   (Eqs. 10-12), groups (connected components, App. A), BS of each group
+//   from the pre-drift state (Sec. 3.2.6), Sun kick, closing kick and the
+//   next candidates.
+// Partner data moves by lane reads (readlane / bpermute), so the only memory
+// traffic of a run is loading and storing the state once.  The tuner picks,
+// by timing the real systems, the register budget per wave (occupancy) and
+// the order in which systems are handed to waves.
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "bs_device.h"
+#include "device_math.h"
+#include "genga_impl.h"
+
+namespace genga {
+namespace {
+
+constexpr size_t kBsRDoubles = (size_t)kBsCols * 6 * 64;  // one sequential-BS tableau
+
+struct BatchArgs {
+  double4* __restrict__ xm;                 // [nb] x, y, z, m (democratic)
+  double4* __restrict__ vv;                 // [nb] vx, vy, vz, 0
+  unsigned long long* __restrict__ cand;    // [nb] candidate partners (local bits)
+  unsigned long long* __restrict__ encm;    // [nb] encounters j > i of the last step
+  const int* __restrict__ off;              // [nsys + 1]
+  const double* __restrict__ m0;            // [nsys]
+  const int* __restrict__ order;            // [nsys] systems in hand-out order
+  BatchSysStat* __restrict__ ss;            // [nsys]
+  unsigned* __restrict__ flags;             // latched error bits
+  double* __restrict__ rbuf;                // BS tableaux of groups over 8 members
+  const int* __restrict__ rslot;            // [nsys] slice of rbuf (systems over 8 bodies)
+  int nsys, nsteps;
+  double G, dt, h, absdt, n1, n2, pf2, tol;
+  int max_depth, max_iter, enc_free;
+};
+
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int l) {
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, l);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Pair acceleration of H_B (Eq. 2 gradient) on the lane's body from every
+// other body of the system; with want_cand, also the partners inside the
+// prechecker radius pf r_crit,ij (Sec. 2.2).  rc = 0 everywhere gives the
+// Newtonian pair sum (K = 1, the encounter-free map).
+__device__ __forceinline__ void sys_kick(int n, int lane, double x, double y, double z, double m,
+                                         double rc, double G, double pf2, bool want_cand,
+                                         double& ax, double& ay, double& az,
+                                         unsigned long long& cand) {
+  ax = ay = az = 0.0;
+  cand = 0ull;
+  for (int j = 0; j < n; ++j) {
+    const double xj = readlane_d(x, j), yj = readlane_d(y, j), zj = readlane_d(z, j);
+    const double mj = readlane_d(m, j), rcj = readlane_d(rc, j);
+    if (j != lane) {
+      const double dx = xj - x, dy = yj - y, dz = zj - z;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double ir = rsqrt_nr(r2);
+      const double ir2 = ir * ir;
+      const double rcij = fmax(rc, rcj);
+      const double r = r2 * ir;
+      double K = 1.0, dK = 0.0;
+      if (r < rcij) changeover(r, rcij, K, dK);
+      const double s = mj * (K * ir2 * ir - dK * ir2);
+      ax += s * dx;
+      ay += s * dy;
+      az += s * dz;
+      if (want_cand && r2 < pf2 * rcij * rcij) cand |= 1ull << j;
+    }
+  }
+  ax *= G;
+  ay *= G;
+  az *= G;
+}
+
+// The b-th lowest set bit of M (b < popc(M)).
+__device__ __forceinline__ int nth_bit(unsigned long long M, int b) {
+  for (int t = 0; t < b; ++t) M &= M - 1ull;
+  return __ffsll((long long)M) - 1;
+}
+
+// One group of sz <= 8 members (mask M) with the column-parallel BS; mm and
+// mrc are this wave's LDS arrays.  Returns the BS status; on return every
+// member lane's pre-drift state pre[] has been replaced by its result.
+template <int P>
+__device__ __forceinline__ int group_par(const BatchArgs& a, int sz, unsigned long long M,
+                                         double pre[6], double m, double rc, double Gm0,
+                                         double* mm, double* mrc, long long* nsub) {
+  const int lane = threadIdx.x & 63;
+  const int b = lane % P;
+  const int body = b < sz ? nth_bit(M, b) : 0;
+  double y[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) y[c] = __shfl(pre[c], body, 64);
+  if (b >= sz) {
+    y[0] = 1.0;
+    y[1] = y[2] = y[3] = y[4] = y[5] = 0.0;
+  }
+  const double mb = __shfl(m, body, 64), rcb = __shfl(rc, body, 64);
+  __syncthreads();
+  if (lane < sz) {
+    mm[lane] = mb;
+    mrc[lane] = rcb;
+  }
+  __syncthreads();
+  const int r = bs_group<P, false>(sz, y, mm, mrc, a.dt, a.G, Gm0, a.tol, a.max_depth, nsub);
+  const int rank = __popcll(M & ((1ull << lane) - 1ull));
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const double t = __shfl(y[c], rank, 64);
+    if ((M >> lane) & 1ull) pre[c] = t;
+  }
+  return r;
+}
+
+// Groups of 9..64 members: lane = member, the sequential BS with its
+// extrapolation tableau in this system's slice R of the workspace.
+__device__ __forceinline__ int group_seq(const BatchArgs& a, int sz, unsigned long long M,
+                                         double pre[6], double m, double rc, double Gm0,
+                                         double (*R)[6][64], long long* nsub) {
+  const int lane = threadIdx.x & 63;
+  const int body = lane < sz ? nth_bit(M, lane) : 0;
+  double y[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) y[c] = __shfl(pre[c], body, 64);
+  double mb = __shfl(m, body, 64), rcb = __shfl(rc, body, 64);
+  if (lane >= sz) {
+    y[0] = 1.0;
+    y[1] = y[2] = y[3] = y[4] = y[5] = 0.0;
+    mb = 0.0;
+    rcb = 0.0;
+  }
+  const int r = bs_integrate(sz, lane, y, a.dt, mb, rcb, a.G, Gm0, a.tol, a.max_depth, R, nsub);
+  const int rank = __popcll(M & ((1ull << lane) - 1ull));
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const double t = __shfl(y[c], rank, 64);
+    if ((M >> lane) & 1ull) pre[c] = t;
+  }
+  return r;
+}
+
+template <int LB>
+__global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
+  __shared__ double mm[kBsPar], mrc[kBsPar];
+  const int lane = threadIdx.x;
+  const int s = a.order[blockIdx.x];
+  const int o = a.off[s];
+  const int n = a.off[s + 1] - o;
+  const bool act = lane < n;
+  const double m0 = a.m0[s];
+  const double Gm0 = a.G * m0;
+  // inactive lanes hold a massless dummy body far from the others
+  double4 p = make_double4(1.0e3 + lane, 0.0, 0.0, 0.0);
+  double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
+  unsigned long long cand = 0ull, enc = 0ull;
+  if (act) {
+    p = a.xm[o + lane];
+    q = a.vv[o + lane];
+    cand = a.cand[o + lane];
+  }
+  double x = p.x, y = p.y, z = p.z, vx = q.x, vy = q.y, vz = q.z;
+  const double m = p.w;
+  long long nsub = 0;
+  unsigned long long enc_total = 0;
+  int kit = 0, nenc = 0, ngrp = 0, maxg = 0;
+  unsigned fl = 0u;
+  for (int step = 0; step < a.nsteps; ++step) {
+    maxg = 0;
+    const double rc =
+        act && !a.enc_free ? rcrit(x, y, z, vx, vy, vz, m, Gm0, m0, a.n1, a.n2, a.absdt) : 0.0;
+    double ax, ay, az;
+    unsigned long long dummy;
+    sys_kick(n, lane, x, y, z, m, rc, a.G, a.pf2, false, ax, ay, az, dummy);
+    vx += a.h * ax;
+    vy += a.h * ay;
+    vz += a.h * az;
+    const double P1x = wave_sum(m * vx), P1y = wave_sum(m * vy), P1z = wave_sum(m * vz);
+    x += a.h * P1x / m0;
+    y += a.h * P1y / m0;
+    z += a.h * P1z / m0;
+    double pre[6] = {x, y, z, vx, vy, vz};
+    if (act) {
+      const int it = kepler_drift(Gm0, a.dt, x, y, z, vx, vy, vz, a.max_iter);
+      if (it < 0) fl |= F_KEPLER;
+      kit = max(kit, abs(it));
+    }
+    // Hermite test of the candidate pairs i < j (Eqs. 10-12)
+    enc = 0ull;
+    const unsigned long long above = lane < 63 ? ~((2ull << lane) - 1ull) : 0ull;
+    const unsigned long long mine = act && !a.enc_free ? (cand & above) : 0ull;
+    unsigned long long pend = mine;
+    for (int o2 = 32; o2 > 0; o2 >>= 1) pend |= __shfl_xor(pend, o2, 64);  // union over lanes
+    while (pend) {
+      const int j = __ffsll((long long)pend) - 1;
+      pend &= pend - 1ull;
+      const double xj = readlane_d(pre[0], j), yj = readlane_d(pre[1], j),
+                   zj = readlane_d(pre[2], j);
+      const double uj = readlane_d(pre[3], j), wj = readlane_d(pre[4], j),
+                   tj = readlane_d(pre[5], j);
+      const double Xj = readlane_d(x, j), Yj = readlane_d(y, j), Zj = readlane_d(z, j);
+      const double Uj = readlane_d(vx, j), Wj = readlane_d(vy, j), Tj = readlane_d(vz, j);
+      const double rcj = readlane_d(rc, j);
+      if ((mine >> j) & 1ull) {
+        const double d2 = hermite_dmin2(a.dt, xj - pre[0], yj - pre[1], zj - pre[2],
+                                        uj - pre[3], wj - pre[4], tj - pre[5], Xj - x, Yj - y,
+                                        Zj - z, Uj - vx, Wj - vy, Tj - vz);
+        const double rcij = fmax(rc, rcj);
+        if (d2 < rcij * rcij) enc |= 1ull << j;
+      }
+    }
+    int ne = __popcll(enc);
+    for (int o2 = 32; o2 > 0; o2 >>= 1) ne += __shfl_xor(ne, o2, 64);
+    nenc = ne;
+    enc_total += (unsigned long long)ne;
+    ngrp = 0;
+    if (ne > 0) {
+      // symmetric adjacency, then minimum-label components (App. A)
+      unsigned long long adj = enc;
+      unsigned long long rows = __ballot(enc != 0ull);
+      while (rows) {
+        const int i2 = __ffsll((long long)rows) - 1;
+        rows &= rows - 1ull;
+        const unsigned long long ei = readlane_u64(enc, i2);
+        if ((ei >> lane) & 1ull) adj |= 1ull << i2;
+      }
+      int lab = lane;
+      bool changed = true;
+      while (changed) {
+        int nl = lab;
+        for (int j = 0; j < n; ++j) {
+          const int lj = __builtin_amdgcn_readlane(lab, j);
+          if (((adj >> j) & 1ull) && lj < nl) nl = lj;
+        }
+        changed = __ballot(nl != lab) != 0ull;
+        lab = nl;
+      }
+      const bool ing = act && adj != 0ull;
+      unsigned long long roots = __ballot(ing && lab == lane);
+      while (roots) {
+        const int r = __ffsll((long long)roots) - 1;
+        roots &= roots - 1ull;
+        const unsigned long long M = __ballot(ing && lab == r);
+        const int sz = __popcll(M);
+        ++ngrp;
+        maxg = max(maxg, sz);
+        int st;
+        if (sz <= 2)
+          st = group_par<2>(a, sz, M, pre, m, rc, Gm0, mm, mrc, &nsub);
+        else if (sz <= 4)
+          st = group_par<4>(a, sz, M, pre, m, rc, Gm0, mm, mrc, &nsub);
+        else if (sz <= kBsPar)
+          st = group_par<8>(a, sz, M, pre, m, rc, Gm0, mm, mrc, &nsub);
+        else
+          st = group_seq(a, sz, M, pre, m, rc, Gm0,
+                         reinterpret_cast<double(*)[6][64]>(a.rbuf + (size_t)a.rslot[s] * kBsRDoubles),
+                         &nsub);
+        if (st != 0) fl |= F_BS;
+      }
+      if (ing) {
+        x = pre[0];
+        y = pre[1];
+        z = pre[2];
+        vx = pre[3];
+        vy = pre[4];
+        vz = pre[5];
+      }
+    }
+    const double P2x = wave_sum(m * vx), P2y = wave_sum(m * vy), P2z = wave_sum(m * vz);
+    x += a.h * P2x / m0;
+    y += a.h * P2y / m0;
+    z += a.h * P2z / m0;
+    sys_kick(n, lane, x, y, z, m, rc, a.G, a.pf2, !a.enc_free, ax, ay, az, cand);
+    vx += a.h * ax;
+    vy += a.h * ay;
+    vz += a.h * az;
+  }
+  if (act) {
+    a.xm[o + lane] = make_double4(x, y, z, m);
+    a.vv[o + lane] = make_double4(vx, vy, vz, 0.0);
+    a.cand[o + lane] = cand;
+    if (a.nsteps > 0) a.encm[o + lane] = enc;
+  }
+  unsigned fall = fl;
+  for (int o2 = 32; o2 > 0; o2 >>= 1) fall |= __shfl_xor(fall, o2, 64);
+  const int kitw = wave_max_i(kit);
+  if (lane == 0 && a.nsteps > 0) {
+    BatchSysStat& t = a.ss[s];
+    t.sub += (unsigned long long)nsub;
+    t.enc_total += enc_total;
+    t.nenc = nenc;
+    t.ngroups = ngrp;
+    t.maxg = maxg;
+    t.kit = max(t.kit, kitw);
+    if (fall) {
+      t.flags |= fall;
+      atomicOr(a.flags, fall);
+    }
+  }
+}
+
+// ---- state conversion, first candidates, energy: one wave per system ------
+__global__ __launch_bounds__(64) void k_batch_pack(const double* __restrict__ m,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ v,
+                                                   const int* __restrict__ off,
+                                                   const double* __restrict__ m0s,
+                                                   double4* __restrict__ xm,
+                                                   double4* __restrict__ vv, int helio,
+                                                   int keep_mass) {
+  const int s = blockIdx.x, lane = threadIdx.x;
+  const int o = off[s], n = off[s + 1] - o;
+  const bool act = lane < n;
+  double mi = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
+  if (act) {
+    mi = keep_mass ? xm[o + lane].w : m[o + lane];
+    ux = v[3 * (o + lane)];
+    uy = v[3 * (o + lane) + 1];
+    uz = v[3 * (o + lane) + 2];
+  }
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  if (helio) {
+    // heliocentric u -> barycentric v = u - sum m u / (m0 + sum m)
+    const double M = wave_sum(mi);
+    const double den = m0s[s] + M;
+    sx = wave_sum(mi * ux) / den;
+    sy = wave_sum(mi * uy) / den;
+    sz = wave_sum(mi * uz) / den;
+  }
+  if (act) {
+    xm[o + lane] = make_double4(x[3 * (o + lane)], x[3 * (o + lane) + 1], x[3 * (o + lane) + 2], mi);
+    vv[o + lane] = make_double4(ux - sx, uy - sy, uz - sz, 0.0);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_batch_unpack(const double4* __restrict__ xm,
+                                                     const double4* __restrict__ vv,
+                                                     const int* __restrict__ off,
+                                                     const double* __restrict__ m0s,
+                                                     double* __restrict__ x,
+                                                     double* __restrict__ v, int helio) {
+  const int s = blockIdx.x, lane = threadIdx.x;
+  const int o = off[s], n = off[s + 1] - o;
+  const bool act = lane < n;
+  double4 p = make_double4(0.0, 0.0, 0.0, 0.0), q = p;
+  if (act) {
+    p = xm[o + lane];
+    q = vv[o + lane];
+  }
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  if (helio) {
+    // barycentric v -> heliocentric u = v + sum m v / m0
+    sx = wave_sum(p.w * q.x) / m0s[s];
+    sy = wave_sum(p.w * q.y) / m0s[s];
+    sz = wave_sum(p.w * q.z) / m0s[s];
+  }
+  if (act) {
+    x[3 * (o + lane)] = p.x;
+    x[3 * (o + lane) + 1] = p.y;
+    x[3 * (o + lane) + 2] = p.z;
+    v[3 * (o + lane)] = q.x + sx;
+    v[3 * (o + lane) + 1] = q.y + sy;
+    v[3 * (o + lane) + 2] = q.z + sz;
+  }
+}
+
+// Candidates entering the first step: radii of the initial state and the
+// prechecker on the initial positions (Sec. 2.2).
+__global__ __launch_bounds__(64) void k_batch_prime(BatchArgs a) {
+  const int s = blockIdx.x, lane = threadIdx.x;
+  const int o = a.off[s], n = a.off[s + 1] - o;
+  const bool act = lane < n;
+  const double m0 = a.m0[s];
+  double4 p = make_double4(1.0e3 + lane, 0.0, 0.0, 0.0), q = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (act) {
+    p = a.xm[o + lane];
+    q = a.vv[o + lane];
+  }
+  const double rc = act && !a.enc_free
+                        ? rcrit(p.x, p.y, p.z, q.x, q.y, q.z, p.w, a.G * m0, m0, a.n1, a.n2, a.absdt)
+                        : 0.0;
+  double ax, ay, az;
+  unsigned long long cand;
+  sys_kick(n, lane, p.x, p.y, p.z, p.w, rc, a.G, a.pf2, !a.enc_free, ax, ay, az, cand);
+  if (act) {
+    a.cand[o + lane] = cand;
+    a.encm[o + lane] = 0ull;
+  }
+}
+
+// E = sum m v^2/2 + |P|^2/2m0 - sum G m0 m/r - sum_{i<j} G m_i m_j/r_ij and
+// L = sum m x x v of each system (Eqs. 1-3).
+__global__ __launch_bounds__(64) void k_batch_energy(const double4* __restrict__ xm,
+                                                     const double4* __restrict__ vv,
+                                                     const int* __restrict__ off,
+                                                     const double* __restrict__ m0s, double G,
+                                                     double* __restrict__ E,
+                                                     double* __restrict__ L) {
+  const int s = blockIdx.x, lane = threadIdx.x;
+  const int o = off[s], n = off[s + 1] - o;
+  const bool act = lane < n;
+  double4 p = make_double4(1.0e3 + lane, 0.0, 0.0, 0.0), q = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (act) {
+    p = xm[o + lane];
+    q = vv[o + lane];
+  }
+  const double m0 = m0s[s];
+  double kin = 0.0, pot = 0.0;
+  if (act) {
+    kin = 0.5 * p.w * (q.x * q.x + q.y * q.y + q.z * q.z);
+    pot = -G * m0 * p.w / sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
+  }
+  for (int j = 0; j < n; ++j) {
+    const double xj = readlane_d(p.x, j), yj = readlane_d(p.y, j), zj = readlane_d(p.z, j);
+    const double mj = readlane_d(p.w, j);
+    if (act && j > lane) {
+      const double dx = xj - p.x, dy = yj - p.y, dz = zj - p.z;
+      pot -= G * p.w * mj / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+  }
+  const double Px = wave_sum(p.w * q.x), Py = wave_sum(p.w * q.y), Pz = wave_sum(p.w * q.z);
+  const double e = wave_sum(kin + pot) + (Px * Px + Py * Py + Pz * Pz) / (2.0 * m0);
+  const double lx = wave_sum(p.w * (p.y * q.z - p.z * q.y));
+  const double ly = wave_sum(p.w * (p.z * q.x - p.x * q.z));
+  const double lz = wave_sum(p.w * (p.x * q.y - p.y * q.x));
+  if (lane == 0) {
+    E[s] = e;
+    L[3 * s] = lx;
+    L[3 * s + 1] = ly;
+    L[3 * s + 2] = lz;
+  }
+}
+
+BatchArgs batch_args(const BatchWs& b, const StepConsts& c, bool scratch, int variant_order) {
+  BatchArgs a;
+  a.xm = scratch ? b.xm2 : b.xm;
+  a.vv = scratch ? b.vv2 : b.vv;
+  a.cand = scratch ? b.cand2 : b.cand;
+  a.encm = scratch ? b.encm2 : b.encm;
+  a.off = b.off;
+  a.m0 = b.m0;
+  a.order = variant_order ? b.order_desc : b.order_nat;
+  a.ss = scratch ? b.ss2 : b.ss;
+  a.rbuf = b.rbuf;
+  a.rslot = b.rslot;
+  a.flags = scratch ? b.flags2 : &b.st->flags;
+  a.nsys = b.nsys;
+  a.nsteps = 0;
+  a.G = c.G;
+  a.dt = c.dt;
+  a.h = c.h;
+  a.absdt = fabs(c.dt);
+  a.n1 = c.n1;
+  a.n2 = c.n2;
+  a.pf2 = c.pf2;
+  a.tol = c.bs_tol;
+  a.max_depth = c.bs_max_depth;
+  a.max_iter = c.kepler_max_iter;
+  a.enc_free = c.encounter_free;
+  return a;
+}
+
+}  // namespace
+
+const char* batch_variant_name(int v) {
+  static const char* names[kBatchVariants] = {
+      "1 wave/SIMD, natural order",  "1 wave/SIMD, largest first",
+      "2 waves/SIMD, natural order", "2 waves/SIMD, largest first",
+      "4 waves/SIMD, natural order", "4 waves/SIMD, largest first"};
+  return v >= 0 && v < kBatchVariants ? names[v] : "?";
+}
+
+size_t batch_carve(BatchWs& b, int nsys, int64_t nb, int nbig, void* base) {
+  b.nsys = nsys;
+  b.nb = nb;
+  b.nbig = nbig;
+  size_t off = 0;
+  auto take = [&](size_t sz) -> void* {
+    const size_t o = off;
+    off += (sz + 255) & ~size_t(255);
+    return base ? (void*)((char*)base + o) : nullptr;
+  };
+  const size_t n = (size_t)std::max<int64_t>(nb, 1), ns = (size_t)nsys;
+  b.xm = (double4*)take(n * sizeof(double4));
+  b.vv = (double4*)take(n * sizeof(double4));
+  b.cand = (unsigned long long*)take(n * sizeof(unsigned long long));
+  b.encm = (unsigned long long*)take(n * sizeof(unsigned long long));
+  b.xm2 = (double4*)take(n * sizeof(double4));
+  b.vv2 = (double4*)take(n * sizeof(double4));
+  b.cand2 = (unsigned long long*)take(n * sizeof(unsigned long long));
+  b.encm2 = (unsigned long long*)take(n * sizeof(unsigned long long));
+  b.off = (int*)take((ns + 1) * sizeof(int));
+  b.m0 = (double*)take(ns * sizeof(double));
+  b.order_nat = (int*)take(ns * sizeof(int));
+  b.order_desc = (int*)take(ns * sizeof(int));
+  b.ss = (BatchSysStat*)take(ns * sizeof(BatchSysStat));
+  b.rslot = (int*)take(ns * sizeof(int));
+  b.rbuf = (double*)take((size_t)std::max(nbig, 1) * kBsRDoubles * sizeof(double));
+  b.ss2 = (BatchSysStat*)take(ns * sizeof(BatchSysStat));
+  b.flags2 = (unsigned*)take(sizeof(unsigned));
+  b.flag_in = (int*)take(sizeof(int));
+  b.st = (DevStat*)take(sizeof(DevStat));
+  return off;
+}
+
+hipError_t batch_pack(const BatchWs& b, const double* m, const double* x, const double* v,
+                      int coords_in, bool keep_mass, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_pack, dim3(b.nsys), dim3(64), 0, s, m, x, v, b.off, b.m0, b.xm, b.vv,
+                     coords_in == GENGA_HELIO, keep_mass ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t batch_unpack(const BatchWs& b, double* x, double* v, int coords_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_unpack, dim3(b.nsys), dim3(64), 0, s, b.xm, b.vv, b.off, b.m0, x, v,
+                     coords_out == GENGA_HELIO);
+  return hipGetLastError();
+}
+
+hipError_t batch_prime(const BatchWs& b, const StepConsts& c, hipStream_t s) {
+  BatchArgs a = batch_args(b, c, false, 0);
+  hipLaunchKernelGGL(k_batch_prime, dim3(b.nsys), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t batch_energy(const BatchWs& b, const StepConsts& c, double* E, double* L,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_energy, dim3(b.nsys), dim3(64), 0, s, b.xm, b.vv, b.off, b.m0, c.G,
+                     E, L);
+  return hipGetLastError();
+}
+
+hipError_t batch_run(const BatchWs& b, const StepConsts& c, int variant, int nsteps, bool scratch,
+                     hipStream_t s) {
+  BatchArgs a = batch_args(b, c, scratch, variant & 1);
+  a.nsteps = nsteps;
+  const dim3 g(b.nsys), blk(64);
+  switch (variant >> 1) {
+    case 0: hipLaunchKernelGGL(k_batch<1>, g, blk, 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_batch<2>, g, blk, 0, s, a); break;
+    default: hipLaunchKernelGGL(k_batch<4>, g, blk, 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t batch_copy_to_scratch(const BatchWs& b, hipStream_t s) {
+  const size_t n = (size_t)std::max<int64_t>(b.nb, 1);
+  hipError_t e = hipMemcpyAsync(b.xm2, b.xm, n * sizeof(double4), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.vv2, b.vv, n * sizeof(double4), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.cand2, b.cand, n * sizeof(unsigned long long), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(b.ss2, 0, (size_t)b.nsys * sizeof(BatchSysStat), s);
+  if (e == hipSuccess) e = hipMemsetAsync(b.flags2, 0, sizeof(unsigned), s);
+  return e;
+}
+
+}  // namespace genga

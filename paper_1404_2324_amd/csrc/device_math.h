@@ -160,10 +160,11 @@ __device__ __forceinline__ void stumpff(double z, double& c0, double& c1,
 // 5 from s = dt/r0 until |ds| <= 2^-50 |s| or |F| <= 2^-48 times the sum of
 // the magnitudes of its terms (rounding floor).  Returns the iteration count, or
 // a negative count when max_iter was reached without convergence.
+// s_out (optional) receives the converged universal anomaly s.
 __device__ __forceinline__ int kepler_drift(double mu, double dt, double& x,
                                             double& y, double& z, double& vx,
                                             double& vy, double& vz,
-                                            int max_iter) {
+                                            int max_iter, double* s_out = nullptr) {
   const double r0 = sqrt(x * x + y * y + z * z);
   const double eta0 = x * vx + y * vy + z * vz;
   const double beta = 2.0 * mu / r0 - (vx * vx + vy * vy + vz * vz);
@@ -193,6 +194,7 @@ __device__ __forceinline__ int kepler_drift(double mu, double dt, double& x,
       break;
     }
   }
+  if (s_out) *s_out = s;
   double c0, c1, c2, c3;
   stumpff(beta * s * s, c0, c1, c2, c3);
   const double G1 = s * c1, G2 = s * s * c2, G3 = s * s * s * c3;

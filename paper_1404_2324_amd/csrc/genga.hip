@@ -1,6 +1,7 @@
 // C ABI of the library (include/genga.h): context, workspace validation,
 // HIP-graph capture of the step, status reporting.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -20,6 +21,7 @@ int status_from_flags(unsigned f) {
   if (f & F_BS) return GENGA_EBS;
   if (f & (F_CAND_OVF | F_ENC_OVF | F_TP_OVF)) return GENGA_EOVERFLOW;
   if (f & F_GROUP) return GENGA_EGROUP;
+  if (f & F_ADJ_ENC) return GENGA_EADJ_ENCOUNTER;
   return GENGA_OK;
 }
 
@@ -39,19 +41,32 @@ constexpr int64_t kTpMaxParticles = 1ll << 30;
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-bool shape_ok(int mode, const genga_params* p, int nm, int64_t ntp) {
+constexpr int kBatchMaxSystems = 1 << 24;
+
+bool shape_ok(int mode, const genga_params* p, int nm, int64_t ntp, int nsys = 0,
+              int64_t nbod = 0) {
   if (mode == GENGA_MASSIVE) return nm >= 1 && nm <= max_bodies(p) && ntp == 0;
   if (mode == GENGA_TEST) return nm >= 1 && nm <= kTpMaxPlanets && ntp >= 0 && ntp <= kTpMaxParticles;
+  if (mode == GENGA_BATCH)
+    return nsys >= 1 && nsys <= kBatchMaxSystems && nbod >= nsys &&
+           nbod <= (int64_t)nsys * kBatchMaxBodies;
   return false;
 }
 
-size_t ws_bytes(int mode, const genga_params& p, int nm, int64_t ntp) {
+size_t ws_bytes(int mode, const genga_params& p, int nm, int64_t ntp, int nsys = 0,
+                int64_t nbod = 0) {
   if (mode == GENGA_TEST) {
     TpWs t;
     return align256(massive_ws_bytes(nm, p, true)) + tp_carve(t, ntp, nullptr);
   }
+  if (mode == GENGA_BATCH) {
+    BatchWs b;
+    return batch_carve(b, nsys, nbod, nsys, nullptr);
+  }
   return massive_ws_bytes(nm, p, false);
 }
+
+constexpr int kTuneSteps = 4;
 
 }  // namespace
 
@@ -61,6 +76,15 @@ struct genga_ctx {
   StepConsts c{};
   MassiveWs w{};
   TpWs t{};
+  BatchWs b{};
+  int variant = 0;                       // batched: the tuner's choice
+  double tune_us[kBatchVariants] = {};   // batched: the tuner's timings
+  hipGraphExec_t g_batch = nullptr;      // batched: one launch of g_batch_steps steps
+  int g_batch_steps = 0;
+  int sb = 64;                           // batched: lanes per system in the adjoint
+  double* adj_ckpt = nullptr;            // the last genga_adj_forward's buffer
+  size_t adj_bytes = 0;
+  int adj_T = 0, adj_K = 0;
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
   hipGraphExec_t g_many = nullptr;
@@ -119,6 +143,163 @@ static int load_state(genga_ctx* ctx, const double* d_m, const double* d_x, cons
   return GENGA_OK;
 }
 
+// ---- batched mode -----------------------------------------------------------
+static int batch_capture(genga_ctx* ctx, int nsteps) {
+  if (ctx->g_batch) {
+    (void)hipGraphExecDestroy(ctx->g_batch);
+    ctx->g_batch = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+  const hipError_t e = batch_run(ctx->b, ctx->c, ctx->variant, nsteps, false, ctx->cap);
+  const hipError_t e2 = hipStreamEndCapture(ctx->cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return GENGA_EHIP;
+  }
+  const hipError_t e3 = hipGraphInstantiate(&ctx->g_batch, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e3 != hipSuccess) return GENGA_EHIP;
+  ctx->g_batch_steps = nsteps;
+  return GENGA_OK;
+}
+
+// Runs every variant for `steps` steps on a copy of the current state and
+// keeps the fastest for later steps.
+static int batch_tune(genga_ctx* ctx, int steps) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return GENGA_EHIP;
+  }
+  int rc = GENGA_OK, best = 0;
+  for (int v = 0; v < kBatchVariants && rc == GENGA_OK; ++v) {
+    float ms = 0.0f;
+    if (batch_copy_to_scratch(ctx->b, ctx->stream) != hipSuccess ||
+        hipEventRecord(e0, ctx->stream) != hipSuccess ||
+        batch_run(ctx->b, ctx->c, v, steps, true, ctx->stream) != hipSuccess ||
+        hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      rc = GENGA_EHIP;
+    ctx->tune_us[v] = ms * 1e3;
+    if (ctx->tune_us[v] < ctx->tune_us[best]) best = v;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != GENGA_OK) return rc;
+  if (best != ctx->variant || !ctx->g_batch) {
+    ctx->variant = best;
+    if (ctx->g_batch) {
+      (void)hipGraphExecDestroy(ctx->g_batch);
+      ctx->g_batch = nullptr;
+    }
+  }
+  return GENGA_OK;
+}
+
+static int batch_load(genga_ctx* ctx, const double* d_m, const double* d_x, const double* d_v,
+                      int coords_in) {
+  const BatchWs& b = ctx->b;
+  HIPCHK(hipMemsetAsync(b.flag_in, 0, sizeof(int), ctx->stream));
+  if (d_m) HIPCHK(validate_finite(d_m, b.nb, b.flag_in, ctx->stream));
+  HIPCHK(validate_finite(d_x, 3 * b.nb, b.flag_in, ctx->stream));
+  HIPCHK(validate_finite(d_v, 3 * b.nb, b.flag_in, ctx->stream));
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, b.flag_in, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (bad) return GENGA_EINVAL;
+  HIPCHK(batch_pack(b, d_m, d_x, d_v, coords_in, d_m == nullptr, ctx->stream));
+  HIPCHK(batch_prime(b, ctx->c, ctx->stream));
+  return GENGA_OK;
+}
+
+static int batch_init(genga_ctx** out, const genga_params* p, int n_sys,
+                      const int32_t* d_offsets, const double* d_m0, const double* d_m,
+                      const double* d_x, const double* d_v, int coords_in, void* d_workspace,
+                      size_t ws_bytes_in, void* stream) {
+  if (!params_ok(p) || n_sys < 1 || n_sys > kBatchMaxSystems || !d_offsets) return GENGA_EINVAL;
+  if (!d_m || !d_x || !d_v || !d_workspace) return GENGA_EINVAL;
+  if (coords_in != GENGA_HELIO && coords_in != GENGA_DEMOCRATIC) return GENGA_EINVAL;
+  if (((uintptr_t)d_workspace & 255u) != 0) return GENGA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  // the system layout is read once on the host: sizes 1..64, contiguous
+  std::vector<int32_t> off((size_t)n_sys + 1);
+  HIPCHK(hipMemcpyAsync(off.data(), d_offsets, off.size() * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, st));
+  std::vector<double> m0((size_t)n_sys, p->m0);
+  if (d_m0)
+    HIPCHK(hipMemcpyAsync(m0.data(), d_m0, m0.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (off[0] != 0) return GENGA_EINVAL;
+  int nbig = 0;
+  for (int s = 0; s < n_sys; ++s) {
+    const int n = off[s + 1] - off[s];
+    if (n < 1 || n > kBatchMaxBodies) return GENGA_EINVAL;
+    if (!(m0[s] > 0.0) || !std::isfinite(m0[s])) return GENGA_EINVAL;
+    if (n > 8) ++nbig;
+  }
+  const int64_t nb = off[n_sys];
+  if (!shape_ok(GENGA_BATCH, p, 0, 0, n_sys, nb)) return GENGA_EINVAL;
+  if (ws_bytes_in < ws_bytes(GENGA_BATCH, *p, 0, 0, n_sys, nb)) return GENGA_ENOMEM;
+  genga_ctx* ctx = new (std::nothrow) genga_ctx();
+  if (!ctx) return GENGA_ENOMEM;
+  ctx->mode = GENGA_BATCH;
+  ctx->p = *p;
+  ctx->c = make_consts(*p);
+  ctx->stream = st;
+  batch_carve(ctx->b, n_sys, nb, n_sys, d_workspace);
+  ctx->w.st = ctx->b.st;  // the status word read by the common calls
+  std::vector<int> order(n_sys), desc(n_sys), rslot(n_sys, 0);
+  for (int s = 0; s < n_sys; ++s) order[s] = s;
+  desc = order;
+  std::stable_sort(desc.begin(), desc.end(), [&](int a, int b) {
+    return off[a + 1] - off[a] > off[b + 1] - off[b];
+  });
+  int maxn = 1;
+  for (int s = 0, k = 0; s < n_sys; ++s) {
+    if (off[s + 1] - off[s] > 8) rslot[s] = k++;
+    maxn = std::max(maxn, off[s + 1] - off[s]);
+  }
+  ctx->sb = adj_segment_lanes(maxn);
+  (void)nbig;
+  int rc = GENGA_OK;
+  if (hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) rc = GENGA_EHIP;
+  const BatchWs& b = ctx->b;
+  if (rc == GENGA_OK &&
+      (hipMemcpyAsync(b.off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemcpyAsync(b.m0, m0.data(), m0.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemcpyAsync(b.order_nat, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemcpyAsync(b.order_desc, desc.data(), desc.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemcpyAsync(b.rslot, rslot.data(), rslot.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemsetAsync(b.ss, 0, (size_t)n_sys * sizeof(BatchSysStat), st) != hipSuccess ||
+       hipMemsetAsync(b.st, 0, sizeof(DevStat), st) != hipSuccess))
+    rc = GENGA_EHIP;
+  if (rc == GENGA_OK) rc = batch_load(ctx, d_m, d_x, d_v, coords_in);
+  if (rc == GENGA_OK) rc = batch_tune(ctx, kTuneSteps);
+  if (rc == GENGA_OK && hipStreamSynchronize(st) != hipSuccess) rc = GENGA_EHIP;
+  if (rc != GENGA_OK) {
+    genga_destroy(ctx);
+    return rc;
+  }
+  *out = ctx;
+  return GENGA_OK;
+}
+
+static int batch_step(genga_ctx* ctx, int64_t nsteps) {
+  while (nsteps > 0) {
+    const int chunk = (int)std::min<int64_t>(nsteps, 1 << 30);
+    if (!ctx->g_batch || ctx->g_batch_steps != chunk) {
+      const int r = batch_capture(ctx, chunk);
+      if (r != GENGA_OK) return r;
+    }
+    HIPCHK(hipGraphLaunch(ctx->g_batch, ctx->stream));
+    ctx->steps += chunk;
+    nsteps -= chunk;
+  }
+  return GENGA_OK;
+}
+
 extern "C" {
 
 void genga_params_default(genga_params* p) {
@@ -140,23 +321,19 @@ void genga_params_default(genga_params* p) {
 
 size_t genga_workspace_bytes(int mode, const genga_params* p, int n_massive, int64_t n_test,
                              int n_sys, int64_t n_bodies) {
-  (void)n_test;
-  (void)n_sys;
-  (void)n_bodies;
-  if (!params_ok(p) || !shape_ok(mode, p, n_massive, n_test)) return 0;
-  return ws_bytes(mode, *p, n_massive, n_test);
+  if (!params_ok(p) || !shape_ok(mode, p, n_massive, n_test, n_sys, n_bodies)) return 0;
+  return ws_bytes(mode, *p, n_massive, n_test, n_sys, n_bodies);
 }
 
 int genga_init(genga_ctx** out, int mode, const genga_params* p, int n_massive, int64_t n_test,
                int n_sys, const int32_t* d_offsets, const double* d_m0, const double* d_m,
                const double* d_x, const double* d_v, int coords_in, void* d_workspace,
                size_t ws_bytes_in, void* stream) {
-  (void)n_test;
-  (void)n_sys;
-  (void)d_offsets;
-  (void)d_m0;
   if (!out) return GENGA_EINVAL;
   *out = nullptr;
+  if (mode == GENGA_BATCH)
+    return batch_init(out, p, n_sys, d_offsets, d_m0, d_m, d_x, d_v, coords_in, d_workspace,
+                      ws_bytes_in, stream);
   if (!params_ok(p) || !shape_ok(mode, p, n_massive, n_test)) return GENGA_EINVAL;
   if (!d_m || !d_x || !d_v || !d_workspace) return GENGA_EINVAL;
   if (coords_in != GENGA_HELIO && coords_in != GENGA_DEMOCRATIC) return GENGA_EINVAL;
@@ -194,6 +371,7 @@ int genga_init(genga_ctx** out, int mode, const genga_params* p, int n_massive, 
 int genga_step(genga_ctx* ctx, int64_t nsteps) {
   if (!ctx || nsteps < 0) return GENGA_EINVAL;
   if (nsteps == 0) return GENGA_OK;
+  if (ctx->mode == GENGA_BATCH) return batch_step(ctx, nsteps);
   if (nsteps >= kGraphSteps && !ctx->g_many) {
     int r = capture(ctx, kGraphSteps, &ctx->g_many);
     if (r != GENGA_OK) return r;
@@ -209,7 +387,7 @@ int genga_step(genga_ctx* ctx, int64_t nsteps) {
 }
 
 int genga_step_profiled(genga_ctx* ctx, int64_t nsteps, double* h_kick_us) {
-  if (!ctx || nsteps < 1 || !h_kick_us) return GENGA_EINVAL;
+  if (!ctx || nsteps < 1 || !h_kick_us || ctx->mode == GENGA_BATCH) return GENGA_EINVAL;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -245,6 +423,10 @@ int genga_sync(genga_ctx* ctx) {
 int genga_get_state(genga_ctx* ctx, double* d_x, double* d_v, int coords_out) {
   if (!ctx || !d_x || !d_v) return GENGA_EINVAL;
   if (coords_out != GENGA_HELIO && coords_out != GENGA_DEMOCRATIC) return GENGA_EINVAL;
+  if (ctx->mode == GENGA_BATCH) {
+    HIPCHK(batch_unpack(ctx->b, d_x, d_v, coords_out, ctx->stream));
+    return genga_sync(ctx);
+  }
   HIPCHK(massive_unpack(ctx->w, ctx->c, d_x, d_v, coords_out, ctx->stream));
   if (ctx->mode == GENGA_TEST) HIPCHK(tp_unpack(ctx->w, ctx->t, ctx->c, d_x, d_v, coords_out, ctx->stream));
   return genga_sync(ctx);
@@ -253,6 +435,11 @@ int genga_get_state(genga_ctx* ctx, double* d_x, double* d_v, int coords_out) {
 int genga_set_state(genga_ctx* ctx, const double* d_x, const double* d_v, int coords_in) {
   if (!ctx || !d_x || !d_v) return GENGA_EINVAL;
   if (coords_in != GENGA_HELIO && coords_in != GENGA_DEMOCRATIC) return GENGA_EINVAL;
+  if (ctx->mode == GENGA_BATCH) {
+    const int r = batch_load(ctx, nullptr, d_x, d_v, coords_in);
+    if (r != GENGA_OK) return r;
+    return genga_sync(ctx);
+  }
   // masses stay: the pre-drift scratch holds them while the state is repacked
   double* dm = reinterpret_cast<double*>(ctx->w.xpre);
   HIPCHK(massive_masses(ctx->w, dm, ctx->stream));
@@ -263,13 +450,35 @@ int genga_set_state(genga_ctx* ctx, const double* d_x, const double* d_v, int co
 
 int genga_energy(genga_ctx* ctx, double* d_E, double* d_L) {
   if (!ctx || !d_E || !d_L) return GENGA_EINVAL;
+  if (ctx->mode == GENGA_BATCH) {
+    HIPCHK(batch_energy(ctx->b, ctx->c, d_E, d_L, ctx->stream));
+    return GENGA_OK;
+  }
   HIPCHK(massive_energy(ctx->w, ctx->c, d_E, d_L, ctx->stream));
   return GENGA_OK;
 }
 
 int genga_accel_state(genga_ctx* ctx, double* d_acc) {
-  if (!ctx || !d_acc) return GENGA_EINVAL;
+  if (!ctx || !d_acc || ctx->mode == GENGA_BATCH) return GENGA_EINVAL;
   HIPCHK(massive_accel(ctx->w, ctx->c, d_acc, ctx->stream));
+  return GENGA_OK;
+}
+
+// Pairs i < j (global rows) of per-body partner masks of the batched layout.
+static int batch_pairs(genga_ctx* ctx, const unsigned long long* d_mask,
+                       std::vector<std::pair<int, int>>* pairs) {
+  const BatchWs& b = ctx->b;
+  std::vector<unsigned long long> mk((size_t)b.nb);
+  std::vector<int32_t> off((size_t)b.nsys + 1);
+  HIPCHK(hipMemcpyAsync(mk.data(), d_mask, mk.size() * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(off.data(), b.off, off.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int s = 0; s < b.nsys; ++s)
+    for (int i = off[s]; i < off[s + 1]; ++i)
+      for (int j = i + 1; j < off[s + 1]; ++j)
+        if ((mk[i] >> (j - off[s])) & 1ull) pairs->emplace_back(i, j);
   return GENGA_OK;
 }
 
@@ -279,6 +488,23 @@ int genga_encounters(genga_ctx* ctx, int32_t* h_ij, double* h_dmin2, double* h_r
   DevStat hs;
   int r = read_status(ctx, &hs);
   if (r != GENGA_OK) return r;
+  if (ctx->mode == GENGA_BATCH) {
+    std::vector<std::pair<int, int>> pr;
+    if (ctx->steps > 0) {
+      r = batch_pairs(ctx, ctx->b.encm, &pr);
+      if (r != GENGA_OK) return r;
+    }
+    const int np = (int)pr.size();
+    for (int k = 0; k < std::min(np, cap); ++k) {
+      h_ij[2 * k] = pr[k].first;
+      h_ij[2 * k + 1] = pr[k].second;
+      if (h_dmin2) h_dmin2[k] = std::nan("");
+      if (h_rc2) h_rc2[k] = std::nan("");
+    }
+    *h_n = np;
+    if (np > cap) return GENGA_EOVERFLOW;
+    return status_from_flags(hs.flags);
+  }
   const int n = ctx->p.encounter_free || ctx->steps == 0 ? 0 : hs.nenc;
   const int have = std::min(n, ctx->w.enc_cap);
   std::vector<int2> ij(have);
@@ -314,6 +540,19 @@ int genga_candidates(genga_ctx* ctx, int32_t* h_ij, int cap, int* h_n) {
   DevStat hs;
   int r = read_status(ctx, &hs);
   if (r != GENGA_OK) return r;
+  if (ctx->mode == GENGA_BATCH) {
+    std::vector<std::pair<int, int>> pr;
+    r = batch_pairs(ctx, ctx->b.cand, &pr);
+    if (r != GENGA_OK) return r;
+    const int np = (int)pr.size();
+    for (int k = 0; k < std::min(np, cap); ++k) {
+      h_ij[2 * k] = pr[k].first;
+      h_ij[2 * k + 1] = pr[k].second;
+    }
+    *h_n = np;
+    if (np > cap) return GENGA_EOVERFLOW;
+    return status_from_flags(hs.flags);
+  }
   const int n = ctx->w.n, cpb = ctx->w.cpb;
   std::vector<int> cnt(n), tab((size_t)n * cpb);
   HIPCHK(hipMemcpyAsync(cnt.data(), ctx->w.ccnt, n * sizeof(int), hipMemcpyDeviceToHost,
@@ -343,6 +582,22 @@ int genga_stats(genga_ctx* ctx, genga_stats_t* s) {
   if (r != GENGA_OK) return r;
   std::memset(s, 0, sizeof(*s));
   s->steps = ctx->steps;
+  if (ctx->mode == GENGA_BATCH) {
+    std::vector<BatchSysStat> ss((size_t)ctx->b.nsys);
+    HIPCHK(hipMemcpyAsync(ss.data(), ctx->b.ss, ss.size() * sizeof(BatchSysStat),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (const BatchSysStat& t : ss) {
+      s->n_enc += ctx->steps > 0 ? t.nenc : 0;
+      s->n_groups += ctx->steps > 0 ? t.ngroups : 0;
+      s->max_group = std::max(s->max_group, t.maxg);
+      s->kepler_iter_max = std::max(s->kepler_iter_max, t.kit);
+      s->bs_substeps += (int64_t)t.sub;
+      s->enc_total += (int64_t)t.enc_total;
+    }
+    s->flags = hs.flags;
+    return status_from_flags(hs.flags);
+  }
   const bool any = ctx->steps > 0 && !ctx->p.encounter_free;
   s->n_cand = any ? hs.ncand : 0;
   s->n_enc = any ? hs.nenc : 0;
@@ -412,6 +667,59 @@ int genga_collisions(genga_ctx* ctx, int64_t* h_tp, int32_t* h_planet, int64_t* 
   return status_from_flags(hs.flags);
 }
 
+int genga_tune(genga_ctx* ctx, int nsteps, double* h_us, int cap, int* h_n, int* h_choice) {
+  if (!ctx || ctx->mode != GENGA_BATCH || nsteps < 1 || cap < 0 || (cap > 0 && !h_us))
+    return GENGA_EINVAL;
+  const int r = batch_tune(ctx, nsteps);
+  if (r != GENGA_OK) return r;
+  for (int v = 0; v < std::min(cap, kBatchVariants); ++v) h_us[v] = ctx->tune_us[v];
+  if (h_n) *h_n = kBatchVariants;
+  if (h_choice) *h_choice = ctx->variant;
+  return cap < kBatchVariants ? GENGA_EOVERFLOW : GENGA_OK;
+}
+
+const char* genga_tune_variant(int v) { return batch_variant_name(v); }
+
+static bool adj_ok(const genga_ctx* ctx) {
+  return ctx && ctx->mode == GENGA_BATCH && ctx->p.encounter_free;
+}
+
+size_t genga_adj_buffer_bytes(genga_ctx* ctx, int64_t nsteps, int ckpt_every) {
+  if (!adj_ok(ctx) || nsteps < 1 || nsteps > INT_MAX || ckpt_every < 1) return 0;
+  const int64_t C = (nsteps + ckpt_every - 1) / ckpt_every;
+  return align256((size_t)C * 6 * (size_t)ctx->b.nb * sizeof(double)) +
+         adj_tape_bytes(ctx->b.nsys, ctx->sb, std::min<int64_t>(ckpt_every, nsteps));
+}
+
+int genga_adj_forward(genga_ctx* ctx, int64_t nsteps, int ckpt_every, void* d_buffer,
+                      size_t buffer_bytes) {
+  if (!adj_ok(ctx) || !d_buffer || ((uintptr_t)d_buffer & 255u) != 0) return GENGA_EINVAL;
+  const size_t need = genga_adj_buffer_bytes(ctx, nsteps, ckpt_every);
+  if (need == 0) return GENGA_EINVAL;
+  if (buffer_bytes < need) return GENGA_ENOMEM;
+  HIPCHK(adj_forward(ctx->b, ctx->c, ctx->sb, (int)nsteps, ckpt_every, (double*)d_buffer,
+                     ctx->stream));
+  ctx->adj_ckpt = (double*)d_buffer;
+  ctx->adj_bytes = buffer_bytes;
+  ctx->adj_T = (int)nsteps;
+  ctx->adj_K = ckpt_every;
+  ctx->steps += nsteps;
+  return GENGA_OK;
+}
+
+int genga_adj_backward(genga_ctx* ctx, const double* d_gxT, const double* d_gvT, double* d_gx0,
+                       double* d_gv0, double* d_gm) {
+  if (!adj_ok(ctx) || !ctx->adj_ckpt || !d_gxT || !d_gvT || !d_gx0 || !d_gv0 || !d_gm)
+    return GENGA_EINVAL;
+  const int T = ctx->adj_T, K = ctx->adj_K;
+  const int64_t C = (T + K - 1) / K;
+  double* tape = (double*)((char*)ctx->adj_ckpt +
+                           align256((size_t)C * 6 * (size_t)ctx->b.nb * sizeof(double)));
+  HIPCHK(adj_backward(ctx->b, ctx->c, ctx->sb, T, std::min(K, T), ctx->adj_ckpt, tape, d_gxT,
+                      d_gvT, d_gx0, d_gv0, d_gm, ctx->stream));
+  return GENGA_OK;
+}
+
 const char* genga_strerror(int code) {
   switch (code) {
     case GENGA_OK: return "ok";
@@ -431,6 +739,7 @@ int genga_destroy(genga_ctx* ctx) {
   if (!ctx) return GENGA_EINVAL;
   if (ctx->stream || ctx->cap) (void)hipStreamSynchronize(ctx->stream);
   if (ctx->g_many) (void)hipGraphExecDestroy(ctx->g_many);
+  if (ctx->g_batch) (void)hipGraphExecDestroy(ctx->g_batch);
   if (ctx->g_one) (void)hipGraphExecDestroy(ctx->g_one);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;

@@ -18,6 +18,7 @@ enum : unsigned {
   F_ENC_OVF = 8u,      // encounter list full
   F_GROUP = 16u,       // group larger than the in-wave BS limit
   F_TP_OVF = 32u,      // more massive bodies than the test-particle mask holds
+  F_ADJ_ENC = 64u,     // a pair inside r_crit during the encounter-free map
 };
 // control bits
 enum : unsigned { C_FULLKICK = 1u };
@@ -175,6 +176,73 @@ hipError_t tp_validate(const TpWs& t, int nm, const double* x, const double* v, 
 // Copies nm + ntp radii (planets first) into the workspace; negative or
 // non-finite values set *dbad.
 hipError_t tp_set_radii(const TpWs& t, int nm, const double* r, int* dbad, hipStream_t s);
+
+// ---- batched independent systems (batch.hip) --------------------------------
+struct BatchSysStat {
+  unsigned long long sub;        // accepted BS substeps since init
+  unsigned long long enc_total;  // encounters since init
+  int nenc;                      // encounters of the last step
+  int ngroups;                   // groups of the last step
+  int maxg;                      // largest group of the last step
+  int kit;                       // largest Kepler iteration count
+  unsigned flags;                // latched error bits of this system
+  int pad;
+};
+
+struct BatchWs {
+  int nsys;
+  int64_t nb;                      // bodies of all systems
+  double4* xm;                     // [nb] x, y, z, m
+  double4* vv;                     // [nb] v
+  unsigned long long* cand;        // [nb] candidate partners (bits of local indices)
+  unsigned long long* encm;        // [nb] encounters j > i of the last step
+  double4 *xm2, *vv2;              // copies the tuner runs on
+  unsigned long long *cand2, *encm2;
+  int* off;                        // [nsys + 1]
+  double* m0;                      // [nsys]
+  int* order_nat;                  // systems in index order
+  int* order_desc;                 // systems by decreasing size
+  BatchSysStat* ss;                // [nsys]
+  BatchSysStat* ss2;
+  int* rslot;                      // [nsys] tableau slice of systems over 8 bodies
+  double* rbuf;                    // [nbig] tableaux of the sequential BS
+  int nbig;
+  unsigned* flags2;
+  int* flag_in;
+  DevStat* st;
+};
+
+constexpr int kBatchMaxBodies = 64;  // one lane per body
+constexpr int kBatchVariants = 6;    // register budget {1, 2, 4 waves/SIMD} x order
+
+// nbig: systems with more than 8 bodies (each gets a sequential-BS tableau)
+size_t batch_carve(BatchWs& b, int nsys, int64_t nb, int nbig, void* base);
+hipError_t batch_pack(const BatchWs& b, const double* m, const double* x, const double* v,
+                      int coords_in, bool keep_mass, hipStream_t s);
+hipError_t batch_unpack(const BatchWs& b, double* x, double* v, int coords_out, hipStream_t s);
+hipError_t batch_prime(const BatchWs& b, const StepConsts& c, hipStream_t s);
+hipError_t batch_energy(const BatchWs& b, const StepConsts& c, double* E, double* L,
+                        hipStream_t s);
+// nsteps steps of every system in one launch of the given variant, on the
+// live state or on the tuner's copies.
+hipError_t batch_run(const BatchWs& b, const StepConsts& c, int variant, int nsteps,
+                     bool scratch, hipStream_t s);
+hipError_t batch_copy_to_scratch(const BatchWs& b, hipStream_t s);
+const char* batch_variant_name(int v);
+
+// ---- adjoint of the encounter-free map (adj.hip) ----------------------------
+// Systems are packed sb lanes each (sb: power of two >= the largest system).
+int adj_segment_lanes(int max_n);
+size_t adj_tape_bytes(int nsys, int sb, int K);
+// T steps of the encounter-free map on the batched state, keeping the state
+// every K steps in ckpt ([ceil(T/K)][6][nb]).
+hipError_t adj_forward(const BatchWs& b, const StepConsts& c, int sb, int T, int K, double* ckpt,
+                       hipStream_t s);
+// Gradients of the state before those T steps from the adjoints of the
+// state after them (rows x 3), using the checkpoints and a tape.
+hipError_t adj_backward(const BatchWs& b, const StepConsts& c, int sb, int T, int K,
+                        double* ckpt, double* tape, const double* gxT, const double* gvT,
+                        double* gx0, double* gv0, double* gm, hipStream_t s);
 
 // ---- single-operation kernels for component checks (ops.hip) ---------------
 hipError_t op_kepler(double mu, int64_t n, const double* x0, const double* v0,

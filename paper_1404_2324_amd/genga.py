@@ -70,6 +70,11 @@ SIGNATURES = {
     "genga_candidates": (_i32, [_vp, _vp, _i32, ctypes.POINTER(_i32)]),
     "genga_stats": (_i32, [_vp, ctypes.POINTER(Stats)]),
     "genga_set_radii": (_i32, [_vp, _vp]),
+    "genga_tune": (_i32, [_vp, _i32, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "genga_tune_variant": (ctypes.c_char_p, [_i32]),
+    "genga_adj_buffer_bytes": (_sz, [_vp, _i64, _i32]),
+    "genga_adj_forward": (_i32, [_vp, _i64, _i32, _vp, _sz]),
+    "genga_adj_backward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "genga_collisions": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64)]),
     "genga_strerror": (ctypes.c_char_p, [_i32]),
     "genga_destroy": (_i32, [_vp]),
@@ -336,3 +341,107 @@ class TestParticleSimulation(Simulation):
     def split_state(self, coords: str = "dem"):
         x, v = self.state(coords)
         return x[:self.nm], v[:self.nm], x[self.nm:], v[self.nm:]
+
+
+class BatchedSimulation(Simulation):
+    """Independent systems (Sec. 3.4), system s in rows
+    [offsets[s], offsets[s+1]), each with its own central mass m0s[s]; every
+    call to ``step(n)`` is one launch (a captured HIP graph) that advances
+    every system n steps.  The tuner runs at construction."""
+
+    def __init__(self, offsets, m0s, m, x, v, params: Params | None = None,
+                 coords: str = "helio", device="cuda", stream=None):
+        self.p = params if params is not None else default_params()
+        self.device = torch.device(device)
+        self.stream = stream
+        off = torch.as_tensor(np.asarray(offsets, dtype=np.int32)).to(self.device).contiguous()
+        m0 = None if m0s is None else _dev(m0s, self.device)
+        m = _dev(m, self.device)
+        x = _dev(x, self.device).reshape(-1, 3)
+        v = _dev(v, self.device).reshape(-1, 3)
+        self.nsys = int(off.numel()) - 1
+        self.n = int(m.numel())
+        self.offsets = np.asarray(offsets, dtype=np.int64)
+        nbytes = lib().genga_workspace_bytes(GENGA_BATCH, ctypes.byref(self.p), 0, 0, self.nsys,
+                                             self.n)
+        if nbytes == 0:
+            raise GengaError(EINVAL, "genga_workspace_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._ctx = ctypes.c_void_p()
+        code = lib().genga_init(ctypes.byref(self._ctx), GENGA_BATCH, ctypes.byref(self.p), 0, 0,
+                                self.nsys, _ptr(off), _ptr(m0), _ptr(m), _ptr(x), _ptr(v),
+                                GENGA_HELIO if coords == "helio" else GENGA_DEMOCRATIC,
+                                _ptr(self.ws), nbytes, _stream(stream))
+        _check(code, "genga_init")
+
+    def energy(self):
+        E = torch.empty(self.nsys, dtype=torch.float64, device=self.device)
+        L = torch.empty(3 * self.nsys, dtype=torch.float64, device=self.device)
+        _check(lib().genga_energy(self._ctx, _ptr(E), _ptr(L)), "genga_energy")
+        torch.cuda.synchronize(self.device)
+        return E.cpu().numpy(), L.cpu().numpy().reshape(-1, 3)
+
+    def tune(self, nsteps: int = 4):
+        """Re-run the tuner; returns ({variant: microseconds}, chosen variant)."""
+        us = (ctypes.c_double * 16)()
+        n, ch = ctypes.c_int(), ctypes.c_int()
+        _check(lib().genga_tune(self._ctx, int(nsteps), us, 16, ctypes.byref(n), ctypes.byref(ch)),
+               "genga_tune")
+        names = {v: lib().genga_tune_variant(v).decode() for v in range(n.value)}
+        return {names[v]: us[v] for v in range(n.value)}, names[ch.value]
+
+    # ---- adjoint of the encounter-free map (contexts with encounter_free=1) --
+    def adj_forward(self, nsteps: int, ckpt_every: int = 32):
+        """Advance nsteps steps keeping checkpoints for adj_backward."""
+        nb = lib().genga_adj_buffer_bytes(self._ctx, int(nsteps), int(ckpt_every))
+        if nb == 0:
+            raise GengaError(EINVAL, "genga_adj_buffer_bytes")
+        self._adj_buf = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        _check(lib().genga_adj_forward(self._ctx, int(nsteps), int(ckpt_every),
+                                       _ptr(self._adj_buf), nb), "genga_adj_forward")
+
+    def adj_backward(self, gxT, gvT):
+        """(dL/dx0, dL/dv0, dL/dm) from dL/dxT, dL/dvT (democratic rows)."""
+        gxT = _dev(gxT, self.device).reshape(-1, 3)
+        gvT = _dev(gvT, self.device).reshape(-1, 3)
+        gx0 = torch.empty_like(gxT)
+        gv0 = torch.empty_like(gvT)
+        gm = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(lib().genga_adj_backward(self._ctx, _ptr(gxT), _ptr(gvT), _ptr(gx0), _ptr(gv0),
+                                        _ptr(gm)), "genga_adj_backward")
+        return gx0, gv0, gm
+
+
+class EncounterFreeMap(torch.autograd.Function):
+    """(x_T, v_T) = nsteps steps of the encounter-free map (K = 1) of every
+    system from democratic (x0, v0) with masses m; backward runs the library's
+    adjoint with a checkpoint every ckpt_every steps."""
+
+    @staticmethod
+    def forward(ctx, x0, v0, m, offsets, m0s, nsteps, ckpt_every=32, params=None):
+        p = params if params is not None else default_params()
+        p.encounter_free = 1
+        sim = BatchedSimulation(offsets, m0s, m.detach(), x0.detach(), v0.detach(), p,
+                                coords="dem", device=x0.device)
+        sim.adj_forward(nsteps, ckpt_every)
+        xT, vT = sim.state("dem")
+        sim.check()
+        ctx.sim = sim
+        return xT, vT
+
+    @staticmethod
+    def backward(ctx, gxT, gvT):
+        sim = ctx.sim
+        if gxT is None:
+            gxT = torch.zeros(sim.n, 3, dtype=torch.float64, device=sim.device)
+        if gvT is None:
+            gvT = torch.zeros(sim.n, 3, dtype=torch.float64, device=sim.device)
+        gx0, gv0, gm = sim.adj_backward(gxT.contiguous(), gvT.contiguous())
+        sim.check()
+        sim.close()
+        ctx.sim = None
+        return gx0, gv0, gm, None, None, None, None, None
+
+
+def encounter_free_map(x0, v0, m, offsets, m0s, nsteps, ckpt_every=32, params=None):
+    return EncounterFreeMap.apply(x0, v0, m, offsets, m0s, nsteps, ckpt_every, params)

@@ -195,19 +195,38 @@ def batched(nsys: int = 4096, seed_index: int = 4, nmin: int = 2, nmax: int = 32
 
 
 def adjoint_systems(nsys: int = 1024, nplanets: int = 8, seed_index: int = 5,
-                    min_spacing_hill: float = 8.0):
-    """Systems of planets drawn as in the test-particle workload, redrawn
-    until every pair of semi-major-axis neighbours is at least
-    `min_spacing_hill` mutual Hill radii apart (so that K = 1 holds).
-    Returns (m, x, u) of shape (nsys, nplanets[, 3])."""
+                    min_spacing_hill: float = 8.0, min_gap: float = 0.1):
+    """Systems of planets drawn as in the test-particle workload, one planet
+    at a time: a planet is redrawn until its orbit keeps apart from every
+    planet already placed: the inner apocentre and the outer pericentre at
+    least `min_spacing_hill` mutual Hill radii and `min_gap` AU apart (so
+    that no pair comes near its critical radius and K = 1 holds).  Returns
+    (m, x, u) of shape (nsys, nplanets[, 3])."""
     rng = rng_for(seed_index)
     ms, xs, us = [], [], []
     while len(ms) < nsys:
-        m, a, e, inc = _planets_tp_mode(rng, nplanets)
-        order = np.argsort(a)
-        a_s, m_s = a[order], m[order]
-        rh = 0.5 * (a_s[1:] + a_s[:-1]) * np.cbrt((m_s[1:] + m_s[:-1]) / 3.0)
-        if np.any((a_s[1:] - a_s[:-1]) < min_spacing_hill * rh):
+        m = np.zeros(nplanets)
+        a = np.zeros(nplanets)
+        e = np.zeros(nplanets)
+        inc = np.zeros(nplanets)
+        k, tries = 0, 0
+        while k < nplanets and tries < 200:
+            tries += 1
+            # 64 candidates at a time; the first that fits is placed
+            mc, ac, ec, ic = _planets_tp_mode(rng, 64)
+            A, E, Mm = a[None, :k], e[None, :k], m[None, :k]
+            inner = A < ac[:, None]
+            apo = np.where(inner, A * (1.0 + E), (ac * (1.0 + ec))[:, None])
+            peri = np.where(inner, (ac * (1.0 - ec))[:, None], A * (1.0 - E))
+            rh = 0.5 * (A + ac[:, None]) * np.cbrt((Mm + mc[:, None]) / 3.0)
+            ok = np.all(peri - apo >= np.maximum(min_spacing_hill * rh, min_gap), axis=1)
+            hit = np.flatnonzero(ok)
+            if hit.size == 0:
+                continue
+            c = hit[0]
+            m[k], a[k], e[k], inc[k] = mc[c], ac[c], ec[c], ic[c]
+            k += 1
+        if k < nplanets:
             continue
         x, u = _draw_system(rng, m, a, e, inc)
         ms.append(m)

@@ -1,0 +1,192 @@
+"""GPU parity of the batched mode (independent systems, Sec. 3.4): every
+system of a GPU run against the oracle running that system on its own, with
+its own central mass.  Tolerances as in main mode: 1e-12 relative per body
+after 10 steps; encounter and candidate sets equal."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1404_2324_amd import genga as G
+from paper_1404_2324_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+REL = 1e-12
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _rel(a, b):
+    num = np.linalg.norm(np.asarray(a) - np.asarray(b), axis=-1)
+    den = np.maximum(np.linalg.norm(np.asarray(b), axis=-1), 1e-300)
+    return num / den
+
+
+def _op(gp, m0=1.0):
+    return O.params(G=gp.G, m0=m0, dt=gp.dt, n1=gp.n1, n2=gp.n2, pf=gp.pf,
+                    bs_tol=gp.bs_tol, bs_max_depth=gp.bs_max_depth,
+                    kepler_max_iter=gp.kepler_max_iter, encounter_free=gp.encounter_free)
+
+
+def _oracle_systems(gp, off, m0s, m, x, u, nsteps, which):
+    """The oracle's run of each listed system from heliocentric inputs:
+    (x, v) democratic per system, the encounter pairs of the last step and the
+    candidate pairs entering the next, in global rows."""
+    out = {}
+    for s in which:
+        a, b = int(off[s]), int(off[s + 1])
+        q = _op(gp, float(m0s[s]))
+        sim = O.MassiveSim(q, m[a:b], x[a:b], u[a:b], coords="helio")
+        st = sim.step(nsteps) if nsteps else None
+        cand = sim.candidates()
+        cand = cand[cand[:, 0] < cand[:, 1]] + a
+        out[s] = (sim.x.copy(), sim.v.copy(), sim.enc + a, cand, st)
+    return out
+
+
+def _check_systems(sim, ref, off):
+    x, v = [t.cpu().numpy() for t in sim.state("dem")]
+    worst = 0.0
+    for s, (xo, vo, _, _, _) in ref.items():
+        a, b = int(off[s]), int(off[s + 1])
+        ex, ev = _rel(x[a:b], xo).max(), _rel(v[a:b], vo).max()
+        worst = max(worst, ex, ev)
+        assert ex < REL and ev < REL, f"system {s} ({b - a} bodies): x {ex:.3e} v {ev:.3e}"
+    return worst
+
+
+def test_batch_small_ten_steps_all_systems():
+    off, m0s, m, x, u = W.batched(nsys=96)
+    gp = G.default_params()
+    sim = G.BatchedSimulation(off, m0s, m, x, u, gp)
+    sim.step(10)
+    sim.check()
+    ref = _oracle_systems(gp, off, m0s, m, x, u, 10, range(96))
+    worst = _check_systems(sim, ref, off)
+    st = sim.stats()
+    enc_o = sum(r[4]["enc_total"] for r in ref.values())
+    _say("batch 96: worst rel", worst, "enc gpu/oracle", st["enc_total"], enc_o, "stats", st)
+    assert st["enc_total"] == enc_o and enc_o > 0
+    ij, _, _ = sim.encounters()
+    enc_ref = np.concatenate([r[2] for r in ref.values()]) if ref else np.zeros((0, 2))
+    enc_ref = enc_ref[np.lexsort((enc_ref[:, 1], enc_ref[:, 0]))]
+    np.testing.assert_array_equal(ij, enc_ref)
+    cand_ref = np.concatenate([r[3] for r in ref.values()])
+    cand_ref = cand_ref[np.lexsort((cand_ref[:, 1], cand_ref[:, 0]))]
+    np.testing.assert_array_equal(sim.candidates(), cand_ref)
+
+
+def test_batch_energy_and_conversions():
+    off, m0s, m, x, u = W.batched(nsys=40, seed_index=7)
+    m0s = np.linspace(0.5, 2.0, 40)     # each system its own central mass
+    gp = G.default_params()
+    sim = G.BatchedSimulation(off, m0s, m, x, u, gp)
+    xh, uh = [t.cpu().numpy() for t in sim.state("helio")]
+    np.testing.assert_allclose(xh, x, rtol=0, atol=0)
+    np.testing.assert_allclose(uh, u, rtol=1e-14, atol=1e-16)
+    sim.step(6)
+    sim.check()
+    E, L = sim.energy()
+    ref = _oracle_systems(gp, off, m0s, m, x, u, 6, range(40))
+    _check_systems(sim, ref, off)
+    for s, (xo, vo, _, _, _) in ref.items():
+        a, b = int(off[s]), int(off[s + 1])
+        Eo, Lo = O.energy(_op(gp, float(m0s[s])), m[a:b], xo, vo)
+        # E is a sum of kinetic and potential terms about twice its size;
+        # states agree to ~1e-13, so E to a few 1e-13 of those terms
+        assert abs(E[s] - Eo) <= 1e-11 * abs(Eo)
+        np.testing.assert_allclose(L[s], Lo, rtol=1e-12, atol=1e-18)
+
+
+def test_batch_edge_sizes_and_large_groups():
+    """Systems of 1, 2, 8, 9, 33 and 64 bodies, two of them packed so tightly
+    that groups of more than 8 members form (the lane-per-member BS)."""
+    rng = np.random.default_rng(11)
+    sizes = [1, 2, 8, 9, 33, 64, 12]
+    xs, us, ms = [], [], []
+    for k, n in enumerate(sizes):
+        tight = k in (3, 6)
+        a = (1.0 + 0.004 * rng.standard_normal(n)) if tight else rng.uniform(0.5, 3.0, n)
+        e = np.full(n, 0.01)
+        inc = np.full(n, 0.001) if tight else rng.uniform(0, 0.02, n)
+        node, peri, M = (rng.uniform(0, 2 * np.pi, n) for _ in range(3))
+        if tight:
+            M = 0.02 * rng.standard_normal(n)
+            node = np.zeros(n)
+            peri = np.zeros(n)
+        mm = np.full(n, 1e-7 if tight else 3e-6)
+        xx, uu = W.elements_to_cartesian(1.0 + mm, a, e, inc, node, peri, M)
+        xs.append(xx)
+        us.append(uu)
+        ms.append(mm)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    m, x, u = np.concatenate(ms), np.concatenate(xs), np.concatenate(us)
+    m0s = np.ones(len(sizes))
+    gp = G.default_params()
+    sim = G.BatchedSimulation(off, m0s, m, x, u, gp)
+    sim.step(1)
+    sim.check()
+    st = sim.stats()
+    _say("edge sizes stats", st)
+    assert st["max_group"] > 8
+    ref = _oracle_systems(gp, off, m0s, m, x, u, 1, range(len(sizes)))
+    _check_systems(sim, ref, off)
+    assert st["bs_substeps"] == sum(r[4]["bs_substeps"] for r in ref.values())
+
+
+def test_batch_full_workload_sampled():
+    """The 4096-system workload for 10 steps in one launch; the oracle runs
+    every 32nd system."""
+    off, m0s, m, x, u = W.batched()
+    gp = G.default_params()
+    sim = G.BatchedSimulation(off, m0s, m, x, u, gp)
+    times, choice = sim.tune(2)
+    _say("tuner", choice, times)
+    assert choice in times
+    sim.step(10)
+    sim.check()
+    which = range(0, 4096, 32)
+    ref = _oracle_systems(gp, off, m0s, m, x, u, 10, which)
+    worst = _check_systems(sim, ref, off)
+    _say("4096 sampled worst", worst, sim.stats())
+
+
+def test_batch_split_steps_equal_one_launch_and_deterministic():
+    off, m0s, m, x, u = W.batched(nsys=64, seed_index=9)
+    gp = G.default_params()
+    a = G.BatchedSimulation(off, m0s, m, x, u, gp)
+    b = G.BatchedSimulation(off, m0s, m, x, u, gp)
+    a.step(12)
+    for k in (5, 4, 3):
+        b.step(k)
+    xa, va = a.state("dem")
+    xb, vb = b.state("dem")
+    assert torch.equal(xa, xb) and torch.equal(va, vb)
+    assert a.stats()["steps"] == b.stats()["steps"] == 12
+
+
+def test_batch_set_state_round_trip_and_errors():
+    off, m0s, m, x, u = W.batched(nsys=16, seed_index=10)
+    gp = G.default_params()
+    sim = G.BatchedSimulation(off, m0s, m, x, u, gp)
+    sim.step(3)
+    xs, vs = sim.state("dem")
+    ref = G.BatchedSimulation(off, m0s, m, x, u, gp)
+    ref.set_state(xs, vs, coords="dem")
+    sim.step(2)
+    ref.step(2)
+    assert torch.equal(sim.state("dem")[0], ref.state("dem")[0])
+    bad = off.copy()
+    bad[3] = bad[2]           # an empty system
+    with pytest.raises(G.GengaError) as ei:
+        G.BatchedSimulation(bad, m0s, m, x, u, gp)
+    assert ei.value.code == G.EINVAL
+    big = np.array([0, 65], dtype=np.int32)
+    mm = np.full(65, 1e-9)
+    xx = np.column_stack([np.linspace(1, 2, 65), np.zeros(65), np.zeros(65)])
+    with pytest.raises(G.GengaError):
+        G.BatchedSimulation(big, [1.0], mm, xx, xx * 0 + [0, 1, 0], gp)
+    with pytest.raises(G.GengaError):
+        G.BatchedSimulation(off, -m0s, m, x, u, gp)

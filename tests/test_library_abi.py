@@ -93,3 +93,18 @@ def test_argument_errors_without_device(G):
                         None, None, None, None, G.GENGA_HELIO, None, 0, None) == G.EINVAL
     for code in (G.OK, G.EINVAL, G.EHIP, G.EOVERFLOW, G.EKEPLER, G.EBS, G.ENOMEM, G.EGROUP):
         assert L.genga_strerror(code)
+
+
+def test_batch_workspace_sizing_and_tuner_names(G):
+    L = G.lib()
+    p = G.default_params()
+    b1 = L.genga_workspace_bytes(G.GENGA_BATCH, ctypes.byref(p), 0, 0, 4096, 69632)
+    b2 = L.genga_workspace_bytes(G.GENGA_BATCH, ctypes.byref(p), 0, 0, 8192, 2 * 69632)
+    assert 0 < b1 < b2
+    # 1..64 bodies per system
+    assert L.genga_workspace_bytes(G.GENGA_BATCH, ctypes.byref(p), 0, 0, 10, 9) == 0
+    assert L.genga_workspace_bytes(G.GENGA_BATCH, ctypes.byref(p), 0, 0, 10, 641) == 0
+    assert L.genga_workspace_bytes(G.GENGA_BATCH, ctypes.byref(p), 0, 0, 0, 0) == 0
+    assert L.genga_tune(None, 4, None, 0, None, None) == G.EINVAL
+    names = {L.genga_tune_variant(v).decode() for v in range(6)}
+    assert len(names) == 6 and L.genga_tune_variant(6).decode() == "?"

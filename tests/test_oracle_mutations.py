@@ -31,6 +31,8 @@ MUTANTS = {
                          "int l = label[a] > label[b] ? label[a] : label[b];"),
     "energy_sun_term": ("*E = kin + dot3(P, P) / (2.0 * p->m0) + pot;", "*E = kin + pot;"),
     "precheck_factor": ("cand[(size_t)i * n + j] = r < p->pf * rcij;", "cand[(size_t)i * n + j] = r < rcij;"),
+    "sun_kick_m0": ("for (int k = 0; k < 3; ++k) x[3 * i + k] += h * P[k] / p->m0;",
+                    "for (int k = 0; k < 3; ++k) x[3 * i + k] += h * P[k];"),
     "coll_particle_radius": ("double R = s->rad[0] + s->rad[j];", "double R = s->rad[j];"),
     "coll_end_points_only": ("if (go_hermite_dmin2(h, dx0, dv0, dx1, dv1) < R * R) return j;",
                              "if (dot3(dx1, dx1) < R * R) return j;"),

@@ -630,6 +630,29 @@ def test_tp_removed_particle_leaves_the_others_unchanged():
     assert len(c.removed()) == 0
 
 
+def test_batched_systems_are_single_runs_and_m0_scales():
+    """Sec. 3.4: systems with their own central mass run independently.  A
+    system around m0' = 4 m0 with masses 4 m, velocities 2 v and time step
+    tau / 2 follows the same path (G m0 t^2 / r^3 is unchanged), which pins
+    every place m0 enters (Kepler mu, Sun kick P/m0, Hill radius m/3m0)."""
+    off, m0s, m, x, u = W.batched(nsys=6, seed_index=4)
+    p = O.params()
+    v = np.concatenate([O.helio_to_dem(p, m[off[s]:off[s + 1]], u[off[s]:off[s + 1]])
+                        for s in range(6)])
+    xb, vb, _ = O.batched_run(p, off, m0s, m, x, v, 5)
+    for s in range(6):
+        a, b = off[s], off[s + 1]
+        sim = O.MassiveSim(p, m[a:b], x[a:b], v[a:b])
+        sim.step(5)
+        np.testing.assert_array_equal(sim.x, xb[a:b])
+        np.testing.assert_array_equal(sim.v, vb[a:b])
+    q = O.params(m0=4.0, dt=p.dt / 2)
+    m0s4 = np.full(6, 4.0)
+    x4, v4, _ = O.batched_run(q, off, m0s4, 4 * m, x, 2 * v, 5)
+    np.testing.assert_allclose(x4, xb, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(v4, 2 * vb, rtol=0, atol=1e-14)
+
+
 # ----------------------------------------------- tangent-linear, adjoint -----
 def _adj_system():
     m, x, u = W.adjoint_systems(nsys=1, nplanets=4, seed_index=5)
