@@ -126,6 +126,7 @@ def batch_measure(G, W, torch, steps: int, cpu: bool):
     sim.check()
     sec = e0.elapsed_time(e1) / 1e3
     st = sim.stats()
+    status, done = sim.status()
     sim.close()
     nsys = len(off) - 1
     sizes = np.diff(off)
@@ -135,7 +136,9 @@ def batch_measure(G, W, torch, steps: int, cpu: bool):
            "pair_interactions_per_s": float((sizes * (sizes - 1)).sum()) * steps / sec,
            "tuner": {"choice": choice, "us_per_variant_4_steps": times},
            "enc_total": st["enc_total"], "bs_substeps": st["bs_substeps"],
-           "max_group_last_step": st["max_group"]}
+           "max_group_last_step": st["max_group"],
+           "systems_stopped": int((status != 0).sum()),
+           "system_steps_completed": int(done.sum())}
     if cpu:  # CPU baseline leg: the oracle on a sample of the same systems
         import oracle as O
         t0 = time.perf_counter()

@@ -84,7 +84,8 @@ enum {
     GENGA_EBS = -5,         /* Bulirsch-Stoer depth exhausted               */
     GENGA_EADJ_ENCOUNTER = -6, /* pair inside r_crit in the K = 1 adjoint map */
     GENGA_ENOMEM = -7,      /* workspace smaller than genga_workspace_bytes */
-    GENGA_EGROUP = -8       /* encounter group larger than supported        */
+    GENGA_EGROUP = -8,      /* encounter group larger than supported        */
+    GENGA_WSTOPPED = 1      /* warning, batched mode: some systems stopped   */
 };
 
 /* Fill *p with the defaults: G = 1, m0 = 1, dt = 2 pi / 100, n1 = 3,
@@ -228,6 +229,16 @@ int genga_tune(genga_ctx *ctx, int nsteps, double *h_us, int cap, int *h_n,
 
 /* Description of tuner variant v (static storage). */
 const char *genga_tune_variant(int v);
+
+/* Batched mode: a system whose step fails (Kepler non-convergence, BS depth)
+ * stops there with the state it had before that step, and the others go on
+ * (the paper's multi-simulation mode stops systems individually, Sec. 3.4);
+ * the synchronising calls then return the warning GENGA_WSTOPPED.  Per
+ * system (host arrays of cap entries): h_status the error that stopped it
+ * (GENGA_OK while running), h_steps the steps it completed since init.
+ * Synchronising.  Errors: EINVAL (other mode), EOVERFLOW (cap < n_sys). */
+int genga_batch_status(genga_ctx *ctx, int32_t *h_status, int64_t *h_steps,
+                       int cap);
 
 /* ---- reverse-mode gradient of the encounter-free map ----------------------
  * For a batched context created with encounter_free = 1: the map with K = 1

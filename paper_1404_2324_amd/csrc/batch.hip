@@ -174,8 +174,14 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
   unsigned long long enc_total = 0;
   int kit = 0, nenc = 0, ngrp = 0, maxg = 0;
   unsigned fl = 0u;
-  for (int step = 0; step < a.nsteps; ++step) {
+  // a system stopped by an earlier failure takes no more steps
+  const bool stopped = (a.ss[s].flags & (F_KEPLER | F_BS)) != 0u;
+  int done = 0;
+  for (int step = 0; step < a.nsteps && !stopped; ++step) {
     maxg = 0;
+    // the step-start state is restored if the step fails
+    const double sx = x, sy = y, sz0 = z, svx = vx, svy = vy, svz = vz;
+    const unsigned long long scand = cand;
     const double rc =
         act && !a.enc_free ? rcrit(x, y, z, vx, vy, vz, m, Gm0, m0, a.n1, a.n2, a.absdt) : 0.0;
     double ax, ay, az;
@@ -283,8 +289,21 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
     vx += a.h * ax;
     vy += a.h * ay;
     vz += a.h * az;
+    if (__ballot(fl != 0u) != 0ull) {
+      // the system stops here (the paper's multi-simulation mode stops
+      // systems individually), keeping its last good state
+      x = sx;
+      y = sy;
+      z = sz0;
+      vx = svx;
+      vy = svy;
+      vz = svz;
+      cand = scand;
+      break;
+    }
+    ++done;
   }
-  if (act) {
+  if (act && !stopped) {
     a.xm[o + lane] = make_double4(x, y, z, m);
     a.vv[o + lane] = make_double4(vx, vy, vz, 0.0);
     a.cand[o + lane] = cand;
@@ -293,8 +312,9 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
   unsigned fall = fl;
   for (int o2 = 32; o2 > 0; o2 >>= 1) fall |= __shfl_xor(fall, o2, 64);
   const int kitw = wave_max_i(kit);
-  if (lane == 0 && a.nsteps > 0) {
+  if (lane == 0 && a.nsteps > 0 && !stopped) {
     BatchSysStat& t = a.ss[s];
+    t.steps += done;
     t.sub += (unsigned long long)nsub;
     t.enc_total += enc_total;
     t.nenc = nenc;
@@ -303,7 +323,7 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
     t.kit = max(t.kit, kitw);
     if (fall) {
       t.flags |= fall;
-      atomicOr(a.flags, fall);
+      atomicOr(a.flags, F_SYS_STOP);
     }
   }
 }

@@ -22,6 +22,7 @@ int status_from_flags(unsigned f) {
   if (f & (F_CAND_OVF | F_ENC_OVF | F_TP_OVF)) return GENGA_EOVERFLOW;
   if (f & F_GROUP) return GENGA_EGROUP;
   if (f & F_ADJ_ENC) return GENGA_EADJ_ENCOUNTER;
+  if (f & F_SYS_STOP) return GENGA_WSTOPPED;
   return GENGA_OK;
 }
 
@@ -680,6 +681,20 @@ int genga_tune(genga_ctx* ctx, int nsteps, double* h_us, int cap, int* h_n, int*
 
 const char* genga_tune_variant(int v) { return batch_variant_name(v); }
 
+int genga_batch_status(genga_ctx* ctx, int32_t* h_status, int64_t* h_steps, int cap) {
+  if (!ctx || ctx->mode != GENGA_BATCH || cap < 0 || (cap > 0 && (!h_status || !h_steps)))
+    return GENGA_EINVAL;
+  std::vector<BatchSysStat> ss((size_t)ctx->b.nsys);
+  HIPCHK(hipMemcpyAsync(ss.data(), ctx->b.ss, ss.size() * sizeof(BatchSysStat),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int s = 0; s < std::min(cap, ctx->b.nsys); ++s) {
+    h_status[s] = status_from_flags(ss[s].flags & ~F_SYS_STOP);
+    h_steps[s] = ss[s].steps;
+  }
+  return cap < ctx->b.nsys ? GENGA_EOVERFLOW : GENGA_OK;
+}
+
 static bool adj_ok(const genga_ctx* ctx) {
   return ctx && ctx->mode == GENGA_BATCH && ctx->p.encounter_free;
 }
@@ -731,6 +746,7 @@ const char* genga_strerror(int code) {
     case GENGA_EADJ_ENCOUNTER: return "pair inside the critical radius in the encounter-free adjoint";
     case GENGA_ENOMEM: return "workspace too small";
     case GENGA_EGROUP: return "encounter group too large";
+    case GENGA_WSTOPPED: return "some systems stopped after a failed step (see genga_batch_status)";
     default: return "unknown error";
   }
 }

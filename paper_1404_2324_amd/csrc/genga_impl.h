@@ -19,6 +19,7 @@ enum : unsigned {
   F_GROUP = 16u,       // group larger than the in-wave BS limit
   F_TP_OVF = 32u,      // more massive bodies than the test-particle mask holds
   F_ADJ_ENC = 64u,     // a pair inside r_crit during the encounter-free map
+  F_SYS_STOP = 128u,   // batched: a system stopped after a failed step (warning)
 };
 // control bits
 enum : unsigned { C_FULLKICK = 1u };
@@ -179,6 +180,7 @@ hipError_t tp_set_radii(const TpWs& t, int nm, const double* r, int* dbad, hipSt
 
 // ---- batched independent systems (batch.hip) --------------------------------
 struct BatchSysStat {
+  long long steps;               // steps completed since init
   unsigned long long sub;        // accepted BS substeps since init
   unsigned long long enc_total;  // encounters since init
   int nenc;                      // encounters of the last step

@@ -19,6 +19,7 @@ GENGA_MASSIVE, GENGA_TEST, GENGA_BATCH = 0, 1, 2
 GENGA_HELIO, GENGA_DEMOCRATIC = 0, 1
 OK, EINVAL, EHIP, EOVERFLOW, EKEPLER, EBS, EADJ_ENCOUNTER, ENOMEM, EGROUP = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
+WSTOPPED = 1  # warning: batched systems stopped after a failed step
 
 
 class GengaError(RuntimeError):
@@ -72,6 +73,7 @@ SIGNATURES = {
     "genga_set_radii": (_i32, [_vp, _vp]),
     "genga_tune": (_i32, [_vp, _i32, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "genga_tune_variant": (ctypes.c_char_p, [_i32]),
+    "genga_batch_status": (_i32, [_vp, _vp, _vp, _i32]),
     "genga_adj_buffer_bytes": (_sz, [_vp, _i64, _i32]),
     "genga_adj_forward": (_i32, [_vp, _i64, _i32, _vp, _sz]),
     "genga_adj_backward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
@@ -103,7 +105,8 @@ def lib():
 
 
 def _check(code, what):
-    if code != OK:
+    """Errors are negative; positive codes are warnings (see check())."""
+    if code < 0:
         raise GengaError(code, what)
 
 
@@ -168,7 +171,11 @@ class Simulation:
         return lib().genga_sync(self._ctx)
 
     def check(self):
-        _check(self.sync(), "device status")
+        """Raise on a latched error; return the status (warnings are > 0)."""
+        code = self.sync()
+        if code < 0:
+            _check(code, "device status")
+        return code
 
     def state(self, coords: str = "dem"):
         x = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
@@ -380,6 +387,14 @@ class BatchedSimulation(Simulation):
         _check(lib().genga_energy(self._ctx, _ptr(E), _ptr(L)), "genga_energy")
         torch.cuda.synchronize(self.device)
         return E.cpu().numpy(), L.cpu().numpy().reshape(-1, 3)
+
+    def status(self):
+        """Per system: (status code, steps completed since init)."""
+        st = np.zeros(self.nsys, dtype=np.int32)
+        ns = np.zeros(self.nsys, dtype=np.int64)
+        _check(lib().genga_batch_status(self._ctx, st.ctypes.data, ns.ctypes.data, self.nsys),
+               "genga_batch_status")
+        return st, ns
 
     def tune(self, nsteps: int = 4):
         """Re-run the tuner; returns ({variant: microseconds}, chosen variant)."""

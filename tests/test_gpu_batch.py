@@ -190,3 +190,43 @@ def test_batch_set_state_round_trip_and_errors():
         G.BatchedSimulation(big, [1.0], mm, xx, xx * 0 + [0, 1, 0], gp)
     with pytest.raises(G.GengaError):
         G.BatchedSimulation(off, -m0s, m, x, u, gp)
+
+
+def test_batch_failing_system_stops_alone():
+    """A head-on collision (no radii) exhausts the BS depth in its system: that
+    system stops with the state before the failing step, the warning is
+    returned, and every other system completes its steps unchanged."""
+    off, m0s, m, x, u = W.batched(nsys=8, seed_index=12)
+    # system 3 becomes two bodies falling straight onto each other
+    a, b = off[3], off[4]
+    keep = np.r_[0:a + 2, b:len(m)]
+    m, x, u = m[keep].copy(), x[keep].copy(), u[keep].copy()
+    sizes = np.diff(off)
+    sizes[3] = 2
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    a = off[3]
+    m[a:a + 2] = 1e-5
+    x[a] = [1.0, 0.0, 0.0]
+    x[a + 1] = [1.0, 0.004, 0.0]
+    vc = np.sqrt(1.0 + 1e-5)
+    u[a] = [0.0, vc + 0.05, 0.0]
+    u[a + 1] = [0.0, vc - 0.05, 0.0]
+    gp = G.default_params()
+    sim = G.BatchedSimulation(off, m0s, m, x, u, gp)
+    sim.step(10)
+    assert sim.check() == G.WSTOPPED
+    st, ns = sim.status()
+    _say("status", st, "steps", ns)
+    assert st[3] == G.EBS and 0 <= ns[3] < 10
+    others = [s for s in range(8) if s != 3]
+    assert np.all(st[others] == G.OK) and np.all(ns[others] == 10)
+    ref = _oracle_systems(gp, off, m0s, m, x, u, 10, others)
+    _check_systems(sim, ref, off)
+    stop = _oracle_systems(gp, off, m0s, m, x, u, int(ns[3]), [3])
+    _check_systems(sim, stop, off)
+    with pytest.raises(O.OracleError):
+        _oracle_systems(gp, off, m0s, m, x, u, int(ns[3]) + 1, [3])
+    # a further call leaves the stopped system where it is
+    sim.step(3)
+    st2, ns2 = sim.status()
+    assert ns2[3] == ns[3] and np.all(ns2[others] == 13)

@@ -106,5 +106,7 @@ def test_batch_workspace_sizing_and_tuner_names(G):
     assert L.genga_workspace_bytes(G.GENGA_BATCH, ctypes.byref(p), 0, 0, 10, 641) == 0
     assert L.genga_workspace_bytes(G.GENGA_BATCH, ctypes.byref(p), 0, 0, 0, 0) == 0
     assert L.genga_tune(None, 4, None, 0, None, None) == G.EINVAL
+    assert L.genga_batch_status(None, None, None, 0) == G.EINVAL
+    assert b"stopped" in L.genga_strerror(G.WSTOPPED)
     names = {L.genga_tune_variant(v).decode() for v in range(6)}
     assert len(names) == 6 and L.genga_tune_variant(6).decode() == "?"
