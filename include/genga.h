@@ -147,11 +147,12 @@ int genga_init(genga_ctx **ctx, int mode, const genga_params *p,
  * errors latch in the device status.  nsteps >= 0. */
 int genga_step(genga_ctx *ctx, int64_t nsteps);
 
-/* Measurement form of genga_step: the same nsteps steps launched one kernel
- * at a time (no graph) on the context's stream, the closing-kick pair kernel
- * through hipExtLaunchKernel with two HIP events that take its dispatch's
- * start and end timestamps; *h_kick_us receives that kernel's average
- * duration in microseconds.  Synchronising; returns the latched status. */
+/* Measurement form of genga_step: the same nsteps (1..4096) steps launched
+ * one kernel at a time (no graph) on the context's stream, back to back, the
+ * closing-kick pair kernel through hipExtLaunchKernel with two HIP events
+ * that take its dispatch's start and end timestamps; *h_kick_us receives
+ * that kernel's average duration in microseconds.  Synchronising; returns
+ * the latched status. */
 int genga_step_profiled(genga_ctx *ctx, int64_t nsteps, double *h_kick_us);
 
 /* Wait for the context's stream and return the latched device status as a

@@ -178,6 +178,21 @@ struct ParBody {
   double i09[P];   // 1 / (0.9 rc_ij), 0 when rc_ij = 0
 };
 
+// Lane shuffles of a double: generic (ds_bpermute) or, for a source lane a
+// fixed distance away inside the same row of 16 lanes, a DPP move.
+__device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src, 64); }
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int2 p = *reinterpret_cast<int2*>(&v);
+  int2 q;
+  q.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, 0xF, 0xF, true);
+  q.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, 0xF, 0xF, true);
+  return *reinterpret_cast<double*>(&q);
+}
+constexpr int kDppQuadSwap1 = 0xB1;     // quad_perm [1,0,3,2]: lane ^ 1
+constexpr int kDppRowShr2 = 0x112;      // row_shr:2: lane - 2 inside the row
+
 template <int P, bool TP>
 __device__ __forceinline__ void ha_accel_par(int sz, int b, double x, double y,
                                              double z, const ParBody<P>& Q,
@@ -193,9 +208,16 @@ __device__ __forceinline__ void ha_accel_par(int sz, int b, double x, double y,
 #pragma unroll
   for (int q = 1; q < P; ++q) {
     if (q >= sz) break;
-    const double xj = __shfl(x, Q.lane[q], 64);
-    const double yj = __shfl(y, Q.lane[q], 64);
-    const double zj = __shfl(z, Q.lane[q], 64);
+    double xj, yj, zj;
+    if (P == 2) {  // the partner is lane ^ 1
+      xj = dpp_d<kDppQuadSwap1>(x);
+      yj = dpp_d<kDppQuadSwap1>(y);
+      zj = dpp_d<kDppQuadSwap1>(z);
+    } else {
+      xj = shfl_d(x, Q.lane[q]);
+      yj = shfl_d(y, Q.lane[q]);
+      zj = shfl_d(z, Q.lane[q]);
+    }
     if (q < np) {
       const double dx = xj - x, dy = yj - y, dz = zj - z;
       const double q2 = dx * dx + dy * dy + dz * dz;
@@ -211,6 +233,15 @@ __device__ __forceinline__ void ha_accel_par(int sz, int b, double x, double y,
   }
 }
 
+// |A - B| <= tol |A| (|A - B| <= tol when A = 0), squared: the per-body
+// relative-change test without square roots or divisions.
+__device__ __forceinline__ bool within3(const double* A, const double* B, double tol2) {
+  const double d0 = A[0] - B[0], d1 = A[1] - B[1], d2 = A[2] - B[2];
+  const double n2 = d0 * d0 + d1 * d1 + d2 * d2;
+  const double a2 = A[0] * A[0] + A[1] * A[1] + A[2] * A[2];
+  return n2 <= tol2 * (a2 > 0.0 ? a2 : 1.0);
+}
+
 // One speculative round: returns the accepted depth offset (0..S-1), with the
 // accepted state in y, or -1 when every slot failed.
 template <int P, bool TP>
@@ -223,6 +254,8 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
   const int b = lane % P;
   const int nsub = 2 * (c + 1);
   const double hs = ldexp(H, -s) / nsub;
+  const double tol2 = tol >= 0.0 ? tol * tol : -1.0;  // a negative tolerance accepts nothing
+  constexpr unsigned long long kMemb = (1ull << P) - 1ull;
   double ym[6], yn[6], T0[6], yacc[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
@@ -231,7 +264,7 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
     T0[q] = y[q];
     yacc[q] = y[q];
   }
-  bool acc = false;  // this slot has accepted a column
+  unsigned accm = 0u;  // slots that have accepted a column (bit s)
   for (int e = 0; e <= 2 * kBsCols; ++e) {
     double d[6];
     ha_accel_par<P, TP>(sz, b, yn[0], yn[1], yn[2], Q, G, Gm0, d[3], d[4], d[5]);
@@ -254,6 +287,8 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
     }
     if (e >= 4 && (e & 1) == 0) {
       const int k = e / 2 - 1;  // column completed by this evaluation
+      // Aitken-Neville across the columns: T[c][j] needs T[c-1][j-1] (lane - P);
+      // weight 1/((n_c/n_{c-j})^2 - 1) = (c-j+1)^2 / ((c+1)^2 - (c-j+1)^2)
       double cur[6], diag[6], sub[6];
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
@@ -264,49 +299,48 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
       for (int j = 1; j <= k; ++j) {
         double nb[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) nb[q] = __shfl(cur[q], lane - (c >= 1 ? P : 0), 64);
+        for (int q = 0; q < 6; ++q)
+          nb[q] = P == 2 ? dpp_d<kDppRowShr2>(cur[q]) : shfl_d(cur[q], lane - (c >= 1 ? P : 0));
         if (j <= c) {
-          const double ratio = (double)(2 * (c + 1)) / (double)(2 * (c - j + 1));
-          const double den = ratio * ratio - 1.0;
+          const int pp = c + 1, qq = c - j + 1;
+          const double w = (double)(qq * qq) / (double)(pp * pp - qq * qq);
 #pragma unroll
           for (int q = 0; q < 6; ++q) {
             if (j == c) sub[q] = cur[q];
-            cur[q] = cur[q] + (cur[q] - nb[q]) / den;
+            cur[q] = cur[q] + (cur[q] - nb[q]) * w;
             if (j == c) diag[q] = cur[q];
           }
         }
       }
-      double err = 0.0;
-      if (c == k && b < sz) err = fmax(relerr3(diag, sub), relerr3(diag + 3, sub + 3));
+      // column k of every slot: accepted unless one of its members fails
+      const bool bad = c == k && b < sz && !(within3(diag, sub, tol2) && within3(diag + 3, sub + 3, tol2));
+      const unsigned long long badm = __ballot(bad);
+      unsigned now = 0u;
 #pragma unroll
-      for (int o = 1; o < P; o <<= 1) err = fmax(err, __shfl_xor(err, o, 64));
-      // err of column k of this lane's slot, from lane (s, k, 0)
-      const double ek = __shfl(err, s * kBsPar * P + k * P, 64);
-      const bool now = !acc && ek <= tol;
-      double got[6];
-#pragma unroll
-      for (int q = 0; q < 6; ++q) got[q] = __shfl(diag[q], s * kBsPar * P + k * P + b, 64);
+      for (int t = 0; t < kBsPar / P; ++t)
+        if (!((accm >> t) & 1u) && ((badm >> (t * kBsPar * P + k * P)) & kMemb) == 0ull)
+          now |= 1u << t;
       if (now) {
+        // the accepted state of this slot's column k, for every lane of the slot
 #pragma unroll
-        for (int q = 0; q < 6; ++q) yacc[q] = got[q];
-        acc = true;
+        for (int q = 0; q < 6; ++q) {
+          const double g = shfl_d(diag[q], s * kBsPar * P + k * P + b);
+          if ((now >> s) & 1u) yacc[q] = g;
+        }
+        accm |= now;
       }
       // slot 0 decided: nothing can precede it
-      if (__ballot(acc && lane == 0) != 0ull) break;
+      if (accm & 1u) break;
     }
   }
   // first accepted slot in sequential order
-  const unsigned long long am = __ballot(acc && c == 0 && b == 0);
-  if (am == 0ull) return -1;
-  const int sacc = (__ffsll((long long)am) - 1) / (kBsPar * P);
+  if (accm == 0u) return -1;
+  const int sacc = __ffs(accm) - 1;
 #pragma unroll
-  for (int q = 0; q < 6; ++q) y[q] = __shfl(yacc[q], sacc * kBsPar * P + b, 64);
+  for (int q = 0; q < 6; ++q) y[q] = shfl_d(yacc[q], sacc * kBsPar * P + b);
   return sacc;
 }
 
-// Binary refinement over [0, H] with speculative depths: a round at depth d
-// also tries d+1..d+S-1 on the first halves, which is where the sequential
-// scheme goes after failures.
 // Test-particle groups (TP) with R2 >= 0 in some lane: after each accepted
 // substep, lane b (a planet member) tests its separation from member 0 over
 // the substep with the Hermite rule; below sqrt(R2) (the sum of the radii)

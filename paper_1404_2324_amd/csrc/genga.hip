@@ -388,25 +388,28 @@ int genga_step(genga_ctx* ctx, int64_t nsteps) {
 }
 
 int genga_step_profiled(genga_ctx* ctx, int64_t nsteps, double* h_kick_us) {
-  if (!ctx || nsteps < 1 || !h_kick_us || ctx->mode == GENGA_BATCH) return GENGA_EINVAL;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIPCHK(hipEventCreate(&e0));
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return GENGA_EHIP;
+  if (!ctx || nsteps < 1 || nsteps > 4096 || !h_kick_us || ctx->mode == GENGA_BATCH)
+    return GENGA_EINVAL;
+  // one event pair per step, read after the last step: the steps run back to
+  // back as in a graph replay (no host round trip between them)
+  std::vector<hipEvent_t> ev((size_t)(2 * nsteps), nullptr);
+  int rc = GENGA_OK;
+  for (auto& e : ev)
+    if (rc == GENGA_OK && hipEventCreate(&e) != hipSuccess) rc = GENGA_EHIP;
+  for (int64_t k = 0; k < nsteps && rc == GENGA_OK; ++k) {
+    if (massive_step(ctx->w, ctx->c, ctx->stream, ev[2 * k], ev[2 * k + 1]) != hipSuccess ||
+        (ctx->mode == GENGA_TEST && tp_step(ctx->w, ctx->t, ctx->c, ctx->stream) != hipSuccess))
+      rc = GENGA_EHIP;
   }
   double tot = 0.0;
-  int rc = GENGA_OK;
+  if (rc == GENGA_OK && hipEventSynchronize(ev.back()) != hipSuccess) rc = GENGA_EHIP;
   for (int64_t k = 0; k < nsteps && rc == GENGA_OK; ++k) {
     float ms = 0.0f;
-    if (massive_step(ctx->w, ctx->c, ctx->stream, e0, e1) != hipSuccess ||
-        (ctx->mode == GENGA_TEST && tp_step(ctx->w, ctx->t, ctx->c, ctx->stream) != hipSuccess) ||
-        hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-      rc = GENGA_EHIP;
+    if (hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) != hipSuccess) rc = GENGA_EHIP;
     tot += ms;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
   if (rc != GENGA_OK) return rc;
   ctx->steps += nsteps;
   *h_kick_us = tot * 1e3 / (double)nsteps;
