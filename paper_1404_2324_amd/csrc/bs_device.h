@@ -264,6 +264,14 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
     T0[q] = y[q];
     yacc[q] = y[q];
   }
+  // Neville weights of this lane's column: 1/((n_c/n_{c-j})^2 - 1) =
+  // (c-j+1)^2 / ((c+1)^2 - (c-j+1)^2), j = 1..c
+  double wj[kBsCols];
+#pragma unroll
+  for (int j = 1; j < kBsCols; ++j) {
+    const int pp = c + 1, qq = c - j + 1;
+    wj[j] = j <= c ? (double)(qq * qq) / (double)(pp * pp - qq * qq) : 0.0;
+  }
   unsigned accm = 0u;  // slots that have accepted a column (bit s)
   for (int e = 0; e <= 2 * kBsCols; ++e) {
     double d[6];
@@ -271,13 +279,12 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
     d[0] = yn[3];
     d[1] = yn[4];
     d[2] = yn[5];
-    if (e == 0) {
-#pragma unroll
-      for (int q = 0; q < 6; ++q) yn[q] = ym[q] + hs * d[q];
-    } else if (e < nsub) {
+    if (e < nsub) {
+      // first substep y0 + hs f(y0) (ym = yn = y0 then), later ym + 2 hs f(yn)
+      const double hf = e == 0 ? hs : 2.0 * hs;
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
-        const double t = ym[q] + 2.0 * hs * d[q];
+        const double t = ym[q] + hf * d[q];
         ym[q] = yn[q];
         yn[q] = t;
       }
@@ -287,8 +294,7 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
     }
     if (e >= 4 && (e & 1) == 0) {
       const int k = e / 2 - 1;  // column completed by this evaluation
-      // Aitken-Neville across the columns: T[c][j] needs T[c-1][j-1] (lane - P);
-      // weight 1/((n_c/n_{c-j})^2 - 1) = (c-j+1)^2 / ((c+1)^2 - (c-j+1)^2)
+      // Aitken-Neville across the columns: T[c][j] needs T[c-1][j-1] (lane - P)
       double cur[6], diag[6], sub[6];
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
@@ -296,14 +302,15 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
         diag[q] = T0[q];
         sub[q] = T0[q];
       }
-      for (int j = 1; j <= k; ++j) {
+#pragma unroll
+      for (int j = 1; j < kBsCols; ++j) {
+        if (j > k) break;
         double nb[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q)
           nb[q] = P == 2 ? dpp_d<kDppRowShr2>(cur[q]) : shfl_d(cur[q], lane - (c >= 1 ? P : 0));
         if (j <= c) {
-          const int pp = c + 1, qq = c - j + 1;
-          const double w = (double)(qq * qq) / (double)(pp * pp - qq * qq);
+          const double w = wj[j];
 #pragma unroll
           for (int q = 0; q < 6; ++q) {
             if (j == c) sub[q] = cur[q];
