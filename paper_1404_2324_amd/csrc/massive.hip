@@ -48,6 +48,30 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// Three such sums with one pair of barriers; sh holds 3 NT/64 doubles.
+template <int NT>
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh) {
+  constexpr int NW = NT / 64;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sh[w] = a;
+    sh[NW + w] = b;
+    sh[2 * NW + w] = c;
+  }
+  __syncthreads();
+  a = b = c = 0.0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    a += sh[k];
+    b += sh[NW + k];
+    c += sh[2 * NW + k];
+  }
+}
+
 // ---------------------------------------------------------------------------
 struct KickArgs {
   const double4* __restrict__ xm;     // read by the pair kernel
@@ -292,7 +316,7 @@ __device__ __forceinline__ void pair_hb(double xi, double yi, double zi,
 // sum is taken instead.  Also installs the step's radii and thresholds and
 // leaves per-block momentum partials for the Sun kick.
 __global__ __launch_bounds__(kVecBlock) void k_kick_open(OpenArgs a) {
-  __shared__ double sh[kVecBlock / 64];
+  __shared__ double sh[3 * (kVecBlock / 64)];
   const int i = blockIdx.x * kVecBlock + threadIdx.x;
   const bool iv = i < a.n;
   const bool full = (__builtin_amdgcn_readfirstlane(a.st->ctl) & C_FULLKICK) != 0;
@@ -368,9 +392,8 @@ __global__ __launch_bounds__(kVecBlock) void k_kick_open(OpenArgs a) {
     vy = v.y;
     vz = v.z;
   }
-  const double Px = block_sum<kVecBlock>(m * vx, sh);
-  const double Py = block_sum<kVecBlock>(m * vy, sh);
-  const double Pz = block_sum<kVecBlock>(m * vz, sh);
+  double Px = m * vx, Py = m * vy, Pz = m * vz;
+  block_sum3<kVecBlock>(Px, Py, Pz, sh);
   if (threadIdx.x == 0) {
     a.partP[4 * blockIdx.x + 0] = Px;
     a.partP[4 * blockIdx.x + 1] = Py;
@@ -399,7 +422,7 @@ struct DriftArgs {
 // leaves the momentum partials of the drifted velocities for the second Sun
 // kick and resets the step's encounter counters and control word.
 __global__ __launch_bounds__(kVecBlock) void k_drift(DriftArgs a) {
-  __shared__ double sh[kVecBlock / 64];
+  __shared__ double sh[3 * (kVecBlock / 64)];
   double Px = 0.0, Py = 0.0, Pz = 0.0;
   for (int b = 0; b < a.nblk; ++b) {
     Px += a.partP[4 * b + 0];
@@ -432,9 +455,8 @@ __global__ __launch_bounds__(kVecBlock) void k_drift(DriftArgs a) {
   }
   const int itm = wave_max_i(abs(it));
   if ((threadIdx.x & 63) == 0 && itm > 0) atomicMax(&a.st->kep_itmax, itm);
-  const double Qx = block_sum<kVecBlock>(m * vx, sh);
-  const double Qy = block_sum<kVecBlock>(m * vy, sh);
-  const double Qz = block_sum<kVecBlock>(m * vz, sh);
+  double Qx = m * vx, Qy = m * vy, Qz = m * vz;
+  block_sum3<kVecBlock>(Qx, Qy, Qz, sh);
   if (threadIdx.x == 0) {
     a.partP2[4 * blockIdx.x + 0] = Qx;
     a.partP2[4 * blockIdx.x + 1] = Qy;
