@@ -54,6 +54,7 @@ constexpr int kBsMaxGroup = 64;        // members per in-wave BS group
 constexpr int kGroupMaxN = 2048;       // bodies the one-workgroup grouping holds
 constexpr int kEncLds = 2048;          // encounter pairs grouped in LDS
 constexpr int kKickWaves = 8;          // waves per kick workgroup
+constexpr int kKickTarget = 512;       // kick workgroups aimed for (j-blocks x i-tiles)
 constexpr int kKickIpl = 1;            // i-bodies per lane in the kick
 constexpr int kVecBlock = 256;         // threads of the per-body kernels
 

@@ -105,8 +105,13 @@ enum { KICK_CLOSE = 0, KICK_INIT = 1, KICK_ACC = 2 };
 // writes its j-block partials; k_kick_finish combines them in a fixed order
 // (a kernel boundary instead of a device-scope fence per workgroup, which
 // costs an L2 write-back on this multi-XCD part).
+// xm and thr come as kernel arguments of their own: as noalias parameters the
+// compiler can prove the wave-uniform j loads invariant and issue them as
+// scalar loads (struct members do not carry that guarantee).
 template <int MODE>
-__global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a) {
+__global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a,
+                                                          const double4* __restrict__ xmj,
+                                                          const double* __restrict__ thrj) {
   constexpr int W = kKickWaves;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -128,10 +133,7 @@ __global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a) {
   const int je = min(j1, js + wl);
 
   double fx = 0.0, fy = 0.0, fz = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
-#pragma unroll 4
-  for (int j = js; j < je; ++j) {
-    const double4 pj = a.xm[j];
-    const double tj = a.thr[j];
+  auto pair = [&](const double4& pj, double tj, int j) {
     const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
     const double r2 = dx * dx + dy * dy + dz * dz;
     const double ir = rsqrt_nr(r2);
@@ -159,7 +161,19 @@ __global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a) {
         }
       }
     }
+  };
+  // four partners per round trip of the scalar loads (the scalar cache
+  // returns out of order, so every use waits for all loads in flight)
+  int j = js;
+  for (; j + 3 < je; j += 4) {
+    const double4 p0 = xmj[j], p1 = xmj[j + 1], p2 = xmj[j + 2], p3 = xmj[j + 3];
+    const double t0 = thrj[j], t1 = thrj[j + 1], t2 = thrj[j + 2], t3 = thrj[j + 3];
+    pair(p0, t0, j);
+    pair(p1, t1, j + 1);
+    pair(p2, t2, j + 2);
+    pair(p3, t3, j + 3);
   }
+  for (; j < je; ++j) pair(xmj[j], thrj[j], j);
 
   if (MODE == KICK_CLOSE && blockIdx.x == 0 && blockIdx.y == 0 && wave == 0) {
     // momentum after the drift and BS for the second Sun kick: drift partials
@@ -193,8 +207,7 @@ __global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a) {
   sh[wave][4][lane] = ny;
   sh[wave][5][lane] = nz;
   __syncthreads();
-  if (threadIdx.x < 6 * 64) {
-    const int c = threadIdx.x >> 6;
+  for (int c = threadIdx.x >> 6; c < 6; c += W) {
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < W; ++w) t += sh[w][c][lane];
@@ -1033,7 +1046,7 @@ StepConsts make_consts(const genga_params& p) {
 
 static void kick_shape(int n, int& nitile, int& njb, int& jb_len) {
   nitile = ceil_div(n, 64);
-  const int by_target = ceil_div(512, nitile);
+  const int by_target = ceil_div(kKickTarget, nitile);
   const int by_len = ceil_div(n, kKickWaves * 16);
   njb = std::max(1, std::min(by_target, by_len));
   jb_len = ceil_div(n, njb);
@@ -1115,7 +1128,8 @@ hipError_t massive_prime(const MassiveWs& w, const StepConsts& c, hipStream_t s)
                      w.rc_cur, w.thr, w.ccnt, w.n, c.mu, c.m0, c.n1, c.n2, fabs(c.dt),
                      c.pf2, c.encounter_free);
   KickArgs a = kick_args(w, c);
-  hipLaunchKernelGGL(k_kick<KICK_INIT>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
+  hipLaunchKernelGGL(k_kick<KICK_INIT>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a,
+                     a.xm, a.thr);
   hipLaunchKernelGGL(k_kick_finish<KICK_INIT>, dim3(ceil_div(4 * w.n, kVecBlock)), dim3(kVecBlock), 0, s, a, w.njb);
   return hipGetLastError();
 }
@@ -1124,7 +1138,8 @@ hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, double* acc,
                          hipStream_t s) {
   KickArgs a = kick_args(w, c);
   a.acc_out = acc;
-  hipLaunchKernelGGL(k_kick<KICK_ACC>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
+  hipLaunchKernelGGL(k_kick<KICK_ACC>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a,
+                     a.xm, a.thr);
   hipLaunchKernelGGL(k_kick_finish<KICK_ACC>, dim3(ceil_div(4 * w.n, kVecBlock)), dim3(kVecBlock), 0, s, a, w.njb);
   return hipGetLastError();
 }
@@ -1215,9 +1230,10 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
   if (ev0 && ev1)
     // the events take the dispatch's own start and end timestamps
     hipExtLaunchKernelGGL(k_kick<KICK_CLOSE>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s,
-                          ev0, ev1, 0, a);
+                          ev0, ev1, 0, a, (const double4*)a.xm, (const double*)a.thr);
   else
-    hipLaunchKernelGGL(k_kick<KICK_CLOSE>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a);
+    hipLaunchKernelGGL(k_kick<KICK_CLOSE>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a,
+                       a.xm, a.thr);
   hipLaunchKernelGGL(k_kick_finish<KICK_CLOSE>, dim3(ceil_div(4 * w.n, kVecBlock)), dim3(kVecBlock), 0, s, a, w.njb);
   return hipGetLastError();
 }

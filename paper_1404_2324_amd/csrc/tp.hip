@@ -78,8 +78,9 @@ struct TpArgs {
 // Kick of H_B on a particle from the planets (Eq. 2 gradient, K from the pair
 // radius max(rct, rc_j)); positions from p (w = mass).
 __device__ __forceinline__ void tp_kick_acc(const TpArgs& a, const double4* __restrict__ p,
-                                            double x, double y, double z, double rct,
-                                            double& ax, double& ay, double& az) {
+                                            const double* __restrict__ prc, double x, double y,
+                                            double z, double rct, double& ax, double& ay,
+                                            double& az) {
   ax = ay = az = 0.0;
   for (int j = 0; j < a.nm; ++j) {
     const double4 pj = p[j];
@@ -89,7 +90,7 @@ __device__ __forceinline__ void tp_kick_acc(const TpArgs& a, const double4* __re
     const double ir2 = ir * ir;
     double K = 1.0, dK = 0.0;
     if (!a.enc_free) {
-      const double rcij = fmax(rct, a.rc[j]);
+      const double rcij = fmax(rct, prc[j]);
       if (r2 < rcij * rcij) changeover(r2 * ir, rcij, K, dK);
     }
     const double s = pj.w * (K * ir2 * ir - dK * ir2);
@@ -103,23 +104,25 @@ __device__ __forceinline__ void tp_kick_acc(const TpArgs& a, const double4* __re
 }
 
 // Second Sun kick, closing kick, new candidate mask; writes the particle.
-__device__ __forceinline__ void tp_finish(const TpArgs& a, int64_t k, double x, double y,
-                                          double z, double vx, double vy, double vz,
+// pfin, prc: the planets at the end of the step and their radii.
+__device__ __forceinline__ void tp_finish(const TpArgs& a, const double4* __restrict__ pfin,
+                                          const double* __restrict__ prc, int64_t k, double x,
+                                          double y, double z, double vx, double vy, double vz,
                                           double rct, double P2x, double P2y, double P2z) {
   x += a.h * P2x / a.m0;
   y += a.h * P2y / a.m0;
   z += a.h * P2z / a.m0;
   double ax, ay, az;
-  tp_kick_acc(a, a.pfin, x, y, z, rct, ax, ay, az);
+  tp_kick_acc(a, pfin, prc, x, y, z, rct, ax, ay, az);
   vx += a.h * ax;
   vy += a.h * ay;
   vz += a.h * az;
   unsigned msk = 0u;
   if (!a.enc_free) {
     for (int j = 0; j < a.nm; ++j) {
-      const double4 pj = a.pfin[j];
+      const double4 pj = pfin[j];
       const double dx = pj.x - x, dy = pj.y - y, dz = pj.z - z;
-      const double rcij = fmax(rct, a.rc[j]);
+      const double rcij = fmax(rct, prc[j]);
       if (dx * dx + dy * dy + dz * dz < a.pf2 * rcij * rcij) msk |= 1u << j;
     }
   }
@@ -132,7 +135,15 @@ __device__ __forceinline__ void tp_finish(const TpArgs& a, int64_t k, double x, 
   a.mask[k] = msk;
 }
 
-__global__ __launch_bounds__(256) void k_tp_main(TpArgs a) {
+// The planets' arrays come as kernel arguments of their own: as noalias
+// parameters their wave-uniform loads become scalar loads.
+__global__ __launch_bounds__(256) void k_tp_main(TpArgs a, const double4* __restrict__ px0,
+                                                 const double4* __restrict__ pfin,
+                                                 const double4* __restrict__ ppre,
+                                                 const double4* __restrict__ vpre,
+                                                 const double4* __restrict__ ppost,
+                                                 const double4* __restrict__ vpost,
+                                                 const double* __restrict__ prc) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int lane = threadIdx.x & 63;
   double P1x = 0.0, P1y = 0.0, P1z = 0.0;
@@ -154,7 +165,7 @@ __global__ __launch_bounds__(256) void k_tp_main(TpArgs a) {
     const unsigned cmask = a.mask[k];
     rct = a.n2 * a.absdt * sqrt(vx * vx + vy * vy + vz * vz);
     double ax, ay, az;
-    tp_kick_acc(a, a.px0, x, y, z, rct, ax, ay, az);
+    tp_kick_acc(a, px0, prc, x, y, z, rct, ax, ay, az);
     vx += a.h * ax;
     vy += a.h * ay;
     vz += a.h * az;
@@ -172,19 +183,19 @@ __global__ __launch_bounds__(256) void k_tp_main(TpArgs a) {
     if (!a.enc_free && cmask) {
       for (int j = 0; j < a.nm; ++j) {
         if (!(cmask & (1u << j))) continue;
-        const double4 p0 = a.ppre[j], q0 = a.vpre[j], p1 = a.ppost[j], q1 = a.vpost[j];
+        const double4 p0 = ppre[j], q0 = vpre[j], p1 = ppost[j], q1 = vpost[j];
         const double d2 = hermite_dmin2(a.dt, p0.x - xm0, p0.y - ym0, p0.z - zm0,
                                         q0.x - vxm, q0.y - vym, q0.z - vzm,
                                         p1.x - x, p1.y - y, p1.z - z,
                                         q1.x - vx, q1.y - vy, q1.z - vz);
-        const double rcij = fmax(rct, a.rc[j]);
+        const double rcij = fmax(rct, prc[j]);
         if (d2 < rcij * rcij) emask |= 1u << j;
       }
     }
     if (emask) {
       listed = true;
     } else {
-      tp_finish(a, k, x, y, z, vx, vy, vz, rct, P2x, P2y, P2z);
+      tp_finish(a, pfin, prc, k, x, y, z, vx, vy, vz, rct, P2x, P2y, P2z);
     }
   }
   // block-level compaction of the particles with an encounter into this
@@ -540,7 +551,8 @@ __global__ __launch_bounds__(256) void k_tp_bs1(TpArgs a) {
     if (hit) {
       tp_remove(a, e, em, 1, 0, y0);
     } else {
-      tp_finish(a, ip, y1[0], y1[1], y1[2], y1[3], y1[4], y1[5], rct, P2x, P2y, P2z);
+      tp_finish(a, a.pfin, a.rc, ip, y1[0], y1[1], y1[2], y1[3], y1[4], y1[5], rct, P2x, P2y,
+                P2z);
     }
     a.bs_mask[e] = 0u;  // done
   }
@@ -594,7 +606,8 @@ __global__ __launch_bounds__(64) void k_tp_bs(TpArgs a) {
     if (r == 1) {
       if (lane == 0) tp_remove(a, e, em, cb, cpos, y);
     } else if (lane == 0) {
-      tp_finish(a, a.bs_idx[e], y[0], y[1], y[2], y[3], y[4], y[5], rct, P2x, P2y, P2z);
+      tp_finish(a, a.pfin, a.rc, a.bs_idx[e], y[0], y[1], y[2], y[3], y[4], y[5], rct, P2x, P2y,
+                P2z);
     }
   }
   if (lane == 0 && nsub > 0) a.sub[kTpBs1Grid + blockIdx.x] += (unsigned long long)nsub;
@@ -844,7 +857,10 @@ hipError_t tp_prime(const MassiveWs& w, const TpWs& t, const StepConsts& c, hipS
 hipError_t tp_step(const MassiveWs& w, const TpWs& t, const StepConsts& c, hipStream_t s) {
   if (t.ntp <= 0) return hipSuccess;
   TpArgs a = tp_args(w, t, c);
-  hipLaunchKernelGGL(k_tp_main, dim3((unsigned)t.nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_tp_main, dim3((unsigned)t.nb), dim3(256), 0, s, a,
+                     (const double4*)a.px0, (const double4*)a.pfin, (const double4*)a.ppre,
+                     (const double4*)a.vpre, (const double4*)a.ppost, (const double4*)a.vpost,
+                     (const double*)a.rc);
   if (!c.encounter_free) {
     hipLaunchKernelGGL(k_tp_scan, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_tp_plan, dim3(1), dim3(256), 0, s, a);
