@@ -108,6 +108,37 @@ def tp_measure(G, W, torch, steps: int, ntp: int = 1_000_000):
             "removed": st["tp_removed"]}
 
 
+def energy_measure(G, W, torch, steps: int = 1000, every: int = 10):
+    """The 16-body system for 1000 steps: relative energy error statistics
+    (Sec. 4.1) and angular-momentum drift, energy read every 10 steps."""
+    s = W.plain_n16()
+    sim = G.Simulation(s.m, s.x, s.u, G.default_params(), coords="helio")
+    E0, L0 = sim.energy()
+    errs, t = [], []
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    gpu_ms = 0.0
+    for k in range(steps // every):
+        e0.record(stream)
+        sim.step(every)
+        e1.record(stream)
+        E, L = sim.energy()          # synchronises
+        gpu_ms += e0.elapsed_time(e1)
+        errs.append(abs((E - E0) / E0))
+        t.append((k + 1) * every)
+    sim.check()
+    st = sim.stats()
+    _, L = sim.energy()
+    sim.close()
+    errs = np.asarray(errs)
+    slope = float(np.polyfit(np.asarray(t, dtype=float), errs, 1)[0])
+    return {"workload": "plain_n16", "steps": steps, "dE_rel_max": float(errs.max()),
+            "dE_rel_median": float(np.median(errs)), "dE_rel_final": float(errs[-1]),
+            "dE_rel_slope_per_step": slope,
+            "L_rel_drift": float(np.linalg.norm(L - L0) / np.linalg.norm(L0)),
+            "enc_total": st["enc_total"], "steps_per_s": steps / (gpu_ms / 1e3)}
+
+
 def batch_measure(G, W, torch, steps: int, cpu: bool):
     """Batched mode: 4096 independent systems of 2..32 bodies (Sec. 3.4), all
     steps in one captured launch; the tuner's table comes from init."""
@@ -215,8 +246,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tp-steps", type=int, default=100,
                     help="steps of the 10^6-particle run reported under extra (0: skip)")
-    ap.add_argument("--batch-steps", type=int, default=1000,
+    ap.add_argument("--batch-steps", type=int, default=10000,
                     help="steps of the 4096-system batched run reported under extra (0: skip)")
+    ap.add_argument("--energy-steps", type=int, default=1000,
+                    help="steps of the 16-body energy-error run reported under extra (0: skip)")
     ap.add_argument("--adj-steps", type=int, default=1000,
                     help="steps of the 1024 x 8 adjoint run reported under extra (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -274,6 +307,8 @@ def main():
         simb.close()
 
     extra = {}
+    if args.energy_steps > 0:
+        extra["energy"] = energy_measure(G, W, torch, args.energy_steps)
     if args.tp_steps > 0:
         extra["test_particles"] = tp_measure(G, W, torch, args.tp_steps)
     if args.batch_steps > 0:

@@ -115,6 +115,35 @@ def test_accel_parity(n):
     assert np.abs(a1 - ao1).max() <= 1e-13 * (np.abs(ao1).max() + 1e-300)
 
 
+def test_accel_parity_maximum_size():
+    """The largest system the library takes (65,536 bodies, encounter-free):
+    the pair sum per body against the oracle's, relative to each body's own
+    acceleration (the far-field sums of 65,535 terms cancel strongly)."""
+    n = 65536
+    s = W.planetesimals(n, seed_index=2)
+    gp = _gparams(encounter_free=1)
+    a = G.accel(gp, s.m, s.x).cpu().numpy()
+    ao = O.accel(_oparams(gp), s.m, s.x)
+    rel = np.linalg.norm(a - ao, axis=1) / np.linalg.norm(ao, axis=1)
+    _say("n 65536 accel: max rel", rel.max(), "median", np.median(rel))
+    assert rel.max() < 1e-11 and np.median(rel) < 1e-13
+
+
+def test_encounter_free_16384_ten_steps():
+    """The capability run of the pair kernel (16,384 bodies, K = 1) for ten
+    steps against the oracle's encounter-free map."""
+    s = W.planetesimals(16384, seed_index=2)
+    gp = _gparams(encounter_free=1)
+    sim = G.Simulation(s.m, s.x, s.u, gp, coords="helio")
+    sim.step(10)
+    sim.check()
+    xg, vg = [t.cpu().numpy() for t in sim.state("dem")]
+    op = _oparams(gp)
+    v0 = O.helio_to_dem(op, s.m, s.u)
+    xo, vo = O.free_step(op, s.m, s.x, v0, 10)
+    assert _rel_body(xg, xo) < REL and _rel_body(vg, vo) < REL
+
+
 # --------------------------------------------------------------- full step --
 def _run_pair(sysm, x, u, gp, steps):
     sim = G.Simulation(sysm, x, u, gp, coords="helio")
