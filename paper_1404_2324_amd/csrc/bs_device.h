@@ -294,31 +294,32 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
     }
     if (e >= 4 && (e & 1) == 0) {
       const int k = e / 2 - 1;  // column completed by this evaluation
-      // Aitken-Neville across the columns: T[c][j] needs T[c-1][j-1] (lane - P)
-      double cur[6], diag[6], sub[6];
+      // Aitken-Neville across the columns: T[c][j] needs T[c-1][j-1] (lane - P).
+      // Only column k's lanes are read: after j steps lane k holds T[k][j],
+      // built from lane k-1 after j-1 steps, ..., lane k-j's T0, all of
+      // them inside their own row (j <= c).  Lanes past their row (w = 0)
+      // keep computing, and whatever they hold never reaches lane k.
+      double cur[6], sub[6];
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
         cur[q] = T0[q];
-        diag[q] = T0[q];
         sub[q] = T0[q];
       }
 #pragma unroll
       for (int j = 1; j < kBsCols; ++j) {
         if (j > k) break;
-        double nb[6];
+        if (j == k) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q)
-          nb[q] = P == 2 ? dpp_d<kDppRowShr2>(cur[q]) : shfl_d(cur[q], lane - (c >= 1 ? P : 0));
-        if (j <= c) {
-          const double w = wj[j];
+          for (int q = 0; q < 6; ++q) sub[q] = cur[q];  // T[k][k-1] in lane k
+        }
+        const double w = wj[j];
 #pragma unroll
-          for (int q = 0; q < 6; ++q) {
-            if (j == c) sub[q] = cur[q];
-            cur[q] = cur[q] + (cur[q] - nb[q]) * w;
-            if (j == c) diag[q] = cur[q];
-          }
+        for (int q = 0; q < 6; ++q) {
+          const double nb = P == 2 ? dpp_d<kDppRowShr2>(cur[q]) : shfl_d(cur[q], lane - (c >= 1 ? P : 0));
+          cur[q] = fma(cur[q] - nb, w, cur[q]);
         }
       }
+      const double* diag = cur;  // T[k][k] in lane k
       // column k of every slot: accepted unless one of its members fails
       const bool bad = c == k && b < sz && !(within3(diag, sub, tol2) && within3(diag + 3, sub + 3, tol2));
       const unsigned long long badm = __ballot(bad);

@@ -322,6 +322,47 @@ __device__ __forceinline__ void pair_hb(double xi, double yi, double zi,
   az += s * dz;
 }
 
+constexpr int kPre = 8;       // partners fetched per batch of loads
+constexpr int kRowSort = 32;  // longest candidate row sorted in registers
+
+// Ascending sort of N (a power of two) values in registers: bitonic network.
+template <int N>
+__device__ __forceinline__ void bitonic_sort(int (&v)[N]) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int u = 0; u < N; ++u) {
+        const int l = u ^ j;
+        if (l > u) {
+          const int lo = min(v[u], v[l]), hi = max(v[u], v[l]);
+          const bool up = (u & k) == 0;
+          v[u] = up ? lo : hi;
+          v[l] = up ? hi : lo;
+        }
+      }
+}
+
+// Pair terms of the sorted partners jj[c0 .. min(c0 + B, cnt) - 1] of body i,
+// in that order; all B partner loads are issued before the first use.
+template <int B, int N>
+__device__ __forceinline__ void sum_partners(const int (&jj)[N], int c0, int cnt, int i,
+                                             const double4& p, double rci, const OpenArgs& a,
+                                             double& cx, double& cy, double& cz) {
+  double4 pj[B];
+  double rj[B];
+#pragma unroll
+  for (int u = 0; u < B; ++u) {
+    const int jl = c0 + u < cnt ? jj[c0 + u] : i;  // padded slots read a valid index
+    pj[u] = a.xm[jl];
+    rj[u] = a.rc_next[jl];
+  }
+#pragma unroll
+  for (int u = 0; u < B; ++u)
+    if (c0 + u < cnt) pair_hb(p.x, p.y, p.z, rci, pj[u], rj[u], a.encounter_free, cx, cy, cz);
+}
+
 // Opening kick (KickA/KickB, Sec. 3.2.3): the closing kick's non-candidate
 // sum is reused; candidate pairs are recomputed with this step's radii in
 // ascending partner order.  When some radius grew beyond pf times the radius
@@ -350,34 +391,36 @@ __global__ __launch_bounds__(kVecBlock) void k_kick_open(OpenArgs a) {
       const int cnt = min(a.ccnt[i], a.cpb);
       const int* row = a.ctab + (size_t)i * a.cpb;
       double cx = 0.0, cy = 0.0, cz = 0.0;
-      // up to 8 partners loaded at once and put in ascending order by a
-      // sorting network; longer rows continue with an ordered scan
-      constexpr int kPre = 8;
-      int jj[kPre];
-#pragma unroll
-      for (int u = 0; u < kPre; ++u) jj[u] = u < cnt ? row[u] : INT_MAX;
-#pragma unroll
-      for (int p1 = 0; p1 < kPre; ++p1)
-#pragma unroll
-        for (int p2 = (p1 & 1); p2 + 1 < kPre; p2 += 2) {
-          const int lo = min(jj[p2], jj[p2 + 1]), hi = max(jj[p2], jj[p2 + 1]);
-          jj[p2] = lo;
-          jj[p2 + 1] = hi;
-        }
-      int prev = -1;
+      // Partners are summed in ascending order (deterministic).  Rows of up
+      // to 8 (nearly all), 16 or kRowSort partners are sorted by a bitonic
+      // network of that width in registers; partner data is then fetched 8
+      // at a time with independent loads.  Longer rows fall back to an
+      // ordered scan.
       if (cnt <= kPre) {
-        double4 pj[kPre];
-        double rj[kPre];
+        int jj[kPre];
 #pragma unroll
-        for (int u = 0; u < kPre; ++u) {
-          const int jl = u < cnt ? jj[u] : i;  // padded slots read a valid index
-          pj[u] = a.xm[jl];
-          rj[u] = a.rc_next[jl];
+        for (int u = 0; u < kPre; ++u) jj[u] = u < cnt ? row[u] : INT_MAX;
+        bitonic_sort(jj);
+        sum_partners<kPre>(jj, 0, cnt, i, p, rci, a, cx, cy, cz);
+      } else if (cnt <= 2 * kPre) {
+        int jj[2 * kPre];
+#pragma unroll
+        for (int u = 0; u < 2 * kPre; ++u) jj[u] = u < cnt ? row[u] : INT_MAX;
+        bitonic_sort(jj);
+        sum_partners<kPre>(jj, 0, cnt, i, p, rci, a, cx, cy, cz);
+        sum_partners<kPre>(jj, kPre, cnt, i, p, rci, a, cx, cy, cz);
+      } else if (cnt <= kRowSort) {
+        int jj[kRowSort];
+#pragma unroll
+        for (int u = 0; u < kRowSort; ++u) jj[u] = u < cnt ? row[u] : INT_MAX;
+        bitonic_sort(jj);
+#pragma unroll
+        for (int c0 = 0; c0 < kRowSort; c0 += kPre) {
+          if (c0 >= cnt) break;
+          sum_partners<kPre>(jj, c0, cnt, i, p, rci, a, cx, cy, cz);
         }
-#pragma unroll
-        for (int u = 0; u < kPre; ++u)
-          if (u < cnt) pair_hb(p.x, p.y, p.z, rci, pj[u], rj[u], a.encounter_free, cx, cy, cz);
       } else {
+        int prev = -1;
         for (int t = 0; t < cnt; ++t) {
           int jm = INT_MAX;
           for (int u = 0; u < cnt; ++u) {

@@ -265,6 +265,33 @@ def test_dense_encounters_small_system():
     assert max(dx, dv) < max(REL, 10 * spread)
 
 
+def test_long_candidate_rows():
+    """A 5 x 5 x 5 lattice of co-orbiting bodies 1.1 r_crit apart: no
+    encounters, but candidate rows of every length class (up to 8, 9-32 and
+    beyond 32 partners), so the opening kick sums every kind of row."""
+    gp = _gparams(cand_per_body=96)
+    rc = gp.n2 * gp.dt * 1.0
+    g = (np.arange(5) - 2.0) * 1.1 * rc
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    x = np.stack([1.0 + X.ravel(), Y.ravel(), Z.ravel()], 1)
+    r = np.linalg.norm(x[:, :2], axis=1)
+    u = np.stack([-x[:, 1], x[:, 0], np.zeros(len(r))], 1) / r[:, None] ** 1.5
+    m = np.full(len(r), 1e-9)
+    sim = G.Simulation(m, x, u, gp, coords="helio")
+    orc = O.MassiveSim(_oparams(gp), m, x, u, coords="helio")
+    cnt = np.bincount(orc.candidates()[:, 0], minlength=len(m))
+    assert (cnt <= 8).any() and ((cnt > 8) & (cnt <= 32)).any() and (cnt > 32).any()
+    for _ in range(4):
+        sim.step(1)
+        orc.step(1)
+        _cand_sets_close(sim.candidates(), orc.candidates(), orc)
+    sim.check()
+    xg, vg = sim.state()
+    assert _rel_body(xg.cpu().numpy(), orc.x) < REL
+    assert _rel_body(vg.cpu().numpy(), orc.v) < REL
+    assert sim.stats()["full_kicks"] == 0
+
+
 def test_encounter_free_reversible_on_gpu():
     s = W.plain_n16()
     gp = _gparams(encounter_free=1)
