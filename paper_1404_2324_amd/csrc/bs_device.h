@@ -256,11 +256,13 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
   const double hs = ldexp(H, -s) / nsub;
   const double tol2 = tol >= 0.0 ? tol * tol : -1.0;  // a negative tolerance accepts nothing
   constexpr unsigned long long kMemb = (1ull << P) - 1ull;
-  double ym[6], yn[6], T0[6], yacc[6];
+  // Gragg states in two buffers used in turn: A holds the even-numbered
+  // points z_0, z_2, ..., B the odd ones, so no copies are needed per substep
+  double A[6], B[6], T0[6], yacc[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    ym[q] = y[q];
-    yn[q] = y[q];
+    A[q] = y[q];
+    B[q] = y[q];
     T0[q] = y[q];
     yacc[q] = y[q];
   }
@@ -273,26 +275,25 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
     wj[j] = j <= c ? (double)(qq * qq) / (double)(pp * pp - qq * qq) : 0.0;
   }
   unsigned accm = 0u;  // slots that have accepted a column (bit s)
-  for (int e = 0; e <= 2 * kBsCols; ++e) {
+  // Evaluation e is at z_e: z_1 = z_0 + hs f(z_0), z_{e+1} = z_{e-1} +
+  // 2 hs f(z_e) while e < nsub; the lane's points stay fixed after z_nsub
+  // (step 0), and T0 = (z_{nsub-1} + z_nsub + hs f(z_nsub)) / 2.
+  for (int e = 0; e <= 2 * kBsCols; e += 2) {
     double d[6];
-    ha_accel_par<P, TP>(sz, b, yn[0], yn[1], yn[2], Q, G, Gm0, d[3], d[4], d[5]);
-    d[0] = yn[3];
-    d[1] = yn[4];
-    d[2] = yn[5];
-    if (e < nsub) {
-      // first substep y0 + hs f(y0) (ym = yn = y0 then), later ym + 2 hs f(yn)
-      const double hf = e == 0 ? hs : 2.0 * hs;
+    ha_accel_par<P, TP>(sz, b, A[0], A[1], A[2], Q, G, Gm0, d[3], d[4], d[5]);
+    d[0] = A[3];
+    d[1] = A[4];
+    d[2] = A[5];
+    if (e == nsub) {
 #pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        const double t = ym[q] + hf * d[q];
-        ym[q] = yn[q];
-        yn[q] = t;
-      }
-    } else if (e == nsub) {
-#pragma unroll
-      for (int q = 0; q < 6; ++q) T0[q] = 0.5 * (ym[q] + yn[q] + hs * d[q]);
+      for (int q = 0; q < 6; ++q) T0[q] = 0.5 * (B[q] + A[q] + hs * d[q]);
     }
-    if (e >= 4 && (e & 1) == 0) {
+    {
+      const double hf = e < nsub ? (e == 0 ? hs : 2.0 * hs) : 0.0;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) B[q] = B[q] + hf * d[q];
+    }
+    if (e >= 4) {
       const int k = e / 2 - 1;  // column completed by this evaluation
       // Aitken-Neville across the columns: T[c][j] needs T[c-1][j-1] (lane - P).
       // Only column k's lanes are read: after j steps lane k holds T[k][j],
@@ -340,6 +341,14 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
       // slot 0 decided: nothing can precede it
       if (accm & 1u) break;
     }
+    if (e == 2 * kBsCols) break;
+    ha_accel_par<P, TP>(sz, b, B[0], B[1], B[2], Q, G, Gm0, d[3], d[4], d[5]);
+    d[0] = B[3];
+    d[1] = B[4];
+    d[2] = B[5];
+    const double hf = e + 1 < nsub ? 2.0 * hs : 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) A[q] = A[q] + hf * d[q];
   }
   // first accepted slot in sequential order
   if (accm == 0u) return -1;
