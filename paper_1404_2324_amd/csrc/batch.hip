@@ -96,7 +96,7 @@ __device__ __forceinline__ int group_par(const BatchArgs& a, int sz, unsigned lo
                                          double pre[6], double m, double rc, double Gm0,
                                          double* mm, double* mrc, long long* nsub) {
   const int lane = threadIdx.x & 63;
-  const int b = lane % P;
+  const int b = par_memb<P>(lane);
   const int body = b < sz ? nth_bit(M, b) : 0;
   double y[6];
 #pragma unroll
@@ -105,7 +105,9 @@ __device__ __forceinline__ int group_par(const BatchArgs& a, int sz, unsigned lo
     y[0] = 1.0;
     y[1] = y[2] = y[3] = y[4] = y[5] = 0.0;
   }
-  const double mb = __shfl(m, body, 64), rcb = __shfl(rc, body, 64);
+  // member tables indexed by member: lane t < sz fetches member t's data
+  const int bt = lane < sz ? nth_bit(M, lane) : 0;
+  const double mb = __shfl(m, bt, 64), rcb = __shfl(rc, bt, 64);
   __syncthreads();
   if (lane < sz) {
     mm[lane] = mb;
@@ -116,7 +118,7 @@ __device__ __forceinline__ int group_par(const BatchArgs& a, int sz, unsigned lo
   const int rank = __popcll(M & ((1ull << lane) - 1ull));
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    const double t = __shfl(y[c], rank, 64);
+    const double t = __shfl(y[c], par_lane<P>(0, 0, min(rank, P - 1)), 64);
     if ((M >> lane) & 1ull) pre[c] = t;
   }
   return r;

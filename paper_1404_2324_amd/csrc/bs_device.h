@@ -25,13 +25,15 @@ __device__ __forceinline__ void ha_accel(int sz, int lane, double x, double y,
   for (int j = 0; j < sz; ++j) {
     const double xj = readlane_d(x, j), yj = readlane_d(y, j), zj = readlane_d(z, j);
     const double mj = readlane_d(m, j), rcj = readlane_d(rc, j);
-    if (j != lane) {
-      const double dx = xj - x, dy = yj - y, dz = zj - z;
-      const double q2 = dx * dx + dy * dy + dz * dz;
+    const double dx = xj - x, dy = yj - y, dz = zj - z;
+    const double q2 = dx * dx + dy * dy + dz * dz;
+    const double rij = fmax(rc, rcj);
+    // the term vanishes exactly beyond rc_ij (K = 1, K' = 0)
+    if (j != lane && q2 < rij * rij * (1.0 + 1e-12)) {
       const double iq = rsqrt_nr(q2);
       const double iq2 = iq * iq;
       double K, dK;
-      changeover(q2 * iq, fmax(rc, rcj), K, dK);
+      changeover(q2 * iq, rij, K, dK);
       const double s = G * mj * ((1.0 - K) * iq2 * iq + dK * iq2);
       ax += s * dx;
       ay += s * dy;
@@ -155,20 +157,43 @@ __device__ __forceinline__ int bs_integrate(int sz, int lane, double y[6], doubl
 
 // ---- groups of up to 8 members: all columns, and several depths, at once ----
 // A wave of 64 lanes holds S = 8/P speculative refinement depths x 8 columns
-// x P member slots (P = 2, 4 or 8 >= group size):
-//   lane = s (8 P) + c P + b,  s = depth slot, c = column, b = member.
-// Column c integrates the modified midpoint rule with n_c = 2 (c + 1)
-// substeps; members exchange positions by lane shuffles.  Slot s attempts
-// the substep of length H / 2^s from the same start: exactly the attempts the
-// sequential scheme makes after s failures (the first half of each halving).
-// The Aitken-Neville tableau is built across the columns (T[c][j] needs
-// T[c-1][j-1] from lane - P); column k is tested when it completes (after
-// 2 k + 3 force evaluations), and each slot keeps its first column within
-// tolerance.  The result is the first accepted slot in sequential order, so
-// the substeps taken equal those of one-at-a-time evaluation.
+// x P member slots (P = 2, 4 or 8 >= group size); s = depth slot, c = column,
+// b = member:
+//   P = 2:   lane = 16 s + 2 c + b  (partner lane ^ 1: a quad permutation)
+//   P >= 4:  lane = 8 P s + 8 b + c (columns adjacent)
+// so that the column neighbour c - 1 of the tableau is a DPP row shift away
+// (by 2 or by 1 lanes, inside the row of 16).  Column c integrates the
+// modified midpoint rule with n_c = 2 (c + 1) substeps; members exchange
+// positions by lane shuffles.  Slot s attempts the substep of length H / 2^s
+// from the same start: exactly the attempts the sequential scheme makes
+// after s failures (the first half of each halving).  The Aitken-Neville
+// tableau is built across the columns (T[c][j] needs T[c-1][j-1]); column k
+// is tested when it completes (after 2 k + 3 force evaluations), and each
+// slot keeps its first column within tolerance.  The result is the first
+// accepted slot in sequential order, so the substeps taken equal those of
+// one-at-a-time evaluation.
 // TP: member 0 is a massless test particle and the other members feel only
 // the star (a test-particle encounter, Sec. 3.3).
 constexpr int kBsPar = 8;
+
+template <int P>
+__device__ __forceinline__ int par_lane(int s, int c, int b) {
+  return P == 2 ? 16 * s + 2 * c + b : 8 * P * s + 8 * b + c;
+}
+template <int P>
+__device__ __forceinline__ int par_col(int lane) {
+  return P == 2 ? (lane >> 1) & 7 : lane & 7;
+}
+template <int P>
+__device__ __forceinline__ int par_memb(int lane) {
+  return P == 2 ? lane & 1 : (lane >> 3) & (P - 1);
+}
+// ballot bits of the P members of slot s, column c
+template <int P>
+__device__ __forceinline__ unsigned long long par_members(int s, int c) {
+  constexpr unsigned long long kStride = P == 2 ? 3ull : (P == 4 ? 0x01010101ull : 0x0101010101010101ull);
+  return kStride << par_lane<P>(s, c, 0);
+}
 
 template <int P>
 struct ParBody {
@@ -176,6 +201,9 @@ struct ParBody {
   double m[P];     // partner mass
   double rcij[P];  // pair radius max(rc_b, rc_j)
   double i09[P];   // 1 / (0.9 rc_ij), 0 when rc_ij = 0
+  double near2[P]; // rc_ij^2 (1 + 1e-12): beyond it the pair's H_A term is 0
+  int lback[P];    // lane of member (b - q) mod sz
+  double mback[P]; // its mass
 };
 
 // Lane shuffles of a double: generic (ds_bpermute) or, for a source lane a
@@ -192,6 +220,7 @@ __device__ __forceinline__ double dpp_d(double v) {
 }
 constexpr int kDppQuadSwap1 = 0xB1;     // quad_perm [1,0,3,2]: lane ^ 1
 constexpr int kDppRowShr2 = 0x112;      // row_shr:2: lane - 2 inside the row
+constexpr int kDppRowShr1 = 0x111;      // row_shr:1: lane - 1 inside the row
 
 template <int P, bool TP>
 __device__ __forceinline__ void ha_accel_par(int sz, int b, double x, double y,
@@ -204,6 +233,41 @@ __device__ __forceinline__ void ha_accel_par(int sz, int b, double x, double y,
   ax = fs * x;
   ay = fs * y;
   az = fs * z;
+  if (!TP && P >= 4) {
+    // Each unordered pair once: member b takes partners b + q (mod sz) for
+    // 2 q <= sz (at 2 q = sz only b < q does) and receives the reaction of
+    // the pair that member b - q took, scaled by that member's mass.
+#pragma unroll
+    for (int q = 1; q <= P / 2; ++q) {
+      if (2 * q > sz) break;
+      const bool half = 2 * q == sz;
+      const double xj = shfl_d(x, Q.lane[q]), yj = shfl_d(y, Q.lane[q]), zj = shfl_d(z, Q.lane[q]);
+      const double dx = xj - x, dy = yj - y, dz = zj - z;
+      const double q2 = dx * dx + dy * dy + dz * dz;
+      double fx = 0.0, fy = 0.0, fz = 0.0;
+      if ((!half || b < q) && q2 < Q.near2[q]) {  // beyond near2 the term is 0
+        const double iq = rsqrt_nr(q2);
+        const double iq2 = iq * iq;
+        double K, dK;
+        changeover_clamped(q2 * iq, Q.rcij[q], Q.i09[q], K, dK);
+        const double f = G * ((1.0 - K) * iq2 * iq + dK * iq2);
+        fx = f * dx;
+        fy = f * dy;
+        fz = f * dz;
+        ax += Q.m[q] * fx;
+        ay += Q.m[q] * fy;
+        az += Q.m[q] * fz;
+      }
+      const double rx = shfl_d(fx, Q.lback[q]), ry = shfl_d(fy, Q.lback[q]),
+                   rz = shfl_d(fz, Q.lback[q]);
+      if (!half || b >= q) {
+        ax -= Q.mback[q] * rx;
+        ay -= Q.mback[q] * ry;
+        az -= Q.mback[q] * rz;
+      }
+    }
+    return;
+  }
   const int np = (TP && b != 0) ? 1 : sz;  // planets in a particle's group: star only
 #pragma unroll
   for (int q = 1; q < P; ++q) {
@@ -218,13 +282,16 @@ __device__ __forceinline__ void ha_accel_par(int sz, int b, double x, double y,
       yj = shfl_d(y, Q.lane[q]);
       zj = shfl_d(z, Q.lane[q]);
     }
-    if (q < np) {
-      const double dx = xj - x, dy = yj - y, dz = zj - z;
-      const double q2 = dx * dx + dy * dy + dz * dz;
+    const double dx = xj - x, dy = yj - y, dz = zj - z;
+    const double q2 = dx * dx + dy * dy + dz * dz;
+    // At r >= rc_ij, K = 1 and K' = 0 exactly (y clamps to 1), so the term
+    // vanishes: lanes beyond near2 (a margin far above the rounding of y)
+    // skip it, and the whole wave does when no pair is inside.
+    if (q < np && q2 < Q.near2[q]) {
       const double iq = rsqrt_nr(q2);
       const double iq2 = iq * iq;
       double K = 1.0, dK = 0.0;
-      if (Q.rcij[q] > 0.0) changeover_clamped(q2 * iq, Q.rcij[q], Q.i09[q], K, dK);
+      changeover_clamped(q2 * iq, Q.rcij[q], Q.i09[q], K, dK);
       const double sc = G * Q.m[q] * ((1.0 - K) * iq2 * iq + dK * iq2);
       ax += sc * dx;
       ay += sc * dy;
@@ -250,12 +317,11 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
                                             double Gm0, double tol) {
   const int lane = threadIdx.x & 63;
   const int s = lane / (kBsPar * P);
-  const int c = (lane / P) % kBsPar;
-  const int b = lane % P;
+  const int c = par_col<P>(lane);
+  const int b = par_memb<P>(lane);
   const int nsub = 2 * (c + 1);
   const double hs = ldexp(H, -s) / nsub;
   const double tol2 = tol >= 0.0 ? tol * tol : -1.0;  // a negative tolerance accepts nothing
-  constexpr unsigned long long kMemb = (1ull << P) - 1ull;
   // Gragg states in two buffers used in turn: A holds the even-numbered
   // points z_0, z_2, ..., B the odd ones, so no copies are needed per substep
   double A[6], B[6], T0[6], yacc[6];
@@ -316,7 +382,7 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
         const double w = wj[j];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-          const double nb = P == 2 ? dpp_d<kDppRowShr2>(cur[q]) : shfl_d(cur[q], lane - (c >= 1 ? P : 0));
+          const double nb = P == 2 ? dpp_d<kDppRowShr2>(cur[q]) : dpp_d<kDppRowShr1>(cur[q]);
           cur[q] = fma(cur[q] - nb, w, cur[q]);
         }
       }
@@ -327,13 +393,13 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
       unsigned now = 0u;
 #pragma unroll
       for (int t = 0; t < kBsPar / P; ++t)
-        if (!((accm >> t) & 1u) && ((badm >> (t * kBsPar * P + k * P)) & kMemb) == 0ull)
+        if (!((accm >> t) & 1u) && (badm & par_members<P>(t, k)) == 0ull)
           now |= 1u << t;
       if (now) {
         // the accepted state of this slot's column k, for every lane of the slot
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-          const double g = shfl_d(diag[q], s * kBsPar * P + k * P + b);
+          const double g = shfl_d(diag[q], par_lane<P>(s, k, b));
           if ((now >> s) & 1u) yacc[q] = g;
         }
         accm |= now;
@@ -354,7 +420,7 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
   if (accm == 0u) return -1;
   const int sacc = __ffs(accm) - 1;
 #pragma unroll
-  for (int q = 0; q < 6; ++q) y[q] = shfl_d(yacc[q], sacc * kBsPar * P + b);
+  for (int q = 0; q < 6; ++q) y[q] = shfl_d(yacc[q], par_lane<P>(sacc, 0, b));
   return sacc;
 }
 
@@ -373,7 +439,7 @@ __device__ __forceinline__ int bs_integrate_par(int sz, double y[6], double H,
                                                 long long* cpos = nullptr) {
   constexpr int S = kBsPar / P;
   const int lane = threadIdx.x & 63;
-  const int b = lane % P;
+  const int b = par_memb<P>(lane);
   const bool coll = TP && __ballot(R2 >= 0.0) != 0ull;
   long long pos = 0;
   const long long total = 1ll << D;
@@ -390,7 +456,7 @@ __device__ __forceinline__ int bs_integrate_par(int sz, double y[6], double H,
     if (sa >= 0) {
       d += sa;
       if (coll) {
-        const int l0 = lane - b;
+        const int l0 = par_lane<P>(lane / (kBsPar * P), par_col<P>(lane), 0);
         double o[6], e[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
@@ -400,9 +466,9 @@ __device__ __forceinline__ int bs_integrate_par(int sz, double y[6], double H,
         const double d2 = hermite_dmin2(ldexp(H, -d), o[0], o[1], o[2], o[3], o[4], o[5],
                                         e[0], e[1], e[2], e[3], e[4], e[5]);
         const bool hit = b >= 1 && b < sz && R2 >= 0.0 && d2 < R2;
-        const unsigned long long hm = __ballot(hit) & ((1ull << P) - 1ull);
+        const unsigned long long hm = __ballot(hit) & par_members<P>(0, 0);
         if (hm != 0ull) {
-          *cb = __ffsll((long long)hm) - 1;
+          *cb = par_memb<P>(__ffsll((long long)hm) - 1);
           *cpos = pos;
           return 1;
         }
@@ -420,10 +486,11 @@ __device__ __forceinline__ int bs_integrate_par(int sz, double y[6], double H,
   return 0;
 }
 
-// One group of sz <= P members over H.  Lane member b = lane % P holds the
-// member's start state in y (dummy state for b >= sz); mm[] and mrc[] (any
-// memory) give every member's mass and critical radius.  On return y holds
-// member b's state after H in every lane.
+// One group of sz <= P members over H.  Every lane of member b =
+// par_memb<P>(lane) holds the member's start state in y (dummy state for
+// b >= sz); mm[] and mrc[] (any memory) give every member's mass and critical
+// radius.  On return y holds member b's state after H in each of its lanes
+// (par_lane<P>(0, 0, b) among them).
 template <int P, bool TP>
 __device__ __forceinline__ int bs_group(int sz, double y[6], const double* mm,
                                         const double* mrc, double H, double G,
@@ -431,7 +498,7 @@ __device__ __forceinline__ int bs_group(int sz, double y[6], const double* mm,
                                         long long* nsub, double R2 = -1.0,
                                         int* cb = nullptr, long long* cpos = nullptr) {
   const int lane = threadIdx.x & 63;
-  const int b = lane % P;
+  const int b = par_memb<P>(lane);
   const double rcb = b < sz ? mrc[b] : 0.0;
   ParBody<P> Q;
 #pragma unroll
@@ -439,14 +506,19 @@ __device__ __forceinline__ int bs_group(int sz, double y[6], const double* mm,
     int j = b + q;
     j = j >= sz ? j - sz : j;
     j = j >= sz ? j - sz : j;  // dummy slots (b >= sz) wrap twice at most
-    Q.lane[q] = lane - b + j;
+    Q.lane[q] = lane + par_lane<P>(0, 0, j) - par_lane<P>(0, 0, b);
+    const int jb = ((b - q) % sz + sz) % sz;  // member (b - q) mod sz (dummies too)
+    Q.lback[q] = lane + par_lane<P>(0, 0, jb) - par_lane<P>(0, 0, b);
+    Q.mback[q] = q < sz ? mm[jb] : 0.0;
     Q.m[q] = 0.0;
     Q.rcij[q] = 0.0;
     Q.i09[q] = 0.0;
+    Q.near2[q] = 0.0;
     if (q < sz) {
       Q.m[q] = mm[j];
       Q.rcij[q] = fmax(rcb, mrc[j]);
       Q.i09[q] = Q.rcij[q] > 0.0 ? 1.0 / (0.9 * Q.rcij[q]) : 0.0;
+      Q.near2[q] = Q.rcij[q] > 0.0 ? Q.rcij[q] * Q.rcij[q] * (1.0 + 1e-12) : 0.0;
     }
   }
   return bs_integrate_par<P, TP>(sz, y, H, Q, G, Gm0, tol, D, nsub, R2, cb, cpos);

@@ -757,7 +757,7 @@ __device__ __forceinline__ int bs_member_group(const BsArgs& a, int sz, const in
                                                long long* nsub, double& dpx, double& dpy,
                                                double& dpz) {
   const int lane = threadIdx.x & 63;
-  const int b = lane % P;
+  const int b = par_memb<P>(lane);
   const int id = b < sz ? mem[b] : -1;
   double y[6] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (id >= 0) {
@@ -771,7 +771,7 @@ __device__ __forceinline__ int bs_member_group(const BsArgs& a, int sz, const in
   }
   const int r = bs_group<P, false>(sz, y, mm, mrc, a.dt, a.G, a.Gm0, a.tol, a.max_depth, nsub);
   dpx = dpy = dpz = 0.0;
-  if (lane < P && id >= 0) {
+  if (lane == par_lane<P>(0, 0, b) && id >= 0) {  // one lane per member writes
     const double m = mm[b];
     const double4 vo = a.vv[id];
     dpx = m * (y[3] - vo.x);

@@ -282,7 +282,7 @@ __device__ __forceinline__ int tp_group(const TpArgs& a, int64_t e, int sz, unsi
                                         long long* nsub, double y[6], int* cb,
                                         long long* cpos) {
   const int lane = threadIdx.x & 63;
-  const int b = lane % P;
+  const int b = par_memb<P>(lane);
   double R2 = -1.0;
   y[0] = 1.0;
   y[1] = y[2] = y[3] = y[4] = y[5] = 0.0;
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(256) void k_tp_plan(TpArgs a) {
 
 // Particle derivative in its group with planet position (qx, qy, qz).
 struct PairK {
-  double Gm, rcij, i09;
+  double Gm, rcij, i09, near2;  // near2: rc_ij^2 (1 + 1e-12), 0 when rc_ij = 0
 };
 __device__ __forceinline__ void tp_pair_acc(double Gm0, const PairK& Q, double x, double y,
                                             double z, double qx, double qy, double qz,
@@ -440,14 +440,17 @@ __device__ __forceinline__ void tp_pair_acc(double Gm0, const PairK& Q, double x
   az = fs * z;
   const double dx = qx - x, dy = qy - y, dz = qz - z;
   const double q2 = dx * dx + dy * dy + dz * dz;
-  const double iq = rsqrt_nr(q2);
-  const double iq2 = iq * iq;
-  double K = 1.0, dK = 0.0;
-  if (Q.rcij > 0.0) changeover_clamped(q2 * iq, Q.rcij, Q.i09, K, dK);
-  const double sc = Q.Gm * ((1.0 - K) * iq2 * iq + dK * iq2);
-  ax += sc * dx;
-  ay += sc * dy;
-  az += sc * dz;
+  // beyond rc_ij the H_A pair term is exactly 0 (K = 1, K' = 0)
+  if (q2 < Q.near2) {
+    const double iq = rsqrt_nr(q2);
+    const double iq2 = iq * iq;
+    double K, dK;
+    changeover_clamped(q2 * iq, Q.rcij, Q.i09, K, dK);
+    const double sc = Q.Gm * ((1.0 - K) * iq2 * iq + dK * iq2);
+    ax += sc * dx;
+    ay += sc * dy;
+    az += sc * dz;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_tp_bs1(TpArgs a) {
@@ -465,6 +468,7 @@ __global__ __launch_bounds__(256) void k_tp_bs1(TpArgs a) {
     Q.Gm = a.G * a.px0[j].w;
     Q.rcij = fmax(rct, a.rc[j]);
     Q.i09 = Q.rcij > 0.0 ? 1.0 / (0.9 * Q.rcij) : 0.0;
+    Q.near2 = Q.rcij > 0.0 ? Q.rcij * Q.rcij * (1.0 + 1e-12) : 0.0;
     const double* tab = a.pl + (size_t)j * kPlStride;
     const double4 pp = a.ppre[j];
     double y0[6];
