@@ -222,6 +222,28 @@ constexpr int kDppQuadSwap1 = 0xB1;     // quad_perm [1,0,3,2]: lane ^ 1
 constexpr int kDppRowShr2 = 0x112;      // row_shr:2: lane - 2 inside the row
 constexpr int kDppRowShr1 = 0x111;      // row_shr:1: lane - 1 inside the row
 
+// (1-K)-weighted pair factor f of H_A (Eq. 1 gradient, without the partner's
+// mass) times d = x_j - x_b, or 0 where use is false.  Beyond rc_ij
+// (q2 >= near2, a margin far above the rounding of y) the term is exactly 0
+// (y clamps to 1: K = 1, K' = 0), and it is 0 for rc_ij = 0 (near2 = 0).
+// Branch-free, so that the compiler can interleave independent terms.
+__device__ __forceinline__ void ha_pair(double dx, double dy, double dz, double rc, double i09,
+                                        double near2, double G, bool use, double& fx,
+                                        double& fy, double& fz) {
+  const double q2 = dx * dx + dy * dy + dz * dz;
+  const double iq = rsqrt_nr(q2);
+  const double iq2 = iq * iq;
+  double K, dK;
+  changeover_clamped(q2 * iq, rc, i09, K, dK);
+  double f = G * ((1.0 - K) * iq2 * iq + dK * iq2);
+  f = (use && q2 < near2) ? f : 0.0;
+  fx = f * dx;
+  fy = f * dy;
+  fz = f * dz;
+}
+
+// dv/dt of H_A for member b of a group of sz members, P/2 < sz <= P (P = 2,
+// 4, 8): the fixed star plus the group's pair terms.
 template <int P, bool TP>
 __device__ __forceinline__ void ha_accel_par(int sz, int b, double x, double y,
                                              double z, const ParBody<P>& Q,
@@ -233,47 +255,49 @@ __device__ __forceinline__ void ha_accel_par(int sz, int b, double x, double y,
   ax = fs * x;
   ay = fs * y;
   az = fs * z;
-  if (!TP && P >= 4) {
+  if (!TP && P == 2) {  // the partner is lane ^ 1
+    const double dx = dpp_d<kDppQuadSwap1>(x) - x, dy = dpp_d<kDppQuadSwap1>(y) - y,
+                 dz = dpp_d<kDppQuadSwap1>(z) - z;
+    double fx, fy, fz;
+    ha_pair(dx, dy, dz, Q.rcij[1], Q.i09[1], Q.near2[1], G, true, fx, fy, fz);
+    ax += Q.m[1] * fx;
+    ay += Q.m[1] * fy;
+    az += Q.m[1] * fz;
+    return;
+  }
+  if (!TP) {
     // Each unordered pair once: member b takes partners b + q (mod sz) for
     // 2 q <= sz (at 2 q = sz only b < q does) and receives the reaction of
-    // the pair that member b - q took, scaled by that member's mass.
+    // the pair that member b - q took, scaled by that member's mass.  With
+    // P/2 < sz the offsets q <= P/4 always exist, so their terms need no
+    // test and form one block of independent work.
 #pragma unroll
     for (int q = 1; q <= P / 2; ++q) {
-      if (2 * q > sz) break;
+      if (q > P / 4 && 2 * q > sz) break;
       const bool half = 2 * q == sz;
-      const double xj = shfl_d(x, Q.lane[q]), yj = shfl_d(y, Q.lane[q]), zj = shfl_d(z, Q.lane[q]);
-      const double dx = xj - x, dy = yj - y, dz = zj - z;
-      const double q2 = dx * dx + dy * dy + dz * dz;
-      double fx = 0.0, fy = 0.0, fz = 0.0;
-      if ((!half || b < q) && q2 < Q.near2[q]) {  // beyond near2 the term is 0
-        const double iq = rsqrt_nr(q2);
-        const double iq2 = iq * iq;
-        double K, dK;
-        changeover_clamped(q2 * iq, Q.rcij[q], Q.i09[q], K, dK);
-        const double f = G * ((1.0 - K) * iq2 * iq + dK * iq2);
-        fx = f * dx;
-        fy = f * dy;
-        fz = f * dz;
-        ax += Q.m[q] * fx;
-        ay += Q.m[q] * fy;
-        az += Q.m[q] * fz;
-      }
+      const double dx = shfl_d(x, Q.lane[q]) - x, dy = shfl_d(y, Q.lane[q]) - y,
+                   dz = shfl_d(z, Q.lane[q]) - z;
+      double fx, fy, fz;
+      ha_pair(dx, dy, dz, Q.rcij[q], Q.i09[q], Q.near2[q], G, !half || b < q, fx, fy, fz);
+      ax += Q.m[q] * fx;
+      ay += Q.m[q] * fy;
+      az += Q.m[q] * fz;
       const double rx = shfl_d(fx, Q.lback[q]), ry = shfl_d(fy, Q.lback[q]),
                    rz = shfl_d(fz, Q.lback[q]);
-      if (!half || b >= q) {
-        ax -= Q.mback[q] * rx;
-        ay -= Q.mback[q] * ry;
-        az -= Q.mback[q] * rz;
-      }
+      const double mb = (!half || b >= q) ? Q.mback[q] : 0.0;
+      ax -= mb * rx;
+      ay -= mb * ry;
+      az -= mb * rz;
     }
     return;
   }
-  const int np = (TP && b != 0) ? 1 : sz;  // planets in a particle's group: star only
+  // test-particle group: member 0 is the massless particle, the planets
+  // (b >= 1) feel only the star
 #pragma unroll
   for (int q = 1; q < P; ++q) {
     if (q >= sz) break;
     double xj, yj, zj;
-    if (P == 2) {  // the partner is lane ^ 1
+    if (P == 2) {
       xj = dpp_d<kDppQuadSwap1>(x);
       yj = dpp_d<kDppQuadSwap1>(y);
       zj = dpp_d<kDppQuadSwap1>(z);
@@ -282,21 +306,11 @@ __device__ __forceinline__ void ha_accel_par(int sz, int b, double x, double y,
       yj = shfl_d(y, Q.lane[q]);
       zj = shfl_d(z, Q.lane[q]);
     }
-    const double dx = xj - x, dy = yj - y, dz = zj - z;
-    const double q2 = dx * dx + dy * dy + dz * dz;
-    // At r >= rc_ij, K = 1 and K' = 0 exactly (y clamps to 1), so the term
-    // vanishes: lanes beyond near2 (a margin far above the rounding of y)
-    // skip it, and the whole wave does when no pair is inside.
-    if (q < np && q2 < Q.near2[q]) {
-      const double iq = rsqrt_nr(q2);
-      const double iq2 = iq * iq;
-      double K = 1.0, dK = 0.0;
-      changeover_clamped(q2 * iq, Q.rcij[q], Q.i09[q], K, dK);
-      const double sc = G * Q.m[q] * ((1.0 - K) * iq2 * iq + dK * iq2);
-      ax += sc * dx;
-      ay += sc * dy;
-      az += sc * dz;
-    }
+    double fx, fy, fz;
+    ha_pair(xj - x, yj - y, zj - z, Q.rcij[q], Q.i09[q], Q.near2[q], G, b == 0, fx, fy, fz);
+    ax += Q.m[q] * fx;
+    ay += Q.m[q] * fy;
+    az += Q.m[q] * fz;
   }
 }
 
@@ -486,7 +500,8 @@ __device__ __forceinline__ int bs_integrate_par(int sz, double y[6], double H,
   return 0;
 }
 
-// One group of sz <= P members over H.  Every lane of member b =
+// One group of sz members over H, P the smallest of 2, 4, 8 not below sz
+// (so P/2 < sz <= P; the pair terms rely on it).  Every lane of member b =
 // par_memb<P>(lane) holds the member's start state in y (dummy state for
 // b >= sz); mm[] and mrc[] (any memory) give every member's mass and critical
 // radius.  On return y holds member b's state after H in each of its lanes
