@@ -66,6 +66,7 @@ struct MassiveWs {
   int enc_cap;
   double4* xm;          // x, y, z, m          (democratic: heliocentric x)
   double4* vv;          // vx, vy, vz, 0       (barycentric v)
+  double4* xs;          // x, m at the start of the step, for the opening kick
   double4* xpre;        // pre-drift x
   double4* vpre;        // pre-drift v
   double4* afar;        // acceleration of non-candidate pairs (x G)

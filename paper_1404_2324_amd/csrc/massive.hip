@@ -1,10 +1,10 @@
 // Main-mode kernels of the hybrid symplectic step (Grimm & Stadel,
 // arXiv:1404.2324, Sec. 2.2 step recipe and Sec. 3.2 kernels), for gfx950.
 //
-// One step is seven launches on one stream (captured once into a HIP graph):
-//   k_kick_open    opening kick: cached non-candidate acceleration + candidate
-//                  pairs recomputed with the new radii (KickA/KickB, Sec 3.2.3)
-//   k_drift        Sun kick tau/2 (Eq. 3) + pre-drift copy + Kepler drift
+// One step is six launches on one stream (captured once into a HIP graph):
+//   k_open_drift   opening kick: cached non-candidate acceleration + candidate
+//                  pairs recomputed with the new radii (KickA/KickB, Sec 3.2.3);
+//                  Sun kick tau/2 (Eq. 3) + pre-drift copy + Kepler drift
 //                  (Eq. 9) + momentum partials for the second Sun kick
 //   k_encounter    Hermite test of every candidate (Eqs. 10-12), ballot
 //                  compaction of the confirmed pairs
@@ -16,6 +16,7 @@
 #include <hip/hip_ext.h>
 
 #include <climits>
+#include <cstddef>
 
 #include "bs_device.h"
 #include "device_math.h"
@@ -76,6 +77,7 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 struct KickArgs {
   const double4* __restrict__ xm;     // read by the pair kernel
   double4* __restrict__ xm_rw;        // same array, updated by the finish
+  double4* __restrict__ xs;           // start positions of the next step
   const double* __restrict__ thr;
   const double* __restrict__ rc;
   double4* __restrict__ part;
@@ -197,8 +199,11 @@ __global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a,
       a.st->P2[0] = px;
       a.st->P2[1] = py;
       a.st->P2[2] = pz;
+      a.st->ctl = 0u;  // the finish sets the bits for the next opening kick
     }
   }
+  if (MODE == KICK_INIT && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+    a.st->ctl = 0u;
   __shared__ double sh[W][6][64];
   sh[wave][0][lane] = fx;
   sh[wave][1][lane] = fy;
@@ -270,6 +275,7 @@ __global__ __launch_bounds__(kVecBlock) void k_kick_finish(KickArgs a, int njb) 
   a.afar[i] = make_double4(G * S0, G * S1, G * S2, 0.0);
   if (MODE == KICK_INIT) {
     a.rc_next[i] = a.rc[i];
+    a.xs[i] = a.xm_rw[i];
     return;
   }
   const double Px = a.st->P2[0], Py = a.st->P2[1], Pz = a.st->P2[2];
@@ -278,6 +284,7 @@ __global__ __launch_bounds__(kVecBlock) void k_kick_finish(KickArgs a, int njb) 
   p.y += a.h * Py / a.m0;
   p.z += a.h * Pz / a.m0;
   a.xm_rw[i] = p;
+  a.xs[i] = p;
   double4 v = a.vv[i];
   v.x += a.h * (G * (S0 + S3));
   v.y += a.h * (G * (S1 + S4));
@@ -291,9 +298,14 @@ __global__ __launch_bounds__(kVecBlock) void k_kick_finish(KickArgs a, int njb) 
 
 // ---------------------------------------------------------------------------
 struct OpenArgs {
-  const double4* __restrict__ xm;
-  double4* __restrict__ xstart;  // snapshot of the start positions (or null)
+  const double4* __restrict__ xs;  // start positions (with mass): partners are read here
+  double4* __restrict__ xm;        // drifted positions out
+  double4* __restrict__ xstart;    // snapshot of the start positions (or null)
   double4* __restrict__ vv;
+  double4* __restrict__ xpre;
+  double4* __restrict__ vpre;
+  double4* __restrict__ xpost;     // snapshot after the drift (or null)
+  double4* __restrict__ vpost;
   const double4* __restrict__ afar;
   const double* __restrict__ rc_next;
   double* __restrict__ rc_cur;
@@ -301,9 +313,10 @@ struct OpenArgs {
   const int* __restrict__ ccnt;
   const int* __restrict__ ctab;
   double* __restrict__ partP;
+  double* __restrict__ partP2;
   DevStat* __restrict__ st;
-  int n, cpb, encounter_free;
-  double G, h, pf2;
+  int n, cpb, encounter_free, max_iter;
+  double G, h, pf2, m0, mu, dt;
 };
 
 __device__ __forceinline__ void pair_hb(double xi, double yi, double zi,
@@ -355,7 +368,7 @@ __device__ __forceinline__ void sum_partners(const int (&jj)[N], int c0, int cnt
 #pragma unroll
   for (int u = 0; u < B; ++u) {
     const int jl = c0 + u < cnt ? jj[c0 + u] : i;  // padded slots read a valid index
-    pj[u] = a.xm[jl];
+    pj[u] = a.xs[jl];
     rj[u] = a.rc_next[jl];
   }
 #pragma unroll
@@ -363,26 +376,36 @@ __device__ __forceinline__ void sum_partners(const int (&jj)[N], int c0, int cnt
     if (c0 + u < cnt) pair_hb(p.x, p.y, p.z, rci, pj[u], rj[u], a.encounter_free, cx, cy, cz);
 }
 
-// Opening kick (KickA/KickB, Sec. 3.2.3): the closing kick's non-candidate
-// sum is reused; candidate pairs are recomputed with this step's radii in
-// ascending partner order.  When some radius grew beyond pf times the radius
-// that formed the candidate table the reuse is not exact and the full pair
-// sum is taken instead.  Also installs the step's radii and thresholds and
-// leaves per-block momentum partials for the Sun kick.
-__global__ __launch_bounds__(kVecBlock) void k_kick_open(OpenArgs a) {
+// Opening kick (KickA/KickB, Sec. 3.2.3), first Sun kick tau/2 (H_C flow,
+// Eq. 3), pre-drift copy and Kepler drift (Eq. 9) in one pass per body.
+// Kick: the closing kick's non-candidate sum is reused; candidate pairs are
+// recomputed with this step's radii in ascending partner order, partners
+// read from the start positions xs (xm receives the drifted positions).
+// When some radius grew beyond pf times the radius that formed the
+// candidate table the reuse is not exact and the full pair sum is taken.
+// Sun kick: the momentum P = sum m v is the one the previous step's second
+// Sun kick used (or that of the initial state); the kicks in between change
+// it by tau/2 sum m a = 0 (pair terms cancel), so it equals the momentum
+// after this opening kick up to rounding.  Also installs the step's radii
+// and thresholds, leaves per-block momentum partials after the kick and
+// after the drift, and resets the step's encounter counters.
+__global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
   __shared__ double sh[3 * (kVecBlock / 64)];
   const int i = blockIdx.x * kVecBlock + threadIdx.x;
   const bool iv = i < a.n;
   const bool full = (__builtin_amdgcn_readfirstlane(a.st->ctl) & C_FULLKICK) != 0;
-  double m = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
+  const double Ps = a.h / a.m0;
+  const double sx = Ps * a.st->P2[0], sy = Ps * a.st->P2[1], sz = Ps * a.st->P2[2];
+  double m = 0.0, kx = 0.0, ky = 0.0, kz = 0.0, dx = 0.0, dy = 0.0, dz = 0.0;
+  int it = 0;
   if (iv) {
-    const double4 p = a.xm[i];
+    const double4 p = a.xs[i];
     const double rci = a.rc_next[i];
     if (a.xstart) a.xstart[i] = p;
     double ax = 0.0, ay = 0.0, az = 0.0;
     if (full) {
       for (int j = 0; j < a.n; ++j)
-        if (j != i) pair_hb(p.x, p.y, p.z, rci, a.xm[j], a.rc_next[j], a.encounter_free, ax, ay, az);
+        if (j != i) pair_hb(p.x, p.y, p.z, rci, a.xs[j], a.rc_next[j], a.encounter_free, ax, ay, az);
       ax *= a.G;
       ay *= a.G;
       az *= a.G;
@@ -429,7 +452,7 @@ __global__ __launch_bounds__(kVecBlock) void k_kick_open(OpenArgs a) {
           }
           if (jm == INT_MAX) break;
           prev = jm;
-          pair_hb(p.x, p.y, p.z, rci, a.xm[jm], a.rc_next[jm], a.encounter_free, cx, cy, cz);
+          pair_hb(p.x, p.y, p.z, rci, a.xs[jm], a.rc_next[jm], a.encounter_free, cx, cy, cz);
         }
       }
       ax = af.x + a.G * cx;
@@ -440,89 +463,46 @@ __global__ __launch_bounds__(kVecBlock) void k_kick_open(OpenArgs a) {
     v.x += a.h * ax;
     v.y += a.h * ay;
     v.z += a.h * az;
-    a.vv[i] = v;
     a.rc_cur[i] = rci;
     a.thr[i] = a.encounter_free ? kTiny : fmax(a.pf2 * rci * rci, kTiny);
     m = p.w;
-    vx = v.x;
-    vy = v.y;
-    vz = v.z;
+    kx = v.x;
+    ky = v.y;
+    kz = v.z;
+    double x = p.x + sx, y = p.y + sy, z = p.z + sz;
+    a.xpre[i] = make_double4(x, y, z, 0.0);
+    a.vpre[i] = make_double4(v.x, v.y, v.z, 0.0);
+    dx = v.x;
+    dy = v.y;
+    dz = v.z;
+    it = kepler_drift(a.mu, a.dt, x, y, z, dx, dy, dz, a.max_iter);
+    if (it < 0) atomicOr(&a.st->flags, F_KEPLER);
+    a.xm[i] = make_double4(x, y, z, p.w);
+    a.vv[i] = make_double4(dx, dy, dz, 0.0);
+    if (a.xpost) {
+      a.xpost[i] = make_double4(x, y, z, p.w);
+      a.vpost[i] = make_double4(dx, dy, dz, 0.0);
+    }
   }
-  double Px = m * vx, Py = m * vy, Pz = m * vz;
+  const int itm = wave_max_i(abs(it));
+  if ((threadIdx.x & 63) == 0 && itm > 0) atomicMax(&a.st->kep_itmax, itm);
+  double Px = m * kx, Py = m * ky, Pz = m * kz;
   block_sum3<kVecBlock>(Px, Py, Pz, sh);
+  double Qx = m * dx, Qy = m * dy, Qz = m * dz;
+  block_sum3<kVecBlock>(Qx, Qy, Qz, sh);
   if (threadIdx.x == 0) {
     a.partP[4 * blockIdx.x + 0] = Px;
     a.partP[4 * blockIdx.x + 1] = Py;
     a.partP[4 * blockIdx.x + 2] = Pz;
-    if (full && blockIdx.x == 0) atomicAdd(&a.st->fullkicks, 1ull);
-  }
-}
-
-// ---------------------------------------------------------------------------
-struct DriftArgs {
-  double4* __restrict__ xm;
-  double4* __restrict__ vv;
-  double4* __restrict__ xpre;
-  double4* __restrict__ vpre;
-  const double* __restrict__ partP;
-  double* __restrict__ partP2;
-  double4* __restrict__ xpost;  // snapshot after the drift (or null)
-  double4* __restrict__ vpost;
-  DevStat* __restrict__ st;
-  int n, nblk, max_iter;
-  double h, m0, mu, dt;
-};
-
-// Sun kick tau/2 (H_C flow: x += tau/2 P/m0, Eq. 3) with P summed from the
-// opening kick's block partials, copy of the pre-drift state, Kepler drift;
-// leaves the momentum partials of the drifted velocities for the second Sun
-// kick and resets the step's encounter counters and control word.
-__global__ __launch_bounds__(kVecBlock) void k_drift(DriftArgs a) {
-  __shared__ double sh[3 * (kVecBlock / 64)];
-  double Px = 0.0, Py = 0.0, Pz = 0.0;
-  for (int b = 0; b < a.nblk; ++b) {
-    Px += a.partP[4 * b + 0];
-    Py += a.partP[4 * b + 1];
-    Pz += a.partP[4 * b + 2];
-  }
-  const int i = blockIdx.x * kVecBlock + threadIdx.x;
-  int it = 0;
-  double m = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
-  if (i < a.n) {
-    const double4 p = a.xm[i];
-    const double4 q = a.vv[i];
-    double x = p.x + a.h * Px / a.m0;
-    double y = p.y + a.h * Py / a.m0;
-    double z = p.z + a.h * Pz / a.m0;
-    vx = q.x;
-    vy = q.y;
-    vz = q.z;
-    a.xpre[i] = make_double4(x, y, z, 0.0);
-    a.vpre[i] = q;
-    it = kepler_drift(a.mu, a.dt, x, y, z, vx, vy, vz, a.max_iter);
-    if (it < 0) atomicOr(&a.st->flags, F_KEPLER);
-    a.xm[i] = make_double4(x, y, z, p.w);
-    a.vv[i] = make_double4(vx, vy, vz, 0.0);
-    if (a.xpost) {
-      a.xpost[i] = make_double4(x, y, z, p.w);
-      a.vpost[i] = make_double4(vx, vy, vz, 0.0);
-    }
-    m = p.w;
-  }
-  const int itm = wave_max_i(abs(it));
-  if ((threadIdx.x & 63) == 0 && itm > 0) atomicMax(&a.st->kep_itmax, itm);
-  double Qx = m * vx, Qy = m * vy, Qz = m * vz;
-  block_sum3<kVecBlock>(Qx, Qy, Qz, sh);
-  if (threadIdx.x == 0) {
     a.partP2[4 * blockIdx.x + 0] = Qx;
     a.partP2[4 * blockIdx.x + 1] = Qy;
     a.partP2[4 * blockIdx.x + 2] = Qz;
     if (blockIdx.x == 0) {
+      if (full) a.st->fullkicks += 1ull;
       a.st->nenc = 0;
       a.st->ncand = 0;
       a.st->ngroups = 0;
       a.st->maxg = 0;
-      a.st->ctl = 0u;
       a.st->nstep += 1ull;
     }
   }
@@ -1037,6 +1017,7 @@ KickArgs kick_args(const MassiveWs& w, const StepConsts& c) {
   KickArgs a;
   a.xm = w.xm;
   a.xm_rw = w.xm;
+  a.xs = w.xs;
   a.thr = w.thr;
   a.rc = w.rc_cur;
   a.part = w.part;
@@ -1120,6 +1101,7 @@ size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base, boo
   };
   w.xm = (double4*)take(np * sizeof(double4));
   w.vv = (double4*)take(np * sizeof(double4));
+  w.xs = (double4*)take(np * sizeof(double4));
   w.xpre = (double4*)take(np * sizeof(double4));
   w.vpre = (double4*)take(np * sizeof(double4));
   w.afar = (double4*)take(np * sizeof(double4));
@@ -1174,6 +1156,9 @@ hipError_t massive_prime(const MassiveWs& w, const StepConsts& c, hipStream_t s)
   hipLaunchKernelGGL(k_kick<KICK_INIT>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a,
                      a.xm, a.thr);
   hipLaunchKernelGGL(k_kick_finish<KICK_INIT>, dim3(ceil_div(4 * w.n, kVecBlock)), dim3(kVecBlock), 0, s, a, w.njb);
+  // the momentum for the first step's first Sun kick
+  double* P2 = reinterpret_cast<double*>(reinterpret_cast<char*>(w.st) + offsetof(DevStat, P2));
+  hipLaunchKernelGGL(k_momentum, dim3(1), dim3(1024), 0, s, nullptr, nullptr, w.xm, w.vv, w.n, P2);
   return hipGetLastError();
 }
 
@@ -1190,9 +1175,14 @@ hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, double* acc,
 hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
                         hipEvent_t ev0, hipEvent_t ev1) {
   OpenArgs o;
+  o.xs = w.xs;
   o.xm = w.xm;
   o.xstart = w.xstart;
   o.vv = w.vv;
+  o.xpre = w.xpre;
+  o.vpre = w.vpre;
+  o.xpost = w.xpost;
+  o.vpost = w.vpost;
   o.afar = w.afar;
   o.rc_next = w.rc_next;
   o.rc_cur = w.rc_cur;
@@ -1200,33 +1190,19 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
   o.ccnt = w.ccnt;
   o.ctab = w.ctab;
   o.partP = w.partP;
+  o.partP2 = w.partP2;
   o.st = w.st;
   o.n = w.n;
   o.cpb = w.cpb;
   o.encounter_free = c.encounter_free;
+  o.max_iter = c.kepler_max_iter;
   o.G = c.G;
   o.h = c.h;
   o.pf2 = c.pf2;
-  hipLaunchKernelGGL(k_kick_open, dim3(w.nblk), dim3(kVecBlock), 0, s, o);
-
-  DriftArgs d;
-  d.xm = w.xm;
-  d.vv = w.vv;
-  d.xpre = w.xpre;
-  d.vpre = w.vpre;
-  d.partP = w.partP;
-  d.partP2 = w.partP2;
-  d.xpost = w.xpost;
-  d.vpost = w.vpost;
-  d.st = w.st;
-  d.n = w.n;
-  d.nblk = w.nblk;
-  d.max_iter = c.kepler_max_iter;
-  d.h = c.h;
-  d.m0 = c.m0;
-  d.mu = c.mu;
-  d.dt = c.dt;
-  hipLaunchKernelGGL(k_drift, dim3(w.nblk), dim3(kVecBlock), 0, s, d);
+  o.m0 = c.m0;
+  o.mu = c.mu;
+  o.dt = c.dt;
+  hipLaunchKernelGGL(k_open_drift, dim3(w.nblk), dim3(kVecBlock), 0, s, o);
 
   if (!c.encounter_free) {
     EncArgs e;
