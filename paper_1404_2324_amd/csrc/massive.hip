@@ -484,8 +484,10 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
       a.vpost[i] = make_double4(dx, dy, dz, 0.0);
     }
   }
+  // the running maximum rarely grows: read it first, so that waves do not
+  // queue on one address every step
   const int itm = wave_max_i(abs(it));
-  if ((threadIdx.x & 63) == 0 && itm > 0) atomicMax(&a.st->kep_itmax, itm);
+  if ((threadIdx.x & 63) == 0 && itm > a.st->kep_itmax) atomicMax(&a.st->kep_itmax, itm);
   double Px = m * kx, Py = m * ky, Pz = m * kz;
   block_sum3<kVecBlock>(Px, Py, Pz, sh);
   double Qx = m * dx, Qy = m * dy, Qz = m * dz;
@@ -553,18 +555,19 @@ __device__ __forceinline__ int block_excl_scan(int v, int* shw, int* total) {
 // Encounter search (Sec. 3.2.4): one lane per candidate slot (body i, slot
 // k) over all workgroups, so the candidates' loads overlap across the chip.
 // The Hermite minimum of Eqs. (10)-(12) is taken for pairs i < j; confirmed
-// pairs are appended with a ballot compaction (one atomic per wave).
+// pairs are appended with a ballot compaction (one atomic per wave that has
+// any; the candidate count is taken by the grouping kernel instead, since
+// an atomic on one address from every wave serialises them).
 __global__ __launch_bounds__(kVecBlock) void k_encounter(EncArgs a) {
   const int t = blockIdx.x * kVecBlock + threadIdx.x;
   const int i = t / a.cpb, k = t - i * a.cpb;
   const int lane = threadIdx.x & 63;
-  bool cand = false, enc = false;
+  bool enc = false;
   int j = -1;
   double d2 = 0.0, rc2 = 0.0;
   if (i < a.n && k < min(a.ccnt[i], a.cpb)) {
     j = a.ctab[(size_t)i * a.cpb + k];
     if (j > i) {
-      cand = true;
       const double4 xi0 = a.xpre[i], xj0 = a.xpre[j], vi0 = a.vpre[i], vj0 = a.vpre[j];
       const double4 xi1 = a.xm[i], xj1 = a.xm[j], vi1 = a.vv[i], vj1 = a.vv[j];
       d2 = hermite_dmin2(a.dt, xj0.x - xi0.x, xj0.y - xi0.y, xj0.z - xi0.z,
@@ -576,13 +579,9 @@ __global__ __launch_bounds__(kVecBlock) void k_encounter(EncArgs a) {
       enc = d2 < rc2;
     }
   }
-  const unsigned long long cm = __ballot(cand);
   const unsigned long long msk = __ballot(enc);
   int b0 = 0;
-  if (lane == 0) {
-    if (cm) atomicAdd(&a.st->ncand, __popcll(cm));
-    if (msk) b0 = atomicAdd(&a.st->nenc, __popcll(msk));
-  }
+  if (lane == 0 && msk) b0 = atomicAdd(&a.st->nenc, __popcll(msk));
   b0 = __shfl(b0, 0, 64);
   if (enc) {
     const int pos = b0 + (int)lanemask_count(msk);
@@ -599,7 +598,7 @@ __global__ __launch_bounds__(kVecBlock) void k_encounter(EncArgs a) {
 // (LDS atomic min), links are shortened by LINK[i] = LINK[LINK[i]], and both
 // sweeps repeat until nothing changes.  Groups are numbered by their smallest
 // member; offsets and members go to global memory for the BS kernel.  Also
-// clears the candidate table for the closing kick.
+// clears the candidate table for the closing kick and counts its pairs.
 __global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
   __shared__ int link[kGroupMaxN];
   __shared__ int gid[kGroupMaxN];
@@ -619,7 +618,13 @@ __global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
   }
   for (int e = tid; e < ne; e += kEncThreads) pr[e] = a.encij[e];
   __syncthreads();
-  for (int i = tid; i < n; i += kEncThreads) a.ccnt[i] = 0;
+  // candidate pairs i < j: every pair sits in both rows (the test is
+  // symmetric), so half the sum of the row lengths
+  int rows = 0;
+  for (int i = tid; i < n; i += kEncThreads) {
+    rows += min(a.ccnt[i], a.cpb);
+    a.ccnt[i] = 0;
+  }
   for (int e = tid; e < ne; e += kEncThreads) {
     inp[pr[e].x] = 1;
     inp[pr[e].y] = 1;
@@ -691,6 +696,8 @@ __global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
     }
   }
   if (tid == 0) a.goff[ng] = tot;
+  int nrow = 0;
+  (void)block_excl_scan(rows, shw, &nrow);
   mx = wave_max_i(mx);
   __syncthreads();
   if (lane == 0) shw[tid >> 6] = mx;
@@ -701,6 +708,7 @@ __global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
     for (int k = 0; k < kEncThreads / 64; ++k) m2 = max(m2, shw[k]);
     a.st->maxg = m2;
     a.st->ngroups = ng;
+    a.st->ncand = nrow / 2;
     a.st->enc_total += (unsigned long long)ne_all;
     if (ne_all > kEncLds || ne_all > a.enc_cap) atomicOr(&a.st->flags, F_ENC_OVF);
   }
