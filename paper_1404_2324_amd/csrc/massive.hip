@@ -741,15 +741,24 @@ struct BsArgs {
 // the BS status and, per member lane, its momentum change m (v_BS - v_drift).
 template <int P>
 __device__ __forceinline__ int bs_member_group(const BsArgs& a, int sz, const int* mem,
-                                               const double* mm, const double* mrc,
-                                               long long* nsub, double& dpx, double& dpy,
-                                               double& dpz) {
+                                               double* mm, double* mrc, long long* nsub,
+                                               double& dpx, double& dpy, double& dpz) {
   const int lane = threadIdx.x & 63;
   const int b = par_memb<P>(lane);
   const int id = b < sz ? mem[b] : -1;
+  // every load the group needs is issued at once: the members' masses and
+  // radii (one per lane), their pre-drift states and drifted velocities
+  const int ml = lane < sz ? mem[lane] : -1;
+  double mw = 0.0, rcw = 0.0;
+  if (ml >= 0) {
+    mw = a.xm[ml].w;
+    rcw = a.rc[ml];
+  }
   double y[6] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double4 vo = make_double4(0.0, 0.0, 0.0, 0.0);
   if (id >= 0) {
     const double4 p = a.xpre[id], q = a.vpre[id];
+    vo = a.vv[id];
     y[0] = p.x;
     y[1] = p.y;
     y[2] = p.z;
@@ -757,11 +766,15 @@ __device__ __forceinline__ int bs_member_group(const BsArgs& a, int sz, const in
     y[4] = q.y;
     y[5] = q.z;
   }
+  if (ml >= 0) {
+    mm[lane] = mw;
+    mrc[lane] = rcw;
+  }
+  __syncthreads();
   const int r = bs_group<P, false>(sz, y, mm, mrc, a.dt, a.G, a.Gm0, a.tol, a.max_depth, nsub);
   dpx = dpy = dpz = 0.0;
   if (lane == par_lane<P>(0, 0, b) && id >= 0) {  // one lane per member writes
     const double m = mm[b];
-    const double4 vo = a.vv[id];
     dpx = m * (y[3] - vo.x);
     dpy = m * (y[4] - vo.y);
     dpz = m * (y[5] - vo.z);
@@ -798,11 +811,6 @@ __global__ __launch_bounds__(64) void k_bs(BsArgs a) {
     __syncthreads();
     double dpx = 0.0, dpy = 0.0, dpz = 0.0;
     if (sz <= kBsPar) {
-      if (lane < sz) {
-        mm[lane] = a.xm[mem[lane]].w;
-        mrc[lane] = a.rc[mem[lane]];
-      }
-      __syncthreads();
       int r;
       if (sz <= 2)
         r = bs_member_group<2>(a, sz, mem, mm, mrc, &nsub, dpx, dpy, dpz);
