@@ -112,6 +112,8 @@ struct TpWs {
   int* blk_kit;         // largest Kepler iteration count per block
   unsigned long long* sub;          // accepted BS substeps per workgroup / wave
   double* pl;           // planets' whole-step BS table
+  int64_t* rq;          // listed entries left to the wave path (this step)
+  int* rq_cnt;          // their count
   void* cum;            // the cumulative counters above, cleared at init
   size_t cum_bytes;
 };

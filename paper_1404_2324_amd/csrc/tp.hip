@@ -69,6 +69,8 @@ struct TpArgs {
   int* __restrict__ blk_kit;          // largest Kepler iteration count per block
   unsigned long long* __restrict__ sub;  // accepted BS substeps per block / wave
   double* __restrict__ pl;            // planets' full-step BS table
+  int64_t* __restrict__ rq;           // entries left to the wave path
+  int* __restrict__ rq_cnt;           // their count
   int64_t ntp, cap, nb;
   int nm, nblk, enc_free, max_iter;
   double G, h, m0, mu, dt, absdt, n2, pf2, tol;
@@ -258,6 +260,7 @@ __global__ __launch_bounds__(1024) void k_tp_scan(TpArgs a) {
     run += a.blk_cnt[b];
   }
   if (t == 1023) a.blk_off[a.nb] = sh[1023];
+  if (t == 0) *a.rq_cnt = 0;  // the wave path's queue of this step
 }
 
 // List entry of the d-th listed particle: the block whose region holds it
@@ -457,108 +460,123 @@ __global__ __launch_bounds__(256) void k_tp_bs1(TpArgs a) {
   const int64_t nl = a.blk_off[a.nb];
   const double P2x = a.st->P2[0], P2y = a.st->P2[1], P2z = a.st->P2[2];
   unsigned long long nsub = 0;
+  const int lane = threadIdx.x & 63;
   for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < nl;
        d += (int64_t)gridDim.x * 256) {
     const int64_t e = tp_entry(a, d);
-    const unsigned em = a.bs_mask[e];
-    if (__popc(em) != 1) continue;  // several planets: the wave path
-    const int j = __ffs(em) - 1;
-    const double rct = a.bs_rct[e];
-    PairK Q;
-    Q.Gm = a.G * a.px0[j].w;
-    Q.rcij = fmax(rct, a.rc[j]);
-    Q.i09 = Q.rcij > 0.0 ? 1.0 / (0.9 * Q.rcij) : 0.0;
-    Q.near2 = Q.rcij > 0.0 ? Q.rcij * Q.rcij * (1.0 + 1e-12) : 0.0;
-    const double* tab = a.pl + (size_t)j * kPlStride;
-    const double4 pp = a.ppre[j];
-    double y0[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) y0[c] = a.bs_y[c * a.cap + e];
-    double f0[6];
-    tp_pair_acc(a.mu, Q, y0[0], y0[1], y0[2], pp.x, pp.y, pp.z, f0[3], f0[4], f0[5]);
-    f0[0] = y0[3];
-    f0[1] = y0[4];
-    f0[2] = y0[5];
-    double R[8][6];
-    int kacc = -1;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      if (kacc < 0) {
-        const int n = 2 * (k + 1);
-        const double hs = a.dt / n;
-        double ym[6], yn[6], dd[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          ym[c] = y0[c];
-          yn[c] = y0[c] + hs * f0[c];
-        }
-        const double* pos = tab + 3 * k * (k + 1);
-        for (int m = 1; m <= n; ++m) {
-          tp_pair_acc(a.mu, Q, yn[0], yn[1], yn[2], pos[3 * (m - 1)], pos[3 * (m - 1) + 1],
-                      pos[3 * (m - 1) + 2], dd[3], dd[4], dd[5]);
-          dd[0] = yn[3];
-          dd[1] = yn[4];
-          dd[2] = yn[5];
-          if (m < n) {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-              const double t = ym[c] + 2.0 * hs * dd[c];
-              ym[c] = yn[c];
-              yn[c] = t;
+    // true when the entry is left to the wave path
+    const bool wave = [&]() -> bool {
+      const unsigned em = a.bs_mask[e];
+      if (__popc(em) != 1) return true;  // several planets
+      const int j = __ffs(em) - 1;
+      const double rct = a.bs_rct[e];
+      PairK Q;
+      Q.Gm = a.G * a.px0[j].w;
+      Q.rcij = fmax(rct, a.rc[j]);
+      Q.i09 = Q.rcij > 0.0 ? 1.0 / (0.9 * Q.rcij) : 0.0;
+      Q.near2 = Q.rcij > 0.0 ? Q.rcij * Q.rcij * (1.0 + 1e-12) : 0.0;
+      const double* tab = a.pl + (size_t)j * kPlStride;
+      const double4 pp = a.ppre[j];
+      double y0[6];
+  #pragma unroll
+      for (int c = 0; c < 6; ++c) y0[c] = a.bs_y[c * a.cap + e];
+      double f0[6];
+      tp_pair_acc(a.mu, Q, y0[0], y0[1], y0[2], pp.x, pp.y, pp.z, f0[3], f0[4], f0[5]);
+      f0[0] = y0[3];
+      f0[1] = y0[4];
+      f0[2] = y0[5];
+      double R[8][6];
+      int kacc = -1;
+  #pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (kacc < 0) {
+          const int n = 2 * (k + 1);
+          const double hs = a.dt / n;
+          double ym[6], yn[6], dd[6];
+  #pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            ym[c] = y0[c];
+            yn[c] = y0[c] + hs * f0[c];
+          }
+          const double* pos = tab + 3 * k * (k + 1);
+          for (int m = 1; m <= n; ++m) {
+            tp_pair_acc(a.mu, Q, yn[0], yn[1], yn[2], pos[3 * (m - 1)], pos[3 * (m - 1) + 1],
+                        pos[3 * (m - 1) + 2], dd[3], dd[4], dd[5]);
+            dd[0] = yn[3];
+            dd[1] = yn[4];
+            dd[2] = yn[5];
+            if (m < n) {
+  #pragma unroll
+              for (int c = 0; c < 6; ++c) {
+                const double t = ym[c] + 2.0 * hs * dd[c];
+                ym[c] = yn[c];
+                yn[c] = t;
+              }
             }
           }
-        }
-        double cur[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) cur[c] = 0.5 * (ym[c] + yn[c] + hs * dd[c]);
-#pragma unroll
-        for (int jn = 1; jn <= k; ++jn) {
-          const double ratio = (double)(2 * (k + 1)) / (double)(2 * (k - jn + 1));
-          const double den = ratio * ratio - 1.0;
-#pragma unroll
-          for (int c = 0; c < 6; ++c) {
-            const double old = R[jn - 1][c];
-            R[jn - 1][c] = cur[c];
-            cur[c] = cur[c] + (cur[c] - old) / den;
+          double cur[6];
+  #pragma unroll
+          for (int c = 0; c < 6; ++c) cur[c] = 0.5 * (ym[c] + yn[c] + hs * dd[c]);
+  #pragma unroll
+          for (int jn = 1; jn <= k; ++jn) {
+            const double ratio = (double)(2 * (k + 1)) / (double)(2 * (k - jn + 1));
+            const double den = ratio * ratio - 1.0;
+  #pragma unroll
+            for (int c = 0; c < 6; ++c) {
+              const double old = R[jn - 1][c];
+              R[jn - 1][c] = cur[c];
+              cur[c] = cur[c] + (cur[c] - old) / den;
+            }
+          }
+  #pragma unroll
+          for (int c = 0; c < 6; ++c) R[k][c] = cur[c];
+          if (k >= 1) {
+            const double err = fmax(fmax(relerr3(R[k], R[k - 1]), relerr3(R[k] + 3, R[k - 1] + 3)),
+                                    tab[kPlErr + k]);
+            if (err <= a.tol) kacc = k;
           }
         }
-#pragma unroll
-        for (int c = 0; c < 6; ++c) R[k][c] = cur[c];
-        if (k >= 1) {
-          const double err = fmax(fmax(relerr3(R[k], R[k - 1]), relerr3(R[k] + 3, R[k - 1] + 3)),
-                                  tab[kPlErr + k]);
-          if (err <= a.tol) kacc = k;
+      }
+      if (kacc < 0) return true;  // refinement needed
+      double y1[6];
+  #pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k == kacc) {
+  #pragma unroll
+          for (int c = 0; c < 6; ++c) y1[c] = R[k][c];
         }
+      ++nsub;
+      const int64_t ip = a.bs_idx[e];
+      const double Rs = a.rad[kTpMaxPlanets + ip] + a.rad[j];
+      bool hit = false;
+      if (Rs > 0.0) {
+        const double4 pv = a.vpre[j];
+        const double* q1 = tab + kPlDiag + 6 * kacc;
+        const double d2 = hermite_dmin2(a.dt, pp.x - y0[0], pp.y - y0[1], pp.z - y0[2],
+                                        pv.x - y0[3], pv.y - y0[4], pv.z - y0[5],
+                                        q1[0] - y1[0], q1[1] - y1[1], q1[2] - y1[2],
+                                        q1[3] - y1[3], q1[4] - y1[4], q1[5] - y1[5]);
+        hit = d2 < Rs * Rs;
       }
-    }
-    if (kacc < 0) continue;  // refinement needed: the wave path
-    double y1[6];
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k == kacc) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) y1[c] = R[k][c];
+      if (hit) {
+        tp_remove(a, e, em, 1, 0, y0);
+      } else {
+        tp_finish(a, a.pfin, a.rc, ip, y1[0], y1[1], y1[2], y1[3], y1[4], y1[5], rct, P2x, P2y,
+                  P2z);
       }
-    ++nsub;
-    const int64_t ip = a.bs_idx[e];
-    const double Rs = a.rad[kTpMaxPlanets + ip] + a.rad[j];
-    bool hit = false;
-    if (Rs > 0.0) {
-      const double4 pv = a.vpre[j];
-      const double* q1 = tab + kPlDiag + 6 * kacc;
-      const double d2 = hermite_dmin2(a.dt, pp.x - y0[0], pp.y - y0[1], pp.z - y0[2],
-                                      pv.x - y0[3], pv.y - y0[4], pv.z - y0[5],
-                                      q1[0] - y1[0], q1[1] - y1[1], q1[2] - y1[2],
-                                      q1[3] - y1[3], q1[4] - y1[4], q1[5] - y1[5]);
-      hit = d2 < Rs * Rs;
+      a.bs_mask[e] = 0u;  // done
+      return false;
+    }();
+    // entries for the wave path go to a queue (one atomic per wave), which
+    // spreads them evenly over the waves of the next kernel
+    const unsigned long long qm = __ballot(wave);
+    if (qm) {
+      const int leader = __ffsll((long long)qm) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(a.rq_cnt, __popcll(qm));
+      base = __shfl(base, leader, 64);
+      if (wave) a.rq[base + (int)lanemask_count_tp(qm)] = e;
     }
-    if (hit) {
-      tp_remove(a, e, em, 1, 0, y0);
-    } else {
-      tp_finish(a, a.pfin, a.rc, ip, y1[0], y1[1], y1[2], y1[3], y1[4], y1[5], rct, P2x, P2y,
-                P2z);
-    }
-    a.bs_mask[e] = 0u;  // done
   }
   for (int o = 32; o > 0; o >>= 1) nsub += __shfl_xor(nsub, o, 64);
   __shared__ unsigned long long s_sub[4];
@@ -570,11 +588,11 @@ __global__ __launch_bounds__(256) void k_tp_bs1(TpArgs a) {
 __global__ __launch_bounds__(64) void k_tp_bs(TpArgs a) {
   __shared__ double mm[kBsPar], mrc[kBsPar];
   const int lane = threadIdx.x;
-  const int64_t nl = a.blk_off[a.nb];
+  const int nq = *a.rq_cnt;
   long long nsub = 0;
   const double P2x = a.st->P2[0], P2y = a.st->P2[1], P2z = a.st->P2[2];
-  for (int64_t d = blockIdx.x; d < nl; d += gridDim.x) {
-    const int64_t e = tp_entry(a, d);
+  for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+    const int64_t e = a.rq[q];
     const unsigned em = a.bs_mask[e];
     if (em == 0u) continue;  // finished by the whole-step attempt
     const int sz = 1 + __popc(em);
@@ -735,6 +753,8 @@ TpArgs tp_args(const MassiveWs& w, const TpWs& t, const StepConsts& c) {
   a.blk_kit = t.blk_kit;
   a.sub = t.sub;
   a.pl = t.pl;
+  a.rq = t.rq;
+  a.rq_cnt = t.rq_cnt;
   a.ntp = t.ntp;
   a.cap = t.cap;
   a.nb = t.nb;
@@ -789,6 +809,8 @@ size_t tp_carve(TpWs& t, int64_t ntp, void* base) {
   t.sub = (unsigned long long*)take(kTpSubSlots * sizeof(unsigned long long));
   t.cum_bytes = off - cum0;
   t.pl = (double*)take((size_t)kTpMaxPlanets * kPlStride * sizeof(double));
+  t.rq = (int64_t*)take(nc * sizeof(int64_t));
+  t.rq_cnt = (int*)take(sizeof(int));
   return off;
 }
 
