@@ -41,12 +41,15 @@ __device__ __forceinline__ int wave_max_i(int v) {
 // 0.99 ulp, mean signed error 1e-4 ulp (no bias), i.e. at least as accurate
 // as 1/sqrt(x) through the IEEE square root and division, at a third of the
 // instruction count.  x = 0 gives NaN (callers mask that case).
+// Each step is written as y += y (1/2 - (x/2) y y): the same roundings as
+// y += (y/2) (1 - x y y), since halving is exact, with one multiply fewer.
 __device__ __forceinline__ double rsqrt_nr(double x) {
+  const double hx = 0.5 * x;
   double y = __builtin_amdgcn_rsq(x);
-  double e = fma(-x * y, y, 1.0);
-  y = fma(0.5 * y, e, y);
-  e = fma(-x * y, y, 1.0);
-  return fma(0.5 * y, e, y);
+  double e = fma(-hx * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-hx * y, y, 0.5);
+  return fma(y, e, y);
 }
 
 // 1/x for x in a bounded, well-scaled range (no zero, infinity or denormal):
