@@ -290,7 +290,12 @@ def main():
 
     # live timing of the closing-kick pair kernel inside real steps (launched
     # one by one with HIP events around it on the context's stream)
-    kick_us = sim.step_profiled(args.kick_steps)
+    # every kernel of the step timed on its own dispatch timestamps (HIP
+    # events recorded by the dispatches, on the context's stream)
+    split = sim.step_kernel_us(min(args.kick_steps, 512))
+    tot_us = sum(split.values())
+    dominant = max(split, key=split.get)
+    kick_us = split["k_kick"]
     kick_s = kick_us * 1e-6
 
     # capability of the same pair kernel at a size that fills the chip
@@ -350,6 +355,14 @@ def main():
                      "flops_per_pair": FLOPS_PER_PAIR,
                      "kick_pair_rate": pairs / kick_s,
                      "large_n": big},
+        "step_kernels": {
+            "us": split,
+            "share": {k: v / tot_us for k, v in split.items()},
+            "dominant": dominant,
+            "dominant_bound": ("latency: one wave per encounter group, and the step waits "
+                               "for the group with the most sequential BS substeps"
+                               if dominant == "k_bs" else "see roofline"),
+        },
         "stats": {k: st[k] for k in ("n_cand", "n_enc", "n_groups", "max_group",
                                       "kepler_iter_max", "bs_substeps", "enc_total",
                                       "full_kicks")},

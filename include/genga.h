@@ -155,6 +155,21 @@ int genga_step(genga_ctx *ctx, int64_t nsteps);
  * the latched status. */
 int genga_step_profiled(genga_ctx *ctx, int64_t nsteps, double *h_kick_us);
 
+/* Number of kernels of one main-mode step, and their order. */
+#define GENGA_STEP_KERNELS 6
+/* Run nsteps (1..512) main-mode steps (in test-particle mode followed by the
+ * particle kernels, untimed) with a HIP event pair around every kernel of
+ * the step, launched so that the events take the dispatch's own start and
+ * end timestamps.  h_us[GENGA_STEP_KERNELS] (host, caller-owned) receives
+ * each kernel's average duration in microseconds, in launch order: opening
+ * kick with Sun kick and Kepler drift, encounter search (Eqs. 10-12),
+ * grouping (App. A), Bulirsch-Stoer of the groups (Sec. 3.2.6), pair kernel
+ * of the closing kick, kick finish; the middle three are 0 with
+ * encounter_free.  The breakdown behind a step's time, not a faster step.
+ * Synchronising; returns the latched status (GENGA_EINVAL for a batched
+ * context, a null pointer or nsteps out of range). */
+int genga_step_kernel_us(genga_ctx *ctx, int64_t nsteps, double *h_us);
+
 /* Wait for the context's stream and return the latched device status as a
  * GENGA_E* code (GENGA_OK when clean).  Synchronising. */
 int genga_sync(genga_ctx *ctx);

@@ -387,33 +387,60 @@ int genga_step(genga_ctx* ctx, int64_t nsteps) {
   return GENGA_OK;
 }
 
-int genga_step_profiled(genga_ctx* ctx, int64_t nsteps, double* h_kick_us) {
-  if (!ctx || nsteps < 1 || nsteps > 4096 || !h_kick_us || ctx->mode == GENGA_BATCH)
-    return GENGA_EINVAL;
-  // one event pair per step, read after the last step: the steps run back to
-  // back as in a graph replay (no host round trip between them)
-  std::vector<hipEvent_t> ev((size_t)(2 * nsteps), nullptr);
+// Steps with event pairs around kernel slots (all of them, or only the pair
+// kernel's); us[k] is slot k's average dispatch duration in microseconds
+// (0 for slots the mode does not launch).  One event pair per slot and step,
+// read after the last step: the steps run back to back as in a graph replay.
+static_assert(GENGA_STEP_KERNELS == kStepKernels, "kernels per step");
+static int step_timed(genga_ctx* ctx, int64_t nsteps, bool all, double* us) {
+  constexpr int K = kStepKernels;
+  std::vector<hipEvent_t> ev((size_t)(2 * K * nsteps), nullptr);
+  const bool enc = !ctx->c.encounter_free;
+  auto timed = [&](int k) { return k == 4 || (all && (enc || k == 0 || k == 5)); };
   int rc = GENGA_OK;
-  for (auto& e : ev)
-    if (rc == GENGA_OK && hipEventCreate(&e) != hipSuccess) rc = GENGA_EHIP;
-  for (int64_t k = 0; k < nsteps && rc == GENGA_OK; ++k) {
-    if (massive_step(ctx->w, ctx->c, ctx->stream, ev[2 * k], ev[2 * k + 1]) != hipSuccess ||
+  for (int64_t t = 0; t < nsteps && rc == GENGA_OK; ++t)
+    for (int k = 0; k < K && rc == GENGA_OK; ++k)
+      if (timed(k))
+        for (int q = 0; q < 2; ++q)
+          if (hipEventCreate(&ev[(size_t)(2 * (K * t + k) + q)]) != hipSuccess) rc = GENGA_EHIP;
+  hipEvent_t last = nullptr;
+  for (int64_t t = 0; t < nsteps && rc == GENGA_OK; ++t) {
+    const hipEvent_t* kev = &ev[(size_t)(2 * K * t)];
+    if (massive_step(ctx->w, ctx->c, ctx->stream, kev) != hipSuccess ||
         (ctx->mode == GENGA_TEST && tp_step(ctx->w, ctx->t, ctx->c, ctx->stream) != hipSuccess))
       rc = GENGA_EHIP;
+    last = kev[2 * 5 + 1] ? kev[2 * 5 + 1] : kev[2 * 4 + 1];
   }
-  double tot = 0.0;
-  if (rc == GENGA_OK && hipEventSynchronize(ev.back()) != hipSuccess) rc = GENGA_EHIP;
-  for (int64_t k = 0; k < nsteps && rc == GENGA_OK; ++k) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) != hipSuccess) rc = GENGA_EHIP;
-    tot += ms;
-  }
+  if (rc == GENGA_OK && hipEventSynchronize(last) != hipSuccess) rc = GENGA_EHIP;
+  for (int k = 0; k < K; ++k) us[k] = 0.0;
+  for (int64_t t = 0; t < nsteps && rc == GENGA_OK; ++t)
+    for (int k = 0; k < K && rc == GENGA_OK; ++k) {
+      if (!timed(k)) continue;
+      float ms = 0.0f;
+      const size_t i = (size_t)(2 * (K * t + k));
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) rc = GENGA_EHIP;
+      us[k] += ms * 1e3 / (double)nsteps;
+    }
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
   if (rc != GENGA_OK) return rc;
   ctx->steps += nsteps;
-  *h_kick_us = tot * 1e3 / (double)nsteps;
   return genga_sync(ctx);
+}
+
+int genga_step_profiled(genga_ctx* ctx, int64_t nsteps, double* h_kick_us) {
+  if (!ctx || nsteps < 1 || nsteps > 4096 || !h_kick_us || ctx->mode == GENGA_BATCH)
+    return GENGA_EINVAL;
+  double us[kStepKernels];
+  const int r = step_timed(ctx, nsteps, false, us);
+  if (r >= 0) *h_kick_us = us[4];
+  return r;
+}
+
+int genga_step_kernel_us(genga_ctx* ctx, int64_t nsteps, double* h_us) {
+  if (!ctx || nsteps < 1 || nsteps > 512 || !h_us || ctx->mode == GENGA_BATCH)
+    return GENGA_EINVAL;
+  return step_timed(ctx, nsteps, true, h_us);
 }
 
 int genga_sync(genga_ctx* ctx) {

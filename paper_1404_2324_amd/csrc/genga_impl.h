@@ -150,10 +150,13 @@ hipError_t massive_unpack(const MassiveWs& w, const StepConsts& c, double* x,
                           double* v, int coords_out, hipStream_t s);
 hipError_t massive_prime(const MassiveWs& w, const StepConsts& c,
                          hipStream_t s);
-// When ev0 and ev1 are both given they take the start and end timestamps of
-// the closing-kick pair kernel's dispatch.
+// Kernels of one main-mode step in launch order: opening kick and drift,
+// encounter search, grouping, BS, pair kernel, kick finish (the middle three
+// only with encounters).  With kev (2 kStepKernels events), the events of
+// slot k take the start and end timestamps of kernel k's dispatch.
+constexpr int kStepKernels = 6;
 hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
-                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                        const hipEvent_t* kev = nullptr);
 hipError_t massive_energy(const MassiveWs& w, const StepConsts& c, double* dE,
                           double* dL, hipStream_t s);
 hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, double* acc,

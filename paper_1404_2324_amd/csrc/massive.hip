@@ -1188,8 +1188,19 @@ hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, double* acc,
   return hipGetLastError();
 }
 
+// Launch of kernel slot `slot` of the step; with kev, through hipExtLaunch so
+// that the slot's two events take the dispatch's own start and end.
+#define STEP_LAUNCH(slot, K, g, b, ...)                                             \
+  do {                                                                              \
+    if (kev)                                                                        \
+      hipExtLaunchKernelGGL(K, g, b, 0, s, kev[2 * (slot)], kev[2 * (slot) + 1], 0, \
+                            __VA_ARGS__);                                           \
+    else                                                                            \
+      hipLaunchKernelGGL(K, g, b, 0, s, __VA_ARGS__);                               \
+  } while (0)
+
 hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
-                        hipEvent_t ev0, hipEvent_t ev1) {
+                        const hipEvent_t* kev) {
   OpenArgs o;
   o.xs = w.xs;
   o.xm = w.xm;
@@ -1218,7 +1229,7 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
   o.m0 = c.m0;
   o.mu = c.mu;
   o.dt = c.dt;
-  hipLaunchKernelGGL(k_open_drift, dim3(w.nblk), dim3(kVecBlock), 0, s, o);
+  STEP_LAUNCH(0, k_open_drift, dim3(w.nblk), dim3(kVecBlock), o);
 
   if (!c.encounter_free) {
     EncArgs e;
@@ -1239,9 +1250,8 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
     e.cpb = w.cpb;
     e.enc_cap = w.enc_cap;
     e.dt = c.dt;
-    hipLaunchKernelGGL(k_encounter, dim3(ceil_div(w.n * w.cpb, kVecBlock)), dim3(kVecBlock), 0,
-                       s, e);
-    hipLaunchKernelGGL(k_group, dim3(1), dim3(kEncThreads), 0, s, e);
+    STEP_LAUNCH(1, k_encounter, dim3(ceil_div(w.n * w.cpb, kVecBlock)), dim3(kVecBlock), e);
+    STEP_LAUNCH(2, k_group, dim3(1), dim3(kEncThreads), e);
 
     BsArgs b;
     b.xm = w.xm;
@@ -1258,18 +1268,14 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
     b.dt = c.dt;
     b.tol = c.bs_tol;
     b.max_depth = c.bs_max_depth;
-    hipLaunchKernelGGL(k_bs, dim3(std::max(1, std::min(256, w.n / 2))), dim3(64), 0, s, b);
+    STEP_LAUNCH(3, k_bs, dim3(std::max(1, std::min(256, w.n / 2))), dim3(64), b);
   }
 
   KickArgs a = kick_args(w, c);
-  if (ev0 && ev1)
-    // the events take the dispatch's own start and end timestamps
-    hipExtLaunchKernelGGL(k_kick<KICK_CLOSE>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s,
-                          ev0, ev1, 0, a, (const double4*)a.xm, (const double*)a.thr);
-  else
-    hipLaunchKernelGGL(k_kick<KICK_CLOSE>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a,
-                       a.xm, a.thr);
-  hipLaunchKernelGGL(k_kick_finish<KICK_CLOSE>, dim3(ceil_div(4 * w.n, kVecBlock)), dim3(kVecBlock), 0, s, a, w.njb);
+  STEP_LAUNCH(4, k_kick<KICK_CLOSE>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), a,
+              (const double4*)a.xm, (const double*)a.thr);
+  STEP_LAUNCH(5, k_kick_finish<KICK_CLOSE>, dim3(ceil_div(4 * w.n, kVecBlock)), dim3(kVecBlock),
+              a, w.njb);
   return hipGetLastError();
 }
 

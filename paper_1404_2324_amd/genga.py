@@ -63,6 +63,7 @@ SIGNATURES = {
     "genga_step": (_i32, [_vp, _i64]),
     "genga_sync": (_i32, [_vp]),
     "genga_step_profiled": (_i32, [_vp, _i64, ctypes.POINTER(ctypes.c_double)]),
+    "genga_step_kernel_us": (_i32, [_vp, _i64, ctypes.POINTER(ctypes.c_double)]),
     "genga_get_state": (_i32, [_vp, _vp, _vp, _i32]),
     "genga_set_state": (_i32, [_vp, _vp, _vp, _i32]),
     "genga_energy": (_i32, [_vp, _vp, _vp]),
@@ -166,6 +167,16 @@ class Simulation:
         _check(lib().genga_step_profiled(self._ctx, int(nsteps), ctypes.byref(us)),
                "genga_step_profiled")
         return us.value
+
+    STEP_KERNELS = ("k_open_drift", "k_encounter", "k_group", "k_bs", "k_kick", "k_kick_finish")
+
+    def step_kernel_us(self, nsteps: int) -> dict:
+        """Run nsteps steps with every kernel timed (HIP events on the
+        dispatches); returns each kernel's average duration in microseconds,
+        in launch order."""
+        us = (ctypes.c_double * len(self.STEP_KERNELS))()
+        _check(lib().genga_step_kernel_us(self._ctx, int(nsteps), us), "genga_step_kernel_us")
+        return dict(zip(self.STEP_KERNELS, list(us)))
 
     def sync(self):
         return lib().genga_sync(self._ctx)

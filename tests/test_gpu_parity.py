@@ -363,6 +363,29 @@ def test_profiled_steps_match_graph_steps():
     assert a.stats()["steps"] == b.stats()["steps"] == 12
 
 
+def test_kernel_timed_steps_match_graph_steps():
+    """Every kernel of the step timed by its own dispatch timestamps: the
+    same steps bit for bit, a positive time for each kernel the mode
+    launches, and none for those it does not (encounter-free)."""
+    s = W.planetesimals(2048)
+    gp = _gparams()
+    a = G.Simulation(s.m, s.x, s.u, gp, coords="helio")
+    b = G.Simulation(s.m, s.x, s.u, gp, coords="helio")
+    a.step(10)
+    us = b.step_kernel_us(10)
+    _say("kernel us", us)
+    assert all(0.0 < v < 1e5 for v in us.values())
+    xa, va = a.state()
+    xb, vb = b.state()
+    assert torch.equal(xa, xb) and torch.equal(va, vb)
+    f = G.Simulation(s.m, s.x, s.u, _gparams(encounter_free=1), coords="helio")
+    uf = f.step_kernel_us(3)
+    assert uf["k_encounter"] == uf["k_group"] == uf["k_bs"] == 0.0
+    assert uf["k_kick"] > 0.0 and uf["k_open_drift"] > 0.0 and uf["k_kick_finish"] > 0.0
+    with pytest.raises(G.GengaError):
+        f.step_kernel_us(513)
+
+
 # ----------------------------------------------------------- error paths --
 def test_nan_input_rejected():
     s = W.plain_n16()
