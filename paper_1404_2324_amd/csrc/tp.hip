@@ -10,9 +10,9 @@
 //   k_tp_plan  a planet's Gragg sequences and extrapolation over the whole
 //              step (it feels only the star inside a particle's group), the
 //              same for every particle that meets it
-//   k_tp_bs1   one lane per particle meeting one planet: the BS attempt over
-//              the whole step with the planet taken from that table; most
-//              passages end here
+//   k_tp_bs1   eight lanes (one per extrapolation column) per particle
+//              meeting one planet: the BS attempt over the whole step with
+//              the planet taken from that table; most passages end here
 //   k_tp_bs    one wave per remaining particle: BS of the particle with the
 //              planets it encounters (planets feel only the star there) with
 //              binary refinement, then the rest of its step
@@ -456,18 +456,34 @@ __device__ __forceinline__ void tp_pair_acc(double Gm0, const PairK& Q, double x
   }
 }
 
+// Whole-step BS attempt of the passages that meet one planet, eight lanes per
+// passage: lane c integrates column c (n_c = 2 (c + 1) Gragg substeps, the
+// planet's positions from its table), the Aitken-Neville tableau is built
+// across the eight lanes by row shifts, and the first column k >= 1 whose
+// relative change, and the planet's own, are within tolerance is taken.
+// Passages that need refinement or meet several planets are queued for the
+// wave path (one atomic per wave), which spreads them evenly over its waves.
 __global__ __launch_bounds__(256) void k_tp_bs1(TpArgs a) {
   const int64_t nl = a.blk_off[a.nb];
   const double P2x = a.st->P2[0], P2y = a.st->P2[1], P2z = a.st->P2[2];
   unsigned long long nsub = 0;
   const int lane = threadIdx.x & 63;
-  for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < nl;
-       d += (int64_t)gridDim.x * 256) {
+  const int c = lane & 7;  // column of this lane
+  const int g0 = lane & ~7;
+  const int nsubs = 2 * (c + 1);
+  // Neville weights of the lane's column: 1/((n_c/n_{c-j})^2 - 1), 0 past c
+  double wj[8];
+#pragma unroll
+  for (int j = 1; j < 8; ++j) {
+    const int pp = c + 1, qq = c - j + 1;
+    wj[j] = j <= c ? (double)(qq * qq) / (double)(pp * pp - qq * qq) : 0.0;
+  }
+  const int64_t stride = (int64_t)gridDim.x * 256 / 8;
+  for (int64_t d = ((int64_t)blockIdx.x * 256 + threadIdx.x) / 8; d < nl; d += stride) {
     const int64_t e = tp_entry(a, d);
-    // true when the entry is left to the wave path
-    const bool wave = [&]() -> bool {
-      const unsigned em = a.bs_mask[e];
-      if (__popc(em) != 1) return true;  // several planets
+    const unsigned em = a.bs_mask[e];
+    bool wave = true;  // left to the wave path
+    if (__popc(em) == 1) {
       const int j = __ffs(em) - 1;
       const double rct = a.bs_rct[e];
       PairK Q;
@@ -478,104 +494,108 @@ __global__ __launch_bounds__(256) void k_tp_bs1(TpArgs a) {
       const double* tab = a.pl + (size_t)j * kPlStride;
       const double4 pp = a.ppre[j];
       double y0[6];
-  #pragma unroll
-      for (int c = 0; c < 6; ++c) y0[c] = a.bs_y[c * a.cap + e];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) y0[q] = a.bs_y[q * a.cap + e];
       double f0[6];
       tp_pair_acc(a.mu, Q, y0[0], y0[1], y0[2], pp.x, pp.y, pp.z, f0[3], f0[4], f0[5]);
       f0[0] = y0[3];
       f0[1] = y0[4];
       f0[2] = y0[5];
-      double R[8][6];
-      int kacc = -1;
-  #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        if (kacc < 0) {
-          const int n = 2 * (k + 1);
-          const double hs = a.dt / n;
-          double ym[6], yn[6], dd[6];
-  #pragma unroll
-          for (int c = 0; c < 6; ++c) {
-            ym[c] = y0[c];
-            yn[c] = y0[c] + hs * f0[c];
+      // Gragg's modified midpoint rule for this lane's column: z_1 = z_0 +
+      // hs f(z_0), z_{m+1} = z_{m-1} + 2 hs f(z_m), T0 = (z_{n-1} + z_n +
+      // hs f(z_n)) / 2, the points in two buffers used in turn
+      const double hs = a.dt / nsubs;
+      const double* pos = tab + 3 * c * (c + 1);
+      double Z0[6], Z1[6], dd[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        Z0[q] = y0[q];
+        Z1[q] = y0[q] + hs * f0[q];
+      }
+      for (int m = 1; m < 16; m += 2) {
+        // odd m: evaluate at z_m (Z1), z_{m+1} into Z0
+        if (m <= nsubs) {
+          tp_pair_acc(a.mu, Q, Z1[0], Z1[1], Z1[2], pos[3 * (m - 1)], pos[3 * (m - 1) + 1],
+                      pos[3 * (m - 1) + 2], dd[3], dd[4], dd[5]);
+          dd[0] = Z1[3];
+          dd[1] = Z1[4];
+          dd[2] = Z1[5];
+          if (m < nsubs) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) Z0[q] = Z0[q] + 2.0 * hs * dd[q];
           }
-          const double* pos = tab + 3 * k * (k + 1);
-          for (int m = 1; m <= n; ++m) {
-            tp_pair_acc(a.mu, Q, yn[0], yn[1], yn[2], pos[3 * (m - 1)], pos[3 * (m - 1) + 1],
-                        pos[3 * (m - 1) + 2], dd[3], dd[4], dd[5]);
-            dd[0] = yn[3];
-            dd[1] = yn[4];
-            dd[2] = yn[5];
-            if (m < n) {
-  #pragma unroll
-              for (int c = 0; c < 6; ++c) {
-                const double t = ym[c] + 2.0 * hs * dd[c];
-                ym[c] = yn[c];
-                yn[c] = t;
-              }
-            }
-          }
-          double cur[6];
-  #pragma unroll
-          for (int c = 0; c < 6; ++c) cur[c] = 0.5 * (ym[c] + yn[c] + hs * dd[c]);
-  #pragma unroll
-          for (int jn = 1; jn <= k; ++jn) {
-            const double ratio = (double)(2 * (k + 1)) / (double)(2 * (k - jn + 1));
-            const double den = ratio * ratio - 1.0;
-  #pragma unroll
-            for (int c = 0; c < 6; ++c) {
-              const double old = R[jn - 1][c];
-              R[jn - 1][c] = cur[c];
-              cur[c] = cur[c] + (cur[c] - old) / den;
-            }
-          }
-  #pragma unroll
-          for (int c = 0; c < 6; ++c) R[k][c] = cur[c];
-          if (k >= 1) {
-            const double err = fmax(fmax(relerr3(R[k], R[k - 1]), relerr3(R[k] + 3, R[k - 1] + 3)),
-                                    tab[kPlErr + k]);
-            if (err <= a.tol) kacc = k;
+        }
+        // even m + 1: evaluate at z_{m+1} (Z0), z_{m+2} into Z1
+        if (m + 1 <= nsubs) {
+          tp_pair_acc(a.mu, Q, Z0[0], Z0[1], Z0[2], pos[3 * m], pos[3 * m + 1], pos[3 * m + 2],
+                      dd[3], dd[4], dd[5]);
+          dd[0] = Z0[3];
+          dd[1] = Z0[4];
+          dd[2] = Z0[5];
+          if (m + 1 < nsubs) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) Z1[q] = Z1[q] + 2.0 * hs * dd[q];
           }
         }
       }
-      if (kacc < 0) return true;  // refinement needed
-      double y1[6];
-  #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (k == kacc) {
-  #pragma unroll
-          for (int c = 0; c < 6; ++c) y1[c] = R[k][c];
+      // n is even: z_n is in Z0 and z_{n-1} in Z1; dd = f(z_n)
+      double cur[6], sub[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        cur[q] = 0.5 * (Z1[q] + Z0[q] + hs * dd[q]);
+        sub[q] = cur[q];
+      }
+      // tableau across the columns: after j steps lane c holds T[c][min(j, c)]
+#pragma unroll
+      for (int jn = 1; jn < 8; ++jn) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          sub[q] = jn == c ? cur[q] : sub[q];  // T[c][c-1]
+          const double nb = dpp_d<kDppRowShr1>(cur[q]);
+          cur[q] = fma(cur[q] - nb, wj[jn], cur[q]);
         }
-      ++nsub;
-      const int64_t ip = a.bs_idx[e];
-      const double Rs = a.rad[kTpMaxPlanets + ip] + a.rad[j];
-      bool hit = false;
-      if (Rs > 0.0) {
-        const double4 pv = a.vpre[j];
-        const double* q1 = tab + kPlDiag + 6 * kacc;
-        const double d2 = hermite_dmin2(a.dt, pp.x - y0[0], pp.y - y0[1], pp.z - y0[2],
-                                        pv.x - y0[3], pv.y - y0[4], pv.z - y0[5],
-                                        q1[0] - y1[0], q1[1] - y1[1], q1[2] - y1[2],
-                                        q1[3] - y1[3], q1[4] - y1[4], q1[5] - y1[5]);
-        hit = d2 < Rs * Rs;
       }
-      if (hit) {
-        tp_remove(a, e, em, 1, 0, y0);
-      } else {
-        tp_finish(a, a.pfin, a.rc, ip, y1[0], y1[1], y1[2], y1[3], y1[4], y1[5], rct, P2x, P2y,
-                  P2z);
+      const double err = fmax(fmax(relerr3(cur, sub), relerr3(cur + 3, sub + 3)), tab[kPlErr + c]);
+      const unsigned okm = (unsigned)(__ballot(c >= 1 && err <= a.tol) >> g0) & 0xFFu;
+      if (okm != 0u) {
+        wave = false;
+        const int kacc = __ffs(okm) - 1;
+        double y1[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) y1[q] = shfl_d(cur[q], g0 + kacc);
+        if (c == 0) {
+          ++nsub;
+          const int64_t ip = a.bs_idx[e];
+          const double Rs = a.rad[kTpMaxPlanets + ip] + a.rad[j];
+          bool hit = false;
+          if (Rs > 0.0) {
+            const double4 pv = a.vpre[j];
+            const double* q1 = tab + kPlDiag + 6 * kacc;
+            const double d2 = hermite_dmin2(a.dt, pp.x - y0[0], pp.y - y0[1], pp.z - y0[2],
+                                            pv.x - y0[3], pv.y - y0[4], pv.z - y0[5],
+                                            q1[0] - y1[0], q1[1] - y1[1], q1[2] - y1[2],
+                                            q1[3] - y1[3], q1[4] - y1[4], q1[5] - y1[5]);
+            hit = d2 < Rs * Rs;
+          }
+          if (hit) {
+            tp_remove(a, e, em, 1, 0, y0);
+          } else {
+            tp_finish(a, a.pfin, a.rc, ip, y1[0], y1[1], y1[2], y1[3], y1[4], y1[5], rct, P2x,
+                      P2y, P2z);
+          }
+          a.bs_mask[e] = 0u;  // done
+        }
       }
-      a.bs_mask[e] = 0u;  // done
-      return false;
-    }();
-    // entries for the wave path go to a queue (one atomic per wave), which
-    // spreads them evenly over the waves of the next kernel
-    const unsigned long long qm = __ballot(wave);
+    }
+    // passages left to the wave path: one queue slot each (lane c = 0)
+    const bool q0 = wave && c == 0;
+    const unsigned long long qm = __ballot(q0);
     if (qm) {
       const int leader = __ffsll((long long)qm) - 1;
       int base = 0;
       if (lane == leader) base = atomicAdd(a.rq_cnt, __popcll(qm));
       base = __shfl(base, leader, 64);
-      if (wave) a.rq[base + (int)lanemask_count_tp(qm)] = e;
+      if (q0) a.rq[base + (int)lanemask_count_tp(qm)] = e;
     }
   }
   for (int o = 32; o > 0; o >>= 1) nsub += __shfl_xor(nsub, o, 64);
