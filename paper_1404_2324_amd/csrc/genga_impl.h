@@ -119,7 +119,7 @@ struct TpWs {
 };
 
 constexpr int kTpMaxPlanets = 32;
-constexpr int kTpBs1Grid = 512;    // workgroups of the whole-step BS attempt
+constexpr int kTpBs1Grid = 1024;   // workgroups of the whole-step BS attempt
 constexpr int kTpBsGrid = 2048;    // waves of the refinement path
 constexpr int kTpSubSlots = kTpBs1Grid + kTpBsGrid;
 
