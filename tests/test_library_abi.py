@@ -86,6 +86,9 @@ def test_argument_errors_without_device(G):
     assert L.genga_step(None, 1) == G.EINVAL
     assert L.genga_sync(None) == G.EINVAL
     assert L.genga_destroy(None) == G.EINVAL
+    us = (ctypes.c_double * 6)()
+    assert L.genga_step_kernel_us(None, 4, us) == G.EINVAL
+    assert L.genga_step_profiled(None, 4, us) == G.EINVAL
     ctx = ctypes.c_void_p()
     p = G.default_params()
     # null arrays are rejected before any device work
