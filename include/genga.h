@@ -234,17 +234,27 @@ int genga_collisions(genga_ctx *ctx, int64_t *h_tp, int32_t *h_planet,
                      int64_t cap, int64_t *h_n);
 
 /* Batched mode: time each kernel variant (register budget per wave: 1, 2 or
- * 4 waves per SIMD; systems handed out in index order or largest first) for
- * nsteps steps on a copy of the current state, with HIP events on the
- * context's stream, and keep the fastest for later steps.  h_us (host, cap
- * doubles) receives each variant's time in microseconds, *h_n the number of
- * variants (6), *h_choice the variant kept.  The state is not advanced.
- * Synchronising.  Errors: EINVAL (other mode), EOVERFLOW (cap < 6), EHIP. */
+ * 4 waves per SIMD; one system per wave handed out in index order or
+ * largest first, or two systems per wave, consecutive in the largest-first
+ * order, for systems of up to 32 bodies) for nsteps steps on a copy of the
+ * current state, with HIP events on the context's stream, and keep the
+ * fastest for later steps.  All variants give the same results.  h_us (host,
+ * cap doubles) receives each variant's time in microseconds (-1 for a
+ * variant these systems cannot use: two per wave with a system over 32
+ * bodies), *h_n the number of variants (9), *h_choice the variant kept.  The
+ * state is not advanced.  Synchronising.  Errors: EINVAL (other mode),
+ * EOVERFLOW (cap < 9), EHIP. */
 int genga_tune(genga_ctx *ctx, int nsteps, double *h_us, int cap, int *h_n,
                int *h_choice);
 
-/* Description of tuner variant v (static storage). */
+/* Description of tuner variant v (static storage; "?" outside 0..8). */
 const char *genga_tune_variant(int v);
+
+/* Batched mode: use variant v (as numbered by genga_tune) for later steps
+ * instead of the tuner's choice.  Not synchronising.  Errors: EINVAL (other
+ * mode, v outside 0..8, or a two-systems-per-wave variant with a system over
+ * 32 bodies). */
+int genga_batch_set_variant(genga_ctx *ctx, int v);
 
 /* Batched mode: a system whose step fails (Kepler non-convergence, BS depth)
  * stops there with the state it had before that step, and the others go on

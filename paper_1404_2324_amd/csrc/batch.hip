@@ -48,32 +48,99 @@ __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v,
   return ((unsigned long long)hi << 32) | lo;
 }
 
+// Reductions over the lanes of one system: the whole wave (PK = 1) or the
+// lane's half (PK = 2, lanes 0-31 and 32-63 hold two systems).
+template <int PK>
+__device__ __forceinline__ double sys_sum(double v) {
+  for (int o = 32 / PK; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int PK>
+__device__ __forceinline__ int sys_max_i(int v) {
+  for (int o = 32 / PK; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int PK>
+__device__ __forceinline__ int sys_sum_i(int v) {
+  for (int o = 32 / PK; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int PK>
+__device__ __forceinline__ unsigned sys_or(unsigned v) {
+  for (int o = 32 / PK; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Lanes of the half that holds lane l (PK = 2) or the whole wave.
+template <int PK>
+__device__ __forceinline__ unsigned long long sys_lanes(int l) {
+  return PK == 1 ? ~0ull : (0xffffffffull << (l & 32));
+}
+
+// LDS slot of lane j for the two-systems-per-wave partner tables: the second
+// half is offset by one entry so that the two halves' broadcast reads of
+// partner jj fall in different banks.
+__device__ __forceinline__ int kick_slot(int j) { return j + (j >> 5); }
+constexpr int kKickSlots = 66;
+
 // Pair acceleration of H_B (Eq. 2 gradient) on the lane's body from every
 // other body of the system; with want_cand, also the partners inside the
-// prechecker radius pf r_crit,ij (Sec. 2.2).  rc = 0 everywhere gives the
-// Newtonian pair sum (K = 1, the encounter-free map).
-__device__ __forceinline__ void sys_kick(int n, int lane, double x, double y, double z, double m,
-                                         double rc, double G, double pf2, bool want_cand,
-                                         double& ax, double& ay, double& az,
-                                         unsigned long long& cand) {
+// prechecker radius pf r_crit,ij (Sec. 2.2), as bits of lane indices.
+// rc = 0 everywhere gives the Newtonian pair sum (K = 1, the encounter-free
+// map).  The system occupies lanes hb .. hb + nh - 1; partners are visited
+// in index order jj = 0 .. nh - 1 whatever PK, so both layouts give the same
+// sums.  One system per wave reads the partner by wave-uniform lane reads;
+// two systems per wave (nloop = the larger size, kp / krc: LDS tables of
+// kKickSlots entries) read it from LDS, where each half's lanes all read one
+// address.
+template <int PK>
+__device__ __forceinline__ void sys_kick(int nloop, int nh, int lane, int hb, double x, double y,
+                                         double z, double m, double rc, double G, double pf2,
+                                         bool want_cand, double& ax, double& ay, double& az,
+                                         unsigned long long& cand, double4* kp, double* krc) {
   ax = ay = az = 0.0;
   cand = 0ull;
-  for (int j = 0; j < n; ++j) {
-    const double xj = readlane_d(x, j), yj = readlane_d(y, j), zj = readlane_d(z, j);
-    const double mj = readlane_d(m, j), rcj = readlane_d(rc, j);
-    if (j != lane) {
+  if (PK == 2) {
+    __syncthreads();  // earlier reads of the tables are done
+    kp[kick_slot(lane)] = make_double4(x, y, z, m);
+    krc[kick_slot(lane)] = rc;
+    __syncthreads();
+  }
+  for (int jj = 0; jj < nloop; ++jj) {
+    const int j = hb + jj;
+    double xj, yj, zj, mj, rcj;
+    if (PK == 1) {
+      xj = readlane_d(x, jj);
+      yj = readlane_d(y, jj);
+      zj = readlane_d(z, jj);
+      mj = readlane_d(m, jj);
+      rcj = readlane_d(rc, jj);
+    } else {
+      const double4 pj = kp[kick_slot(j)];
+      xj = pj.x;
+      yj = pj.y;
+      zj = pj.z;
+      mj = pj.w;
+      rcj = krc[kick_slot(j)];
+    }
+    if (j != lane && (PK == 1 || jj < nh)) {
+      // the fused operations are spelled out, so that the roundings do not
+      // depend on how the partner data arrive (lane reads or LDS)
       const double dx = xj - x, dy = yj - y, dz = zj - z;
-      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
       const double ir = rsqrt_nr(r2);
       const double ir2 = ir * ir;
       const double rcij = fmax(rc, rcj);
       const double r = r2 * ir;
       double K = 1.0, dK = 0.0;
       if (r < rcij) changeover(r, rcij, K, dK);
-      const double s = mj * (K * ir2 * ir - dK * ir2);
-      ax += s * dx;
-      ay += s * dy;
-      az += s * dz;
+      const double s = mj * fma(K * ir2, ir, -(dK * ir2));
+      ax = fma(s, dx, ax);
+      ay = fma(s, dy, ay);
+      az = fma(s, dz, az);
       if (want_cand && r2 < pf2 * rcij * rcij) cand |= 1ull << j;
     }
   }
@@ -151,24 +218,38 @@ __device__ __forceinline__ int group_seq(const BatchArgs& a, int sz, unsigned lo
   return r;
 }
 
-template <int LB>
+// PK systems per wave: one (lanes 0..63 for up to 64 bodies) or two (lanes
+// 0-31 and 32-63, systems of up to 32 bodies, so that small systems fill the
+// wave).  Every per-system quantity is a per-lane value uniform over the
+// system's lanes; the wave runs the step while either of its systems is
+// live, a stopped system's lanes keeping their state.  Both layouts do the
+// same arithmetic in the same order on each system.
+template <int LB, int PK>
 __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
   __shared__ double mm[kBsPar], mrc[kBsPar];
+  __shared__ double4 kp[PK == 2 ? kKickSlots : 1];
+  __shared__ double krc[PK == 2 ? kKickSlots : 1];
   const int lane = threadIdx.x;
-  const int s = a.order[blockIdx.x];
-  const int o = a.off[s];
-  const int n = a.off[s + 1] - o;
-  const bool act = lane < n;
-  const double m0 = a.m0[s];
+  const int hb = PK == 1 ? 0 : (lane & 32);  // first lane of the lane's system
+  const int hl = lane - hb;                  // the body's index in its system
+  const int si = PK * blockIdx.x + (PK == 1 ? 0 : (lane >> 5));
+  const bool has = si < a.nsys;
+  const int s = has ? a.order[si] : 0;
+  const int o = has ? a.off[s] : 0;
+  const int n = has ? a.off[s + 1] - o : 0;
+  const int nloop =
+      PK == 1 ? n : max(__builtin_amdgcn_readlane(n, 0), __builtin_amdgcn_readlane(n, 32));
+  const bool act = hl < n;
+  const double m0 = has ? a.m0[s] : 1.0;
   const double Gm0 = a.G * m0;
   // inactive lanes hold a massless dummy body far from the others
   double4 p = make_double4(1.0e3 + lane, 0.0, 0.0, 0.0);
   double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
-  unsigned long long cand = 0ull, enc = 0ull;
+  unsigned long long cand = 0ull, enc = 0ull, enc_last = 0ull;
   if (act) {
-    p = a.xm[o + lane];
-    q = a.vv[o + lane];
-    cand = a.cand[o + lane];
+    p = a.xm[o + hl];
+    q = a.vv[o + hl];
+    cand = a.cand[o + hl] << hb;  // stored as bits of indices in the system
   }
   double x = p.x, y = p.y, z = p.z, vx = q.x, vy = q.y, vz = q.z;
   const double m = p.w;
@@ -177,27 +258,32 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
   int kit = 0, nenc = 0, ngrp = 0, maxg = 0;
   unsigned fl = 0u;
   // a system stopped by an earlier failure takes no more steps
-  const bool stopped = (a.ss[s].flags & (F_KEPLER | F_BS)) != 0u;
+  const bool stopped = !has || (a.ss[s].flags & (F_KEPLER | F_BS)) != 0u;
+  bool live = !stopped;
   int done = 0;
-  for (int step = 0; step < a.nsteps && !stopped; ++step) {
-    maxg = 0;
+  for (int step = 0; step < a.nsteps; ++step) {
+    if (__ballot(live) == 0ull) break;
+    const bool live0 = live;
+    const bool actv = act && live0;
     // the step-start state is restored if the step fails
     const double sx = x, sy = y, sz0 = z, svx = vx, svy = vy, svz = vz;
     const unsigned long long scand = cand;
     const double rc =
-        act && !a.enc_free ? rcrit(x, y, z, vx, vy, vz, m, Gm0, m0, a.n1, a.n2, a.absdt) : 0.0;
+        actv && !a.enc_free ? rcrit(x, y, z, vx, vy, vz, m, Gm0, m0, a.n1, a.n2, a.absdt) : 0.0;
     double ax, ay, az;
     unsigned long long dummy;
-    sys_kick(n, lane, x, y, z, m, rc, a.G, a.pf2, false, ax, ay, az, dummy);
+    sys_kick<PK>(nloop, n, lane, hb, x, y, z, m, rc, a.G, a.pf2, false, ax, ay, az, dummy, kp,
+                 krc);
     vx += a.h * ax;
     vy += a.h * ay;
     vz += a.h * az;
-    const double P1x = wave_sum(m * vx), P1y = wave_sum(m * vy), P1z = wave_sum(m * vz);
+    const double P1x = sys_sum<PK>(m * vx), P1y = sys_sum<PK>(m * vy),
+                 P1z = sys_sum<PK>(m * vz);
     x += a.h * P1x / m0;
     y += a.h * P1y / m0;
     z += a.h * P1z / m0;
     double pre[6] = {x, y, z, vx, vy, vz};
-    if (act) {
+    if (actv) {
       const int it = kepler_drift(Gm0, a.dt, x, y, z, vx, vy, vz, a.max_iter);
       if (it < 0) fl |= F_KEPLER;
       kit = max(kit, abs(it));
@@ -205,7 +291,7 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
     // Hermite test of the candidate pairs i < j (Eqs. 10-12)
     enc = 0ull;
     const unsigned long long above = lane < 63 ? ~((2ull << lane) - 1ull) : 0ull;
-    const unsigned long long mine = act && !a.enc_free ? (cand & above) : 0ull;
+    const unsigned long long mine = actv && !a.enc_free ? (cand & above) : 0ull;
     unsigned long long pend = mine;
     for (int o2 = 32; o2 > 0; o2 >>= 1) pend |= __shfl_xor(pend, o2, 64);  // union over lanes
     while (pend) {
@@ -226,12 +312,11 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
         if (d2 < rcij * rcij) enc |= 1ull << j;
       }
     }
-    int ne = __popcll(enc);
-    for (int o2 = 32; o2 > 0; o2 >>= 1) ne += __shfl_xor(ne, o2, 64);
-    nenc = ne;
-    enc_total += (unsigned long long)ne;
-    ngrp = 0;
-    if (ne > 0) {
+    const int ne = sys_sum_i<PK>(__popcll(enc));
+    const int ne_w =
+        PK == 1 ? ne : __builtin_amdgcn_readlane(ne, 0) + __builtin_amdgcn_readlane(ne, 32);
+    int sgrp = 0, smaxg = 0;
+    if (ne_w > 0) {
       // symmetric adjacency, then minimum-label components (App. A)
       unsigned long long adj = enc;
       unsigned long long rows = __ballot(enc != 0ull);
@@ -241,38 +326,56 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
         const unsigned long long ei = readlane_u64(enc, i2);
         if ((ei >> lane) & 1ull) adj |= 1ull << i2;
       }
+      const unsigned long long U = __ballot(adj != 0ull);  // lanes in some pair
       int lab = lane;
       bool changed = true;
       while (changed) {
         int nl = lab;
-        for (int j = 0; j < n; ++j) {
-          const int lj = __builtin_amdgcn_readlane(lab, j);
-          if (((adj >> j) & 1ull) && lj < nl) nl = lj;
+        if (PK == 1) {
+          for (int j = 0; j < n; ++j) {
+            const int lj = __builtin_amdgcn_readlane(lab, j);
+            if (((adj >> j) & 1ull) && lj < nl) nl = lj;
+          }
+        } else {
+          for (unsigned long long u = U; u; u &= u - 1ull) {
+            const int j = __ffsll((long long)u) - 1;
+            const int lj = __builtin_amdgcn_readlane(lab, j);
+            if (((adj >> j) & 1ull) && lj < nl) nl = lj;
+          }
         }
         changed = __ballot(nl != lab) != 0ull;
         lab = nl;
       }
-      const bool ing = act && adj != 0ull;
+      const bool ing = actv && adj != 0ull;
       unsigned long long roots = __ballot(ing && lab == lane);
       while (roots) {
         const int r = __ffsll((long long)roots) - 1;
         roots &= roots - 1ull;
         const unsigned long long M = __ballot(ing && lab == r);
         const int sz = __popcll(M);
-        ++ngrp;
-        maxg = max(maxg, sz);
+        // the group belongs to the system of lane r
+        const bool own = PK == 1 || ((lane ^ r) & 32) == 0;
+        const double Gm0g = PK == 1 ? Gm0 : readlane_d(Gm0, r);
+        long long gsub = 0;
         int st;
         if (sz <= 2)
-          st = group_par<2>(a, sz, M, pre, m, rc, Gm0, mm, mrc, &nsub);
+          st = group_par<2>(a, sz, M, pre, m, rc, Gm0g, mm, mrc, &gsub);
         else if (sz <= 4)
-          st = group_par<4>(a, sz, M, pre, m, rc, Gm0, mm, mrc, &nsub);
+          st = group_par<4>(a, sz, M, pre, m, rc, Gm0g, mm, mrc, &gsub);
         else if (sz <= kBsPar)
-          st = group_par<8>(a, sz, M, pre, m, rc, Gm0, mm, mrc, &nsub);
-        else
-          st = group_seq(a, sz, M, pre, m, rc, Gm0,
-                         reinterpret_cast<double(*)[6][64]>(a.rbuf + (size_t)a.rslot[s] * kBsRDoubles),
-                         &nsub);
-        if (st != 0) fl |= F_BS;
+          st = group_par<8>(a, sz, M, pre, m, rc, Gm0g, mm, mrc, &gsub);
+        else {
+          const int sg = PK == 1 ? s : __builtin_amdgcn_readlane(s, r);
+          st = group_seq(a, sz, M, pre, m, rc, Gm0g,
+                         reinterpret_cast<double(*)[6][64]>(a.rbuf + (size_t)a.rslot[sg] * kBsRDoubles),
+                         &gsub);
+        }
+        if (own) {
+          ++sgrp;
+          smaxg = max(smaxg, sz);
+          nsub += gsub;
+          if (st != 0) fl |= F_BS;
+        }
       }
       if (ing) {
         x = pre[0];
@@ -283,17 +386,21 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
         vz = pre[5];
       }
     }
-    const double P2x = wave_sum(m * vx), P2y = wave_sum(m * vy), P2z = wave_sum(m * vz);
+    const double P2x = sys_sum<PK>(m * vx), P2y = sys_sum<PK>(m * vy),
+                 P2z = sys_sum<PK>(m * vz);
     x += a.h * P2x / m0;
     y += a.h * P2y / m0;
     z += a.h * P2z / m0;
-    sys_kick(n, lane, x, y, z, m, rc, a.G, a.pf2, !a.enc_free, ax, ay, az, cand);
+    sys_kick<PK>(nloop, n, lane, hb, x, y, z, m, rc, a.G, a.pf2, !a.enc_free, ax, ay, az, cand,
+                 kp, krc);
     vx += a.h * ax;
     vy += a.h * ay;
     vz += a.h * az;
-    if (__ballot(fl != 0u) != 0ull) {
-      // the system stops here (the paper's multi-simulation mode stops
-      // systems individually), keeping its last good state
+    // a failing system stops here (the paper's multi-simulation mode stops
+    // systems individually), keeping its last good state; a system stopped
+    // earlier keeps its state through the steps its partner half still takes
+    const bool fail = (__ballot(fl != 0u) & sys_lanes<PK>(lane)) != 0ull;
+    if (!live0 || fail) {
       x = sx;
       y = sy;
       z = sz0;
@@ -301,20 +408,28 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
       vy = svy;
       vz = svz;
       cand = scand;
-      break;
     }
-    ++done;
+    if (live0) {
+      enc_last = enc;
+      enc_total += (unsigned long long)ne;
+      nenc = ne;
+      ngrp = sgrp;
+      maxg = smaxg;
+      if (fail)
+        live = false;
+      else
+        ++done;
+    }
   }
   if (act && !stopped) {
-    a.xm[o + lane] = make_double4(x, y, z, m);
-    a.vv[o + lane] = make_double4(vx, vy, vz, 0.0);
-    a.cand[o + lane] = cand;
-    if (a.nsteps > 0) a.encm[o + lane] = enc;
+    a.xm[o + hl] = make_double4(x, y, z, m);
+    a.vv[o + hl] = make_double4(vx, vy, vz, 0.0);
+    a.cand[o + hl] = cand >> hb;
+    if (a.nsteps > 0) a.encm[o + hl] = enc_last >> hb;
   }
-  unsigned fall = fl;
-  for (int o2 = 32; o2 > 0; o2 >>= 1) fall |= __shfl_xor(fall, o2, 64);
-  const int kitw = wave_max_i(kit);
-  if (lane == 0 && a.nsteps > 0 && !stopped) {
+  const unsigned fall = sys_or<PK>(fl);
+  const int kitw = sys_max_i<PK>(kit);
+  if (hl == 0 && a.nsteps > 0 && !stopped) {
     BatchSysStat& t = a.ss[s];
     t.steps += done;
     t.sub += (unsigned long long)nsub;
@@ -412,7 +527,8 @@ __global__ __launch_bounds__(64) void k_batch_prime(BatchArgs a) {
                         : 0.0;
   double ax, ay, az;
   unsigned long long cand;
-  sys_kick(n, lane, p.x, p.y, p.z, p.w, rc, a.G, a.pf2, !a.enc_free, ax, ay, az, cand);
+  sys_kick<1>(n, n, lane, 0, p.x, p.y, p.z, p.w, rc, a.G, a.pf2, !a.enc_free, ax, ay, az, cand,
+              nullptr, nullptr);
   if (act) {
     a.cand[o + lane] = cand;
     a.encm[o + lane] = 0ull;
@@ -497,8 +613,15 @@ const char* batch_variant_name(int v) {
   static const char* names[kBatchVariants] = {
       "1 wave/SIMD, natural order",  "1 wave/SIMD, largest first",
       "2 waves/SIMD, natural order", "2 waves/SIMD, largest first",
-      "4 waves/SIMD, natural order", "4 waves/SIMD, largest first"};
+      "4 waves/SIMD, natural order", "4 waves/SIMD, largest first",
+      "2 systems/wave, 1 wave/SIMD, largest first",
+      "2 systems/wave, 2 waves/SIMD, largest first",
+      "2 systems/wave, 4 waves/SIMD, largest first"};
   return v >= 0 && v < kBatchVariants ? names[v] : "?";
+}
+
+bool batch_variant_ok(const BatchWs& b, int v) {
+  return v >= 0 && v < kBatchVariants && (v < kBatchPackedVariant0 || b.maxn <= 32);
 }
 
 size_t batch_carve(BatchWs& b, int nsys, int64_t nb, int nbig, void* base) {
@@ -562,13 +685,26 @@ hipError_t batch_energy(const BatchWs& b, const StepConsts& c, double* E, double
 
 hipError_t batch_run(const BatchWs& b, const StepConsts& c, int variant, int nsteps, bool scratch,
                      hipStream_t s) {
-  BatchArgs a = batch_args(b, c, scratch, variant & 1);
+  if (!batch_variant_ok(b, variant)) return hipErrorInvalidValue;
+  const bool packed = variant >= kBatchPackedVariant0;
+  BatchArgs a = batch_args(b, c, scratch, packed ? 1 : (variant & 1));
   a.nsteps = nsteps;
-  const dim3 g(b.nsys), blk(64);
-  switch (variant >> 1) {
-    case 0: hipLaunchKernelGGL(k_batch<1>, g, blk, 0, s, a); break;
-    case 1: hipLaunchKernelGGL(k_batch<2>, g, blk, 0, s, a); break;
-    default: hipLaunchKernelGGL(k_batch<4>, g, blk, 0, s, a); break;
+  const dim3 blk(64);
+  if (!packed) {
+    const dim3 g(b.nsys);
+    switch (variant >> 1) {
+      case 0: hipLaunchKernelGGL((k_batch<1, 1>), g, blk, 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_batch<2, 1>), g, blk, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_batch<4, 1>), g, blk, 0, s, a); break;
+    }
+  } else {
+    // two systems per wave: consecutive systems of the largest-first order
+    const dim3 g((b.nsys + 1) / 2);
+    switch (variant - kBatchPackedVariant0) {
+      case 0: hipLaunchKernelGGL((k_batch<1, 2>), g, blk, 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_batch<2, 2>), g, blk, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_batch<4, 2>), g, blk, 0, s, a); break;
+    }
   }
   return hipGetLastError();
 }

@@ -174,8 +174,10 @@ static int batch_tune(genga_ctx* ctx, int steps) {
     (void)hipEventDestroy(e0);
     return GENGA_EHIP;
   }
-  int rc = GENGA_OK, best = 0;
+  int rc = GENGA_OK, best = -1;
   for (int v = 0; v < kBatchVariants && rc == GENGA_OK; ++v) {
+    ctx->tune_us[v] = -1.0;  // variants that cannot run these systems
+    if (!batch_variant_ok(ctx->b, v)) continue;
     float ms = 0.0f;
     if (batch_copy_to_scratch(ctx->b, ctx->stream) != hipSuccess ||
         hipEventRecord(e0, ctx->stream) != hipSuccess ||
@@ -184,7 +186,7 @@ static int batch_tune(genga_ctx* ctx, int steps) {
         hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
       rc = GENGA_EHIP;
     ctx->tune_us[v] = ms * 1e3;
-    if (ctx->tune_us[v] < ctx->tune_us[best]) best = v;
+    if (best < 0 || ctx->tune_us[v] < ctx->tune_us[best]) best = v;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -263,6 +265,7 @@ static int batch_init(genga_ctx** out, const genga_params* p, int n_sys,
     maxn = std::max(maxn, off[s + 1] - off[s]);
   }
   ctx->sb = adj_segment_lanes(maxn);
+  ctx->b.maxn = maxn;
   (void)nbig;
   int rc = GENGA_OK;
   if (hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) rc = GENGA_EHIP;
@@ -710,6 +713,18 @@ int genga_tune(genga_ctx* ctx, int nsteps, double* h_us, int cap, int* h_n, int*
 }
 
 const char* genga_tune_variant(int v) { return batch_variant_name(v); }
+
+int genga_batch_set_variant(genga_ctx* ctx, int v) {
+  if (!ctx || ctx->mode != GENGA_BATCH || !batch_variant_ok(ctx->b, v)) return GENGA_EINVAL;
+  if (v != ctx->variant) {
+    ctx->variant = v;
+    if (ctx->g_batch) {
+      (void)hipGraphExecDestroy(ctx->g_batch);
+      ctx->g_batch = nullptr;
+    }
+  }
+  return GENGA_OK;
+}
 
 int genga_batch_status(genga_ctx* ctx, int32_t* h_status, int64_t* h_steps, int cap) {
   if (!ctx || ctx->mode != GENGA_BATCH || cap < 0 || (cap > 0 && (!h_status || !h_steps)))

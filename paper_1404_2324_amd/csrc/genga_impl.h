@@ -216,13 +216,17 @@ struct BatchWs {
   int* rslot;                      // [nsys] tableau slice of systems over 8 bodies
   double* rbuf;                    // [nbig] tableaux of the sequential BS
   int nbig;
+  int maxn;                        // largest system
   unsigned* flags2;
   int* flag_in;
   DevStat* st;
 };
 
 constexpr int kBatchMaxBodies = 64;  // one lane per body
-constexpr int kBatchVariants = 6;    // register budget {1, 2, 4 waves/SIMD} x order
+// register budget {1, 2, 4 waves/SIMD} x order (one system per wave), then
+// register budget x two systems per wave (systems of up to 32 bodies)
+constexpr int kBatchVariants = 9;
+constexpr int kBatchPackedVariant0 = 6;
 
 // nbig: systems with more than 8 bodies (each gets a sequential-BS tableau)
 size_t batch_carve(BatchWs& b, int nsys, int64_t nb, int nbig, void* base);
@@ -238,6 +242,8 @@ hipError_t batch_run(const BatchWs& b, const StepConsts& c, int variant, int nst
                      bool scratch, hipStream_t s);
 hipError_t batch_copy_to_scratch(const BatchWs& b, hipStream_t s);
 const char* batch_variant_name(int v);
+// whether variant v can run these systems (two per wave needs sizes <= 32)
+bool batch_variant_ok(const BatchWs& b, int v);
 
 // ---- adjoint of the encounter-free map (adj.hip) ----------------------------
 // Systems are packed sb lanes each (sb: power of two >= the largest system).

@@ -74,6 +74,7 @@ SIGNATURES = {
     "genga_set_radii": (_i32, [_vp, _vp]),
     "genga_tune": (_i32, [_vp, _i32, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "genga_tune_variant": (ctypes.c_char_p, [_i32]),
+    "genga_batch_set_variant": (_i32, [_vp, _i32]),
     "genga_batch_status": (_i32, [_vp, _vp, _vp, _i32]),
     "genga_adj_buffer_bytes": (_sz, [_vp, _i64, _i32]),
     "genga_adj_forward": (_i32, [_vp, _i64, _i32, _vp, _sz]),
@@ -414,7 +415,11 @@ class BatchedSimulation(Simulation):
         _check(lib().genga_tune(self._ctx, int(nsteps), us, 16, ctypes.byref(n), ctypes.byref(ch)),
                "genga_tune")
         names = {v: lib().genga_tune_variant(v).decode() for v in range(n.value)}
-        return {names[v]: us[v] for v in range(n.value)}, names[ch.value]
+        return {names[v]: us[v] for v in range(n.value) if us[v] >= 0.0}, names[ch.value]
+
+    def set_variant(self, v: int):
+        """Use kernel variant v (numbered as by the tuner) for later steps."""
+        _check(lib().genga_batch_set_variant(self._ctx, int(v)), "genga_batch_set_variant")
 
     # ---- adjoint of the encounter-free map (contexts with encounter_free=1) --
     def adj_forward(self, nsteps: int, ckpt_every: int = 32):

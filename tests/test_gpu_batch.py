@@ -126,6 +126,12 @@ def test_batch_edge_sizes_and_large_groups():
     m0s = np.ones(len(sizes))
     gp = G.default_params()
     sim = G.BatchedSimulation(off, m0s, m, x, u, gp)
+    times, _ = sim.tune(1)
+    assert len(times) == 6  # two systems per wave needs sizes <= 32
+    for v in (6, 9, -1):
+        with pytest.raises(G.GengaError) as ei:
+            sim.set_variant(v)
+        assert ei.value.code == G.EINVAL
     sim.step(1)
     sim.check()
     st = sim.stats()
@@ -192,10 +198,12 @@ def test_batch_set_state_round_trip_and_errors():
         G.BatchedSimulation(off, -m0s, m, x, u, gp)
 
 
-def test_batch_failing_system_stops_alone():
+@pytest.mark.parametrize("variant", [None, 7])
+def test_batch_failing_system_stops_alone(variant):
     """A head-on collision (no radii) exhausts the BS depth in its system: that
     system stops with the state before the failing step, the warning is
-    returned, and every other system completes its steps unchanged."""
+    returned, and every other system completes its steps unchanged; also with
+    two systems per wave, where the stopped system shares its wave."""
     off, m0s, m, x, u = W.batched(nsys=8, seed_index=12)
     # system 3 becomes two bodies falling straight onto each other
     a, b = off[3], off[4]
@@ -213,6 +221,8 @@ def test_batch_failing_system_stops_alone():
     u[a + 1] = [0.0, vc - 0.05, 0.0]
     gp = G.default_params()
     sim = G.BatchedSimulation(off, m0s, m, x, u, gp)
+    if variant is not None:
+        sim.set_variant(variant)
     sim.step(10)
     assert sim.check() == G.WSTOPPED
     st, ns = sim.status()
@@ -230,3 +240,37 @@ def test_batch_failing_system_stops_alone():
     sim.step(3)
     st2, ns2 = sim.status()
     assert ns2[3] == ns[3] and np.all(ns2[others] == 13)
+
+
+def test_batch_variants_bitwise_equal():
+    """Every kernel variant (register budget, hand-out order, one or two
+    systems per wave) does the same arithmetic on each system: states,
+    candidates, encounters and counters agree bit for bit.  95 systems leave
+    the last two-per-wave wave half empty; the oracle checks the packed run on
+    every fifth system."""
+    off, m0s, m, x, u = W.batched(nsys=95, seed_index=13)
+    gp = G.default_params()
+    base = None
+    for v in range(9):
+        _say("variant", v, G.lib().genga_tune_variant(v).decode())
+        sim = G.BatchedSimulation(off, m0s, m, x, u, gp)
+        sim.set_variant(v)
+        sim.step(7)
+        sim.step(5)
+        sim.check()
+        xs, vs = sim.state("dem")
+        got = (xs.cpu(), vs.cpu(), sim.candidates(), sim.encounters()[0], sim.stats(),
+               sim.status())
+        if base is None:
+            base = got
+            assert got[4]["enc_total"] > 0
+            continue
+        assert torch.equal(got[0], base[0]) and torch.equal(got[1], base[1]), v
+        np.testing.assert_array_equal(got[2], base[2])
+        np.testing.assert_array_equal(got[3], base[3])
+        assert got[4] == base[4], (v, got[4], base[4])
+        np.testing.assert_array_equal(got[5][0], base[5][0])
+        np.testing.assert_array_equal(got[5][1], base[5][1])
+        if v == 7:
+            ref = _oracle_systems(gp, off, m0s, m, x, u, 12, range(0, 95, 5))
+            _check_systems(sim, ref, off)

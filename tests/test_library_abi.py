@@ -111,5 +111,7 @@ def test_batch_workspace_sizing_and_tuner_names(G):
     assert L.genga_tune(None, 4, None, 0, None, None) == G.EINVAL
     assert L.genga_batch_status(None, None, None, 0) == G.EINVAL
     assert b"stopped" in L.genga_strerror(G.WSTOPPED)
-    names = {L.genga_tune_variant(v).decode() for v in range(6)}
-    assert len(names) == 6 and L.genga_tune_variant(6).decode() == "?"
+    assert L.genga_batch_set_variant(None, 0) == G.EINVAL
+    names = {L.genga_tune_variant(v).decode() for v in range(9)}
+    assert len(names) == 9 and L.genga_tune_variant(9).decode() == "?"
+    assert L.genga_tune_variant(-1).decode() == "?"
