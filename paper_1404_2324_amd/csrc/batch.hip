@@ -86,6 +86,84 @@ __device__ __forceinline__ unsigned long long sys_lanes(int l) {
 __device__ __forceinline__ int kick_slot(int j) { return j + (j >> 5); }
 constexpr int kKickSlots = 66;
 
+// Partner jj of the lane's system: wave-uniform lane reads (PK = 1) or the
+// LDS tables (PK = 2).
+template <int PK>
+__device__ __forceinline__ void kick_partner(int jj, int hb, double x, double y, double z,
+                                             double m, double rc, const double4* kp,
+                                             const double* krc, double& xj, double& yj,
+                                             double& zj, double& mj, double& rcj) {
+  if (PK == 1) {
+    xj = readlane_d(x, jj);
+    yj = readlane_d(y, jj);
+    zj = readlane_d(z, jj);
+    mj = readlane_d(m, jj);
+    rcj = readlane_d(rc, jj);
+  } else {
+    const double4 pj = kp[kick_slot(hb + jj)];
+    xj = pj.x;
+    yj = pj.y;
+    zj = pj.z;
+    mj = pj.w;
+    rcj = krc[kick_slot(hb + jj)];
+  }
+}
+
+// U consecutive partners jj0 .. jj0 + U - 1 (all below nloop), accumulated
+// in index order.  The U pair terms are independent until the accumulation,
+// so their latency chains overlap.  The common case K = 1 (dK = 0) is taken
+// for every pair first, and the rare pairs inside r_crit,ij are redone with
+// the changeover (Eqs. 4-5); mj (K ir^3 - dK ir^2) with K = 1, dK = 0 is
+// mj ir^3 exactly, so both paths round as the single formula does.  The
+// fused operations are spelled out, so that the roundings do not depend on
+// how the partner data arrive (lane reads or LDS).
+template <int PK, int U>
+__device__ __forceinline__ void kick_chunk(int jj0, int nh, int lane, int hb, double x, double y,
+                                           double z, double m, double rc, double pf2,
+                                           bool want_cand, const double4* kp, const double* krc,
+                                           double& ax, double& ay, double& az,
+                                           unsigned long long& cand) {
+  double dx[U], dy[U], dz[U], r2[U], ir[U], rcij[U], mj[U], s[U];
+  bool ok[U];
+  bool near = false;
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    const int jj = jj0 + k;
+    double xj, yj, zj, rcj;
+    kick_partner<PK>(jj, hb, x, y, z, m, rc, kp, krc, xj, yj, zj, mj[k], rcj);
+    ok[k] = hb + jj != lane && (PK == 1 || jj < nh);
+    dx[k] = xj - x;
+    dy[k] = yj - y;
+    dz[k] = zj - z;
+    r2[k] = fma(dz[k], dz[k], fma(dy[k], dy[k], dx[k] * dx[k]));
+    ir[k] = rsqrt_nr(r2[k]);
+    rcij[k] = fmax(rc, rcj);
+    s[k] = mj[k] * ((ir[k] * ir[k]) * ir[k]);
+    near = near || (ok[k] && r2[k] * ir[k] < rcij[k]);
+  }
+  if (near) {
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const double r = r2[k] * ir[k];
+      if (ok[k] && r < rcij[k]) {
+        double K, dK;
+        changeover(r, rcij[k], K, dK);
+        const double ir2 = ir[k] * ir[k];
+        s[k] = mj[k] * fma(K * ir2, ir[k], -(dK * ir2));
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    if (ok[k]) {
+      ax = fma(s[k], dx[k], ax);
+      ay = fma(s[k], dy[k], ay);
+      az = fma(s[k], dz[k], az);
+      if (want_cand && r2[k] < pf2 * rcij[k] * rcij[k]) cand |= 1ull << (hb + jj0 + k);
+    }
+  }
+}
+
 // Pair acceleration of H_B (Eq. 2 gradient) on the lane's body from every
 // other body of the system; with want_cand, also the partners inside the
 // prechecker radius pf r_crit,ij (Sec. 2.2), as bits of lane indices.
@@ -109,41 +187,13 @@ __device__ __forceinline__ void sys_kick(int nloop, int nh, int lane, int hb, do
     krc[kick_slot(lane)] = rc;
     __syncthreads();
   }
-  for (int jj = 0; jj < nloop; ++jj) {
-    const int j = hb + jj;
-    double xj, yj, zj, mj, rcj;
-    if (PK == 1) {
-      xj = readlane_d(x, jj);
-      yj = readlane_d(y, jj);
-      zj = readlane_d(z, jj);
-      mj = readlane_d(m, jj);
-      rcj = readlane_d(rc, jj);
-    } else {
-      const double4 pj = kp[kick_slot(j)];
-      xj = pj.x;
-      yj = pj.y;
-      zj = pj.z;
-      mj = pj.w;
-      rcj = krc[kick_slot(j)];
-    }
-    if (j != lane && (PK == 1 || jj < nh)) {
-      // the fused operations are spelled out, so that the roundings do not
-      // depend on how the partner data arrive (lane reads or LDS)
-      const double dx = xj - x, dy = yj - y, dz = zj - z;
-      const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-      const double ir = rsqrt_nr(r2);
-      const double ir2 = ir * ir;
-      const double rcij = fmax(rc, rcj);
-      const double r = r2 * ir;
-      double K = 1.0, dK = 0.0;
-      if (r < rcij) changeover(r, rcij, K, dK);
-      const double s = mj * fma(K * ir2, ir, -(dK * ir2));
-      ax = fma(s, dx, ax);
-      ay = fma(s, dy, ay);
-      az = fma(s, dz, az);
-      if (want_cand && r2 < pf2 * rcij * rcij) cand |= 1ull << j;
-    }
-  }
+  int jj = 0;
+  for (; jj + 4 <= nloop; jj += 4)
+    kick_chunk<PK, 4>(jj, nh, lane, hb, x, y, z, m, rc, pf2, want_cand, kp, krc, ax, ay, az,
+                      cand);
+  for (; jj < nloop; ++jj)
+    kick_chunk<PK, 1>(jj, nh, lane, hb, x, y, z, m, rc, pf2, want_cand, kp, krc, ax, ay, az,
+                      cand);
   ax *= G;
   ay *= G;
   az *= G;
