@@ -50,9 +50,42 @@ __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v,
 
 // Reductions over the lanes of one system: the whole wave (PK = 1) or the
 // lane's half (PK = 2, lanes 0-31 and 32-63 hold two systems).
+// The halves of a double exchanged between rows 2r and 2r + 1 (W = 16) or
+// between the two halves of the wave (W = 32); returns the lane's value plus
+// its partner's, the pair ordered by row so that both partners hold the same
+// bits.
+template <int W>
+__device__ __forceinline__ double swap_sum(double v) {
+  const int2 p = *reinterpret_cast<int2*>(&v);
+  int2 lo, hi;
+  if (W == 16) {
+    const auto a = __builtin_amdgcn_permlane16_swap(p.x, p.x, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(p.y, p.y, false, false);
+    lo = make_int2(a[0], b[0]);
+    hi = make_int2(a[1], b[1]);
+  } else {
+    const auto a = __builtin_amdgcn_permlane32_swap(p.x, p.x, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(p.y, p.y, false, false);
+    lo = make_int2(a[0], b[0]);
+    hi = make_int2(a[1], b[1]);
+  }
+  return *reinterpret_cast<double*>(&lo) + *reinterpret_cast<double*>(&hi);
+}
+
+// Sum over the lanes of one system, on every lane: the butterfly over lane
+// distances 1, 2 (DPP quad permutes), 4, 8 (DPP half-row and row mirrors,
+// which pair the same partial sums as lane ^ 4 and lane ^ 8 once those are
+// uniform over their quad or half-row), 16 (row swap) and, one system per
+// wave, 32.  Each step adds the same two partial sums as the xor butterfly,
+// so every layout gives the same bits.  Called with the whole wave active.
 template <int PK>
 __device__ __forceinline__ double sys_sum(double v) {
-  for (int o = 32 / PK; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v += dpp_d<kDppQuadSwap1>(v);
+  v += dpp_d<kDppQuadSwap2>(v);
+  v += dpp_d<kDppRowHalfMirror>(v);
+  v += dpp_d<kDppRowMirror>(v);
+  v = swap_sum<16>(v);
+  if (PK == 1) v = swap_sum<32>(v);
   return v;
 }
 
@@ -126,6 +159,8 @@ __device__ __forceinline__ void kick_chunk(int jj0, int nh, int lane, int hb, do
   double dx[U], dy[U], dz[U], r2[U], ir[U], rcij[U], mj[U], s[U];
   bool ok[U];
   bool near = false;
+  // stage by stage over the U pairs, so that the independent chains
+  // interleave (the reciprocal square root is rsqrt_nr written out)
 #pragma unroll
   for (int k = 0; k < U; ++k) {
     const int jj = jj0 + k;
@@ -135,9 +170,25 @@ __device__ __forceinline__ void kick_chunk(int jj0, int nh, int lane, int hb, do
     dx[k] = xj - x;
     dy[k] = yj - y;
     dz[k] = zj - z;
-    r2[k] = fma(dz[k], dz[k], fma(dy[k], dy[k], dx[k] * dx[k]));
-    ir[k] = rsqrt_nr(r2[k]);
     rcij[k] = fmax(rc, rcj);
+  }
+  double hx[U], e[U];
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    r2[k] = fma(dz[k], dz[k], fma(dy[k], dy[k], dx[k] * dx[k]));
+    hx[k] = 0.5 * r2[k];
+    ir[k] = __builtin_amdgcn_rsq(r2[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < U; ++k) e[k] = fma(-hx[k] * ir[k], ir[k], 0.5);
+#pragma unroll
+  for (int k = 0; k < U; ++k) ir[k] = fma(ir[k], e[k], ir[k]);
+#pragma unroll
+  for (int k = 0; k < U; ++k) e[k] = fma(-hx[k] * ir[k], ir[k], 0.5);
+#pragma unroll
+  for (int k = 0; k < U; ++k) ir[k] = fma(ir[k], e[k], ir[k]);
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
     s[k] = mj[k] * ((ir[k] * ir[k]) * ir[k]);
     near = near || (ok[k] && r2[k] * ir[k] < rcij[k]);
   }
@@ -188,9 +239,14 @@ __device__ __forceinline__ void sys_kick(int nloop, int nh, int lane, int hb, do
     __syncthreads();
   }
   int jj = 0;
-  for (; jj + 4 <= nloop; jj += 4)
+  for (; jj + 8 <= nloop; jj += 8)
+    kick_chunk<PK, 8>(jj, nh, lane, hb, x, y, z, m, rc, pf2, want_cand, kp, krc, ax, ay, az,
+                      cand);
+  if (jj + 4 <= nloop) {
     kick_chunk<PK, 4>(jj, nh, lane, hb, x, y, z, m, rc, pf2, want_cand, kp, krc, ax, ay, az,
                       cand);
+    jj += 4;
+  }
   for (; jj < nloop; ++jj)
     kick_chunk<PK, 1>(jj, nh, lane, hb, x, y, z, m, rc, pf2, want_cand, kp, krc, ax, ay, az,
                       cand);

@@ -219,6 +219,9 @@ __device__ __forceinline__ double dpp_d(double v) {
   return *reinterpret_cast<double*>(&q);
 }
 constexpr int kDppQuadSwap1 = 0xB1;     // quad_perm [1,0,3,2]: lane ^ 1
+constexpr int kDppQuadSwap2 = 0x4E;     // quad_perm [2,3,0,1]: lane ^ 2
+constexpr int kDppRowHalfMirror = 0x141;  // lane 7 - i inside each 8 lanes
+constexpr int kDppRowMirror = 0x140;      // lane 15 - i inside each row
 constexpr int kDppRowShr2 = 0x112;      // row_shr:2: lane - 2 inside the row
 constexpr int kDppRowShr1 = 0x111;      // row_shr:1: lane - 1 inside the row
 
