@@ -1,17 +1,19 @@
 // Batched independent systems (Sec. 3.4): each system has its own central
 // mass and 1..64 bodies; systems never interact.  One wave integrates one
-// system, one lane per body, and runs every requested step inside a single
-// launch with the state held in registers (the method's step of Sec. 2.2,
-// as in main mode, with each system's own central mass):
+// system (or two systems of up to 32 bodies, one per half-wave), one lane
+// per body, and runs every requested step inside a single launch with the
+// state held in registers (the method's step of Sec. 2.2, as in main mode,
+// with each system's own central mass):
 //   radii (Eq. 6), opening kick (Eq. 2 gradient, every pair), Sun kick,
 //   Kepler drift (Eq. 9), Hermite test of the prechecker's candidates
 //   (Eqs. 10-12), groups (connected components, App. A), BS of each group
 //   from the pre-drift state (Sec. 3.2.6), Sun kick, closing kick and the
 //   next candidates.
-// Partner data moves by lane reads (readlane / bpermute), so the only memory
-// traffic of a run is loading and storing the state once.  The tuner picks,
-// by timing the real systems, the register budget per wave (occupancy) and
-// the order in which systems are handed to waves.
+// Partner data moves by lane reads (readlane / bpermute / DPP) and through
+// LDS, so the only memory traffic of a run is loading and storing the state
+// once.  The tuner picks, by timing the real systems, the register budget
+// per wave (occupancy), the order in which systems are handed to waves and
+// whether small systems share a wave.
 #include <algorithm>
 #include <climits>
 #include <vector>
