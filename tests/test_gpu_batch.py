@@ -100,30 +100,35 @@ def test_batch_energy_and_conversions():
         np.testing.assert_allclose(L[s], Lo, rtol=1e-12, atol=1e-18)
 
 
-def test_batch_edge_sizes_and_large_groups():
-    """Systems of 1, 2, 8, 9, 33 and 64 bodies, two of them packed so tightly
-    that groups of more than 8 members form (the lane-per-member BS)."""
-    rng = np.random.default_rng(11)
-    sizes = [1, 2, 8, 9, 33, 64, 12]
+def _systems(sizes, tight, seed):
+    """Systems of the given sizes; those listed in `tight` packed so closely
+    that groups of more than 8 members form."""
+    rng = np.random.default_rng(seed)
     xs, us, ms = [], [], []
     for k, n in enumerate(sizes):
-        tight = k in (3, 6)
-        a = (1.0 + 0.004 * rng.standard_normal(n)) if tight else rng.uniform(0.5, 3.0, n)
+        t = k in tight
+        a = (1.0 + 0.004 * rng.standard_normal(n)) if t else rng.uniform(0.5, 3.0, n)
         e = np.full(n, 0.01)
-        inc = np.full(n, 0.001) if tight else rng.uniform(0, 0.02, n)
+        inc = np.full(n, 0.001) if t else rng.uniform(0, 0.02, n)
         node, peri, M = (rng.uniform(0, 2 * np.pi, n) for _ in range(3))
-        if tight:
+        if t:
             M = 0.02 * rng.standard_normal(n)
             node = np.zeros(n)
             peri = np.zeros(n)
-        mm = np.full(n, 1e-7 if tight else 3e-6)
+        mm = np.full(n, 1e-7 if t else 3e-6)
         xx, uu = W.elements_to_cartesian(1.0 + mm, a, e, inc, node, peri, M)
         xs.append(xx)
         us.append(uu)
         ms.append(mm)
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
-    m, x, u = np.concatenate(ms), np.concatenate(xs), np.concatenate(us)
-    m0s = np.ones(len(sizes))
+    return off, np.ones(len(sizes)), np.concatenate(ms), np.concatenate(xs), np.concatenate(us)
+
+
+def test_batch_edge_sizes_and_large_groups():
+    """Systems of 1, 2, 8, 9, 33 and 64 bodies, two of them packed so tightly
+    that groups of more than 8 members form (the lane-per-member BS)."""
+    sizes = [1, 2, 8, 9, 33, 64, 12]
+    off, m0s, m, x, u = _systems(sizes, (3, 6), 11)
     gp = G.default_params()
     sim = G.BatchedSimulation(off, m0s, m, x, u, gp)
     times, _ = sim.tune(1)
@@ -274,3 +279,28 @@ def test_batch_variants_bitwise_equal():
         if v == 7:
             ref = _oracle_systems(gp, off, m0s, m, x, u, 12, range(0, 95, 5))
             _check_systems(sim, ref, off)
+
+
+def test_batch_packed_large_groups_and_empty_half():
+    """Two systems per wave with groups of more than 8 members in both halves
+    (the lane-per-member BS and its per-system tableau), and a last wave with
+    one system: bit-identical to one system per wave, and the oracle's
+    result."""
+    sizes = [30, 12, 9, 2, 1]
+    off, m0s, m, x, u = _systems(sizes, (1, 2), 17)
+    gp = G.default_params()
+    got = {}
+    for v in (1, 7):
+        sim = G.BatchedSimulation(off, m0s, m, x, u, gp)
+        sim.set_variant(v)
+        sim.step(1)
+        sim.check()
+        xs, vs = sim.state("dem")
+        got[v] = (xs.cpu(), vs.cpu(), sim.stats())
+    _say("packed large groups stats", got[7][2])
+    assert got[7][2]["max_group"] > 8
+    assert torch.equal(got[1][0], got[7][0]) and torch.equal(got[1][1], got[7][1])
+    assert got[1][2] == got[7][2]
+    ref = _oracle_systems(gp, off, m0s, m, x, u, 1, range(len(sizes)))
+    _check_systems(sim, ref, off)
+    assert got[7][2]["bs_substeps"] == sum(r[4]["bs_substeps"] for r in ref.values())
