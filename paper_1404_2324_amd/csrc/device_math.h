@@ -160,9 +160,14 @@ __device__ __forceinline__ void stumpff(double z, double& c0, double& c1,
 // x = f x0 + g v0, v = fdot x0 + gdot v0 about mu = G m0.  The universal Kepler
 // equation F(s) = r0 G1 + eta0 G2 + mu G3 - dt = 0 (G_k = s^k c_k(beta s^2),
 // beta = 2 mu/r0 - v0^2) is solved by the Laguerre-Conway iteration of order
-// 5 from s = dt/r0 until |ds| <= 2^-50 |s| or |F| <= 2^-48 times the sum of
-// the magnitudes of its terms (rounding floor).  Returns the iteration count, or
-// a negative count when max_iter was reached without convergence.
+// 5 until |ds| <= 2^-50 |s| or |F| <= 2^-48 times the sum of the magnitudes
+// of its terms (rounding floor).  The first guess inverts the cubic Taylor
+// form dt = r0 s + eta0 s^2/2 + zeta0 s^3/6 (zeta0 = mu - beta r0) for s,
+// s = t - eta0 t^2/(2 r0) + (eta0^2/2 - r0 zeta0/6) t^3/r0^2 with t = dt/r0,
+// when its corrections are small against t (short steps); otherwise s = t.
+// The Stumpff values of the last residual evaluation are reused for f and g
+// when the iteration stopped there.  Returns the iteration count, or a
+// negative count when max_iter was reached without convergence.
 // s_out (optional) receives the converged universal anomaly s.
 __device__ __forceinline__ int kepler_drift(double mu, double dt, double& x,
                                             double& y, double& z, double& vx,
@@ -172,11 +177,15 @@ __device__ __forceinline__ int kepler_drift(double mu, double dt, double& x,
   const double eta0 = x * vx + y * vy + z * vz;
   const double beta = 2.0 * mu / r0 - (vx * vx + vy * vy + vz * vz);
   const double zeta0 = mu - beta * r0;
-  double s = dt / r0;
+  const double t = dt / r0;
+  const double ir0 = 1.0 / r0;
+  const double k2 = -0.5 * eta0 * ir0 * t;
+  const double k3 = (0.5 * eta0 * eta0 - r0 * zeta0 * (1.0 / 6.0)) * ir0 * ir0 * t * t;
+  double s = (fabs(k2) + fabs(k3) <= 0.125) ? t * (1.0 + k2 + k3) : t;
   int it = 1;
-  bool ok = false;
+  bool ok = false, fresh = false;  // fresh: c0..c3 belong to the current s
+  double c0, c1, c2, c3;
   for (; it <= max_iter; ++it) {
-    double c0, c1, c2, c3;
     stumpff(beta * s * s, c0, c1, c2, c3);
     const double G1 = s * c1, G2 = s * s * c2, G3 = s * s * s * c3;
     const double F = r0 * G1 + eta0 * G2 + mu * G3 - dt;
@@ -184,6 +193,7 @@ __device__ __forceinline__ int kepler_drift(double mu, double dt, double& x,
     const double Fs = fabs(r0 * G1) + fabs(eta0 * G2) + fabs(mu * G3) + fabs(dt);
     if (fabs(F) <= 0x1p-48 * Fs) {
       ok = true;
+      fresh = true;
       break;
     }
     const double Fp = r0 + eta0 * G1 + zeta0 * G2;
@@ -198,8 +208,7 @@ __device__ __forceinline__ int kepler_drift(double mu, double dt, double& x,
     }
   }
   if (s_out) *s_out = s;
-  double c0, c1, c2, c3;
-  stumpff(beta * s * s, c0, c1, c2, c3);
+  if (!fresh) stumpff(beta * s * s, c0, c1, c2, c3);
   const double G1 = s * c1, G2 = s * s * c2, G3 = s * s * s * c3;
   const double r = r0 + eta0 * G1 + zeta0 * G2;
   const double f = 1.0 - mu * G2 / r0;
