@@ -135,12 +135,14 @@ __device__ __forceinline__ void kick_partner(int jj, int hb, double x, double y,
     mj = readlane_d(m, jj);
     rcj = readlane_d(rc, jj);
   } else {
-    const double4 pj = kp[kick_slot(hb + jj)];
+    // kick_slot(hb + jj) = kick_slot(hb) + jj for jj < 32
+    const int t = kick_slot(hb) + jj;
+    const double4 pj = kp[t];
     xj = pj.x;
     yj = pj.y;
     zj = pj.z;
     mj = pj.w;
-    rcj = krc[kick_slot(hb + jj)];
+    rcj = krc[t];
   }
 }
 
