@@ -339,6 +339,7 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
   __shared__ double mm[kBsPar], mrc[kBsPar];
   __shared__ double4 kp[PK == 2 ? kKickSlots : 1];
   __shared__ double krc[PK == 2 ? kKickSlots : 1];
+  __shared__ double hs[13][kKickSlots];  // pre-drift state, drifted state, radius
   const int lane = threadIdx.x;
   const int hb = PK == 1 ? 0 : (lane & 32);  // first lane of the lane's system
   const int hl = lane - hb;                  // the body's index in its system
@@ -402,24 +403,35 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
     enc = 0ull;
     const unsigned long long above = lane < 63 ? ~((2ull << lane) - 1ull) : 0ull;
     const unsigned long long mine = actv && !a.enc_free ? (cand & above) : 0ull;
-    unsigned long long pend = mine;
-    for (int o2 = 32; o2 > 0; o2 >>= 1) pend |= __shfl_xor(pend, o2, 64);  // union over lanes
-    while (pend) {
-      const int j = __ffsll((long long)pend) - 1;
-      pend &= pend - 1ull;
-      const double xj = readlane_d(pre[0], j), yj = readlane_d(pre[1], j),
-                   zj = readlane_d(pre[2], j);
-      const double uj = readlane_d(pre[3], j), wj = readlane_d(pre[4], j),
-                   tj = readlane_d(pre[5], j);
-      const double Xj = readlane_d(x, j), Yj = readlane_d(y, j), Zj = readlane_d(z, j);
-      const double Uj = readlane_d(vx, j), Wj = readlane_d(vy, j), Tj = readlane_d(vz, j);
-      const double rcj = readlane_d(rc, j);
-      if ((mine >> j) & 1ull) {
-        const double d2 = hermite_dmin2(a.dt, xj - pre[0], yj - pre[1], zj - pre[2],
-                                        uj - pre[3], wj - pre[4], tj - pre[5], Xj - x, Yj - y,
-                                        Zj - z, Uj - vx, Wj - vy, Tj - vz);
-        const double rcij = fmax(rc, rcj);
-        if (d2 < rcij * rcij) enc |= 1ull << j;
+    // Each lane walks its own candidates, reading the partner's states from
+    // LDS, so a pass serves one candidate of every lane (not one partner of
+    // the whole wave)
+    if (__ballot(mine != 0ull) != 0ull) {
+      __syncthreads();  // earlier reads of the table are done
+      const int t = kick_slot(lane);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) hs[q][t] = pre[q];
+      hs[6][t] = x;
+      hs[7][t] = y;
+      hs[8][t] = z;
+      hs[9][t] = vx;
+      hs[10][t] = vy;
+      hs[11][t] = vz;
+      hs[12][t] = rc;
+      __syncthreads();
+      unsigned long long mc = mine;
+      while (__ballot(mc != 0ull) != 0ull) {
+        if (mc) {
+          const int j = __ffsll((long long)mc) - 1;
+          mc &= mc - 1ull;
+          const int tj = kick_slot(j);
+          const double d2 = hermite_dmin2(
+              a.dt, hs[0][tj] - pre[0], hs[1][tj] - pre[1], hs[2][tj] - pre[2],
+              hs[3][tj] - pre[3], hs[4][tj] - pre[4], hs[5][tj] - pre[5], hs[6][tj] - x,
+              hs[7][tj] - y, hs[8][tj] - z, hs[9][tj] - vx, hs[10][tj] - vy, hs[11][tj] - vz);
+          const double rcij = fmax(rc, hs[12][tj]);
+          if (d2 < rcij * rcij) enc |= 1ull << j;
+        }
       }
     }
     const int ne = sys_sum_i<PK>(__popcll(enc));
