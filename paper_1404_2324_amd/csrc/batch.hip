@@ -208,13 +208,17 @@ __device__ __forceinline__ void kick_chunk(int jj0, int nh, int lane, int hb, do
       }
     }
   }
+  // accumulated without branches: a pair that does not count adds 0 * dx
+  // (its own lane: dx = 0; a partner slot past the system: finite dx)
 #pragma unroll
   for (int k = 0; k < U; ++k) {
-    if (ok[k]) {
-      ax = fma(s[k], dx[k], ax);
-      ay = fma(s[k], dy[k], ay);
-      az = fma(s[k], dz[k], az);
-      if (want_cand && r2[k] < pf2 * rcij[k] * rcij[k]) cand |= 1ull << (hb + jj0 + k);
+    const double sk = ok[k] ? s[k] : 0.0;
+    ax = fma(sk, dx[k], ax);
+    ay = fma(sk, dy[k], ay);
+    az = fma(sk, dz[k], az);
+    if (want_cand) {
+      const bool c = ok[k] && r2[k] < pf2 * rcij[k] * rcij[k];
+      cand |= c ? (1ull << (hb + jj0 + k)) : 0ull;
     }
   }
 }
