@@ -209,18 +209,18 @@ __device__ __forceinline__ void kick_chunk(int jj0, int nh, int lane, int hb, do
     }
   }
   // accumulated without branches: a pair that does not count adds 0 * dx
-  // (its own lane: dx = 0; a partner slot past the system: finite dx)
+  // (its own lane: dx = 0; a partner slot past the system: finite dx); the
+  // chunk's candidate bits gather in a small mask placed once
+  unsigned cb = 0u;
 #pragma unroll
   for (int k = 0; k < U; ++k) {
     const double sk = ok[k] ? s[k] : 0.0;
     ax = fma(sk, dx[k], ax);
     ay = fma(sk, dy[k], ay);
     az = fma(sk, dz[k], az);
-    if (want_cand) {
-      const bool c = ok[k] && r2[k] < pf2 * rcij[k] * rcij[k];
-      cand |= c ? (1ull << (hb + jj0 + k)) : 0ull;
-    }
+    if (want_cand) cb |= (ok[k] && r2[k] < pf2 * rcij[k] * rcij[k]) ? (1u << k) : 0u;
   }
+  if (want_cand) cand |= (unsigned long long)cb << (hb + jj0);
 }
 
 // Pair acceleration of H_B (Eq. 2 gradient) on the lane's body from every
