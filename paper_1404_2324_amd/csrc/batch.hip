@@ -50,8 +50,6 @@ __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v,
   return ((unsigned long long)hi << 32) | lo;
 }
 
-// Reductions over the lanes of one system: the whole wave (PK = 1) or the
-// lane's half (PK = 2, lanes 0-31 and 32-63 hold two systems).
 // The halves of a double exchanged between rows 2r and 2r + 1 (W = 16) or
 // between the two halves of the wave (W = 32); returns the lane's value plus
 // its partner's, the pair ordered by row so that both partners hold the same
@@ -91,6 +89,8 @@ __device__ __forceinline__ double sys_sum(double v) {
   return v;
 }
 
+// Integer reductions over the lanes of one system: the whole wave (PK = 1)
+// or the lane's half (PK = 2, lanes 0-31 and 32-63 hold two systems).
 template <int PK>
 __device__ __forceinline__ int sys_max_i(int v) {
   for (int o = 32 / PK; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
@@ -115,9 +115,10 @@ __device__ __forceinline__ unsigned long long sys_lanes(int l) {
   return PK == 1 ? ~0ull : (0xffffffffull << (l & 32));
 }
 
-// LDS slot of lane j for the two-systems-per-wave partner tables: the second
-// half is offset by one entry so that the two halves' broadcast reads of
-// partner jj fall in different banks.
+// LDS slot of lane j in the per-lane tables (the kick's partner tables with
+// two systems per wave, the Hermite test's states): the second half is
+// offset by one entry so that the two halves' broadcast reads of partner jj
+// fall in different banks.
 __device__ __forceinline__ int kick_slot(int j) { return j + (j >> 5); }
 constexpr int kKickSlots = 66;
 
