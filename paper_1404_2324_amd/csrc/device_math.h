@@ -166,7 +166,8 @@ __device__ __forceinline__ void stumpff(double z, double& c0, double& c1,
 // s = t - eta0 t^2/(2 r0) + (eta0^2/2 - r0 zeta0/6) t^3/r0^2 with t = dt/r0,
 // when its corrections are small against t (short steps); otherwise s = t.
 // The Stumpff values of the last residual evaluation are reused for f and g
-// when the iteration stopped there.  Returns the iteration count, or a
+// when the iteration stopped there; 1/r0 and 1/r are formed once and
+// multiplied in.  Returns the iteration count, or a
 // negative count when max_iter was reached without convergence.
 // s_out (optional) receives the converged universal anomaly s.
 __device__ __forceinline__ int kepler_drift(double mu, double dt, double& x,
@@ -174,11 +175,11 @@ __device__ __forceinline__ int kepler_drift(double mu, double dt, double& x,
                                             double& vy, double& vz,
                                             int max_iter, double* s_out = nullptr) {
   const double r0 = sqrt(x * x + y * y + z * z);
-  const double eta0 = x * vx + y * vy + z * vz;
-  const double beta = 2.0 * mu / r0 - (vx * vx + vy * vy + vz * vz);
-  const double zeta0 = mu - beta * r0;
-  const double t = dt / r0;
   const double ir0 = 1.0 / r0;
+  const double eta0 = x * vx + y * vy + z * vz;
+  const double beta = 2.0 * mu * ir0 - (vx * vx + vy * vy + vz * vz);
+  const double zeta0 = mu - beta * r0;
+  const double t = dt * ir0;
   const double k2 = -0.5 * eta0 * ir0 * t;
   const double k3 = (0.5 * eta0 * eta0 - r0 * zeta0 * (1.0 / 6.0)) * ir0 * ir0 * t * t;
   double s = (fabs(k2) + fabs(k3) <= 0.125) ? t * (1.0 + k2 + k3) : t;
@@ -211,10 +212,11 @@ __device__ __forceinline__ int kepler_drift(double mu, double dt, double& x,
   if (!fresh) stumpff(beta * s * s, c0, c1, c2, c3);
   const double G1 = s * c1, G2 = s * s * c2, G3 = s * s * s * c3;
   const double r = r0 + eta0 * G1 + zeta0 * G2;
-  const double f = 1.0 - mu * G2 / r0;
+  const double ir = 1.0 / r;
+  const double f = 1.0 - mu * G2 * ir0;
   const double g = dt - mu * G3;
-  const double fd = -mu * G1 / (r * r0);
-  const double gd = 1.0 - mu * G2 / r;
+  const double fd = -mu * G1 * ir0 * ir;
+  const double gd = 1.0 - mu * G2 * ir;
   const double nx = f * x + g * vx, ny = f * y + g * vy, nz = f * z + g * vz;
   const double nvx = fd * x + gd * vx, nvy = fd * y + gd * vy,
                nvz = fd * z + gd * vz;
