@@ -107,17 +107,18 @@ __device__ __forceinline__ void free_step(const AdjArgs& a, bool act, double Gm0
   vx += a.h * ax;
   vy += a.h * ay;
   vz += a.h * az;
+  const double hm0 = a.h / m0;  // the Sun kick's factor (the replay uses the same)
   double Px = seg_sum<SB>(m * vx), Py = seg_sum<SB>(m * vy), Pz = seg_sum<SB>(m * vz);
-  x += a.h * Px / m0;
-  y += a.h * Py / m0;
-  z += a.h * Pz / m0;
+  x += hm0 * Px;
+  y += hm0 * Py;
+  z += hm0 * Pz;
   if (act && kepler_drift(Gm0, a.dt, x, y, z, vx, vy, vz, a.max_iter) < 0) fl |= F_KEPLER;
   Px = seg_sum<SB>(m * vx);
   Py = seg_sum<SB>(m * vy);
   Pz = seg_sum<SB>(m * vz);
-  x += a.h * Px / m0;
-  y += a.h * Py / m0;
-  z += a.h * Pz / m0;
+  x += hm0 * Px;
+  y += hm0 * Py;
+  z += hm0 * Pz;
   seg_acc<SB>(a.G, x, y, z, m, ax, ay, az);
   vx += a.h * ax;
   vy += a.h * ay;
@@ -260,10 +261,12 @@ __device__ __forceinline__ void stumpff45(double z, double c2, double c3, double
 __device__ __forceinline__ void kepler_vjp(double mu, double dt, const double x0[3],
                                            const double v0[3], double s, const double lx1[3],
                                            const double lv1[3], double lx0[3], double lv0[3]) {
+  // 1/r0 and 1/r are formed once and multiplied in
   const double r0 = sqrt(x0[0] * x0[0] + x0[1] * x0[1] + x0[2] * x0[2]);
+  const double ir0 = 1.0 / r0;
   const double eta = x0[0] * v0[0] + x0[1] * v0[1] + x0[2] * v0[2];
   const double vv = v0[0] * v0[0] + v0[1] * v0[1] + v0[2] * v0[2];
-  const double beta = 2.0 * mu / r0 - vv;
+  const double beta = 2.0 * mu * ir0 - vv;
   double c0, c1, c2, c3, c4, c5;
   const double zz = beta * s * s;
   stumpff(zz, c0, c1, c2, c3);
@@ -272,8 +275,9 @@ __device__ __forceinline__ void kepler_vjp(double mu, double dt, const double x0
   const double G0 = c0, G1 = s * c1, G2 = s2 * c2, G3 = s2 * s * c3, G4 = s2 * s2 * c4,
                G5 = s2 * s2 * s * c5;
   const double r = r0 * G0 + eta * G1 + mu * G2;
-  const double f = 1.0 - mu * G2 / r0, g = dt - mu * G3;
-  const double fd = -mu * G1 / (r * r0), gd = 1.0 - mu * G2 / r;
+  const double ir = 1.0 / r;
+  const double f = 1.0 - mu * G2 * ir0, g = dt - mu * G3;
+  const double fd = -mu * G1 * ir * ir0, gd = 1.0 - mu * G2 * ir;
   // scalar adjoints of f, g, fdot, gdot
   const double wf = x0[0] * lx1[0] + x0[1] * lx1[1] + x0[2] * lx1[2];
   const double wg = v0[0] * lx1[0] + v0[1] * lx1[1] + v0[2] * lx1[2];
@@ -281,17 +285,17 @@ __device__ __forceinline__ void kepler_vjp(double mu, double dt, const double x0
   const double wgd = v0[0] * lv1[0] + v0[1] * lv1[1] + v0[2] * lv1[2];
   double bG0 = 0.0, bG1 = 0.0, bG2 = 0.0, bG3 = 0.0, br = 0.0, br0 = 0.0, beta_ = 0.0, bb = 0.0;
   // gdot = 1 - mu G2/r
-  bG2 += -mu / r * wgd;
-  br += mu * G2 / (r * r) * wgd;
+  bG2 += -mu * ir * wgd;
+  br += mu * G2 * (ir * ir) * wgd;
   // fdot = -mu G1/(r r0)
-  bG1 += -mu / (r * r0) * wfd;
-  br += mu * G1 / (r * r * r0) * wfd;
-  br0 += mu * G1 / (r * r0 * r0) * wfd;
+  bG1 += -mu * (ir * ir0) * wfd;
+  br += mu * G1 * (ir * ir * ir0) * wfd;
+  br0 += mu * G1 * (ir * ir0 * ir0) * wfd;
   // g = dt - mu G3
   bG3 += -mu * wg;
   // f = 1 - mu G2/r0
-  bG2 += -mu / r0 * wf;
-  br0 += mu * G2 / (r0 * r0) * wf;
+  bG2 += -mu * ir0 * wf;
+  br0 += mu * G2 * (ir0 * ir0) * wf;
   // r = r0 G0 + eta G1 + mu G2
   bG0 += r0 * br;
   bG1 += eta * br;
@@ -305,11 +309,11 @@ __device__ __forceinline__ void kepler_vjp(double mu, double dt, const double x0
   bb += bG0 * dG0b + bG1 * dG1b + bG2 * dG2b + bG3 * dG3b;
   // s(r0, eta, beta) from r0 G1 + eta G2 + mu G3 = dt; dF/ds = r
   const double Fb = r0 * dG1b + eta * dG2b + mu * dG3b;
-  br0 += bs * (-G1 / r);
-  beta_ += bs * (-G2 / r);
-  bb += bs * (-Fb / r);
+  br0 += bs * (-G1 * ir);
+  beta_ += bs * (-G2 * ir);
+  bb += bs * (-Fb * ir);
   // inputs: r0 = |x0|, eta = x0.v0, beta = 2 mu/r0 - v0.v0
-  const double cx = br0 / r0 - bb * 2.0 * mu / (r0 * r0 * r0);
+  const double cx = br0 * ir0 - bb * 2.0 * mu * (ir0 * ir0 * ir0);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     lx0[k] = f * lx1[k] + fd * lv1[k] + cx * x0[k] + beta_ * v0[k];
@@ -371,9 +375,9 @@ __global__ __launch_bounds__(64) void k_adj_bwd(AdjArgs a) {
       qz += a.h * az;
       const double v1[3] = {qx, qy, qz};  // velocities of the first Sun kick
       double Px = seg_sum<SB>(m * qx), Py = seg_sum<SB>(m * qy), Pz = seg_sum<SB>(m * qz);
-      px += a.h * Px / m0;
-      py += a.h * Py / m0;
-      pz += a.h * Pz / m0;
+      px += (a.h / m0) * Px;
+      py += (a.h / m0) * Py;
+      pz += (a.h / m0) * Pz;
       const double x2[3] = {px, py, pz};  // pre-drift state (x2, v1)
       double sK = 0.0;
       if (L.act) kepler_drift(Gm0, a.dt, px, py, pz, qx, qy, qz, a.max_iter, &sK);
@@ -381,9 +385,9 @@ __global__ __launch_bounds__(64) void k_adj_bwd(AdjArgs a) {
       Px = seg_sum<SB>(m * qx);
       Py = seg_sum<SB>(m * qy);
       Pz = seg_sum<SB>(m * qz);
-      px += a.h * Px / m0;
-      py += a.h * Py / m0;
-      pz += a.h * Pz / m0;  // (px, py, pz): positions of the second kick
+      px += (a.h / m0) * Px;
+      py += (a.h / m0) * Py;
+      pz += (a.h / m0) * Pz;  // (px, py, pz): positions of the second kick
       // second kick: x4 -> v5 = v3 + h a(x4)
       double gx = lx, gy = ly, gz = lz;
       kick_vjp<SB>(a.G, a.h, px, py, pz, m, lvx, lvy, lvz, gx, gy, gz, lm);
