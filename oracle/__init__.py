@@ -59,6 +59,20 @@ class Stats(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class Event(ctypes.Structure):
+    """A merger or an ejection (Sec. 3.2.7, 3.2.8)."""
+    _fields_ = [("kind", ctypes.c_int32), ("id_i", ctypes.c_int32), ("id_j", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("step", ctypes.c_int64), ("frac", ctypes.c_double),
+                ("m_i", ctypes.c_double), ("m_j", ctypes.c_double), ("R_i", ctypes.c_double),
+                ("R_j", ctypes.c_double)] + [
+        (f"{q}_{b}", ctypes.c_double * 3) for b in "ij" for q in ("x", "v", "s")] + [
+        ("U", ctypes.c_double)]
+
+
+EV_MERGE, EV_EJECT_FAR, EV_EJECT_SUN = 1, 2, 3
+GO_STOPPED = 2
+
+
 def params(G=1.0, m0=1.0, dt=0.01 * 2 * np.pi, n1=3.0, n2=0.4, pf=3.0,
            bs_tol=1e-13, bs_max_depth=20, kepler_max_iter=40,
            encounter_free=0) -> Params:
@@ -103,7 +117,16 @@ def lib():
             "go_tp_init": (i32, [_P, i32, _D, _D, _D, _D, _U8, i64, _D, _D, _U8]),
             "go_tp_step": (i32, [_P, i32, _D, _D, _D, _D, _U8, i64, _D, _D, _U8,
                                  i64, ctypes.POINTER(Stats), _D, i64, _I32, _I64, _D,
-                                 _D]),
+                                 _D, _D, _D]),
+            "go_massive_step_phys": (i32, [_P, ctypes.POINTER(ctypes.c_int), _D, _D, _D, _D, _U8,
+                                           i64, ctypes.POINTER(Stats), _D, _D, _I32,
+                                           ctypes.c_double, ctypes.c_double, i32, i64,
+                                           ctypes.POINTER(Event), i32,
+                                           ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_double)]),
+            "go_merge": (ctypes.c_double, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           _D, _D, ctypes.c_double, ctypes.c_double, _D, _D,
+                                           _D, _D, _D, _D]),
             "go_free_step": (i32, [_P, i32, _D, _D, _D, i64]),
             "go_free_tlm": (i32, [_P, i32, _D, _D, _D, _D, _D, _D, i64, _D, _D,
                                   _D, _D]),
@@ -228,11 +251,29 @@ def dem_to_helio(p: Params, m, v):
     return u
 
 
+def merge(G, mi, mj, yi, yj, Ri, Rj, si, sj):
+    """The merger of Sec. 3.2.7: (m, y = x and v of the new body, R, spin, U)."""
+    yi, yj, si, sj = _f64(yi, (6,)), _f64(yj, (6,)), _f64(si, (3,)), _f64(sj, (3,))
+    mo, Ro = ctypes.c_double(), ctypes.c_double()
+    yo, so = np.zeros(6), np.zeros(3)
+    U = lib().go_merge(float(G), float(mi), float(mj), _d(yi), _d(yj), float(Ri), float(Rj),
+                       _d(si), _d(sj), ctypes.byref(mo), _d(yo), ctypes.byref(Ro), _d(so))
+    return mo.value, yo, Ro.value, so, U
+
+
 # ------------------------------------------------------------ main mode ---
 class MassiveSim:
-    """One planetary system in main mode; state in democratic coordinates."""
+    """One planetary system in main mode; state in democratic coordinates.
 
-    def __init__(self, p: Params, m, x, v, coords="dem"):
+    radii (optional, one per body) turns on collisions between massive
+    bodies (Sec. 3.2.7), rcut / rcut_sun on ejections (Sec. 3.2.8) and nmin
+    the stop below that many bodies (Sec. 3.4.6).  Bodies then leave the
+    arrays (the last moves into a freed row); ``id`` holds each row's original
+    index, ``S`` the spins, ``U`` the internal energy of the mergers and
+    ``events`` every merger and ejection."""
+
+    def __init__(self, p: Params, m, x, v, coords="dem", radii=None, rcut=0.0, rcut_sun=0.0,
+                 nmin=0):
         self.p = p
         self.m = _f64(m).copy()
         self.x = _f64(x, (-1, 3)).copy()
@@ -250,16 +291,56 @@ class MassiveSim:
         self.enc = np.zeros((0, 2), dtype=np.int32)
         self.enc_d2 = np.zeros(0)
         self.enc_rc2 = np.zeros(0)
+        self.phys = radii is not None or rcut > 0.0 or rcut_sun > 0.0
+        self.R = np.zeros(n) if radii is None else _f64(radii).copy()
+        self.S = np.zeros((n, 3))
+        self.id = np.arange(n, dtype=np.int32)
+        self.rcut, self.rcut_sun, self.nmin = float(rcut), float(rcut_sun), int(nmin)
+        self.U = 0.0
+        self.events = []
+        self.nstep = 0
+        self.stopped = False
 
     @property
     def n(self):
         return len(self.m)
+
+    def _step_phys(self, nsteps):
+        n0 = self.n
+        nn = ctypes.c_int(n0)
+        m, x, v, rc = self.m.copy(), self.x.copy(), self.v.copy(), self.rc.copy()
+        R, S, idv = self.R.copy(), self.S.copy(), self.id.copy()
+        cap = 4 * n0 + 16
+        ev = (Event * cap)()
+        nev = ctypes.c_int()
+        U = ctypes.c_double(self.U)
+        st = Stats()
+        code = lib().go_massive_step_phys(
+            ctypes.byref(self.p), ctypes.byref(nn), _d(m), _d(x), _d(v), _d(rc),
+            self.cand.ctypes.data_as(_U8), int(nsteps), ctypes.byref(st), _d(R), _d(S),
+            idv.ctypes.data_as(_I32), self.rcut, self.rcut_sun, self.nmin, self.nstep, ev, cap,
+            ctypes.byref(nev), ctypes.byref(U))
+        k = nn.value
+        self.m, self.x, self.v, self.rc = m[:k], x[:k], v[:k], rc[:k]
+        self.R, self.S, self.id = R[:k], S[:k], idv[:k]
+        self.cand = np.ascontiguousarray(self.cand.reshape(-1)[:k * k].reshape(k, k))
+        self.U = U.value
+        self.events += [ev[i] for i in range(min(nev.value, cap))]
+        self.nstep += int(st.steps)
+        self.stats = st
+        if code == GO_STOPPED:
+            self.stopped = True
+            return st.as_dict()
+        _check(code, "massive_step_phys")
+        return st.as_dict()
 
     def candidates(self):
         i, j = np.nonzero(self.cand)
         return np.stack([i, j], 1).astype(np.int32)
 
     def step(self, nsteps=1, enc_cap=None):
+        if self.phys:
+            return self._step_phys(nsteps)
         n = self.n
         cap = n * (n - 1) // 2 if enc_cap is None else enc_cap
         ij = np.zeros((max(cap, 1), 2), dtype=np.int32)
@@ -315,6 +396,9 @@ class TPSim:
         self.coll_step = np.zeros(ntp, dtype=np.int64)
         self.coll_frac = np.zeros(ntp)
         self.coll_xv = np.zeros((ntp, 6))
+        # last step: Hermite minimum and threshold of every tested pair
+        self.tp_d2 = np.full((ntp, nm), np.nan)
+        self.tp_rc2 = np.full((ntp, nm), np.nan)
         self.nstep = 0
         self.rc = np.zeros(nm)
         self.cand = np.zeros((nm, nm), dtype=np.uint8)
@@ -335,7 +419,7 @@ class TPSim:
                                 ctypes.byref(st), rad, self.nstep,
                                 self.coll_planet.ctypes.data_as(_I32),
                                 self.coll_step.ctypes.data_as(_I64), _d(self.coll_frac),
-                                _d(self.coll_xv))
+                                _d(self.coll_xv), _d(self.tp_d2), _d(self.tp_rc2))
         self.stats = st
         self.nstep += int(st.steps)
         _check(code, "tp_step")
@@ -344,6 +428,14 @@ class TPSim:
     def removed(self):
         """Indices of the removed particles, ascending."""
         return np.nonzero(self.coll_planet >= 0)[0]
+
+    def tp_encounters(self):
+        """Test-particle encounters of the last step (Sec. 3.3): rows
+        (particle, planet) with d2 < r_crit,ij^2, sorted, and their d2, rc2."""
+        with np.errstate(invalid="ignore"):
+            k, j = np.nonzero(self.tp_d2 < self.tp_rc2)
+        return (np.stack([k, j], 1).astype(np.int64), self.tp_d2[k, j].copy(),
+                self.tp_rc2[k, j].copy())
 
 
 # ------------------------------------------------------------- batched ---

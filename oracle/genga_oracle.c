@@ -518,11 +518,49 @@ static int tp_collision(const ha_sys *s, const double *y0, const double *y1, dou
     return 0;
 }
 
+/* Massive groups with radii (Sec. 3.2.7): the first member pair (a, b),
+ * a < b in member order, whose separation falls below R_a + R_b during the
+ * substep y0 -> y1 of length h (the Hermite rule of Eqs. (10)-(12) applied
+ * to the substep, as the paper reuses the encounter test between BS steps);
+ * returns 1 and sets *ca, *cb, or 0.                                       */
+static int group_collision(const ha_sys *s, const double *y0, const double *y1, double h,
+                           int *ca, int *cb) {
+    for (int a = 0; a < s->ng; ++a)
+        for (int b = a + 1; b < s->ng; ++b) {
+            double R = s->rad[a] + s->rad[b];
+            if (!(R > 0.0)) continue;
+            double dx0[3], dv0[3], dx1[3], dv1[3];
+            for (int k = 0; k < 3; ++k) {
+                dx0[k] = y0[6 * b + k] - y0[6 * a + k];
+                dv0[k] = y0[6 * b + 3 + k] - y0[6 * a + 3 + k];
+                dx1[k] = y1[6 * b + k] - y1[6 * a + k];
+                dv1[k] = y1[6 * b + 3 + k] - y1[6 * a + 3 + k];
+            }
+            if (go_hermite_dmin2(h, dx0, dv0, dx1, dv1) < R * R) {
+                *ca = a;
+                *cb = b;
+                return 1;
+            }
+        }
+    return 0;
+}
+
 /* Returns GO_OK, GO_EBS, GO_EINVAL, or BS_COLLIDED with *coll_member (the
- * planet member) and *coll_frac (the fraction of H covered before the
- * substep in which the collision happens; y is the state there).           */
+ * planet member; for a massive group the first member of the pair and
+ * *coll_b the second) and *coll_frac (the fraction of H covered before the
+ * substep in which the collision happens; y is the state there), and the
+ * length of that substep in *coll_h.                                       */
+static int bs_integrate2(const ha_sys *s, double *y, double H, int64_t *substeps,
+                         int *coll_member, int *coll_b, double *coll_frac, double *coll_h);
 static int bs_integrate(const ha_sys *s, double *y, double H, int64_t *substeps,
                         int *coll_member, double *coll_frac) {
+    int cb = 0;
+    double ch = 0.0;
+    return bs_integrate2(s, y, H, substeps, coll_member, &cb, coll_frac, &ch);
+}
+
+static int bs_integrate2(const ha_sys *s, double *y, double H, int64_t *substeps,
+                         int *coll_member, int *coll_b, double *coll_frac, double *coll_h) {
     int dim = 6 * s->ng;
     int D = s->p->bs_max_depth;
     if (D < 0 || D > 40) return GO_EINVAL;
@@ -545,6 +583,17 @@ static int bs_integrate(const ha_sys *s, double *y, double H, int64_t *substeps,
                 if (j > 0) {
                     *coll_member = j;
                     *coll_frac = ldexp((double)pos, -D);
+                    *coll_h = h;
+                    rcode = BS_COLLIDED;
+                    break;
+                }
+            } else if (s->rad) {
+                int ca, cb;
+                if (group_collision(s, y, ynew, h, &ca, &cb)) {
+                    *coll_member = ca;
+                    *coll_b = cb;
+                    *coll_frac = ldexp((double)pos, -D);
+                    *coll_h = h;
                     rcode = BS_COLLIDED;
                     break;
                 }
@@ -707,14 +756,190 @@ typedef struct {
  *  precheck.  Reading: the closing kick and its precheck use the radii of
  *  step 1; an encounter is a candidate pair whose Hermite minimum is below
  *  r_crit,ij^2 (strict).                                                   */
-static int massive_step1(const go_params *p, int n, const double *m, double *x,
+/* Collision / ejection state of a main-mode run (NULL: none).             */
+typedef struct {
+    double *R, *S;
+    int32_t *id;
+    double rcut, rcut_sun;
+    int64_t step;
+    go_event *ev;
+    int ev_cap, n_ev;
+    double U;
+    uint8_t *dead;
+    double *gR, *gS;
+} phys_ctx;
+
+static void cross3(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Perfect merger (Sec. 3.2.7): mass and momentum add up, the new body sits
+ * at the centre of mass with its velocity, and its spin is the two spins
+ * plus the pair's orbital angular momentum about that centre (angular
+ * momentum conservation); U is the paper's internal energy of the collision.
+ * Reading: the radius is that of the merged volume (equal densities).      */
+double go_merge(double G, double mi, double mj, const double *yi, const double *yj,
+                double Ri, double Rj, const double *si, const double *sj, double *m_out,
+                double *y_out, double *R_out, double *s_out) {
+    double M = mi + mj;
+    for (int k = 0; k < 6; ++k) y_out[k] = (mi * yi[k] + mj * yj[k]) / M;
+    double di[3], ui[3], dj[3], uj[3], li[3], lj[3];
+    for (int k = 0; k < 3; ++k) {
+        di[k] = yi[k] - y_out[k];
+        ui[k] = yi[3 + k] - y_out[3 + k];
+        dj[k] = yj[k] - y_out[k];
+        uj[k] = yj[3 + k] - y_out[3 + k];
+    }
+    cross3(di, ui, li);
+    cross3(dj, uj, lj);
+    for (int k = 0; k < 3; ++k) s_out[k] = si[k] + sj[k] + mi * li[k] + mj * lj[k];
+    *m_out = M;
+    *R_out = cbrt(Ri * Ri * Ri + Rj * Rj * Rj);
+    double dv[3], dx[3];
+    for (int k = 0; k < 3; ++k) {
+        dv[k] = yi[3 + k] - yj[3 + k];
+        dx[k] = yi[k] - yj[k];
+    }
+    return 0.5 * mi * mj / M * dot3(dv, dv) - G * mi * mj / sqrt(dot3(dx, dx));
+}
+
+static void put_event(phys_ctx *ph, const go_event *e) {
+    if (ph->n_ev < ph->ev_cap) ph->ev[ph->n_ev] = *e;
+    ++ph->n_ev;
+}
+
+/* BS of one group with mergers (Sec. 3.2.6-3.2.7).  Members (ascending body
+ * index gi) with masses m, radii rc, physical radii R and spins S; states
+ * in y (6 per member).  When a member pair touches, the integration stops at
+ * the start of that BS substep (the last state before the collision), the
+ * pair merges (the more massive body survives, the lower index on equal
+ * masses, Sec. 3.2.7) and the group, one member fewer, is integrated over
+ * the rest of the step afresh.  Reading: the merged body keeps the larger
+ * critical radius of the two for the rest of the step.  *png: members left. */
+static int bs_group_phys(const go_params *p, int *png, int32_t *gi, double *m, double *rc,
+                         double *R, double *S, double *y, int64_t *substeps, phys_ctx *ph) {
+    int ng = *png;
+    double H = p->dt, f0 = 0.0;
+    int rcode = GO_OK;
+    for (;;) {
+        ha_sys hs = {p, ng, m, rc, 0, R};
+        int ca = 0, cb = 0;
+        double cf = 0.0, ch = 0.0;
+        int r = bs_integrate2(&hs, y, H, substeps, &ca, &cb, &cf, &ch);
+        if (r != BS_COLLIDED) {
+            rcode = r;
+            break;
+        }
+        double frac = f0 + (1.0 - f0) * cf;
+        int sv = m[cb] > m[ca] ? cb : ca, gh = sv == ca ? cb : ca;
+        go_event e;
+        memset(&e, 0, sizeof(e));
+        e.kind = GO_EV_MERGE;
+        e.id_i = ph->id[gi[sv]];
+        e.id_j = ph->id[gi[gh]];
+        e.step = ph->step;
+        e.frac = frac;
+        e.m_i = m[sv];
+        e.m_j = m[gh];
+        e.R_i = R[sv];
+        e.R_j = R[gh];
+        for (int k = 0; k < 3; ++k) {
+            e.x_i[k] = y[6 * sv + k];
+            e.v_i[k] = y[6 * sv + 3 + k];
+            e.s_i[k] = S[3 * sv + k];
+            e.x_j[k] = y[6 * gh + k];
+            e.v_j[k] = y[6 * gh + 3 + k];
+            e.s_j[k] = S[3 * gh + k];
+        }
+        double ym[6], Mm, Rm, sm[3];
+        e.U = go_merge(p->G, m[sv], m[gh], &y[6 * sv], &y[6 * gh], R[sv], R[gh], &S[3 * sv],
+                       &S[3 * gh], &Mm, ym, &Rm, sm);
+        put_event(ph, &e);
+        ph->U += e.U;
+        memcpy(&y[6 * sv], ym, sizeof(ym));
+        m[sv] = Mm;
+        R[sv] = Rm;
+        memcpy(&S[3 * sv], sm, sizeof(sm));
+        rc[sv] = rc[sv] > rc[gh] ? rc[sv] : rc[gh];
+        ph->dead[gi[gh]] = 1;
+        for (int q = gh; q + 1 < ng; ++q) {
+            gi[q] = gi[q + 1];
+            m[q] = m[q + 1];
+            rc[q] = rc[q + 1];
+            R[q] = R[q + 1];
+            memcpy(&S[3 * q], &S[3 * (q + 1)], 3 * sizeof(double));
+            memcpy(&y[6 * q], &y[6 * (q + 1)], 6 * sizeof(double));
+        }
+        --ng;
+        H = H * (1.0 - cf);
+        f0 = frac;
+    }
+    *png = ng;
+    return rcode;
+}
+
+/* Ejections (Sec. 3.2.8) after the direct integration: a body farther from
+ * the central mass than rcut, or closer than rcut_sun, is reported and
+ * removed.  Then the freed rows are filled (Sec. 3.4.6: the last body moves
+ * into a deleted position), in descending row order.  Returns the new n.   */
+static int remove_dead(const go_params *p, int n, double *m, double *x, double *v, double *rc,
+                       phys_ctx *ph) {
+    (void)p;
+    for (int i = 0; i < n; ++i) {
+        if (ph->dead[i]) continue;
+        double r = sqrt(dot3(V3(x, i), V3(x, i)));
+        int kind = 0;
+        if (ph->rcut > 0.0 && r > ph->rcut) kind = GO_EV_EJECT_FAR;
+        if (ph->rcut_sun > 0.0 && r < ph->rcut_sun) kind = GO_EV_EJECT_SUN;
+        if (!kind) continue;
+        go_event e;
+        memset(&e, 0, sizeof(e));
+        e.kind = kind;
+        e.id_i = ph->id[i];
+        e.id_j = -1;
+        e.step = ph->step;
+        e.frac = 1.0;
+        e.m_i = m[i];
+        e.R_i = ph->R[i];
+        for (int k = 0; k < 3; ++k) {
+            e.x_i[k] = x[3 * i + k];
+            e.v_i[k] = v[3 * i + k];
+            e.s_i[k] = ph->S[3 * i + k];
+        }
+        put_event(ph, &e);
+        ph->dead[i] = 1;
+    }
+    for (int h = n - 1; h >= 0; --h) {
+        if (!ph->dead[h]) continue;
+        int last = n - 1;
+        if (h != last) {
+            m[h] = m[last];
+            rc[h] = rc[last];
+            ph->R[h] = ph->R[last];
+            ph->id[h] = ph->id[last];
+            memcpy(V3(x, h), V3(x, last), 3 * sizeof(double));
+            memcpy(V3(v, h), V3(v, last), 3 * sizeof(double));
+            memcpy(V3(ph->S, h), V3(ph->S, last), 3 * sizeof(double));
+        }
+        ph->dead[h] = 0;
+        --n;
+    }
+    return n;
+}
+
+static int massive_step1(const go_params *p, int *pn, double *m, double *x,
                          double *v, double *rc, uint8_t *cand, go_stats *st,
                          enc_rec *enc, double *acc, double *xm, double *vm,
                          int32_t *pairs, int32_t *label, int32_t *order,
-                         double *gx, double *gv, double *gm, double *grc) {
+                         double *gx, double *gv, double *gm, double *grc,
+                         phys_ctx *ph) {
+    int n = *pn;
     double h = 0.5 * p->dt;
     int rcode = GO_OK;
     if (p->encounter_free) {
+        if (ph) return GO_EINVAL;
         kick_half(p, n, m, x, v, rc, acc);
         go_sun_drift(p, n, m, x, v, h);
         rcode = drift_all(p, n, x, v, &st->kepler_iter_max);
@@ -792,16 +1017,50 @@ static int massive_step1(const go_params *p, int n, const double *m, double *x,
                 gm[q] = m[i];
                 grc[q] = rc[i];
             }
-            int rc2 = go_bs_group(p, ng, gm, grc, gx, gv, p->dt, &st->bs_substeps);
-            if (rc2 != GO_OK) return rc2;
-            for (int q = 0; q < ng; ++q) {
-                int i = order[q];
-                for (int k = 0; k < 3; ++k) {
-                    x[3 * i + k] = gx[3 * q + k];
-                    v[3 * i + k] = gv[3 * q + k];
+            if (!ph) {
+                int rc2 = go_bs_group(p, ng, gm, grc, gx, gv, p->dt, &st->bs_substeps);
+                if (rc2 != GO_OK) return rc2;
+                for (int q = 0; q < ng; ++q) {
+                    int i = order[q];
+                    for (int k = 0; k < 3; ++k) {
+                        x[3 * i + k] = gx[3 * q + k];
+                        v[3 * i + k] = gv[3 * q + k];
+                    }
+                }
+            } else {
+                /* y holds x, v per member in gx (6 per member) */
+                double *y = gx;
+                for (int q = ng - 1; q >= 0; --q) {
+                    int i = order[q];
+                    for (int k = 0; k < 3; ++k) {
+                        y[6 * q + k] = xm[3 * i + k];
+                        y[6 * q + 3 + k] = vm[3 * i + k];
+                    }
+                    ph->gR[q] = ph->R[i];
+                    for (int k = 0; k < 3; ++k) ph->gS[3 * q + k] = ph->S[3 * i + k];
+                }
+                int ngl = ng;
+                int rc2 = bs_group_phys(p, &ngl, order, gm, grc, ph->gR, ph->gS, y,
+                                        &st->bs_substeps, ph);
+                if (rc2 != GO_OK) return rc2;
+                for (int q = 0; q < ngl; ++q) {
+                    int i = order[q];
+                    for (int k = 0; k < 3; ++k) {
+                        x[3 * i + k] = y[6 * q + k];
+                        v[3 * i + k] = y[6 * q + 3 + k];
+                        ph->S[3 * i + k] = ph->gS[3 * q + k];
+                    }
+                    m[i] = gm[q];
+                    rc[i] = grc[q];
+                    ph->R[i] = ph->gR[q];
                 }
             }
         }
+    }
+    /* do collisions: absorbed bodies and ejections leave (Sec. 3.2.7-3.2.8) */
+    if (ph) {
+        n = remove_dead(p, n, m, x, v, rc, ph);
+        *pn = n;
     }
     /* 8, 9 */
     go_sun_drift(p, n, m, x, v, h);
@@ -836,8 +1095,9 @@ int go_massive_step(const go_params *p, int n, const double *m, double *x,
         rcode = GO_EINVAL;
     } else {
         for (int64_t s = 0; s < nsteps && rcode == GO_OK; ++s) {
-            rcode = massive_step1(p, n, m, x, v, rc, cand, st, enc, acc, xm, vm,
-                                  pairs, label, order, gx, gv, gm, grc);
+            int nn = n;
+            rcode = massive_step1(p, &nn, (double *)m, x, v, rc, cand, st, enc, acc, xm, vm,
+                                  pairs, label, order, gx, gv, gm, grc, NULL);
             if (rcode == GO_OK) ++st->steps;
         }
         if (n_enc) {
@@ -865,6 +1125,67 @@ int go_massive_step(const go_params *p, int n, const double *m, double *x,
     free(gv);
     free(gm);
     free(grc);
+    return rcode;
+}
+
+int go_massive_step_phys(const go_params *p, int *pn, double *m, double *x, double *v,
+                         double *rc, uint8_t *cand, int64_t nsteps, go_stats *st,
+                         double *R, double *S, int32_t *id, double rcut, double rcut_sun,
+                         int nmin, int64_t step0, go_event *ev, int ev_cap, int *n_ev,
+                         double *U) {
+    if (!pn || *pn < 1 || nsteps < 0 || !R || !S || !id || !U || ev_cap < 0) return GO_EINVAL;
+    if (p->encounter_free || (ev_cap > 0 && !ev)) return GO_EINVAL;
+    go_stats local;
+    if (!st) st = &local;
+    memset(st, 0, sizeof(*st));
+    size_t N = (size_t)*pn;
+    enc_rec *enc = (enc_rec *)malloc(sizeof(enc_rec) * (N * (N - 1) / 2 + 1));
+    double *acc = (double *)malloc(sizeof(double) * 3 * N);
+    double *xm = (double *)malloc(sizeof(double) * 3 * N);
+    double *vm = (double *)malloc(sizeof(double) * 3 * N);
+    int32_t *pairs = (int32_t *)malloc(sizeof(int32_t) * (N * (N - 1) + 2));
+    int32_t *label = (int32_t *)malloc(sizeof(int32_t) * N);
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * N);
+    double *gx = (double *)malloc(sizeof(double) * 6 * N);
+    double *gv = (double *)malloc(sizeof(double) * 3 * N);
+    double *gm = (double *)malloc(sizeof(double) * N);
+    double *grc = (double *)malloc(sizeof(double) * N);
+    double *gR = (double *)malloc(sizeof(double) * N);
+    double *gS = (double *)malloc(sizeof(double) * 3 * N);
+    uint8_t *dead = (uint8_t *)calloc(N, 1);
+    phys_ctx ph = {R, S, id, rcut, rcut_sun, step0, ev, ev_cap, 0, *U, dead, gR, gS};
+    int rcode = GO_OK;
+    if (!enc || !acc || !xm || !vm || !pairs || !label || !order || !gx || !gv || !gm ||
+        !grc || !gR || !gS || !dead) {
+        rcode = GO_EINVAL;
+    } else {
+        for (int64_t s = 0; s < nsteps && rcode == GO_OK; ++s) {
+            ph.step = step0 + s;
+            rcode = massive_step1(p, pn, m, x, v, rc, cand, st, enc, acc, xm, vm, pairs, label,
+                                  order, gx, gv, gm, grc, &ph);
+            if (rcode == GO_OK) {
+                ++st->steps;
+                if (*pn < nmin) rcode = GO_STOPPED;
+            }
+        }
+    }
+    *U = ph.U;
+    if (n_ev) *n_ev = ph.n_ev;
+    if (rcode == GO_OK && ph.n_ev > ev_cap) rcode = GO_EOVERFLOW;
+    free(enc);
+    free(acc);
+    free(xm);
+    free(vm);
+    free(pairs);
+    free(label);
+    free(order);
+    free(gx);
+    free(gv);
+    free(gm);
+    free(grc);
+    free(gR);
+    free(gS);
+    free(dead);
     return rcode;
 }
 
@@ -936,8 +1257,10 @@ int go_tp_step(const go_params *p, int nm, const double *m, double *x,
                double *v, double *rc, uint8_t *cand, int64_t ntp, double *xt,
                double *vt, uint8_t *cand_tp, int64_t nsteps, go_stats *st,
                const double *rad, int64_t step0, int32_t *coll_planet,
-               int64_t *coll_step, double *coll_frac, double *coll_xv) {
+               int64_t *coll_step, double *coll_frac, double *coll_xv,
+               double *tp_d2, double *tp_rc2) {
     if (nm < 1 || nm > 64 || ntp < 0 || nsteps < 0) return GO_EINVAL;
+    if ((tp_d2 == NULL) != (tp_rc2 == NULL)) return GO_EINVAL;
     if (rad && (!coll_planet || !coll_step || !coll_frac || !coll_xv)) return GO_EINVAL;
     go_stats local;
     if (!st) st = &local;
@@ -1058,6 +1381,9 @@ int go_tp_step(const go_params *p, int nm, const double *m, double *x,
     reduction(| : bad) reduction(max : itmx)
         for (int64_t k = 0; k < ntp; ++k) {
             double *xk = V3(xt, k), *vk = V3(vt, k);
+            if (tp_d2)
+                for (int j = 0; j < nm; ++j)
+                    tp_d2[(size_t)k * nm + j] = tp_rc2[(size_t)k * nm + j] = NAN;
             if (isnan(xk[0])) continue; /* removed earlier */
             double rct = tp_rcrit(p, vk);
             double a[3];
@@ -1083,6 +1409,10 @@ int go_tp_step(const go_params *p, int nm, const double *m, double *x,
                     }
                     double d2 = go_hermite_dmin2(p->dt, dx0, dv0, dx1, dv1);
                     double rcij = rct > rc[j] ? rct : rc[j];
+                    if (tp_d2) {
+                        tp_d2[(size_t)k * nm + j] = d2;
+                        tp_rc2[(size_t)k * nm + j] = rcij * rcij;
+                    }
                     if (d2 < rcij * rcij) sel[ns++] = j;
                 }
                 if (ns > 0) {

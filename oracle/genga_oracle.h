@@ -91,6 +91,48 @@ int go_massive_step(const go_params *p, int n, const double *m, double *x,
                     go_stats *st, int enc_cap, int32_t *enc_ij,
                     double *enc_d2, double *enc_rc2, int *n_enc);
 
+/* ---- collisions and ejections of massive bodies (Sec. 3.2.7, 3.2.8, 3.4) */
+enum { GO_EV_MERGE = 1, GO_EV_EJECT_FAR = 2, GO_EV_EJECT_SUN = 3 };
+enum { GO_STOPPED = 2 };  /* fewer than nmin bodies left: the run stops */
+
+typedef struct {
+    int32_t kind;          /* GO_EV_*                                       */
+    int32_t id_i, id_j;    /* merger: survivor and the absorbed body (their
+                            * original indices); ejection: the body, -1     */
+    int32_t pad_;
+    int64_t step;          /* step index (step0 + steps of this call)       */
+    double frac;           /* merger: part of the step before the colliding
+                            * BS substep; ejection: 1                        */
+    double m_i, m_j, R_i, R_j;
+    double x_i[3], v_i[3], s_i[3];  /* democratic state and spin at the    */
+    double x_j[3], v_j[3], s_j[3];  /* report (merger: start of the
+                                     * colliding substep)                   */
+    double U;              /* merger: internal energy, else 0              */
+} go_event;
+
+/* The main-mode step with collisions and ejections: *n bodies with radii R,
+ * spins S (n x 3) and original indices id; m, x, v, rc, R, S, id change
+ * as bodies merge or leave (the last body moves into each freed row, rows
+ * in descending order, and *n shrinks).  rcut / rcut_sun: ejection limits on
+ * the distance from the central mass (0 = off).  nmin: the run stops with
+ * GO_STOPPED when fewer bodies remain.  Events go to ev (cap ev_cap; *n_ev
+ * counts all, GO_EOVERFLOW when more than cap); *U accumulates the internal
+ * energy of the mergers.  cand is the n x n candidate matrix of the current
+ * n.  step0: steps taken before this call.                                 */
+int go_massive_step_phys(const go_params *p, int *n, double *m, double *x, double *v,
+                         double *rc, uint8_t *cand, int64_t nsteps, go_stats *st,
+                         double *R, double *S, int32_t *id, double rcut, double rcut_sun,
+                         int nmin, int64_t step0, go_event *ev, int ev_cap, int *n_ev,
+                         double *U);
+/* The merger of two bodies (Sec. 3.2.7): a perfectly inelastic merger that
+ * conserves mass, momentum and angular momentum (orbital plus spin), with
+ * the internal energy U = 1/2 m_i m_j/(m_i+m_j) v_ij^2 - G m_i m_j/r_ij.
+ * y: x, v (6 values) per body; the merged body in m_out, y_out, R_out (the
+ * radius of the merged volume), s_out; returns U.                          */
+double go_merge(double G, double mi, double mj, const double *yi, const double *yj,
+                double Ri, double Rj, const double *si, const double *sj, double *m_out,
+                double *y_out, double *R_out, double *s_out);
+
 /* ---- test-particle mode ------------------------------------------------- */
 int go_tp_init(const go_params *p, int nm, const double *m, const double *x,
                const double *v, double *rc, uint8_t *cand, int64_t ntp,
@@ -103,12 +145,18 @@ int go_tp_init(const go_params *p, int nm, const double *m, const double *x,
  * index, the fraction of the step at the start of that substep and the
  * particle's state there (democratic coordinates, x then v); xt and vt of a
  * removed particle become NaN and later steps skip it.  coll_planet holds -1
- * for particles still present.  The report arrays may be NULL when rad is. */
+ * for particles still present.  The report arrays may be NULL when rad is.
+ * tp_d2, tp_rc2: NULL (both), or ntp x nm arrays that receive, for the last
+ * step of the call, the Hermite minimum squared separation (Eqs. 10-12) of
+ * every particle-planet pair the prechecker had listed and its threshold
+ * r_crit,ij^2; NaN for pairs not tested and for removed particles.  The
+ * step's test-particle encounter set (Sec. 3.3) is {(k, j): d2 < rc2}. */
 int go_tp_step(const go_params *p, int nm, const double *m, double *x,
                double *v, double *rc, uint8_t *cand, int64_t ntp, double *xt,
                double *vt, uint8_t *cand_tp, int64_t nsteps, go_stats *st,
                const double *rad, int64_t step0, int32_t *coll_planet,
-               int64_t *coll_step, double *coll_frac, double *coll_xv);
+               int64_t *coll_step, double *coll_frac, double *coll_xv,
+               double *tp_d2, double *tp_rc2);
 
 /* ---- encounter-free map, tangent-linear model and adjoint ---------------- */
 int go_free_step(const go_params *p, int n, const double *m, double *x,

@@ -530,6 +530,29 @@ def test_tp_mode_equals_massive_path_with_zero_masses():
         np.testing.assert_allclose(ms.v[3:], tp.vt, rtol=0, atol=1e-11)
 
 
+def test_tp_encounter_set_equals_massive_path_pairs():
+    """Sec. 3.3: the particle-planet encounters of a step (E and C of the
+    Hermite rule, Eqs. 10-12) are the planet-particle pairs the main-mode path
+    finds when the particles are bodies of zero mass, step by step."""
+    planets, xt, ut = W.test_particles(ntp=400, nplanets=3, seed_index=3)
+    p = O.params()
+    tp = O.TPSim(p, planets.m, planets.x, planets.u, xt, ut, coords="helio")
+    nm = len(planets.m)
+    ms = O.MassiveSim(p, np.concatenate([planets.m, np.zeros(len(xt))]),
+                      np.concatenate([tp.x, tp.xt]), np.concatenate([tp.v, tp.vt]))
+    total = 0
+    for _ in range(20):
+        tp.step(1)
+        ms.step(1)
+        ij, d2, rc2 = tp.tp_encounters()
+        assert np.all(d2 < rc2)
+        got = set(map(tuple, ij.tolist()))
+        ref = {(int(j) - nm, int(i)) for i, j in ms.enc if i < nm <= j}
+        assert got == ref
+        total += len(got)
+    assert total > 100
+
+
 def _pericentre(mu, r, v):
     """Closest approach of the two-body relative orbit (textbook)."""
     E = 0.5 * v @ v - mu / np.linalg.norm(r)
@@ -688,3 +711,98 @@ def test_adjoint_dot_product_with_tlm():
     lhs = np.sum(dxT * lx) + np.sum(dvT * lv)
     rhs = np.sum(dx * gx) + np.sum(dv * gv) + np.sum(dm * gm)
     assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+# ------------------------------------- collisions and ejections (massive) --
+def test_merge_by_hand():
+    """Sec. 3.2.7: the merged body has the total mass, the centre-of-mass
+    position and velocity (momentum conserved), the spin equal to the pair's
+    orbital angular momentum about that centre, mu (r x v_rel) with
+    mu = m_i m_j / (m_i + m_j), the volume-sum radius, and
+    U = mu v_ij^2 / 2 - G m_i m_j / r_ij, all worked out by hand here."""
+    mi, mj = 1e-3, 2e-3
+    yi = np.array([1.0, 0.0, 0.0, 0.0, 1.0, 0.0])
+    yj = np.array([1.001, 0.0, 0.0, 0.0, 1.01, 0.0])
+    m, y, R, spin, U = O.merge(1.0, mi, mj, yi, yj, 3e-5, 4e-5, np.zeros(3), np.zeros(3))
+    assert m == pytest.approx(3e-3, rel=1e-15)
+    np.testing.assert_allclose(y, [1.0 + 0.002 / 3, 0, 0, 0, 1.0 + 0.02 / 3, 0], rtol=1e-14, atol=1e-17)
+    mu = mi * mj / (mi + mj)                       # 6.666...e-4
+    np.testing.assert_allclose(spin, [0, 0, mu * 0.001 * 0.01], rtol=1e-12, atol=1e-25)
+    assert R == pytest.approx((3e-5 ** 3 + 4e-5 ** 3) ** (1 / 3), rel=1e-14)
+    assert U == pytest.approx(0.5 * mu * 0.01 ** 2 - 2e-6 / 0.001, rel=1e-13)
+    # spins add, momentum m v adds
+    m2, y2, _, s2, _ = O.merge(1.0, mi, mj, yi, yj, 0, 0, np.array([1e-9, 0, 0]),
+                               np.array([0, 2e-9, 0]))
+    np.testing.assert_allclose(s2, [1e-9, 2e-9, mu * 0.001 * 0.01], rtol=1e-12)
+    np.testing.assert_allclose(m2 * y2[3:], mi * yi[3:] + mj * yj[3:], rtol=1e-15)
+
+
+def _headon(mA, mB, RA=4e-4, RB=6e-4, d=0.01, w=1.0):
+    """Body B approaches body A (at 1 AU on a circular orbit) along the radius
+    with relative speed w from distance d: in straight-line relative motion
+    contact comes at t* = (d - RA - RB) / w.  The masses are tiny; the star's
+    differential pull (at most 3 G m0 d / r^3 along the pair) moves the pair
+    off that line by less than 1.5 d t^2 by time t."""
+    x = np.array([[1.0, 0.0, 0.0], [1.0 + d, 0.0, 0.0]])
+    u = np.array([[0.0, 1.0, 0.0], [-w, 1.0, 0.0]])
+    return np.array([mA, mB]), x, u, np.array([RA, RB]), (d - RA - RB) / w
+
+
+def test_headon_merger_reported_before_contact():
+    m, x, u, R, tstar = _headon(1e-10, 2e-10)
+    p = O.params()
+    sim = O.MassiveSim(p, m, x, u, coords="helio", radii=R)
+    L0 = np.sum(m[:, None] * np.cross(sim.x, sim.v), axis=0)
+    sim.step(1)
+    assert sim.n == 1 and len(sim.events) == 1
+    e = sim.events[0]
+    assert e.kind == O.EV_MERGE and e.step == 0
+    assert e.id_i == 1 and e.id_j == 0          # the more massive body survives
+    assert sim.id.tolist() == [1] and sim.m[0] == pytest.approx(3e-10, rel=1e-15)
+    # reported at the start of the BS substep of the contact: apart by more
+    # than the radii, and on the straight line to contact at t*
+    t_rep = e.frac * p.dt
+    sep = np.linalg.norm(np.array(e.x_j) - np.array(e.x_i))
+    assert 0.0 <= t_rep < tstar and sep > R.sum()
+    assert abs(sep - R.sum() - 1.0 * (tstar - t_rep)) <= 1.5 * 0.01 * tstar ** 2
+    # orbital plus spin angular momentum is unchanged by the step
+    L1 = np.sum(sim.m[:, None] * np.cross(sim.x, sim.v), axis=0) + sim.S.sum(axis=0)
+    np.testing.assert_allclose(L1, L0, rtol=1e-12)
+    # U of the report state, by the paper's formula
+    mu = e.m_i * e.m_j / (e.m_i + e.m_j)
+    dv = np.array(e.v_i) - np.array(e.v_j)
+    assert e.U == pytest.approx(0.5 * mu * dv @ dv - e.m_i * e.m_j / sep, rel=1e-12)
+    assert sim.U == e.U
+
+
+def test_merger_equal_masses_lower_index_survives():
+    m, x, u, R, _ = _headon(1e-10, 1e-10)
+    sim = O.MassiveSim(O.params(), m, x, u, coords="helio", radii=R)
+    sim.step(1)
+    assert [(e.kind, e.id_i, e.id_j) for e in sim.events] == [(O.EV_MERGE, 0, 1)]
+    assert sim.id.tolist() == [0]
+
+
+def test_ejection_compaction_and_nmin():
+    """Sec. 3.2.8 and 3.4.6: bodies beyond rcut or inside rcut_sun leave,
+    reported; each freed row takes the last body (rows in descending order);
+    below nmin bodies the run stops."""
+    s = W.planetesimals(6, seed_index=61)
+    x = s.x.copy()
+    x[1] *= 30.0 / np.linalg.norm(x[1])          # beyond rcut
+    x[3] *= 0.01 / np.linalg.norm(x[3])          # inside rcut_sun
+    u = s.u.copy()
+    u[1] *= 0.0
+    u[3] *= 0.0
+    p = O.params()
+    sim = O.MassiveSim(p, s.m, x, u, coords="helio", radii=np.zeros(6), rcut=20.0, rcut_sun=0.05)
+    sim.step(1)
+    kinds = sorted((e.id_i, e.kind) for e in sim.events)
+    assert kinds == [(1, O.EV_EJECT_FAR), (3, O.EV_EJECT_SUN)]
+    # rows 3 then 1 freed: row 3 takes body 5, row 1 takes body 4
+    assert sim.id.tolist() == [0, 4, 2, 5]
+    assert sim.n == 4
+    stop = O.MassiveSim(p, s.m, x, u, coords="helio", radii=np.zeros(6), rcut=20.0,
+                        rcut_sun=0.05, nmin=5)
+    stop.step(3)
+    assert stop.stopped and stop.n == 4 and stop.nstep == 1
