@@ -41,6 +41,16 @@ MUTANTS = {
                           "                    rcode = BS_COLLIDED;\n"),
     "coll_frac_after": ("*coll_frac = ldexp((double)pos, -D);",
                         "*coll_frac = ldexp((double)(pos + ((int64_t)1 << (D - d))), -D);"),
+    "merge_survivor_tie": ("int sv = m[cb] > m[ca] ? cb : ca", "int sv = m[cb] >= m[ca] ? cb : ca"),
+    "merge_U_sign": ("- G * mi * mj / sqrt(dot3(dx, dx));", "+ G * mi * mj / sqrt(dot3(dx, dx));"),
+    "merge_spin_orbital": ("s_out[k] = si[k] + sj[k] + mi * li[k] + mj * lj[k];",
+                           "s_out[k] = si[k] + sj[k];"),
+    "merge_report_after": ("                    *coll_b = cb;\n",
+                           "                    *coll_b = cb;\n"
+                           "                    memcpy(y, ynew, sizeof(double) * dim);\n"),
+    "compaction_ascending": ("for (int h = n - 1; h >= 0; --h) {", "for (int h = 0; h < n; ++h) {"),
+    "eject_rcut_sun_off": ("if (ph->rcut_sun > 0.0 && r < ph->rcut_sun) kind = GO_EV_EJECT_SUN;",
+                           "if (ph->rcut_sun > 0.0 && r > ph->rcut_sun) kind = GO_EV_EJECT_SUN;"),
 }
 
 
