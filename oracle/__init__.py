@@ -127,6 +127,9 @@ def lib():
             "go_merge": (ctypes.c_double, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                            _D, _D, ctypes.c_double, ctypes.c_double, _D, _D,
                                            _D, _D, _D, _D]),
+            "go_composition": (i32, [i32, _D]),
+            "go_massive_step_order": (i32, [_P, i32, i32, _D, _D, _D, _D, i64,
+                                            ctypes.POINTER(Stats)]),
             "go_free_step": (i32, [_P, i32, _D, _D, _D, i64]),
             "go_free_tlm": (i32, [_P, i32, _D, _D, _D, _D, _D, _D, i64, _D, _D,
                                   _D, _D]),
@@ -454,6 +457,29 @@ def batched_run(p: Params, offsets, m0s, m, x, v, nsteps):
         stats.append(sim.step(nsteps))
         x[a:b], v[a:b] = sim.x, sim.v
     return x, v, stats
+
+
+# ---------------------------------------------------- higher orders ---
+def composition(order):
+    """Sub-step coefficients w_k of the composed step (Sec. 2.3)."""
+    w = np.zeros(7)
+    k = lib().go_composition(int(order), _d(w))
+    if k == 0:
+        raise OracleError(GO_EINVAL, "composition")
+    return w[:k].copy()
+
+
+def step_order(p: Params, order, m, x, v, nsteps):
+    """nsteps composed steps of the given order (2, 4, 6) from democratic
+    (x, v): each sub-step the full hybrid step with every pair Hermite-tested.
+    Returns x, v, the radii of the last sub-step and the counters."""
+    m = _f64(m)
+    x, v = _f64(x, (-1, 3)).copy(), _f64(v, (-1, 3)).copy()
+    rc = np.zeros(len(m))
+    st = Stats()
+    _check(lib().go_massive_step_order(ctypes.byref(p), int(order), len(m), _d(m), _d(x), _d(v),
+                                       _d(rc), int(nsteps), ctypes.byref(st)), "step_order")
+    return x, v, rc, st.as_dict()
 
 
 # ------------------------------------------- encounter-free map + adjoint ---

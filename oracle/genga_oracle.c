@@ -934,7 +934,7 @@ static int massive_step1(const go_params *p, int *pn, double *m, double *x,
                          enc_rec *enc, double *acc, double *xm, double *vm,
                          int32_t *pairs, int32_t *label, int32_t *order,
                          double *gx, double *gv, double *gm, double *grc,
-                         phys_ctx *ph) {
+                         phys_ctx *ph, int all_pairs) {
     int n = *pn;
     double h = 0.5 * p->dt;
     int rcode = GO_OK;
@@ -974,7 +974,7 @@ static int massive_step1(const go_params *p, int *pn, double *m, double *x,
             double d2 = go_hermite_dmin2(p->dt, dx0, dv0, dx1, dv1);
             double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
             if (d2 < rcij * rcij) {
-                if (cand[(size_t)i * n + j]) {
+                if (all_pairs || cand[(size_t)i * n + j]) {
                     enc[nenc].i = i;
                     enc[nenc].j = j;
                     enc[nenc].d2 = d2;
@@ -1097,7 +1097,7 @@ int go_massive_step(const go_params *p, int n, const double *m, double *x,
         for (int64_t s = 0; s < nsteps && rcode == GO_OK; ++s) {
             int nn = n;
             rcode = massive_step1(p, &nn, (double *)m, x, v, rc, cand, st, enc, acc, xm, vm,
-                                  pairs, label, order, gx, gv, gm, grc, NULL);
+                                  pairs, label, order, gx, gv, gm, grc, NULL, 0);
             if (rcode == GO_OK) ++st->steps;
         }
         if (n_enc) {
@@ -1162,7 +1162,7 @@ int go_massive_step_phys(const go_params *p, int *pn, double *m, double *x, doub
         for (int64_t s = 0; s < nsteps && rcode == GO_OK; ++s) {
             ph.step = step0 + s;
             rcode = massive_step1(p, pn, m, x, v, rc, cand, st, enc, acc, xm, vm, pairs, label,
-                                  order, gx, gv, gm, grc, &ph);
+                                  order, gx, gv, gm, grc, &ph, 0);
             if (rcode == GO_OK) {
                 ++st->steps;
                 if (*pn < nmin) rcode = GO_STOPPED;
@@ -1186,6 +1186,100 @@ int go_massive_step_phys(const go_params *p, int *pn, double *m, double *x, doub
     free(gR);
     free(gS);
     free(dead);
+    return rcode;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Higher orders (Sec. 2.3): the step is a symmetric composition of the
+ * second-order step with sub-steps w_k tau (Yoshida 1990; fourth order:
+ * w1, w0, w1 with w1 = 1/(2 - 2^(1/3)), w0 = 1 - 2 w1; sixth order, his
+ * solution A: w3, w2, w1, w0, w1, w2, w3 with w0 = 1 - 2 (w1 + w2 + w3)).
+ * Some sub-steps run backward in time.  Each sub-step is the full hybrid
+ * scheme -- critical radii with |w_k tau|, kicks, drift, encounter search,
+ * grouping, BS -- except the prechecker: its candidates come from the
+ * previous sub-step's closing kick, which is not synchronous with this
+ * sub-step's drift, so every pair takes the Hermite test (Reading: "without
+ * the prechecker" means the encounter set is E over all pairs, not E and C).
+ * order 2 is the plain step.                                               */
+int go_composition(int order, double *w) {
+    if (order == 2) {
+        w[0] = 1.0;
+        return 1;
+    }
+    if (order == 4) {
+        double c = cbrt(2.0);
+        w[0] = w[2] = 1.0 / (2.0 - c);
+        w[1] = 1.0 - 2.0 * w[0];
+        return 3;
+    }
+    if (order == 6) {
+        double w1 = -1.17767998417887, w2 = 0.235573213359357, w3 = 0.784513610477560;
+        double w0 = 1.0 - 2.0 * (w1 + w2 + w3);
+        double q[7] = {w3, w2, w1, w0, w1, w2, w3};
+        memcpy(w, q, sizeof(q));
+        return 7;
+    }
+    return 0;
+}
+
+int go_massive_step_order(const go_params *p, int order, int n, const double *m, double *x,
+                          double *v, double *rc, int64_t nsteps, go_stats *st) {
+    double w[7];
+    int K = go_composition(order, w);
+    if (K == 0 || n < 1 || nsteps < 0) return GO_EINVAL;
+    go_stats local;
+    if (!st) st = &local;
+    memset(st, 0, sizeof(*st));
+    size_t N = (size_t)n;
+    enc_rec *enc = (enc_rec *)malloc(sizeof(enc_rec) * (N * (N - 1) / 2 + 1));
+    double *acc = (double *)malloc(sizeof(double) * 3 * N);
+    double *xm = (double *)malloc(sizeof(double) * 3 * N);
+    double *vm = (double *)malloc(sizeof(double) * 3 * N);
+    int32_t *pairs = (int32_t *)malloc(sizeof(int32_t) * (N * (N - 1) + 2));
+    int32_t *label = (int32_t *)malloc(sizeof(int32_t) * N);
+    int32_t *order_ = (int32_t *)malloc(sizeof(int32_t) * N);
+    double *gx = (double *)malloc(sizeof(double) * 3 * N);
+    double *gv = (double *)malloc(sizeof(double) * 3 * N);
+    double *gm = (double *)malloc(sizeof(double) * N);
+    double *grc = (double *)malloc(sizeof(double) * N);
+    uint8_t *cand = (uint8_t *)calloc(N * N, 1);
+    int rcode = GO_OK;
+    if (!enc || !acc || !xm || !vm || !pairs || !label || !order_ || !gx || !gv || !gm ||
+        !grc || !cand) {
+        rcode = GO_EINVAL;
+    } else {
+        go_stats sub;
+        for (int64_t s = 0; s < nsteps && rcode == GO_OK; ++s) {
+            for (int k = 0; k < K && rcode == GO_OK; ++k) {
+                go_params q = *p;
+                q.dt = w[k] * p->dt;
+                memset(&sub, 0, sizeof(sub));
+                int nn = n;
+                rcode = massive_step1(&q, &nn, (double *)m, x, v, rc, cand, &sub, enc, acc, xm,
+                                      vm, pairs, label, order_, gx, gv, gm, grc, NULL, 1);
+                st->enc_total += sub.enc_total;
+                st->bs_substeps += sub.bs_substeps;
+                if (sub.kepler_iter_max > st->kepler_iter_max)
+                    st->kepler_iter_max = sub.kepler_iter_max;
+                st->n_enc = sub.n_enc;
+                st->n_groups = sub.n_groups;
+                st->max_group = sub.max_group;
+            }
+            if (rcode == GO_OK) ++st->steps;
+        }
+    }
+    free(enc);
+    free(acc);
+    free(xm);
+    free(vm);
+    free(pairs);
+    free(label);
+    free(order_);
+    free(gx);
+    free(gv);
+    free(gm);
+    free(grc);
+    free(cand);
     return rcode;
 }
 

@@ -91,6 +91,17 @@ int go_massive_step(const go_params *p, int n, const double *m, double *x,
                     go_stats *st, int enc_cap, int32_t *enc_ij,
                     double *enc_d2, double *enc_rc2, int *n_enc);
 
+/* ---- higher orders (Sec. 2.3) ------------------------------------------- */
+/* Sub-step coefficients of the composition of the given order (2, 4 or 6)
+ * into w (up to 7); returns their number, 0 for another order.            */
+int go_composition(int order, double *w);
+/* nsteps composed steps (main mode): each sub-step w_k dt is the full hybrid
+ * step with the encounter search over all pairs (no prechecker).  The
+ * radii rc are those of the last sub-step on return.  st: counters summed
+ * over the sub-steps (n_enc, n_groups, max_group: the last sub-step).     */
+int go_massive_step_order(const go_params *p, int order, int n, const double *m, double *x,
+                          double *v, double *rc, int64_t nsteps, go_stats *st);
+
 /* ---- collisions and ejections of massive bodies (Sec. 3.2.7, 3.2.8, 3.4) */
 enum { GO_EV_MERGE = 1, GO_EV_EJECT_FAR = 2, GO_EV_EJECT_SUN = 3 };
 enum { GO_STOPPED = 2 };  /* fewer than nmin bodies left: the run stops */

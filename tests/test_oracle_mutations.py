@@ -49,6 +49,8 @@ MUTANTS = {
                            "                    *coll_b = cb;\n"
                            "                    memcpy(y, ynew, sizeof(double) * dim);\n"),
     "compaction_ascending": ("for (int h = n - 1; h >= 0; --h) {", "for (int h = 0; h < n; ++h) {"),
+    "yoshida_w0": ("w[1] = 1.0 - 2.0 * w[0];", "w[1] = 1.0 - w[0];"),
+    "yoshida_w1": ("w[0] = w[2] = 1.0 / (2.0 - c);", "w[0] = w[2] = 1.0 / (2.0 + c);"),
     "eject_rcut_sun_off": ("if (ph->rcut_sun > 0.0 && r < ph->rcut_sun) kind = GO_EV_EJECT_SUN;",
                            "if (ph->rcut_sun > 0.0 && r > ph->rcut_sun) kind = GO_EV_EJECT_SUN;"),
 }

@@ -806,3 +806,62 @@ def test_ejection_compaction_and_nmin():
                         rcut_sun=0.05, nmin=5)
     stop.step(3)
     assert stop.stopped and stop.n == 4 and stop.nstep == 1
+
+
+# ------------------------------------------------------- higher orders --
+@pytest.mark.parametrize("order,steps,ratio", [(4, (12, 24, 48), 16.0), (6, (5, 10, 20), 64.0)])
+def test_composed_step_convergence_order(order, steps, ratio):
+    """Sec. 2.3 with Yoshida's coefficients: star + one planet (no pair
+    terms, so the hybrid step is the H_A / H_C splitting) against the exact
+    relative orbit with mu = G (m0 + m): halving tau divides the error at a
+    fixed time by 2^order."""
+    m1 = 1e-3
+    mu = 1.0 + m1
+    a, e = 1.0, 0.1
+    x0, u0 = _two_body(mu, a, e, 0.0)
+    T = 2.0
+    errs = []
+    for nst in steps:
+        p = O.params(dt=T / nst)
+        v0 = O.helio_to_dem(p, [m1], u0[None])
+        x, v, _, _ = O.step_order(p, order, [m1], x0[None], v0, nst)
+        xr, _ = _two_body(mu, a, e, T)
+        errs.append(np.linalg.norm(x[0] - xr))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 0.85 * ratio < r1 < 1.15 * ratio and 0.85 * ratio < r2 < 1.15 * ratio, (errs, r1, r2)
+
+
+def test_composition_coefficients():
+    """Yoshida's conditions: the coefficients sum to 1 and, for the odd
+    powers of the error, sum w^3 = 0 (fourth order) and in addition
+    sum w^5 = 0 (sixth order, solution A, to its printed digits)."""
+    for order in (4, 6):
+        w = O.composition(order)
+        assert w.sum() == pytest.approx(1.0, abs=1e-15)
+        assert np.allclose(w, w[::-1])
+        assert abs((w ** 3).sum()) < 1e-12
+    assert abs((O.composition(6) ** 5).sum()) < 1e-12
+
+
+def test_composed_order2_is_the_plain_step_and_reversible():
+    """Order 2 is the plain step (all pairs Hermite-tested instead of the
+    prechecker's candidates: the same sets when the prechecker misses
+    nothing); the composed encounter-free map (K = 1) is time-symmetric: tau
+    then -tau returns.  (With encounters the hybrid step is not exactly
+    reversible: the radii come from the state at the start of each step.)"""
+    s = W.plain_n16()
+    p = O.params()
+    v0 = O.helio_to_dem(p, s.m, s.u)
+    x2, v2, _, st = O.step_order(p, 2, s.m, s.x, v0, 20)
+    ref = O.MassiveSim(p, s.m, s.x, v0)
+    ref.step(20)
+    assert ref.stats.miss_total == 0
+    np.testing.assert_array_equal(x2, ref.x)
+    np.testing.assert_array_equal(v2, ref.v)
+    pf = O.params(encounter_free=1)
+    for order in (4, 6):
+        x1, v1, _, _ = O.step_order(pf, order, s.m, s.x, v0, 10)
+        pb = O.params(dt=-p.dt, encounter_free=1)
+        xb, vb, _, _ = O.step_order(pb, order, s.m, x1, v1, 10)
+        np.testing.assert_allclose(xb, s.x, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(vb, v0, rtol=0, atol=1e-13)
