@@ -53,8 +53,37 @@ typedef struct genga_params {
     int32_t encounter_free; /* 1: K == 1 (the MVS map); no encounter work   */
     int32_t cand_per_body;  /* candidate partners stored per body           */
     int32_t enc_cap;        /* capacity of the encounter list               */
+    int32_t order;          /* 2 (or 0): the second-order step of Eq. (7);
+                             * 4 or 6: Yoshida's composition of it (Sec. 2.3),
+                             * main mode only                              */
+    /* Ejections (Sec. 3.2.8) and the minimal body count (Sec. 3.4.6),
+     * batched and main mode: a body farther from its central mass than rcut,
+     * or closer than rcut_sun, leaves the system (0 = no limit); a batched
+     * system with fewer than nmin bodies left stops (0 = never).           */
+    double rcut, rcut_sun;
+    int32_t nmin;
     int32_t reserved;
 } genga_params;
+
+/* A merger or an ejection (Sec. 3.2.7, 3.2.8). */
+enum { GENGA_EV_MERGE = 1, GENGA_EV_EJECT_FAR = 2, GENGA_EV_EJECT_SUN = 3 };
+typedef struct genga_event_s {
+    int32_t kind;           /* GENGA_EV_*                                     */
+    int32_t sys;            /* the system (batched mode; 0 in main mode)       */
+    int32_t id_i, id_j;     /* original rows: merger: the surviving and the
+                             * absorbed body; ejection: the body and -1        */
+    int64_t step;           /* the step (since init) in which it happened     */
+    double frac;            /* merger: part of the step before the BS substep
+                             * of the contact; ejection: 1                     */
+    double m_i, m_j, R_i, R_j;        /* masses and physical radii             */
+    double x_i[3], v_i[3], s_i[3];    /* democratic state and spin of each     */
+    double x_j[3], v_j[3], s_j[3];    /* body at the report (merger: the start
+                                       * of the substep of the contact)        */
+    double U;               /* merger: the internal energy of Sec. 3.2.7      */
+} genga_event;
+
+/* Bins of the Kepler-iteration histogram in genga_stats_t. */
+#define GENGA_KEPLER_BINS 16
 
 typedef struct genga_stats_s {
     int64_t steps;          /* steps taken since init                       */
@@ -71,6 +100,12 @@ typedef struct genga_stats_s {
     int64_t tp_removed;     /* test particles removed by collisions         */
     uint32_t flags;         /* latched device error bits                    */
     uint32_t reserved;
+    /* Kepler drifts since init by iteration count (Sec. 3.2.1: the f and g
+     * iteration converges in a few steps): bin k < 15 counts the drifts of
+     * the step that took k iterations, bin 15 those that took 15 or more or
+     * did not converge.  Every body's drift of every step of genga_step
+     * counts once (massive bodies, particles, every system of a batch). */
+    int64_t kepler_hist[GENGA_KEPLER_BINS];
 } genga_stats_t;
 
 enum { GENGA_MASSIVE = 0, GENGA_TEST = 1, GENGA_BATCH = 2 };
@@ -85,13 +120,14 @@ enum {
     GENGA_EADJ_ENCOUNTER = -6, /* pair inside r_crit in the K = 1 adjoint map */
     GENGA_ENOMEM = -7,      /* workspace smaller than genga_workspace_bytes */
     GENGA_EGROUP = -8,      /* encounter group larger than supported        */
-    GENGA_WSTOPPED = 1      /* warning, batched mode: some systems stopped   */
+    GENGA_WSTOPPED = 1,     /* warning, batched mode: some systems stopped   */
+    GENGA_WNMIN = 2         /* batched system status: fewer than nmin bodies  */
 };
 
 /* Fill *p with the defaults: G = 1, m0 = 1, dt = 2 pi / 100, n1 = 3,
  * n2 = 0.4 (Sec. 2.1), pf = 3 (Sec. 2.2), bs_tol = 1e-13, bs_max_depth =
  * 20, kepler_max_iter = 40, encounter_free = 0, cand_per_body = 32,
- * enc_cap = 2048. */
+ * enc_cap = 2048, order = 2. */
 void genga_params_default(genga_params *p);
 
 /* Device workspace (bytes) a context of this shape needs.  Main mode:
@@ -143,11 +179,17 @@ int genga_init(genga_ctx **ctx, int mode, const genga_params *p,
  * opening kick (reusing the closing kick's accelerations for non-candidate
  * pairs, Sec. 3.2.3), Sun kick, Kepler drift, encounter search, grouping,
  * BS integration of groups, Sun kick, closing kick with the prechecker.
+ * With order 4 or 6 each step is Yoshida's composition of that step (Sec.
+ * 2.3: sub-steps w_k dt, some backward in time; fourth order w1, w0, w1 with
+ * w1 = 1/(2 - 2^(1/3)); sixth order his solution A), every sub-step the full
+ * scheme with its own critical radii and the encounter search over all
+ * pairs in place of the prechecker's candidates.
  * Asynchronous on the context's stream (replays a captured HIP graph);
  * errors latch in the device status.  nsteps >= 0. */
 int genga_step(genga_ctx *ctx, int64_t nsteps);
 
-/* Measurement form of genga_step: the same nsteps (1..4096) steps launched
+/* Measurement form of genga_step (second order only): the same nsteps
+ * (1..4096) steps launched
  * one kernel at a time (no graph) on the context's stream, back to back, the
  * closing-kick pair kernel through hipExtLaunchKernel with two HIP events
  * that take its dispatch's start and end timestamps; *h_kick_us receives
@@ -156,7 +198,7 @@ int genga_step(genga_ctx *ctx, int64_t nsteps);
 int genga_step_profiled(genga_ctx *ctx, int64_t nsteps, double *h_kick_us);
 
 /* Number of kernels of one main-mode step, and their order. */
-#define GENGA_STEP_KERNELS 6
+#define GENGA_STEP_KERNELS 5
 /* Run nsteps (1..512) main-mode steps (in test-particle mode followed by the
  * particle kernels, untimed) with a HIP event pair around every kernel of
  * the step, launched so that the events take the dispatch's own start and
@@ -164,10 +206,11 @@ int genga_step_profiled(genga_ctx *ctx, int64_t nsteps, double *h_kick_us);
  * each kernel's average duration in microseconds, in launch order: opening
  * kick with Sun kick and Kepler drift, encounter search (Eqs. 10-12),
  * grouping (App. A), Bulirsch-Stoer of the groups (Sec. 3.2.6), pair kernel
- * of the closing kick, kick finish; the middle three are 0 with
- * encounter_free.  The breakdown behind a step's time, not a faster step.
- * Synchronising; returns the latched status (GENGA_EINVAL for a batched
- * context, a null pointer or nsteps out of range). */
+ * of the closing kick with its epilogue (second Sun kick, velocity update,
+ * next critical radii); the middle three are 0 with encounter_free.  The
+ * breakdown behind a step's time, not a faster step.  Synchronising; returns
+ * the latched status (GENGA_EINVAL for a batched context, a null pointer or
+ * nsteps out of range). */
 int genga_step_kernel_us(genga_ctx *ctx, int64_t nsteps, double *h_us);
 
 /* Wait for the context's stream and return the latched device status as a
@@ -207,19 +250,37 @@ int genga_encounters(genga_ctx *ctx, int32_t *h_ij, double *h_dmin2,
 
 /* Prechecker candidates entering the next step (Sec. 2.2): pairs i < j with
  * r_ij < pf r_crit,ij at the end of the last closing kick, sorted, as in
- * genga_encounters.  Synchronising. */
-int genga_candidates(genga_ctx *ctx, int32_t *h_ij, int cap, int *h_n);
+ * genga_encounters.  h_r2 (may be NULL) receives r_ij^2 as the closing kick
+ * computed it (NaN in batched mode, whose kernel keeps only the pair bits).
+ * Synchronising. */
+int genga_candidates(genga_ctx *ctx, int32_t *h_ij, double *h_r2, int cap, int *h_n);
 
-/* Test-particle mode: physical radii (Sec. 3.2.7, Sec. 3.3), device array of
- * n_massive + n_test values (planets first), copied.  From the next step on,
+/* Test-particle mode: the particle-planet close encounters of the last step
+ * (Sec. 3.3: a particle that meets a planet within the critical radius is
+ * integrated with it by BS; the set is the prechecker's candidates whose
+ * Hermite minimum of Eqs. 10-12 falls below r_crit,ij^2).  Per pair: particle
+ * index among the particles (h_tp), massive-body index (h_planet), the
+ * Hermite minimum squared separation (h_d2) and r_crit,ij^2 (h_rc2), as the
+ * step's kernel computed them (copied, no arithmetic); sorted by (particle,
+ * planet).  Particles removed in that step keep their encounter there.  Host
+ * arrays of cap entries (h_d2, h_rc2 may be NULL); *h_n receives the count;
+ * GENGA_EOVERFLOW when it exceeds cap (cap pairs written).  Synchronising.
+ * Errors: EINVAL (other mode). */
+int genga_tp_encounters(genga_ctx *ctx, int64_t *h_tp, int32_t *h_planet, double *h_d2,
+                        double *h_rc2, int64_t cap, int64_t *h_n);
+
+/* Physical radii (Sec. 3.2.7), device array, copied.  Batched mode: one per
+ * row; any positive radius turns on the mergers described at genga_events.
+ * Test-particle mode (Sec. 3.3): n_massive + n_test values (planets first).
+ * From the next step on,
  * a particle whose separation from a planet, Hermite-interpolated over a
  * Bulirsch-Stoer substep of its encounter (Eqs. 10-12 over that substep),
  * falls below the sum of their radii is removed: its x and v become NaN,
  * later steps skip it, and a report is kept (genga_collisions).  Radii start
  * at 0 (no collisions).  A particle only meets this test inside an encounter,
  * so radii should stay below the critical radii.  Synchronising.  Errors:
- * EINVAL (other mode, negative or non-finite radius; the radii are then
- * reset to 0), EHIP. */
+ * EINVAL (main mode, negative or non-finite radius; test-particle radii are
+ * then reset to 0, batched radii left as they were), EHIP. */
 int genga_set_radii(genga_ctx *ctx, const double *d_radii);
 
 /* Reports of the particles removed since init, sorted by (step, particle):
@@ -265,6 +326,31 @@ int genga_batch_set_variant(genga_ctx *ctx, int v);
  * Synchronising.  Errors: EINVAL (other mode), EOVERFLOW (cap < n_sys). */
 int genga_batch_status(genga_ctx *ctx, int32_t *h_status, int64_t *h_steps,
                        int cap);
+
+/* Batched mode, collisions and ejections (Sec. 3.2.7, 3.2.8, 3.4.6).  With
+ * physical radii set (genga_set_radii, one per row) two bodies of a group
+ * that come closer than the sum of their radii during a BS substep (the
+ * Hermite test of Eqs. 10-12 applied to the substep) merge at the start of
+ * that substep: mass, momentum and orbital-plus-spin angular momentum are
+ * kept, the radius is that of the summed volume, the more massive body
+ * survives (the lower row on equal masses), and the group is integrated
+ * over the rest of the step.  With rcut / rcut_sun (genga_params) bodies
+ * beyond or inside those distances from their central mass leave after the
+ * direct integration.  Each freed row takes the system's last body (freed
+ * rows in descending order) and the system's count drops; with fewer than
+ * nmin bodies left a system stops (status GENGA_WNMIN).  genga_get_state
+ * writes NaN rows past a system's count.
+ * genga_events: every merger and ejection since init (host array of cap
+ * records), sorted by (step, system, part of the step, survivor); *h_n
+ * receives the count, GENGA_EOVERFLOW when it exceeds cap or the record
+ * store (one record per row).  Synchronising.  Errors: EINVAL (other mode).
+ * genga_bodies: per row the original row of the body it holds (-1 past the
+ * system's count; host, cap >= the rows), per system the bodies left and
+ * the summed internal energy U of its mergers (host, sys_cap >= n_sys).
+ * Synchronising.  Errors: EINVAL (other mode), EOVERFLOW (small caps). */
+int genga_events(genga_ctx *ctx, genga_event *h_ev, int64_t cap, int64_t *h_n);
+int genga_bodies(genga_ctx *ctx, int32_t *h_id, int64_t cap, int32_t *h_nlive, double *h_U,
+                 int sys_cap);
 
 /* ---- reverse-mode gradient of the encounter-free map ----------------------
  * For a batched context created with encounter_free = 1: the map with K = 1

@@ -96,6 +96,8 @@ def lib():
         L = ctypes.CDLL(_LIB)
         i64, i32 = ctypes.c_int64, ctypes.c_int
         sig = {
+            "go_set_threads": (None, [i32]),
+            "go_threads": (i32, []),
             "go_changeover": (None, [ctypes.c_double, _D, _D]),
             "go_rcrit": (None, [_P, i32, _D, _D, _D, _D]),
             "go_accel": (None, [_P, i32, _D, _D, _D, _D]),
@@ -164,6 +166,16 @@ class OracleError(RuntimeError):
     def __init__(self, code, what):
         super().__init__(f"{what}: oracle error {code}")
         self.code = code
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops; returns the number now used."""
+    lib().go_set_threads(int(n))
+    return int(lib().go_threads())
+
+
+def threads():
+    return int(lib().go_threads())
 
 
 # ---------------------------------------------------------------- blocks ---

@@ -22,6 +22,7 @@
 #include "genga_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -30,6 +31,13 @@
 static double dot3(const double *a, const double *b) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
+
+/* Threads of the OpenMP loops over independent rows (the timing of the
+ * oracle on all host cores and on one core).                               */
+void go_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+}
+int go_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* Changeover function, Eq. (4) with y of Eq. (5).

@@ -61,6 +61,10 @@ enum {
     GO_EADJ_ENCOUNTER = -6
 };
 
+/* Threads of the OpenMP row loops (n > 0), and their current number. */
+void go_set_threads(int n);
+int go_threads(void);
+
 /* ---- building blocks (exported for the pins) ---------------------------- */
 void go_changeover(double y, double *K, double *dKdy);
 void go_rcrit(const go_params *p, int n, const double *m, const double *x,

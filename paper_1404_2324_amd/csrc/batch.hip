@@ -39,9 +39,20 @@ struct BatchArgs {
   unsigned* __restrict__ flags;             // latched error bits
   double* __restrict__ rbuf;                // BS tableaux of groups over 8 members
   const int* __restrict__ rslot;            // [nsys] slice of rbuf (systems over 8 bodies)
+  double* __restrict__ rad;                 // [nb] physical radii
+  double4* __restrict__ sp;                 // [nb] spins
+  int* __restrict__ ids;                    // [nb] original rows
+  genga_event* __restrict__ ev;             // mergers and ejections
+  unsigned long long* __restrict__ ev_cnt;
+  long long ev_cap;
   int nsys, nsteps;
   double G, dt, h, absdt, n1, n2, pf2, tol;
   int max_depth, max_iter, enc_free;
+  double rcut, rcut_sun;
+  int nmin;
+  int coll;    // radii are set: mergers (Sec. 3.2.7)
+  int phys;    // coll, or ejection limits, or nmin: bodies can leave
+  int record;  // events go to ev (not on the tuner's copies)
 };
 
 __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int l) {
@@ -276,7 +287,8 @@ __device__ __forceinline__ int nth_bit(unsigned long long M, int b) {
 template <int P>
 __device__ __forceinline__ int group_par(const BatchArgs& a, int sz, unsigned long long M,
                                          double pre[6], double m, double rc, double Gm0,
-                                         double* mm, double* mrc, long long* nsub) {
+                                         double* mm, double* mrc, long long* nsub, double H,
+                                         double R, double* mR, int* ckey, long long* cpos) {
   const int lane = threadIdx.x & 63;
   const int b = par_memb<P>(lane);
   const int body = b < sz ? nth_bit(M, b) : 0;
@@ -289,14 +301,16 @@ __device__ __forceinline__ int group_par(const BatchArgs& a, int sz, unsigned lo
   }
   // member tables indexed by member: lane t < sz fetches member t's data
   const int bt = lane < sz ? nth_bit(M, lane) : 0;
-  const double mb = __shfl(m, bt, 64), rcb = __shfl(rc, bt, 64);
+  const double mb = __shfl(m, bt, 64), rcb = __shfl(rc, bt, 64), Rbt = __shfl(R, bt, 64);
   __syncthreads();
   if (lane < sz) {
     mm[lane] = mb;
     mrc[lane] = rcb;
+    if (mR) mR[lane] = Rbt;
   }
   __syncthreads();
-  const int r = bs_group<P, false>(sz, y, mm, mrc, a.dt, a.G, Gm0, a.tol, a.max_depth, nsub);
+  const int r = bs_group<P, false>(sz, y, mm, mrc, H, a.G, Gm0, a.tol, a.max_depth, nsub, -1.0,
+                                   ckey, cpos, mR);
   const int rank = __popcll(M & ((1ull << lane) - 1ull));
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
@@ -310,20 +324,23 @@ __device__ __forceinline__ int group_par(const BatchArgs& a, int sz, unsigned lo
 // extrapolation tableau in this system's slice R of the workspace.
 __device__ __forceinline__ int group_seq(const BatchArgs& a, int sz, unsigned long long M,
                                          double pre[6], double m, double rc, double Gm0,
-                                         double (*R)[6][64], long long* nsub) {
+                                         double (*R)[6][64], long long* nsub, double H,
+                                         double Rad, bool coll, int* ckey, long long* cpos) {
   const int lane = threadIdx.x & 63;
   const int body = lane < sz ? nth_bit(M, lane) : 0;
   double y[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) y[c] = __shfl(pre[c], body, 64);
-  double mb = __shfl(m, body, 64), rcb = __shfl(rc, body, 64);
+  double mb = __shfl(m, body, 64), rcb = __shfl(rc, body, 64), Rb = __shfl(Rad, body, 64);
   if (lane >= sz) {
     y[0] = 1.0;
     y[1] = y[2] = y[3] = y[4] = y[5] = 0.0;
     mb = 0.0;
     rcb = 0.0;
+    Rb = 0.0;
   }
-  const int r = bs_integrate(sz, lane, y, a.dt, mb, rcb, a.G, Gm0, a.tol, a.max_depth, R, nsub);
+  const int r = bs_integrate(sz, lane, y, H, mb, rcb, a.G, Gm0, a.tol, a.max_depth, R, nsub, Rb,
+                             coll ? ckey : nullptr, cpos);
   const int rank = __popcll(M & ((1ull << lane) - 1ull));
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
@@ -333,57 +350,120 @@ __device__ __forceinline__ int group_seq(const BatchArgs& a, int sz, unsigned lo
   return r;
 }
 
+// Event record of a merger or an ejection, written by one lane.
+__device__ __forceinline__ void put_event(const BatchArgs& a, int kind, int sys, int idi, int idj,
+                                          long long step, double frac, double mi, double mj,
+                                          double Ri, double Rj, const double* yi,
+                                          const double* si, const double* yj, const double* sj,
+                                          double U) {
+  if (!a.record) return;
+  const unsigned long long k = atomicAdd(a.ev_cnt, 1ull);
+  if ((long long)k >= a.ev_cap) return;
+  genga_event e;
+  e.kind = kind;
+  e.sys = sys;
+  e.id_i = idi;
+  e.id_j = idj;
+  e.step = step;
+  e.frac = frac;
+  e.m_i = mi;
+  e.m_j = mj;
+  e.R_i = Ri;
+  e.R_j = Rj;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    e.x_i[q] = yi[q];
+    e.v_i[q] = yi[3 + q];
+    e.s_i[q] = si[q];
+    e.x_j[q] = yj ? yj[q] : 0.0;
+    e.v_j[q] = yj ? yj[3 + q] : 0.0;
+    e.s_j[q] = sj ? sj[q] : 0.0;
+  }
+  e.U = U;
+  a.ev[k] = e;
+}
+
 // PK systems per wave: one (lanes 0..63 for up to 64 bodies) or two (lanes
 // 0-31 and 32-63, systems of up to 32 bodies, so that small systems fill the
 // wave).  Every per-system quantity is a per-lane value uniform over the
 // system's lanes; the wave runs the step while either of its systems is
 // live, a stopped system's lanes keeping their state.  Both layouts do the
 // same arithmetic in the same order on each system.
-template <int LB, int PK>
+// With radii, limits or nmin (a.phys), bodies leave as in the paper's
+// multi-simulation mode (Sec. 3.2.7, 3.2.8, 3.4.6): a group's BS stops at
+// the substep in which two members touch, they merge, and the group goes on
+// over the rest of the step; after the groups, bodies beyond rcut or inside
+// rcut_sun leave; every freed lane takes the system's last body (freed lanes
+// in descending order) and the system's count drops; below nmin bodies the
+// system stops.  The step's encounter bits stay with the lanes they were
+// found on (the rows before the removal).
+template <int LB, int PK, bool PH>
 __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
-  __shared__ double mm[kBsPar], mrc[kBsPar];
+  __shared__ double mm[kBsPar], mrc[kBsPar], mR[kBsPar];
   __shared__ double4 kp[PK == 2 ? kKickSlots : 1];
   __shared__ double krc[PK == 2 ? kKickSlots : 1];
   __shared__ double hs[13][kKickSlots];  // pre-drift state, drifted state, radius
+  __shared__ unsigned kh[PK][kKepBins];  // each system's drifts by iteration count
   const int lane = threadIdx.x;
+  if (lane < PK * kKepBins) kh[lane / kKepBins][lane % kKepBins] = 0u;
+  __syncthreads();
   const int hb = PK == 1 ? 0 : (lane & 32);  // first lane of the lane's system
   const int hl = lane - hb;                  // the body's index in its system
   const int si = PK * blockIdx.x + (PK == 1 ? 0 : (lane >> 5));
   const bool has = si < a.nsys;
   const int s = has ? a.order[si] : 0;
   const int o = has ? a.off[s] : 0;
-  const int n = has ? a.off[s + 1] - o : 0;
-  const int nloop =
-      PK == 1 ? n : max(__builtin_amdgcn_readlane(n, 0), __builtin_amdgcn_readlane(n, 32));
-  const bool act = hl < n;
+  const int ncap = has ? a.off[s + 1] - o : 0;  // the system's rows
+  int n = has ? a.ss[s].nlive : 0;              // bodies still in it
+  auto loop_n = [&](int nn) {
+    return PK == 1 ? nn : max(__builtin_amdgcn_readlane(nn, 0), __builtin_amdgcn_readlane(nn, 32));
+  };
+  int nloop = loop_n(n);
+  bool act = hl < n;
   const double m0 = has ? a.m0[s] : 1.0;
   const double Gm0 = a.G * m0;
   // inactive lanes hold a massless dummy body far from the others
   double4 p = make_double4(1.0e3 + lane, 0.0, 0.0, 0.0);
   double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
   unsigned long long cand = 0ull, enc = 0ull, enc_last = 0ull;
+  double R = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0;
+  int id = 0;
   if (act) {
     p = a.xm[o + hl];
     q = a.vv[o + hl];
     cand = a.cand[o + hl] << hb;  // stored as bits of indices in the system
+    if (PH) {
+      R = a.rad[o + hl];
+      const double4 t = a.sp[o + hl];
+      S0 = t.x;
+      S1 = t.y;
+      S2 = t.z;
+      id = a.ids[o + hl];
+    }
   }
   double x = p.x, y = p.y, z = p.z, vx = q.x, vy = q.y, vz = q.z;
-  const double m = p.w;
+  double m = p.w;
   long long nsub = 0;
   unsigned long long enc_total = 0;
   int kit = 0, nenc = 0, ngrp = 0, maxg = 0;
   unsigned fl = 0u;
+  double Usys = 0.0;
+  const long long step0 = has ? a.ss[s].steps : 0;
   // a system stopped by an earlier failure takes no more steps
-  const bool stopped = !has || (a.ss[s].flags & (F_KEPLER | F_BS)) != 0u;
+  const bool stopped = !has || (a.ss[s].flags & (F_KEPLER | F_BS | F_NMIN)) != 0u;
   bool live = !stopped;
   int done = 0;
   for (int step = 0; step < a.nsteps; ++step) {
     if (__ballot(live) == 0ull) break;
     const bool live0 = live;
     const bool actv = act && live0;
-    // the step-start state is restored if the step fails
+    // the step-start state is restored if the step fails (with the bodies a
+    // merger or an ejection removed in it)
     const double sx = x, sy = y, sz0 = z, svx = vx, svy = vy, svz = vz;
     const unsigned long long scand = cand;
+    const double sm = m, sR = R, sS0 = S0, sS1 = S1, sS2 = S2, sU = Usys;
+    const int sid = id, sn = n;
+    (void)sm, (void)sR, (void)sS0, (void)sS1, (void)sS2, (void)sU, (void)sid, (void)sn;
     const double rc =
         actv && !a.enc_free ? rcrit(x, y, z, vx, vy, vz, m, Gm0, m0, a.n1, a.n2, a.absdt) : 0.0;
     double ax, ay, az;
@@ -403,6 +483,7 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
       const int it = kepler_drift(Gm0, a.dt, x, y, z, vx, vy, vz, a.max_iter);
       if (it < 0) fl |= F_KEPLER;
       kit = max(kit, abs(it));
+      atomicAdd(&kh[PK == 1 ? 0 : (lane >> 5)][min(abs(it), kKepBins - 1)], 1u);
     }
     // Hermite test of the candidate pairs i < j (Eqs. 10-12)
     enc = 0ull;
@@ -415,7 +496,7 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
       __syncthreads();  // earlier reads of the table are done
       const int t = kick_slot(lane);
 #pragma unroll
-      for (int q = 0; q < 6; ++q) hs[q][t] = pre[q];
+      for (int c = 0; c < 6; ++c) hs[c][t] = pre[c];
       hs[6][t] = x;
       hs[7][t] = y;
       hs[8][t] = z;
@@ -443,6 +524,8 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
     const int ne_w =
         PK == 1 ? ne : __builtin_amdgcn_readlane(ne, 0) + __builtin_amdgcn_readlane(ne, 32);
     int sgrp = 0, smaxg = 0;
+    bool dead = false;
+    double rcl = rc;  // a merged body keeps the larger radius for the step
     if (ne_w > 0) {
       // symmetric adjacency, then minimum-label components (App. A)
       unsigned long long adj = enc;
@@ -478,30 +561,78 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
       while (roots) {
         const int r = __ffsll((long long)roots) - 1;
         roots &= roots - 1ull;
-        const unsigned long long M = __ballot(ing && lab == r);
-        const int sz = __popcll(M);
+        unsigned long long M = __ballot(ing && lab == r);
+        int sz = __popcll(M);
         // the group belongs to the system of lane r
         const bool own = PK == 1 || ((lane ^ r) & 32) == 0;
         const double Gm0g = PK == 1 ? Gm0 : readlane_d(Gm0, r);
-        long long gsub = 0;
-        int st;
-        if (sz <= 2)
-          st = group_par<2>(a, sz, M, pre, m, rc, Gm0g, mm, mrc, &gsub);
-        else if (sz <= 4)
-          st = group_par<4>(a, sz, M, pre, m, rc, Gm0g, mm, mrc, &gsub);
-        else if (sz <= kBsPar)
-          st = group_par<8>(a, sz, M, pre, m, rc, Gm0g, mm, mrc, &gsub);
-        else {
-          const int sg = PK == 1 ? s : __builtin_amdgcn_readlane(s, r);
-          st = group_seq(a, sz, M, pre, m, rc, Gm0g,
-                         reinterpret_cast<double(*)[6][64]>(a.rbuf + (size_t)a.rslot[sg] * kBsRDoubles),
-                         &gsub);
-        }
+        const int sg = PK == 1 ? s : __builtin_amdgcn_readlane(s, r);
         if (own) {
           ++sgrp;
           smaxg = max(smaxg, sz);
-          nsub += gsub;
-          if (st != 0) fl |= F_BS;
+        }
+        double H = a.dt, f0 = 0.0;
+        for (;;) {
+          long long gsub = 0, cpos = 0;
+          int key = -1, st;
+          double* mRp = PH && a.coll ? mR : nullptr;
+          if (sz <= 2)
+            st = group_par<2>(a, sz, M, pre, m, rcl, Gm0g, mm, mrc, &gsub, H, R, mRp, &key, &cpos);
+          else if (sz <= 4)
+            st = group_par<4>(a, sz, M, pre, m, rcl, Gm0g, mm, mrc, &gsub, H, R, mRp, &key, &cpos);
+          else if (sz <= kBsPar)
+            st = group_par<8>(a, sz, M, pre, m, rcl, Gm0g, mm, mrc, &gsub, H, R, mRp, &key, &cpos);
+          else
+            st = group_seq(a, sz, M, pre, m, rcl, Gm0g,
+                           reinterpret_cast<double(*)[6][64]>(a.rbuf + (size_t)a.rslot[sg] * kBsRDoubles),
+                           &gsub, H, R, PH && a.coll != 0, &key, &cpos);
+          if (own) nsub += gsub;
+          if (!PH || st != 1) {
+            if (st != 0 && own) fl |= F_BS;
+            break;
+          }
+          // two members touch: merge them at the start of that substep and
+          // integrate the group, one member fewer, over the rest of the step
+          const double fc = ldexp((double)cpos, -a.max_depth);
+          const int la = nth_bit(M, key >> 6), lb = nth_bit(M, key & 63);
+          const double mla = readlane_d(m, la), mlb = readlane_d(m, lb);
+          const int ls = mlb > mla ? lb : la, lg = ls == la ? lb : la;
+          double ys[6], yg[6], ss[3], sgv[3], ym[6], sm[3], Mm, Rm;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            ys[c] = readlane_d(pre[c], ls);
+            yg[c] = readlane_d(pre[c], lg);
+          }
+          ss[0] = readlane_d(S0, ls);
+          ss[1] = readlane_d(S1, ls);
+          ss[2] = readlane_d(S2, ls);
+          sgv[0] = readlane_d(S0, lg);
+          sgv[1] = readlane_d(S1, lg);
+          sgv[2] = readlane_d(S2, lg);
+          const double ms = readlane_d(m, ls), mg = readlane_d(m, lg);
+          const double Rs = readlane_d(R, ls), Rg = readlane_d(R, lg);
+          const double Uc = merge_bodies(a.G, ms, mg, ys, yg, Rs, Rg, ss, sgv, Mm, ym, Rm, sm);
+          const double frac = f0 + (1.0 - f0) * fc;
+          if (lane == ls)
+            put_event(a, GENGA_EV_MERGE, sg, id, __builtin_amdgcn_readlane(id, lg),
+                      step0 + step, frac, ms, mg, Rs, Rg, ys, ss, yg, sgv, Uc);
+          if (own) Usys += Uc;
+          const double rcm = fmax(readlane_d(rcl, ls), readlane_d(rcl, lg));
+          if (lane == ls) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) pre[c] = ym[c];
+            m = Mm;
+            R = Rm;
+            S0 = sm[0];
+            S1 = sm[1];
+            S2 = sm[2];
+            rcl = rcm;
+          }
+          if (lane == lg) dead = true;
+          M &= ~(1ull << lg);
+          --sz;
+          H = H * (1.0 - fc);
+          f0 = frac;
         }
       }
       if (ing) {
@@ -513,12 +644,64 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
         vz = pre[5];
       }
     }
+    if (PH) {
+      // ejections (Sec. 3.2.8) of the bodies still present
+      if (actv && !dead && (a.rcut > 0.0 || a.rcut_sun > 0.0)) {
+        const double r = sqrt(x * x + y * y + z * z);
+        int kind = 0;
+        if (a.rcut > 0.0 && r > a.rcut) kind = GENGA_EV_EJECT_FAR;
+        if (a.rcut_sun > 0.0 && r < a.rcut_sun) kind = GENGA_EV_EJECT_SUN;
+        if (kind) {
+          const double yv[6] = {x, y, z, vx, vy, vz}, sv[3] = {S0, S1, S2};
+          put_event(a, kind, s, id, -1, step0 + step, 1.0, m, 0.0, R, 0.0, yv, sv, nullptr,
+                    nullptr, 0.0);
+          dead = true;
+        }
+      }
+      // the freed lanes take the last bodies (highest freed lane first)
+      while (true) {
+        const unsigned long long dm = __ballot(dead && act) & sys_lanes<PK>(lane);
+        if (__ballot(dm != 0ull) == 0ull) break;
+        int src = lane;
+        if (dm != 0ull) {
+          const int hgh = 63 - __builtin_clzll(dm);
+          const int last = hb + n - 1;
+          if (lane == hgh) src = last;
+          --n;  // uniform over the half
+        }
+        x = __shfl(x, src, 64);
+        y = __shfl(y, src, 64);
+        z = __shfl(z, src, 64);
+        vx = __shfl(vx, src, 64);
+        vy = __shfl(vy, src, 64);
+        vz = __shfl(vz, src, 64);
+        m = __shfl(m, src, 64);
+        R = __shfl(R, src, 64);
+        S0 = __shfl(S0, src, 64);
+        S1 = __shfl(S1, src, 64);
+        S2 = __shfl(S2, src, 64);
+        rcl = __shfl(rcl, src, 64);
+        id = __shfl(id, src, 64);
+        dead = __shfl((int)dead, src, 64) != 0;
+        act = hl < n;
+        if (!act) dead = false;
+      }
+      nloop = loop_n(n);
+      if (!act) {
+        // a lane past the system's count holds a massless dummy body
+        x = 1.0e3 + lane;
+        y = z = vx = vy = vz = 0.0;
+        m = 0.0;
+        R = 0.0;
+        rcl = 0.0;
+      }
+    }
     const double P2x = sys_sum<PK>(m * vx), P2y = sys_sum<PK>(m * vy),
                  P2z = sys_sum<PK>(m * vz);
     x += a.h * P2x / m0;
     y += a.h * P2y / m0;
     z += a.h * P2z / m0;
-    sys_kick<PK>(nloop, n, lane, hb, x, y, z, m, rc, a.G, a.pf2, !a.enc_free, ax, ay, az, cand,
+    sys_kick<PK>(nloop, n, lane, hb, x, y, z, m, rcl, a.G, a.pf2, !a.enc_free, ax, ay, az, cand,
                  kp, krc);
     vx += a.h * ax;
     vy += a.h * ay;
@@ -535,6 +718,18 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
       vy = svy;
       vz = svz;
       cand = scand;
+      if (PH) {
+        m = sm;
+        R = sR;
+        S0 = sS0;
+        S1 = sS1;
+        S2 = sS2;
+        id = sid;
+        n = sn;
+        Usys = sU;
+        act = hl < n;
+        nloop = loop_n(n);
+      }
     }
     if (live0) {
       enc_last = enc;
@@ -542,20 +737,35 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
       nenc = ne;
       ngrp = sgrp;
       maxg = smaxg;
-      if (fail)
+      if (fail) {
         live = false;
-      else
+      } else {
         ++done;
+        if (PH && a.nmin > 0 && n < a.nmin) {
+          fl |= F_NMIN;  // fewer than nmin bodies: the system stops (Sec. 3.4.6)
+          live = false;
+        }
+      }
     }
   }
   if (act && !stopped) {
     a.xm[o + hl] = make_double4(x, y, z, m);
     a.vv[o + hl] = make_double4(vx, vy, vz, 0.0);
     a.cand[o + hl] = cand >> hb;
-    if (a.nsteps > 0) a.encm[o + hl] = enc_last >> hb;
+    if (PH) {
+      a.sp[o + hl] = make_double4(S0, S1, S2, 0.0);
+      a.ids[o + hl] = id;
+      a.rad[o + hl] = R;
+    }
   }
+  // every row of the system: in a step that removed bodies the encounter
+  // bits stay on the rows they were found on
+  if (hl < ncap && !stopped && a.nsteps > 0) a.encm[o + hl] = enc_last >> hb;
   const unsigned fall = sys_or<PK>(fl);
   const int kitw = sys_max_i<PK>(kit);
+  __syncthreads();  // the histogram's LDS atomics are complete
+  if (hl < kKepBins && a.nsteps > 0 && !stopped)
+    a.ss[s].khist[hl] += kh[PK == 1 ? 0 : (lane >> 5)][hl];
   if (hl == 0 && a.nsteps > 0 && !stopped) {
     BatchSysStat& t = a.ss[s];
     t.steps += done;
@@ -565,6 +775,8 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
     t.ngroups = ngrp;
     t.maxg = maxg;
     t.kit = max(t.kit, kitw);
+    t.nlive = n;
+    t.U += Usys;
     if (fall) {
       t.flags |= fall;
       atomicOr(a.flags, F_SYS_STOP);
@@ -606,15 +818,22 @@ __global__ __launch_bounds__(64) void k_batch_pack(const double* __restrict__ m,
   }
 }
 
+// Rows past a system's live count (bodies that merged or left) are NaN.
 __global__ __launch_bounds__(64) void k_batch_unpack(const double4* __restrict__ xm,
                                                      const double4* __restrict__ vv,
                                                      const int* __restrict__ off,
                                                      const double* __restrict__ m0s,
+                                                     const BatchSysStat* __restrict__ ss,
                                                      double* __restrict__ x,
                                                      double* __restrict__ v, int helio) {
   const int s = blockIdx.x, lane = threadIdx.x;
-  const int o = off[s], n = off[s + 1] - o;
+  const int o = off[s], ncap = off[s + 1] - o, n = ss[s].nlive;
   const bool act = lane < n;
+  if (lane >= n && lane < ncap) {
+    const double nan = __builtin_nan("");
+#pragma unroll
+    for (int q = 0; q < 3; ++q) x[3 * (o + lane) + q] = v[3 * (o + lane) + q] = nan;
+  }
   double4 p = make_double4(0.0, 0.0, 0.0, 0.0), q = p;
   if (act) {
     p = xm[o + lane];
@@ -641,7 +860,7 @@ __global__ __launch_bounds__(64) void k_batch_unpack(const double4* __restrict__
 // prechecker on the initial positions (Sec. 2.2).
 __global__ __launch_bounds__(64) void k_batch_prime(BatchArgs a) {
   const int s = blockIdx.x, lane = threadIdx.x;
-  const int o = a.off[s], n = a.off[s + 1] - o;
+  const int o = a.off[s], n = a.ss[s].nlive;
   const bool act = lane < n;
   const double m0 = a.m0[s];
   double4 p = make_double4(1.0e3 + lane, 0.0, 0.0, 0.0), q = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -667,11 +886,12 @@ __global__ __launch_bounds__(64) void k_batch_prime(BatchArgs a) {
 __global__ __launch_bounds__(64) void k_batch_energy(const double4* __restrict__ xm,
                                                      const double4* __restrict__ vv,
                                                      const int* __restrict__ off,
-                                                     const double* __restrict__ m0s, double G,
+                                                     const double* __restrict__ m0s,
+                                                     const BatchSysStat* __restrict__ ss, double G,
                                                      double* __restrict__ E,
                                                      double* __restrict__ L) {
   const int s = blockIdx.x, lane = threadIdx.x;
-  const int o = off[s], n = off[s + 1] - o;
+  const int o = off[s], n = ss[s].nlive;
   const bool act = lane < n;
   double4 p = make_double4(1.0e3 + lane, 0.0, 0.0, 0.0), q = make_double4(0.0, 0.0, 0.0, 0.0);
   if (act) {
@@ -705,6 +925,21 @@ __global__ __launch_bounds__(64) void k_batch_energy(const double4* __restrict__
   }
 }
 
+// Every system's bodies present, rows as given (init).
+__global__ __launch_bounds__(64) void k_batch_reset(const int* __restrict__ off,
+                                                    BatchSysStat* __restrict__ ss,
+                                                    int* __restrict__ ids, double4* __restrict__ sp,
+                                                    double* __restrict__ rad) {
+  const int s = blockIdx.x, lane = threadIdx.x;
+  const int o = off[s], n = off[s + 1] - o;
+  if (lane < n) {
+    ids[o + lane] = o + lane;
+    sp[o + lane] = make_double4(0.0, 0.0, 0.0, 0.0);
+    rad[o + lane] = 0.0;
+  }
+  if (lane == 0) ss[s].nlive = n;
+}
+
 BatchArgs batch_args(const BatchWs& b, const StepConsts& c, bool scratch, int variant_order) {
   BatchArgs a;
   a.xm = scratch ? b.xm2 : b.xm;
@@ -717,6 +952,18 @@ BatchArgs batch_args(const BatchWs& b, const StepConsts& c, bool scratch, int va
   a.ss = scratch ? b.ss2 : b.ss;
   a.rbuf = b.rbuf;
   a.rslot = b.rslot;
+  a.rad = scratch ? b.rad2 : b.rad;
+  a.sp = scratch ? b.sp2 : b.sp;
+  a.ids = scratch ? b.ids2 : b.ids;
+  a.ev = b.ev;
+  a.ev_cnt = b.ev_cnt;
+  a.ev_cap = b.nb;
+  a.record = scratch ? 0 : 1;
+  a.coll = b.coll;
+  a.rcut = b.rcut;
+  a.rcut_sun = b.rcut_sun;
+  a.nmin = b.nmin;
+  a.phys = b.coll || b.rcut > 0.0 || b.rcut_sun > 0.0 || b.nmin > 0;
   a.flags = scratch ? b.flags2 : &b.st->flags;
   a.nsys = b.nsys;
   a.nsteps = 0;
@@ -778,6 +1025,14 @@ size_t batch_carve(BatchWs& b, int nsys, int64_t nb, int nbig, void* base) {
   b.rslot = (int*)take(ns * sizeof(int));
   b.rbuf = (double*)take((size_t)std::max(nbig, 1) * kBsRDoubles * sizeof(double));
   b.ss2 = (BatchSysStat*)take(ns * sizeof(BatchSysStat));
+  b.rad = (double*)take(n * sizeof(double));
+  b.rad2 = (double*)take(n * sizeof(double));
+  b.sp = (double4*)take(n * sizeof(double4));
+  b.sp2 = (double4*)take(n * sizeof(double4));
+  b.ids = (int*)take(n * sizeof(int));
+  b.ids2 = (int*)take(n * sizeof(int));
+  b.ev = (genga_event*)take(n * sizeof(genga_event));
+  b.ev_cnt = (unsigned long long*)take(sizeof(unsigned long long));
   b.flags2 = (unsigned*)take(sizeof(unsigned));
   b.flag_in = (int*)take(sizeof(int));
   b.st = (DevStat*)take(sizeof(DevStat));
@@ -792,8 +1047,8 @@ hipError_t batch_pack(const BatchWs& b, const double* m, const double* x, const 
 }
 
 hipError_t batch_unpack(const BatchWs& b, double* x, double* v, int coords_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_unpack, dim3(b.nsys), dim3(64), 0, s, b.xm, b.vv, b.off, b.m0, x, v,
-                     coords_out == GENGA_HELIO);
+  hipLaunchKernelGGL(k_batch_unpack, dim3(b.nsys), dim3(64), 0, s, b.xm, b.vv, b.off, b.m0, b.ss,
+                     x, v, coords_out == GENGA_HELIO);
   return hipGetLastError();
 }
 
@@ -805,8 +1060,8 @@ hipError_t batch_prime(const BatchWs& b, const StepConsts& c, hipStream_t s) {
 
 hipError_t batch_energy(const BatchWs& b, const StepConsts& c, double* E, double* L,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_energy, dim3(b.nsys), dim3(64), 0, s, b.xm, b.vv, b.off, b.m0, c.G,
-                     E, L);
+  hipLaunchKernelGGL(k_batch_energy, dim3(b.nsys), dim3(64), 0, s, b.xm, b.vv, b.off, b.m0, b.ss,
+                     c.G, E, L);
   return hipGetLastError();
 }
 
@@ -817,20 +1072,28 @@ hipError_t batch_run(const BatchWs& b, const StepConsts& c, int variant, int nst
   BatchArgs a = batch_args(b, c, scratch, packed ? 1 : (variant & 1));
   a.nsteps = nsteps;
   const dim3 blk(64);
+  // contexts whose bodies can leave run the kernel with that logic compiled
+  // in; the others run it without
   if (!packed) {
     const dim3 g(b.nsys);
-    switch (variant >> 1) {
-      case 0: hipLaunchKernelGGL((k_batch<1, 1>), g, blk, 0, s, a); break;
-      case 1: hipLaunchKernelGGL((k_batch<2, 1>), g, blk, 0, s, a); break;
-      default: hipLaunchKernelGGL((k_batch<4, 1>), g, blk, 0, s, a); break;
+    switch ((variant >> 1) + (a.phys ? 3 : 0)) {
+      case 0: hipLaunchKernelGGL((k_batch<1, 1, false>), g, blk, 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_batch<2, 1, false>), g, blk, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_batch<4, 1, false>), g, blk, 0, s, a); break;
+      case 3: hipLaunchKernelGGL((k_batch<1, 1, true>), g, blk, 0, s, a); break;
+      case 4: hipLaunchKernelGGL((k_batch<2, 1, true>), g, blk, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_batch<4, 1, true>), g, blk, 0, s, a); break;
     }
   } else {
     // two systems per wave: consecutive systems of the largest-first order
     const dim3 g((b.nsys + 1) / 2);
-    switch (variant - kBatchPackedVariant0) {
-      case 0: hipLaunchKernelGGL((k_batch<1, 2>), g, blk, 0, s, a); break;
-      case 1: hipLaunchKernelGGL((k_batch<2, 2>), g, blk, 0, s, a); break;
-      default: hipLaunchKernelGGL((k_batch<4, 2>), g, blk, 0, s, a); break;
+    switch ((variant - kBatchPackedVariant0) + (a.phys ? 3 : 0)) {
+      case 0: hipLaunchKernelGGL((k_batch<1, 2, false>), g, blk, 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_batch<2, 2, false>), g, blk, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_batch<4, 2, false>), g, blk, 0, s, a); break;
+      case 3: hipLaunchKernelGGL((k_batch<1, 2, true>), g, blk, 0, s, a); break;
+      case 4: hipLaunchKernelGGL((k_batch<2, 2, true>), g, blk, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_batch<4, 2, true>), g, blk, 0, s, a); break;
     }
   }
   return hipGetLastError();
@@ -843,8 +1106,23 @@ hipError_t batch_copy_to_scratch(const BatchWs& b, hipStream_t s) {
     e = hipMemcpyAsync(b.vv2, b.vv, n * sizeof(double4), hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b.cand2, b.cand, n * sizeof(unsigned long long), hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess) e = hipMemsetAsync(b.ss2, 0, (size_t)b.nsys * sizeof(BatchSysStat), s);
+  // the systems' counters go along (the live counts are needed)
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.ss2, b.ss, (size_t)b.nsys * sizeof(BatchSysStat), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.rad2, b.rad, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.sp2, b.sp, n * sizeof(double4), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.ids2, b.ids, n * sizeof(int), hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(b.flags2, 0, sizeof(unsigned), s);
+  return e;
+}
+
+hipError_t batch_reset_bodies(const BatchWs& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(b.nsys), dim3(64), 0, s, b.off, b.ss, b.ids, b.sp, b.rad);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemsetAsync(b.ev_cnt, 0, sizeof(unsigned long long), s);
   return e;
 }
 

@@ -3,6 +3,8 @@
 // test-particle kernels.  One wave integrates one group.
 #pragma once
 
+#include <climits>
+
 #include "device_math.h"
 
 namespace genga {
@@ -127,21 +129,60 @@ __device__ __forceinline__ bool bs_attempt(int sz, int lane, double y[6], double
   return false;
 }
 
+// Collision of two massive members over an accepted substep (Sec. 3.2.7,
+// the encounter test of Eqs. 10-12 reused between BS steps): the relative
+// states of the pair at its start (o) and end (e), the substep length h and
+// the sum of the radii Rs; true when the separation dips below Rs.
+__device__ __forceinline__ bool pair_touches(double h, const double o[6], const double e[6],
+                                             double Rs) {
+  if (!(Rs > 0.0)) return false;
+  return hermite_dmin2(h, o[0], o[1], o[2], o[3], o[4], o[5], e[0], e[1], e[2], e[3], e[4],
+                       e[5]) < Rs * Rs;
+}
+
 // Binary refinement over [0, H]: a failed substep is halved; after finishing
 // both halves of a node the next sibling is tried at the node's length.
+// With ckey (massive groups with radii; Rb the lane's member radius): after
+// each accepted substep every member pair whose radii sum is positive is
+// tested over the substep; at the first pair (a, b), a < b in member order,
+// that touches, the integration stops at the start of that substep and
+// returns 1 with a * 64 + b in *ckey and the covered part of [0, H] in *cpos
+// (units of H / 2^D).
 __device__ __forceinline__ int bs_integrate(int sz, int lane, double y[6], double H, double m,
                             double rc, double G, double Gm0, double tol,
-                            int D, double (*R)[6][64], long long* nsub) {
+                            int D, double (*R)[6][64], long long* nsub, double Rb = 0.0,
+                            int* ckey = nullptr, long long* cpos = nullptr) {
   long long pos = 0;
   const long long total = 1ll << D;
   int d = 0;
   int attempts = 0;
+  const bool coll = ckey && __ballot(lane < sz && Rb > 0.0) != 0ull;
   while (pos < total) {
     if (++attempts > kBsMaxAttempts) return -1;
     double yt[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) yt[c] = y[c];
     if (bs_attempt(sz, lane, yt, ldexp(H, -d), m, rc, G, Gm0, tol, R)) {
+      if (coll) {
+        const double h = ldexp(H, -d);
+        int best = INT_MAX;
+        for (int j = 0; j < sz; ++j) {
+          double o[6], e[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            o[c] = readlane_d(y[c], j) - y[c];
+            e[c] = readlane_d(yt[c], j) - yt[c];
+          }
+          const double Rs = Rb + readlane_d(Rb, j);
+          if (lane < sz && j > lane && pair_touches(h, o, e, Rs)) best = min(best, lane * 64 + j);
+        }
+        best = wave_min_i(best);
+        if (best != INT_MAX) {
+          *ckey = best;
+          *cpos = pos;
+          return 1;
+        }
+      }
 #pragma unroll
       for (int c = 0; c < 6; ++c) y[c] = yt[c];
       ++*nsub;
@@ -447,17 +488,24 @@ __device__ __forceinline__ int bs_round_par(int sz, double y[6], double H,
 // the integration stops at the start of that substep and returns 1, with the
 // lowest such member in *cb and the covered part of [0, H] in *cpos (units of
 // H / 2^D).  Returns 0 when H is covered, -1 when the depth is exhausted.
+// Massive groups (!TP) with mR (the members' physical radii, any memory):
+// every member pair with a positive radius sum is tested the same way, and
+// the first pair (a, b), a < b, that touches stops the integration with
+// a * 64 + b in *cb.
 template <int P, bool TP>
 __device__ __forceinline__ int bs_integrate_par(int sz, double y[6], double H,
                                                 const ParBody<P>& Q, double G,
                                                 double Gm0, double tol, int D,
                                                 long long* nsub, double R2 = -1.0,
                                                 int* cb = nullptr,
-                                                long long* cpos = nullptr) {
+                                                long long* cpos = nullptr,
+                                                const double* mR = nullptr) {
   constexpr int S = kBsPar / P;
   const int lane = threadIdx.x & 63;
   const int b = par_memb<P>(lane);
   const bool coll = TP && __ballot(R2 >= 0.0) != 0ull;
+  const double Rb = (!TP && mR && b < sz) ? mR[b] : 0.0;
+  const bool mcoll = !TP && mR && __ballot(Rb > 0.0) != 0ull;
   long long pos = 0;
   const long long total = 1ll << D;
   int d = 0;
@@ -490,6 +538,30 @@ __device__ __forceinline__ int bs_integrate_par(int sz, double y[6], double H,
           return 1;
         }
       }
+      if (mcoll) {
+        const double h = ldexp(H, -d);
+        int best = INT_MAX;
+#pragma unroll
+        for (int q = 1; q < P; ++q) {
+          if (q >= sz) break;
+          const int j = b + q < sz ? b + q : b + q - sz;  // member (b + q) mod sz
+          double o[6], e[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            o[c] = shfl_d(y[c], Q.lane[q]) - y[c];
+            e[c] = shfl_d(yt[c], Q.lane[q]) - yt[c];
+          }
+          const double Rs = b < sz ? Rb + mR[j] : 0.0;
+          if (b < sz && b < j && pair_touches(h, o, e, Rs)) best = min(best, b * 64 + j);
+        }
+        if (!((par_members<P>(0, 0) >> lane) & 1ull)) best = INT_MAX;
+        best = wave_min_i(best);
+        if (best != INT_MAX) {
+          *cb = best;
+          *cpos = pos;
+          return 1;
+        }
+      }
 #pragma unroll
       for (int q = 0; q < 6; ++q) y[q] = yt[q];
       ++*nsub;
@@ -514,7 +586,8 @@ __device__ __forceinline__ int bs_group(int sz, double y[6], const double* mm,
                                         const double* mrc, double H, double G,
                                         double Gm0, double tol, int D,
                                         long long* nsub, double R2 = -1.0,
-                                        int* cb = nullptr, long long* cpos = nullptr) {
+                                        int* cb = nullptr, long long* cpos = nullptr,
+                                        const double* mR = nullptr) {
   const int lane = threadIdx.x & 63;
   const int b = par_memb<P>(lane);
   const double rcb = b < sz ? mrc[b] : 0.0;
@@ -539,7 +612,40 @@ __device__ __forceinline__ int bs_group(int sz, double y[6], const double* mm,
       Q.near2[q] = Q.rcij[q] > 0.0 ? Q.rcij[q] * Q.rcij[q] * (1.0 + 1e-12) : 0.0;
     }
   }
-  return bs_integrate_par<P, TP>(sz, y, H, Q, G, Gm0, tol, D, nsub, R2, cb, cpos);
+  return bs_integrate_par<P, TP>(sz, y, H, Q, G, Gm0, tol, D, nsub, R2, cb, cpos, mR);
+}
+
+// The merger of Sec. 3.2.7 of survivor s and absorbed body g (states ys, yg:
+// x then v): mass and momentum add up, the new body sits at the centre of
+// mass with its velocity, its spin is both spins plus the pair's orbital
+// angular momentum about that centre, its radius that of the summed volume.
+// Returns the internal energy U = 1/2 m_s m_g/(m_s+m_g) v_sg^2 - G m_s m_g/r_sg.
+__device__ __forceinline__ double merge_bodies(double G, double ms, double mg, const double* ys,
+                                               const double* yg, double Rs, double Rg,
+                                               const double* ss, const double* sg, double& M,
+                                               double* y, double& R, double* S) {
+  M = ms + mg;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) y[k] = (ms * ys[k] + mg * yg[k]) / M;
+  double di[3], ui[3], dj[3], uj[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    di[k] = ys[k] - y[k];
+    ui[k] = ys[3 + k] - y[3 + k];
+    dj[k] = yg[k] - y[k];
+    uj[k] = yg[3 + k] - y[3 + k];
+  }
+  const double li[3] = {di[1] * ui[2] - di[2] * ui[1], di[2] * ui[0] - di[0] * ui[2],
+                        di[0] * ui[1] - di[1] * ui[0]};
+  const double lj[3] = {dj[1] * uj[2] - dj[2] * uj[1], dj[2] * uj[0] - dj[0] * uj[2],
+                        dj[0] * uj[1] - dj[1] * uj[0]};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) S[k] = ss[k] + sg[k] + ms * li[k] + mg * lj[k];
+  R = cbrt(Rs * Rs * Rs + Rg * Rg * Rg);
+  const double dv0 = ys[3] - yg[3], dv1 = ys[4] - yg[4], dv2 = ys[5] - yg[5];
+  const double dx0 = ys[0] - yg[0], dx1 = ys[1] - yg[1], dx2 = ys[2] - yg[2];
+  return 0.5 * ms * mg / M * (dv0 * dv0 + dv1 * dv1 + dv2 * dv2) -
+         G * ms * mg / sqrt(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
 }
 
 }  // namespace genga

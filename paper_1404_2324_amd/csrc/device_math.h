@@ -34,6 +34,11 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
+__device__ __forceinline__ int wave_min_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 // ---- reciprocal square root ------------------------------------------------
 // 1/sqrt(x) for positive normal x: the hardware estimate y (24.2 bits
 // measured) refined by one step of third order on the residual
@@ -48,6 +53,23 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   const double e = fma(-x * y, y, 1.0);
   return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// m / r^3 from r2 = r^2 (positive normal): with the hardware estimate y of
+// 1/sqrt(r2) and its residual e = 1 - r2 y^2, r^-3 = y^3 (1 - e)^(-3/2),
+// summed to second order, m y^3 (1 + 3e/2 + 15e^2/8): the next term,
+// 35e^3/16, is ~2^-71 for the 24-bit estimate.  Eight FP64 instructions
+// against nine for the refined 1/sqrt cubed and scaled, and a shorter
+// dependency chain.  r2 = 0 gives NaN or infinity (callers mask that case).
+// c1875 = 1.875 and c15 = 1.5 may be passed in registers that a caller's
+// loop holds (this target's three-operand FMA takes no literal operand).
+__device__ __forceinline__ double m_rinv3(double m, double r2, double c1875 = 1.875,
+                                          double c15 = 1.5) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double y2 = y * y;
+  const double e = fma(-r2, y2, 1.0);
+  const double my3 = (m * y) * y2;
+  return fma(my3, e * fma(e, c1875, c15), my3);
 }
 
 // 1/x for x in a bounded, well-scaled range (no zero, infinity or denormal):

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -22,19 +23,28 @@ int status_from_flags(unsigned f) {
   if (f & (F_CAND_OVF | F_ENC_OVF | F_TP_OVF)) return GENGA_EOVERFLOW;
   if (f & F_GROUP) return GENGA_EGROUP;
   if (f & F_ADJ_ENC) return GENGA_EADJ_ENCOUNTER;
+  if (f & F_NMIN) return GENGA_WNMIN;
   if (f & F_SYS_STOP) return GENGA_WSTOPPED;
   return GENGA_OK;
 }
 
-bool params_ok(const genga_params* p) {
+}  // namespace
+
+bool genga::params_valid(const genga_params* p) {
   if (!p) return false;
-  const double v[] = {p->G, p->m0, p->dt, p->n1, p->n2, p->pf, p->bs_tol};
+  const double v[] = {p->G, p->m0, p->dt, p->n1, p->n2, p->pf, p->bs_tol, p->rcut, p->rcut_sun};
   for (double d : v)
     if (!std::isfinite(d)) return false;
+  double w[8];
   return p->G > 0.0 && p->m0 > 0.0 && p->dt != 0.0 && p->n1 >= 0.0 && p->n2 >= 0.0 &&
          p->pf >= 1.0 && p->bs_max_depth >= 0 && p->bs_max_depth <= 40 &&
-         p->kepler_max_iter >= 1 && p->cand_per_body >= 1 && p->enc_cap >= 1;
+         p->kepler_max_iter >= 1 && p->cand_per_body >= 1 && p->enc_cap >= 1 &&
+         composition(p->order, w) > 0 && p->rcut >= 0.0 && p->rcut_sun >= 0.0 && p->nmin >= 0;
 }
+
+namespace {
+
+bool params_ok(const genga_params* p) { return params_valid(p); }
 
 int max_bodies(const genga_params* p) { return p->encounter_free ? 65536 : kGroupMaxN; }
 
@@ -46,6 +56,7 @@ constexpr int kBatchMaxSystems = 1 << 24;
 
 bool shape_ok(int mode, const genga_params* p, int nm, int64_t ntp, int nsys = 0,
               int64_t nbod = 0) {
+  if (p->order > 2 && mode != GENGA_MASSIVE) return false;  // compositions: main mode
   if (mode == GENGA_MASSIVE) return nm >= 1 && nm <= max_bodies(p) && ntp == 0;
   if (mode == GENGA_TEST) return nm >= 1 && nm <= kTpMaxPlanets && ntp >= 0 && ntp <= kTpMaxParticles;
   if (mode == GENGA_BATCH)
@@ -58,7 +69,7 @@ size_t ws_bytes(int mode, const genga_params& p, int nm, int64_t ntp, int nsys =
                 int64_t nbod = 0) {
   if (mode == GENGA_TEST) {
     TpWs t;
-    return align256(massive_ws_bytes(nm, p, true)) + tp_carve(t, ntp, nullptr);
+    return align256(massive_ws_bytes(nm, p, true)) + tp_carve(t, ntp, nm, nullptr);
   }
   if (mode == GENGA_BATCH) {
     BatchWs b;
@@ -86,6 +97,7 @@ struct genga_ctx {
   double* adj_ckpt = nullptr;            // the last genga_adj_forward's buffer
   size_t adj_bytes = 0;
   int adj_T = 0, adj_K = 0;
+  std::vector<StepConsts> sub;           // main mode: the constants of each sub-step
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
   hipGraphExec_t g_many = nullptr;
@@ -103,7 +115,8 @@ static int capture(genga_ctx* ctx, int nsteps, hipGraphExec_t* out) {
   HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
   for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
-    e = massive_step(ctx->w, ctx->c, ctx->cap);
+    for (size_t q = 0; q < ctx->sub.size() && e == hipSuccess; ++q)
+      e = massive_step(ctx->w, ctx->sub[q], ctx->cap);
     if (e == hipSuccess && ctx->mode == GENGA_TEST) e = tp_step(ctx->w, ctx->t, ctx->c, ctx->cap);
   }
   hipError_t e2 = hipStreamEndCapture(ctx->cap, &g);
@@ -139,9 +152,26 @@ static int load_state(genga_ctx* ctx, const double* d_m, const double* d_x, cons
   if (bad) return GENGA_EINVAL;
   HIPCHK(massive_pack(ctx->w, ctx->c, d_m, d_x, d_v, coords_in, ctx->stream));
   if (ctx->mode == GENGA_TEST) HIPCHK(tp_pack(ctx->w, ctx->t, ctx->c, d_x, d_v, coords_in, ctx->stream));
-  HIPCHK(massive_prime(ctx->w, ctx->c, ctx->stream));
+  HIPCHK(massive_prime(ctx->w, ctx->sub[0], ctx->stream));
   if (ctx->mode == GENGA_TEST) HIPCHK(tp_prime(ctx->w, ctx->t, ctx->c, ctx->stream));
   return GENGA_OK;
+}
+
+// The constants of each sub-step of the (composed) step: dt_k = w_k dt, the
+// radii formed at its end with the next sub-step's |dt|, and (orders above
+// two) the encounter search over all pairs.
+static void make_substeps(genga_ctx* ctx) {
+  double w[8];
+  const int K = composition(ctx->p.order, w);
+  ctx->sub.clear();
+  for (int k = 0; k < K; ++k) {
+    genga_params q = ctx->p;
+    q.dt = w[k] * ctx->p.dt;
+    StepConsts c = make_consts(q);
+    c.absdt_next = fabs(w[(k + 1) % K] * ctx->p.dt);
+    c.all_pairs = K > 1;
+    ctx->sub.push_back(c);
+  }
 }
 
 // ---- batched mode -----------------------------------------------------------
@@ -252,6 +282,10 @@ static int batch_init(genga_ctx** out, const genga_params* p, int n_sys,
   ctx->c = make_consts(*p);
   ctx->stream = st;
   batch_carve(ctx->b, n_sys, nb, n_sys, d_workspace);
+  ctx->b.coll = 0;
+  ctx->b.rcut = p->rcut;
+  ctx->b.rcut_sun = p->rcut_sun;
+  ctx->b.nmin = p->nmin;
   ctx->w.st = ctx->b.st;  // the status word read by the common calls
   std::vector<int> order(n_sys), desc(n_sys), rslot(n_sys, 0);
   for (int s = 0; s < n_sys; ++s) order[s] = s;
@@ -277,7 +311,8 @@ static int batch_init(genga_ctx** out, const genga_params* p, int n_sys,
        hipMemcpyAsync(b.order_desc, desc.data(), desc.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
        hipMemcpyAsync(b.rslot, rslot.data(), rslot.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
        hipMemsetAsync(b.ss, 0, (size_t)n_sys * sizeof(BatchSysStat), st) != hipSuccess ||
-       hipMemsetAsync(b.st, 0, sizeof(DevStat), st) != hipSuccess))
+       hipMemsetAsync(b.st, 0, sizeof(DevStat), st) != hipSuccess ||
+       batch_reset_bodies(b, st) != hipSuccess))
     rc = GENGA_EHIP;
   if (rc == GENGA_OK) rc = batch_load(ctx, d_m, d_x, d_v, coords_in);
   if (rc == GENGA_OK) rc = batch_tune(ctx, kTuneSteps);
@@ -349,13 +384,17 @@ int genga_init(genga_ctx** out, int mode, const genga_params* p, int n_massive, 
   ctx->mode = mode;
   ctx->p = *p;
   ctx->c = make_consts(*p);
+  make_substeps(ctx);
   ctx->stream = (hipStream_t)stream;
   const bool tp = mode == GENGA_TEST;
   const size_t moff = align256(massive_carve(ctx->w, n_massive, *p, d_workspace, tp));
-  if (tp) tp_carve(ctx->t, n_test, (char*)d_workspace + moff);
+  if (tp) tp_carve(ctx->t, n_test, n_massive, (char*)d_workspace + moff);
   int rc = GENGA_OK;
   if (hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) rc = GENGA_EHIP;
-  if (rc == GENGA_OK && hipMemsetAsync(ctx->w.st, 0, sizeof(DevStat), ctx->stream) != hipSuccess)
+  if (rc == GENGA_OK &&
+      (hipMemsetAsync(ctx->w.st, 0, sizeof(DevStat), ctx->stream) != hipSuccess ||
+       hipMemsetAsync(ctx->w.khist, 0, (size_t)ctx->w.nblk * kKepBins * sizeof(unsigned long long),
+                      ctx->stream) != hipSuccess))
     rc = GENGA_EHIP;
   if (rc == GENGA_OK && tp &&
       (hipMemsetAsync(ctx->t.rad, 0, (kTpMaxPlanets + std::max<int64_t>(n_test, 1)) * sizeof(double),
@@ -399,7 +438,7 @@ static int step_timed(genga_ctx* ctx, int64_t nsteps, bool all, double* us) {
   constexpr int K = kStepKernels;
   std::vector<hipEvent_t> ev((size_t)(2 * K * nsteps), nullptr);
   const bool enc = !ctx->c.encounter_free;
-  auto timed = [&](int k) { return k == 4 || (all && (enc || k == 0 || k == 5)); };
+  auto timed = [&](int k) { return k == 4 || (all && (enc || k == 0)); };
   int rc = GENGA_OK;
   for (int64_t t = 0; t < nsteps && rc == GENGA_OK; ++t)
     for (int k = 0; k < K && rc == GENGA_OK; ++k)
@@ -409,10 +448,10 @@ static int step_timed(genga_ctx* ctx, int64_t nsteps, bool all, double* us) {
   hipEvent_t last = nullptr;
   for (int64_t t = 0; t < nsteps && rc == GENGA_OK; ++t) {
     const hipEvent_t* kev = &ev[(size_t)(2 * K * t)];
-    if (massive_step(ctx->w, ctx->c, ctx->stream, kev) != hipSuccess ||
+    if (massive_step(ctx->w, ctx->sub[0], ctx->stream, kev) != hipSuccess ||
         (ctx->mode == GENGA_TEST && tp_step(ctx->w, ctx->t, ctx->c, ctx->stream) != hipSuccess))
       rc = GENGA_EHIP;
-    last = kev[2 * 5 + 1] ? kev[2 * 5 + 1] : kev[2 * 4 + 1];
+    last = kev[2 * 4 + 1];
   }
   if (rc == GENGA_OK && hipEventSynchronize(last) != hipSuccess) rc = GENGA_EHIP;
   for (int k = 0; k < K; ++k) us[k] = 0.0;
@@ -432,7 +471,8 @@ static int step_timed(genga_ctx* ctx, int64_t nsteps, bool all, double* us) {
 }
 
 int genga_step_profiled(genga_ctx* ctx, int64_t nsteps, double* h_kick_us) {
-  if (!ctx || nsteps < 1 || nsteps > 4096 || !h_kick_us || ctx->mode == GENGA_BATCH)
+  if (!ctx || nsteps < 1 || nsteps > 4096 || !h_kick_us || ctx->mode == GENGA_BATCH ||
+      ctx->sub.size() != 1)
     return GENGA_EINVAL;
   double us[kStepKernels];
   const int r = step_timed(ctx, nsteps, false, us);
@@ -441,7 +481,8 @@ int genga_step_profiled(genga_ctx* ctx, int64_t nsteps, double* h_kick_us) {
 }
 
 int genga_step_kernel_us(genga_ctx* ctx, int64_t nsteps, double* h_us) {
-  if (!ctx || nsteps < 1 || nsteps > 512 || !h_us || ctx->mode == GENGA_BATCH)
+  if (!ctx || nsteps < 1 || nsteps > 512 || !h_us || ctx->mode == GENGA_BATCH ||
+      ctx->sub.size() != 1)
     return GENGA_EINVAL;
   return step_timed(ctx, nsteps, true, h_us);
 }
@@ -494,7 +535,7 @@ int genga_energy(genga_ctx* ctx, double* d_E, double* d_L) {
 
 int genga_accel_state(genga_ctx* ctx, double* d_acc) {
   if (!ctx || !d_acc || ctx->mode == GENGA_BATCH) return GENGA_EINVAL;
-  HIPCHK(massive_accel(ctx->w, ctx->c, d_acc, ctx->stream));
+  HIPCHK(massive_accel(ctx->w, ctx->c, ctx->w.xs, d_acc, ctx->stream));
   return GENGA_OK;
 }
 
@@ -569,7 +610,7 @@ int genga_encounters(genga_ctx* ctx, int32_t* h_ij, double* h_dmin2, double* h_r
   return status_from_flags(hs.flags);
 }
 
-int genga_candidates(genga_ctx* ctx, int32_t* h_ij, int cap, int* h_n) {
+int genga_candidates(genga_ctx* ctx, int32_t* h_ij, double* h_r2, int cap, int* h_n) {
   if (!ctx || !h_n || cap < 0 || (cap > 0 && !h_ij)) return GENGA_EINVAL;
   DevStat hs;
   int r = read_status(ctx, &hs);
@@ -582,6 +623,7 @@ int genga_candidates(genga_ctx* ctx, int32_t* h_ij, int cap, int* h_n) {
     for (int k = 0; k < std::min(np, cap); ++k) {
       h_ij[2 * k] = pr[k].first;
       h_ij[2 * k + 1] = pr[k].second;
+      if (h_r2) h_r2[k] = std::nan("");
     }
     *h_n = np;
     if (np > cap) return GENGA_EOVERFLOW;
@@ -589,20 +631,27 @@ int genga_candidates(genga_ctx* ctx, int32_t* h_ij, int cap, int* h_n) {
   }
   const int n = ctx->w.n, cpb = ctx->w.cpb;
   std::vector<int> cnt(n), tab((size_t)n * cpb);
+  std::vector<double> r2((size_t)n * cpb);
   HIPCHK(hipMemcpyAsync(cnt.data(), ctx->w.ccnt, n * sizeof(int), hipMemcpyDeviceToHost,
                         ctx->stream));
   HIPCHK(hipMemcpyAsync(tab.data(), ctx->w.ctab, (size_t)n * cpb * sizeof(int),
                         hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(r2.data(), ctx->w.cr2, (size_t)n * cpb * sizeof(double),
+                        hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  std::vector<std::pair<int, int>> pairs;
+  // (i, j, slot of the pair in row i)
+  std::vector<std::tuple<int, int, size_t>> pairs;
   for (int i = 0; i < n; ++i)
-    for (int k = 0; k < std::min(cnt[i], cpb); ++k)
-      if (tab[(size_t)i * cpb + k] > i) pairs.emplace_back(i, tab[(size_t)i * cpb + k]);
+    for (int k = 0; k < std::min(cnt[i], cpb); ++k) {
+      const size_t at = (size_t)i * cpb + k;
+      if (tab[at] > i) pairs.emplace_back(i, tab[at], at);
+    }
   std::sort(pairs.begin(), pairs.end());
   const int np = (int)pairs.size();
   for (int k = 0; k < std::min(np, cap); ++k) {
-    h_ij[2 * k] = pairs[k].first;
-    h_ij[2 * k + 1] = pairs[k].second;
+    h_ij[2 * k] = std::get<0>(pairs[k]);
+    h_ij[2 * k + 1] = std::get<1>(pairs[k]);
+    if (h_r2) h_r2[k] = r2[std::get<2>(pairs[k])];
   }
   *h_n = np;
   if (np > cap) return GENGA_EOVERFLOW;
@@ -622,6 +671,7 @@ int genga_stats(genga_ctx* ctx, genga_stats_t* s) {
                           hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     for (const BatchSysStat& t : ss) {
+      for (int q = 0; q < kKepBins; ++q) s->kepler_hist[q] += (int64_t)t.khist[q];
       s->n_enc += ctx->steps > 0 ? t.nenc : 0;
       s->n_groups += ctx->steps > 0 ? t.ngroups : 0;
       s->max_group = std::max(s->max_group, t.maxg);
@@ -637,8 +687,14 @@ int genga_stats(genga_ctx* ctx, genga_stats_t* s) {
   s->n_enc = any ? hs.nenc : 0;
   s->n_groups = any ? hs.ngroups : 0;
   s->max_group = any ? hs.maxg : 0;
-  TpCounters tc = {0, 0, 0, 0};
+  TpCounters tc = {};
   if (ctx->mode == GENGA_TEST) HIPCHK(tp_read_counters(ctx->t, &tc, ctx->stream));
+  std::vector<unsigned long long> kh((size_t)ctx->w.nblk * kKepBins);
+  HIPCHK(hipMemcpyAsync(kh.data(), ctx->w.khist, kh.size() * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (size_t q = 0; q < kh.size(); ++q) s->kepler_hist[q % kKepBins] += (int64_t)kh[q];
+  for (int q = 0; q < kKepBins; ++q) s->kepler_hist[q] += (int64_t)tc.khist[q];
   s->kepler_iter_max = std::max(hs.kep_itmax, tc.kit);
   s->tp_enc = ctx->steps > 0 && !ctx->p.encounter_free ? (int32_t)tc.enc : 0;
   s->bs_substeps = (int64_t)(hs.bs_sub + tc.sub);
@@ -650,8 +706,55 @@ int genga_stats(genga_ctx* ctx, genga_stats_t* s) {
   return status_from_flags(hs.flags);
 }
 
+int genga_tp_encounters(genga_ctx* ctx, int64_t* h_tp, int32_t* h_planet, double* h_d2,
+                        double* h_rc2, int64_t cap, int64_t* h_n) {
+  if (!ctx || !h_n || cap < 0 || ctx->mode != GENGA_TEST) return GENGA_EINVAL;
+  if (cap > 0 && (!h_tp || !h_planet)) return GENGA_EINVAL;
+  DevStat hs;
+  int r = read_status(ctx, &hs);
+  if (r != GENGA_OK) return r;
+  std::vector<TpEnc> e;
+  if (ctx->steps > 0 && !ctx->p.encounter_free) HIPCHK(tp_read_encounters(ctx->t, &e, ctx->stream));
+  std::sort(e.begin(), e.end(), [](const TpEnc& a, const TpEnc& b) {
+    return a.tp != b.tp ? a.tp < b.tp : a.planet < b.planet;
+  });
+  const int64_t n = (int64_t)e.size(), wr = std::min(n, cap);
+  for (int64_t k = 0; k < wr; ++k) {
+    h_tp[k] = e[k].tp;
+    h_planet[k] = e[k].planet;
+    if (h_d2) h_d2[k] = e[k].d2;
+    if (h_rc2) h_rc2[k] = e[k].rc2;
+  }
+  *h_n = n;
+  if (n > cap) return GENGA_EOVERFLOW;
+  return status_from_flags(hs.flags);
+}
+
 int genga_set_radii(genga_ctx* ctx, const double* d_radii) {
-  if (!ctx || !d_radii || ctx->mode != GENGA_TEST) return GENGA_EINVAL;
+  if (!ctx || !d_radii) return GENGA_EINVAL;
+  if (ctx->mode == GENGA_BATCH) {
+    // one radius per row; any positive one turns the mergers on
+    const BatchWs& b = ctx->b;
+    std::vector<double> r((size_t)b.nb);
+    HIPCHK(hipMemcpyAsync(r.data(), d_radii, r.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    bool any = false;
+    for (double q : r) {
+      if (!(q >= 0.0) || !std::isfinite(q)) return GENGA_EINVAL;
+      any = any || q > 0.0;
+    }
+    HIPCHK(hipMemcpyAsync(b.rad, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if ((int)any != ctx->b.coll && ctx->g_batch) {
+      (void)hipGraphExecDestroy(ctx->g_batch);  // the launch changes kernel
+      ctx->g_batch = nullptr;
+    }
+    ctx->b.coll = any ? 1 : 0;
+    return GENGA_OK;
+  }
+  if (ctx->mode != GENGA_TEST) return GENGA_EINVAL;
   HIPCHK(hipMemsetAsync(ctx->w.flag_in, 0, sizeof(int), ctx->stream));
   HIPCHK(tp_set_radii(ctx->t, ctx->w.n, d_radii, ctx->w.flag_in, ctx->stream));
   int bad = 0;
@@ -699,6 +802,59 @@ int genga_collisions(genga_ctx* ctx, int64_t* h_tp, int32_t* h_planet, int64_t* 
   *h_n = total;
   if (total > cap || total > n) return GENGA_EOVERFLOW;
   return status_from_flags(hs.flags);
+}
+
+int genga_events(genga_ctx* ctx, genga_event* h_ev, int64_t cap, int64_t* h_n) {
+  if (!ctx || !h_n || cap < 0 || (cap > 0 && !h_ev) || ctx->mode != GENGA_BATCH)
+    return GENGA_EINVAL;
+  DevStat hs;
+  int r = read_status(ctx, &hs);
+  if (r != GENGA_OK) return r;
+  unsigned long long cnt = 0;
+  HIPCHK(hipMemcpyAsync(&cnt, ctx->b.ev_cnt, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  const int64_t have = std::min<int64_t>((int64_t)cnt, ctx->b.nb);
+  std::vector<genga_event> ev((size_t)have);
+  if (have > 0) {
+    HIPCHK(hipMemcpyAsync(ev.data(), ctx->b.ev, (size_t)have * sizeof(genga_event),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  std::sort(ev.begin(), ev.end(), [](const genga_event& a, const genga_event& b) {
+    if (a.step != b.step) return a.step < b.step;
+    if (a.sys != b.sys) return a.sys < b.sys;
+    if (a.frac != b.frac) return a.frac < b.frac;
+    return a.id_i < b.id_i;
+  });
+  for (int64_t k = 0; k < std::min(have, cap); ++k) h_ev[k] = ev[(size_t)k];
+  *h_n = (int64_t)cnt;
+  if ((int64_t)cnt > cap || (int64_t)cnt > have) return GENGA_EOVERFLOW;
+  return status_from_flags(hs.flags);
+}
+
+int genga_bodies(genga_ctx* ctx, int32_t* h_id, int64_t cap, int32_t* h_nlive, double* h_U,
+                 int sys_cap) {
+  if (!ctx || ctx->mode != GENGA_BATCH || cap < 0 || sys_cap < 0) return GENGA_EINVAL;
+  const BatchWs& b = ctx->b;
+  if ((cap > 0 && !h_id) || (sys_cap > 0 && (!h_nlive || !h_U))) return GENGA_EINVAL;
+  std::vector<BatchSysStat> ss((size_t)b.nsys);
+  std::vector<int32_t> ids((size_t)b.nb), off((size_t)b.nsys + 1);
+  HIPCHK(hipMemcpyAsync(ss.data(), b.ss, ss.size() * sizeof(BatchSysStat), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipMemcpyAsync(ids.data(), b.ids, ids.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipMemcpyAsync(off.data(), b.off, off.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int s = 0; s < b.nsys; ++s) {
+    for (int r = off[s]; r < off[s + 1]; ++r)
+      if (r < cap) h_id[r] = r - off[s] < ss[s].nlive ? ids[r] : -1;
+    if (s < sys_cap) {
+      h_nlive[s] = ss[s].nlive;
+      h_U[s] = ss[s].U;
+    }
+  }
+  return cap < b.nb || sys_cap < b.nsys ? GENGA_EOVERFLOW : GENGA_OK;
 }
 
 int genga_tune(genga_ctx* ctx, int nsteps, double* h_us, int cap, int* h_n, int* h_choice) {
@@ -811,9 +967,7 @@ size_t genga_accel_workspace_bytes(int n) {
   if (n < 1 || n > 65536) return 0;
   genga_params p;
   genga_params_default(&p);
-  p.cand_per_body = 1;
-  p.enc_cap = 1;
-  return massive_ws_bytes(n, p);
+  return massive_ws_bytes(n, accel_params(p));
 }
 
 int genga_accel(const genga_params* p, int n, const double* d_m, const double* d_x,
@@ -823,20 +977,11 @@ int genga_accel(const genga_params* p, int n, const double* d_m, const double* d
     return GENGA_EINVAL;
   if (!p->encounter_free && !d_rc) return GENGA_EINVAL;
   if (((uintptr_t)d_workspace & 255u) != 0) return GENGA_EINVAL;
-  genga_params q = *p;
-  q.cand_per_body = 1;
-  q.enc_cap = 1;
+  const genga_params q = accel_params(*p);
   if (ws_bytes < massive_ws_bytes(n, q)) return GENGA_ENOMEM;
   MassiveWs w;
   massive_carve(w, n, q, d_workspace);
-  StepConsts c = make_consts(q);
-  hipStream_t s = (hipStream_t)stream;
-  HIPCHK(massive_pack(w, c, d_m, d_x, d_x, GENGA_DEMOCRATIC, s));
-  HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStat), s));
-  if (!q.encounter_free)
-    HIPCHK(hipMemcpyAsync(w.rc_cur, d_rc, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIPCHK(thresholds_from_radii(w, c, s));
-  HIPCHK(massive_accel(w, c, d_acc, s));
+  HIPCHK(accel_run(w, make_consts(q), d_m, d_x, d_rc, d_acc, (hipStream_t)stream));
   return GENGA_OK;
 }
 

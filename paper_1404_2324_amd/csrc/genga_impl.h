@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/genga.h"
 
 namespace genga {
@@ -20,6 +22,7 @@ enum : unsigned {
   F_TP_OVF = 32u,      // more massive bodies than the test-particle mask holds
   F_ADJ_ENC = 64u,     // a pair inside r_crit during the encounter-free map
   F_SYS_STOP = 128u,   // batched: a system stopped after a failed step (warning)
+  F_NMIN = 256u,       // batched: a system stopped with fewer than nmin bodies
 };
 // control bits
 enum : unsigned { C_FULLKICK = 1u };
@@ -50,27 +53,25 @@ struct CollRec {
   double xv[6];        // the particle's democratic state there
 };
 
+constexpr int kKepBins = GENGA_KEPLER_BINS;  // Kepler-iteration histogram bins
 constexpr int kBsMaxGroup = 64;        // members per in-wave BS group
 constexpr int kGroupMaxN = 2048;       // bodies the one-workgroup grouping holds
 constexpr int kEncLds = 2048;          // encounter pairs grouped in LDS
-constexpr int kKickWaves = 8;          // waves per kick workgroup
-constexpr int kKickTarget = 512;       // kick workgroups aimed for (j-blocks x i-tiles)
-constexpr int kKickIpl = 1;            // i-bodies per lane in the kick
 constexpr int kVecBlock = 256;         // threads of the per-body kernels
 
 // Views into the caller's workspace for main mode (also the massive part of
 // test-particle mode).  Bodies are padded to np (a multiple of 256).
 struct MassiveWs {
-  int n, np, njb, jb_len, nitile, nblk;
+  int n, np, npair, nblk;          // npair: workgroups of the pair kernel
   int cpb;              // candidate slots per body
   int enc_cap;
   double4* xm;          // x, y, z, m          (democratic: heliocentric x)
   double4* vv;          // vx, vy, vz, 0       (barycentric v)
-  double4* xs;          // x, m at the start of the step, for the opening kick
+  double4* xs;          // x, m between steps (the closing kick's output; the
+                        // opening kick reads its partners here)
   double4* xpre;        // pre-drift x
   double4* vpre;        // pre-drift v
   double4* afar;        // acceleration of non-candidate pairs (x G)
-  double4* part;        // kick partials [njb][np][2]
   double* rc_cur;       // radii of the current step
   double* rc_next;      // radii for the next step
   double* thr;          // max((pf rc)^2, tiny): candidate threshold
@@ -80,6 +81,8 @@ struct MassiveWs {
   double* red;          // scratch for reductions (energy, conversions)
   int* ccnt;            // candidates per body
   int* ctab;            // candidate partners [np][cpb]
+  double* cr2;          // their squared separations [np][cpb]
+  unsigned long long* khist;  // Kepler iterations per block, cumulative [nblk][kKepBins]
   int2* encij;          // encounter pairs of the last step
   double* encd2;
   double* encrc2;
@@ -99,7 +102,11 @@ struct TpWs {
   double* v;            // [3][ntp]
   unsigned* mask;       // candidate planets per particle
   int* bs_idx;          // listed particles
-  unsigned* bs_mask;    // their encounter planets
+  unsigned* bs_mask;    // their encounter planets (cleared as they finish)
+  unsigned* bs_emask;   // the same, kept for the encounter report
+  double* enc_d2;       // Hermite minimum of each encounter [nm][ntp]
+  double* enc_rc2;      // its threshold r_crit,ij^2 [nm][ntp]
+  int nm;               // massive bodies (stride of enc_d2, enc_rc2)
   double* bs_rct;       // their critical radii
   double* bs_y;         // their pre-drift state [6][ntp]
   double* rad;          // physical radii: planets [32], then particles [ntp]
@@ -110,6 +117,7 @@ struct TpWs {
   int* blk_enc;         // encounters per block (this step)
   unsigned long long* blk_enc_tot;  // encounters per block since init
   int* blk_kit;         // largest Kepler iteration count per block
+  unsigned long long* khist;  // Kepler iterations per block, cumulative [nb][kKepBins]
   unsigned long long* sub;          // accepted BS substeps per workgroup / wave
   double* pl;           // planets' whole-step BS table
   int64_t* rq;          // listed entries left to the wave path (this step)
@@ -128,14 +136,26 @@ struct TpCounters {
   unsigned long long enc_total;  // since init
   int kit;                       // largest Kepler iteration count
   unsigned long long sub;        // accepted BS substeps since init
+  unsigned long long khist[kKepBins];  // Kepler iterations since init
 };
 
 struct StepConsts {
   double G, m0, mu, dt, h, n1, n2, pf, pf2, bs_tol;
   int bs_max_depth, kepler_max_iter, encounter_free;
+  // composed steps (Sec. 2.3): |dt| of the sub-step that follows (its
+  // critical radii are formed at the end of this one), and the encounter
+  // search over every pair instead of the prechecker's candidates
+  double absdt_next;
+  int all_pairs;
 };
 
+// Sub-steps of the composed step of the given order (2: one, 4: three, 6:
+// seven), their coefficients in w; 0 for an unsupported order.
+int composition(int order, double* w);
+
 StepConsts make_consts(const genga_params& p);
+// Finite parameters inside their documented ranges.
+bool params_valid(const genga_params* p);
 
 // ---- main-mode launchers (massive.hip) --------------------------------------
 size_t massive_ws_bytes(int n, const genga_params& p, bool snap = false);
@@ -151,22 +171,40 @@ hipError_t massive_unpack(const MassiveWs& w, const StepConsts& c, double* x,
 hipError_t massive_prime(const MassiveWs& w, const StepConsts& c,
                          hipStream_t s);
 // Kernels of one main-mode step in launch order: opening kick and drift,
-// encounter search, grouping, BS, pair kernel, kick finish (the middle three
-// only with encounters).  With kev (2 kStepKernels events), the events of
-// slot k take the start and end timestamps of kernel k's dispatch.
-constexpr int kStepKernels = 6;
+// encounter search, grouping, BS, pair kernel with the closing kick's
+// epilogue (the middle three only with encounters).  With kev (2
+// kStepKernels events), the events of slot k take the start and end
+// timestamps of kernel k's dispatch.
+constexpr int kStepKernels = 5;
 hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
                         const hipEvent_t* kev = nullptr);
 hipError_t massive_energy(const MassiveWs& w, const StepConsts& c, double* dE,
                           double* dL, hipStream_t s);
-hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, double* acc,
-                         hipStream_t s);
+// H_B acceleration of positions x (w = mass; x = xs for a context's state).
+hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, const double4* x,
+                         double* acc, hipStream_t s);
 hipError_t thresholds_from_radii(const MassiveWs& w, const StepConsts& c,
                                  hipStream_t s);
 hipError_t massive_masses(const MassiveWs& w, double* m, hipStream_t s);
+// H_B acceleration of n bodies given as caller arrays (m, x n x 3, rc or
+// null), on a carved context-free workspace: kernels only (no memset or
+// copy nodes), so that the sequence can be recorded into a HIP graph.
+hipError_t accel_run(const MassiveWs& w, const StepConsts& c, const double* m, const double* x,
+                     const double* rc, double* acc, hipStream_t s);
+// Parameters of the context-free acceleration (one candidate slot, one
+// encounter slot: the pair kernel keeps no lists in this form).
+genga_params accel_params(const genga_params& p);
 
 // ---- test-particle mode (tp.hip) --------------------------------------------
-size_t tp_carve(TpWs& t, int64_t ntp, void* base);
+size_t tp_carve(TpWs& t, int64_t ntp, int nm, void* base);
+// The last step's particle-planet encounters (particle, planet, d2, rc2),
+// unsorted (synchronising).
+struct TpEnc {
+  long long tp;
+  int planet;
+  double d2, rc2;
+};
+hipError_t tp_read_encounters(const TpWs& t, std::vector<TpEnc>* out, hipStream_t s);
 hipError_t tp_pack(const MassiveWs& w, const TpWs& t, const StepConsts& c,
                    const double* x, const double* v, int coords_in, hipStream_t s);
 hipError_t tp_unpack(const MassiveWs& w, const TpWs& t, const StepConsts& c,
@@ -195,7 +233,9 @@ struct BatchSysStat {
   int maxg;                      // largest group of the last step
   int kit;                       // largest Kepler iteration count
   unsigned flags;                // latched error bits of this system
-  int pad;
+  int nlive;                     // bodies left (mergers and ejections remove)
+  unsigned long long khist[kKepBins];  // Kepler iterations since init
+  double U;                      // internal energy of the system's mergers
 };
 
 struct BatchWs {
@@ -215,6 +255,17 @@ struct BatchWs {
   BatchSysStat* ss2;
   int* rslot;                      // [nsys] tableau slice of systems over 8 bodies
   double* rbuf;                    // [nbig] tableaux of the sequential BS
+  double* rad;                     // [nb] physical radii (0: no collisions)
+  double4* sp;                     // [nb] spins (x, y, z, 0)
+  int* ids;                        // [nb] original row of each body
+  double4* sp2;                    // the tuner's copies
+  int* ids2;
+  double* rad2;
+  genga_event* ev;                 // [nb] mergers and ejections since init
+  unsigned long long* ev_cnt;      // their count (also those beyond nb)
+  int coll;                        // some radius is positive
+  double rcut, rcut_sun;
+  int nmin;
   int nbig;
   int maxn;                        // largest system
   unsigned* flags2;
@@ -241,6 +292,9 @@ hipError_t batch_energy(const BatchWs& b, const StepConsts& c, double* E, double
 hipError_t batch_run(const BatchWs& b, const StepConsts& c, int variant, int nsteps,
                      bool scratch, hipStream_t s);
 hipError_t batch_copy_to_scratch(const BatchWs& b, hipStream_t s);
+// Bodies of every system present, original rows, zero spins and radii, no
+// events (init).
+hipError_t batch_reset_bodies(const BatchWs& b, hipStream_t s);
 const char* batch_variant_name(int v);
 // whether variant v can run these systems (two per wave needs sizes <= 32)
 bool batch_variant_ok(const BatchWs& b, int v);

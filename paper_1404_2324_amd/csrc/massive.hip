@@ -1,7 +1,7 @@
 // Main-mode kernels of the hybrid symplectic step (Grimm & Stadel,
 // arXiv:1404.2324, Sec. 2.2 step recipe and Sec. 3.2 kernels), for gfx950.
 //
-// One step is six launches on one stream (captured once into a HIP graph):
+// One step is five launches on one stream (captured once into a HIP graph):
 //   k_open_drift   opening kick: cached non-candidate acceleration + candidate
 //                  pairs recomputed with the new radii (KickA/KickB, Sec 3.2.3);
 //                  Sun kick tau/2 (Eq. 3) + pre-drift copy + Kepler drift
@@ -10,9 +10,10 @@
 //                  compaction of the confirmed pairs
 //   k_group        equivalence classes of the pairs in LDS (App. A)
 //   k_bs           Bulirsch-Stoer integration of H_A per group, one wave each
-//   k_kick         closing kick: all pairs and the prechecker, per j-block
-//   k_kick_finish  fixed-order sum of the partials, second Sun kick tau/2,
-//                  v += tau/2 a, next radii
+//   k_pairs        closing kick: all pairs and the prechecker, then per body
+//                  the second Sun kick tau/2, v += tau/2 a and the next radii
+// Between steps the positions live in xs (the closing kick's output); x
+// holds them while a step runs.
 #include <hip/hip_ext.h>
 
 #include <climits>
@@ -74,197 +75,206 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 }
 
 // ---------------------------------------------------------------------------
-struct KickArgs {
-  const double4* __restrict__ xm;     // read by the pair kernel
-  double4* __restrict__ xm_rw;        // same array, updated by the finish
-  double4* __restrict__ xs;           // start positions of the next step
-  const double* __restrict__ thr;
-  const double* __restrict__ rc;
-  double4* __restrict__ part;
-  int* __restrict__ ccnt;
+// The pair kernel: all pairs of H_B (the gradient of Eq. 2, Sec. 3.2.3) with
+// the prechecker (Sec. 2.2), and the per-body epilogue, in one launch.
+// Third word of a raw buffer resource on this target (no format conversion).
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kPairTile = 8;                               // i-bodies per workgroup
+constexpr int kPairWaves = 8;                              // waves per workgroup
+constexpr int kPairThreads = kPairWaves * 64;
+constexpr int kPairStreams = kPairThreads / kPairTile;     // j-streams (64)
+
+struct PairArgs {
+  const double* __restrict__ rc;      // radii of the step
+  int* __restrict__ ccnt;             // candidate table (appended)
   int* __restrict__ ctab;
+  double* __restrict__ cr2;
+  double4* __restrict__ xs;           // positions at the end of the step (out)
   double4* __restrict__ vv;
-  double4* __restrict__ afar;
+  double4* __restrict__ afar;         // non-candidate acceleration (x G), reused next step
   double* __restrict__ rc_next;
   double* __restrict__ acc_out;
   const double* __restrict__ partP2;  // momentum partials after the drift
   const double* __restrict__ dP;      // momentum change of each BS group
   DevStat* __restrict__ st;
-  int n, np, jb_len, cpb, nblk;
-  int encounter_free;
+  int n, np, cpb, nblk, encounter_free;
   double G, h, m0, mu, n1, n2, absdt, pf;
 };
 
 enum { KICK_CLOSE = 0, KICK_INIT = 1, KICK_ACC = 2 };
 
-// All-pairs kick of H_B (Eq. 2 gradient) with the prechecker.
-// Grid (ceil(n/64), njb); a workgroup holds 64 i-bodies (one per lane) and a
-// j-range split over its waves.  j-data is wave-uniform and read through the
-// scalar cache into SGPRs; the FP64 pair loop runs on the VALU.  Pairs with
-// r^2 < max((pf rc_i)^2, (pf rc_j)^2) are candidates: their K-weighted term is
-// summed apart ("near") and appended to the per-body candidate table; all
-// other pairs have K = 1 and form the reusable "far" sum.  Each workgroup
-// writes its j-block partials; k_kick_finish combines them in a fixed order
-// (a kernel boundary instead of a device-scope fence per workgroup, which
-// costs an L2 write-back on this multi-XCD part).
-// xm and thr come as kernel arguments of their own: as noalias parameters the
-// compiler can prove the wave-uniform j loads invariant and issue them as
-// scalar loads (struct members do not carry that guarantee).
+// Workgroup b owns bodies i = 8b .. 8b+7 and every partner j.  Lane l of
+// wave w serves body 8b + (l mod 8) and j-stream s = 8w + l/8, which takes
+// j = s, s + 64, s + 128, ...; the eight lanes of one j read the same
+// address (one request), adjacent streams adjacent bodies.  A pair with
+// r^2 < max((pf rc_i)^2, (pf rc_j)^2) is a candidate: its K-weighted term is
+// summed apart ("near") and appended to the body's candidate table; every
+// other pair has K = 1 and joins the "far" sum that the next opening kick
+// reuses (KickB).  The 64 streams of a body are added in LDS in a fixed
+// order, so results do not depend on timing.  Epilogue, one lane per body:
+//   CLOSE  second Sun kick (x += tau/2 P/m0, P from the drift's momentum
+//          partials and each BS group's change, added in the same order by
+//          every workgroup), v += tau/2 a, next radii (Eq. 6) and the reuse
+//          check.  The shifted positions go to xs, not back to x: other
+//          workgroups may still be reading x for their pairs.
+//   INIT   the far sum and xs = x (the first step's opening kick)
+//   ACC    the acceleration out
+// x and thr come as kernel arguments of their own (noalias) so that the
+// compiler may keep their loads free of the epilogue's stores.
 template <int MODE>
-__global__ __launch_bounds__(kKickWaves * 64) void k_kick(KickArgs a,
-                                                          const double4* __restrict__ xmj,
-                                                          const double* __restrict__ thrj) {
-  constexpr int W = kKickWaves;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int i = blockIdx.x * 64 + lane;
+__global__ __launch_bounds__(kPairThreads) void k_pairs(PairArgs a, const double4* __restrict__ x,
+                                                        const double* __restrict__ thr) {
+  __shared__ double red[6][kPairThreads];
+  __shared__ double red2[6][kPairTile][8];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int il = lane & (kPairTile - 1);
+  const int sj = wave * (64 / kPairTile) + lane / kPairTile;
+  const int i = blockIdx.x * kPairTile + il;
   const bool iv = i < a.n;
   double xi = 0.0, yi = 0.0, zi = 0.0, ti = kTiny;
   if (iv) {
-    const double4 p = a.xm[i];
+    const double4 p = x[i];
     xi = p.x;
     yi = p.y;
     zi = p.z;
-    ti = a.thr[i];
+    ti = thr[i];
   }
-  const int jb = blockIdx.y;
-  const int j0 = jb * a.jb_len;
-  const int j1 = min(a.n, j0 + a.jb_len);
-  const int wl = (max(0, j1 - j0) + W - 1) / W;
-  const int js = j0 + wave * wl;
-  const int je = min(j1, js + wl);
-
   double fx = 0.0, fy = 0.0, fz = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
+  // the series constants of m_rinv3 in registers for the whole loop (an
+  // empty asm statement hides their values, so that they are not re-made
+  // from literals for every pair)
+  double c1875 = 1.875, c15 = 1.5;
+  asm volatile("" : "+v"(c1875), "+v"(c15));
   auto pair = [&](const double4& pj, double tj, int j) {
     const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const double ir = rsqrt_nr(r2);
-    const double ir2 = ir * ir;
-    const double s = pj.w * (ir2 * ir);
-    const bool cand = r2 < fmax(ti, tj);
-    const double sf = cand ? 0.0 : s;
-    fx += sf * dx;
-    fy += sf * dy;
-    fz += sf * dz;
-    if (__builtin_expect(cand, 0)) {
-      if (iv && j != i) {
-        double K = 1.0, dK = 0.0;
-        if (!a.encounter_free) changeover(r2 * ir, fmax(a.rc[i], a.rc[j]), K, dK);
-        const double sn = pj.w * (K * ir2 * ir - dK * ir2);
-        nx += sn * dx;
-        ny += sn * dy;
-        nz += sn * dz;
-        if (MODE != KICK_ACC && !a.encounter_free) {
-          const int slot = atomicAdd(&a.ccnt[i], 1);
-          if (slot < a.cpb)
-            a.ctab[(size_t)i * a.cpb + slot] = j;
-          else
-            atomicOr(&a.st->flags, F_CAND_OVF);
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double s = m_rinv3(pj.w, r2, c1875, c15);
+    // r2 < max(ti, tj) as two compares; the second is written as the
+    // unordered form (the same for the finite values here) so that the
+    // code generator does not fuse them into a maximum, which costs three
+    // instructions on this target
+    const bool cand = (r2 < ti) | !(r2 >= tj);
+    if (__builtin_expect(!cand, 1)) {
+      fx = fma(s, dx, fx);
+      fy = fma(s, dy, fy);
+      fz = fma(s, dz, fz);
+    } else if (iv && j != i && j < a.n) {
+      const double ir = rsqrt_nr(r2);
+      const double ir2 = ir * ir;
+      double K = 1.0, dK = 0.0;
+      if (!a.encounter_free) changeover(r2 * ir, fmax(a.rc[i], a.rc[j]), K, dK);
+      const double sn = pj.w * (K * ir2 * ir - dK * ir2);
+      nx += sn * dx;
+      ny += sn * dy;
+      nz += sn * dz;
+      if (MODE != KICK_ACC && !a.encounter_free) {
+        const int slot = atomicAdd(&a.ccnt[i], 1);
+        if (slot < a.cpb) {
+          a.ctab[(size_t)i * a.cpb + slot] = j;
+          a.cr2[(size_t)i * a.cpb + slot] = r2;
+        } else {
+          atomicOr(&a.st->flags, F_CAND_OVF);
         }
       }
     }
   };
-  // four partners per round trip of the scalar loads (the scalar cache
-  // returns out of order, so every use waits for all loads in flight)
-  int j = js;
-  for (; j + 3 < je; j += 4) {
-    const double4 p0 = xmj[j], p1 = xmj[j + 1], p2 = xmj[j + 2], p3 = xmj[j + 3];
-    const double t0 = thrj[j], t1 = thrj[j + 1], t2 = thrj[j + 2], t3 = thrj[j + 3];
-    pair(p0, t0, j);
-    pair(p1, t1, j + 1);
-    pair(p2, t2, j + 2);
-    pair(p3, t3, j + 3);
+  // Every lane takes the same number of partners: the bodies are padded to a
+  // multiple of 256 with zero mass at the origin (their terms are exact
+  // zeros), so j runs over np.  Partners come in batches of four per lane
+  // (j = sj + 64 (4b + u)); while one batch is summed the next one is in
+  // flight, alternating between two register buffers.  Loads are raw buffer
+  // loads: the lane's fixed offset in a VGPR, the batch offset in an SGPR,
+  // so the addressing costs no vector instructions.
+  constexpr int U = 4, S = kPairStreams;
+  const int nb = a.np / (U * S);
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double4*>(x), (short)0, a.np * (int)sizeof(double4), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(thr), (short)0, a.np * (int)sizeof(double), kBufferWord3);
+  const unsigned lo4 = (unsigned)sj * sizeof(double4), lo1 = (unsigned)sj * sizeof(double);
+  auto load = [&](int b, double4 (&p)[U], double (&t)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ox = (U * b + u) * S * (int)sizeof(double4);
+      const int ot = (U * b + u) * S * (int)sizeof(double);
+      const double2 lo = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rx, lo4, ox, 0));
+      const double2 hi = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rx, lo4 + 16u, ox, 0));
+      p[u] = make_double4(lo.x, lo.y, hi.x, hi.y);
+      t[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rt, lo1, ot, 0));
+    }
+  };
+  auto sum = [&](int b, const double4 (&p)[U], const double (&t)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) pair(p[u], t[u], sj + S * (U * b + u));
+  };
+  double4 pa[U], pb[U];
+  double ta[U], tb[U];
+  load(0, pa, ta);
+  for (int b = 0; b < nb; b += 2) {
+    if (b + 1 < nb) load(b + 1, pb, tb);
+    sum(b, pa, ta);
+    if (b + 1 >= nb) break;
+    if (b + 2 < nb) load(b + 2, pa, ta);
+    sum(b + 1, pb, tb);
   }
-  for (; j < je; ++j) pair(xmj[j], thrj[j], j);
 
-  if (MODE == KICK_CLOSE && blockIdx.x == 0 && blockIdx.y == 0 && wave == 0) {
-    // momentum after the drift and BS for the second Sun kick: drift partials
-    // plus each group's change, strided over the lanes, then a butterfly
-    double px = 0.0, py = 0.0, pz = 0.0;
+  // fixed-order sum over the 64 streams: eight groups of eight, then the
+  // groups
+  red[0][tid] = fx;
+  red[1][tid] = fy;
+  red[2][tid] = fz;
+  red[3][tid] = nx;
+  red[4][tid] = ny;
+  red[5][tid] = nz;
+  __syncthreads();
+  if (tid < 6 * kPairTile * 8) {
+    const int c = tid >> 6, b = (tid >> 3) & 7, q = tid & 7;
+    // streams 8q .. 8q+7 of body b: threads 64q + 8u + b
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t += red[c][64 * q + 8 * u + b];
+    red2[c][b][q] = t;
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  double Px = 0.0, Py = 0.0, Pz = 0.0;
+  if (MODE == KICK_CLOSE) {
+    // momentum after the drift and BS for the second Sun kick: drift
+    // partials plus each group's change, strided over the lanes, then a
+    // butterfly (every workgroup adds the same terms in the same order)
     for (int b = lane; b < a.nblk; b += 64) {
-      px += a.partP2[4 * b + 0];
-      py += a.partP2[4 * b + 1];
-      pz += a.partP2[4 * b + 2];
+      Px += a.partP2[4 * b + 0];
+      Py += a.partP2[4 * b + 1];
+      Pz += a.partP2[4 * b + 2];
     }
     const int ng = a.encounter_free ? 0 : a.st->ngroups;
     for (int g = lane; g < ng; g += 64) {
-      px += a.dP[4 * g + 0];
-      py += a.dP[4 * g + 1];
-      pz += a.dP[4 * g + 2];
+      Px += a.dP[4 * g + 0];
+      Py += a.dP[4 * g + 1];
+      Pz += a.dP[4 * g + 2];
     }
-    px = wave_sum(px);
-    py = wave_sum(py);
-    pz = wave_sum(pz);
-    if (lane == 0) {
-      a.st->P2[0] = px;
-      a.st->P2[1] = py;
-      a.st->P2[2] = pz;
-      a.st->ctl = 0u;  // the finish sets the bits for the next opening kick
+    Px = wave_sum(Px);
+    Py = wave_sum(Py);
+    Pz = wave_sum(Pz);
+    if (blockIdx.x == 0 && lane == 0) {
+      a.st->P2[0] = Px;
+      a.st->P2[1] = Py;
+      a.st->P2[2] = Pz;
     }
   }
-  if (MODE == KICK_INIT && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
-    a.st->ctl = 0u;
-  __shared__ double sh[W][6][64];
-  sh[wave][0][lane] = fx;
-  sh[wave][1][lane] = fy;
-  sh[wave][2][lane] = fz;
-  sh[wave][3][lane] = nx;
-  sh[wave][4][lane] = ny;
-  sh[wave][5][lane] = nz;
-  __syncthreads();
-  for (int c = threadIdx.x >> 6; c < 6; c += W) {
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) t += sh[w][c][lane];
-    sh[0][c][lane] = t;
-  }
-  __syncthreads();
-  if (threadIdx.x < 64 && iv) {
-    double4* q = &a.part[((size_t)jb * a.np + i) * 2];
-    q[0] = make_double4(sh[0][0][lane], sh[0][1][lane], sh[0][2][lane], 0.0);
-    q[1] = make_double4(sh[0][3][lane], sh[0][4][lane], sh[0][5][lane], 0.0);
-  }
-}
-
-// Closing-kick epilogue, four lanes per body: the j-block partials are summed
-// in a fixed order (strided per lane, then a butterfly over the four lanes);
-// the far part is kept for the next opening kick.
-//   CLOSE: second Sun kick of the step (x += tau/2 P/m0 with P assembled by
-//          the pair kernel from the drift's momentum partials and each BS
-//          group's momentum change; the pair kernel only needs relative
-//          positions, so the shift can follow it), v += tau/2 a, next radii
-//          (Eq. 6) and the reuse check
-//   INIT:  far part only (first step's opening kick)
-//   ACC:   acceleration out
-template <int MODE>
-__global__ __launch_bounds__(kVecBlock) void k_kick_finish(KickArgs a, int njb) {
-  const int t = blockIdx.x * kVecBlock + threadIdx.x;
-  const int i = t >> 2, sub = t & 3;
-  const bool iv = i < a.n;
+  if (MODE == KICK_INIT && blockIdx.x == 0 && lane == 0) a.st->ctl = 0u;
+  if (lane >= kPairTile || !iv) return;
   double S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0;
-  if (iv) {
-    for (int b = sub; b < njb; b += 4) {
-      const double4* q = &a.part[((size_t)b * a.np + i) * 2];
-      const double4 f = q[0];
-      const double4 g = q[1];
-      S0 += f.x;
-      S1 += f.y;
-      S2 += f.z;
-      S3 += g.x;
-      S4 += g.y;
-      S5 += g.z;
-    }
-  }
 #pragma unroll
-  for (int o = 1; o < 4; o <<= 1) {
-    S0 += __shfl_xor(S0, o, 64);
-    S1 += __shfl_xor(S1, o, 64);
-    S2 += __shfl_xor(S2, o, 64);
-    S3 += __shfl_xor(S3, o, 64);
-    S4 += __shfl_xor(S4, o, 64);
-    S5 += __shfl_xor(S5, o, 64);
+  for (int q = 0; q < 8; ++q) {
+    S0 += red2[0][lane][q];
+    S1 += red2[1][lane][q];
+    S2 += red2[2][lane][q];
+    S3 += red2[3][lane][q];
+    S4 += red2[4][lane][q];
+    S5 += red2[5][lane][q];
   }
-  if (!iv || sub != 0) return;
   const double G = a.G;
   if (MODE == KICK_ACC) {
     a.acc_out[3 * (size_t)i + 0] = G * (S0 + S3);
@@ -273,17 +283,15 @@ __global__ __launch_bounds__(kVecBlock) void k_kick_finish(KickArgs a, int njb) 
     return;
   }
   a.afar[i] = make_double4(G * S0, G * S1, G * S2, 0.0);
+  double4 p = x[i];
   if (MODE == KICK_INIT) {
     a.rc_next[i] = a.rc[i];
-    a.xs[i] = a.xm_rw[i];
+    a.xs[i] = p;
     return;
   }
-  const double Px = a.st->P2[0], Py = a.st->P2[1], Pz = a.st->P2[2];
-  double4 p = a.xm_rw[i];
   p.x += a.h * Px / a.m0;
   p.y += a.h * Py / a.m0;
   p.z += a.h * Pz / a.m0;
-  a.xm_rw[i] = p;
   a.xs[i] = p;
   double4 v = a.vv[i];
   v.x += a.h * (G * (S0 + S3));
@@ -314,6 +322,7 @@ struct OpenArgs {
   const int* __restrict__ ctab;
   double* __restrict__ partP;
   double* __restrict__ partP2;
+  unsigned long long* __restrict__ khist;
   DevStat* __restrict__ st;
   int n, cpb, encounter_free, max_iter;
   double G, h, pf2, m0, mu, dt;
@@ -391,6 +400,9 @@ __device__ __forceinline__ void sum_partners(const int (&jj)[N], int c0, int cnt
 // after the drift, and resets the step's encounter counters.
 __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
   __shared__ double sh[3 * (kVecBlock / 64)];
+  __shared__ unsigned kh[kKepBins];  // this block's drifts by iteration count
+  if (threadIdx.x < kKepBins) kh[threadIdx.x] = 0u;
+  __syncthreads();
   const int i = blockIdx.x * kVecBlock + threadIdx.x;
   const bool iv = i < a.n;
   const bool full = (__builtin_amdgcn_readfirstlane(a.st->ctl) & C_FULLKICK) != 0;
@@ -477,6 +489,7 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
     dz = v.z;
     it = kepler_drift(a.mu, a.dt, x, y, z, dx, dy, dz, a.max_iter);
     if (it < 0) atomicOr(&a.st->flags, F_KEPLER);
+    atomicAdd(&kh[min(abs(it), kKepBins - 1)], 1u);
     a.xm[i] = make_double4(x, y, z, p.w);
     a.vv[i] = make_double4(dx, dy, dz, 0.0);
     if (a.xpost) {
@@ -491,7 +504,9 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
   double Px = m * kx, Py = m * ky, Pz = m * kz;
   block_sum3<kVecBlock>(Px, Py, Pz, sh);
   double Qx = m * dx, Qy = m * dy, Qz = m * dz;
-  block_sum3<kVecBlock>(Qx, Qy, Qz, sh);
+  block_sum3<kVecBlock>(Qx, Qy, Qz, sh);  // its barriers also order kh
+  if (threadIdx.x < kKepBins)
+    a.khist[(size_t)blockIdx.x * kKepBins + threadIdx.x] += kh[threadIdx.x];
   if (threadIdx.x == 0) {
     a.partP[4 * blockIdx.x + 0] = Px;
     a.partP[4 * blockIdx.x + 1] = Py;
@@ -593,6 +608,85 @@ __global__ __launch_bounds__(kVecBlock) void k_encounter(EncArgs a) {
   }
 }
 
+// Encounter search over every pair i < j (the composed steps, Sec. 2.3: no
+// prechecker).  Workgroup (ti, tj), tj >= ti, takes i in tile ti and j in
+// tile tj (64 bodies each); the j tile's states before and after the drift
+// and radii sit in LDS; lane l serves i = 64 ti + l over the 16 partners of
+// its quarter, and confirmed pairs are appended as in k_encounter.
+constexpr int kEncTile = 64;
+__global__ __launch_bounds__(256) void k_encounter_all(EncArgs a) {
+  __shared__ double sj[13][kEncTile];
+  const int ti = blockIdx.x, tj = blockIdx.y;
+  if (tj < ti) return;  // upper triangle of tiles (uniform over the workgroup)
+  const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
+  if (tid < kEncTile) {
+    const int j = tj * kEncTile + tid;
+    double4 p0 = make_double4(0, 0, 0, 0), v0 = p0, p1 = p0, v1 = p0;
+    double rc = 0.0;
+    if (j < a.n) {
+      p0 = a.xpre[j];
+      v0 = a.vpre[j];
+      p1 = a.xm[j];
+      v1 = a.vv[j];
+      rc = a.rc[j];
+    }
+    sj[0][tid] = p0.x;
+    sj[1][tid] = p0.y;
+    sj[2][tid] = p0.z;
+    sj[3][tid] = v0.x;
+    sj[4][tid] = v0.y;
+    sj[5][tid] = v0.z;
+    sj[6][tid] = p1.x;
+    sj[7][tid] = p1.y;
+    sj[8][tid] = p1.z;
+    sj[9][tid] = v1.x;
+    sj[10][tid] = v1.y;
+    sj[11][tid] = v1.z;
+    sj[12][tid] = rc;
+  }
+  __syncthreads();
+  const int i = ti * kEncTile + lane;
+  const bool iv = i < a.n;
+  double4 xi0 = make_double4(0, 0, 0, 0), vi0 = xi0, xi1 = xi0, vi1 = xi0;
+  double rci = 0.0;
+  if (iv) {
+    xi0 = a.xpre[i];
+    vi0 = a.vpre[i];
+    xi1 = a.xm[i];
+    vi1 = a.vv[i];
+    rci = a.rc[i];
+  }
+  for (int t = 0; t < kEncTile / 4; ++t) {
+    const int k = q * (kEncTile / 4) + t;
+    const int j = tj * kEncTile + k;
+    bool enc = false;
+    double d2 = 0.0, rc2 = 0.0;
+    if (iv && j < a.n && j > i) {
+      d2 = hermite_dmin2(a.dt, sj[0][k] - xi0.x, sj[1][k] - xi0.y, sj[2][k] - xi0.z,
+                         sj[3][k] - vi0.x, sj[4][k] - vi0.y, sj[5][k] - vi0.z,
+                         sj[6][k] - xi1.x, sj[7][k] - xi1.y, sj[8][k] - xi1.z,
+                         sj[9][k] - vi1.x, sj[10][k] - vi1.y, sj[11][k] - vi1.z);
+      const double rcij = fmax(rci, sj[12][k]);
+      rc2 = rcij * rcij;
+      enc = d2 < rc2;
+    }
+    const unsigned long long msk = __ballot(enc);
+    if (msk) {
+      int b0 = 0;
+      if (lane == 0) b0 = atomicAdd(&a.st->nenc, __popcll(msk));
+      b0 = __shfl(b0, 0, 64);
+      if (enc) {
+        const int pos = b0 + (int)lanemask_count(msk);
+        if (pos < a.enc_cap) {
+          a.encij[pos] = make_int2(i, j);
+          a.encd2[pos] = d2;
+          a.encrc2[pos] = rc2;
+        }
+      }
+    }
+  }
+}
+
 // Equivalence classes of the encounter pairs (App. A), one workgroup: LINK
 // starts as the identity, every pair lowers both ends to the smaller link
 // (LDS atomic min), links are shortened by LINK[i] = LINK[LINK[i]], and both
@@ -612,6 +706,9 @@ __global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
   const int n = a.n;
   const int ne_all = a.st->nenc;
   const int ne = min(min(ne_all, kEncLds), a.enc_cap);
+  // the opening kick has read the reuse flag; this step's closing kick sets
+  // it again for the next one
+  if (tid == 0) a.st->ctl = 0u;
   for (int i = tid; i < n; i += kEncThreads) {
     link[i] = i;
     inp[i] = 0;
@@ -902,15 +999,18 @@ __global__ __launch_bounds__(1024) void k_momentum(const double* __restrict__ m,
 }
 
 // Heliocentric velocities become barycentric: v = u - sum m u / (m0 + sum m).
+// Rows n..np-1 (padding) become massless bodies at the origin in x and xs:
+// the pair kernel runs over them and their terms are exact zeros.
 __global__ void k_pack(const double* __restrict__ m, const double* __restrict__ x,
                        const double* __restrict__ v, const double* __restrict__ mom,
-                       double4* __restrict__ xm, double4* __restrict__ vv, int n,
-                       int np, int helio, double m0) {
+                       double4* __restrict__ xm, double4* __restrict__ vv,
+                       double4* __restrict__ xs, int n, int np, int helio, double m0) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= np) return;
   if (i >= n) {
     xm[i] = make_double4(0.0, 0.0, 0.0, 0.0);
     vv[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+    xs[i] = make_double4(0.0, 0.0, 0.0, 0.0);
     return;
   }
   double sx = 0.0, sy = 0.0, sz = 0.0;
@@ -951,8 +1051,11 @@ __global__ void k_rcrit_init(const double4* __restrict__ xm, const double4* __re
                              int* __restrict__ ccnt, int n, double mu, double m0,
                              double n1, double n2, double absdt, double pf2,
                              int enc_free) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // grid: the padded count
+  if (i >= n) {
+    thr[i] = kTiny;
+    return;
+  }
   const double4 p = xm[i], q = vv[i];
   const double r = rcrit(p.x, p.y, p.z, q.x, q.y, q.z, p.w, mu, m0, n1, n2, absdt);
   rc[i] = r;
@@ -1011,9 +1114,28 @@ __global__ __launch_bounds__(256) void k_energy_final(const double* __restrict__
 // Candidate thresholds from given radii: max((pf rc)^2, tiny).
 __global__ void k_thresholds(const double* __restrict__ rc, double* __restrict__ thr,
                              int* __restrict__ ccnt, int n, double pf2, int enc_free) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // grid: the padded count
+  if (i >= n) {
+    thr[i] = kTiny;
+    return;
+  }
   thr[i] = enc_free ? kTiny : fmax(pf2 * rc[i] * rc[i], kTiny);
+  ccnt[i] = 0;
+}
+
+// Radii given by the caller: installed with their thresholds (zero and the
+// smallest threshold when rc_in is null, the K = 1 map).
+__global__ void k_radii_in(const double* __restrict__ rc_in, double* __restrict__ rc,
+                           double* __restrict__ thr, int* __restrict__ ccnt, int n, double pf2,
+                           int enc_free) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // grid: the padded count
+  if (i >= n) {
+    thr[i] = kTiny;
+    return;
+  }
+  const double r = rc_in ? rc_in[i] : 0.0;
+  rc[i] = r;
+  thr[i] = enc_free ? kTiny : fmax(pf2 * r * r, kTiny);
   ccnt[i] = 0;
 }
 
@@ -1029,16 +1151,13 @@ __global__ void k_validate(const double* __restrict__ a, int64_t cnt, int* __res
   if (i < cnt && !isfinite(a[i])) atomicOr(bad, 1);
 }
 
-KickArgs kick_args(const MassiveWs& w, const StepConsts& c) {
-  KickArgs a;
-  a.xm = w.xm;
-  a.xm_rw = w.xm;
-  a.xs = w.xs;
-  a.thr = w.thr;
+PairArgs pair_args(const MassiveWs& w, const StepConsts& c) {
+  PairArgs a;
   a.rc = w.rc_cur;
-  a.part = w.part;
   a.ccnt = w.ccnt;
   a.ctab = w.ctab;
+  a.cr2 = w.cr2;
+  a.xs = w.xs;
   a.vv = w.vv;
   a.afar = w.afar;
   a.rc_next = w.rc_next;
@@ -1048,7 +1167,6 @@ KickArgs kick_args(const MassiveWs& w, const StepConsts& c) {
   a.st = w.st;
   a.n = w.n;
   a.np = w.np;
-  a.jb_len = w.jb_len;
   a.cpb = w.cpb;
   a.nblk = w.nblk;
   a.encounter_free = c.encounter_free;
@@ -1058,7 +1176,7 @@ KickArgs kick_args(const MassiveWs& w, const StepConsts& c) {
   a.mu = c.mu;
   a.n1 = c.n1;
   a.n2 = c.n2;
-  a.absdt = fabs(c.dt);
+  a.absdt = c.absdt_next;  // the next (sub-)step's radii are formed here
   a.pf = c.pf;
   return a;
 }
@@ -1081,16 +1199,39 @@ StepConsts make_consts(const genga_params& p) {
   c.bs_max_depth = p.bs_max_depth;
   c.kepler_max_iter = p.kepler_max_iter;
   c.encounter_free = p.encounter_free;
+  c.absdt_next = fabs(p.dt);
+  c.all_pairs = 0;
   return c;
 }
 
-static void kick_shape(int n, int& nitile, int& njb, int& jb_len) {
-  nitile = ceil_div(n, 64);
-  const int by_target = ceil_div(kKickTarget, nitile);
-  const int by_len = ceil_div(n, kKickWaves * 16);
-  njb = std::max(1, std::min(by_target, by_len));
-  jb_len = ceil_div(n, njb);
-  njb = ceil_div(n, jb_len);
+// Yoshida's symmetric compositions (fourth order; sixth order, his solution
+// A), the coefficients as published.
+int composition(int order, double* w) {
+  if (order == 0 || order == 2) {
+    w[0] = 1.0;
+    return 1;
+  }
+  if (order == 4) {
+    const double c = cbrt(2.0);
+    w[0] = w[2] = 1.0 / (2.0 - c);
+    w[1] = 1.0 - 2.0 * w[0];
+    return 3;
+  }
+  if (order == 6) {
+    const double w1 = -1.17767998417887, w2 = 0.235573213359357, w3 = 0.784513610477560;
+    const double w0 = 1.0 - 2.0 * (w1 + w2 + w3);
+    const double q[7] = {w3, w2, w1, w0, w1, w2, w3};
+    for (int k = 0; k < 7; ++k) w[k] = q[k];
+    return 7;
+  }
+  return 0;
+}
+
+genga_params accel_params(const genga_params& p) {
+  genga_params q = p;
+  q.cand_per_body = 1;
+  q.enc_cap = 1;
+  return q;
 }
 
 size_t massive_ws_bytes(int n, const genga_params& p, bool snap) {
@@ -1104,7 +1245,7 @@ size_t massive_ws_bytes(int n, const genga_params& p, bool snap) {
 size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base, bool snap) {
   w.n = n;
   w.np = ceil_div(n, 256) * 256;
-  kick_shape(n, w.nitile, w.njb, w.jb_len);
+  w.npair = ceil_div(n, kPairTile);
   w.nblk = ceil_div(n, kVecBlock);
   w.cpb = p.cand_per_body;
   w.enc_cap = p.enc_cap;
@@ -1121,7 +1262,6 @@ size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base, boo
   w.xpre = (double4*)take(np * sizeof(double4));
   w.vpre = (double4*)take(np * sizeof(double4));
   w.afar = (double4*)take(np * sizeof(double4));
-  w.part = (double4*)take((size_t)w.njb * np * 2 * sizeof(double4));
   w.rc_cur = (double*)take(np * sizeof(double));
   w.rc_next = (double*)take(np * sizeof(double));
   w.thr = (double*)take(np * sizeof(double));
@@ -1131,6 +1271,8 @@ size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base, boo
   w.red = (double*)take(std::max<size_t>(np * 9, 64) * sizeof(double));
   w.ccnt = (int*)take(np * sizeof(int));
   w.ctab = (int*)take(np * (size_t)std::max(1, w.cpb) * sizeof(int));
+  w.cr2 = (double*)take(np * (size_t)std::max(1, w.cpb) * sizeof(double));
+  w.khist = (unsigned long long*)take((size_t)w.nblk * kKepBins * sizeof(unsigned long long));
   w.encij = (int2*)take((size_t)std::max(1, w.enc_cap) * sizeof(int2));
   w.encd2 = (double*)take((size_t)std::max(1, w.enc_cap) * sizeof(double));
   w.encrc2 = (double*)take((size_t)std::max(1, w.enc_cap) * sizeof(double));
@@ -1150,7 +1292,7 @@ hipError_t massive_pack(const MassiveWs& w, const StepConsts& c, const double* m
   const int helio = coords_in == GENGA_HELIO;
   if (helio) hipLaunchKernelGGL(k_momentum, dim3(1), dim3(1024), 0, s, m, v, nullptr, nullptr, w.n, w.red);
   hipLaunchKernelGGL(k_pack, dim3(ceil_div(w.np, 256)), dim3(256), 0, s, m, x, v, w.red,
-                     w.xm, w.vv, w.n, w.np, helio, c.m0);
+                     w.xm, w.vv, w.xs, w.n, w.np, helio, c.m0);
   return hipGetLastError();
 }
 
@@ -1158,8 +1300,8 @@ hipError_t massive_unpack(const MassiveWs& w, const StepConsts& c, double* x,
                           double* v, int coords_out, hipStream_t s) {
   const int helio = coords_out == GENGA_HELIO;
   if (helio)
-    hipLaunchKernelGGL(k_momentum, dim3(1), dim3(1024), 0, s, nullptr, nullptr, w.xm, w.vv, w.n, w.red);
-  hipLaunchKernelGGL(k_unpack, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xm, w.vv, w.red,
+    hipLaunchKernelGGL(k_momentum, dim3(1), dim3(1024), 0, s, nullptr, nullptr, w.xs, w.vv, w.n, w.red);
+  hipLaunchKernelGGL(k_unpack, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xs, w.vv, w.red,
                      x, v, w.n, helio, c.m0);
   return hipGetLastError();
 }
@@ -1168,23 +1310,21 @@ hipError_t massive_prime(const MassiveWs& w, const StepConsts& c, hipStream_t s)
   hipLaunchKernelGGL(k_rcrit_init, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xm, w.vv,
                      w.rc_cur, w.thr, w.ccnt, w.n, c.mu, c.m0, c.n1, c.n2, fabs(c.dt),
                      c.pf2, c.encounter_free);
-  KickArgs a = kick_args(w, c);
-  hipLaunchKernelGGL(k_kick<KICK_INIT>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a,
-                     a.xm, a.thr);
-  hipLaunchKernelGGL(k_kick_finish<KICK_INIT>, dim3(ceil_div(4 * w.n, kVecBlock)), dim3(kVecBlock), 0, s, a, w.njb);
+  PairArgs a = pair_args(w, c);
+  hipLaunchKernelGGL(k_pairs<KICK_INIT>, dim3(w.npair), dim3(kPairThreads), 0, s, a,
+                     (const double4*)w.xm, (const double*)w.thr);
   // the momentum for the first step's first Sun kick
   double* P2 = reinterpret_cast<double*>(reinterpret_cast<char*>(w.st) + offsetof(DevStat, P2));
   hipLaunchKernelGGL(k_momentum, dim3(1), dim3(1024), 0, s, nullptr, nullptr, w.xm, w.vv, w.n, P2);
   return hipGetLastError();
 }
 
-hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, double* acc,
-                         hipStream_t s) {
-  KickArgs a = kick_args(w, c);
+hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, const double4* x,
+                         double* acc, hipStream_t s) {
+  PairArgs a = pair_args(w, c);
   a.acc_out = acc;
-  hipLaunchKernelGGL(k_kick<KICK_ACC>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), 0, s, a,
-                     a.xm, a.thr);
-  hipLaunchKernelGGL(k_kick_finish<KICK_ACC>, dim3(ceil_div(4 * w.n, kVecBlock)), dim3(kVecBlock), 0, s, a, w.njb);
+  hipLaunchKernelGGL(k_pairs<KICK_ACC>, dim3(w.npair), dim3(kPairThreads), 0, s, a, x,
+                     (const double*)w.thr);
   return hipGetLastError();
 }
 
@@ -1218,6 +1358,7 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
   o.ctab = w.ctab;
   o.partP = w.partP;
   o.partP2 = w.partP2;
+  o.khist = w.khist;
   o.st = w.st;
   o.n = w.n;
   o.cpb = w.cpb;
@@ -1250,7 +1391,12 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
     e.cpb = w.cpb;
     e.enc_cap = w.enc_cap;
     e.dt = c.dt;
-    STEP_LAUNCH(1, k_encounter, dim3(ceil_div(w.n * w.cpb, kVecBlock)), dim3(kVecBlock), e);
+    if (c.all_pairs) {
+      const int nt = ceil_div(w.n, kEncTile);
+      STEP_LAUNCH(1, k_encounter_all, dim3(nt, nt), dim3(256), e);
+    } else {
+      STEP_LAUNCH(1, k_encounter, dim3(ceil_div(w.n * w.cpb, kVecBlock)), dim3(kVecBlock), e);
+    }
     STEP_LAUNCH(2, k_group, dim3(1), dim3(kEncThreads), e);
 
     BsArgs b;
@@ -1271,17 +1417,15 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
     STEP_LAUNCH(3, k_bs, dim3(std::max(1, std::min(256, w.n / 2))), dim3(64), b);
   }
 
-  KickArgs a = kick_args(w, c);
-  STEP_LAUNCH(4, k_kick<KICK_CLOSE>, dim3(w.nitile, w.njb), dim3(kKickWaves * 64), a,
-              (const double4*)a.xm, (const double*)a.thr);
-  STEP_LAUNCH(5, k_kick_finish<KICK_CLOSE>, dim3(ceil_div(4 * w.n, kVecBlock)), dim3(kVecBlock),
-              a, w.njb);
+  PairArgs a = pair_args(w, c);
+  STEP_LAUNCH(4, k_pairs<KICK_CLOSE>, dim3(w.npair), dim3(kPairThreads), a, (const double4*)w.xm,
+              (const double*)w.thr);
   return hipGetLastError();
 }
 
 hipError_t massive_energy(const MassiveWs& w, const StepConsts& c, double* dE,
                           double* dL, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy_rows, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xm, w.vv,
+  hipLaunchKernelGGL(k_energy_rows, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xs, w.vv,
                      w.n, c.G, c.m0, w.red);
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, w.red, w.n, c.m0, dE, dL);
   return hipGetLastError();
@@ -1299,8 +1443,18 @@ hipError_t thresholds_from_radii(const MassiveWs& w, const StepConsts& c, hipStr
   return hipGetLastError();
 }
 
+hipError_t accel_run(const MassiveWs& w, const StepConsts& c, const double* m, const double* x,
+                     const double* rc, double* acc, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(ceil_div(w.np, 256)), dim3(256), 0, s, m, x, x,
+                     (const double*)nullptr, w.xm, w.vv, w.xs, w.n, w.np, 0, c.m0);
+  hipLaunchKernelGGL(k_radii_in, dim3(ceil_div(w.n, 256)), dim3(256), 0, s,
+                     c.encounter_free ? nullptr : rc, w.rc_cur, w.thr, w.ccnt, w.n, c.pf2,
+                     c.encounter_free);
+  return massive_accel(w, c, w.xm, acc, s);
+}
+
 hipError_t massive_masses(const MassiveWs& w, double* m, hipStream_t s) {
-  hipLaunchKernelGGL(k_masses, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xm, m, w.n);
+  hipLaunchKernelGGL(k_masses, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xs, m, w.n);
   return hipGetLastError();
 }
 

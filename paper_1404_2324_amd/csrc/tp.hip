@@ -58,6 +58,9 @@ struct TpArgs {
   DevStat* __restrict__ st;
   int* __restrict__ bs_idx;           // listed particles
   unsigned* __restrict__ bs_mask;     // their encounter planets
+  unsigned* __restrict__ bs_emask;    // the same, kept for the encounter report
+  double* __restrict__ enc_d2;        // Hermite minimum per encounter [nm][ntp]
+  double* __restrict__ enc_rc2;       // its threshold [nm][ntp]
   double* __restrict__ bs_rct;        // their radii
   double* __restrict__ bs_y;          // their pre-drift state [6][cap]
   const double* __restrict__ rad;     // radii: planets [32], particles [ntp]
@@ -67,6 +70,7 @@ struct TpArgs {
   int* __restrict__ blk_enc;          // encounters of each block, last step
   unsigned long long* __restrict__ blk_enc_tot;
   int* __restrict__ blk_kit;          // largest Kepler iteration count per block
+  unsigned long long* __restrict__ khist;  // Kepler iterations per block [nb][bins]
   unsigned long long* __restrict__ sub;  // accepted BS substeps per block / wave
   double* __restrict__ pl;            // planets' full-step BS table
   int64_t* __restrict__ rq;           // entries left to the wave path
@@ -146,6 +150,9 @@ __global__ __launch_bounds__(256) void k_tp_main(TpArgs a, const double4* __rest
                                                  const double4* __restrict__ ppost,
                                                  const double4* __restrict__ vpost,
                                                  const double* __restrict__ prc) {
+  __shared__ unsigned kh[kKepBins];  // this block's drifts by iteration count
+  if (threadIdx.x < kKepBins) kh[threadIdx.x] = 0u;
+  __syncthreads();
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int lane = threadIdx.x & 63;
   double P1x = 0.0, P1y = 0.0, P1z = 0.0;
@@ -182,6 +189,7 @@ __global__ __launch_bounds__(256) void k_tp_main(TpArgs a, const double4* __rest
     vzm = vz;
     it = kepler_drift(a.mu, a.dt, x, y, z, vx, vy, vz, a.max_iter);
     if (it < 0) atomicOr(&a.st->flags, F_KEPLER);
+    atomicAdd(&kh[min(abs(it), kKepBins - 1)], 1u);
     if (!a.enc_free && cmask) {
       for (int j = 0; j < a.nm; ++j) {
         if (!(cmask & (1u << j))) continue;
@@ -191,7 +199,11 @@ __global__ __launch_bounds__(256) void k_tp_main(TpArgs a, const double4* __rest
                                         p1.x - x, p1.y - y, p1.z - z,
                                         q1.x - vx, q1.y - vy, q1.z - vz);
         const double rcij = fmax(rct, prc[j]);
-        if (d2 < rcij * rcij) emask |= 1u << j;
+        if (d2 < rcij * rcij) {
+          emask |= 1u << j;
+          a.enc_d2[(size_t)j * a.ntp + k] = d2;
+          a.enc_rc2[(size_t)j * a.ntp + k] = rcij * rcij;
+        }
       }
     }
     if (emask) {
@@ -224,10 +236,13 @@ __global__ __launch_bounds__(256) void k_tp_main(TpArgs a, const double4* __rest
     a.blk_enc_tot[b] += (unsigned long long)ne;
     a.blk_kit[b] = max(a.blk_kit[b], max(max(s_kit[0], s_kit[1]), max(s_kit[2], s_kit[3])));
   }
+  if (threadIdx.x < kKepBins)
+    a.khist[(size_t)blockIdx.x * kKepBins + threadIdx.x] += kh[threadIdx.x];
   if (listed) {
     const int64_t pos = (int64_t)blockIdx.x * 256 + base + (int)lanemask_count_tp(lm);
     a.bs_idx[pos] = (int)k;
     a.bs_mask[pos] = emask;
+    a.bs_emask[pos] = emask;
     a.bs_rct[pos] = rct;
     a.bs_y[pos] = xm0;
     a.bs_y[a.cap + pos] = ym0;
@@ -756,12 +771,15 @@ TpArgs tp_args(const MassiveWs& w, const TpWs& t, const StepConsts& c) {
   a.vpre = w.vpre;
   a.ppost = w.xpost;
   a.vpost = w.vpost;
-  a.pfin = w.xm;
+  a.pfin = w.xs;
   a.rc = w.rc_cur;
   a.partP = w.partP;
   a.st = w.st;
   a.bs_idx = t.bs_idx;
   a.bs_mask = t.bs_mask;
+  a.bs_emask = t.bs_emask;
+  a.enc_d2 = t.enc_d2;
+  a.enc_rc2 = t.enc_rc2;
   a.bs_rct = t.bs_rct;
   a.bs_y = t.bs_y;
   a.rad = t.rad;
@@ -771,6 +789,7 @@ TpArgs tp_args(const MassiveWs& w, const TpWs& t, const StepConsts& c) {
   a.blk_enc = t.blk_enc;
   a.blk_enc_tot = t.blk_enc_tot;
   a.blk_kit = t.blk_kit;
+  a.khist = t.khist;
   a.sub = t.sub;
   a.pl = t.pl;
   a.rq = t.rq;
@@ -797,8 +816,9 @@ TpArgs tp_args(const MassiveWs& w, const TpWs& t, const StepConsts& c) {
 
 }  // namespace
 
-size_t tp_carve(TpWs& t, int64_t ntp, void* base) {
+size_t tp_carve(TpWs& t, int64_t ntp, int nm, void* base) {
   t.ntp = ntp;
+  t.nm = nm;
   t.nb = std::max<int64_t>((ntp + 255) / 256, 1);
   t.cap = t.nb * 256;  // one 256-entry region of the list per block
   const size_t n = (size_t)std::max<int64_t>(ntp, 1);
@@ -814,6 +834,9 @@ size_t tp_carve(TpWs& t, int64_t ntp, void* base) {
   t.mask = (unsigned*)take(n * sizeof(unsigned));
   t.bs_idx = (int*)take(nc * sizeof(int));
   t.bs_mask = (unsigned*)take(nc * sizeof(unsigned));
+  t.bs_emask = (unsigned*)take(nc * sizeof(unsigned));
+  t.enc_d2 = (double*)take((size_t)nm * n * sizeof(double));
+  t.enc_rc2 = (double*)take((size_t)nm * n * sizeof(double));
   t.bs_rct = (double*)take(nc * sizeof(double));
   t.bs_y = (double*)take(6 * nc * sizeof(double));
   t.rad = (double*)take((kTpMaxPlanets + n) * sizeof(double));
@@ -826,6 +849,7 @@ size_t tp_carve(TpWs& t, int64_t ntp, void* base) {
   const size_t cum0 = off;
   t.blk_enc_tot = (unsigned long long*)take(nb * sizeof(unsigned long long));
   t.blk_kit = (int*)take(nb * sizeof(int));
+  t.khist = (unsigned long long*)take(nb * kKepBins * sizeof(unsigned long long));
   t.sub = (unsigned long long*)take(kTpSubSlots * sizeof(unsigned long long));
   t.cum_bytes = off - cum0;
   t.pl = (double*)take((size_t)kTpMaxPlanets * kPlStride * sizeof(double));
@@ -839,9 +863,10 @@ hipError_t tp_read_counters(const TpWs& t, TpCounters* h, hipStream_t s) {
   h->enc_total = 0;
   h->kit = 0;
   h->sub = 0;
+  for (int q = 0; q < kKepBins; ++q) h->khist[q] = 0;
   if (t.ntp <= 0) return hipSuccess;
   std::vector<int> enc(t.nb), kit(t.nb);
-  std::vector<unsigned long long> tot(t.nb), sub(kTpSubSlots);
+  std::vector<unsigned long long> tot(t.nb), sub(kTpSubSlots), kh((size_t)t.nb * kKepBins);
   hipError_t e = hipMemcpyAsync(enc.data(), t.blk_enc, t.nb * sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(kit.data(), t.blk_kit, t.nb * sizeof(int), hipMemcpyDeviceToHost, s);
@@ -851,6 +876,9 @@ hipError_t tp_read_counters(const TpWs& t, TpCounters* h, hipStream_t s) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(sub.data(), t.sub, kTpSubSlots * sizeof(unsigned long long),
                        hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(kh.data(), t.khist, kh.size() * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
   for (int64_t b = 0; b < t.nb; ++b) {
@@ -859,6 +887,40 @@ hipError_t tp_read_counters(const TpWs& t, TpCounters* h, hipStream_t s) {
     h->kit = std::max(h->kit, kit[b]);
   }
   for (int q = 0; q < kTpSubSlots; ++q) h->sub += sub[q];
+  for (size_t q = 0; q < kh.size(); ++q) h->khist[q % kKepBins] += kh[q];
+  return hipSuccess;
+}
+
+// Copies of the list (per block region: its particles and their encounter
+// planets) and of the stored minima; no arithmetic.
+hipError_t tp_read_encounters(const TpWs& t, std::vector<TpEnc>* out, hipStream_t s) {
+  out->clear();
+  if (t.ntp <= 0) return hipSuccess;
+  std::vector<int> cnt(t.nb), idx(t.cap);
+  std::vector<unsigned> em(t.cap);
+  std::vector<double> d2((size_t)t.nm * t.ntp), rc2((size_t)t.nm * t.ntp);
+  hipError_t e = hipMemcpyAsync(cnt.data(), t.blk_cnt, t.nb * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(idx.data(), t.bs_idx, t.cap * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(em.data(), t.bs_emask, t.cap * sizeof(unsigned), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d2.data(), t.enc_d2, d2.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(rc2.data(), t.enc_rc2, rc2.size() * sizeof(double), hipMemcpyDeviceToHost,
+                       s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  for (int64_t b = 0; b < t.nb; ++b)
+    for (int q = 0; q < cnt[b]; ++q) {
+      const int64_t pos = b * 256 + q;
+      const long long k = idx[pos];
+      for (unsigned m = em[pos]; m; m &= m - 1u) {
+        const int j = __builtin_ctz(m);
+        const size_t at = (size_t)j * t.ntp + k;
+        out->push_back(TpEnc{k, j, d2[at], rc2[at]});
+      }
+    }
   return hipSuccess;
 }
 

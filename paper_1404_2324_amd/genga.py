@@ -20,6 +20,7 @@ GENGA_HELIO, GENGA_DEMOCRATIC = 0, 1
 OK, EINVAL, EHIP, EOVERFLOW, EKEPLER, EBS, EADJ_ENCOUNTER, ENOMEM, EGROUP = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 WSTOPPED = 1  # warning: batched systems stopped after a failed step
+KEPLER_BINS = 16  # GENGA_KEPLER_BINS
 
 
 class GengaError(RuntimeError):
@@ -35,7 +36,23 @@ class Params(ctypes.Structure):
                 ("bs_tol", ctypes.c_double), ("bs_max_depth", ctypes.c_int32),
                 ("kepler_max_iter", ctypes.c_int32), ("encounter_free", ctypes.c_int32),
                 ("cand_per_body", ctypes.c_int32), ("enc_cap", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("rcut", ctypes.c_double),
+                ("rcut_sun", ctypes.c_double), ("nmin", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class Event(ctypes.Structure):
+    """A merger or an ejection (genga_event)."""
+    _fields_ = [("kind", ctypes.c_int32), ("sys", ctypes.c_int32), ("id_i", ctypes.c_int32),
+                ("id_j", ctypes.c_int32), ("step", ctypes.c_int64), ("frac", ctypes.c_double),
+                ("m_i", ctypes.c_double), ("m_j", ctypes.c_double), ("R_i", ctypes.c_double),
+                ("R_j", ctypes.c_double)] + [
+        (f"{q}_{b}", ctypes.c_double * 3) for b in "ij" for q in ("x", "v", "s")] + [
+        ("U", ctypes.c_double)]
+
+
+EV_MERGE, EV_EJECT_FAR, EV_EJECT_SUN = 1, 2, 3
+WNMIN = 2  # batched system status: fewer than nmin bodies left
 
 
 class Stats(ctypes.Structure):
@@ -46,10 +63,14 @@ class Stats(ctypes.Structure):
                 ("enc_total", ctypes.c_int64), ("full_kicks", ctypes.c_int64),
                 ("tp_enc_total", ctypes.c_int64), ("tp_removed", ctypes.c_int64),
                 ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("reserved", ctypes.c_uint32),
+                ("kepler_hist", ctypes.c_int64 * KEPLER_BINS)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+        d = {k: int(getattr(self, k)) for k, _ in self._fields_
+             if k not in ("reserved", "kepler_hist")}
+        d["kepler_hist"] = [int(v) for v in self.kepler_hist]
+        return d
 
 
 # every symbol the header declares, with its ctypes signature
@@ -69,13 +90,16 @@ SIGNATURES = {
     "genga_energy": (_i32, [_vp, _vp, _vp]),
     "genga_accel_state": (_i32, [_vp, _vp]),
     "genga_encounters": (_i32, [_vp, _vp, _vp, _vp, _i32, ctypes.POINTER(_i32)]),
-    "genga_candidates": (_i32, [_vp, _vp, _i32, ctypes.POINTER(_i32)]),
+    "genga_candidates": (_i32, [_vp, _vp, _vp, _i32, ctypes.POINTER(_i32)]),
+    "genga_tp_encounters": (_i32, [_vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64)]),
     "genga_stats": (_i32, [_vp, ctypes.POINTER(Stats)]),
     "genga_set_radii": (_i32, [_vp, _vp]),
     "genga_tune": (_i32, [_vp, _i32, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "genga_tune_variant": (ctypes.c_char_p, [_i32]),
     "genga_batch_set_variant": (_i32, [_vp, _i32]),
     "genga_batch_status": (_i32, [_vp, _vp, _vp, _i32]),
+    "genga_events": (_i32, [_vp, ctypes.POINTER(Event), _i64, ctypes.POINTER(_i64)]),
+    "genga_bodies": (_i32, [_vp, _vp, _i64, _vp, _vp, _i32]),
     "genga_adj_buffer_bytes": (_sz, [_vp, _i64, _i32]),
     "genga_adj_forward": (_i32, [_vp, _i64, _i32, _vp, _sz]),
     "genga_adj_backward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
@@ -169,7 +193,7 @@ class Simulation:
                "genga_step_profiled")
         return us.value
 
-    STEP_KERNELS = ("k_open_drift", "k_encounter", "k_group", "k_bs", "k_kick", "k_kick_finish")
+    STEP_KERNELS = ("k_open_drift", "k_encounter", "k_group", "k_bs", "k_pairs")
 
     def step_kernel_us(self, nsteps: int) -> dict:
         """Run nsteps steps with every kernel timed (HIP events on the
@@ -233,16 +257,19 @@ class Simulation:
         k = n.value
         return ij[:k], d2[:k], rc2[:k]
 
-    def candidates(self):
+    def candidates(self, with_r2: bool = False):
+        """Prechecker pairs i < j entering the next step (and r_ij^2)."""
         n = ctypes.c_int()
-        code = lib().genga_candidates(self._ctx, None, 0, ctypes.byref(n))
+        code = lib().genga_candidates(self._ctx, None, None, 0, ctypes.byref(n))
         if code not in (OK, EOVERFLOW):
             _check(code, "genga_candidates")
         cap = max(n.value, 1)
         ij = np.zeros((cap, 2), dtype=np.int32)
-        _check(lib().genga_candidates(self._ctx, ij.ctypes.data_as(_vp), cap, ctypes.byref(n)),
-               "genga_candidates")
-        return ij[:n.value]
+        r2 = np.zeros(cap)
+        _check(lib().genga_candidates(self._ctx, ij.ctypes.data_as(_vp), r2.ctypes.data_as(_vp),
+                                      cap, ctypes.byref(n)), "genga_candidates")
+        k = n.value
+        return (ij[:k], r2[:k]) if with_r2 else ij[:k]
 
     def stats(self, check: bool = True):
         s = Stats()
@@ -357,6 +384,23 @@ class TestParticleSimulation(Simulation):
                    "genga_collisions")
         return {"tp": tp, "planet": pl, "step": stp, "frac": fr, "xv": xv}
 
+    def tp_encounters(self):
+        """Particle-planet encounters of the last step: rows (particle,
+        planet) sorted, with the Hermite minimum d2 and r_crit,ij^2."""
+        n = ctypes.c_int64()
+        code = lib().genga_tp_encounters(self._ctx, None, None, None, None, 0, ctypes.byref(n))
+        if code not in (OK, EOVERFLOW):
+            _check(code, "genga_tp_encounters")
+        k = int(n.value)
+        tp = np.zeros(max(k, 1), dtype=np.int64)
+        pl = np.zeros(max(k, 1), dtype=np.int32)
+        d2 = np.zeros(max(k, 1))
+        rc2 = np.zeros(max(k, 1))
+        _check(lib().genga_tp_encounters(self._ctx, tp.ctypes.data, pl.ctypes.data, d2.ctypes.data,
+                                         rc2.ctypes.data, max(k, 1), ctypes.byref(n)),
+               "genga_tp_encounters")
+        return np.stack([tp[:k], pl[:k].astype(np.int64)], 1), d2[:k], rc2[:k]
+
     def split_state(self, coords: str = "dem"):
         x, v = self.state(coords)
         return x[:self.nm], v[:self.nm], x[self.nm:], v[self.nm:]
@@ -407,6 +451,34 @@ class BatchedSimulation(Simulation):
         _check(lib().genga_batch_status(self._ctx, st.ctypes.data, ns.ctypes.data, self.nsys),
                "genga_batch_status")
         return st, ns
+
+    def set_radii(self, radii):
+        """Physical radii, one per row (mergers, Sec. 3.2.7)."""
+        r = _dev(radii, self.device).reshape(-1).contiguous()
+        if r.numel() != self.n:
+            raise ValueError("radii: one per row")
+        _check(lib().genga_set_radii(self._ctx, _ptr(r)), "genga_set_radii")
+
+    def events(self):
+        """Every merger and ejection since init, sorted (list of Event)."""
+        n = ctypes.c_int64()
+        code = lib().genga_events(self._ctx, None, 0, ctypes.byref(n))
+        if code not in (OK, EOVERFLOW) and code < 0:
+            _check(code, "genga_events")
+        k = int(n.value)
+        buf = (Event * max(k, 1))()
+        _check(lib().genga_events(self._ctx, buf, max(k, 1), ctypes.byref(n)), "genga_events")
+        return [buf[i] for i in range(k)]
+
+    def bodies(self):
+        """(original row per row, -1 past a system's count; bodies left per
+        system; internal energy U of each system's mergers)."""
+        ids = np.zeros(self.n, dtype=np.int32)
+        nl = np.zeros(self.nsys, dtype=np.int32)
+        U = np.zeros(self.nsys)
+        _check(lib().genga_bodies(self._ctx, ids.ctypes.data, self.n, nl.ctypes.data,
+                                  U.ctypes.data, self.nsys), "genga_bodies")
+        return ids, nl, U
 
     def tune(self, nsteps: int = 4):
         """Re-run the tuner; returns ({variant: microseconds}, chosen variant)."""

@@ -69,6 +69,9 @@ def test_batch_small_ten_steps_all_systems():
     enc_o = sum(r[4]["enc_total"] for r in ref.values())
     _say("batch 96: worst rel", worst, "enc gpu/oracle", st["enc_total"], enc_o, "stats", st)
     assert st["enc_total"] == enc_o and enc_o > 0
+    # every body's drift of the 10 steps is in the Kepler-iteration histogram
+    assert sum(st["kepler_hist"]) == 10 * len(m)
+    assert max(k for k, c in enumerate(st["kepler_hist"]) if c) == st["kepler_iter_max"]
     ij, _, _ = sim.encounters()
     enc_ref = np.concatenate([r[2] for r in ref.values()]) if ref else np.zeros((0, 2))
     enc_ref = enc_ref[np.lexsort((enc_ref[:, 1], enc_ref[:, 0]))]

@@ -33,6 +33,35 @@ def _sample(ntp_total, sel, seed_index=3):
     return planets, xt[sel], ut[sel]
 
 
+def _tp_sets_close(sim, orc, sel=None, band=1e-10):
+    """The last step's particle-planet encounter pairs (Sec. 3.3) of the GPU
+    run against the oracle's, as sets: equal except pairs whose Hermite
+    minimum lies within `band` (relative) of r_crit,ij^2 on either side.
+    Pairs in both sets carry the same threshold and minimum (to the rounding
+    of states that agree to 1e-12).  sel: the GPU particle index of each
+    oracle particle when the oracle follows a subset.  Returns the count."""
+    ij_g, d2_g, rc2_g = sim.tp_encounters()
+    assert np.all(d2_g < rc2_g)
+    if sel is not None:
+        pos = {int(g): o for o, g in enumerate(sel)}
+        keep = np.array([int(k) in pos for k in ij_g[:, 0]], dtype=bool)
+        ij_g, d2_g, rc2_g = ij_g[keep], d2_g[keep], rc2_g[keep]
+        ij_g = np.stack([np.array([pos[int(k)] for k in ij_g[:, 0]], dtype=np.int64),
+                         ij_g[:, 1]], 1)
+    ij_o, d2_o, rc2_o = orc.tp_encounters()
+    A = {tuple(q): (v, t) for q, v, t in zip(ij_g.tolist(), d2_g, rc2_g)}
+    B = {tuple(q): (v, t) for q, v, t in zip(ij_o.tolist(), d2_o, rc2_o)}
+    for k in set(A) ^ set(B):
+        seen = [A.get(k), B.get(k), (orc.tp_d2[k], orc.tp_rc2[k])]
+        assert any(c is not None and np.isfinite(c[0]) and abs(c[0] - c[1]) <= band * c[1]
+                   for c in seen), f"pair {k} differs and is not in the band: {seen}"
+    for k in set(A) & set(B):
+        (vg, tg), (vo, to) = A[k], B[k]
+        assert abs(tg - to) <= 1e-11 * to, k
+        assert abs(vg - vo) <= 1e-8 * to, k
+    return len(B)
+
+
 @pytest.mark.parametrize("ntp", [0, 1, 63, 2000])
 def test_tp_ten_steps(ntp):
     _say("tp parity ntp", ntp)
@@ -41,26 +70,37 @@ def test_tp_ten_steps(ntp):
     gp = G.default_params()
     sim = G.TestParticleSimulation(planets.m, planets.x, planets.u, xt, ut, gp, coords="helio")
     orc = O.TPSim(_op(gp), planets.m, planets.x, planets.u, xt, ut, coords="helio")
-    enc_g, enc_o = 0, 0
+    enc_o = 0
     for _ in range(10):
         sim.step(1)
         st = orc.step(1)
         enc_o += st["tp_enc"]
+        # the step's encounter set, pair by pair, every step
+        assert _tp_sets_close(sim, orc) == st["tp_enc"]
     sim.check()
     gs = sim.stats()
-    enc_g = gs["tp_enc_total"]
     xp, vp, xg, vg = [t.cpu().numpy() for t in sim.split_state()]
     assert _rel(xp, orc.x).max() < REL and _rel(vp, orc.v).max() < REL
+    # every drift of the 10 steps is in the Kepler-iteration histogram
+    assert sum(gs["kepler_hist"]) == 10 * (planets.m.size + ntp)
+    assert max(k for k, c in enumerate(gs["kepler_hist"]) if c) == gs["kepler_iter_max"]
     if ntp:
         ex, ev = _rel(xg, orc.xt), _rel(vg, orc.vt)
-        _say("tp", ntp, "enc gpu/oracle", enc_g, enc_o, "max rel x", ex.max(), "v", ev.max())
-        assert abs(enc_g - enc_o) <= max(2, enc_o // 200)
+        _say("tp", ntp, "enc gpu total", gs["tp_enc_total"], "oracle", enc_o, "max rel x",
+             ex.max(), "v", ev.max())
         assert ex.max() < REL and ev.max() < REL
+    if ntp == 2000:
+        assert enc_o > 50
 
 
 def test_tp_million_sampled():
     """10^6 particles on the GPU for 3 steps; the oracle follows every 997th
-    particle (plus all of the first 500) with the same planets."""
+    particle (plus all of the first 500) with the same planets, held to the
+    1e-12 bar, and every particle with an encounter in the last step, whose
+    encounter pairs are compared as sets.  Deep passages by a planet amplify
+    rounding differences (nothing removes a particle here), so the particles
+    of the encounter sample are held to 10 times the oracle's own spread
+    under 1-ulp input changes, measured here."""
     planets, xt, ut = W.test_particles(ntp=1_000_000, seed_index=3)
     gp = G.default_params()
     sim = G.TestParticleSimulation(planets.m, planets.x, planets.u, xt, ut, gp, coords="helio")
@@ -70,25 +110,45 @@ def test_tp_million_sampled():
     _say("1e6 tp stats", st)
     assert st["tp_enc"] > 1000  # the workload exercises the particle BS path
     _, _, xg, vg = [t.cpu().numpy() for t in sim.split_state()]
-    sel = np.unique(np.concatenate([np.arange(500), np.arange(0, 1_000_000, 997)]))
+    base = np.unique(np.concatenate([np.arange(500), np.arange(0, 1_000_000, 997)]))
+    ij, _, _ = sim.tp_encounters()
+    assert len(ij) == st["tp_enc"]
+    sel = np.unique(np.concatenate([base, ij[:, 0]]))
+    inb = np.isin(sel, base)
     orc = O.TPSim(_op(gp), planets.m, planets.x, planets.u, xt[sel], ut[sel], coords="helio")
     orc.step(3)
     ex, ev = _rel(xg[sel], orc.xt), _rel(vg[sel], orc.vt)
-    _say("sampled", len(sel), "max rel x", ex.max(), "v", ev.max())
-    assert ex.max() < REL and ev.max() < REL
+    _say("sampled", int(inb.sum()), "max rel x", ex[inb].max(), "v", ev[inb].max())
+    assert ex[inb].max() < REL and ev[inb].max() < REL
+    spread = 0.0
+    for seed in (1, 2):
+        pr = np.random.default_rng(seed)
+        xp = xt[sel] * (1 + 2.0 ** -52 * pr.choice([-1.0, 1.0], (len(sel), 3)))
+        o2 = O.TPSim(_op(gp), planets.m, planets.x, planets.u, xp, ut[sel], coords="helio")
+        o2.step(3)
+        spread = max(spread, _rel(o2.xt, orc.xt).max(), _rel(o2.vt, orc.vt).max())
+    _say("encounter sample", int((~inb).sum()), "max rel x", ex.max(), "v", ev.max(),
+         "oracle 1-ulp spread", spread)
+    assert max(ex.max(), ev.max()) < max(REL, 10 * spread)
+    n_o = _tp_sets_close(sim, orc, sel=sel)
+    _say("sampled encounter pairs (last step)", n_o)
+    assert n_o > 1000
 
 
-def test_tp_masks_match_oracle():
+def test_tp_encounter_sets_5000():
+    """The prechecker masks and the Hermite test of 5000 particles, through
+    the encounter pairs of each of 5 steps."""
     planets, xt, ut = W.test_particles(ntp=5000, seed_index=3)
     gp = G.default_params()
     orc = O.TPSim(_op(gp), planets.m, planets.x, planets.u, xt, ut, coords="helio")
     sim = G.TestParticleSimulation(planets.m, planets.x, planets.u, xt, ut, gp, coords="helio")
-    # masks are internal; compare through the encounter counts of single steps
+    total = 0
     for _ in range(5):
         sim.step(1)
         so = orc.step(1)
-        sg = sim.stats()
-        assert abs(sg["tp_enc"] - so["tp_enc"]) <= 2
+        total += _tp_sets_close(sim, orc)
+        assert sim.stats()["tp_enc"] == len(sim.tp_encounters()[0])
+    assert total > 100
 
 
 def test_tp_encounter_free_equals_massive_free():
@@ -104,18 +164,44 @@ def test_tp_encounter_free_equals_massive_free():
     assert _rel(xg, orc.xt).max() < REL
 
 
-def _coll_parity(sim, orc, ntp, tol):
+def _coll_spread(planets, xt, ut, rad, gp, orc, steps, seeds=(1, 2, 3)):
+    """The oracle against itself with the particles' positions moved by 1 ulp
+    (random signs): the removal sets, the agreement of the collision
+    fractions, and the relative spread of the reports and of the survivors.
+    Close passages amplify any rounding difference, so this is the yardstick
+    for the GPU-oracle difference in the same run."""
+    out = {"frac_equal": 1.0, "dfrac": 0.0, "report": 0.0, "x": 0.0, "v": 0.0}
+    gone = orc.removed()
+    for seed in seeds:
+        pr = np.random.default_rng(seed)
+        xp = xt * (1 + 2.0 ** -52 * pr.choice([-1.0, 1.0], xt.shape))
+        o2 = O.TPSim(_op(gp), planets.m, planets.x, planets.u, xp, ut, coords="helio", radii=rad)
+        o2.step(steps)
+        assert np.array_equal(o2.removed(), gone)
+        eq = o2.coll_frac[gone] == orc.coll_frac[gone]
+        out["frac_equal"] = min(out["frac_equal"], float(eq.mean()) if len(gone) else 1.0)
+        out["dfrac"] = max(out["dfrac"], float(np.abs(o2.coll_frac[gone] - orc.coll_frac[gone]).max(initial=0)))
+        out["report"] = max(out["report"], float(_rel(o2.coll_xv[gone][eq], orc.coll_xv[gone][eq]).max(initial=0)))
+        alive = np.setdiff1d(np.arange(len(xt)), gone)
+        out["x"] = max(out["x"], float(_rel(o2.xt[alive], orc.xt[alive]).max(initial=0)))
+        out["v"] = max(out["v"], float(_rel(o2.vt[alive], orc.vt[alive]).max(initial=0)))
+    return out
+
+
+def _coll_parity(sim, orc, ntp, spread):
     """Removal reports and surviving states of the GPU run against the
     oracle's.  Unique and compared exactly: which particles are removed, by
     which planet, in which step.  The part of the step at which a collision is
-    reported is resolved to the BS substep, and where the two sides take an
+    reported is resolved to the BS substep; where the two sides take an
     accept/reject decision on different sides of the tolerance (their forces
-    differ in the last bits) the substep partition differs: it must agree for
-    most reports and stay within a few of the finest substeps otherwise
-    (the oracle's own runs under 1-ulp input changes differ the same way)."""
+    differ in the last bits) the substep partition differs.  The bounds for
+    those are the oracle's own spread under 1-ulp input changes (`spread`):
+    the share of equal fractions at least 0.9 of the oracle's own, their
+    largest difference at most 4 times the oracle's, report states of equal
+    fraction within 10 times the oracle's report spread."""
     rep = sim.collisions()
     gone_o = orc.removed()
-    _say("removed gpu", len(rep["tp"]), "oracle", len(gone_o))
+    _say("removed gpu", len(rep["tp"]), "oracle", len(gone_o), "oracle spread", spread)
     order = np.argsort(rep["tp"], kind="stable")
     np.testing.assert_array_equal(rep["tp"][order], gone_o)
     np.testing.assert_array_equal(rep["planet"][order], orc.coll_planet[gone_o])
@@ -124,13 +210,14 @@ def _coll_parity(sim, orc, ntp, tol):
     same = fg == fo
     _say("frac equal", int(same.sum()), "gpu earlier", int((fg < fo).sum()),
          "gpu later", int((fg > fo).sum()), "max |dfrac|", float(np.abs(fg - fo).max(initial=0)))
-    assert same.sum() >= 0.8 * len(gone_o)
-    assert np.abs(fg - fo).max(initial=0) <= 2.0**-8
+    assert same.mean() >= 0.9 * spread["frac_equal"]
+    assert np.abs(fg - fo).max(initial=0) <= 4 * max(spread["dfrac"], 2.0 ** -20)
     if len(gone_o):
         xg_r, xo_r = rep["xv"][order], orc.coll_xv[gone_o]
         dx = _rel(xg_r[same, :3], xo_r[same, :3]).max(initial=0)
         dv = _rel(xg_r[same, 3:], xo_r[same, 3:]).max(initial=0)
         _say("reports with equal frac: max rel x", dx, "v", dv)
+        tol = max(REL, 10 * spread["report"])
         assert dx < tol and dv < tol
     _, _, xg, vg = [t.cpu().numpy() for t in sim.split_state(coords="dem")]
     alive = np.setdiff1d(np.arange(ntp), gone_o)
@@ -148,16 +235,12 @@ def _flyby_inputs(n_bg=2000, n_fly=2000):
     return planets, xt, ut, W.tp_radii(planets.m, len(xt))
 
 
-# Passages within a few planet radii amplify differences: the BS tolerance
-# (1e-13 of the heliocentric |x|) is ~1e-10 of the particle-planet distance
-# there.  The oracle itself, rerun with the particles' inputs moved by 1 ulp,
-# spreads by up to 4e-10 (relative) on the survivors of these passages after
-# 12 steps; the bound below leaves a factor 25 over that.
-DEEP_TOL = 1e-8
-
-
 def test_tp_collisions_match_oracle():
-    """Sec. 3.3 removal: about 900 of 4000 particles hit a planet in 12 steps."""
+    """Sec. 3.3 removal: about 900 of 4000 particles hit a planet in 12 steps.
+    Passages within a few planet radii amplify differences (the BS tolerance
+    is ~1e-10 of the particle-planet distance there), so the survivors of
+    these passages are held to 10 times the oracle's own 1-ulp spread,
+    measured here; the background particles hold the 1e-12 bar."""
     planets, xt, ut, rad = _flyby_inputs()
     ntp = len(xt)
     gp = G.default_params()
@@ -173,10 +256,11 @@ def test_tp_collisions_match_oracle():
     _say("bs substeps gpu", st["bs_substeps"], "oracle", sub_o)
     assert abs(st["bs_substeps"] - sub_o) <= 0.01 * sub_o
     assert st["tp_removed"] == len(orc.removed()) > 500
-    xg, vg, alive = _coll_parity(sim, orc, ntp, DEEP_TOL)
+    spread = _coll_spread(planets, xt, ut, rad, gp, orc, 12)
+    xg, vg, alive = _coll_parity(sim, orc, ntp, spread)
     ex, ev = _rel(xg[alive], orc.xt[alive]), _rel(vg[alive], orc.vt[alive])
     _say("survivors max rel x", ex.max(), "v", ev.max(), "beyond 1e-12:", int((ex > 1e-12).sum()))
-    assert ex.max() < DEEP_TOL and ev.max() < DEEP_TOL
+    assert ex.max() < max(REL, 10 * spread["x"]) and ev.max() < max(REL, 10 * spread["v"])
     # the background particles (no aimed passage) hold the 1e-12 bar
     bg = alive[alive < 2000]
     assert ex[: len(bg)].max() < REL and ev[: len(bg)].max() < REL

@@ -79,6 +79,13 @@ def test_workspace_sizing_and_limits(G):
     assert L.genga_workspace_bytes(G.GENGA_MASSIVE, ctypes.byref(bad), 16, 0, 0, 0) == 0
     bad = G.default_params(m0=-1.0)
     assert L.genga_workspace_bytes(G.GENGA_MASSIVE, ctypes.byref(bad), 16, 0, 0, 0) == 0
+    # composed steps (Sec. 2.3): orders 2, 4, 6, main mode only
+    for order, ok in ((0, True), (2, True), (4, True), (6, True), (3, False), (8, False)):
+        q = G.default_params(order=order)
+        assert (L.genga_workspace_bytes(G.GENGA_MASSIVE, ctypes.byref(q), 16, 0, 0, 0) > 0) == ok
+    q4 = G.default_params(order=4)
+    assert L.genga_workspace_bytes(G.GENGA_TEST, ctypes.byref(q4), 8, 100, 0, 0) == 0
+    assert L.genga_workspace_bytes(G.GENGA_BATCH, ctypes.byref(q4), 0, 0, 4, 8) == 0
 
 
 def test_argument_errors_without_device(G):
