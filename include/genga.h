@@ -227,6 +227,14 @@ int genga_get_state(genga_ctx *ctx, double *d_x, double *d_v, int coords_out);
 int genga_set_state(genga_ctx *ctx, const double *d_x, const double *d_v,
                     int coords_in);
 
+/* Batched mode: replace the mass of every row (d_m, n_bodies doubles,
+ * device) keeping positions and velocities, then prepare the next opening
+ * kick as genga_init does (the masses enter Eqs. 1-3 and 6).  With
+ * genga_set_state in democratic coordinates this re-runs a context from new
+ * initial conditions without a new init.  Synchronising.  Errors: EINVAL
+ * (other mode, NULL, a non-finite mass), EHIP. */
+int genga_set_masses(genga_ctx *ctx, const double *d_m);
+
 /* Total energy E = H_A + H_B + H_C of Eqs. (1)-(3) (K summed out:
  * sum m v^2/2 + |P|^2/2m0 - sum G m0 m_i/r_i - sum_{i<j} G m_i m_j/r_ij) and
  * angular momentum L = sum m_i x_i x v_i of each system, written to d_E

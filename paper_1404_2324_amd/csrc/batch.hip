@@ -176,7 +176,9 @@ __device__ __forceinline__ void kick_chunk(int jj0, int nh, int lane, int hb, do
   bool ok[U];
   bool near = false;
   // stage by stage over the U pairs, so that the independent chains
-  // interleave (the reciprocal square root is rsqrt_nr written out)
+  // interleave; the reciprocal square root is the hardware estimate refined
+  // by two Newton steps on the halved residual (not the single third-order
+  // step of rsqrt_nr, so the last bit can differ from the main-mode kick's)
 #pragma unroll
   for (int k = 0; k < U; ++k) {
     const int jj = jj0 + k;
@@ -613,9 +615,13 @@ __global__ __launch_bounds__(64, LB) void k_batch(BatchArgs a) {
           const double Rs = readlane_d(R, ls), Rg = readlane_d(R, lg);
           const double Uc = merge_bodies(a.G, ms, mg, ys, yg, Rs, Rg, ss, sgv, Mm, ym, Rm, sm);
           const double frac = f0 + (1.0 - f0) * fc;
+          // read in converged control flow: inside the branch below lane lg
+          // is inactive, and a register's value in an inactive lane need not
+          // survive register allocation there
+          const int idg = __builtin_amdgcn_readlane(id, lg);
           if (lane == ls)
-            put_event(a, GENGA_EV_MERGE, sg, id, __builtin_amdgcn_readlane(id, lg),
-                      step0 + step, frac, ms, mg, Rs, Rg, ys, ss, yg, sgv, Uc);
+            put_event(a, GENGA_EV_MERGE, sg, id, idg, step0 + step, frac, ms, mg, Rs, Rg, ys, ss,
+                      yg, sgv, Uc);
           if (own) Usys += Uc;
           const double rcm = fmax(readlane_d(rcl, ls), readlane_d(rcl, lg));
           if (lane == ls) {
@@ -1117,6 +1123,20 @@ hipError_t batch_copy_to_scratch(const BatchWs& b, hipStream_t s) {
     e = hipMemcpyAsync(b.ids2, b.ids, n * sizeof(int), hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(b.flags2, 0, sizeof(unsigned), s);
   return e;
+}
+
+// New masses for every row; positions and velocities stay.
+__global__ __launch_bounds__(256) void k_batch_masses(const double* __restrict__ m,
+                                                      double4* __restrict__ xm, int64_t nb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) xm[i].w = m[i];
+}
+
+hipError_t batch_set_masses(const BatchWs& b, const double* m, hipStream_t s) {
+  if (b.nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_masses, dim3((unsigned)((b.nb + 255) / 256)), dim3(256), 0, s, m,
+                     b.xm, b.nb);
+  return hipGetLastError();
 }
 
 hipError_t batch_reset_bodies(const BatchWs& b, hipStream_t s) {

@@ -15,7 +15,7 @@ using namespace genga;
 
 namespace {
 
-constexpr int kGraphSteps = 16;  // steps per captured graph
+constexpr int kGraphSteps = 16;  // steps per captured graph (and at most 15 in a remainder graph)
 
 int status_from_flags(unsigned f) {
   if (f & F_KEPLER) return GENGA_EKEPLER;
@@ -101,8 +101,9 @@ struct genga_ctx {
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
   hipGraphExec_t g_many = nullptr;
-  hipGraphExec_t g_one = nullptr;
+  hipGraphExec_t g_rem[16] = {};  // r steps in one graph, r = 1 .. 15
   int64_t steps = 0;
+  bool tuned = false;                    // batched mode: the tuner has chosen a variant
 };
 
 #define HIPCHK(expr)                          \
@@ -221,6 +222,7 @@ static int batch_tune(genga_ctx* ctx, int steps) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != GENGA_OK) return rc;
+  ctx->tuned = true;
   if (best != ctx->variant || !ctx->g_batch) {
     ctx->variant = best;
     if (ctx->g_batch) {
@@ -315,7 +317,6 @@ static int batch_init(genga_ctx** out, const genga_params* p, int n_sys,
        batch_reset_bodies(b, st) != hipSuccess))
     rc = GENGA_EHIP;
   if (rc == GENGA_OK) rc = batch_load(ctx, d_m, d_x, d_v, coords_in);
-  if (rc == GENGA_OK) rc = batch_tune(ctx, kTuneSteps);
   if (rc == GENGA_OK && hipStreamSynchronize(st) != hipSuccess) rc = GENGA_EHIP;
   if (rc != GENGA_OK) {
     genga_destroy(ctx);
@@ -326,6 +327,12 @@ static int batch_init(genga_ctx** out, const genga_params* p, int n_sys,
 }
 
 static int batch_step(genga_ctx* ctx, int64_t nsteps) {
+  // the tuner runs before the first steps (not at init: contexts that only
+  // take the adjoint never launch the step kernel)
+  if (!ctx->tuned) {
+    const int r = batch_tune(ctx, kTuneSteps);
+    if (r != GENGA_OK) return r;
+  }
   while (nsteps > 0) {
     const int chunk = (int)std::min<int64_t>(nsteps, 1 << 30);
     if (!ctx->g_batch || ctx->g_batch_steps != chunk) {
@@ -419,12 +426,15 @@ int genga_step(genga_ctx* ctx, int64_t nsteps) {
     int r = capture(ctx, kGraphSteps, &ctx->g_many);
     if (r != GENGA_OK) return r;
   }
-  if (nsteps % kGraphSteps && !ctx->g_one) {
-    int r = capture(ctx, 1, &ctx->g_one);
+  // the remaining steps as one graph of their own, so that a call's time per
+  // step does not depend on how its count divides into graphs of 16
+  const int rem = (int)(nsteps % kGraphSteps);
+  if (rem && !ctx->g_rem[rem]) {
+    int r = capture(ctx, rem, &ctx->g_rem[rem]);
     if (r != GENGA_OK) return r;
   }
   for (int64_t k = 0; k < nsteps / kGraphSteps; ++k) HIPCHK(hipGraphLaunch(ctx->g_many, ctx->stream));
-  for (int64_t k = 0; k < nsteps % kGraphSteps; ++k) HIPCHK(hipGraphLaunch(ctx->g_one, ctx->stream));
+  if (rem) HIPCHK(hipGraphLaunch(ctx->g_rem[rem], ctx->stream));
   ctx->steps += nsteps;
   return GENGA_OK;
 }
@@ -520,6 +530,20 @@ int genga_set_state(genga_ctx* ctx, const double* d_x, const double* d_v, int co
   HIPCHK(massive_masses(ctx->w, dm, ctx->stream));
   int r = load_state(ctx, dm, d_x, d_v, coords_in);
   if (r != GENGA_OK) return r;
+  return genga_sync(ctx);
+}
+
+int genga_set_masses(genga_ctx* ctx, const double* d_m) {
+  if (!ctx || !d_m || ctx->mode != GENGA_BATCH) return GENGA_EINVAL;
+  const BatchWs& b = ctx->b;
+  HIPCHK(hipMemsetAsync(b.flag_in, 0, sizeof(int), ctx->stream));
+  HIPCHK(validate_finite(d_m, b.nb, b.flag_in, ctx->stream));
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, b.flag_in, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (bad) return GENGA_EINVAL;
+  HIPCHK(batch_set_masses(b, d_m, ctx->stream));
+  HIPCHK(batch_prime(b, ctx->c, ctx->stream));
   return genga_sync(ctx);
 }
 
@@ -872,6 +896,7 @@ const char* genga_tune_variant(int v) { return batch_variant_name(v); }
 
 int genga_batch_set_variant(genga_ctx* ctx, int v) {
   if (!ctx || ctx->mode != GENGA_BATCH || !batch_variant_ok(ctx->b, v)) return GENGA_EINVAL;
+  ctx->tuned = true;
   if (v != ctx->variant) {
     ctx->variant = v;
     if (ctx->g_batch) {
@@ -957,7 +982,8 @@ int genga_destroy(genga_ctx* ctx) {
   if (ctx->stream || ctx->cap) (void)hipStreamSynchronize(ctx->stream);
   if (ctx->g_many) (void)hipGraphExecDestroy(ctx->g_many);
   if (ctx->g_batch) (void)hipGraphExecDestroy(ctx->g_batch);
-  if (ctx->g_one) (void)hipGraphExecDestroy(ctx->g_one);
+  for (hipGraphExec_t g : ctx->g_rem)
+    if (g) (void)hipGraphExecDestroy(g);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;
   return GENGA_OK;

@@ -295,6 +295,8 @@ hipError_t batch_copy_to_scratch(const BatchWs& b, hipStream_t s);
 // Bodies of every system present, original rows, zero spins and radii, no
 // events (init).
 hipError_t batch_reset_bodies(const BatchWs& b, hipStream_t s);
+// Masses of every row replaced (state kept).
+hipError_t batch_set_masses(const BatchWs& b, const double* m, hipStream_t s);
 const char* batch_variant_name(int v);
 // whether variant v can run these systems (two per wave needs sizes <= 32)
 bool batch_variant_ok(const BatchWs& b, int v);

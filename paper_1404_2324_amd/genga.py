@@ -87,6 +87,7 @@ SIGNATURES = {
     "genga_step_kernel_us": (_i32, [_vp, _i64, ctypes.POINTER(ctypes.c_double)]),
     "genga_get_state": (_i32, [_vp, _vp, _vp, _i32]),
     "genga_set_state": (_i32, [_vp, _vp, _vp, _i32]),
+    "genga_set_masses": (_i32, [_vp, _vp]),
     "genga_energy": (_i32, [_vp, _vp, _vp]),
     "genga_accel_state": (_i32, [_vp, _vp]),
     "genga_encounters": (_i32, [_vp, _vp, _vp, _vp, _i32, ctypes.POINTER(_i32)]),
@@ -410,7 +411,7 @@ class BatchedSimulation(Simulation):
     """Independent systems (Sec. 3.4), system s in rows
     [offsets[s], offsets[s+1]), each with its own central mass m0s[s]; every
     call to ``step(n)`` is one launch (a captured HIP graph) that advances
-    every system n steps.  The tuner runs at construction."""
+    every system n steps.  The tuner runs before the first steps."""
 
     def __init__(self, offsets, m0s, m, x, v, params: Params | None = None,
                  coords: str = "helio", device="cuda", stream=None):
@@ -451,6 +452,13 @@ class BatchedSimulation(Simulation):
         _check(lib().genga_batch_status(self._ctx, st.ctypes.data, ns.ctypes.data, self.nsys),
                "genga_batch_status")
         return st, ns
+
+    def set_masses(self, m):
+        """New masses, one per row; positions and velocities stay."""
+        m = _dev(m, self.device).reshape(-1).contiguous()
+        if m.numel() != self.n:
+            raise ValueError("masses: one per row")
+        _check(lib().genga_set_masses(self._ctx, _ptr(m)), "genga_set_masses")
 
     def set_radii(self, radii):
         """Physical radii, one per row (mergers, Sec. 3.2.7)."""
@@ -515,34 +523,76 @@ class BatchedSimulation(Simulation):
         return gx0, gv0, gm
 
 
+# Idle encounter-free contexts by (device, system layout, central masses,
+# parameters): a forward takes one (or makes one), its backward gives it back,
+# so repeated calls re-use the workspace instead of a new init each time.
+_EF_IDLE: dict = {}
+
+
+def _ef_key(device, offsets, m0s, p):
+    off = tuple(int(q) for q in np.asarray(offsets).reshape(-1))
+    m0 = None if m0s is None else tuple(float(q) for q in np.asarray(
+        m0s.detach().cpu() if torch.is_tensor(m0s) else m0s, dtype=np.float64).reshape(-1))
+    return (str(device), off, m0, bytes(p))
+
+
+def _ef_take(x0, v0, m, offsets, m0s, p):
+    key = _ef_key(x0.device, offsets, m0s, p)
+    idle = _EF_IDLE.get(key)
+    if idle:
+        sim = idle.pop()
+        sim.set_masses(m.detach())
+        sim.set_state(x0.detach(), v0.detach(), "dem")
+    else:
+        sim = BatchedSimulation(offsets, m0s, m.detach(), x0.detach(), v0.detach(), p,
+                                coords="dem", device=x0.device)
+    sim._ef_key = key
+    return sim
+
+
+def _ef_give_back(sim):
+    sim._adj_buf = None
+    _EF_IDLE.setdefault(sim._ef_key, []).append(sim)
+
+
 class EncounterFreeMap(torch.autograd.Function):
     """(x_T, v_T) = nsteps steps of the encounter-free map (K = 1) of every
     system from democratic (x0, v0) with masses m; backward runs the library's
-    adjoint with a checkpoint every ckpt_every steps."""
+    adjoint with a checkpoint every ckpt_every steps.  Contexts are re-used
+    across calls of the same shape and parameters."""
 
     @staticmethod
     def forward(ctx, x0, v0, m, offsets, m0s, nsteps, ckpt_every=32, params=None):
-        p = params if params is not None else default_params()
+        p = Params()
+        ctypes.memmove(ctypes.byref(p), ctypes.byref(params if params is not None
+                                                     else default_params()), ctypes.sizeof(p))
         p.encounter_free = 1
-        sim = BatchedSimulation(offsets, m0s, m.detach(), x0.detach(), v0.detach(), p,
-                                coords="dem", device=x0.device)
-        sim.adj_forward(nsteps, ckpt_every)
-        xT, vT = sim.state("dem")
-        sim.check()
+        sim = _ef_take(x0, v0, m, offsets, m0s, p)
+        try:
+            sim.adj_forward(nsteps, ckpt_every)
+            xT, vT = sim.state("dem")
+            sim.check()
+        except Exception:
+            sim.close()
+            raise
         ctx.sim = sim
         return xT, vT
 
     @staticmethod
     def backward(ctx, gxT, gvT):
         sim = ctx.sim
+        ctx.sim = None
         if gxT is None:
             gxT = torch.zeros(sim.n, 3, dtype=torch.float64, device=sim.device)
         if gvT is None:
             gvT = torch.zeros(sim.n, 3, dtype=torch.float64, device=sim.device)
-        gx0, gv0, gm = sim.adj_backward(gxT.contiguous(), gvT.contiguous())
-        sim.check()
-        sim.close()
-        ctx.sim = None
+        try:
+            gx0, gv0, gm = sim.adj_backward(gxT.contiguous(), gvT.contiguous())
+            sim.check()
+        except Exception:
+            sim.close()
+            raise
+        _ef_give_back(sim)
         return gx0, gv0, gm, None, None, None, None, None
 
 
