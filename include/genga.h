@@ -409,6 +409,22 @@ int genga_accel(const genga_params *p, int n, const double *d_m,
                 const double *d_x, const double *d_rc, double *d_acc,
                 void *d_workspace, size_t ws_bytes, void *stream);
 
+/* genga_accel with no workspace argument and no allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, same
+ * kernels and the same bits as genga_accel, for 1 <= n <=
+ * GENGA_ACCEL_NOALLOC_MAX bodies (EINVAL beyond).  The library keeps the
+ * packed bodies, radii and thresholds in a fixed device array of its own,
+ * about 1.9 MB, one per GPU, held until the process ends; the first call on
+ * a device looks up that device's copy (on the device current at the call,
+ * which must be the stream's).  Calls that overlap on one GPU (concurrent
+ * streams or threads) share that array and race: serialise them.
+ * Asynchronous.  Errors: EINVAL, EHIP. */
+#define GENGA_ACCEL_NOALLOC_MAX 16384
+int genga_accel_noalloc(const genga_params *p, int n, const double *d_m,
+                        const double *d_x, const double *d_rc, double *d_acc,
+                        void *stream);
+
 /* Kepler drift of n independent bodies for dt about mu (Eq. 9, universal
  * variables).  d_x0, d_v0 in, d_x, d_v out (n x 3, device; may alias the
  * inputs).  d_iters (n ints, device, may be NULL) receives the iteration

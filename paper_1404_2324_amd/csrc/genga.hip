@@ -1011,6 +1011,16 @@ int genga_accel(const genga_params* p, int n, const double* d_m, const double* d
   return GENGA_OK;
 }
 
+int genga_accel_noalloc(const genga_params* p, int n, const double* d_m, const double* d_x,
+                        const double* d_rc, double* d_acc, void* stream) {
+  if (!params_ok(p) || n < 1 || n > GENGA_ACCEL_NOALLOC_MAX || !d_m || !d_x || !d_acc)
+    return GENGA_EINVAL;
+  if (!p->encounter_free && !d_rc) return GENGA_EINVAL;
+  HIPCHK(accel_noalloc_run(make_consts(accel_params(*p)), n, d_m, d_x, d_rc, d_acc,
+                           (hipStream_t)stream));
+  return GENGA_OK;
+}
+
 int genga_kepler(double mu, int64_t n, const double* d_x0, const double* d_v0, double dt,
                  double* d_x, double* d_v, int max_iter, int32_t* d_iters, void* stream) {
   if (n < 0 || !(mu > 0.0) || !std::isfinite(dt) || max_iter < 1) return GENGA_EINVAL;

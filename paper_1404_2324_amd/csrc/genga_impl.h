@@ -194,6 +194,11 @@ hipError_t accel_run(const MassiveWs& w, const StepConsts& c, const double* m, c
 // Parameters of the context-free acceleration (one candidate slot, one
 // encounter slot: the pair kernel keeps no lists in this form).
 genga_params accel_params(const genga_params& p);
+// The pair kernel's acceleration mode on the library's own device scratch
+// (no workspace argument, no allocation); n <= kAccelNoAllocMax.
+constexpr int kAccelNoAllocMax = GENGA_ACCEL_NOALLOC_MAX;
+hipError_t accel_noalloc_run(const StepConsts& c, int n, const double* m, const double* x,
+                             const double* rc, double* acc, hipStream_t s);
 
 // ---- test-particle mode (tp.hip) --------------------------------------------
 size_t tp_carve(TpWs& t, int64_t ntp, int nm, void* base);

@@ -18,6 +18,7 @@
 
 #include <climits>
 #include <cstddef>
+#include <mutex>
 
 #include "bs_device.h"
 #include "device_math.h"
@@ -1451,6 +1452,76 @@ hipError_t accel_run(const MassiveWs& w, const StepConsts& c, const double* m, c
                      c.encounter_free ? nullptr : rc, w.rc_cur, w.thr, w.ccnt, w.n, c.pf2,
                      c.encounter_free);
   return massive_accel(w, c, w.xm, acc, s);
+}
+
+// ---- the pair kernel with no workspace argument ----------------------------
+// Scratch of accel_noalloc_run: the packed bodies (x, y, z, m), the velocity
+// and start-position rows the packing kernel also fills, radii, thresholds
+// and candidate counts of up to kNoAllocBodies bodies (116 bytes per padded
+// body, 1.9 MB).  Each GPU holds its own copy until the process ends; every
+// call on a GPU uses that GPU's copy, so calls that overlap on one GPU race.
+// Every byte a call reads is written earlier in the same call.
+constexpr int kNoAllocBodies = kAccelNoAllocMax;
+static_assert(kNoAllocBodies % 256 == 0, "bodies are padded to multiples of 256");
+constexpr size_t kNoAllocBytes =
+    (size_t)kNoAllocBodies * (3 * sizeof(double4) + 2 * sizeof(double) + sizeof(int));
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of the current device's scratch, looked up once per
+// device.  In host code the array's name is only a host-side stand-in, so
+// this address is what every launch and copy uses.
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+hipError_t accel_noalloc_run(const StepConsts& c, int n, const double* m, const double* x,
+                             const double* rc, double* acc, hipStream_t s) {
+  if (n < 1 || n > kNoAllocBodies) return hipErrorInvalidValue;
+  void* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) return e;
+  // the arrays the packing, radii and pair kernels of accel_run touch; the
+  // pair kernel's accumulation mode reads no other workspace field
+  MassiveWs w{};
+  w.n = n;
+  w.np = ceil_div(n, 256) * 256;
+  w.npair = ceil_div(n, kPairTile);
+  w.nblk = ceil_div(n, kVecBlock);
+  const size_t np = (size_t)w.np;
+  char* q = static_cast<char*>(base);
+  w.xm = reinterpret_cast<double4*>(q);
+  q += np * sizeof(double4);
+  w.vv = reinterpret_cast<double4*>(q);
+  q += np * sizeof(double4);
+  w.xs = reinterpret_cast<double4*>(q);
+  q += np * sizeof(double4);
+  w.rc_cur = reinterpret_cast<double*>(q);
+  q += np * sizeof(double);
+  w.thr = reinterpret_cast<double*>(q);
+  q += np * sizeof(double);
+  w.ccnt = reinterpret_cast<int*>(q);
+  q += np * sizeof(int);
+  if ((size_t)(q - static_cast<char*>(base)) > kNoAllocBytes) return hipErrorInvalidValue;
+  return accel_run(w, c, m, x, rc, acc, s);
 }
 
 hipError_t massive_masses(const MassiveWs& w, double* m, hipStream_t s) {

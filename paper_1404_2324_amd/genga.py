@@ -109,6 +109,7 @@ SIGNATURES = {
     "genga_destroy": (_i32, [_vp]),
     "genga_accel_workspace_bytes": (_sz, [_i32]),
     "genga_accel": (_i32, [_PP, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "genga_accel_noalloc": (_i32, [_PP, _i32, _vp, _vp, _vp, _vp, _vp]),
     "genga_kepler": (_i32, [_d, _i64, _vp, _vp, _d, _vp, _vp, _i32, _vp, _vp]),
     "genga_hermite": (_i32, [_i64, _d, _vp, _vp, _vp]),
 }
