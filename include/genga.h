@@ -198,7 +198,7 @@ int genga_step(genga_ctx *ctx, int64_t nsteps);
 int genga_step_profiled(genga_ctx *ctx, int64_t nsteps, double *h_kick_us);
 
 /* Number of kernels of one main-mode step, and their order. */
-#define GENGA_STEP_KERNELS 5
+#define GENGA_STEP_KERNELS 6
 /* Run nsteps (1..512) main-mode steps (in test-particle mode followed by the
  * particle kernels, untimed) with a HIP event pair around every kernel of
  * the step, launched so that the events take the dispatch's own start and
@@ -206,8 +206,10 @@ int genga_step_profiled(genga_ctx *ctx, int64_t nsteps, double *h_kick_us);
  * each kernel's average duration in microseconds, in launch order: opening
  * kick with Sun kick and Kepler drift, encounter search (Eqs. 10-12),
  * grouping (App. A), Bulirsch-Stoer of the groups (Sec. 3.2.6), pair kernel
- * of the closing kick with its epilogue (second Sun kick, velocity update,
- * next critical radii); the middle three are 0 with encounter_free.  The
+ * of the closing kick (partial sums with the prechecker), the closing
+ * kick's per-body epilogue (the partial sums added, second Sun kick,
+ * velocity update, next critical radii); the middle three are 0 with
+ * encounter_free.  The
  * breakdown behind a step's time, not a faster step.  Synchronising; returns
  * the latched status (GENGA_EINVAL for a batched context, a null pointer or
  * nsteps out of range). */
@@ -415,7 +417,7 @@ int genga_accel(const genga_params *p, int n, const double *d_m,
  * kernels and the same bits as genga_accel, for 1 <= n <=
  * GENGA_ACCEL_NOALLOC_MAX bodies (EINVAL beyond).  The library keeps the
  * packed bodies, radii and thresholds in a fixed device array of its own,
- * about 1.9 MB, one per GPU, held until the process ends; the first call on
+ * about 2.7 MB, one per GPU, held until the process ends; the first call on
  * a device looks up that device's copy (on the device current at the call,
  * which must be the stream's).  Calls that overlap on one GPU (concurrent
  * streams or threads) share that array and race: serialise them.

@@ -448,7 +448,9 @@ static int step_timed(genga_ctx* ctx, int64_t nsteps, bool all, double* us) {
   constexpr int K = kStepKernels;
   std::vector<hipEvent_t> ev((size_t)(2 * K * nsteps), nullptr);
   const bool enc = !ctx->c.encounter_free;
-  auto timed = [&](int k) { return k == 4 || (all && (enc || k == 0)); };
+  // the pair kernel always; with all, every kernel the step launches
+  auto timed = [&](int k) { return k == 4 || (all && (enc || k == 0 || k == 5)); };
+  const int klast = all ? K - 1 : 4;  // the last timed slot of a step
   int rc = GENGA_OK;
   for (int64_t t = 0; t < nsteps && rc == GENGA_OK; ++t)
     for (int k = 0; k < K && rc == GENGA_OK; ++k)
@@ -461,7 +463,7 @@ static int step_timed(genga_ctx* ctx, int64_t nsteps, bool all, double* us) {
     if (massive_step(ctx->w, ctx->sub[0], ctx->stream, kev) != hipSuccess ||
         (ctx->mode == GENGA_TEST && tp_step(ctx->w, ctx->t, ctx->c, ctx->stream) != hipSuccess))
       rc = GENGA_EHIP;
-    last = kev[2 * 4 + 1];
+    last = kev[2 * klast + 1];
   }
   if (rc == GENGA_OK && hipEventSynchronize(last) != hipSuccess) rc = GENGA_EHIP;
   for (int k = 0; k < K; ++k) us[k] = 0.0;

@@ -62,7 +62,7 @@ constexpr int kVecBlock = 256;         // threads of the per-body kernels
 // Views into the caller's workspace for main mode (also the massive part of
 // test-particle mode).  Bodies are padded to np (a multiple of 256).
 struct MassiveWs {
-  int n, np, npair, nblk;          // npair: workgroups of the pair kernel
+  int n, np, njs, nblk;            // njs: partner splits of the pair kernel
   int cpb;              // candidate slots per body
   int enc_cap;
   double4* xm;          // x, y, z, m          (democratic: heliocentric x)
@@ -75,6 +75,8 @@ struct MassiveWs {
   double* rc_cur;       // radii of the current step
   double* rc_next;      // radii for the next step
   double* thr;          // max((pf rc)^2, tiny): candidate threshold
+  double* thrmax;       // largest threshold of each 256-body block [nblk]
+  double* pp;           // pair kernel's partial sums [njs][6][np]
   double* partP;        // momentum partials after the opening kick [nblk][4]
   double* partP2;       // momentum partials after the drift [nblk][4]
   double* dP;           // momentum change of each BS group [np/2+1][4]
@@ -171,11 +173,11 @@ hipError_t massive_unpack(const MassiveWs& w, const StepConsts& c, double* x,
 hipError_t massive_prime(const MassiveWs& w, const StepConsts& c,
                          hipStream_t s);
 // Kernels of one main-mode step in launch order: opening kick and drift,
-// encounter search, grouping, BS, pair kernel with the closing kick's
-// epilogue (the middle three only with encounters).  With kev (2
-// kStepKernels events), the events of slot k take the start and end
-// timestamps of kernel k's dispatch.
-constexpr int kStepKernels = 5;
+// encounter search, grouping, BS, pair kernel (partial sums), the closing
+// kick's per-body epilogue (encounter search, grouping and BS only with
+// encounters).  With kev (2 kStepKernels events), the events of slot k take
+// the start and end timestamps of kernel k's dispatch.
+constexpr int kStepKernels = 6;
 hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
                         const hipEvent_t* kev = nullptr);
 hipError_t massive_energy(const MassiveWs& w, const StepConsts& c, double* dE,

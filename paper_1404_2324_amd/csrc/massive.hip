@@ -1,7 +1,7 @@
 // Main-mode kernels of the hybrid symplectic step (Grimm & Stadel,
 // arXiv:1404.2324, Sec. 2.2 step recipe and Sec. 3.2 kernels), for gfx950.
 //
-// One step is five launches on one stream (captured once into a HIP graph):
+// One step is six launches on one stream (captured once into a HIP graph):
 //   k_open_drift   opening kick: cached non-candidate acceleration + candidate
 //                  pairs recomputed with the new radii (KickA/KickB, Sec 3.2.3);
 //                  Sun kick tau/2 (Eq. 3) + pre-drift copy + Kepler drift
@@ -10,8 +10,10 @@
 //                  compaction of the confirmed pairs
 //   k_group        equivalence classes of the pairs in LDS (App. A)
 //   k_bs           Bulirsch-Stoer integration of H_A per group, one wave each
-//   k_pairs        closing kick: all pairs and the prechecker, then per body
-//                  the second Sun kick tau/2, v += tau/2 a and the next radii
+//   k_pair_part    closing kick: all pairs and the prechecker, partial sums
+//                  per split of the partners
+//   k_pair_finish  per body: the splits added, the second Sun kick tau/2,
+//                  v += tau/2 a and the next radii
 // Between steps the positions live in xs (the closing kick's output); x
 // holds them while a step runs.
 #include <hip/hip_ext.h>
@@ -77,19 +79,23 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 
 // ---------------------------------------------------------------------------
 // The pair kernel: all pairs of H_B (the gradient of Eq. 2, Sec. 3.2.3) with
-// the prechecker (Sec. 2.2), and the per-body epilogue, in one launch.
-// Third word of a raw buffer resource on this target (no format conversion).
-constexpr int kBufferWord3 = 0x00020000;
-constexpr int kPairTile = 8;                               // i-bodies per workgroup
-constexpr int kPairWaves = 8;                              // waves per workgroup
-constexpr int kPairThreads = kPairWaves * 64;
-constexpr int kPairStreams = kPairThreads / kPairTile;     // j-streams (64)
+// the prechecker (Sec. 2.2), as per-split partial sums; a second kernel
+// adds the splits of each body in a fixed order and applies the per-body
+// epilogue.
+constexpr int kPairW = 16;                     // waves per workgroup
+constexpr int kPairThreads = kPairW * 64;
+constexpr int kPairBlock = 64;                 // i-bodies per workgroup (one per lane)
+constexpr int kPairU = 2;                      // partners per prefetched batch
+constexpr int kPairTarget = 16384;             // splits x padded bodies aimed for
+constexpr int kFinThreads = 64;                // threads of the finishing kernel
 
 struct PairArgs {
   const double* __restrict__ rc;      // radii of the step
+  const double* __restrict__ thrmax;  // largest threshold of each 256-body block
   int* __restrict__ ccnt;             // candidate table (appended)
   int* __restrict__ ctab;
   double* __restrict__ cr2;
+  double* __restrict__ pp;            // partial sums [njs][6][np]: far x y z, near x y z
   double4* __restrict__ xs;           // positions at the end of the step (out)
   double4* __restrict__ vv;
   double4* __restrict__ afar;         // non-candidate acceleration (x G), reused next step
@@ -98,152 +104,140 @@ struct PairArgs {
   const double* __restrict__ partP2;  // momentum partials after the drift
   const double* __restrict__ dP;      // momentum change of each BS group
   DevStat* __restrict__ st;
-  int n, np, cpb, nblk, encounter_free;
+  int n, np, cpb, nblk, njs, encounter_free;
   double G, h, m0, mu, n1, n2, absdt, pf;
 };
 
 enum { KICK_CLOSE = 0, KICK_INIT = 1, KICK_ACC = 2 };
 
-// Workgroup b owns bodies i = 8b .. 8b+7 and every partner j.  Lane l of
-// wave w serves body 8b + (l mod 8) and j-stream s = 8w + l/8, which takes
-// j = s, s + 64, s + 128, ...; the eight lanes of one j read the same
-// address (one request), adjacent streams adjacent bodies.  A pair with
-// r^2 < max((pf rc_i)^2, (pf rc_j)^2) is a candidate: its K-weighted term is
-// summed apart ("near") and appended to the body's candidate table; every
-// other pair has K = 1 and joins the "far" sum that the next opening kick
-// reuses (KickB).  The 64 streams of a body are added in LDS in a fixed
-// order, so results do not depend on timing.  Epilogue, one lane per body:
-//   CLOSE  second Sun kick (x += tau/2 P/m0, P from the drift's momentum
-//          partials and each BS group's change, added in the same order by
-//          every workgroup), v += tau/2 a, next radii (Eq. 6) and the reuse
-//          check.  The shifted positions go to xs, not back to x: other
-//          workgroups may still be reading x for their pairs.
-//   INIT   the far sum and xs = x (the first step's opening kick)
-//   ACC    the acceleration out
-// x and thr come as kernel arguments of their own (noalias) so that the
-// compiler may keep their loads free of the epilogue's stores.
+// Workgroup b takes the 64 bodies i = 64 (b / njs) + lane and the partners
+// of split b mod njs; each of its 16 waves a contiguous range of L = np /
+// (16 njs) partners j, the same j for every lane, so the partner data
+// (x, y, z, m) comes through the scalar cache into SGPRs, two partners ahead
+// of their use: the pair loop issues no vector memory instruction.  The
+// bodies are padded to a multiple of 256 with massless bodies at the origin,
+// whose terms are exact zeros (a lane's own j and padded pairs at r = 0 are
+// excluded by the candidate test below).
+// A pair with r^2 < max(thr_i, thr_j), thr = max((pf rc)^2, tiny), is a
+// candidate: its K-weighted term is summed apart ("near") and, outside the
+// accumulation mode, appended to the body's candidate table; every other
+// pair has K = 1 and joins the "far" sum that the next opening kick reuses
+// (KickB).  The common test is one compare against the largest threshold T
+// of the step: below it the term is held out of the far sum by a select, and
+// a wave with any such lane takes the exact test for those lanes.  The 16
+// waves' sums are added in LDS in wave order; the split's sums go to pp.
 template <int MODE>
-__global__ __launch_bounds__(kPairThreads) void k_pairs(PairArgs a, const double4* __restrict__ x,
-                                                        const double* __restrict__ thr) {
-  __shared__ double red[6][kPairThreads];
-  __shared__ double red2[6][kPairTile][8];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int il = lane & (kPairTile - 1);
-  const int sj = wave * (64 / kPairTile) + lane / kPairTile;
-  const int i = blockIdx.x * kPairTile + il;
-  const bool iv = i < a.n;
-  double xi = 0.0, yi = 0.0, zi = 0.0, ti = kTiny;
-  if (iv) {
-    const double4 p = x[i];
-    xi = p.x;
-    yi = p.y;
-    zi = p.z;
-    ti = thr[i];
+__global__ __launch_bounds__(kPairThreads) void k_pair_part(PairArgs a,
+                                                            const double4* __restrict__ x,
+                                                            const double* __restrict__ thr) {
+  __shared__ double red[6][kPairW][kPairBlock];
+  __shared__ double tmax_sh;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ib = blockIdx.x / a.njs, sp = blockIdx.x - ib * a.njs;
+  if (wave == 0) {
+    double t = kTiny;
+    for (int k = lane; k < a.nblk; k += 64) t = fmax(t, a.thrmax[k]);
+    t = wave_max(t);
+    if (lane == 0) tmax_sh = t;
   }
+  const int i = ib * kPairBlock + lane;
+  const bool iv = i < a.n;
+  const double4 pi = x[i];
+  const double ti = thr[i];
+  const int L = a.np / (a.njs * kPairW);
+  const int j0 = __builtin_amdgcn_readfirstlane((sp * kPairW + wave) * L);
   double fx = 0.0, fy = 0.0, fz = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
   // the series constants of m_rinv3 in registers for the whole loop (an
   // empty asm statement hides their values, so that they are not re-made
   // from literals for every pair)
   double c1875 = 1.875, c15 = 1.5;
   asm volatile("" : "+v"(c1875), "+v"(c15));
-  auto pair = [&](const double4& pj, double tj, int j) {
-    const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
-    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const double s = m_rinv3(pj.w, r2, c1875, c15);
-    // r2 < max(ti, tj) as two compares; the second is written as the
-    // unordered form (the same for the finite values here) so that the
-    // code generator does not fuse them into a maximum, which costs three
-    // instructions on this target
-    const bool cand = (r2 < ti) | !(r2 >= tj);
-    if (__builtin_expect(!cand, 1)) {
-      fx = fma(s, dx, fx);
-      fy = fma(s, dy, fy);
-      fz = fma(s, dz, fz);
-    } else if (iv && j != i && j < a.n) {
-      const double ir = rsqrt_nr(r2);
-      const double ir2 = ir * ir;
-      double K = 1.0, dK = 0.0;
-      if (!a.encounter_free) changeover(r2 * ir, fmax(a.rc[i], a.rc[j]), K, dK);
-      const double sn = pj.w * (K * ir2 * ir - dK * ir2);
-      nx += sn * dx;
-      ny += sn * dy;
-      nz += sn * dz;
-      if (MODE != KICK_ACC && !a.encounter_free) {
-        const int slot = atomicAdd(&a.ccnt[i], 1);
-        if (slot < a.cpb) {
-          a.ctab[(size_t)i * a.cpb + slot] = j;
-          a.cr2[(size_t)i * a.cpb + slot] = r2;
-        } else {
-          atomicOr(&a.st->flags, F_CAND_OVF);
+  __syncthreads();
+  const double T = tmax_sh;
+  const double4* xj = x + j0;
+  double4 cur[kPairU], nxt[kPairU];
+#pragma unroll
+  for (int q = 0; q < kPairU; ++q) nxt[q] = xj[q];
+  for (int k = 0; k < L; k += kPairU) {
+#pragma unroll
+    for (int q = 0; q < kPairU; ++q) cur[q] = nxt[q];
+    if (k + kPairU < L) {
+#pragma unroll
+      for (int q = 0; q < kPairU; ++q) nxt[q] = xj[k + kPairU + q];
+    }
+#pragma unroll
+    for (int q = 0; q < kPairU; ++q) {
+      const double4 pj = cur[q];
+      const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      const double s = m_rinv3(pj.w, r2, c1875, c15);
+      const bool c = r2 < T;
+      const double sf = c ? 0.0 : s;
+      fx = fma(sf, dx, fx);
+      fy = fma(sf, dy, fy);
+      fz = fma(sf, dz, fz);
+      if (__builtin_expect(__builtin_amdgcn_ballot_w64(c) != 0ull, 0)) {
+        const int j = j0 + k + q;
+        const double tj = thr[j];
+        if (c) {
+          if (!(r2 < ti || r2 < tj)) {
+            fx = fma(s, dx, fx);
+            fy = fma(s, dy, fy);
+            fz = fma(s, dz, fz);
+          } else if (iv && j != i && j < a.n) {
+            const double ir = rsqrt_nr(r2);
+            const double ir2 = ir * ir;
+            double K = 1.0, dK = 0.0;
+            if (!a.encounter_free) changeover(r2 * ir, fmax(a.rc[i], a.rc[j]), K, dK);
+            const double sn = pj.w * (K * ir2 * ir - dK * ir2);
+            nx += sn * dx;
+            ny += sn * dy;
+            nz += sn * dz;
+            if (MODE != KICK_ACC && !a.encounter_free) {
+              const int slot = atomicAdd(&a.ccnt[i], 1);
+              if (slot < a.cpb) {
+                a.ctab[(size_t)i * a.cpb + slot] = j;
+                a.cr2[(size_t)i * a.cpb + slot] = r2;
+              } else {
+                atomicOr(&a.st->flags, F_CAND_OVF);
+              }
+            }
+          }
         }
       }
     }
-  };
-  // Every lane takes the same number of partners: the bodies are padded to a
-  // multiple of 256 with zero mass at the origin (their terms are exact
-  // zeros), so j runs over np.  Partners come in batches of four per lane
-  // (j = sj + 64 (4b + u)); while one batch is summed the next one is in
-  // flight, alternating between two register buffers.  Loads are raw buffer
-  // loads: the lane's fixed offset in a VGPR, the batch offset in an SGPR,
-  // so the addressing costs no vector instructions.
-  constexpr int U = 4, S = kPairStreams;
-  const int nb = a.np / (U * S);
-  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<double4*>(x), (short)0, a.np * (int)sizeof(double4), kBufferWord3);
-  const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<double*>(thr), (short)0, a.np * (int)sizeof(double), kBufferWord3);
-  const unsigned lo4 = (unsigned)sj * sizeof(double4), lo1 = (unsigned)sj * sizeof(double);
-  auto load = [&](int b, double4 (&p)[U], double (&t)[U]) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int ox = (U * b + u) * S * (int)sizeof(double4);
-      const int ot = (U * b + u) * S * (int)sizeof(double);
-      const double2 lo = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rx, lo4, ox, 0));
-      const double2 hi = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rx, lo4 + 16u, ox, 0));
-      p[u] = make_double4(lo.x, lo.y, hi.x, hi.y);
-      t[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rt, lo1, ot, 0));
-    }
-  };
-  auto sum = [&](int b, const double4 (&p)[U], const double (&t)[U]) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) pair(p[u], t[u], sj + S * (U * b + u));
-  };
-  double4 pa[U], pb[U];
-  double ta[U], tb[U];
-  load(0, pa, ta);
-  for (int b = 0; b < nb; b += 2) {
-    if (b + 1 < nb) load(b + 1, pb, tb);
-    sum(b, pa, ta);
-    if (b + 1 >= nb) break;
-    if (b + 2 < nb) load(b + 2, pa, ta);
-    sum(b + 1, pb, tb);
   }
-
-  // fixed-order sum over the 64 streams: eight groups of eight, then the
-  // groups
-  red[0][tid] = fx;
-  red[1][tid] = fy;
-  red[2][tid] = fz;
-  red[3][tid] = nx;
-  red[4][tid] = ny;
-  red[5][tid] = nz;
+  red[0][wave][lane] = fx;
+  red[1][wave][lane] = fy;
+  red[2][wave][lane] = fz;
+  red[3][wave][lane] = nx;
+  red[4][wave][lane] = ny;
+  red[5][wave][lane] = nz;
   __syncthreads();
-  if (tid < 6 * kPairTile * 8) {
-    const int c = tid >> 6, b = (tid >> 3) & 7, q = tid & 7;
-    // streams 8q .. 8q+7 of body b: threads 64q + 8u + b
+  if (threadIdx.x < 6 * kPairBlock) {
+    const int cpt = threadIdx.x >> 6, q = threadIdx.x & 63;
     double t = 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) t += red[c][64 * q + 8 * u + b];
-    red2[c][b][q] = t;
+    for (int w = 0; w < kPairW; ++w) t += red[cpt][w][q];
+    a.pp[((size_t)sp * 6 + cpt) * a.np + ib * kPairBlock + q] = t;
   }
-  __syncthreads();
-  if (wave != 0) return;
+}
+
+// Per body: the splits' partial sums added in split order, then
+//   CLOSE  second Sun kick (x += tau/2 P/m0, P from the drift's momentum
+//          partials and each BS group's change, added in the same order by
+//          every workgroup), v += tau/2 a, next radii (Eq. 6) and the reuse
+//          check; the cached far sum; the shifted positions to xs
+//   INIT   the far sum and xs = x (the first step's opening kick)
+//   ACC    the acceleration out
+template <int MODE>
+__global__ __launch_bounds__(kFinThreads) void k_pair_finish(PairArgs a,
+                                                             const double4* __restrict__ x) {
+  const int lane = threadIdx.x;
+  const int i = blockIdx.x * kFinThreads + lane;
   double Px = 0.0, Py = 0.0, Pz = 0.0;
   if (MODE == KICK_CLOSE) {
-    // momentum after the drift and BS for the second Sun kick: drift
-    // partials plus each group's change, strided over the lanes, then a
-    // butterfly (every workgroup adds the same terms in the same order)
     for (int b = lane; b < a.nblk; b += 64) {
       Px += a.partP2[4 * b + 0];
       Py += a.partP2[4 * b + 1];
@@ -265,25 +259,29 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs(PairArgs a, const double
     }
   }
   if (MODE == KICK_INIT && blockIdx.x == 0 && lane == 0) a.st->ctl = 0u;
-  if (lane >= kPairTile || !iv) return;
-  double S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0;
+  if (i >= a.n) return;
+  double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // eight splits' loads in flight at a time, added in split order
+  for (int s0 = 0; s0 < a.njs; s0 += 8) {
+    double v[8][6];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    S0 += red2[0][lane][q];
-    S1 += red2[1][lane][q];
-    S2 += red2[2][lane][q];
-    S3 += red2[3][lane][q];
-    S4 += red2[4][lane][q];
-    S5 += red2[5][lane][q];
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        v[u][c] = s0 + u < a.njs ? a.pp[((size_t)(s0 + u) * 6 + c) * a.np + i] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) S[c] += v[u][c];
   }
   const double G = a.G;
   if (MODE == KICK_ACC) {
-    a.acc_out[3 * (size_t)i + 0] = G * (S0 + S3);
-    a.acc_out[3 * (size_t)i + 1] = G * (S1 + S4);
-    a.acc_out[3 * (size_t)i + 2] = G * (S2 + S5);
+    a.acc_out[3 * (size_t)i + 0] = G * (S[0] + S[3]);
+    a.acc_out[3 * (size_t)i + 1] = G * (S[1] + S[4]);
+    a.acc_out[3 * (size_t)i + 2] = G * (S[2] + S[5]);
     return;
   }
-  a.afar[i] = make_double4(G * S0, G * S1, G * S2, 0.0);
+  a.afar[i] = make_double4(G * S[0], G * S[1], G * S[2], 0.0);
   double4 p = x[i];
   if (MODE == KICK_INIT) {
     a.rc_next[i] = a.rc[i];
@@ -295,14 +293,29 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs(PairArgs a, const double
   p.z += a.h * Pz / a.m0;
   a.xs[i] = p;
   double4 v = a.vv[i];
-  v.x += a.h * (G * (S0 + S3));
-  v.y += a.h * (G * (S1 + S4));
-  v.z += a.h * (G * (S2 + S5));
+  v.x += a.h * (G * (S[0] + S[3]));
+  v.y += a.h * (G * (S[1] + S[4]));
+  v.z += a.h * (G * (S[2] + S[5]));
   a.vv[i] = v;
   const double rcn =
       rcrit(p.x, p.y, p.z, v.x, v.y, v.z, p.w, a.mu, a.m0, a.n1, a.n2, a.absdt);
   a.rc_next[i] = rcn;
   if (!a.encounter_free && rcn > a.pf * a.rc[i]) atomicOr(&a.st->ctl, C_FULLKICK);
+}
+
+// Largest threshold of a 256-thread block (threads past the bodies hold
+// kTiny), written to thrmax[blockIdx.x] by thread 0.
+__device__ __forceinline__ void block_thrmax(double t, double* thrmax, double* sh) {
+  t = wave_max(t);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = sh[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, sh[k]);
+    thrmax[blockIdx.x] = m;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -319,6 +332,7 @@ struct OpenArgs {
   const double* __restrict__ rc_next;
   double* __restrict__ rc_cur;
   double* __restrict__ thr;
+  double* __restrict__ thrmax;
   const int* __restrict__ ccnt;
   const int* __restrict__ ctab;
   double* __restrict__ partP;
@@ -402,6 +416,7 @@ __device__ __forceinline__ void sum_partners(const int (&jj)[N], int c0, int cnt
 __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
   __shared__ double sh[3 * (kVecBlock / 64)];
   __shared__ unsigned kh[kKepBins];  // this block's drifts by iteration count
+  double tloc = kTiny;               // the lane's candidate threshold
   if (threadIdx.x < kKepBins) kh[threadIdx.x] = 0u;
   __syncthreads();
   const int i = blockIdx.x * kVecBlock + threadIdx.x;
@@ -477,7 +492,8 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
     v.y += a.h * ay;
     v.z += a.h * az;
     a.rc_cur[i] = rci;
-    a.thr[i] = a.encounter_free ? kTiny : fmax(a.pf2 * rci * rci, kTiny);
+    tloc = a.encounter_free ? kTiny : fmax(a.pf2 * rci * rci, kTiny);
+    a.thr[i] = tloc;
     m = p.w;
     kx = v.x;
     ky = v.y;
@@ -508,6 +524,7 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
   block_sum3<kVecBlock>(Qx, Qy, Qz, sh);  // its barriers also order kh
   if (threadIdx.x < kKepBins)
     a.khist[(size_t)blockIdx.x * kKepBins + threadIdx.x] += kh[threadIdx.x];
+  block_thrmax(tloc, a.thrmax, sh);
   if (threadIdx.x == 0) {
     a.partP[4 * blockIdx.x + 0] = Px;
     a.partP[4 * blockIdx.x + 1] = Py;
@@ -1047,21 +1064,22 @@ __global__ void k_unpack(const double4* __restrict__ xm, const double4* __restri
 }
 
 // Radii of the first step (Eq. 6), thresholds, empty candidate table.
-__global__ void k_rcrit_init(const double4* __restrict__ xm, const double4* __restrict__ vv,
-                             double* __restrict__ rc, double* __restrict__ thr,
-                             int* __restrict__ ccnt, int n, double mu, double m0,
-                             double n1, double n2, double absdt, double pf2,
-                             int enc_free) {
+__global__ __launch_bounds__(256) void k_rcrit_init(
+    const double4* __restrict__ xm, const double4* __restrict__ vv, double* __restrict__ rc,
+    double* __restrict__ thr, double* __restrict__ thrmax, int* __restrict__ ccnt, int n,
+    double mu, double m0, double n1, double n2, double absdt, double pf2, int enc_free) {
+  __shared__ double sh[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;  // grid: the padded count
-  if (i >= n) {
-    thr[i] = kTiny;
-    return;
+  double t = kTiny;
+  if (i < n) {
+    const double4 p = xm[i], q = vv[i];
+    const double r = rcrit(p.x, p.y, p.z, q.x, q.y, q.z, p.w, mu, m0, n1, n2, absdt);
+    rc[i] = r;
+    t = enc_free ? kTiny : fmax(pf2 * r * r, kTiny);
+    ccnt[i] = 0;
   }
-  const double4 p = xm[i], q = vv[i];
-  const double r = rcrit(p.x, p.y, p.z, q.x, q.y, q.z, p.w, mu, m0, n1, n2, absdt);
-  rc[i] = r;
-  thr[i] = enc_free ? kTiny : fmax(pf2 * r * r, kTiny);
-  ccnt[i] = 0;
+  thr[i] = t;
+  block_thrmax(t, thrmax, sh);
 }
 
 // Per-body energy terms and angular momentum; rows[8 i + k]:
@@ -1113,31 +1131,41 @@ __global__ __launch_bounds__(256) void k_energy_final(const double* __restrict__
 }
 
 // Candidate thresholds from given radii: max((pf rc)^2, tiny).
-__global__ void k_thresholds(const double* __restrict__ rc, double* __restrict__ thr,
-                             int* __restrict__ ccnt, int n, double pf2, int enc_free) {
+__global__ __launch_bounds__(256) void k_thresholds(const double* __restrict__ rc,
+                                                    double* __restrict__ thr,
+                                                    double* __restrict__ thrmax,
+                                                    int* __restrict__ ccnt, int n, double pf2,
+                                                    int enc_free) {
+  __shared__ double sh[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;  // grid: the padded count
-  if (i >= n) {
-    thr[i] = kTiny;
-    return;
+  double t = kTiny;
+  if (i < n) {
+    t = enc_free ? kTiny : fmax(pf2 * rc[i] * rc[i], kTiny);
+    ccnt[i] = 0;
   }
-  thr[i] = enc_free ? kTiny : fmax(pf2 * rc[i] * rc[i], kTiny);
-  ccnt[i] = 0;
+  thr[i] = t;
+  block_thrmax(t, thrmax, sh);
 }
 
 // Radii given by the caller: installed with their thresholds (zero and the
 // smallest threshold when rc_in is null, the K = 1 map).
-__global__ void k_radii_in(const double* __restrict__ rc_in, double* __restrict__ rc,
-                           double* __restrict__ thr, int* __restrict__ ccnt, int n, double pf2,
-                           int enc_free) {
+__global__ __launch_bounds__(256) void k_radii_in(const double* __restrict__ rc_in,
+                                                  double* __restrict__ rc,
+                                                  double* __restrict__ thr,
+                                                  double* __restrict__ thrmax,
+                                                  int* __restrict__ ccnt, int n, double pf2,
+                                                  int enc_free) {
+  __shared__ double sh[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;  // grid: the padded count
-  if (i >= n) {
-    thr[i] = kTiny;
-    return;
+  double t = kTiny;
+  if (i < n) {
+    const double r = rc_in ? rc_in[i] : 0.0;
+    rc[i] = r;
+    t = enc_free ? kTiny : fmax(pf2 * r * r, kTiny);
+    ccnt[i] = 0;
   }
-  const double r = rc_in ? rc_in[i] : 0.0;
-  rc[i] = r;
-  thr[i] = enc_free ? kTiny : fmax(pf2 * r * r, kTiny);
-  ccnt[i] = 0;
+  thr[i] = t;
+  block_thrmax(t, thrmax, sh);
 }
 
 // Masses out of the packed state.
@@ -1158,6 +1186,9 @@ PairArgs pair_args(const MassiveWs& w, const StepConsts& c) {
   a.ccnt = w.ccnt;
   a.ctab = w.ctab;
   a.cr2 = w.cr2;
+  a.thrmax = w.thrmax;
+  a.pp = w.pp;
+  a.njs = w.njs;
   a.xs = w.xs;
   a.vv = w.vv;
   a.afar = w.afar;
@@ -1181,6 +1212,9 @@ PairArgs pair_args(const MassiveWs& w, const StepConsts& c) {
   a.pf = c.pf;
   return a;
 }
+
+// Workgroups of the pair kernel: 64-body blocks x splits.
+inline unsigned pair_grid(const MassiveWs& w) { return (unsigned)(w.np / kPairBlock * w.njs); }
 
 }  // namespace
 
@@ -1243,10 +1277,22 @@ size_t massive_ws_bytes(int n, const genga_params& p, bool snap) {
 
 // Lay the main-mode arrays out in the workspace starting at base (nullptr:
 // only size the layout).  Returns the bytes used.
+// Splits of the partner range per 64-body block of the pair kernel: the
+// largest divisor of np / (16 waves x 2 partners) with splits x np at most
+// kPairTarget, so that small systems still spread over the whole chip
+// (2048 bodies: 8 splits, 4096 waves) and every wave takes whole batches.
+int pair_splits(int np) {
+  const int q = np / (kPairW * kPairU);
+  int best = 1;
+  for (int d = 1; d <= q; ++d)
+    if (q % d == 0 && (size_t)d * np <= (size_t)kPairTarget) best = d;
+  return best;
+}
+
 size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base, bool snap) {
   w.n = n;
   w.np = ceil_div(n, 256) * 256;
-  w.npair = ceil_div(n, kPairTile);
+  w.njs = pair_splits(w.np);
   w.nblk = ceil_div(n, kVecBlock);
   w.cpb = p.cand_per_body;
   w.enc_cap = p.enc_cap;
@@ -1266,6 +1312,8 @@ size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base, boo
   w.rc_cur = (double*)take(np * sizeof(double));
   w.rc_next = (double*)take(np * sizeof(double));
   w.thr = (double*)take(np * sizeof(double));
+  w.thrmax = (double*)take((size_t)w.nblk * sizeof(double));
+  w.pp = (double*)take((size_t)w.njs * 6 * np * sizeof(double));
   w.partP = (double*)take((size_t)w.nblk * 4 * sizeof(double));
   w.partP2 = (double*)take((size_t)w.nblk * 4 * sizeof(double));
   w.dP = (double*)take((np / 2 + 1) * 4 * sizeof(double));
@@ -1309,11 +1357,13 @@ hipError_t massive_unpack(const MassiveWs& w, const StepConsts& c, double* x,
 
 hipError_t massive_prime(const MassiveWs& w, const StepConsts& c, hipStream_t s) {
   hipLaunchKernelGGL(k_rcrit_init, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xm, w.vv,
-                     w.rc_cur, w.thr, w.ccnt, w.n, c.mu, c.m0, c.n1, c.n2, fabs(c.dt),
+                     w.rc_cur, w.thr, w.thrmax, w.ccnt, w.n, c.mu, c.m0, c.n1, c.n2, fabs(c.dt),
                      c.pf2, c.encounter_free);
   PairArgs a = pair_args(w, c);
-  hipLaunchKernelGGL(k_pairs<KICK_INIT>, dim3(w.npair), dim3(kPairThreads), 0, s, a,
+  hipLaunchKernelGGL(k_pair_part<KICK_INIT>, dim3(pair_grid(w)), dim3(kPairThreads), 0, s, a,
                      (const double4*)w.xm, (const double*)w.thr);
+  hipLaunchKernelGGL(k_pair_finish<KICK_INIT>, dim3(ceil_div(w.n, kFinThreads)), dim3(kFinThreads),
+                     0, s, a, (const double4*)w.xm);
   // the momentum for the first step's first Sun kick
   double* P2 = reinterpret_cast<double*>(reinterpret_cast<char*>(w.st) + offsetof(DevStat, P2));
   hipLaunchKernelGGL(k_momentum, dim3(1), dim3(1024), 0, s, nullptr, nullptr, w.xm, w.vv, w.n, P2);
@@ -1324,8 +1374,10 @@ hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, const double4*
                          double* acc, hipStream_t s) {
   PairArgs a = pair_args(w, c);
   a.acc_out = acc;
-  hipLaunchKernelGGL(k_pairs<KICK_ACC>, dim3(w.npair), dim3(kPairThreads), 0, s, a, x,
+  hipLaunchKernelGGL(k_pair_part<KICK_ACC>, dim3(pair_grid(w)), dim3(kPairThreads), 0, s, a, x,
                      (const double*)w.thr);
+  hipLaunchKernelGGL(k_pair_finish<KICK_ACC>, dim3(ceil_div(w.n, kFinThreads)), dim3(kFinThreads),
+                     0, s, a, x);
   return hipGetLastError();
 }
 
@@ -1355,6 +1407,7 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
   o.rc_next = w.rc_next;
   o.rc_cur = w.rc_cur;
   o.thr = w.thr;
+  o.thrmax = w.thrmax;
   o.ccnt = w.ccnt;
   o.ctab = w.ctab;
   o.partP = w.partP;
@@ -1419,8 +1472,10 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
   }
 
   PairArgs a = pair_args(w, c);
-  STEP_LAUNCH(4, k_pairs<KICK_CLOSE>, dim3(w.npair), dim3(kPairThreads), a, (const double4*)w.xm,
-              (const double*)w.thr);
+  STEP_LAUNCH(4, k_pair_part<KICK_CLOSE>, dim3(pair_grid(w)), dim3(kPairThreads), a,
+              (const double4*)w.xm, (const double*)w.thr);
+  STEP_LAUNCH(5, k_pair_finish<KICK_CLOSE>, dim3(ceil_div(w.n, kFinThreads)), dim3(kFinThreads), a,
+              (const double4*)w.xm);
   return hipGetLastError();
 }
 
@@ -1440,7 +1495,7 @@ hipError_t validate_finite(const double* a, int64_t cnt, int* dbad, hipStream_t 
 
 hipError_t thresholds_from_radii(const MassiveWs& w, const StepConsts& c, hipStream_t s) {
   hipLaunchKernelGGL(k_thresholds, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.rc_cur, w.thr,
-                     w.ccnt, w.n, c.pf2, c.encounter_free);
+                     w.thrmax, w.ccnt, w.n, c.pf2, c.encounter_free);
   return hipGetLastError();
 }
 
@@ -1449,7 +1504,7 @@ hipError_t accel_run(const MassiveWs& w, const StepConsts& c, const double* m, c
   hipLaunchKernelGGL(k_pack, dim3(ceil_div(w.np, 256)), dim3(256), 0, s, m, x, x,
                      (const double*)nullptr, w.xm, w.vv, w.xs, w.n, w.np, 0, c.m0);
   hipLaunchKernelGGL(k_radii_in, dim3(ceil_div(w.n, 256)), dim3(256), 0, s,
-                     c.encounter_free ? nullptr : rc, w.rc_cur, w.thr, w.ccnt, w.n, c.pf2,
+                     c.encounter_free ? nullptr : rc, w.rc_cur, w.thr, w.thrmax, w.ccnt, w.n, c.pf2,
                      c.encounter_free);
   return massive_accel(w, c, w.xm, acc, s);
 }
@@ -1458,13 +1513,17 @@ hipError_t accel_run(const MassiveWs& w, const StepConsts& c, const double* m, c
 // Scratch of accel_noalloc_run: the packed bodies (x, y, z, m), the velocity
 // and start-position rows the packing kernel also fills, radii, thresholds
 // and candidate counts of up to kNoAllocBodies bodies (116 bytes per padded
-// body, 1.9 MB).  Each GPU holds its own copy until the process ends; every
-// call on a GPU uses that GPU's copy, so calls that overlap on one GPU race.
-// Every byte a call reads is written earlier in the same call.
+// body), the blocks' largest thresholds and the pair kernel's partial sums
+// (6 doubles x splits x padded bodies, splits x padded bodies <=
+// kPairTarget): 2.7 MB.  Each GPU holds its own copy until the process ends;
+// every call on a GPU uses that GPU's copy, so calls that overlap on one GPU
+// race.  Every byte a call reads is written earlier in the same call.
 constexpr int kNoAllocBodies = kAccelNoAllocMax;
 static_assert(kNoAllocBodies % 256 == 0, "bodies are padded to multiples of 256");
+static_assert(kNoAllocBodies <= kPairTarget, "partial sums sized by kPairTarget");
 constexpr size_t kNoAllocBytes =
-    (size_t)kNoAllocBodies * (3 * sizeof(double4) + 2 * sizeof(double) + sizeof(int));
+    (size_t)kNoAllocBodies * (3 * sizeof(double4) + 2 * sizeof(double) + sizeof(int)) +
+    (size_t)kNoAllocBodies / 256 * sizeof(double) + (size_t)kPairTarget * 6 * sizeof(double);
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
@@ -1504,7 +1563,7 @@ hipError_t accel_noalloc_run(const StepConsts& c, int n, const double* m, const 
   MassiveWs w{};
   w.n = n;
   w.np = ceil_div(n, 256) * 256;
-  w.npair = ceil_div(n, kPairTile);
+  w.njs = pair_splits(w.np);
   w.nblk = ceil_div(n, kVecBlock);
   const size_t np = (size_t)w.np;
   char* q = static_cast<char*>(base);
@@ -1520,6 +1579,10 @@ hipError_t accel_noalloc_run(const StepConsts& c, int n, const double* m, const 
   q += np * sizeof(double);
   w.ccnt = reinterpret_cast<int*>(q);
   q += np * sizeof(int);
+  w.thrmax = reinterpret_cast<double*>(q);
+  q += (size_t)kNoAllocBodies / 256 * sizeof(double);
+  w.pp = reinterpret_cast<double*>(q);
+  q += (size_t)w.njs * 6 * np * sizeof(double);
   if ((size_t)(q - static_cast<char*>(base)) > kNoAllocBytes) return hipErrorInvalidValue;
   return accel_run(w, c, m, x, rc, acc, s);
 }
