@@ -57,9 +57,10 @@ typedef struct genga_params {
                              * 4 or 6: Yoshida's composition of it (Sec. 2.3),
                              * main mode only                              */
     /* Ejections (Sec. 3.2.8) and the minimal body count (Sec. 3.4.6),
-     * batched and main mode: a body farther from its central mass than rcut,
-     * or closer than rcut_sun, leaves the system (0 = no limit); a batched
-     * system with fewer than nmin bodies left stops (0 = never).           */
+     * batched and main mode (main mode: second order with encounters;
+     * test-particle mode: all 0): a body farther from its central mass
+     * than rcut, or closer than rcut_sun, leaves the system (0 = no limit);
+     * a system with fewer than nmin bodies left stops (0 = never).         */
     double rcut, rcut_sun;
     int32_t nmin;
     int32_t reserved;
@@ -127,7 +128,9 @@ enum {
 /* Fill *p with the defaults: G = 1, m0 = 1, dt = 2 pi / 100, n1 = 3,
  * n2 = 0.4 (Sec. 2.1), pf = 3 (Sec. 2.2), bs_tol = 1e-13, bs_max_depth =
  * 20, kepler_max_iter = 40, encounter_free = 0, cand_per_body = 32,
- * enc_cap = 2048, order = 2. */
+ * enc_cap = 16384, order = 2.  The encounter list may hold any number of
+ * pairs (enc_cap); the grouping keeps the first 2048 in LDS and reads the
+ * rest from the list. */
 void genga_params_default(genga_params *p);
 
 /* Device workspace (bytes) a context of this shape needs.  Main mode:
@@ -208,7 +211,7 @@ int genga_step_profiled(genga_ctx *ctx, int64_t nsteps, double *h_kick_us);
  * grouping (App. A), Bulirsch-Stoer of the groups (Sec. 3.2.6), pair kernel
  * of the closing kick (partial sums with the prechecker), the closing
  * kick's per-body epilogue (the partial sums added, second Sun kick,
- * velocity update, next critical radii); the middle three are 0 with
+ * velocity update, next critical radii); the second to fourth are 0 with
  * encounter_free.  The
  * breakdown behind a step's time, not a faster step.  Synchronising; returns
  * the latched status (GENGA_EINVAL for a batched context, a null pointer or
@@ -279,8 +282,9 @@ int genga_candidates(genga_ctx *ctx, int32_t *h_ij, double *h_r2, int cap, int *
 int genga_tp_encounters(genga_ctx *ctx, int64_t *h_tp, int32_t *h_planet, double *h_d2,
                         double *h_rc2, int64_t cap, int64_t *h_n);
 
-/* Physical radii (Sec. 3.2.7), device array, copied.  Batched mode: one per
- * row; any positive radius turns on the mergers described at genga_events.
+/* Physical radii (Sec. 3.2.7), device array, copied.  Batched mode and main
+ * mode (second order, with encounters): one per row; any positive radius
+ * turns on the mergers described at genga_events.
  * Test-particle mode (Sec. 3.3): n_massive + n_test values (planets first).
  * From the next step on,
  * a particle whose separation from a planet, Hermite-interpolated over a
@@ -289,8 +293,9 @@ int genga_tp_encounters(genga_ctx *ctx, int64_t *h_tp, int32_t *h_planet, double
  * later steps skip it, and a report is kept (genga_collisions).  Radii start
  * at 0 (no collisions).  A particle only meets this test inside an encounter,
  * so radii should stay below the critical radii.  Synchronising.  Errors:
- * EINVAL (main mode, negative or non-finite radius; test-particle radii are
- * then reset to 0, batched radii left as they were), EHIP. */
+ * EINVAL (main mode with composed steps or encounter_free, negative or
+ * non-finite radius; test-particle radii are then reset to 0, main-mode and
+ * batched radii left as they were), EHIP. */
 int genga_set_radii(genga_ctx *ctx, const double *d_radii);
 
 /* Reports of the particles removed since init, sorted by (step, particle):
@@ -337,8 +342,11 @@ int genga_batch_set_variant(genga_ctx *ctx, int v);
 int genga_batch_status(genga_ctx *ctx, int32_t *h_status, int64_t *h_steps,
                        int cap);
 
-/* Batched mode, collisions and ejections (Sec. 3.2.7, 3.2.8, 3.4.6).  With
- * physical radii set (genga_set_radii, one per row) two bodies of a group
+/* Collisions and ejections (Sec. 3.2.7, 3.2.8, 3.4.6), batched mode and
+ * main mode (second order with encounters; a main-mode run is one system,
+ * sys = 0).  With physical radii set (genga_set_radii, one per row) two
+ * bodies of a group of up to 64 members (GENGA_EGROUP for larger groups
+ * with radii)
  * that come closer than the sum of their radii during a BS substep (the
  * Hermite test of Eqs. 10-12 applied to the substep) merge at the start of
  * that substep: mass, momentum and orbital-plus-spin angular momentum are
@@ -348,16 +356,19 @@ int genga_batch_status(genga_ctx *ctx, int32_t *h_status, int64_t *h_steps,
  * beyond or inside those distances from their central mass leave after the
  * direct integration.  Each freed row takes the system's last body (freed
  * rows in descending order) and the system's count drops; with fewer than
- * nmin bodies left a system stops (status GENGA_WNMIN).  genga_get_state
- * writes NaN rows past a system's count.
+ * nmin bodies left a system stops (status GENGA_WNMIN; in main mode the
+ * synchronising calls return that warning and later steps change nothing).
+ * genga_get_state writes NaN rows past a system's count.
  * genga_events: every merger and ejection since init (host array of cap
  * records), sorted by (step, system, part of the step, survivor); *h_n
  * receives the count, GENGA_EOVERFLOW when it exceeds cap or the record
- * store (one record per row).  Synchronising.  Errors: EINVAL (other mode).
+ * store (one record per row).  Synchronising.  Errors: EINVAL
+ * (test-particle mode).
  * genga_bodies: per row the original row of the body it holds (-1 past the
  * system's count; host, cap >= the rows), per system the bodies left and
  * the summed internal energy U of its mergers (host, sys_cap >= n_sys).
- * Synchronising.  Errors: EINVAL (other mode), EOVERFLOW (small caps). */
+ * Synchronising.  Errors: EINVAL (test-particle mode), EOVERFLOW (small
+ * caps). */
 int genga_events(genga_ctx *ctx, genga_event *h_ev, int64_t cap, int64_t *h_n);
 int genga_bodies(genga_ctx *ctx, int32_t *h_id, int64_t cap, int32_t *h_nlive, double *h_U,
                  int sys_cap);

@@ -57,6 +57,11 @@ constexpr int kBatchMaxSystems = 1 << 24;
 bool shape_ok(int mode, const genga_params* p, int nm, int64_t ntp, int nsys = 0,
               int64_t nbod = 0) {
   if (p->order > 2 && mode != GENGA_MASSIVE) return false;  // compositions: main mode
+  // bodies leaving (rcut, rcut_sun, nmin): main mode at second order with
+  // encounters, and batched mode
+  const bool leave = p->rcut > 0.0 || p->rcut_sun > 0.0 || p->nmin > 0;
+  if (leave && mode == GENGA_TEST) return false;
+  if (leave && mode == GENGA_MASSIVE && (p->order > 2 || p->encounter_free)) return false;
   if (mode == GENGA_MASSIVE) return nm >= 1 && nm <= max_bodies(p) && ntp == 0;
   if (mode == GENGA_TEST) return nm >= 1 && nm <= kTpMaxPlanets && ntp >= 0 && ntp <= kTpMaxParticles;
   if (mode == GENGA_BATCH)
@@ -110,6 +115,16 @@ struct genga_ctx {
   do {                                        \
     if ((expr) != hipSuccess) return GENGA_EHIP; \
   } while (0)
+
+// Captured step graphs are dropped when the step's launches change.
+static void drop_graphs(genga_ctx* ctx) {
+  if (ctx->g_many) (void)hipGraphExecDestroy(ctx->g_many);
+  ctx->g_many = nullptr;
+  for (hipGraphExec_t& g : ctx->g_rem) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
 
 static int capture(genga_ctx* ctx, int nsteps, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
@@ -362,7 +377,7 @@ void genga_params_default(genga_params* p) {
   p->kepler_max_iter = 40;
   p->encounter_free = 0;
   p->cand_per_body = 32;
-  p->enc_cap = 2048;
+  p->enc_cap = 16384;
 }
 
 size_t genga_workspace_bytes(int mode, const genga_params* p, int n_massive, int64_t n_test,
@@ -401,7 +416,8 @@ int genga_init(genga_ctx** out, int mode, const genga_params* p, int n_massive, 
   if (rc == GENGA_OK &&
       (hipMemsetAsync(ctx->w.st, 0, sizeof(DevStat), ctx->stream) != hipSuccess ||
        hipMemsetAsync(ctx->w.khist, 0, (size_t)ctx->w.nblk * kKepBins * sizeof(unsigned long long),
-                      ctx->stream) != hipSuccess))
+                      ctx->stream) != hipSuccess ||
+       massive_reset_bodies(ctx->w, true, ctx->stream) != hipSuccess))
     rc = GENGA_EHIP;
   if (rc == GENGA_OK && tp &&
       (hipMemsetAsync(ctx->t.rad, 0, (kTpMaxPlanets + std::max<int64_t>(n_test, 1)) * sizeof(double),
@@ -449,8 +465,10 @@ static int step_timed(genga_ctx* ctx, int64_t nsteps, bool all, double* us) {
   std::vector<hipEvent_t> ev((size_t)(2 * K * nsteps), nullptr);
   const bool enc = !ctx->c.encounter_free;
   // the pair kernel always; with all, every kernel the step launches
-  auto timed = [&](int k) { return k == 4 || (all && (enc || k == 0 || k == 5)); };
-  const int klast = all ? K - 1 : 4;  // the last timed slot of a step
+  auto timed = [&](int k) {
+    return k == kSlotPairs || (all && (enc || k == 0 || k == K - 1));
+  };
+  const int klast = all ? K - 1 : kSlotPairs;  // the last timed slot of a step
   int rc = GENGA_OK;
   for (int64_t t = 0; t < nsteps && rc == GENGA_OK; ++t)
     for (int k = 0; k < K && rc == GENGA_OK; ++k)
@@ -488,7 +506,7 @@ int genga_step_profiled(genga_ctx* ctx, int64_t nsteps, double* h_kick_us) {
     return GENGA_EINVAL;
   double us[kStepKernels];
   const int r = step_timed(ctx, nsteps, false, us);
-  if (r >= 0) *h_kick_us = us[4];
+  if (r >= 0) *h_kick_us = us[kSlotPairs];
   return r;
 }
 
@@ -780,6 +798,33 @@ int genga_set_radii(genga_ctx* ctx, const double* d_radii) {
     ctx->b.coll = any ? 1 : 0;
     return GENGA_OK;
   }
+  if (ctx->mode == GENGA_MASSIVE) {
+    // one radius per row (bodies that left keep theirs); any positive one
+    // turns the collision tests on (second order with encounters only)
+    if (ctx->sub.size() != 1 || ctx->p.encounter_free) return GENGA_EINVAL;
+    const int n = ctx->w.n;
+    std::vector<double> r((size_t)n);
+    HIPCHK(hipMemcpyAsync(r.data(), d_radii, r.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    bool any = false;
+    for (double q : r) {
+      if (!(q >= 0.0) || !std::isfinite(q)) return GENGA_EINVAL;
+      any = any || q > 0.0;
+    }
+    HIPCHK(hipMemcpyAsync(ctx->w.rad, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    StepConsts& c = ctx->sub[0];
+    const int coll = any ? 1 : 0;
+    const int phys = coll || c.rcut > 0.0 || c.rcut_sun > 0.0 || c.nmin > 0;
+    if (coll != c.coll || phys != c.phys) {
+      c.coll = coll;
+      c.phys = phys;
+      drop_graphs(ctx);  // the step's launches change
+    }
+    return GENGA_OK;
+  }
   if (ctx->mode != GENGA_TEST) return GENGA_EINVAL;
   HIPCHK(hipMemsetAsync(ctx->w.flag_in, 0, sizeof(int), ctx->stream));
   HIPCHK(tp_set_radii(ctx->t, ctx->w.n, d_radii, ctx->w.flag_in, ctx->stream));
@@ -831,18 +876,21 @@ int genga_collisions(genga_ctx* ctx, int64_t* h_tp, int32_t* h_planet, int64_t* 
 }
 
 int genga_events(genga_ctx* ctx, genga_event* h_ev, int64_t cap, int64_t* h_n) {
-  if (!ctx || !h_n || cap < 0 || (cap > 0 && !h_ev) || ctx->mode != GENGA_BATCH)
+  if (!ctx || !h_n || cap < 0 || (cap > 0 && !h_ev) || ctx->mode == GENGA_TEST)
     return GENGA_EINVAL;
   DevStat hs;
   int r = read_status(ctx, &hs);
   if (r != GENGA_OK) return r;
+  const bool bat = ctx->mode == GENGA_BATCH;
   unsigned long long cnt = 0;
-  HIPCHK(hipMemcpyAsync(&cnt, ctx->b.ev_cnt, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
+  if (bat)
+    HIPCHK(hipMemcpyAsync(&cnt, ctx->b.ev_cnt, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  const int64_t have = std::min<int64_t>((int64_t)cnt, ctx->b.nb);
+  if (!bat) cnt = hs.ev_cnt;
+  const int64_t have = std::min<int64_t>((int64_t)cnt, bat ? ctx->b.nb : (int64_t)ctx->w.ev_cap);
   std::vector<genga_event> ev((size_t)have);
   if (have > 0) {
-    HIPCHK(hipMemcpyAsync(ev.data(), ctx->b.ev, (size_t)have * sizeof(genga_event),
+    HIPCHK(hipMemcpyAsync(ev.data(), bat ? ctx->b.ev : ctx->w.ev, (size_t)have * sizeof(genga_event),
                           hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
   }
@@ -860,7 +908,24 @@ int genga_events(genga_ctx* ctx, genga_event* h_ev, int64_t cap, int64_t* h_n) {
 
 int genga_bodies(genga_ctx* ctx, int32_t* h_id, int64_t cap, int32_t* h_nlive, double* h_U,
                  int sys_cap) {
-  if (!ctx || ctx->mode != GENGA_BATCH || cap < 0 || sys_cap < 0) return GENGA_EINVAL;
+  if (!ctx || ctx->mode == GENGA_TEST || cap < 0 || sys_cap < 0) return GENGA_EINVAL;
+  if (ctx->mode == GENGA_MASSIVE) {
+    if ((cap > 0 && !h_id) || (sys_cap > 0 && (!h_nlive || !h_U))) return GENGA_EINVAL;
+    DevStat hs;
+    int r = read_status(ctx, &hs);
+    if (r != GENGA_OK) return r;
+    const int n = ctx->w.n;
+    std::vector<int32_t> ids((size_t)n);
+    HIPCHK(hipMemcpyAsync(ids.data(), ctx->w.ids, ids.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int q = 0; q < std::min<int64_t>(n, cap); ++q) h_id[q] = q < hs.nlive ? ids[q] : -1;
+    if (sys_cap > 0) {
+      h_nlive[0] = hs.nlive;
+      h_U[0] = hs.U;
+    }
+    return cap < n || sys_cap < 1 ? GENGA_EOVERFLOW : GENGA_OK;
+  }
   const BatchWs& b = ctx->b;
   if ((cap > 0 && !h_id) || (sys_cap > 0 && (!h_nlive || !h_U))) return GENGA_EINVAL;
   std::vector<BatchSysStat> ss((size_t)b.nsys);

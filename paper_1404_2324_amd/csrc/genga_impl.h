@@ -41,6 +41,11 @@ struct DevStat {
   unsigned long long nstep;      // steps begun since init
   unsigned long long tp_removed; // test particles removed by collisions
   double P2[4];        // momentum for the second Sun kick of the step
+  int nlive;           // main mode: bodies present (rows past it are padding)
+  int stopped;         // main mode: fewer than nmin bodies left, steps do nothing
+  double U;            // main mode: summed internal energy of the mergers
+  unsigned long long ev_cnt;  // main mode: mergers and ejections since init
+  double Pej[4];       // main mode: momentum of the bodies ejected in the step
 };
 
 // Report of a test particle removed by a collision with a planet.
@@ -54,7 +59,7 @@ struct CollRec {
 };
 
 constexpr int kKepBins = GENGA_KEPLER_BINS;  // Kepler-iteration histogram bins
-constexpr int kBsMaxGroup = 64;        // members per in-wave BS group
+constexpr int kBsMaxGroup = 64;        // members of the lane-per-member BS path
 constexpr int kGroupMaxN = 2048;       // bodies the one-workgroup grouping holds
 constexpr int kEncLds = 2048;          // encounter pairs grouped in LDS
 constexpr int kVecBlock = 256;         // threads of the per-body kernels
@@ -75,7 +80,7 @@ struct MassiveWs {
   double* rc_cur;       // radii of the current step
   double* rc_next;      // radii for the next step
   double* thr;          // max((pf rc)^2, tiny): candidate threshold
-  double* thrmax;       // largest threshold of each 256-body block [nblk]
+  double* tmax64;       // largest threshold of each 64-body chunk [np/64]
   double* pp;           // pair kernel's partial sums [njs][6][np]
   double* partP;        // momentum partials after the opening kick [nblk][4]
   double* partP2;       // momentum partials after the drift [nblk][4]
@@ -90,6 +95,15 @@ struct MassiveWs {
   double* encrc2;
   int* goff;            // group offsets [np+1]
   int* gmem;            // group members [np]
+  double* rad;          // physical radii (collisions, Sec. 3.2.7) [np]
+  double4* sp;          // spins [np]
+  int* ids;             // original row of the body in each row [np]
+  int* dead;            // bodies leaving in this step [np]
+  genga_event* ev;      // mergers and ejections since init [ev_cap]
+  int ev_cap;
+  double* bsbig;        // BS records of members of groups over 64 [np][66]
+  double4* bspos;       // their Gragg-point positions and masses [np]
+  int* bsmem;           // their sorted member lists (at the group offsets) [np]
   int* flag_in;         // input validation flag
   double4* xstart;      // positions at the start of the step (test-particle mode)
   double4* xpost;       // state after the drift, before BS (test-particle mode)
@@ -149,6 +163,10 @@ struct StepConsts {
   // search over every pair instead of the prechecker's candidates
   double absdt_next;
   int all_pairs;
+  // bodies can leave (Sec. 3.2.7, 3.2.8, 3.4.6): phys adds the compaction
+  // after BS, coll the collision tests inside BS (some radius positive)
+  int phys, coll, nmin;
+  double rcut, rcut_sun;
 };
 
 // Sub-steps of the composed step of the given order (2: one, 4: three, 6:
@@ -172,12 +190,16 @@ hipError_t massive_unpack(const MassiveWs& w, const StepConsts& c, double* x,
                           double* v, int coords_out, hipStream_t s);
 hipError_t massive_prime(const MassiveWs& w, const StepConsts& c,
                          hipStream_t s);
+// Every body present in its own row (count, original rows, spins; radii too
+// with clear_radii).
+hipError_t massive_reset_bodies(const MassiveWs& w, bool clear_radii, hipStream_t s);
 // Kernels of one main-mode step in launch order: opening kick and drift,
 // encounter search, grouping, BS, pair kernel (partial sums), the closing
-// kick's per-body epilogue (encounter search, grouping and BS only with
-// encounters).  With kev (2 kStepKernels events), the events of slot k take
-// the start and end timestamps of kernel k's dispatch.
+// kick's per-body epilogue (the middle three only with encounters).  With
+// kev (2 kStepKernels events), the events of slot k take the start and end
+// timestamps of kernel k's dispatch.
 constexpr int kStepKernels = 6;
+constexpr int kSlotPairs = 4;  // the pair kernel's slot
 hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
                         const hipEvent_t* kev = nullptr);
 hipError_t massive_energy(const MassiveWs& w, const StepConsts& c, double* dE,

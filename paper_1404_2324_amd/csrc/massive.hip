@@ -1,7 +1,8 @@
 // Main-mode kernels of the hybrid symplectic step (Grimm & Stadel,
 // arXiv:1404.2324, Sec. 2.2 step recipe and Sec. 3.2 kernels), for gfx950.
 //
-// One step is six launches on one stream (captured once into a HIP graph):
+// One step is six launches on one stream (captured once into a HIP graph;
+// a seventh, the compaction, when bodies can leave):
 //   k_open_drift   opening kick: cached non-candidate acceleration + candidate
 //                  pairs recomputed with the new radii (KickA/KickB, Sec 3.2.3);
 //                  Sun kick tau/2 (Eq. 3) + pre-drift copy + Kepler drift
@@ -91,7 +92,7 @@ constexpr int kFinThreads = 64;                // threads of the finishing kerne
 
 struct PairArgs {
   const double* __restrict__ rc;      // radii of the step
-  const double* __restrict__ thrmax;  // largest threshold of each 256-body block
+  const double* __restrict__ tmax64;  // largest threshold of each 64-body chunk
   int* __restrict__ ccnt;             // candidate table (appended)
   int* __restrict__ ctab;
   double* __restrict__ cr2;
@@ -122,43 +123,44 @@ enum { KICK_CLOSE = 0, KICK_INIT = 1, KICK_ACC = 2 };
 // candidate: its K-weighted term is summed apart ("near") and, outside the
 // accumulation mode, appended to the body's candidate table; every other
 // pair has K = 1 and joins the "far" sum that the next opening kick reuses
-// (KickB).  The common test is one compare against the largest threshold T
-// of the step: below it the term is held out of the far sum by a select, and
-// a wave with any such lane takes the exact test for those lanes.  The 16
-// waves' sums are added in LDS in wave order; the split's sums go to pp.
+// (KickB).  The common test is one compare against the wave's largest
+// threshold T (over its 64 bodies and its partner range, from the 64-body
+// chunk maxima): below it the term is held out of the far sum by a select,
+// and a wave with any such lane takes the exact test for those lanes.  The
+// 16 waves' sums are added in LDS in wave order; the split's sums go to pp.
 template <int MODE>
 __global__ __launch_bounds__(kPairThreads) void k_pair_part(PairArgs a,
                                                             const double4* __restrict__ x,
                                                             const double* __restrict__ thr) {
   __shared__ double red[6][kPairW][kPairBlock];
-  __shared__ double tmax_sh;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ib = blockIdx.x / a.njs, sp = blockIdx.x - ib * a.njs;
-  if (wave == 0) {
-    double t = kTiny;
-    for (int k = lane; k < a.nblk; k += 64) t = fmax(t, a.thrmax[k]);
-    t = wave_max(t);
-    if (lane == 0) tmax_sh = t;
-  }
+  // a context's step: stopped runs do nothing, and rows past the count are
+  // padding (bodies that left); the acceleration form has no status word
+  // (st may be null) and takes every body
+  if (MODE != KICK_ACC && a.st->stopped) return;
+  const int nl = MODE == KICK_ACC ? a.n : a.st->nlive;
   const int i = ib * kPairBlock + lane;
-  const bool iv = i < a.n;
-  const double4 pi = x[i];
-  const double ti = thr[i];
+  const bool iv = i < nl;
   const int L = a.np / (a.njs * kPairW);
   const int j0 = __builtin_amdgcn_readfirstlane((sp * kPairW + wave) * L);
+  const double4* xj = x + j0;
+  double4 cur[kPairU], nxt[kPairU];
+#pragma unroll
+  for (int q = 0; q < kPairU; ++q) nxt[q] = xj[q];
+  const double4 pi = x[i];
+  const double ti = thr[i];
+  // T = the largest threshold of the wave's bodies and of its partners
+  double T = a.tmax64[ib];
+  for (int c = (j0 >> 6) + lane; c <= (j0 + L - 1) >> 6; c += 64) T = fmax(T, a.tmax64[c]);
+  T = wave_max(T);
   double fx = 0.0, fy = 0.0, fz = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
   // the series constants of m_rinv3 in registers for the whole loop (an
   // empty asm statement hides their values, so that they are not re-made
   // from literals for every pair)
   double c1875 = 1.875, c15 = 1.5;
   asm volatile("" : "+v"(c1875), "+v"(c15));
-  __syncthreads();
-  const double T = tmax_sh;
-  const double4* xj = x + j0;
-  double4 cur[kPairU], nxt[kPairU];
-#pragma unroll
-  for (int q = 0; q < kPairU; ++q) nxt[q] = xj[q];
   for (int k = 0; k < L; k += kPairU) {
 #pragma unroll
     for (int q = 0; q < kPairU; ++q) cur[q] = nxt[q];
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_part(PairArgs a,
             fx = fma(s, dx, fx);
             fy = fma(s, dy, fy);
             fz = fma(s, dz, fz);
-          } else if (iv && j != i && j < a.n) {
+          } else if (iv && j != i && j < nl) {
             const double ir = rsqrt_nr(r2);
             const double ir2 = ir * ir;
             double K = 1.0, dK = 0.0;
@@ -236,6 +238,7 @@ __global__ __launch_bounds__(kFinThreads) void k_pair_finish(PairArgs a,
                                                              const double4* __restrict__ x) {
   const int lane = threadIdx.x;
   const int i = blockIdx.x * kFinThreads + lane;
+  if (MODE != KICK_ACC && a.st->stopped) return;  // no status word in the ACC form
   double Px = 0.0, Py = 0.0, Pz = 0.0;
   if (MODE == KICK_CLOSE) {
     for (int b = lane; b < a.nblk; b += 64) {
@@ -252,6 +255,10 @@ __global__ __launch_bounds__(kFinThreads) void k_pair_finish(PairArgs a,
     Px = wave_sum(Px);
     Py = wave_sum(Py);
     Pz = wave_sum(Pz);
+    // bodies ejected after BS take their momentum with them (0 otherwise)
+    Px -= a.st->Pej[0];
+    Py -= a.st->Pej[1];
+    Pz -= a.st->Pej[2];
     if (blockIdx.x == 0 && lane == 0) {
       a.st->P2[0] = Px;
       a.st->P2[1] = Py;
@@ -259,7 +266,7 @@ __global__ __launch_bounds__(kFinThreads) void k_pair_finish(PairArgs a,
     }
   }
   if (MODE == KICK_INIT && blockIdx.x == 0 && lane == 0) a.st->ctl = 0u;
-  if (i >= a.n) return;
+  if (i >= (MODE == KICK_ACC ? a.n : a.st->nlive)) return;
   double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   // eight splits' loads in flight at a time, added in split order
   for (int s0 = 0; s0 < a.njs; s0 += 8) {
@@ -303,19 +310,12 @@ __global__ __launch_bounds__(kFinThreads) void k_pair_finish(PairArgs a,
   if (!a.encounter_free && rcn > a.pf * a.rc[i]) atomicOr(&a.st->ctl, C_FULLKICK);
 }
 
-// Largest threshold of a 256-thread block (threads past the bodies hold
-// kTiny), written to thrmax[blockIdx.x] by thread 0.
-__device__ __forceinline__ void block_thrmax(double t, double* thrmax, double* sh) {
+// Largest threshold of the 64 bodies i0 .. i0 + 63 of a wave (lanes past
+// the bodies hold kTiny), written to tmax64[i0 / 64]: the pair kernel's
+// common candidate test.
+__device__ __forceinline__ void chunk_tmax(double t, int i0, double* tmax64) {
   t = wave_max(t);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[w] = t;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = sh[0];
-    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, sh[k]);
-    thrmax[blockIdx.x] = m;
-  }
+  if ((threadIdx.x & 63) == 0) tmax64[i0 >> 6] = t;
 }
 
 // ---------------------------------------------------------------------------
@@ -332,7 +332,7 @@ struct OpenArgs {
   const double* __restrict__ rc_next;
   double* __restrict__ rc_cur;
   double* __restrict__ thr;
-  double* __restrict__ thrmax;
+  double* __restrict__ tmax64;
   const int* __restrict__ ccnt;
   const int* __restrict__ ctab;
   double* __restrict__ partP;
@@ -419,8 +419,13 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
   double tloc = kTiny;               // the lane's candidate threshold
   if (threadIdx.x < kKepBins) kh[threadIdx.x] = 0u;
   __syncthreads();
+  if (a.st->flags & F_NMIN) {
+    // fewer than nmin bodies left after the last step: the run has stopped
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.st->stopped = 1;
+    return;
+  }
   const int i = blockIdx.x * kVecBlock + threadIdx.x;
-  const bool iv = i < a.n;
+  const bool iv = i < a.st->nlive;
   const bool full = (__builtin_amdgcn_readfirstlane(a.st->ctl) & C_FULLKICK) != 0;
   const double Ps = a.h / a.m0;
   const double sx = Ps * a.st->P2[0], sy = Ps * a.st->P2[1], sz = Ps * a.st->P2[2];
@@ -524,7 +529,7 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
   block_sum3<kVecBlock>(Qx, Qy, Qz, sh);  // its barriers also order kh
   if (threadIdx.x < kKepBins)
     a.khist[(size_t)blockIdx.x * kKepBins + threadIdx.x] += kh[threadIdx.x];
-  block_thrmax(tloc, a.thrmax, sh);
+  chunk_tmax(tloc, i & ~63, a.tmax64);
   if (threadIdx.x == 0) {
     a.partP[4 * blockIdx.x + 0] = Px;
     a.partP[4 * blockIdx.x + 1] = Py;
@@ -592,6 +597,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int* shw, int* total) {
 // any; the candidate count is taken by the grouping kernel instead, since
 // an atomic on one address from every wave serialises them).
 __global__ __launch_bounds__(kVecBlock) void k_encounter(EncArgs a) {
+  if (a.st->flags & F_NMIN) return;  // the run stopped below nmin bodies
   const int t = blockIdx.x * kVecBlock + threadIdx.x;
   const int i = t / a.cpb, k = t - i * a.cpb;
   const int lane = threadIdx.x & 63;
@@ -711,19 +717,35 @@ __global__ __launch_bounds__(256) void k_encounter_all(EncArgs a) {
 // sweeps repeat until nothing changes.  Groups are numbered by their smallest
 // member; offsets and members go to global memory for the BS kernel.  Also
 // clears the candidate table for the closing kick and counts its pairs.
-__global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
-  __shared__ int link[kGroupMaxN];
-  __shared__ int gid[kGroupMaxN];
-  __shared__ int2 pr[kEncLds];
-  __shared__ int gsz[kGroupMaxN / 2 + 1];
-  __shared__ int gof[kGroupMaxN / 2 + 1];
-  __shared__ unsigned char inp[kGroupMaxN];
-  __shared__ int shw[kEncThreads / 64];
-  __shared__ int s_changed;
+// The first kEncLds pairs are held in LDS; pairs beyond (many-pair regimes,
+// up to the list capacity) are read from the encounter list in place, so
+// the workgroup's LINK array, not the pair count, bounds the grouping.
+struct GroupLds {
+  int link[kGroupMaxN];
+  int gid[kGroupMaxN];
+  int2 pr[kEncLds];
+  int gsz[kGroupMaxN / 2 + 1];
+  int gof[kGroupMaxN / 2 + 1];
+  unsigned char inp[kGroupMaxN];
+  int shw[kEncThreads / 64];
+  int s_changed;
+};
+
+// The grouping of ne_all encounter pairs by one workgroup of kEncThreads.
+__device__ __forceinline__ void group_phase(const EncArgs& a, int ne_all, GroupLds& L) {
+  int* link = L.link;
+  int* gid = L.gid;
+  int2* pr = L.pr;
+  int* gsz = L.gsz;
+  int* gof = L.gof;
+  unsigned char* inp = L.inp;
+  int* shw = L.shw;
+  int& s_changed = L.s_changed;
   const int tid = threadIdx.x, lane = tid & 63;
   const int n = a.n;
-  const int ne_all = a.st->nenc;
-  const int ne = min(min(ne_all, kEncLds), a.enc_cap);
+  const int ne = min(ne_all, a.enc_cap);
+  const int nl = min(ne, kEncLds);  // pairs held in LDS
+  auto pair_at = [&](int e) { return e < nl ? pr[e] : a.encij[e]; };
   // the opening kick has read the reuse flag; this step's closing kick sets
   // it again for the next one
   if (tid == 0) a.st->ctl = 0u;
@@ -731,7 +753,7 @@ __global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
     link[i] = i;
     inp[i] = 0;
   }
-  for (int e = tid; e < ne; e += kEncThreads) pr[e] = a.encij[e];
+  for (int e = tid; e < nl; e += kEncThreads) pr[e] = a.encij[e];
   __syncthreads();
   // candidate pairs i < j: every pair sits in both rows (the test is
   // symmetric), so half the sum of the row lengths
@@ -741,8 +763,9 @@ __global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
     a.ccnt[i] = 0;
   }
   for (int e = tid; e < ne; e += kEncThreads) {
-    inp[pr[e].x] = 1;
-    inp[pr[e].y] = 1;
+    const int2 q = pair_at(e);
+    inp[q.x] = 1;
+    inp[q.y] = 1;
   }
   // equivalence classes
   while (true) {
@@ -750,7 +773,8 @@ __global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
     __syncthreads();
     bool ch = false;
     for (int e = tid; e < ne; e += kEncThreads) {
-      const int p1 = pr[e].x, p2 = pr[e].y;
+      const int2 q = pair_at(e);
+      const int p1 = q.x, p2 = q.y;
       const int l1 = link[p1], l2 = link[p2];
       if (l1 != l2) {
         atomicMin(&link[p1], l2);
@@ -825,7 +849,7 @@ __global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
     a.st->ngroups = ng;
     a.st->ncand = nrow / 2;
     a.st->enc_total += (unsigned long long)ne_all;
-    if (ne_all > kEncLds || ne_all > a.enc_cap) atomicOr(&a.st->flags, F_ENC_OVF);
+    if (ne_all > a.enc_cap) atomicOr(&a.st->flags, F_ENC_OVF);
   }
   for (int i = tid; i < n; i += kEncThreads) {
     if (inp[i]) {
@@ -835,6 +859,13 @@ __global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
     }
   }
 }
+
+__global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
+  __shared__ GroupLds L;
+  if (a.st->flags & F_NMIN) return;  // the run stopped below nmin bodies
+  group_phase(a, a.st->nenc, L);
+}
+
 
 // ---------------------------------------------------------------------------
 struct BsArgs {
@@ -846,10 +877,231 @@ struct BsArgs {
   const double* __restrict__ rc;
   const int* __restrict__ goff;
   const int* __restrict__ gmem;
+  double* __restrict__ big;    // per-body records of groups over 64 members
+  double4* __restrict__ bpos;  // their positions and masses at a Gragg point
+  int* __restrict__ bmem;      // their members, sorted, at the group's offset
+  double* __restrict__ rc_w;   // this step's radii (a merged body keeps the larger)
+  double* __restrict__ rad;    // physical radii (collisions)
+  double4* __restrict__ sp;    // spins
+  const int* __restrict__ ids; // original rows
+  int* __restrict__ dead;      // absorbed bodies of this step
+  genga_event* __restrict__ ev;
   DevStat* __restrict__ st;
   double G, Gm0, dt, tol;
-  int max_depth;
+  int max_depth, coll, ev_cap;
 };
+
+// ---- groups of more than 64 members ------------------------------------------
+// One wave integrates the group with the BS scheme of the smaller paths (the
+// same column sequence, Aitken-Neville tableau, error norm and halving), each
+// lane taking the members lane, lane + 64, ...  The state of member id lives
+// in the record big[id][kBigRec] (groups are disjoint, so records are too):
+// substep start y0, the Gragg points z_{s-1} and z_s, the tableau R[8][6];
+// the positions of the current Gragg point are published in bpos[id] for the
+// pair sums, between barriers (a one-wave workgroup: the barrier orders the
+// lanes' global stores and loads).  Members are sorted ascending, so every
+// sum runs in a fixed order.  The cost grows as sz^2 per force evaluation:
+// a fallback for rare large groups (the paper steers those from the CPU,
+// Sec. 3.2.6), not a fast path.
+constexpr int kBigRec = 66;  // y0[6], zp[6], zc[6], R[8][6]
+constexpr int kBigY0 = 0, kBigZp = 6, kBigZc = 12, kBigR = 18;
+
+// dv/dt of H_A for member m at (x, y, z): the fixed star and every other
+// member's (1-K)-weighted pair term in member order (the formula of
+// ha_accel).
+__device__ __forceinline__ void ha_accel_big(const BsArgs& a, const int* mem, int sz, int m,
+                                             double x, double y, double z, double rc,
+                                             double& ax, double& ay, double& az) {
+  const double r2 = x * x + y * y + z * z;
+  const double ir = rsqrt_nr(r2);
+  const double fs = -a.Gm0 * (ir * ir * ir);
+  ax = fs * x;
+  ay = fs * y;
+  az = fs * z;
+  for (int q = 0; q < sz; ++q) {
+    const int jd = mem[q];
+    const double4 pj = a.bpos[jd];
+    const double dx = pj.x - x, dy = pj.y - y, dz = pj.z - z;
+    const double q2 = dx * dx + dy * dy + dz * dz;
+    const double rij = fmax(rc, a.rc[jd]);
+    if (q != m && q2 < rij * rij * (1.0 + 1e-12)) {
+      const double iq = rsqrt_nr(q2);
+      const double iq2 = iq * iq;
+      double K, dK;
+      changeover(q2 * iq, rij, K, dK);
+      const double sc = a.G * pj.w * ((1.0 - K) * iq2 * iq + dK * iq2);
+      ax += sc * dx;
+      ay += sc * dy;
+      az += sc * dz;
+    }
+  }
+}
+
+// Positions of the Gragg point held at record offset off published to bpos.
+__device__ __forceinline__ void big_publish(const BsArgs& a, const int* mem, int sz, int off) {
+  for (int m = threadIdx.x; m < sz; m += 64) {
+    const int id = mem[m];
+    const double* r = a.big + (size_t)id * kBigRec + off;
+    a.bpos[id] = make_double4(r[0], r[1], r[2], a.xm[id].w);
+  }
+  __syncthreads();
+}
+
+// One attempt over H (columns n_k = 2k, k = 1..8, accepted at the first
+// column k >= 2 within tol); on success y0 of every member becomes the
+// accepted state.  Returns whether it was accepted (wave-uniform).
+__device__ bool big_attempt(const BsArgs& a, const int* mem, int sz, double H) {
+  for (int k = 0; k < kBsCols; ++k) {
+    const int nk = 2 * (k + 1);
+    const double hs = H / nk;
+    // z_0 = y0, z_1 = z_0 + hs f(z_0)
+    for (int m = threadIdx.x; m < sz; m += 64) {
+      double* r = a.big + (size_t)mem[m] * kBigRec;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) r[kBigZp + c] = r[kBigY0 + c];
+    }
+    big_publish(a, mem, sz, kBigY0);
+    for (int m = threadIdx.x; m < sz; m += 64) {
+      const int id = mem[m];
+      double* r = a.big + (size_t)id * kBigRec;
+      double d[6];
+      d[0] = r[kBigZp + 3];
+      d[1] = r[kBigZp + 4];
+      d[2] = r[kBigZp + 5];
+      ha_accel_big(a, mem, sz, m, r[kBigZp], r[kBigZp + 1], r[kBigZp + 2], a.rc[id], d[3], d[4], d[5]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) r[kBigZc + c] = r[kBigZp + c] + hs * d[c];
+    }
+    __syncthreads();
+    big_publish(a, mem, sz, kBigZc);
+    // z_{s+1} = z_{s-1} + 2 hs f(z_s), s = 1 .. nk - 1
+    for (int st = 1; st < nk; ++st) {
+      for (int m = threadIdx.x; m < sz; m += 64) {
+        const int id = mem[m];
+        double* r = a.big + (size_t)id * kBigRec;
+        double d[6];
+        d[0] = r[kBigZc + 3];
+        d[1] = r[kBigZc + 4];
+        d[2] = r[kBigZc + 5];
+        ha_accel_big(a, mem, sz, m, r[kBigZc], r[kBigZc + 1], r[kBigZc + 2], a.rc[id], d[3], d[4],
+                     d[5]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const double t = r[kBigZp + c] + 2.0 * hs * d[c];
+          r[kBigZp + c] = r[kBigZc + c];
+          r[kBigZc + c] = t;
+        }
+      }
+      __syncthreads();
+      big_publish(a, mem, sz, kBigZc);
+    }
+    // T_k0 = (z_{n-1} + z_n + hs f(z_n)) / 2, then the tableau row
+    double e = 0.0;
+    for (int m = threadIdx.x; m < sz; m += 64) {
+      const int id = mem[m];
+      double* r = a.big + (size_t)id * kBigRec;
+      double d[6], t[6];
+      d[0] = r[kBigZc + 3];
+      d[1] = r[kBigZc + 4];
+      d[2] = r[kBigZc + 5];
+      ha_accel_big(a, mem, sz, m, r[kBigZc], r[kBigZc + 1], r[kBigZc + 2], a.rc[id], d[3], d[4],
+                   d[5]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) t[c] = 0.5 * (r[kBigZp + c] + r[kBigZc + c] + hs * d[c]);
+      double* R = r + kBigR;
+      for (int j = 1; j <= k; ++j) {
+        const double ratio = (double)nk / (double)(2 * (k - j + 1));
+        const double den = ratio * ratio - 1.0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const double u = t[c] + (t[c] - R[6 * (j - 1) + c]) / den;
+          R[6 * (j - 1) + c] = t[c];
+          t[c] = u;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) R[6 * k + c] = t[c];
+      if (k >= 1) e = fmax(e, fmax(relerr3(R + 6 * k, R + 6 * (k - 1)),
+                                   relerr3(R + 6 * k + 3, R + 6 * (k - 1) + 3)));
+    }
+    e = wave_max(e);
+    __syncthreads();
+    if (k >= 1 && e <= a.tol) {
+      for (int m = threadIdx.x; m < sz; m += 64) {
+        double* r = a.big + (size_t)mem[m] * kBigRec;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) r[kBigY0 + c] = r[kBigR + 6 * k + c];
+      }
+      __syncthreads();
+      return true;
+    }
+  }
+  return false;
+}
+
+// Group g of sz > 64 members at offset o: members sorted into bmem, state
+// from the pre-drift copy, binary refinement over tau as bs_integrate does,
+// result written back; returns the BS status (0, or -1 when the depth or
+// the attempt cap is exhausted) and the group's momentum change.
+__device__ int bs_group_big(const BsArgs& a, int o, int sz, long long* nsub, double& dpx,
+                            double& dpy, double& dpz) {
+  const int lane = threadIdx.x;
+  const int* gm = a.gmem + o;
+  int* mem = a.bmem + o;
+  for (int m = lane; m < sz; m += 64) {
+    const int id = gm[m];
+    int rank = 0;
+    for (int q = 0; q < sz; ++q) rank += gm[q] < id ? 1 : 0;
+    mem[rank] = id;
+  }
+  __syncthreads();
+  for (int m = lane; m < sz; m += 64) {
+    const int id = mem[m];
+    const double4 p = a.xpre[id], q = a.vpre[id];
+    double* r = a.big + (size_t)id * kBigRec;
+    r[kBigY0 + 0] = p.x;
+    r[kBigY0 + 1] = p.y;
+    r[kBigY0 + 2] = p.z;
+    r[kBigY0 + 3] = q.x;
+    r[kBigY0 + 4] = q.y;
+    r[kBigY0 + 5] = q.z;
+  }
+  __syncthreads();
+  const int D = a.max_depth;
+  const long long total = 1ll << D;
+  long long pos = 0;
+  int d = 0, attempts = 0, status = 0;
+  while (pos < total) {
+    if (++attempts > kBsMaxAttempts) {
+      status = -1;
+      break;
+    }
+    if (big_attempt(a, mem, sz, ldexp(a.dt, -d))) {
+      ++*nsub;
+      pos += 1ll << (D - d);
+      while (d > 0 && (pos % (1ll << (D - d + 1))) == 0) --d;
+    } else {
+      ++d;
+      if (d > D) {
+        status = -1;
+        break;
+      }
+    }
+  }
+  dpx = dpy = dpz = 0.0;
+  for (int m = lane; m < sz; m += 64) {
+    const int id = mem[m];
+    const double* r = a.big + (size_t)id * kBigRec;
+    const double mass = a.xm[id].w;
+    const double4 vo = a.vv[id];
+    dpx += mass * (r[kBigY0 + 3] - vo.x);
+    dpy += mass * (r[kBigY0 + 4] - vo.y);
+    dpz += mass * (r[kBigY0 + 5] - vo.z);
+    a.xm[id] = make_double4(r[kBigY0], r[kBigY0 + 1], r[kBigY0 + 2], mass);
+    a.vv[id] = make_double4(r[kBigY0 + 3], r[kBigY0 + 4], r[kBigY0 + 5], 0.0);
+  }
+  return status;
+}
 
 // Main-mode group of sz <= P members (sorted indices in mem, masses and radii
 // in mm, mrc): start from the pre-drift copy, integrate, write back; returns
@@ -899,6 +1151,194 @@ __device__ __forceinline__ int bs_member_group(const BsArgs& a, int sz, const in
   return r;
 }
 
+// ---- groups whose members can collide (Sec. 3.2.7) ----------------------------
+// Member t of the group (ascending row) sits in lane t < sz: its pre-drift
+// state pre[], mass, critical and physical radius, spin and original row.
+// The group is integrated by the path its size selects; when two members
+// touch during a substep (the Hermite test of Eqs. 10-12 over the substep)
+// the integration stops at the start of that substep, the pair merges there
+// (the more massive survives, the lower row on equal masses; mass, momentum
+// and orbital-plus-spin angular momentum kept, the summed volume, the larger
+// critical radius for the rest of the step), the merger is recorded, the
+// absorbed member leaves the lanes, and the group, one member fewer, goes on
+// over the rest of the step (the batched kernel's rule).
+template <int P>
+__device__ __forceinline__ int coll_par(const BsArgs& a, int sz, double pre[6], double m,
+                                        double rc, double Rd, double* mm, double* mrc, double* mR,
+                                        long long* nsub, double H, int* key, long long* cpos) {
+  const int lane = threadIdx.x & 63;
+  const int b = par_memb<P>(lane);
+  double y[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) y[c] = __shfl(pre[c], b < sz ? b : 0, 64);
+  if (b >= sz) {
+    y[0] = 1.0;
+    y[1] = y[2] = y[3] = y[4] = y[5] = 0.0;
+  }
+  __syncthreads();
+  if (lane < sz) {
+    mm[lane] = m;
+    mrc[lane] = rc;
+    mR[lane] = Rd;
+  }
+  __syncthreads();
+  const int r = bs_group<P, false>(sz, y, mm, mrc, H, a.G, a.Gm0, a.tol, a.max_depth, nsub, -1.0,
+                                   key, cpos, mR);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const double t = __shfl(y[c], par_lane<P>(0, 0, min(lane, P - 1)), 64);
+    if (lane < sz) pre[c] = t;
+  }
+  return r;
+}
+
+__device__ int bs_group_coll(const BsArgs& a, int g, int sz, const int* mem, double* mm,
+                             double* mrc, double* mR, double (*R)[6][64], long long* nsub,
+                             double& dpx, double& dpy, double& dpz, double& Ug) {
+  const int lane = threadIdx.x & 63;
+  const bool act = lane < sz;  // members at the start
+  int id = act ? mem[lane] : 0;
+  double pre[6] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double m = 0.0, rc = 0.0, Rd = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0;
+  double b0x = 0.0, b0y = 0.0, b0z = 0.0;  // momentum before, after the drift
+  if (act) {
+    const double4 p = a.xpre[id], q = a.vpre[id], vo = a.vv[id], sv = a.sp[id];
+    pre[0] = p.x;
+    pre[1] = p.y;
+    pre[2] = p.z;
+    pre[3] = q.x;
+    pre[4] = q.y;
+    pre[5] = q.z;
+    m = a.xm[id].w;
+    rc = a.rc_w[id];
+    Rd = a.rad[id];
+    S0 = sv.x;
+    S1 = sv.y;
+    S2 = sv.z;
+    b0x = m * vo.x;
+    b0y = m * vo.y;
+    b0z = m * vo.z;
+  }
+  const long long step = (long long)a.st->nstep - 1;
+  double H = a.dt, f0 = 0.0;
+  Ug = 0.0;
+  int status = 0;
+  for (;;) {
+    long long gsub = 0, cpos = 0;
+    int key = -1, st;
+    if (sz <= 2)
+      st = coll_par<2>(a, sz, pre, m, rc, Rd, mm, mrc, mR, &gsub, H, &key, &cpos);
+    else if (sz <= 4)
+      st = coll_par<4>(a, sz, pre, m, rc, Rd, mm, mrc, mR, &gsub, H, &key, &cpos);
+    else if (sz <= kBsPar)
+      st = coll_par<8>(a, sz, pre, m, rc, Rd, mm, mrc, mR, &gsub, H, &key, &cpos);
+    else
+      st = bs_integrate(sz, lane, pre, H, lane < sz ? m : 0.0, lane < sz ? rc : 0.0, a.G, a.Gm0,
+                        a.tol, a.max_depth, R, &gsub, lane < sz ? Rd : 0.0, &key, &cpos);
+    *nsub += gsub;
+    if (st != 1) {
+      status = st;
+      break;
+    }
+    // members key >> 6 < key & 63 touch: merge them at the start of that
+    // substep, then the rest of the step with one member fewer
+    const double fc = ldexp((double)cpos, -a.max_depth);
+    const int la = key >> 6, lb = key & 63;
+    const double mla = readlane_d(m, la), mlb = readlane_d(m, lb);
+    const int ls = mlb > mla ? lb : la, lg = ls == la ? lb : la;
+    double ys[6], yg[6], ss[3], sg[3], ym[6], sm[3], Mm, Rm;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      ys[c] = readlane_d(pre[c], ls);
+      yg[c] = readlane_d(pre[c], lg);
+    }
+    ss[0] = readlane_d(S0, ls);
+    ss[1] = readlane_d(S1, ls);
+    ss[2] = readlane_d(S2, ls);
+    sg[0] = readlane_d(S0, lg);
+    sg[1] = readlane_d(S1, lg);
+    sg[2] = readlane_d(S2, lg);
+    const double ms = readlane_d(m, ls), mg = readlane_d(m, lg);
+    const double Rs = readlane_d(Rd, ls), Rg = readlane_d(Rd, lg);
+    const double Uc = merge_bodies(a.G, ms, mg, ys, yg, Rs, Rg, ss, sg, Mm, ym, Rm, sm);
+    const double frac = f0 + (1.0 - f0) * fc;
+    const int ids_s = a.ids[__builtin_amdgcn_readlane(id, ls)];
+    const int idg = __builtin_amdgcn_readlane(id, lg);
+    const int ids_g = a.ids[idg];
+    const double rcm = fmax(readlane_d(rc, ls), readlane_d(rc, lg));
+    if (lane == 0) {
+      const unsigned long long k = atomicAdd(&a.st->ev_cnt, 1ull);
+      if ((long long)k < a.ev_cap) {
+        genga_event e;
+        e.kind = GENGA_EV_MERGE;
+        e.sys = 0;
+        e.id_i = ids_s;
+        e.id_j = ids_g;
+        e.step = step;
+        e.frac = frac;
+        e.m_i = ms;
+        e.m_j = mg;
+        e.R_i = Rs;
+        e.R_j = Rg;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          e.x_i[q] = ys[q];
+          e.v_i[q] = ys[3 + q];
+          e.s_i[q] = ss[q];
+          e.x_j[q] = yg[q];
+          e.v_j[q] = yg[3 + q];
+          e.s_j[q] = sg[q];
+        }
+        e.U = Uc;
+        a.ev[k] = e;
+      }
+      a.dead[idg] = 1;
+    }
+    Ug += Uc;
+    if (lane == ls) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) pre[c] = ym[c];
+      m = Mm;
+      Rd = Rm;
+      S0 = sm[0];
+      S1 = sm[1];
+      S2 = sm[2];
+      rc = rcm;
+    }
+    // the absorbed member leaves: the lanes above it move down by one
+    const int src = lane >= lg ? min(lane + 1, 63) : lane;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) pre[c] = __shfl(pre[c], src, 64);
+    m = __shfl(m, src, 64);
+    rc = __shfl(rc, src, 64);
+    Rd = __shfl(Rd, src, 64);
+    S0 = __shfl(S0, src, 64);
+    S1 = __shfl(S1, src, 64);
+    S2 = __shfl(S2, src, 64);
+    id = __shfl(id, src, 64);
+    --sz;
+    H = H * (1.0 - fc);
+    f0 = frac;
+  }
+  // survivors written back; the group's momentum change for the second Sun
+  // kick includes the absorbed members' momentum before the step
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  if (lane < sz) {
+    a.xm[id] = make_double4(pre[0], pre[1], pre[2], m);
+    a.vv[id] = make_double4(pre[3], pre[4], pre[5], 0.0);
+    a.rad[id] = Rd;
+    a.sp[id] = make_double4(S0, S1, S2, 0.0);
+    a.rc_w[id] = rc;
+    ax = m * pre[3];
+    ay = m * pre[4];
+    az = m * pre[5];
+  }
+  dpx = ax - b0x;
+  dpy = ay - b0y;
+  dpz = az - b0z;
+  return status;
+}
+
 // One wave per encounter group (grid-stride over the device-side count):
 // members sorted ascending, state reset to the pre-drift copy, H_A integrated
 // over tau by BS, result written back.  Groups of up to 8 members take the
@@ -907,15 +1347,33 @@ __device__ __forceinline__ int bs_member_group(const BsArgs& a, int sz, const in
 __global__ __launch_bounds__(64) void k_bs(BsArgs a) {
   __shared__ double R[kBsCols][6][64];
   __shared__ int mem[64];
-  __shared__ double mm[kBsPar], mrc[kBsPar];
+  __shared__ double mm[kBsPar], mrc[kBsPar], mR[kBsPar];
   const int lane = threadIdx.x;
+  if (a.st->flags & F_NMIN) return;  // the run stopped below nmin bodies
   const int ng = __builtin_amdgcn_readfirstlane(a.st->ngroups);
   long long nsub = 0;
   for (int g = blockIdx.x; g < ng; g += gridDim.x) {
     const int o = a.goff[g];
     const int sz = a.goff[g + 1] - o;
-    if (sz > kBsMaxGroup) {
+    if (a.coll && sz > kBsMaxGroup) {
+      // collisions are tested in groups of up to 64 members only
       if (lane == 0) atomicOr(&a.st->flags, F_GROUP);
+      continue;
+    }
+    if (sz > kBsMaxGroup) {
+      double dpx, dpy, dpz;
+      const int r = bs_group_big(a, o, sz, &nsub, dpx, dpy, dpz);
+      if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
+      dpx = wave_sum(dpx);
+      dpy = wave_sum(dpy);
+      dpz = wave_sum(dpz);
+      if (lane == 0) {
+        a.dP[4 * g + 0] = dpx;
+        a.dP[4 * g + 1] = dpy;
+        a.dP[4 * g + 2] = dpz;
+        a.dP[4 * g + 3] = 0.0;
+      }
+      __syncthreads();
       continue;
     }
     const int my = lane < sz ? a.gmem[o + lane] : INT_MAX;
@@ -924,8 +1382,11 @@ __global__ __launch_bounds__(64) void k_bs(BsArgs a) {
     __syncthreads();
     if (lane < sz) mem[rank] = my;
     __syncthreads();
-    double dpx = 0.0, dpy = 0.0, dpz = 0.0;
-    if (sz <= kBsPar) {
+    double dpx = 0.0, dpy = 0.0, dpz = 0.0, Ug = 0.0;
+    if (a.coll) {
+      const int r = bs_group_coll(a, g, sz, mem, mm, mrc, mR, R, &nsub, dpx, dpy, dpz, Ug);
+      if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
+    } else if (sz <= kBsPar) {
       int r;
       if (sz <= 2)
         r = bs_member_group<2>(a, sz, mem, mm, mrc, &nsub, dpx, dpy, dpz);
@@ -969,10 +1430,180 @@ __global__ __launch_bounds__(64) void k_bs(BsArgs a) {
       a.dP[4 * g + 0] = dpx;
       a.dP[4 * g + 1] = dpy;
       a.dP[4 * g + 2] = dpz;
+      a.dP[4 * g + 3] = Ug;  // internal energy of the group's mergers
     }
     __syncthreads();
   }
   if (lane == 0 && nsub > 0) atomicAdd(&a.st->bs_sub, (unsigned long long)nsub);
+}
+
+// ---- bodies leaving the system (Sec. 3.2.7, 3.2.8, 3.4.6) ------------------
+struct CompactArgs {
+  double4* __restrict__ xs;
+  double4* __restrict__ xm;
+  double4* __restrict__ vv;
+  double* __restrict__ rc;
+  double* __restrict__ thr;
+  double* __restrict__ tmax64;
+  double* __restrict__ rad;
+  double4* __restrict__ sp;
+  int* __restrict__ ids;
+  int* __restrict__ dead;
+  const double* __restrict__ dP;
+  genga_event* __restrict__ ev;
+  DevStat* __restrict__ st;
+  int np, nmin, ev_cap;
+  double rcut, rcut_sun;
+};
+
+// After BS, in one workgroup: the groups' merger energies added in group
+// order; bodies beyond rcut or inside rcut_sun of the central mass leave
+// (recorded); then every freed row, in descending order, takes the last
+// body (the oracle's compaction), the rows past the count become padding
+// (massless at the origin), the 64-body threshold maxima are rebuilt, and
+// with fewer than nmin bodies left the run stops (later steps do nothing).
+__global__ __launch_bounds__(1024) void k_compact(CompactArgs a) {
+  __shared__ int dl[kGroupMaxN];
+  __shared__ int s_nd;
+  const int tid = threadIdx.x;
+  if (a.st->flags & F_NMIN) return;
+  const int n = a.st->nlive;
+  const long long step = (long long)a.st->nstep - 1;
+  if (tid == 0) {
+    s_nd = 0;
+    double U = 0.0;
+    for (int g = 0; g < a.st->ngroups; ++g) U += a.dP[4 * g + 3];
+    a.st->U += U;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += 1024) {
+    if (!a.dead[i] && (a.rcut > 0.0 || a.rcut_sun > 0.0)) {
+      const double4 p = a.xm[i];
+      const double r = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
+      int kind = 0;
+      if (a.rcut > 0.0 && r > a.rcut) kind = GENGA_EV_EJECT_FAR;
+      if (a.rcut_sun > 0.0 && r < a.rcut_sun) kind = GENGA_EV_EJECT_SUN;
+      if (kind) {
+        const unsigned long long k = atomicAdd(&a.st->ev_cnt, 1ull);
+        if ((long long)k < a.ev_cap) {
+          const double4 q = a.vv[i], s = a.sp[i];
+          genga_event e;
+          e.kind = kind;
+          e.sys = 0;
+          e.id_i = a.ids[i];
+          e.id_j = -1;
+          e.step = step;
+          e.frac = 1.0;
+          e.m_i = p.w;
+          e.m_j = 0.0;
+          e.R_i = a.rad[i];
+          e.R_j = 0.0;
+          e.x_i[0] = p.x;
+          e.x_i[1] = p.y;
+          e.x_i[2] = p.z;
+          e.v_i[0] = q.x;
+          e.v_i[1] = q.y;
+          e.v_i[2] = q.z;
+          e.s_i[0] = s.x;
+          e.s_i[1] = s.y;
+          e.s_i[2] = s.z;
+          for (int c = 0; c < 3; ++c) e.x_j[c] = e.v_j[c] = e.s_j[c] = 0.0;
+          e.U = 0.0;
+          a.ev[k] = e;
+        }
+        a.dead[i] = 2;  // ejected (1: absorbed in a merger)
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += 1024)
+    if (a.dead[i]) dl[atomicAdd(&s_nd, 1)] = i;
+  __syncthreads();
+  const int nd = s_nd;
+  if (tid == 0) {
+    // freed rows in descending order: a short insertion sort of the list
+    for (int k = 1; k < nd; ++k) {
+      const int v = dl[k];
+      int q = k - 1;
+      while (q >= 0 && dl[q] < v) {
+        dl[q + 1] = dl[q];
+        --q;
+      }
+      dl[q + 1] = v;
+    }
+    // the ejected bodies' momentum, in that order, leaves with them: the
+    // second Sun kick takes the momentum of the bodies that stay
+    double ex = 0.0, ey = 0.0, ez = 0.0;
+    for (int k = 0; k < nd; ++k) {
+      const int h = dl[k];
+      if (a.dead[h] == 2) {
+        const double mh = a.xm[h].w;
+        const double4 q = a.vv[h];
+        ex += mh * q.x;
+        ey += mh * q.y;
+        ez += mh * q.z;
+      }
+    }
+    a.st->Pej[0] = ex;
+    a.st->Pej[1] = ey;
+    a.st->Pej[2] = ez;
+    int nn = n;
+    for (int k = 0; k < nd; ++k) {
+      const int h = dl[k];
+      const int last = nn - 1;
+      if (h != last) {
+        a.xm[h] = a.xm[last];
+        a.vv[h] = a.vv[last];
+        a.rc[h] = a.rc[last];
+        a.thr[h] = a.thr[last];
+        a.rad[h] = a.rad[last];
+        a.sp[h] = a.sp[last];
+        a.ids[h] = a.ids[last];
+      }
+      a.xs[last] = make_double4(0.0, 0.0, 0.0, 0.0);
+      a.xm[last] = make_double4(0.0, 0.0, 0.0, 0.0);
+      a.vv[last] = make_double4(0.0, 0.0, 0.0, 0.0);
+      a.rc[last] = 0.0;
+      a.thr[last] = kTiny;
+      a.rad[last] = 0.0;
+      a.sp[last] = make_double4(0.0, 0.0, 0.0, 0.0);
+      a.ids[last] = -1;
+      a.dead[h] = 0;
+      nn = last;
+    }
+    a.st->nlive = nn;
+    if (nn < a.nmin) atomicOr(&a.st->flags, F_NMIN);
+  }
+  __syncthreads();
+  if (nd > 0) {
+    // the moved rows' thresholds: rebuild every 64-body chunk maximum
+    const int w = tid >> 6, lane = tid & 63;
+    for (int c = w; c < a.np / 64; c += 16) {
+      double t = a.thr[64 * c + lane];
+      t = wave_max(t);
+      if (lane == 0) a.tmax64[c] = t;
+    }
+  }
+}
+
+// Every body present in its own row, no spins, none leaving; radii cleared
+// only with clear_rad (init; a new state keeps them).
+__global__ __launch_bounds__(256) void k_bodies_reset(int* __restrict__ ids,
+                                                      double4* __restrict__ sp,
+                                                      int* __restrict__ dead,
+                                                      double* __restrict__ rad,
+                                                      DevStat* __restrict__ st, int n, int np,
+                                                      int clear_rad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    st->nlive = n;
+    st->stopped = 0;
+  }
+  if (i >= np) return;
+  ids[i] = i < n ? i : -1;
+  sp[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+  dead[i] = 0;
+  if (clear_rad) rad[i] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1045,9 +1676,15 @@ __global__ void k_pack(const double* __restrict__ m, const double* __restrict__ 
 // Barycentric velocities back to heliocentric: u = v + sum m v / m0.
 __global__ void k_unpack(const double4* __restrict__ xm, const double4* __restrict__ vv,
                          const double* __restrict__ mom, double* __restrict__ x,
-                         double* __restrict__ v, int n, int helio, double m0) {
+                         double* __restrict__ v, int n, int helio, double m0,
+                         const DevStat* __restrict__ st) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (i >= st->nlive) {  // a body that left: NaN row
+    const double q = __builtin_nan("");
+    for (int c = 0; c < 3; ++c) x[3 * i + c] = v[3 * i + c] = q;
+    return;
+  }
   double sx = 0.0, sy = 0.0, sz = 0.0;
   if (helio) {
     sx = mom[0] / m0;
@@ -1066,9 +1703,8 @@ __global__ void k_unpack(const double4* __restrict__ xm, const double4* __restri
 // Radii of the first step (Eq. 6), thresholds, empty candidate table.
 __global__ __launch_bounds__(256) void k_rcrit_init(
     const double4* __restrict__ xm, const double4* __restrict__ vv, double* __restrict__ rc,
-    double* __restrict__ thr, double* __restrict__ thrmax, int* __restrict__ ccnt, int n,
+    double* __restrict__ thr, double* __restrict__ tmax64, int* __restrict__ ccnt, int n,
     double mu, double m0, double n1, double n2, double absdt, double pf2, int enc_free) {
-  __shared__ double sh[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;  // grid: the padded count
   double t = kTiny;
   if (i < n) {
@@ -1079,15 +1715,20 @@ __global__ __launch_bounds__(256) void k_rcrit_init(
     ccnt[i] = 0;
   }
   thr[i] = t;
-  block_thrmax(t, thrmax, sh);
+  chunk_tmax(t, i & ~63, tmax64);
 }
 
 // Per-body energy terms and angular momentum; rows[8 i + k]:
 // kinetic, -G m0 m/r, -1/2 G m sum_j m_j/r_ij, m v (3), m x x v (3) -> 9 terms
 __global__ void k_energy_rows(const double4* __restrict__ xm, const double4* __restrict__ vv,
-                              int n, double G, double m0, double* __restrict__ rows) {
+                              int n, double G, double m0, double* __restrict__ rows,
+                              const DevStat* __restrict__ st) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (i >= st->nlive) {  // padding rows (bodies that left) add nothing
+    for (int k = 0; k < 9; ++k) rows[9 * (size_t)i + k] = 0.0;
+    return;
+  }
   const double4 p = xm[i], q = vv[i];
   double pp = 0.0;
   for (int j = 0; j < n; ++j) {
@@ -1133,10 +1774,9 @@ __global__ __launch_bounds__(256) void k_energy_final(const double* __restrict__
 // Candidate thresholds from given radii: max((pf rc)^2, tiny).
 __global__ __launch_bounds__(256) void k_thresholds(const double* __restrict__ rc,
                                                     double* __restrict__ thr,
-                                                    double* __restrict__ thrmax,
+                                                    double* __restrict__ tmax64,
                                                     int* __restrict__ ccnt, int n, double pf2,
                                                     int enc_free) {
-  __shared__ double sh[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;  // grid: the padded count
   double t = kTiny;
   if (i < n) {
@@ -1144,7 +1784,7 @@ __global__ __launch_bounds__(256) void k_thresholds(const double* __restrict__ r
     ccnt[i] = 0;
   }
   thr[i] = t;
-  block_thrmax(t, thrmax, sh);
+  chunk_tmax(t, i & ~63, tmax64);
 }
 
 // Radii given by the caller: installed with their thresholds (zero and the
@@ -1152,10 +1792,9 @@ __global__ __launch_bounds__(256) void k_thresholds(const double* __restrict__ r
 __global__ __launch_bounds__(256) void k_radii_in(const double* __restrict__ rc_in,
                                                   double* __restrict__ rc,
                                                   double* __restrict__ thr,
-                                                  double* __restrict__ thrmax,
+                                                  double* __restrict__ tmax64,
                                                   int* __restrict__ ccnt, int n, double pf2,
                                                   int enc_free) {
-  __shared__ double sh[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;  // grid: the padded count
   double t = kTiny;
   if (i < n) {
@@ -1165,7 +1804,7 @@ __global__ __launch_bounds__(256) void k_radii_in(const double* __restrict__ rc_
     ccnt[i] = 0;
   }
   thr[i] = t;
-  block_thrmax(t, thrmax, sh);
+  chunk_tmax(t, i & ~63, tmax64);
 }
 
 // Masses out of the packed state.
@@ -1186,7 +1825,7 @@ PairArgs pair_args(const MassiveWs& w, const StepConsts& c) {
   a.ccnt = w.ccnt;
   a.ctab = w.ctab;
   a.cr2 = w.cr2;
-  a.thrmax = w.thrmax;
+  a.tmax64 = w.tmax64;
   a.pp = w.pp;
   a.njs = w.njs;
   a.xs = w.xs;
@@ -1236,6 +1875,11 @@ StepConsts make_consts(const genga_params& p) {
   c.encounter_free = p.encounter_free;
   c.absdt_next = fabs(p.dt);
   c.all_pairs = 0;
+  c.rcut = p.rcut;
+  c.rcut_sun = p.rcut_sun;
+  c.nmin = p.nmin;
+  c.coll = 0;
+  c.phys = p.rcut > 0.0 || p.rcut_sun > 0.0 || p.nmin > 0;
   return c;
 }
 
@@ -1312,7 +1956,7 @@ size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base, boo
   w.rc_cur = (double*)take(np * sizeof(double));
   w.rc_next = (double*)take(np * sizeof(double));
   w.thr = (double*)take(np * sizeof(double));
-  w.thrmax = (double*)take((size_t)w.nblk * sizeof(double));
+  w.tmax64 = (double*)take(np / 64 * sizeof(double));
   w.pp = (double*)take((size_t)w.njs * 6 * np * sizeof(double));
   w.partP = (double*)take((size_t)w.nblk * 4 * sizeof(double));
   w.partP2 = (double*)take((size_t)w.nblk * 4 * sizeof(double));
@@ -1327,12 +1971,27 @@ size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base, boo
   w.encrc2 = (double*)take((size_t)std::max(1, w.enc_cap) * sizeof(double));
   w.goff = (int*)take((np + 1) * sizeof(int));
   w.gmem = (int*)take(np * sizeof(int));
+  w.rad = (double*)take(np * sizeof(double));
+  w.sp = (double4*)take(np * sizeof(double4));
+  w.ids = (int*)take(np * sizeof(int));
+  w.dead = (int*)take(np * sizeof(int));
+  w.ev_cap = 2 * w.n + 16;  // every body leaves at most once
+  w.ev = (genga_event*)take((size_t)w.ev_cap * sizeof(genga_event));
+  w.bsbig = (double*)take(np * kBigRec * sizeof(double));
+  w.bspos = (double4*)take(np * sizeof(double4));
+  w.bsmem = (int*)take(np * sizeof(int));
   w.flag_in = (int*)take(sizeof(int));
   w.xstart = snap ? (double4*)take(np * sizeof(double4)) : nullptr;
   w.xpost = snap ? (double4*)take(np * sizeof(double4)) : nullptr;
   w.vpost = snap ? (double4*)take(np * sizeof(double4)) : nullptr;
   w.st = (DevStat*)take(sizeof(DevStat));
   return off;
+}
+
+hipError_t massive_reset_bodies(const MassiveWs& w, bool clear_radii, hipStream_t s) {
+  hipLaunchKernelGGL(k_bodies_reset, dim3(ceil_div(w.np, 256)), dim3(256), 0, s, w.ids, w.sp,
+                     w.dead, w.rad, w.st, w.n, w.np, clear_radii ? 1 : 0);
+  return hipGetLastError();
 }
 
 hipError_t massive_pack(const MassiveWs& w, const StepConsts& c, const double* m,
@@ -1351,13 +2010,13 @@ hipError_t massive_unpack(const MassiveWs& w, const StepConsts& c, double* x,
   if (helio)
     hipLaunchKernelGGL(k_momentum, dim3(1), dim3(1024), 0, s, nullptr, nullptr, w.xs, w.vv, w.n, w.red);
   hipLaunchKernelGGL(k_unpack, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xs, w.vv, w.red,
-                     x, v, w.n, helio, c.m0);
+                     x, v, w.n, helio, c.m0, (const DevStat*)w.st);
   return hipGetLastError();
 }
 
 hipError_t massive_prime(const MassiveWs& w, const StepConsts& c, hipStream_t s) {
   hipLaunchKernelGGL(k_rcrit_init, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xm, w.vv,
-                     w.rc_cur, w.thr, w.thrmax, w.ccnt, w.n, c.mu, c.m0, c.n1, c.n2, fabs(c.dt),
+                     w.rc_cur, w.thr, w.tmax64, w.ccnt, w.n, c.mu, c.m0, c.n1, c.n2, fabs(c.dt),
                      c.pf2, c.encounter_free);
   PairArgs a = pair_args(w, c);
   hipLaunchKernelGGL(k_pair_part<KICK_INIT>, dim3(pair_grid(w)), dim3(kPairThreads), 0, s, a,
@@ -1407,7 +2066,7 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
   o.rc_next = w.rc_next;
   o.rc_cur = w.rc_cur;
   o.thr = w.thr;
-  o.thrmax = w.thrmax;
+  o.tmax64 = w.tmax64;
   o.ccnt = w.ccnt;
   o.ctab = w.ctab;
   o.partP = w.partP;
@@ -1446,12 +2105,15 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
     e.enc_cap = w.enc_cap;
     e.dt = c.dt;
     if (c.all_pairs) {
+      // composed steps (not timed per kernel): every pair tested, then the
+      // grouping on its own
       const int nt = ceil_div(w.n, kEncTile);
-      STEP_LAUNCH(1, k_encounter_all, dim3(nt, nt), dim3(256), e);
+      hipLaunchKernelGGL(k_encounter_all, dim3(nt, nt), dim3(256), 0, s, e);
+      hipLaunchKernelGGL(k_group, dim3(1), dim3(kEncThreads), 0, s, e);
     } else {
       STEP_LAUNCH(1, k_encounter, dim3(ceil_div(w.n * w.cpb, kVecBlock)), dim3(kVecBlock), e);
+      STEP_LAUNCH(2, k_group, dim3(1), dim3(kEncThreads), e);
     }
-    STEP_LAUNCH(2, k_group, dim3(1), dim3(kEncThreads), e);
 
     BsArgs b;
     b.xm = w.xm;
@@ -1462,13 +2124,48 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
     b.rc = w.rc_cur;
     b.goff = w.goff;
     b.gmem = w.gmem;
+    b.big = w.bsbig;
+    b.bpos = w.bspos;
+    b.bmem = w.bsmem;
+    b.rc_w = w.rc_cur;
+    b.rad = w.rad;
+    b.sp = w.sp;
+    b.ids = w.ids;
+    b.dead = w.dead;
+    b.ev = w.ev;
     b.st = w.st;
     b.G = c.G;
     b.Gm0 = c.mu;
     b.dt = c.dt;
     b.tol = c.bs_tol;
     b.max_depth = c.bs_max_depth;
+    b.coll = c.coll;
+    b.ev_cap = w.ev_cap;
     STEP_LAUNCH(3, k_bs, dim3(std::max(1, std::min(256, w.n / 2))), dim3(64), b);
+    if (c.phys) {
+      // bodies that merged or crossed rcut / rcut_sun leave (not timed per
+      // kernel: the measurement forms run without these limits)
+      CompactArgs ca;
+      ca.xs = w.xs;
+      ca.xm = w.xm;
+      ca.vv = w.vv;
+      ca.rc = w.rc_cur;
+      ca.thr = w.thr;
+      ca.tmax64 = w.tmax64;
+      ca.rad = w.rad;
+      ca.sp = w.sp;
+      ca.ids = w.ids;
+      ca.dead = w.dead;
+      ca.dP = w.dP;
+      ca.ev = w.ev;
+      ca.st = w.st;
+      ca.np = w.np;
+      ca.nmin = c.nmin;
+      ca.ev_cap = w.ev_cap;
+      ca.rcut = c.rcut;
+      ca.rcut_sun = c.rcut_sun;
+      hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, ca);
+    }
   }
 
   PairArgs a = pair_args(w, c);
@@ -1482,7 +2179,7 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
 hipError_t massive_energy(const MassiveWs& w, const StepConsts& c, double* dE,
                           double* dL, hipStream_t s) {
   hipLaunchKernelGGL(k_energy_rows, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.xs, w.vv,
-                     w.n, c.G, c.m0, w.red);
+                     w.n, c.G, c.m0, w.red, (const DevStat*)w.st);
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, w.red, w.n, c.m0, dE, dL);
   return hipGetLastError();
 }
@@ -1495,7 +2192,7 @@ hipError_t validate_finite(const double* a, int64_t cnt, int* dbad, hipStream_t 
 
 hipError_t thresholds_from_radii(const MassiveWs& w, const StepConsts& c, hipStream_t s) {
   hipLaunchKernelGGL(k_thresholds, dim3(ceil_div(w.n, 256)), dim3(256), 0, s, w.rc_cur, w.thr,
-                     w.thrmax, w.ccnt, w.n, c.pf2, c.encounter_free);
+                     w.tmax64, w.ccnt, w.n, c.pf2, c.encounter_free);
   return hipGetLastError();
 }
 
@@ -1504,7 +2201,7 @@ hipError_t accel_run(const MassiveWs& w, const StepConsts& c, const double* m, c
   hipLaunchKernelGGL(k_pack, dim3(ceil_div(w.np, 256)), dim3(256), 0, s, m, x, x,
                      (const double*)nullptr, w.xm, w.vv, w.xs, w.n, w.np, 0, c.m0);
   hipLaunchKernelGGL(k_radii_in, dim3(ceil_div(w.n, 256)), dim3(256), 0, s,
-                     c.encounter_free ? nullptr : rc, w.rc_cur, w.thr, w.thrmax, w.ccnt, w.n, c.pf2,
+                     c.encounter_free ? nullptr : rc, w.rc_cur, w.thr, w.tmax64, w.ccnt, w.n, c.pf2,
                      c.encounter_free);
   return massive_accel(w, c, w.xm, acc, s);
 }
@@ -1513,7 +2210,7 @@ hipError_t accel_run(const MassiveWs& w, const StepConsts& c, const double* m, c
 // Scratch of accel_noalloc_run: the packed bodies (x, y, z, m), the velocity
 // and start-position rows the packing kernel also fills, radii, thresholds
 // and candidate counts of up to kNoAllocBodies bodies (116 bytes per padded
-// body), the blocks' largest thresholds and the pair kernel's partial sums
+// body), the 64-body chunks' largest thresholds and the pair kernel's partial sums
 // (6 doubles x splits x padded bodies, splits x padded bodies <=
 // kPairTarget): 2.7 MB.  Each GPU holds its own copy until the process ends;
 // every call on a GPU uses that GPU's copy, so calls that overlap on one GPU
@@ -1523,7 +2220,7 @@ static_assert(kNoAllocBodies % 256 == 0, "bodies are padded to multiples of 256"
 static_assert(kNoAllocBodies <= kPairTarget, "partial sums sized by kPairTarget");
 constexpr size_t kNoAllocBytes =
     (size_t)kNoAllocBodies * (3 * sizeof(double4) + 2 * sizeof(double) + sizeof(int)) +
-    (size_t)kNoAllocBodies / 256 * sizeof(double) + (size_t)kPairTarget * 6 * sizeof(double);
+    (size_t)kNoAllocBodies / 64 * sizeof(double) + (size_t)kPairTarget * 6 * sizeof(double);
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
@@ -1579,8 +2276,8 @@ hipError_t accel_noalloc_run(const StepConsts& c, int n, const double* m, const 
   q += np * sizeof(double);
   w.ccnt = reinterpret_cast<int*>(q);
   q += np * sizeof(int);
-  w.thrmax = reinterpret_cast<double*>(q);
-  q += (size_t)kNoAllocBodies / 256 * sizeof(double);
+  w.tmax64 = reinterpret_cast<double*>(q);
+  q += np / 64 * sizeof(double);
   w.pp = reinterpret_cast<double*>(q);
   q += (size_t)w.njs * 6 * np * sizeof(double);
   if ((size_t)(q - static_cast<char*>(base)) > kNoAllocBytes) return hipErrorInvalidValue;

@@ -281,6 +281,36 @@ class Simulation:
             _check(code, "genga_stats")
         return s.as_dict()
 
+    def set_radii(self, radii):
+        """Physical radii, one per row: collisions between massive bodies
+        (Sec. 3.2.7; main and batched mode)."""
+        r = _dev(radii, self.device).reshape(-1).contiguous()
+        if r.numel() != self.n:
+            raise ValueError("radii: one per row")
+        _check(lib().genga_set_radii(self._ctx, _ptr(r)), "genga_set_radii")
+
+    def events(self):
+        """Every merger and ejection since init, sorted (list of Event)."""
+        n = ctypes.c_int64()
+        code = lib().genga_events(self._ctx, None, 0, ctypes.byref(n))
+        if code not in (OK, EOVERFLOW) and code < 0:
+            _check(code, "genga_events")
+        k = int(n.value)
+        buf = (Event * max(k, 1))()
+        _check(lib().genga_events(self._ctx, buf, max(k, 1), ctypes.byref(n)), "genga_events")
+        return [buf[i] for i in range(k)]
+
+    def bodies(self):
+        """(original row per row, -1 past a system's count; bodies left per
+        system; internal energy U of each system's mergers)."""
+        nsys = getattr(self, "nsys", 1)
+        ids = np.zeros(self.n, dtype=np.int32)
+        nl = np.zeros(nsys, dtype=np.int32)
+        U = np.zeros(nsys)
+        _check(lib().genga_bodies(self._ctx, ids.ctypes.data, self.n, nl.ctypes.data,
+                                  U.ctypes.data, nsys), "genga_bodies")
+        return ids, nl, U
+
     def close(self):
         if getattr(self, "_ctx", None):
             lib().genga_destroy(self._ctx)
@@ -461,34 +491,6 @@ class BatchedSimulation(Simulation):
         if m.numel() != self.n:
             raise ValueError("masses: one per row")
         _check(lib().genga_set_masses(self._ctx, _ptr(m)), "genga_set_masses")
-
-    def set_radii(self, radii):
-        """Physical radii, one per row (mergers, Sec. 3.2.7)."""
-        r = _dev(radii, self.device).reshape(-1).contiguous()
-        if r.numel() != self.n:
-            raise ValueError("radii: one per row")
-        _check(lib().genga_set_radii(self._ctx, _ptr(r)), "genga_set_radii")
-
-    def events(self):
-        """Every merger and ejection since init, sorted (list of Event)."""
-        n = ctypes.c_int64()
-        code = lib().genga_events(self._ctx, None, 0, ctypes.byref(n))
-        if code not in (OK, EOVERFLOW) and code < 0:
-            _check(code, "genga_events")
-        k = int(n.value)
-        buf = (Event * max(k, 1))()
-        _check(lib().genga_events(self._ctx, buf, max(k, 1), ctypes.byref(n)), "genga_events")
-        return [buf[i] for i in range(k)]
-
-    def bodies(self):
-        """(original row per row, -1 past a system's count; bodies left per
-        system; internal energy U of each system's mergers)."""
-        ids = np.zeros(self.n, dtype=np.int32)
-        nl = np.zeros(self.nsys, dtype=np.int32)
-        U = np.zeros(self.nsys)
-        _check(lib().genga_bodies(self._ctx, ids.ctypes.data, self.n, nl.ctypes.data,
-                                  U.ctypes.data, self.nsys), "genga_bodies")
-        return ids, nl, U
 
     def tune(self, nsteps: int = 4):
         """Re-run the tuner; returns ({variant: microseconds}, chosen variant)."""

@@ -438,17 +438,25 @@ def test_bs_depth_reported():
     assert sim.sync() == G.EBS
 
 
-@pytest.mark.parametrize("k", [2, 7, 8, 9, 12])
-def test_bs_group_size_boundaries(k):
-    """A tight cluster of k bodies forms one group of k members: groups of up
-    to 8 take the all-columns BS path, larger ones the lane-per-member path."""
-    rng = np.random.default_rng(50 + k)
+def _cluster(k, spacing, seed):
+    """k co-orbiting bodies on an arc `spacing` rad apart (a chain of
+    encounters: one group of k members)."""
+    rng = np.random.default_rng(seed)
     m = np.full(k, 3e-7)
-    ang = 0.3 + 0.004 * np.arange(k)
+    ang = 0.3 + spacing * np.arange(k)
     a = 1.0 + 0.0005 * rng.standard_normal(k)
     x = np.stack([a * np.cos(ang), a * np.sin(ang), 1e-4 * rng.standard_normal(k)], 1)
     u = np.stack([-np.sin(ang), np.cos(ang), np.zeros(k)], 1) / np.sqrt(a)[:, None]
-    gp = _gparams()
+    return m, x, u
+
+
+@pytest.mark.parametrize("k", [2, 7, 8, 9, 12, 64, 65, 100])
+def test_bs_group_size_boundaries(k):
+    """A tight cluster of k bodies forms one group of k members: groups of up
+    to 8 take the all-columns BS path, up to 64 the lane-per-member path,
+    larger ones the members-in-chunks path (Sec. 3.2.6's large groups)."""
+    m, x, u = _cluster(k, 0.004, 50 + k)
+    gp = _gparams(cand_per_body=96 if k >= 64 else 32)
     sim = G.Simulation(m, x, u, gp, coords="helio")
     orc = O.MassiveSim(_oparams(gp), m, x, u, coords="helio")
     osub = 0
@@ -462,3 +470,32 @@ def test_bs_group_size_boundaries(k):
     assert _rel_body(xg.cpu().numpy(), orc.x) < REL
     assert _rel_body(vg.cpu().numpy(), orc.v) < REL
     assert st["bs_substeps"] == osub
+
+
+def test_many_encounter_pairs_one_large_group():
+    """200 bodies 0.002 rad apart on an arc: about 2,300 encounter pairs per
+    step (beyond the 2,048 the grouping holds in LDS) chaining into one group
+    of 200 members; encounter sets, group size, BS substeps and states against
+    the oracle over two steps (a tighter arc makes the oracle's BS exhaust its
+    depth in the second step)."""
+    m, x, u = _cluster(200, 0.002, 250)
+    gp = _gparams(cand_per_body=160)
+    sim = G.Simulation(m, x, u, gp, coords="helio")
+    orc = O.MassiveSim(_oparams(gp), m, x, u, coords="helio")
+    osub = 0
+    for _ in range(2):
+        sim.step(1)
+        osub += orc.step(1)["bs_substeps"]
+        ij, d2, rc2 = sim.encounters()
+        _say("many pairs: gpu", len(ij), sim.stats(), "oracle", len(orc.enc), orc.stats.as_dict())
+        xg, vg = sim.state()
+        _say("rel x", _rel_body(xg.cpu().numpy(), orc.x), "v", _rel_body(vg.cpu().numpy(), orc.v))
+        _pairs_close(ij, orc.enc, d2, rc2, orc.enc_d2, orc.enc_rc2)
+        assert len(ij) > 2048
+    st = sim.stats()
+    _say("many pairs", st, orc.stats.as_dict())
+    assert st["max_group"] == orc.stats.max_group == 200 and st["n_groups"] == 1
+    assert st["bs_substeps"] == osub
+    xg, vg = sim.state()
+    assert _rel_body(xg.cpu().numpy(), orc.x) < REL
+    assert _rel_body(vg.cpu().numpy(), orc.v) < REL

@@ -317,9 +317,10 @@ def test_tp_radii_errors_and_removed_rows_round_trip():
     x[planets.m.size + gone[0]] = 0.5
     with pytest.raises(G.GengaError):
         sim2.set_state(x, v, coords="dem")
-    # main mode has no radii
+    # main mode takes radii only with encounters (the K = 1 map has no BS)
     import torch
-    ms = G.Simulation(planets.m, planets.x, planets.u, gp, coords="helio")
+    ms = G.Simulation(planets.m, planets.x, planets.u, G.default_params(encounter_free=1),
+                      coords="helio")
     r = torch.zeros(planets.m.size, dtype=torch.float64, device="cuda")
     assert G.lib().genga_set_radii(ms._ctx, r.data_ptr()) == G.EINVAL
     ms.close()

@@ -392,6 +392,28 @@ def test_bs_deep_encounter_conserves_HA_and_converges():
     np.testing.assert_allclose(L1, L0, rtol=0, atol=1e-13 * np.abs(L0).max())
 
 
+def test_bs_large_group_conserves_HA_and_L():
+    """A chain of 100 bodies 0.004 AU apart, all inside each other's
+    changeover band (one group far beyond the GPU's in-wave limit of 64):
+    H_A and the angular momentum of the group are kept over tau."""
+    p = O.params(bs_tol=1e-13)
+    rng = np.random.default_rng(77)
+    k = 100
+    m = np.full(k, 3e-7)
+    ang = 0.3 + 0.004 * np.arange(k)
+    a = 1.0 + 0.0005 * rng.standard_normal(k)
+    x = np.stack([a * np.cos(ang), a * np.sin(ang), 1e-4 * rng.standard_normal(k)], 1)
+    v = np.stack([-np.sin(ang), np.cos(ang), np.zeros(k)], 1) / np.sqrt(a)[:, None]
+    rc = np.full(k, 0.025)
+    E0 = _HA(p, m, rc, x, v)
+    xb, vb, sub = O.bs_group(p, m, rc, x, v, 0.0628)
+    E1 = _HA(p, m, rc, xb, vb)
+    assert sub >= 1 and abs((E1 - E0) / E0) < 1e-11
+    L0 = (m[:, None] * np.cross(x, v)).sum(0)
+    L1 = (m[:, None] * np.cross(xb, vb)).sum(0)
+    np.testing.assert_allclose(L1, L0, rtol=0, atol=1e-13 * np.abs(L0).max())
+
+
 def test_bs_depth_exhaustion_is_an_error():
     p = O.params(bs_tol=-1.0, bs_max_depth=3)  # no column can ever be accepted
     m = np.array([1e-6, 1e-6])
