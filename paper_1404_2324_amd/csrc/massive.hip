@@ -92,7 +92,6 @@ constexpr int kFinThreads = 64;                // threads of the finishing kerne
 
 struct PairArgs {
   const double* __restrict__ rc;      // radii of the step
-  const double* __restrict__ tmax64;  // largest threshold of each 64-body chunk
   int* __restrict__ ccnt;             // candidate table (appended)
   int* __restrict__ ctab;
   double* __restrict__ cr2;
@@ -105,15 +104,15 @@ struct PairArgs {
   const double* __restrict__ partP2;  // momentum partials after the drift
   const double* __restrict__ dP;      // momentum change of each BS group
   DevStat* __restrict__ st;
-  int n, np, cpb, nblk, njs, encounter_free;
+  int n, np, cpb, nblk, njs, jl, encounter_free;  // jl = np / (16 njs) partners per wave
   double G, h, m0, mu, n1, n2, absdt, pf;
 };
 
 enum { KICK_CLOSE = 0, KICK_INIT = 1, KICK_ACC = 2 };
 
-// Workgroup b takes the 64 bodies i = 64 (b / njs) + lane and the partners
-// of split b mod njs; each of its 16 waves a contiguous range of L = np /
-// (16 njs) partners j, the same j for every lane, so the partner data
+// Workgroup (b, s) takes the 64 bodies i = 64 b + lane and the partners of
+// split s; each of its 16 waves a contiguous range of L = np / (16 njs)
+// partners j (L is even: np is a multiple of 32 njs), the same j for every lane, so the partner data
 // (x, y, z, m) comes through the scalar cache into SGPRs, two partners ahead
 // of their use: the pair loop issues no vector memory instruction.  The
 // bodies are padded to a multiple of 256 with massless bodies at the origin,
@@ -131,19 +130,25 @@ enum { KICK_CLOSE = 0, KICK_INIT = 1, KICK_ACC = 2 };
 template <int MODE>
 __global__ __launch_bounds__(kPairThreads) void k_pair_part(PairArgs a,
                                                             const double4* __restrict__ x,
-                                                            const double* __restrict__ thr) {
+                                                            const double* __restrict__ thr,
+                                                            const double* __restrict__ tmx) {
   __shared__ double red[6][kPairW][kPairBlock];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int ib = blockIdx.x / a.njs, sp = blockIdx.x - ib * a.njs;
-  // a context's step: stopped runs do nothing, and rows past the count are
-  // padding (bodies that left); the acceleration form has no status word
-  // (st may be null) and takes every body
-  if (MODE != KICK_ACC && a.st->stopped) return;
-  const int nl = MODE == KICK_ACC ? a.n : a.st->nlive;
+  const int ib = blockIdx.x, sp = blockIdx.y;
+  // a context's step: a stopped run appends nothing (its partial sums are
+  // written and ignored by the finishing kernel), and rows past the live
+  // count are padding (bodies that left); the acceleration form has no
+  // status word (st may be null) and takes every body.  The status word is
+  // loaded here and first read in the rare candidate branch, so that no
+  // wave waits for it before its pair loop.
+  int nl = a.n, stopped = 0;
+  if (MODE != KICK_ACC) {
+    nl = a.st->nlive;
+    stopped = a.st->stopped;
+  }
   const int i = ib * kPairBlock + lane;
-  const bool iv = i < nl;
-  const int L = a.np / (a.njs * kPairW);
+  const int L = a.jl;
   const int j0 = __builtin_amdgcn_readfirstlane((sp * kPairW + wave) * L);
   const double4* xj = x + j0;
   double4 cur[kPairU], nxt[kPairU];
@@ -151,17 +156,29 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_part(PairArgs a,
   for (int q = 0; q < kPairU; ++q) nxt[q] = xj[q];
   const double4 pi = x[i];
   const double ti = thr[i];
-  // T = the largest threshold of the wave's bodies and of its partners
-  double T = a.tmax64[ib];
-  for (int c = (j0 >> 6) + lane; c <= (j0 + L - 1) >> 6; c += 64) T = fmax(T, a.tmax64[c]);
-  T = wave_max(T);
+  // T = the largest threshold of the wave's bodies and of the 64-body chunk
+  // of partners in use, from the chunk maxima (wave-uniform, through the
+  // scalar cache); the next chunk's maximum is loaded a chunk ahead, so that
+  // every load of the prologue is issued before the first wait
+  const double Ti = tmx[ib];
+  const int clast = (j0 + L - 1) >> 6;
+  int cn = j0 >> 6;
+  double tn = tmx[cn], T = 0.0;
   double fx = 0.0, fy = 0.0, fz = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
   // the series constants of m_rinv3 in registers for the whole loop (an
   // empty asm statement hides their values, so that they are not re-made
   // from literals for every pair)
   double c1875 = 1.875, c15 = 1.5;
   asm volatile("" : "+v"(c1875), "+v"(c15));
-  for (int k = 0; k < L; k += kPairU) {
+  int k = 0;
+  do {  // L >= 2: no test before the first batch, so that the prologue's loads go out together
+    // partner ranges and kPairU-partner batches are aligned so that a batch
+    // never straddles two chunks
+    if (((j0 + k) >> 6) == cn) {
+      T = fmax(Ti, tn);
+      ++cn;
+      tn = tmx[min(cn, clast)];
+    }
 #pragma unroll
     for (int q = 0; q < kPairU; ++q) cur[q] = nxt[q];
     if (k + kPairU < L) {
@@ -182,12 +199,16 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_part(PairArgs a,
       if (__builtin_expect(__builtin_amdgcn_ballot_w64(c) != 0ull, 0)) {
         const int j = j0 + k + q;
         const double tj = thr[j];
+        // (an empty asm statement keeps the status word's use, and its
+        // wait, inside this branch)
+        int nlv = nl, stv = stopped;
+        asm volatile("" : "+s"(nlv), "+s"(stv));
         if (c) {
           if (!(r2 < ti || r2 < tj)) {
             fx = fma(s, dx, fx);
             fy = fma(s, dy, fy);
             fz = fma(s, dz, fz);
-          } else if (iv && j != i && j < nl) {
+          } else if (i < nlv && j != i && j < nlv) {
             const double ir = rsqrt_nr(r2);
             const double ir2 = ir * ir;
             double K = 1.0, dK = 0.0;
@@ -196,7 +217,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_part(PairArgs a,
             nx += sn * dx;
             ny += sn * dy;
             nz += sn * dz;
-            if (MODE != KICK_ACC && !a.encounter_free) {
+            if (MODE != KICK_ACC && !a.encounter_free && !stv) {
               const int slot = atomicAdd(&a.ccnt[i], 1);
               if (slot < a.cpb) {
                 a.ctab[(size_t)i * a.cpb + slot] = j;
@@ -209,7 +230,8 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_part(PairArgs a,
         }
       }
     }
-  }
+    k += kPairU;
+  } while (k < L);
   red[0][wave][lane] = fx;
   red[1][wave][lane] = fy;
   red[2][wave][lane] = fz;
@@ -1825,9 +1847,9 @@ PairArgs pair_args(const MassiveWs& w, const StepConsts& c) {
   a.ccnt = w.ccnt;
   a.ctab = w.ctab;
   a.cr2 = w.cr2;
-  a.tmax64 = w.tmax64;
   a.pp = w.pp;
   a.njs = w.njs;
+  a.jl = w.np / (w.njs * kPairW);
   a.xs = w.xs;
   a.vv = w.vv;
   a.afar = w.afar;
@@ -1853,7 +1875,7 @@ PairArgs pair_args(const MassiveWs& w, const StepConsts& c) {
 }
 
 // Workgroups of the pair kernel: 64-body blocks x splits.
-inline unsigned pair_grid(const MassiveWs& w) { return (unsigned)(w.np / kPairBlock * w.njs); }
+inline dim3 pair_grid(const MassiveWs& w) { return dim3(w.np / kPairBlock, w.njs); }
 
 }  // namespace
 
@@ -2019,8 +2041,8 @@ hipError_t massive_prime(const MassiveWs& w, const StepConsts& c, hipStream_t s)
                      w.rc_cur, w.thr, w.tmax64, w.ccnt, w.n, c.mu, c.m0, c.n1, c.n2, fabs(c.dt),
                      c.pf2, c.encounter_free);
   PairArgs a = pair_args(w, c);
-  hipLaunchKernelGGL(k_pair_part<KICK_INIT>, dim3(pair_grid(w)), dim3(kPairThreads), 0, s, a,
-                     (const double4*)w.xm, (const double*)w.thr);
+  hipLaunchKernelGGL(k_pair_part<KICK_INIT>, pair_grid(w), dim3(kPairThreads), 0, s, a,
+                     (const double4*)w.xm, (const double*)w.thr, (const double*)w.tmax64);
   hipLaunchKernelGGL(k_pair_finish<KICK_INIT>, dim3(ceil_div(w.n, kFinThreads)), dim3(kFinThreads),
                      0, s, a, (const double4*)w.xm);
   // the momentum for the first step's first Sun kick
@@ -2033,8 +2055,8 @@ hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, const double4*
                          double* acc, hipStream_t s) {
   PairArgs a = pair_args(w, c);
   a.acc_out = acc;
-  hipLaunchKernelGGL(k_pair_part<KICK_ACC>, dim3(pair_grid(w)), dim3(kPairThreads), 0, s, a, x,
-                     (const double*)w.thr);
+  hipLaunchKernelGGL(k_pair_part<KICK_ACC>, pair_grid(w), dim3(kPairThreads), 0, s, a, x,
+                     (const double*)w.thr, (const double*)w.tmax64);
   hipLaunchKernelGGL(k_pair_finish<KICK_ACC>, dim3(ceil_div(w.n, kFinThreads)), dim3(kFinThreads),
                      0, s, a, x);
   return hipGetLastError();
@@ -2169,8 +2191,8 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
   }
 
   PairArgs a = pair_args(w, c);
-  STEP_LAUNCH(4, k_pair_part<KICK_CLOSE>, dim3(pair_grid(w)), dim3(kPairThreads), a,
-              (const double4*)w.xm, (const double*)w.thr);
+  STEP_LAUNCH(4, k_pair_part<KICK_CLOSE>, pair_grid(w), dim3(kPairThreads), a,
+              (const double4*)w.xm, (const double*)w.thr, (const double*)w.tmax64);
   STEP_LAUNCH(5, k_pair_finish<KICK_CLOSE>, dim3(ceil_div(w.n, kFinThreads)), dim3(kFinThreads), a,
               (const double4*)w.xm);
   return hipGetLastError();
