@@ -14,6 +14,9 @@ Parity status (see the C source for the passage each routine follows):
   BS sequence / error norm / tolerance, the Hill-radius reading and the
   strictness of the encounter threshold: parity unpinned against the paper
   (readings), pinned only by the physics invariants.
+  Derivative of the hybrid step (``genga_cstep.c``, complex step): pinned by
+  its real parts (equal to the main-mode step), the tangent-linear model of
+  the encounter-free map and central differences of the main-mode step.
 """
 from __future__ import annotations
 
@@ -25,6 +28,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "genga_oracle.c")
+_SRC_CS = os.path.join(_HERE, "genga_cstep.c")
 _LIB = os.path.join(_HERE, "libgenga_oracle.so")
 
 GO_OK, GO_EINVAL, GO_EOVERFLOW, GO_EKEPLER, GO_EBS, GO_EADJ_ENCOUNTER = 0, -1, -3, -4, -5, -6
@@ -34,7 +38,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc into ``oracle/libgenga_oracle.so``."""
     if force or not os.path.exists(_LIB):
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-               "-fopenmp", "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+               "-fopenmp", "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, _SRC_CS, "-lm"]
         subprocess.check_call(cmd, cwd=_HERE)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -137,6 +141,10 @@ def lib():
                                   _D, _D]),
             "go_free_adjoint": (i32, [_P, i32, _D, _D, _D, i64, _D, _D, _D, _D,
                                       _D]),
+            "go_cs_massive": (i32, [_P, i32, _D, _D, _D, _D, _D, _D, ctypes.c_double, i64,
+                                    _D, _D, _D, _D, ctypes.POINTER(Stats)]),
+            "go_kepler_root": (i32, [ctypes.c_double, _D, _D, ctypes.c_double, i32, _D,
+                                     ctypes.POINTER(ctypes.c_int)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -524,3 +532,45 @@ def free_adjoint(p: Params, m, x0, v0, nsteps, gxT, gvT):
                                  int(nsteps), _d(gxT), _d(gvT), _d(gx0), _d(gv0),
                                  _d(gm)), "free_adjoint")
     return gx0, gv0, gm
+
+
+# ------------------- derivative of the hybrid step (complex step) ---
+def cs_massive(p: Params, m, x0, v0, dm, dx0, dv0, nsteps, h=1e-30):
+    """nsteps steps of the main-mode step (as MassiveSim.step, no collisions)
+    from democratic (x0, v0) and their derivative along (dm, dx0, dv0), with
+    every decision of the run (candidates, encounters, groups, BS acceptance
+    and halving, Kepler stopping) held fixed: the complex-step derivative of
+    genga_cstep.c.  Returns xT, vT (equal to the real run's), dxT, dvT and
+    the counters."""
+    m = _f64(m)
+    x0, v0 = _f64(x0, (-1, 3)), _f64(v0, (-1, 3))
+    dm = _f64(dm) if dm is not None else np.zeros_like(m)
+    dx0 = _f64(dx0, (-1, 3)) if dx0 is not None else np.zeros_like(x0)
+    dv0 = _f64(dv0, (-1, 3)) if dv0 is not None else np.zeros_like(v0)
+    xT, vT = np.zeros_like(x0), np.zeros_like(v0)
+    dxT, dvT = np.zeros_like(x0), np.zeros_like(v0)
+    st = Stats()
+    _check(lib().go_cs_massive(ctypes.byref(p), len(m), _d(m), _d(x0), _d(v0), _d(dm), _d(dx0),
+                               _d(dv0), float(h), int(nsteps), _d(xT), _d(vT), _d(dxT), _d(dvT),
+                               ctypes.byref(st)), "cs_massive")
+    return xT, vT, dxT, dvT, st.as_dict()
+
+
+def cs_gradient(p: Params, m, x0, v0, nsteps, gxT, gvT):
+    """Gradient of L with dL/dx_T = gxT, dL/dv_T = gvT with respect to
+    (x0, v0, m) through nsteps hybrid steps, one directional derivative per
+    input coordinate (7 n runs of cs_massive: small systems only)."""
+    m = _f64(m)
+    x0, v0 = _f64(x0, (-1, 3)), _f64(v0, (-1, 3))
+    gxT, gvT = _f64(gxT, (-1, 3)), _f64(gvT, (-1, 3))
+    n = len(m)
+    gx, gv, gm = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(n)
+    for which, out in ((0, gx), (1, gv), (2, gm)):
+        for idx in np.ndindex(out.shape):
+            d = [None, None, None]
+            e = np.zeros(out.shape)
+            e[idx] = 1.0
+            d[which] = e
+            _, _, dxT, dvT, _ = cs_massive(p, m, x0, v0, d[2], d[0], d[1], nsteps)
+            out[idx] = np.sum(gxT * dxT) + np.sum(gvT * dvT)
+    return gx, gv, gm

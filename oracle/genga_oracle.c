@@ -294,6 +294,16 @@ int go_kepler(double mu, const double *x0, const double *v0, double dt,
     return rcode;
 }
 
+/* The root s of the universal Kepler equation that go_kepler takes (its own
+ * iteration), for the complex-step derivative of the drift. */
+int go_kepler_root(double mu, const double *x0, const double *v0, double dt, int max_iter,
+                   double *s, int *iters) {
+    double r0 = sqrt(dot3(x0, x0));
+    double eta0 = dot3(x0, v0);
+    double beta = 2.0 * mu / r0 - dot3(v0, v0);
+    return kepler_solve(mu, r0, eta0, beta, dt, max_iter, s, iters);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Close-encounter test, Eqs. (10)-(12).  P(t) is the cubic Hermite
  * interpolant of the squared separation over t in [0,1] (physical time

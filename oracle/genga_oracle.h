@@ -76,6 +76,8 @@ void go_sun_drift(const go_params *p, int n, const double *m, double *x,
 int go_kepler(double mu, const double *x0, const double *v0, double dt,
               double *x, double *v, int max_iter, int *iters);
 void go_stumpff(double z, double c[4]);
+int go_kepler_root(double mu, const double *x0, const double *v0, double dt, int max_iter,
+                   double *s, int *iters);
 double go_hermite_dmin2(double dt, const double *dx0, const double *dv0,
                         const double *dx1, const double *dv1);
 int go_groups(int n, int npairs, const int32_t *ij, int32_t *label);
@@ -94,6 +96,17 @@ int go_massive_step(const go_params *p, int n, const double *m, double *x,
                     double *v, double *rc, uint8_t *cand, int64_t nsteps,
                     go_stats *st, int enc_cap, int32_t *enc_ij,
                     double *enc_d2, double *enc_rc2, int *n_enc);
+
+/* ---- complex-step derivative of the hybrid step (genga_cstep.c) ---------
+ * nsteps steps of go_massive_step (no collisions) from (m, x, v) in complex
+ * arithmetic along the direction (dm, dx, dv) (any may be NULL = 0) with
+ * imaginary step hstep: xT, vT the real state (equal to go_massive_step's),
+ * dxT, dvT the directional derivative of the state with every decision of
+ * the run held fixed.  st: counters as go_massive_step (may be NULL).     */
+int go_cs_massive(const go_params *p, int n, const double *m, const double *x,
+                  const double *v, const double *dm, const double *dx, const double *dv,
+                  double hstep, int64_t nsteps, double *xT, double *vT, double *dxT,
+                  double *dvT, go_stats *st);
 
 /* ---- higher orders (Sec. 2.3) ------------------------------------------- */
 /* Sub-step coefficients of the composition of the given order (2, 4 or 6)

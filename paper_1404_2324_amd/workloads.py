@@ -235,6 +235,29 @@ def adjoint_systems(nsys: int = 1024, nplanets: int = 8, seed_index: int = 5,
     return np.stack(ms), np.stack(xs), np.stack(us)
 
 
+def encounter_systems(nsys: int = 1024, nplanets: int = 8, seed_index: int = 7,
+                      da: float = 0.01, dphase: float = 0.06):
+    """Systems of planets packed so that close encounters happen from the
+    first step: masses log-uniform in [1e-8, 1e-7], a ~ U(1 - da, 1 + da),
+    e ~ Ray(0.005), i ~ Ray(0.001), random node and pericentre, and mean
+    longitudes within dphase rad of each other (the radii of Eq. 6 are
+    ~0.025 AU, the velocity term, so most pairs start inside their changeover
+    zone).  Returns (m, x, u) of shape (nsys, nplanets[, 3])."""
+    rng = rng_for(seed_index)
+    n = nsys * nplanets
+    m = np.exp(rng.uniform(np.log(1e-8), np.log(1e-7), n))
+    a = rng.uniform(1.0 - da, 1.0 + da, n)
+    e = rayleigh(rng, 0.005, n)
+    inc = rayleigh(rng, 0.001, n)
+    node = rng.uniform(0.0, 2.0 * np.pi, n)
+    peri = rng.uniform(0.0, 2.0 * np.pi, n)
+    lam = rng.uniform(0.0, dphase, n)
+    M = np.mod(lam - node - peri, 2.0 * np.pi)
+    x, u = elements_to_cartesian(1.0 + m, a, e, inc, node, peri, M)
+    return (m.reshape(nsys, nplanets), x.reshape(nsys, nplanets, 3),
+            u.reshape(nsys, nplanets, 3))
+
+
 def perturbed(x, u, rel: float = 1e-6, seed_index: int = 1005):
     """Relative Gaussian perturbation of a state (for adjoint targets)."""
     rng = rng_for(seed_index)

@@ -56,6 +56,47 @@ MUTANTS = {
 }
 
 
+# the complex-step derivative of the hybrid step (genga_cstep.c)
+CS_MUTANTS = {
+    "cs_kepler_root_fixed": ("cplx sc = CMPLX(s, -cimag(F) / creal(Fp));", "cplx sc = s;"),
+    "cs_sqrt_slope": ("return CMPLX(s, cimag(z) / (2.0 * s));", "return CMPLX(s, cimag(z) / s);"),
+    "cs_cbrt_slope": ("return CMPLX(c, cimag(z) / (3.0 * c * c));",
+                      "return CMPLX(c, cimag(z) / (3.0 * c));"),
+    "cs_radius_fixed": ("cplx y = (r - 0.1 * rcij) / (0.9 * rcij);",
+                        "cplx y = (r - 0.1 * creal(rcij)) / (0.9 * creal(rcij));"),
+    "cs_bs_mass_fixed": ("cplx sj = s->p->G * s->m[j] * f;",
+                         "cplx sj = s->p->G * creal(s->m[j]) * f;"),
+    "cs_ha_kprime_sign": ("cplx f = (1.0 - K) / (q2 * q) + dK / q2;",
+                          "cplx f = (1.0 - K) / (q2 * q) - dK / q2;"),
+    "cs_sun_mass_fixed": ("P[k] += m[j] * v[3 * j + k];", "P[k] += creal(m[j]) * v[3 * j + k];"),
+}
+
+
+def _run_mutant(tmp_path, fname, a, b, pins_filter=None):
+    src = open(os.path.join(ROOT, "oracle", fname)).read()
+    assert a in src, "mutation pattern no longer present in the oracle"
+    pkg = tmp_path / "oracle"
+    shutil.copytree(os.path.join(ROOT, "oracle"), pkg,
+                    ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    (pkg / fname).write_text(src.replace(a, b, 1))
+    args = ['-q', '-x', '-p', 'no:cacheprovider']
+    if pins_filter:
+        args += ['-k', pins_filter]
+    code = ("import sys; sys.path.insert(0, %r); sys.path.insert(1, %r); import pytest; "
+            "sys.exit(pytest.main(%r + [%r]))"
+            % (str(tmp_path), ROOT, args, os.path.join(ROOT, "tests", "test_oracle_pins.py")))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OMP_WAIT_POLICY="passive")
+    return subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                          cwd=str(tmp_path), timeout=600, env=env)
+
+
+@pytest.mark.parametrize("name", sorted(CS_MUTANTS))
+def test_cs_pins_catch_mutant(name, tmp_path):
+    a, b = CS_MUTANTS[name]
+    r = _run_mutant(tmp_path, "genga_cstep.c", a, b, pins_filter="cs_")
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_mutant(name, tmp_path):
     a, b = MUTANTS[name]

@@ -887,3 +887,77 @@ def test_composed_order2_is_the_plain_step_and_reversible():
         xb, vb, _, _ = O.step_order(pb, order, s.m, x1, v1, 10)
         np.testing.assert_allclose(xb, s.x, rtol=0, atol=1e-13)
         np.testing.assert_allclose(vb, v0, rtol=0, atol=1e-13)
+
+
+# --------------------- derivative of the hybrid step (complex step) --------
+def _enc_system(seed_index=7, nplanets=6):
+    m, x, u = W.encounter_systems(nsys=1, nplanets=nplanets, seed_index=seed_index)
+    p = O.params()
+    return p, m[0], x[0], O.helio_to_dem(p, m[0], u[0])
+
+
+def test_cs_real_parts_are_the_main_step():
+    """The complex run's real parts are the main-mode step's results bit for
+    bit (same decisions, same counters); a zero direction gives zero."""
+    for seed in (7, 8):
+        p, m, x, v = _enc_system(seed)
+        sim = O.MassiveSim(p, m, x, v)
+        st = sim.step(25)
+        assert st["enc_total"] > 0 and st["bs_substeps"] > 0
+        xT, vT, dxT, dvT, st2 = O.cs_massive(p, m, x, v, None, None, None, 25)
+        assert np.array_equal(xT, sim.x) and np.array_equal(vT, sim.v)
+        assert (st2["enc_total"], st2["bs_substeps"], st2["max_group"]) == \
+            (st["enc_total"], st["bs_substeps"], st["max_group"])
+        assert not dxT.any() and not dvT.any()
+
+
+def test_cs_encounter_free_equals_tlm():
+    """K = 1: the complex-step derivative is the tangent-linear model's."""
+    p, m, x, v = _adj_system()
+    rng = np.random.default_rng(31)
+    dx, dv = rng.standard_normal(x.shape), rng.standard_normal(v.shape)
+    dm = rng.standard_normal(m.shape) * m
+    _, _, cx, cv, _ = O.cs_massive(p, m, x, v, dm, dx, dv, 100)
+    _, _, tx, tv = O.free_tlm(p, m, x, v, dm, dx, dv, 100)
+    assert np.abs(cx - tx).max() <= 1e-12 * np.abs(tx).max()
+    assert np.abs(cv - tv).max() <= 1e-12 * np.abs(tv).max()
+
+
+# (system, direction) -> the step of the differences, where their error is
+# smallest; "heavy": masses in [1e-6, 1e-5], where the Hill term of Eq. (6)
+# sets the radii and their derivative matters
+_CS_FD = {("light", "all"): 1e-7, ("light", "x"): 1e-7, ("light", "v"): 1e-6,
+          ("light", "m"): 1e-3, ("heavy", "x"): 1e-7, ("heavy", "v"): 1e-6,
+          ("heavy", "m"): 1e-3}
+
+
+@pytest.mark.parametrize("case,which", sorted(_CS_FD))
+def test_cs_hybrid_matches_central_differences(case, which):
+    """With encounters, the changeover zone and BS groups, the complex-step
+    derivative agrees with central differences of the main-mode step.  Over
+    3 steps the differences are 1e-8 to 1e-6 relative (their truncation and
+    the rare BS decisions that the perturbation moves); a dropped or
+    mis-scaled term of the derivative is far larger."""
+    p, m, x, v = _enc_system(7)
+    if case == "heavy":
+        m = np.exp(np.random.default_rng(3).uniform(np.log(1e-6), np.log(1e-5), len(m)))
+    rng = np.random.default_rng(41 + sorted(_CS_FD).index((case, which)))
+    dx, dv = rng.standard_normal(x.shape), rng.standard_normal(v.shape)
+    dm = rng.standard_normal(m.shape) * m
+    if which == "x":
+        dv, dm = 0 * dv, 0 * dm
+    elif which == "v":
+        dx, dm = 0 * dx, 0 * dm
+    elif which == "m":
+        dx, dv = 0 * dx, 0 * dv
+    T = 3
+    _, _, cx, cv, st = O.cs_massive(p, m, x, v, dm, dx, dv, T)
+    assert st["n_groups"] > 0 and st["bs_substeps"] > 0
+    eps = _CS_FD[(case, which)]
+    sp = O.MassiveSim(p, m + eps * dm, x + eps * dx, v + eps * dv)
+    sp.step(T)
+    sm = O.MassiveSim(p, m - eps * dm, x - eps * dx, v - eps * dv)
+    sm.step(T)
+    fx, fv = (sp.x - sm.x) / (2 * eps), (sp.v - sm.v) / (2 * eps)
+    assert np.abs(fx - cx).max() <= 1e-5 * np.abs(cx).max()
+    assert np.abs(fv - cv).max() <= 1e-5 * np.abs(cv).max()
