@@ -259,17 +259,67 @@ template <int MODE>
 __global__ __launch_bounds__(kFinThreads) void k_pair_finish(PairArgs a,
                                                              const double4* __restrict__ x) {
   const int lane = threadIdx.x;
-  const int i = blockIdx.x * kFinThreads + lane;
-  if (MODE != KICK_ACC && a.st->stopped) return;  // no status word in the ACC form
-  double Px = 0.0, Py = 0.0, Pz = 0.0;
+  const int i = blockIdx.x * kFinThreads + lane;  // < np: pp and x hold np rows
+  // Every load that does not depend on the status word goes out before it
+  // is read: the status word (the ACC form has none), the momentum partials
+  // and the first 64 groups' momentum changes (dP holds more than 64), and
+  // the splits' partial sums.
+  int stopped = 0, nl = a.n, ng = 0;
+  if (MODE != KICK_ACC) {
+    stopped = a.st->stopped;
+    nl = a.st->nlive;
+    ng = a.encounter_free ? 0 : a.st->ngroups;
+  }
+  double Px = 0.0, Py = 0.0, Pz = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
   if (MODE == KICK_CLOSE) {
-    for (int b = lane; b < a.nblk; b += 64) {
+    if (lane < a.nblk) {
+      Px = a.partP2[4 * lane + 0];
+      Py = a.partP2[4 * lane + 1];
+      Pz = a.partP2[4 * lane + 2];
+    }
+    for (int b = lane + 64; b < a.nblk; b += 64) {
       Px += a.partP2[4 * b + 0];
       Py += a.partP2[4 * b + 1];
       Pz += a.partP2[4 * b + 2];
     }
-    const int ng = a.encounter_free ? 0 : a.st->ngroups;
-    for (int g = lane; g < ng; g += 64) {
+    gx = a.dP[4 * lane + 0];
+    gy = a.dP[4 * lane + 1];
+    gz = a.dP[4 * lane + 2];
+  }
+  double4 p = make_double4(0.0, 0.0, 0.0, 0.0), vi = p;
+  double rci = 0.0;
+  if (MODE != KICK_ACC) {
+    p = x[i];
+    rci = a.rc[i];
+  }
+  if (MODE == KICK_CLOSE) vi = a.vv[i];
+  double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // eight splits' loads in flight at a time, added in split order (past
+  // the last split the load repeats it and the value is dropped)
+  for (int s0 = 0; s0 < a.njs; s0 += 8) {
+    double v[8][6];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const size_t su = (size_t)min(s0 + u, a.njs - 1);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double t = a.pp[(su * 6 + c) * a.np + i];
+        v[u][c] = s0 + u < a.njs ? t : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) S[c] += v[u][c];
+  }
+  if (stopped) return;
+  if (MODE == KICK_CLOSE) {
+    if (lane < ng) {
+      Px += gx;
+      Py += gy;
+      Pz += gz;
+    }
+    for (int g = lane + 64; g < ng; g += 64) {
       Px += a.dP[4 * g + 0];
       Py += a.dP[4 * g + 1];
       Pz += a.dP[4 * g + 2];
@@ -288,21 +338,7 @@ __global__ __launch_bounds__(kFinThreads) void k_pair_finish(PairArgs a,
     }
   }
   if (MODE == KICK_INIT && blockIdx.x == 0 && lane == 0) a.st->ctl = 0u;
-  if (i >= (MODE == KICK_ACC ? a.n : a.st->nlive)) return;
-  double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  // eight splits' loads in flight at a time, added in split order
-  for (int s0 = 0; s0 < a.njs; s0 += 8) {
-    double v[8][6];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-#pragma unroll
-      for (int c = 0; c < 6; ++c)
-        v[u][c] = s0 + u < a.njs ? a.pp[((size_t)(s0 + u) * 6 + c) * a.np + i] : 0.0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-#pragma unroll
-      for (int c = 0; c < 6; ++c) S[c] += v[u][c];
-  }
+  if (i >= nl) return;
   const double G = a.G;
   if (MODE == KICK_ACC) {
     a.acc_out[3 * (size_t)i + 0] = G * (S[0] + S[3]);
@@ -311,9 +347,8 @@ __global__ __launch_bounds__(kFinThreads) void k_pair_finish(PairArgs a,
     return;
   }
   a.afar[i] = make_double4(G * S[0], G * S[1], G * S[2], 0.0);
-  double4 p = x[i];
   if (MODE == KICK_INIT) {
-    a.rc_next[i] = a.rc[i];
+    a.rc_next[i] = rci;
     a.xs[i] = p;
     return;
   }
@@ -321,7 +356,7 @@ __global__ __launch_bounds__(kFinThreads) void k_pair_finish(PairArgs a,
   p.y += a.h * Py / a.m0;
   p.z += a.h * Pz / a.m0;
   a.xs[i] = p;
-  double4 v = a.vv[i];
+  double4 v = vi;
   v.x += a.h * (G * (S[0] + S[3]));
   v.y += a.h * (G * (S[1] + S[4]));
   v.z += a.h * (G * (S[2] + S[5]));
@@ -329,7 +364,7 @@ __global__ __launch_bounds__(kFinThreads) void k_pair_finish(PairArgs a,
   const double rcn =
       rcrit(p.x, p.y, p.z, v.x, v.y, v.z, p.w, a.mu, a.m0, a.n1, a.n2, a.absdt);
   a.rc_next[i] = rcn;
-  if (!a.encounter_free && rcn > a.pf * a.rc[i]) atomicOr(&a.st->ctl, C_FULLKICK);
+  if (!a.encounter_free && rcn > a.pf * rci) atomicOr(&a.st->ctl, C_FULLKICK);
 }
 
 // Largest threshold of the 64 bodies i0 .. i0 + 63 of a wave (lanes past
