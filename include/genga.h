@@ -373,23 +373,39 @@ int genga_events(genga_ctx *ctx, genga_event *h_ev, int64_t cap, int64_t *h_n);
 int genga_bodies(genga_ctx *ctx, int32_t *h_id, int64_t cap, int32_t *h_nlive, double *h_U,
                  int sys_cap);
 
-/* ---- reverse-mode gradient of the encounter-free map ----------------------
- * For a batched context created with encounter_free = 1: the map with K = 1
- * (the MVS map in democratic coordinates, Sec. 2.1; kick tau/2, Sun kick
- * tau/2, Kepler drift tau, Sun kick tau/2, kick tau/2).  The paper has no
- * adjoint; this one differentiates that map exactly (up to rounding). */
+/* ---- reverse-mode gradients ------------------------------------------------
+ * The paper has no adjoint.  Two maps of a batched context are
+ * differentiated, chosen by its parameters:
+ *  - encounter_free = 1: the map with K = 1 (the MVS map in democratic
+ *    coordinates, Sec. 2.1; kick tau/2, Sun kick tau/2, Kepler drift tau,
+ *    Sun kick tau/2, kick tau/2), exactly (up to rounding);
+ *  - encounter_free = 0, no radii, rcut = rcut_sun = 0: the second-order
+ *    hybrid step (Eq. 7, Sec. 2.2) with the changeover K, K' (Eqs. 4-5), the
+ *    critical radii (Eq. 6) as functions of the state and masses, the
+ *    encounter test (Eqs. 10-12), the groups (App. A) and BS of H_A per
+ *    group, differentiated with every decision of the run held fixed
+ *    (candidates, encounters, groups, accepted BS substeps and their
+ *    extrapolation column, branches of K and Eq. 6).  The first step's
+ *    candidates are the precheck of the initial state with its own radii.
+ *    A group that takes more than 64 accepted BS substeps in one step
+ *    latches GENGA_EOVERFLOW in the backward pass; BS depth exhaustion
+ *    GENGA_EBS. */
 
 /* Bytes of the caller's buffer for nsteps steps with a checkpoint every
- * ckpt_every steps (the checkpoints plus one segment's tape); 0 when the
- * context is not a batched encounter-free one or the arguments are invalid. */
+ * ckpt_every steps (the checkpoints plus the backward pass's workspace: one
+ * segment's tape, and for the hybrid map the starts of a group's accepted BS
+ * substeps and the positions of one Gragg sequence); 0 when the context
+ * supports neither map or the arguments are invalid. */
 size_t genga_adj_buffer_bytes(genga_ctx *ctx, int64_t nsteps, int ckpt_every);
 
-/* Advance every system nsteps steps of the encounter-free map, keeping the
- * state every ckpt_every steps in d_buffer (device, 256-B aligned, caller-
- * owned, at least genga_adj_buffer_bytes; it must stay untouched until the
- * matching genga_adj_backward).  Asynchronous.  A pair that comes inside its
- * critical radius (Eq. 6) latches GENGA_EADJ_ENCOUNTER (the hybrid method
- * would no longer use K = 1 there).  Errors: EINVAL, ENOMEM, EHIP. */
+/* Advance every system nsteps steps of the context's map, keeping the state
+ * (and for the hybrid map the candidate set) every ckpt_every steps in
+ * d_buffer (device, 256-B aligned, caller-owned, at least
+ * genga_adj_buffer_bytes; it must stay untouched until the matching
+ * genga_adj_backward).  Asynchronous.  Encounter-free map: a pair that comes
+ * inside its critical radius (Eq. 6) latches GENGA_EADJ_ENCOUNTER (the
+ * hybrid method would no longer use K = 1 there).  Errors: EINVAL, ENOMEM,
+ * EHIP. */
 int genga_adj_forward(genga_ctx *ctx, int64_t nsteps, int ckpt_every,
                       void *d_buffer, size_t buffer_bytes);
 

@@ -23,7 +23,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # The batched kernel is instantiated for one and for two systems per wave; with
 # multiply-adds fused only inside one source expression (not wherever the
 # code generator finds a pair) both layouts round identically.
-FILE_FLAGS = {"batch.hip": ["-ffp-contract=on"]}
+# The hybrid adjoint rounds like the plain FP64 definitions it differentiates
+# (no fused multiply-adds), so that its decisions fall where theirs do.
+FILE_FLAGS = {"batch.hip": ["-ffp-contract=on"], "hadj.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str, obj: str) -> None:

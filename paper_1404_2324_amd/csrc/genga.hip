@@ -20,7 +20,7 @@ constexpr int kGraphSteps = 16;  // steps per captured graph (and at most 15 in 
 int status_from_flags(unsigned f) {
   if (f & F_KEPLER) return GENGA_EKEPLER;
   if (f & F_BS) return GENGA_EBS;
-  if (f & (F_CAND_OVF | F_ENC_OVF | F_TP_OVF)) return GENGA_EOVERFLOW;
+  if (f & (F_CAND_OVF | F_ENC_OVF | F_TP_OVF | F_ADJ_LEAF)) return GENGA_EOVERFLOW;
   if (f & F_GROUP) return GENGA_EGROUP;
   if (f & F_ADJ_ENC) return GENGA_EADJ_ENCOUNTER;
   if (f & F_NMIN) return GENGA_WNMIN;
@@ -988,15 +988,27 @@ int genga_batch_status(genga_ctx* ctx, int32_t* h_status, int64_t* h_steps, int 
   return cap < ctx->b.nsys ? GENGA_EOVERFLOW : GENGA_OK;
 }
 
+// The encounter-free adjoint (K = 1), or the hybrid one: a batched context
+// with encounters and no bodies leaving (no radii, rcut or rcut_sun).
+static bool adj_hybrid(const genga_ctx* ctx) {
+  return !ctx->p.encounter_free && !ctx->b.coll && ctx->b.rcut == 0.0 && ctx->b.rcut_sun == 0.0;
+}
 static bool adj_ok(const genga_ctx* ctx) {
-  return ctx && ctx->mode == GENGA_BATCH && ctx->p.encounter_free;
+  return ctx && ctx->mode == GENGA_BATCH && (ctx->p.encounter_free || adj_hybrid(ctx));
+}
+
+static size_t adj_ckpt_bytes(const genga_ctx* ctx, int64_t nsteps, int ckpt_every) {
+  if (adj_hybrid(ctx)) return align256(hadj_ckpt_bytes(ctx->b.nb, (int)nsteps, ckpt_every));
+  const int64_t C = (nsteps + ckpt_every - 1) / ckpt_every;
+  return align256((size_t)C * 6 * (size_t)ctx->b.nb * sizeof(double));
 }
 
 size_t genga_adj_buffer_bytes(genga_ctx* ctx, int64_t nsteps, int ckpt_every) {
   if (!adj_ok(ctx) || nsteps < 1 || nsteps > INT_MAX || ckpt_every < 1) return 0;
-  const int64_t C = (nsteps + ckpt_every - 1) / ckpt_every;
-  return align256((size_t)C * 6 * (size_t)ctx->b.nb * sizeof(double)) +
-         adj_tape_bytes(ctx->b.nsys, ctx->sb, std::min<int64_t>(ckpt_every, nsteps));
+  const int K = (int)std::min<int64_t>(ckpt_every, nsteps);
+  if (adj_hybrid(ctx))
+    return adj_ckpt_bytes(ctx, nsteps, ckpt_every) + hadj_work_bytes(ctx->b.nsys, K);
+  return adj_ckpt_bytes(ctx, nsteps, ckpt_every) + adj_tape_bytes(ctx->b.nsys, ctx->sb, K);
 }
 
 int genga_adj_forward(genga_ctx* ctx, int64_t nsteps, int ckpt_every, void* d_buffer,
@@ -1005,8 +1017,11 @@ int genga_adj_forward(genga_ctx* ctx, int64_t nsteps, int ckpt_every, void* d_bu
   const size_t need = genga_adj_buffer_bytes(ctx, nsteps, ckpt_every);
   if (need == 0) return GENGA_EINVAL;
   if (buffer_bytes < need) return GENGA_ENOMEM;
-  HIPCHK(adj_forward(ctx->b, ctx->c, ctx->sb, (int)nsteps, ckpt_every, (double*)d_buffer,
-                     ctx->stream));
+  if (adj_hybrid(ctx))
+    HIPCHK(hadj_forward(ctx->b, ctx->c, (int)nsteps, ckpt_every, (double*)d_buffer, ctx->stream));
+  else
+    HIPCHK(adj_forward(ctx->b, ctx->c, ctx->sb, (int)nsteps, ckpt_every, (double*)d_buffer,
+                       ctx->stream));
   ctx->adj_ckpt = (double*)d_buffer;
   ctx->adj_bytes = buffer_bytes;
   ctx->adj_T = (int)nsteps;
@@ -1020,11 +1035,13 @@ int genga_adj_backward(genga_ctx* ctx, const double* d_gxT, const double* d_gvT,
   if (!adj_ok(ctx) || !ctx->adj_ckpt || !d_gxT || !d_gvT || !d_gx0 || !d_gv0 || !d_gm)
     return GENGA_EINVAL;
   const int T = ctx->adj_T, K = ctx->adj_K;
-  const int64_t C = (T + K - 1) / K;
-  double* tape = (double*)((char*)ctx->adj_ckpt +
-                           align256((size_t)C * 6 * (size_t)ctx->b.nb * sizeof(double)));
-  HIPCHK(adj_backward(ctx->b, ctx->c, ctx->sb, T, std::min(K, T), ctx->adj_ckpt, tape, d_gxT,
-                      d_gvT, d_gx0, d_gv0, d_gm, ctx->stream));
+  double* tape = (double*)((char*)ctx->adj_ckpt + adj_ckpt_bytes(ctx, T, K));
+  if (adj_hybrid(ctx))
+    HIPCHK(hadj_backward(ctx->b, ctx->c, T, std::min(K, T), ctx->adj_ckpt, tape, d_gxT, d_gvT,
+                         d_gx0, d_gv0, d_gm, ctx->stream));
+  else
+    HIPCHK(adj_backward(ctx->b, ctx->c, ctx->sb, T, std::min(K, T), ctx->adj_ckpt, tape, d_gxT,
+                        d_gvT, d_gx0, d_gv0, d_gm, ctx->stream));
   return GENGA_OK;
 }
 

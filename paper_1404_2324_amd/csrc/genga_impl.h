@@ -23,6 +23,7 @@ enum : unsigned {
   F_ADJ_ENC = 64u,     // a pair inside r_crit during the encounter-free map
   F_SYS_STOP = 128u,   // batched: a system stopped after a failed step (warning)
   F_NMIN = 256u,       // batched: a system stopped with fewer than nmin bodies
+  F_ADJ_LEAF = 512u,   // hybrid adjoint: a group took more BS substeps in a step than it keeps
 };
 // control bits
 enum : unsigned { C_FULLKICK = 1u };
@@ -332,6 +333,16 @@ bool batch_variant_ok(const BatchWs& b, int v);
 
 // ---- adjoint of the encounter-free map (adj.hip) ----------------------------
 // Systems are packed sb lanes each (sb: power of two >= the largest system).
+// hybrid adjoint (hadj.hip): checkpoints of T steps every K, and the backward
+// pass's workspace (tape of a segment, BS substep starts, Gragg positions)
+size_t hadj_ckpt_bytes(int64_t nb, int T, int K);
+size_t hadj_work_bytes(int nsys, int K);
+hipError_t hadj_forward(const BatchWs& b, const StepConsts& c, int T, int K, double* ckpt,
+                        hipStream_t s);
+hipError_t hadj_backward(const BatchWs& b, const StepConsts& c, int T, int K, double* ckpt,
+                         double* work, const double* gxT, const double* gvT, double* gx0,
+                         double* gv0, double* gm, hipStream_t s);
+
 int adj_segment_lanes(int max_n);
 size_t adj_tape_bytes(int nsys, int sb, int K);
 // T steps of the encounter-free map on the batched state, keeping the state

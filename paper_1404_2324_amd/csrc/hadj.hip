@@ -1,0 +1,915 @@
+// Reverse-mode gradient of the second-order hybrid step (Eq. 7) with its
+// close-encounter machinery (the paper has no adjoint): the changeover K and
+// K' of Eqs. (4)-(5) in both kicks, the critical radii of Eq. (6) as
+// functions of the state and the masses, the Sun kicks, the Kepler drift,
+// and the Bulirsch-Stoer integration of H_A for each close-encounter group
+// (Sec. 2.2, 3.2.6).  It differentiates the map the step computes with every
+// decision held where it falls: the candidate and encounter sets (Eqs.
+// 10-12), the groups (App. A), the accepted BS substeps and the column each
+// stops at, and the branches of K and of Eq. (6).  K = 1 outside the
+// critical radius, so where a decision changes the map moves by no more
+// than the BS tolerance: this is the derivative almost everywhere.
+//
+// The step follows the recipe of Sec. 2.2 as the main mode does: radii,
+// kick tau/2 (H_B with K), Sun kick tau/2, Kepler drift tau, encounter test
+// of the candidate pairs, groups, BS of each group over tau from the
+// pre-drift state, Sun kick tau/2, kick tau/2, precheck (the next step's
+// candidates).  The first step's candidates are the precheck of the initial
+// state with its own radii.
+//
+// One wave per system, one lane per body; partner data by lane reads in
+// wave-uniform loops.  Forward: the state and the candidate set every k
+// steps.  Backward, per segment from the last: the segment replayed keeping
+// each step's start (the tape), then per step in reverse the step
+// recomputed and its pieces reversed:
+//   kick   v' = v + h a_B(x; m, rc):  x^ += A^T (h v'^), with the mass and
+//          radius adjoints; for a pair term G m_j f(r, rc) d, d = x_j - x_i,
+//          f = K/r^3 - K'/r^2, the lane's share is
+//          G [f u + (f_r / r)(d.u) d], u = m_i w_j - m_j w_i
+//   Sun    x' = x + h P(v)/m0
+//   drift  the Kepler VJP (implicit function for the universal anomaly)
+//   BS     the group's BS rerun keeping the start of each accepted substep;
+//          an accepted substep's value is a fixed linear combination
+//          sum_q W_q G_q of the Gragg results of its columns (the
+//          Aitken-Neville tableau is linear in them), so its adjoint is
+//          sum_q G_q^T (W_q y^); each Gragg sequence is recomputed keeping
+//          its positions and reversed substep by substep, with H_A's pair
+//          terms weighted by 1 - K (g = 1/r^3 - f) and the star's term
+//   radii  rc = max(n1 R_H, n2 |tau| |v|): x^, v^, m^ of the branch taken.
+#include "adj_device.h"
+#include "device_math.h"
+#include "genga_impl.h"
+
+namespace genga {
+namespace {
+
+constexpr int kHK = 8;              // BS columns, n_k = 2k substeps
+constexpr int kHLeaf = 64;          // accepted BS substeps of one group in one step
+constexpr int kHPos = 2 * kHK + 1;  // positions of the longest Gragg sequence
+
+// Aitken-Neville weights: an attempt that stops at column kk (0-based)
+// returns sum_q W[kk][q] G_q, G_q the Gragg result with 2 (q + 1) substeps
+// (the tableau recursion applied to unit vectors).
+struct NevilleW {
+  double w[kHK][kHK];
+};
+constexpr NevilleW neville_weights() {
+  NevilleW out{};
+  double T[kHK][kHK][kHK] = {};  // T[k][j][q]
+  for (int k = 0; k < kHK; ++k) {
+    for (int q = 0; q < kHK; ++q) T[k][0][q] = q == k ? 1.0 : 0.0;
+    for (int j = 1; j <= k; ++j) {
+      const double ratio = (double)(2 * (k + 1)) / (double)(2 * (k - j + 1));
+      const double den = ratio * ratio - 1.0;
+      for (int q = 0; q < kHK; ++q)
+        T[k][j][q] = T[k][j - 1][q] + (T[k][j - 1][q] - T[k - 1][j - 1][q]) / den;
+    }
+    for (int q = 0; q < kHK; ++q) out.w[k][q] = T[k][k][q];
+  }
+  return out;
+}
+__constant__ NevilleW kNW = neville_weights();
+
+struct HArgs {
+  double4* __restrict__ xm;  // batched state (x, m), advanced by the forward pass
+  double4* __restrict__ vv;
+  const int* __restrict__ off;
+  const double* __restrict__ m0;
+  double* __restrict__ ckpt;  // [C][7][nb]: x, y, z, vx, vy, vz, candidate bits
+  double* __restrict__ tape;  // [K][7][nl]
+  double* __restrict__ leaf;  // [kHLeaf][6][nl]: starts of accepted BS substeps
+  double* __restrict__ zpos;  // [kHPos][3][nl]: positions of one Gragg sequence
+  const double* __restrict__ gxT;
+  const double* __restrict__ gvT;
+  double* __restrict__ gx0;
+  double* __restrict__ gv0;
+  double* __restrict__ gm;
+  unsigned* __restrict__ flags;
+  int nsys, T, K, C, nl, max_iter, bs_depth;
+  int64_t nb;
+  double G, dt, h, n1, n2, pf, absdt, bs_tol;
+};
+
+// the lane's body
+struct Sys {
+  int lane, n, row;
+  bool act;
+  size_t gl;                  // lane index in the per-lane scratch
+  double m, m0, Gm0;
+  unsigned long long all;     // the system's bodies as a lane mask
+};
+
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int j) {
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, j);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), j);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Changeover of Eqs. (4)-(5) for a pair at r with pair radius rc: K, dK/dr
+// and, with D2, d2K/dr2, dK/drc, d2K/(dr drc).  y = (r - 0.1 rc)/(0.9 rc),
+// K = y^2/D, D = 2y^2 - 2y + 1; kappa' = 2y(1-y)/D^2,
+// kappa'' = (2 - 4y)(1 + 2y - 2y^2)/D^3, dy/drc = -r/(0.9 rc^2).
+template <bool D2>
+__device__ __forceinline__ void chg(double r, double rc, double& K, double& Kr, double& Krr,
+                                    double& Kc, double& Krc) {
+  Krr = Kc = Krc = 0.0;
+  if (!(rc > 0.0)) {
+    K = 1.0;
+    Kr = 0.0;
+    return;
+  }
+  const double y = (r - 0.1 * rc) / (0.9 * rc);
+  if (y <= 0.0) {
+    K = 0.0;
+    Kr = 0.0;
+  } else if (y >= 1.0) {
+    K = 1.0;
+    Kr = 0.0;
+  } else {
+    const double D = 2.0 * y * y - 2.0 * y + 1.0;
+    K = y * y / D;
+    const double k1 = 2.0 * y * (1.0 - y) / (D * D);
+    Kr = k1 / (0.9 * rc);
+    if (D2) {
+      const double k2 = (2.0 - 4.0 * y) * (1.0 + 2.0 * y - 2.0 * y * y) / (D * D * D);
+      const double s = 1.0 / (0.9 * rc);
+      const double yc = -r / (0.9 * rc * rc);
+      Krr = k2 * s * s;
+      Kc = k1 * yc;
+      Krc = k2 * yc * s - k1 / (0.9 * rc * rc);
+    }
+  }
+}
+
+// ---- forward pieces ----------------------------------------------------------
+// H_B acceleration (the gradient of Eq. 2): sum over the system's other bodies.
+__device__ void accel_B(const HArgs& a, const Sys& S, const double x[3], double rc, double acc[3]) {
+  acc[0] = acc[1] = acc[2] = 0.0;
+  for (int j = 0; j < S.n; ++j) {
+    const double xj = readlane_d(x[0], j), yj = readlane_d(x[1], j), zj = readlane_d(x[2], j);
+    const double mj = readlane_d(S.m, j), rcj = readlane_d(rc, j);
+    if (S.act && j != S.lane) {
+      const double d0 = xj - x[0], d1 = yj - x[1], d2 = zj - x[2];
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const double r = sqrt(r2);
+      const double rcij = rc > rcj ? rc : rcj;
+      double K, dK, u0, u1, u2;
+      chg<false>(r, rcij, K, dK, u0, u1, u2);
+      const double f = K / (r2 * r) - dK / r2;
+      const double s = a.G * mj * f;
+      acc[0] += s * d0;
+      acc[1] += s * d1;
+      acc[2] += s * d2;
+    }
+  }
+}
+
+// P = sum_j m_j v_j in body order
+__device__ __forceinline__ void momentum(const Sys& S, const double v[3], double P[3]) {
+  P[0] = P[1] = P[2] = 0.0;
+  for (int j = 0; j < S.n; ++j) {
+    const double mj = readlane_d(S.m, j);
+    P[0] += mj * readlane_d(v[0], j);
+    P[1] += mj * readlane_d(v[1], j);
+    P[2] += mj * readlane_d(v[2], j);
+  }
+}
+
+__device__ __forceinline__ void lane_sum3(const Sys& S, const double w[3], double out[3]) {
+  out[0] = out[1] = out[2] = 0.0;
+  for (int j = 0; j < S.n; ++j) {
+    out[0] += readlane_d(w[0], j);
+    out[1] += readlane_d(w[1], j);
+    out[2] += readlane_d(w[2], j);
+  }
+}
+
+// H_A derivative of a group member (star fixed at the origin, pair terms of
+// the members weighted by 1 - K): y = (x, v) -> (v, a).
+__device__ void ha_deriv(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
+                         const double y[6], double dy[6]) {
+  const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+  const double r = sqrt(r2);
+  const double fs = -S.Gm0 / (r2 * r);
+  double a0 = fs * y[0], a1 = fs * y[1], a2 = fs * y[2];
+  for (unsigned long long q = M; q; q &= q - 1) {
+    const int j = __builtin_ctzll(q);
+    const double xj = readlane_d(y[0], j), yj = readlane_d(y[1], j), zj = readlane_d(y[2], j);
+    const double mj = readlane_d(S.m, j), rcj = readlane_d(rc, j);
+    if (mem && j != S.lane) {
+      const double d0 = xj - y[0], d1 = yj - y[1], d2 = zj - y[2];
+      const double q2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const double qq = sqrt(q2);
+      const double rcij = rc > rcj ? rc : rcj;
+      double K, dK, u0, u1, u2;
+      chg<false>(qq, rcij, K, dK, u0, u1, u2);
+      const double f = (1.0 - K) / (q2 * qq) + dK / q2;
+      const double sj = a.G * mj * f;
+      a0 += sj * d0;
+      a1 += sj * d1;
+      a2 += sj * d2;
+    }
+  }
+  dy[0] = y[3];
+  dy[1] = y[4];
+  dy[2] = y[5];
+  dy[3] = a0;
+  dy[4] = a1;
+  dy[5] = a2;
+}
+
+// Gragg's modified midpoint rule over H with nsub substeps; with keep, the
+// positions z_0 .. z_nsub go to the lane's zpos slots.
+__device__ void gragg(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
+                      const double y0[6], double H, int nsub, double out[6], bool keep) {
+  const double hs = H / nsub;
+  double d[6], ym[6], yn[6];
+  ha_deriv(a, S, M, mem, rc, y0, d);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    ym[c] = y0[c];
+    yn[c] = y0[c] + hs * d[c];
+  }
+  if (keep) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a.zpos[(size_t)c * a.nl + S.gl] = y0[c];
+      a.zpos[(size_t)(3 + c) * a.nl + S.gl] = yn[c];
+    }
+  }
+  for (int m = 1; m < nsub; ++m) {
+    ha_deriv(a, S, M, mem, rc, yn, d);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double t = ym[c] + 2.0 * hs * d[c];
+      ym[c] = yn[c];
+      yn[c] = t;
+    }
+    if (keep) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.zpos[((size_t)(m + 1) * 3 + c) * a.nl + S.gl] = yn[c];
+    }
+  }
+  ha_deriv(a, S, M, mem, rc, yn, d);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) out[c] = 0.5 * (ym[c] + yn[c] + hs * d[c]);
+}
+
+__device__ __forceinline__ double vrel3(const double* A, const double* B) {
+  const double d0 = A[0] - B[0], d1 = A[1] - B[1], d2 = A[2] - B[2];
+  const double num = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  const double den = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+  return den > 0.0 ? num / den : num;
+}
+
+// One BS attempt over H from y0: the accepted column (>= 1) with its value
+// in yout (members), or -1 when no column meets the tolerance.
+__device__ int bs_attempt(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
+                          const double y0[6], double H, double yout[6]) {
+  double Tr[kHK][6] = {};
+#pragma unroll
+  for (int k = 0; k < kHK; ++k) {
+    double g[6];
+    gragg(a, S, M, mem, rc, y0, H, 2 * (k + 1), g, false);
+    double up[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      up[c] = Tr[0][c];
+      Tr[0][c] = g[c];
+    }
+#pragma unroll
+    for (int j = 1; j <= k; ++j) {
+      const double ratio = (double)(2 * (k + 1)) / (double)(2 * (k - j + 1));
+      const double den = ratio * ratio - 1.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double nw = Tr[j - 1][c] + (Tr[j - 1][c] - up[c]) / den;
+        if (j < k) up[c] = Tr[j][c];
+        Tr[j][c] = nw;
+      }
+    }
+    if (k >= 1) {
+      double err = 0.0;
+      if (mem) err = fmax(vrel3(&Tr[k][0], &Tr[k - 1][0]), vrel3(&Tr[k][3], &Tr[k - 1][3]));
+      err = wave_max(err);
+      if (err <= a.bs_tol) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) yout[c] = Tr[k][c];
+        return k;
+      }
+    }
+  }
+  return -1;
+}
+
+// BS of one group over tau with binary refinement (as the main mode): y is
+// the members' state in and out.  With REC the start of every accepted
+// substep goes to the lane's leaf slots and its length and column to lh, lk
+// (LDS).  Returns 0, or -1 when the depth is exhausted; *nleaf counts the
+// accepted substeps.
+template <bool REC>
+__device__ int bs_group(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
+                        double y[6], double* lh, int* lk, int* nleaf) {
+  const int D = a.bs_depth;
+  const int64_t total = (int64_t)1 << D;
+  int64_t pos = 0;
+  int d = 0, nl = 0;
+  while (pos < total) {
+    const double hh = ldexp(a.dt, -d);
+    double yn[6];
+    const int k = bs_attempt(a, S, M, mem, rc, y, hh, yn);
+    if (k >= 1) {
+      if (REC) {
+        if (nl < kHLeaf) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) a.leaf[((size_t)nl * 6 + c) * a.nl + S.gl] = y[c];
+          if (S.lane == 0) {
+            lh[nl] = hh;
+            lk[nl] = k;
+          }
+        }
+        ++nl;
+      }
+      if (mem) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) y[c] = yn[c];
+      }
+      pos += (int64_t)1 << (D - d);
+      while (d > 0 && (pos % ((int64_t)1 << (D - d + 1))) == 0) --d;
+    } else {
+      ++d;
+      if (d > D) {
+        if (nleaf) *nleaf = nl;
+        return -1;
+      }
+    }
+  }
+  if (nleaf) *nleaf = nl;
+  return 0;
+}
+
+// Intermediate values of one step kept for its reverse.
+struct StepVals {
+  double x0[3], v0[3];  // start
+  double rc;            // radii of the step (Eq. 6 at the start)
+  double x1[3], v1[3];  // after the opening kick and Sun kick: the drift's start
+  double s;             // universal anomaly of the Kepler drift
+  double x2[3], v2[3];  // after the drift (BS for group members)
+  double x3[3];         // after the second Sun kick: the closing kick's positions
+  int label;            // group label (the smallest member), or -1
+};
+
+// Encounters among the candidate pairs j > i (Hermite test of the drift,
+// Eqs. 10-12, below rc_ij^2), then the groups: every lane takes the smallest
+// label of its neighbours until nothing changes (the components of the
+// encounter graph, labelled by their smallest member).
+__device__ int groups(const HArgs& a, const Sys& S, unsigned long long cand, const double xa[3],
+                      const double va[3], const double xb[3], const double vb[3], double rc) {
+  unsigned long long E = 0ull;
+  for (int j = 0; j < S.n; ++j) {
+    const double x0j = readlane_d(xa[0], j), y0j = readlane_d(xa[1], j), z0j = readlane_d(xa[2], j);
+    const double u0j = readlane_d(va[0], j), w0j = readlane_d(va[1], j), q0j = readlane_d(va[2], j);
+    const double x1j = readlane_d(xb[0], j), y1j = readlane_d(xb[1], j), z1j = readlane_d(xb[2], j);
+    const double u1j = readlane_d(vb[0], j), w1j = readlane_d(vb[1], j), q1j = readlane_d(vb[2], j);
+    const double rcj = readlane_d(rc, j);
+    if (S.act && j > S.lane && ((cand >> j) & 1ull)) {
+      const double d2 = hermite_dmin2(a.dt, x0j - xa[0], y0j - xa[1], z0j - xa[2], u0j - va[0],
+                                      w0j - va[1], q0j - va[2], x1j - xb[0], y1j - xb[1],
+                                      z1j - xb[2], u1j - vb[0], w1j - vb[1], q1j - vb[2]);
+      const double rcij = rc > rcj ? rc : rcj;
+      if (d2 < rcij * rcij) E |= 1ull << j;
+    }
+  }
+  // neighbours: the lane's pairs and those of lower lanes that name it
+  unsigned long long nbr = E;
+  for (int j = 0; j < S.n; ++j) {
+    const unsigned long long Ej = readlane_u64(E, j);
+    if ((Ej >> S.lane) & 1ull) nbr |= 1ull << j;
+  }
+  int label = nbr ? S.lane : 64;
+  for (int it = 0; it < 64; ++it) {
+    int nw = label;
+    for (int j = 0; j < S.n; ++j) {
+      const int lj = __builtin_amdgcn_readlane(label, j);
+      if ((nbr >> j) & 1ull) nw = min(nw, lj);
+    }
+    const bool ch = nw != label;
+    label = nw;
+    if (__builtin_amdgcn_ballot_w64(ch) == 0ull) break;
+  }
+  return nbr ? label : -1;
+}
+
+// The precheck (Sec. 2.2): partners j > i closer than pf rc_ij.
+__device__ unsigned long long precheck(const HArgs& a, const Sys& S, const double x[3], double rc) {
+  unsigned long long c = 0ull;
+  for (int j = 0; j < S.n; ++j) {
+    const double xj = readlane_d(x[0], j), yj = readlane_d(x[1], j), zj = readlane_d(x[2], j);
+    const double rcj = readlane_d(rc, j);
+    if (S.act && j > S.lane) {
+      const double d0 = xj - x[0], d1 = yj - x[1], d2 = zj - x[2];
+      const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      const double rcij = rc > rcj ? rc : rcj;
+      if (r < a.pf * rcij) c |= 1ull << j;
+    }
+  }
+  return c;
+}
+
+__device__ __forceinline__ double radius(const HArgs& a, const Sys& S, const double x[3],
+                                         const double v[3]) {
+  return S.act ? rcrit(x[0], x[1], x[2], v[0], v[1], v[2], S.m, S.Gm0, S.m0, a.n1, a.n2, a.absdt)
+               : 0.0;
+}
+
+// One hybrid step of the lane's system: x, v and the candidate bits in and
+// out; R keeps the intermediate values.
+__device__ void hyb_step(const HArgs& a, const Sys& S, double x[3], double v[3],
+                         unsigned long long& cand, StepVals& R, unsigned& fl) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    R.x0[c] = x[c];
+    R.v0[c] = v[c];
+  }
+  const double rc = radius(a, S, x, v);
+  R.rc = rc;
+  double acc[3], P[3];
+  accel_B(a, S, x, rc, acc);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[c] += a.h * acc[c];
+  momentum(S, v, P);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x[c] += a.h * P[c] / S.m0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    R.x1[c] = x[c];
+    R.v1[c] = v[c];
+  }
+  double s = 0.0;
+  if (S.act && kepler_drift(S.Gm0, a.dt, x[0], x[1], x[2], v[0], v[1], v[2], a.max_iter, &s) < 0)
+    fl |= F_KEPLER;
+  R.s = s;
+  const int label = groups(a, S, cand, R.x1, R.v1, x, v, rc);
+  R.label = label;
+  // BS of each group from the pre-drift state, groups by ascending label
+  unsigned long long roots = __builtin_amdgcn_ballot_w64(label == S.lane);
+  for (; roots; roots &= roots - 1) {
+    const int g = __builtin_ctzll(roots);
+    const bool mem = label == g;
+    const unsigned long long M = __builtin_amdgcn_ballot_w64(mem);
+    double y[6] = {R.x1[0], R.x1[1], R.x1[2], R.v1[0], R.v1[1], R.v1[2]};
+    if (bs_group<false>(a, S, M, mem, rc, y, nullptr, nullptr, nullptr) < 0) fl |= F_BS;
+    if (mem) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        x[c] = y[c];
+        v[c] = y[3 + c];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    R.x2[c] = x[c];
+    R.v2[c] = v[c];
+  }
+  momentum(S, v, P);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x[c] += a.h * P[c] / S.m0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) R.x3[c] = x[c];
+  accel_B(a, S, x, rc, acc);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[c] += a.h * acc[c];
+  cand = precheck(a, S, x, rc);
+}
+
+// ---- reverse pieces --------------------------------------------------------
+// Pair terms over the partners in P (bits of lanes) at positions x for the
+// acceleration adjoint w: out += A^T w, with the mass and radius adjoints of
+// the lane's body.  HA: H_A's 1 - K weighting (g = 1/r^3 - f).  The radius
+// of a pair is the larger of the two (the first when neither is larger, as
+// the term of the first body sees it), so each term's radius adjoint goes
+// to the body whose radius it used.
+template <bool HA>
+__device__ void pair_vjp(const HArgs& a, const Sys& S, unsigned long long Pm, bool on, double rc,
+                         const double x[3], const double w[3], double out[3], double& mb,
+                         double& rcb) {
+  for (unsigned long long q = Pm; q; q &= q - 1) {
+    const int j = __builtin_ctzll(q);
+    const double xj = readlane_d(x[0], j), yj = readlane_d(x[1], j), zj = readlane_d(x[2], j);
+    const double wx = readlane_d(w[0], j), wy = readlane_d(w[1], j), wz = readlane_d(w[2], j);
+    const double mj = readlane_d(S.m, j), rcj = readlane_d(rc, j);
+    if (on && j != S.lane) {
+      const double d0 = xj - x[0], d1 = yj - x[1], d2 = zj - x[2];
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const double r = sqrt(r2);
+      const double ir = 1.0 / r, ir2 = ir * ir, ir3 = ir2 * ir, ir4 = ir2 * ir2;
+      const double rcij = rc > rcj ? rc : rcj;
+      double K, Kr, Krr, Kc, Krc;
+      chg<true>(r, rcij, K, Kr, Krr, Kc, Krc);
+      double f = K * ir3 - Kr * ir2;
+      double fr = 3.0 * Kr * ir3 - 3.0 * K * ir4 - Krr * ir2;
+      double fc = Kc * ir3 - Krc * ir2;
+      if (HA) {
+        f = ir3 - f;
+        fr = -3.0 * ir4 - fr;
+        fc = -fc;
+      }
+      const double u0 = S.m * wx - mj * w[0], u1 = S.m * wy - mj * w[1], u2 = S.m * wz - mj * w[2];
+      const double du = d0 * u0 + d1 * u1 + d2 * u2;
+      const double c = fr * ir * du;
+      out[0] += a.G * (f * u0 + c * d0);
+      out[1] += a.G * (f * u1 + c * d1);
+      out[2] += a.G * (f * u2 + c * d2);
+      mb -= a.G * f * (d0 * wx + d1 * wy + d2 * wz);
+      // the lane's term (rc_ij = rc when rc > rcj) and the partner's term
+      // (rc_ij = rc when rc >= rcj)
+      const double tl = a.G * fc * mj * (d0 * w[0] + d1 * w[1] + d2 * w[2]);
+      const double tp = -a.G * fc * S.m * (d0 * wx + d1 * wy + d2 * wz);
+      if (rc > rcj) rcb += tl;
+      if (rc >= rcj) rcb += tp;
+    }
+  }
+}
+
+// H_A acceleration adjoint of a group member: the star's term and the pairs.
+__device__ void ha_vjp(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
+                       const double z[3], const double w[3], double out[3], double& mb,
+                       double& rcb) {
+  out[0] = out[1] = out[2] = 0.0;
+  const double r2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+  const double r = sqrt(r2);
+  const double ir = 1.0 / r, ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
+  const double xw = z[0] * w[0] + z[1] * w[1] + z[2] * w[2];
+  if (mem) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c] = -S.Gm0 * (w[c] * ir3 - 3.0 * xw * z[c] * ir5);
+  }
+  pair_vjp<true>(a, S, M, mem, rc, z, w, out, mb, rcb);
+}
+
+// yb += G^T ob for the Gragg sequence of nsub substeps over H from y0.
+__device__ void gragg_vjp(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
+                          const double y0[6], double H, int nsub, const double ob[6],
+                          double yb[6], double& mb, double& rcb) {
+  const double hs = H / nsub;
+  double tmp[6];
+  gragg(a, S, M, mem, rc, y0, H, nsub, tmp, true);
+  double z[3], w[3], o[3];
+  double Pa[6], Qa[6];
+  // out = (z_{n-1} + z_n + hs F(z_n)) / 2
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    z[c] = a.zpos[((size_t)nsub * 3 + c) * a.nl + S.gl];
+    w[c] = 0.5 * hs * ob[3 + c];
+  }
+  ha_vjp(a, S, M, mem, rc, z, w, o, mb, rcb);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    Pa[c] = 0.5 * ob[c] + o[c];
+    Pa[3 + c] = 0.5 * ob[3 + c] + 0.5 * hs * ob[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) Qa[c] = 0.5 * ob[c];
+  // z_{m+1} = z_{m-1} + 2 hs F(z_m), m = nsub - 1 .. 1
+  for (int m = nsub - 1; m >= 1; --m) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      z[c] = a.zpos[((size_t)m * 3 + c) * a.nl + S.gl];
+      w[c] = 2.0 * hs * Pa[3 + c];
+    }
+    ha_vjp(a, S, M, mem, rc, z, w, o, mb, rcb);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Qa[c] += o[c];
+      Qa[3 + c] += 2.0 * hs * Pa[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double t = Pa[c];
+      Pa[c] = Qa[c];
+      Qa[c] = t;
+    }
+  }
+  // z_1 = z_0 + hs F(z_0)
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    z[c] = a.zpos[(size_t)c * a.nl + S.gl];
+    w[c] = hs * Pa[3 + c];
+  }
+  ha_vjp(a, S, M, mem, rc, z, w, o, mb, rcb);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    Qa[c] += Pa[c] + o[c];
+    Qa[3 + c] += Pa[3 + c] + hs * Pa[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) yb[c] += Qa[c];
+}
+
+// Adjoint of one group's BS over tau from y1 (the members' pre-drift
+// state): yb holds the adjoint of the BS result in and that of y1 out.
+__device__ void bs_group_vjp(const HArgs& a, const Sys& S, unsigned long long M, bool mem,
+                             double rc, const double y1[6], double yb[6], double& mb, double& rcb,
+                             double* lh, int* lk, unsigned& fl) {
+  double y[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) y[c] = y1[c];
+  int nleaf = 0;
+  const int rcode = bs_group<true>(a, S, M, mem, rc, y, lh, lk, &nleaf);
+  __syncthreads();  // the substeps' lengths and columns (LDS) for every lane
+  if (rcode < 0) {
+    fl |= F_BS;
+    return;
+  }
+  if (nleaf > kHLeaf) {
+    fl |= F_ADJ_LEAF;
+    return;
+  }
+  for (int l = nleaf - 1; l >= 0; --l) {
+    const double hh = lh[l];
+    const int kk = lk[l];
+    double yin[6], acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) yin[c] = a.leaf[((size_t)l * 6 + c) * a.nl + S.gl];
+    for (int q = 0; q <= kk; ++q) {
+      const double wq = kNW.w[kk][q];
+      double ob[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ob[c] = wq * yb[c];
+      gragg_vjp(a, S, M, mem, rc, yin, hh, 2 * (q + 1), ob, acc, mb, rcb);
+    }
+    if (mem) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) yb[c] = acc[c];
+    }
+  }
+  __syncthreads();  // lh, lk are rewritten by the next group
+}
+
+// Radius adjoint (Eq. 6, the branch taken) into x^, v^, m^.
+__device__ void radius_vjp(const HArgs& a, const Sys& S, const double x[3], const double v[3],
+                           double rcb, double xb[3], double vb[3], double& mb) {
+  if (!S.act) return;
+  const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  const double r = sqrt(r2);
+  const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const double inva = 2.0 / r - vv / S.Gm0;
+  const double am = inva > 0.0 ? 1.0 / inva : r;
+  const double cb = cbrt(S.m / (3.0 * S.m0));
+  const double r1 = a.n1 * (am * cb);
+  const double rv = a.n2 * a.absdt * sqrt(vv);
+  if (r1 > rv) {
+    const double k = rcb * a.n1 * cb;
+    if (inva > 0.0) {
+      const double a2 = am * am;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        xb[c] += k * 2.0 * a2 * x[c] / (r2 * r);
+        vb[c] += k * 2.0 * a2 * v[c] / S.Gm0;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xb[c] += k * x[c] / r;
+    }
+    mb += rcb * a.n1 * am * cb / (3.0 * S.m);
+  } else {
+    const double k = rcb * a.n2 * a.absdt / sqrt(vv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vb[c] += k * v[c];
+  }
+}
+
+__device__ __forceinline__ Sys sys_of(const HArgs& a) {
+  Sys S;
+  S.lane = threadIdx.x & 63;
+  const int s = blockIdx.x;
+  S.n = a.off[s + 1] - a.off[s];
+  S.act = S.lane < S.n;
+  S.row = a.off[s] + (S.act ? S.lane : 0);
+  S.gl = (size_t)s * 64 + S.lane;
+  S.m0 = a.m0[s];
+  S.Gm0 = a.G * S.m0;
+  S.m = S.act ? a.xm[S.row].w : 0.0;
+  S.all = S.n >= 64 ? ~0ull : ((1ull << S.n) - 1ull);
+  return S;
+}
+
+__device__ __forceinline__ void load_body(const HArgs& a, const Sys& S, double x[3], double v[3]) {
+  x[0] = 1.0e3 + S.lane;  // lanes past the system: far away, massless, never read
+  x[1] = x[2] = v[0] = v[1] = v[2] = 0.0;
+  if (S.act) {
+    const double4 p = a.xm[S.row], q = a.vv[S.row];
+    x[0] = p.x;
+    x[1] = p.y;
+    x[2] = p.z;
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_hadj_fwd(HArgs a) {
+  const Sys S = sys_of(a);
+  double x[3], v[3];
+  load_body(a, S, x, v);
+  unsigned long long cand = precheck(a, S, x, radius(a, S, x, v));
+  unsigned fl = 0u;
+  for (int t = 0; t < a.T; ++t) {
+    if (t % a.K == 0 && S.act) {
+      double* c = a.ckpt + (size_t)(t / a.K) * 7 * a.nb;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        c[k * a.nb + S.row] = x[k];
+        c[(3 + k) * a.nb + S.row] = v[k];
+      }
+      c[6 * a.nb + S.row] = __longlong_as_double((long long)cand);
+    }
+    StepVals R;
+    hyb_step(a, S, x, v, cand, R, fl);
+  }
+  if (S.act) {
+    a.xm[S.row] = make_double4(x[0], x[1], x[2], S.m);
+    a.vv[S.row] = make_double4(v[0], v[1], v[2], 0.0);
+  }
+  if (fl) atomicOr(a.flags, fl);
+}
+
+__global__ __launch_bounds__(64) void k_hadj_bwd(HArgs a) {
+  __shared__ double lh[kHLeaf];
+  __shared__ int lk[kHLeaf];
+  const Sys S = sys_of(a);
+  double lx[3] = {0.0, 0.0, 0.0}, lv[3] = {0.0, 0.0, 0.0}, lm = 0.0;
+  if (S.act) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lx[c] = a.gxT[3 * (size_t)S.row + c];
+      lv[c] = a.gvT[3 * (size_t)S.row + c];
+    }
+  }
+  unsigned fl = 0u;
+  for (int cseg = a.C - 1; cseg >= 0; --cseg) {
+    const int t0 = cseg * a.K, t1 = min(a.T, t0 + a.K);
+    double x[3], v[3];
+    unsigned long long cand = 0ull;
+    load_body(a, S, x, v);
+    if (S.act) {
+      const double* cp = a.ckpt + (size_t)cseg * 7 * a.nb;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        x[k] = cp[k * a.nb + S.row];
+        v[k] = cp[(3 + k) * a.nb + S.row];
+      }
+      cand = (unsigned long long)__double_as_longlong(cp[6 * a.nb + S.row]);
+    }
+    // replay the segment, keeping every step's start
+    for (int t = t0; t < t1; ++t) {
+      double* tp = a.tape + (size_t)(t - t0) * 7 * a.nl;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        tp[k * a.nl + S.gl] = x[k];
+        tp[(3 + k) * a.nl + S.gl] = v[k];
+      }
+      tp[6 * a.nl + S.gl] = __longlong_as_double((long long)cand);
+      StepVals R;
+      hyb_step(a, S, x, v, cand, R, fl);
+    }
+    for (int t = t1 - 1; t >= t0; --t) {
+      const double* tp = a.tape + (size_t)(t - t0) * 7 * a.nl;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        x[k] = tp[k * a.nl + S.gl];
+        v[k] = tp[(3 + k) * a.nl + S.gl];
+      }
+      cand = (unsigned long long)__double_as_longlong(tp[6 * a.nl + S.gl]);
+      StepVals R;
+      hyb_step(a, S, x, v, cand, R, fl);
+      const double rc = R.rc;
+      double rcb = 0.0;
+      // closing kick: v4 = v2 + h a_B(x3)
+      double w[3] = {a.h * lv[0], a.h * lv[1], a.h * lv[2]};
+      double xb[3] = {lx[0], lx[1], lx[2]}, vb[3] = {lv[0], lv[1], lv[2]};
+      pair_vjp<false>(a, S, S.all, S.act, rc, R.x3, w, xb, lm, rcb);
+      // second Sun kick: x3 = x2 + h P(v2)/m0
+      double Sx[3];
+      lane_sum3(S, xb, Sx);
+      const double hm = a.h / S.m0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vb[c] += hm * S.m * Sx[c];
+      lm += hm * (R.v2[0] * Sx[0] + R.v2[1] * Sx[1] + R.v2[2] * Sx[2]);
+      // drift: Kepler for bodies outside the groups, BS for each group
+      double xb1[3] = {xb[0], xb[1], xb[2]}, vb1[3] = {vb[0], vb[1], vb[2]};
+      if (S.act && R.label < 0) {
+        const double lx2[3] = {xb[0], xb[1], xb[2]}, lv2[3] = {vb[0], vb[1], vb[2]};
+        kepler_vjp(S.Gm0, a.dt, R.x1, R.v1, R.s, lx2, lv2, xb1, vb1);
+      }
+      unsigned long long roots = __builtin_amdgcn_ballot_w64(R.label == S.lane);
+      for (; roots; roots &= roots - 1) {
+        const int g = __builtin_ctzll(roots);
+        const bool mem = R.label == g;
+        const unsigned long long M = __builtin_amdgcn_ballot_w64(mem);
+        const double y1[6] = {R.x1[0], R.x1[1], R.x1[2], R.v1[0], R.v1[1], R.v1[2]};
+        double yb[6] = {xb[0], xb[1], xb[2], vb[0], vb[1], vb[2]};
+        bs_group_vjp(a, S, M, mem, rc, y1, yb, lm, rcb, lh, lk, fl);
+        if (mem) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            xb1[c] = yb[c];
+            vb1[c] = yb[3 + c];
+          }
+        }
+      }
+      // first Sun kick: x1 = x0 + h P(v1)/m0
+      lane_sum3(S, xb1, Sx);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vb1[c] += hm * S.m * Sx[c];
+      lm += hm * (R.v1[0] * Sx[0] + R.v1[1] * Sx[1] + R.v1[2] * Sx[2]);
+      // opening kick: v1 = v0 + h a_B(x0)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[c] = a.h * vb1[c];
+      pair_vjp<false>(a, S, S.all, S.act, rc, R.x0, w, xb1, lm, rcb);
+      // radii of the step
+      radius_vjp(a, S, R.x0, R.v0, rcb, xb1, vb1, lm);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        lx[c] = S.act ? xb1[c] : 0.0;
+        lv[c] = S.act ? vb1[c] : 0.0;
+      }
+      if (!S.act) lm = 0.0;
+    }
+  }
+  if (S.act) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a.gx0[3 * (size_t)S.row + c] = lx[c];
+      a.gv0[3 * (size_t)S.row + c] = lv[c];
+    }
+    a.gm[S.row] = lm;
+  }
+  if (fl) atomicOr(a.flags, fl);
+}
+
+HArgs hargs(const BatchWs& b, const StepConsts& c, int T, int K) {
+  HArgs a{};
+  a.xm = b.xm;
+  a.vv = b.vv;
+  a.off = b.off;
+  a.m0 = b.m0;
+  a.flags = &b.st->flags;
+  a.nsys = b.nsys;
+  a.T = T;
+  a.K = K;
+  a.C = (T + K - 1) / K;
+  a.nl = b.nsys * 64;
+  a.nb = b.nb;
+  a.G = c.G;
+  a.dt = c.dt;
+  a.h = c.h;
+  a.n1 = c.n1;
+  a.n2 = c.n2;
+  a.pf = c.pf;
+  a.absdt = fabs(c.dt);
+  a.bs_tol = c.bs_tol;
+  a.bs_depth = c.bs_max_depth;
+  a.max_iter = c.kepler_max_iter;
+  return a;
+}
+
+}  // namespace
+
+size_t hadj_ckpt_bytes(int64_t nb, int T, int K) {
+  return (size_t)((T + K - 1) / K) * 7 * (size_t)nb * sizeof(double);
+}
+
+size_t hadj_work_bytes(int nsys, int K) {
+  const size_t nl = (size_t)nsys * 64;
+  return nl * sizeof(double) * (7 * (size_t)K + 6 * kHLeaf + 3 * kHPos);
+}
+
+hipError_t hadj_forward(const BatchWs& b, const StepConsts& c, int T, int K, double* ckpt,
+                        hipStream_t s) {
+  HArgs a = hargs(b, c, T, K);
+  a.ckpt = ckpt;
+  hipLaunchKernelGGL(k_hadj_fwd, dim3(b.nsys), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t hadj_backward(const BatchWs& b, const StepConsts& c, int T, int K, double* ckpt,
+                         double* work, const double* gxT, const double* gvT, double* gx0,
+                         double* gv0, double* gm, hipStream_t s) {
+  HArgs a = hargs(b, c, T, K);
+  a.ckpt = ckpt;
+  const size_t nl = (size_t)b.nsys * 64;
+  a.tape = work;
+  a.leaf = a.tape + nl * 7 * (size_t)K;
+  a.zpos = a.leaf + nl * 6 * (size_t)kHLeaf;
+  a.gxT = gxT;
+  a.gvT = gvT;
+  a.gx0 = gx0;
+  a.gv0 = gv0;
+  a.gm = gm;
+  hipLaunchKernelGGL(k_hadj_bwd, dim3(b.nsys), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace genga

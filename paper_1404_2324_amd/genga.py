@@ -527,7 +527,7 @@ class BatchedSimulation(Simulation):
         return gx0, gv0, gm
 
 
-# Idle encounter-free contexts by (device, system layout, central masses,
+# Idle adjoint contexts by (device, system layout, central masses,
 # parameters): a forward takes one (or makes one), its backward gives it back,
 # so repeated calls re-use the workspace instead of a new init each time.
 _EF_IDLE: dict = {}
@@ -559,6 +559,40 @@ def _ef_give_back(sim):
     _EF_IDLE.setdefault(sim._ef_key, []).append(sim)
 
 
+def _map_forward(ctx, x0, v0, m, offsets, m0s, nsteps, ckpt_every, params, encounter_free):
+    p = Params()
+    ctypes.memmove(ctypes.byref(p), ctypes.byref(params if params is not None
+                                                 else default_params()), ctypes.sizeof(p))
+    p.encounter_free = encounter_free
+    sim = _ef_take(x0, v0, m, offsets, m0s, p)
+    try:
+        sim.adj_forward(nsteps, ckpt_every)
+        xT, vT = sim.state("dem")
+        sim.check()
+    except Exception:
+        sim.close()
+        raise
+    ctx.sim = sim
+    return xT, vT
+
+
+def _map_backward(ctx, gxT, gvT):
+    sim = ctx.sim
+    ctx.sim = None
+    if gxT is None:
+        gxT = torch.zeros(sim.n, 3, dtype=torch.float64, device=sim.device)
+    if gvT is None:
+        gvT = torch.zeros(sim.n, 3, dtype=torch.float64, device=sim.device)
+    try:
+        gx0, gv0, gm = sim.adj_backward(gxT.contiguous(), gvT.contiguous())
+        sim.check()
+    except Exception:
+        sim.close()
+        raise
+    _ef_give_back(sim)
+    return gx0, gv0, gm, None, None, None, None, None
+
+
 class EncounterFreeMap(torch.autograd.Function):
     """(x_T, v_T) = nsteps steps of the encounter-free map (K = 1) of every
     system from democratic (x0, v0) with masses m; backward runs the library's
@@ -567,37 +601,31 @@ class EncounterFreeMap(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x0, v0, m, offsets, m0s, nsteps, ckpt_every=32, params=None):
-        p = Params()
-        ctypes.memmove(ctypes.byref(p), ctypes.byref(params if params is not None
-                                                     else default_params()), ctypes.sizeof(p))
-        p.encounter_free = 1
-        sim = _ef_take(x0, v0, m, offsets, m0s, p)
-        try:
-            sim.adj_forward(nsteps, ckpt_every)
-            xT, vT = sim.state("dem")
-            sim.check()
-        except Exception:
-            sim.close()
-            raise
-        ctx.sim = sim
-        return xT, vT
+        return _map_forward(ctx, x0, v0, m, offsets, m0s, nsteps, ckpt_every, params, 1)
 
     @staticmethod
     def backward(ctx, gxT, gvT):
-        sim = ctx.sim
-        ctx.sim = None
-        if gxT is None:
-            gxT = torch.zeros(sim.n, 3, dtype=torch.float64, device=sim.device)
-        if gvT is None:
-            gvT = torch.zeros(sim.n, 3, dtype=torch.float64, device=sim.device)
-        try:
-            gx0, gv0, gm = sim.adj_backward(gxT.contiguous(), gvT.contiguous())
-            sim.check()
-        except Exception:
-            sim.close()
-            raise
-        _ef_give_back(sim)
-        return gx0, gv0, gm, None, None, None, None, None
+        return _map_backward(ctx, gxT, gvT)
+
+
+class HybridMap(torch.autograd.Function):
+    """(x_T, v_T) = nsteps hybrid steps (Eq. 7: changeover, encounter groups
+    integrated by BS) of every system from democratic (x0, v0) with masses
+    m; backward runs the library's encounter-aware adjoint, which holds every
+    decision of the run fixed (candidates, encounters, groups, accepted BS
+    substeps).  The first step's candidates are the precheck of (x0, v0)."""
+
+    @staticmethod
+    def forward(ctx, x0, v0, m, offsets, m0s, nsteps, ckpt_every=32, params=None):
+        return _map_forward(ctx, x0, v0, m, offsets, m0s, nsteps, ckpt_every, params, 0)
+
+    @staticmethod
+    def backward(ctx, gxT, gvT):
+        return _map_backward(ctx, gxT, gvT)
+
+
+def hybrid_map(x0, v0, m, offsets, m0s, nsteps, ckpt_every=32, params=None):
+    return HybridMap.apply(x0, v0, m, offsets, m0s, nsteps, ckpt_every, params)
 
 
 def encounter_free_map(x0, v0, m, offsets, m0s, nsteps, ckpt_every=32, params=None):
