@@ -272,6 +272,87 @@ def adjoint_measure(G, W, torch, steps: int, ckpt: int = 32):
             "system_steps_per_s_forward": nsys * steps / (fwd / 1e3)}
 
 
+def hybrid_adjoint_measure(G, W, torch, steps: int, ckpt: int = 16, cpu: bool = True):
+    """Adjoint of the hybrid step with encounters (changeover, groups, BS):
+    1024 systems x 8 planets packed so that encounters happen every step
+    (~140 encounters and ~120 BS substeps per system over 64 steps), a
+    checkpoint every 16 steps.  Ratio = backward (segment recompute, BS
+    rerun keeping its substeps, VJPs) over the forward without checkpoints;
+    beside it the general batched kernel on the same systems and steps."""
+    nsys, npl = 1024, 8
+    m, x, u = W.encounter_systems(nsys=nsys, nplanets=npl, seed_index=7, da=0.03, dphase=0.3)
+    off = np.arange(0, npl * nsys + 1, npl, dtype=np.int32)
+    gp = G.default_params()
+    sim = G.BatchedSimulation(off, np.ones(nsys), m.reshape(-1), x.reshape(-1, 3),
+                              u.reshape(-1, 3), gp, coords="helio")
+    xd, vd = sim.state("dem")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    # loss sum |x_T - x_target|^2 with x_target from initial conditions
+    # perturbed by 1e-6 (relative, normal; seed + 1000)
+    rng = np.random.default_rng(W.SEED_BASE + 7 + 1000)
+    xp = xd * (1.0 + 1e-6 * torch.tensor(rng.standard_normal(tuple(xd.shape)), device="cuda"))
+    vp = vd * (1.0 + 1e-6 * torch.tensor(rng.standard_normal(tuple(vd.shape)), device="cuda"))
+    sim.set_state(xp, vp, coords="dem")
+    sim.adj_forward(steps, steps)            # warm-up: the target
+    xt, _ = sim.state("dem")
+    sim.set_state(xd, vd, coords="dem")
+    sim.adj_forward(steps, steps)
+    xT, _ = sim.state("dem")
+    gx = (2.0 * (xT - xt)).contiguous()
+    gv = torch.zeros_like(gx)
+    sim.set_state(xd, vd, coords="dem")
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    sim.adj_forward(steps, steps)            # forward (one checkpoint)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    sim.set_state(xd, vd, coords="dem")
+    torch.cuda.synchronize()
+    ev[2].record(stream)
+    sim.adj_forward(steps, ckpt)             # forward keeping checkpoints
+    ev[3].record(stream)
+    sim.adj_backward(gx, gv)
+    ev[4].record(stream)
+    torch.cuda.synchronize()
+    sim.check()
+    sim.set_state(xd, vd, coords="dem")
+    sim.step(1)                              # the batched kernel's tuner runs here, untimed
+    sim.set_state(xd, vd, coords="dem")
+    torch.cuda.synchronize()
+    ev[5].record(stream)
+    sim.step(steps)                          # the general batched kernel, same systems
+    ev[6].record(stream)
+    torch.cuda.synchronize()
+    sim.check()
+    fwd = ev[0].elapsed_time(ev[1])
+    fck = ev[2].elapsed_time(ev[3])
+    bwd = ev[3].elapsed_time(ev[4])
+    gen = ev[5].elapsed_time(ev[6])
+    sim.close()
+    out = {"workload": f"hybrid_adjoint_{nsys}x{npl}_encounters", "steps": steps,
+           "ckpt_every": ckpt, "loss": float(((xT - xt) ** 2).sum()),
+           "forward_ms": fwd, "forward_ckpt_ms": fck, "backward_ms": bwd,
+           "adjoint_forward_ratio": bwd / fwd, "forward_plus_backward_ratio": (fck + bwd) / fwd,
+           "general_batched_kernel_ms": gen,
+           "system_steps_per_s_forward": nsys * steps / (fwd / 1e3)}
+    if cpu:
+        # the oracle's complex-step derivative (one direction, every decision
+        # fixed) on a sample: the CPU's cost of one directional derivative
+        import oracle as O
+        p = O.params()
+        ns = 16
+        t0 = time.perf_counter()
+        for k in range(ns):
+            vk = O.helio_to_dem(p, m[k], u[k])
+            O.cs_massive(p, m[k], x[k], vk, None, np.ones_like(x[k]), None, steps)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"directional_derivatives_per_s": ns / dt,
+                             "sample": f"first {ns} systems x {steps} steps, one direction each",
+                             "cores": 1}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,6 +371,8 @@ def main():
                     help="steps of the 16-body energy-error run reported under extra (0: skip)")
     ap.add_argument("--adj-steps", type=int, default=1000,
                     help="steps of the 1024 x 8 adjoint run reported under extra (0: skip)")
+    ap.add_argument("--hadj-steps", type=int, default=64,
+                    help="steps of the 1024 x 8 hybrid (encounter) adjoint run under extra (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed region run one 256 MiB device copy (counter scale)")
     args = ap.parse_args()
@@ -358,6 +441,9 @@ def main():
         extra["batched"] = batch_measure(G, W, torch, args.batch_steps, not args.no_cpu)
     if args.adj_steps > 0:
         extra["adjoint"] = adjoint_measure(G, W, torch, args.adj_steps)
+    if args.hadj_steps > 0:
+        extra["hybrid_adjoint"] = hybrid_adjoint_measure(G, W, torch, args.hadj_steps,
+                                                         cpu=not args.no_cpu)
 
     if args.calib_copy:
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")

@@ -23,8 +23,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # The batched kernel is instantiated for one and for two systems per wave; with
 # multiply-adds fused only inside one source expression (not wherever the
 # code generator finds a pair) both layouts round identically.
-# The hybrid adjoint rounds like the plain FP64 definitions it differentiates
-# (no fused multiply-adds), so that its decisions fall where theirs do.
+# The hybrid adjoint's forward map rounds like the plain FP64 definitions it
+# differentiates (no fused multiply-adds), so that its close encounters follow
+# theirs as closely as rounding allows.
 FILE_FLAGS = {"batch.hip": ["-ffp-contract=on"], "hadj.hip": ["-ffp-contract=off"]}
 
 

@@ -105,14 +105,13 @@ __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v,
   return ((unsigned long long)hi << 32) | lo;
 }
 
-// Changeover of Eqs. (4)-(5) for a pair at r with pair radius rc: K, dK/dr
-// and, with D2, d2K/dr2, dK/drc, d2K/(dr drc).  y = (r - 0.1 rc)/(0.9 rc),
-// K = y^2/D, D = 2y^2 - 2y + 1; kappa' = 2y(1-y)/D^2,
-// kappa'' = (2 - 4y)(1 + 2y - 2y^2)/D^3, dy/drc = -r/(0.9 rc^2).
-template <bool D2>
-__device__ __forceinline__ void chg(double r, double rc, double& K, double& Kr, double& Krr,
-                                    double& Kc, double& Krc) {
-  Krr = Kc = Krc = 0.0;
+// Changeover of Eqs. (4)-(5) for a pair at r with pair radius rc:
+// y = (r - 0.1 rc)/(0.9 rc), K = y^2/D, D = 2y^2 - 2y + 1, and dK/dr.  The
+// forward map rounds like the plain definitions (divisions and square roots
+// correctly rounded, no fused multiply-adds: this file is built with
+// -ffp-contract=off), so that its close encounters follow the reference
+// trajectory as closely as rounding allows.
+__device__ __forceinline__ void chg(double r, double rc, double& K, double& Kr) {
   if (!(rc > 0.0)) {
     K = 1.0;
     Kr = 0.0;
@@ -128,22 +127,46 @@ __device__ __forceinline__ void chg(double r, double rc, double& K, double& Kr, 
   } else {
     const double D = 2.0 * y * y - 2.0 * y + 1.0;
     K = y * y / D;
-    const double k1 = 2.0 * y * (1.0 - y) / (D * D);
-    Kr = k1 / (0.9 * rc);
-    if (D2) {
-      const double k2 = (2.0 - 4.0 * y) * (1.0 + 2.0 * y - 2.0 * y * y) / (D * D * D);
-      const double s = 1.0 / (0.9 * rc);
-      const double yc = -r / (0.9 * rc * rc);
-      Krr = k2 * s * s;
-      Kc = k1 * yc;
-      Krc = k2 * yc * s - k1 / (0.9 * rc * rc);
-    }
+    Kr = 2.0 * y * (1.0 - y) / (D * D) / (0.9 * rc);
+  }
+}
+
+// The same with the second derivatives for the reverse pass (reciprocals
+// refined from the hardware estimates): K, dK/dr, d2K/dr2, dK/drc,
+// d2K/(dr drc); kappa' = 2y(1-y)/D^2, kappa'' = (2 - 4y)(1 + 2y - 2y^2)/D^3,
+// dy/drc = -r/(0.9 rc^2) = -0.9 r s^2 with s = 1/(0.9 rc).
+__device__ __forceinline__ void chg2(double r, double rc, double& K, double& Kr, double& Krr,
+                                     double& Kc, double& Krc) {
+  Krr = Kc = Krc = 0.0;
+  if (!(rc > 0.0)) {
+    K = 1.0;
+    Kr = 0.0;
+    return;
+  }
+  const double s = rcp_nr(0.9 * rc);
+  const double y = (r - 0.1 * rc) * s;
+  if (y <= 0.0) {
+    K = 0.0;
+    Kr = 0.0;
+  } else if (y >= 1.0) {
+    K = 1.0;
+    Kr = 0.0;
+  } else {
+    const double iD = rcp_nr(2.0 * y * y - 2.0 * y + 1.0);  // D in [1/2, 1]
+    K = y * y * iD;
+    const double k1 = 2.0 * y * (1.0 - y) * iD * iD;
+    const double k2 = (2.0 - 4.0 * y) * (1.0 + 2.0 * y - 2.0 * y * y) * iD * iD * iD;
+    const double yc = -0.9 * r * s * s;
+    Kr = k1 * s;
+    Krr = k2 * s * s;
+    Kc = k1 * yc;
+    Krc = k2 * yc * s - 0.9 * k1 * s * s;
   }
 }
 
 // ---- forward pieces ----------------------------------------------------------
 // H_B acceleration (the gradient of Eq. 2): sum over the system's other bodies.
-__device__ void accel_B(const HArgs& a, const Sys& S, const double x[3], double rc, double acc[3]) {
+__device__ __forceinline__ void accel_B(const HArgs& a, const Sys& S, const double x[3], double rc, double acc[3]) {
   acc[0] = acc[1] = acc[2] = 0.0;
   for (int j = 0; j < S.n; ++j) {
     const double xj = readlane_d(x[0], j), yj = readlane_d(x[1], j), zj = readlane_d(x[2], j);
@@ -153,8 +176,8 @@ __device__ void accel_B(const HArgs& a, const Sys& S, const double x[3], double 
       const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
       const double r = sqrt(r2);
       const double rcij = rc > rcj ? rc : rcj;
-      double K, dK, u0, u1, u2;
-      chg<false>(r, rcij, K, dK, u0, u1, u2);
+      double K, dK;
+      chg(r, rcij, K, dK);
       const double f = K / (r2 * r) - dK / r2;
       const double s = a.G * mj * f;
       acc[0] += s * d0;
@@ -186,7 +209,7 @@ __device__ __forceinline__ void lane_sum3(const Sys& S, const double w[3], doubl
 
 // H_A derivative of a group member (star fixed at the origin, pair terms of
 // the members weighted by 1 - K): y = (x, v) -> (v, a).
-__device__ void ha_deriv(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
+__device__ __forceinline__ void ha_deriv(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
                          const double y[6], double dy[6]) {
   const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
   const double r = sqrt(r2);
@@ -201,8 +224,8 @@ __device__ void ha_deriv(const HArgs& a, const Sys& S, unsigned long long M, boo
       const double q2 = d0 * d0 + d1 * d1 + d2 * d2;
       const double qq = sqrt(q2);
       const double rcij = rc > rcj ? rc : rcj;
-      double K, dK, u0, u1, u2;
-      chg<false>(qq, rcij, K, dK, u0, u1, u2);
+      double K, dK;
+      chg(qq, rcij, K, dK);
       const double f = (1.0 - K) / (q2 * qq) + dK / q2;
       const double sj = a.G * mj * f;
       a0 += sj * d0;
@@ -219,40 +242,44 @@ __device__ void ha_deriv(const HArgs& a, const Sys& S, unsigned long long M, boo
 }
 
 // Gragg's modified midpoint rule over H with nsub substeps; with keep, the
-// positions z_0 .. z_nsub go to the lane's zpos slots.
-__device__ void gragg(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
-                      const double y0[6], double H, int nsub, double out[6], bool keep) {
+// positions z_0 .. z_nsub go to the lane's zpos slots.  One derivative per
+// pass of the loop: at z_0, at z_1 .. z_{nsub-1} (the midpoint steps), and at
+// z_nsub (the smoothing step).
+__device__ __forceinline__ void gragg(const HArgs& a, const Sys& S, unsigned long long M, bool mem,
+                                      double rc, const double y0[6], double H, int nsub,
+                                      double out[6], bool keep) {
   const double hs = H / nsub;
   double d[6], ym[6], yn[6];
-  ha_deriv(a, S, M, mem, rc, y0, d);
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    ym[c] = y0[c];
-    yn[c] = y0[c] + hs * d[c];
-  }
+  for (int c = 0; c < 6; ++c) yn[c] = y0[c];
   if (keep) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      a.zpos[(size_t)c * a.nl + S.gl] = y0[c];
-      a.zpos[(size_t)(3 + c) * a.nl + S.gl] = yn[c];
-    }
+    for (int c = 0; c < 3; ++c) a.zpos[(size_t)c * a.nl + S.gl] = y0[c];
   }
-  for (int m = 1; m < nsub; ++m) {
+  for (int m = 0; m <= nsub; ++m) {
     ha_deriv(a, S, M, mem, rc, yn, d);
+    if (m == 0) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const double t = ym[c] + 2.0 * hs * d[c];
-      ym[c] = yn[c];
-      yn[c] = t;
+      for (int c = 0; c < 6; ++c) {
+        ym[c] = y0[c];
+        yn[c] = y0[c] + hs * d[c];
+      }
+    } else if (m < nsub) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double t = ym[c] + 2.0 * hs * d[c];
+        ym[c] = yn[c];
+        yn[c] = t;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) out[c] = 0.5 * (ym[c] + yn[c] + hs * d[c]);
     }
-    if (keep) {
+    if (keep && m < nsub) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) a.zpos[((size_t)(m + 1) * 3 + c) * a.nl + S.gl] = yn[c];
     }
   }
-  ha_deriv(a, S, M, mem, rc, yn, d);
-#pragma unroll
-  for (int c = 0; c < 6; ++c) out[c] = 0.5 * (ym[c] + yn[c] + hs * d[c]);
 }
 
 __device__ __forceinline__ double vrel3(const double* A, const double* B) {
@@ -263,38 +290,43 @@ __device__ __forceinline__ double vrel3(const double* A, const double* B) {
 }
 
 // One BS attempt over H from y0: the accepted column (>= 1) with its value
-// in yout (members), or -1 when no column meets the tolerance.
-__device__ int bs_attempt(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
-                          const double y0[6], double H, double yout[6]) {
-  double Tr[kHK][6] = {};
-#pragma unroll
+// in yout (members), or -1 when no column meets the tolerance.  The lane's
+// tableau row lives in LDS (its own column of tab), so that the columns can
+// be a loop.
+__device__ __forceinline__ int bs_attempt(const HArgs& a, const Sys& S, unsigned long long M,
+                                          bool mem, double rc, const double y0[6], double H,
+                                          double yout[6]) {
+  __shared__ double tab[kHK][6][64];  // T(k - 1, j) on entry to column k, T(k, j) after
+  const int L = S.lane;
   for (int k = 0; k < kHK; ++k) {
-    double g[6];
-    gragg(a, S, M, mem, rc, y0, H, 2 * (k + 1), g, false);
-    double up[6];
+    double cur[6], up[6];
+    gragg(a, S, M, mem, rc, y0, H, 2 * (k + 1), cur, false);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      up[c] = Tr[0][c];
-      Tr[0][c] = g[c];
+      up[c] = tab[0][c][L];
+      tab[0][c][L] = cur[c];
     }
-#pragma unroll
     for (int j = 1; j <= k; ++j) {
       const double ratio = (double)(2 * (k + 1)) / (double)(2 * (k - j + 1));
       const double den = ratio * ratio - 1.0;
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        const double nw = Tr[j - 1][c] + (Tr[j - 1][c] - up[c]) / den;
-        if (j < k) up[c] = Tr[j][c];
-        Tr[j][c] = nw;
+        const double nw = cur[c] + (cur[c] - up[c]) / den;
+        if (j < k) up[c] = tab[j][c][L];
+        tab[j][c][L] = nw;
+        cur[c] = nw;
       }
     }
     if (k >= 1) {
+      double prev[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) prev[c] = tab[k - 1][c][L];
       double err = 0.0;
-      if (mem) err = fmax(vrel3(&Tr[k][0], &Tr[k - 1][0]), vrel3(&Tr[k][3], &Tr[k - 1][3]));
+      if (mem) err = fmax(vrel3(&cur[0], &prev[0]), vrel3(&cur[3], &prev[3]));
       err = wave_max(err);
       if (err <= a.bs_tol) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) yout[c] = Tr[k][c];
+        for (int c = 0; c < 6; ++c) yout[c] = cur[c];
         return k;
       }
     }
@@ -308,7 +340,7 @@ __device__ int bs_attempt(const HArgs& a, const Sys& S, unsigned long long M, bo
 // (LDS).  Returns 0, or -1 when the depth is exhausted; *nleaf counts the
 // accepted substeps.
 template <bool REC>
-__device__ int bs_group(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
+__device__ __forceinline__ int bs_group(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
                         double y[6], double* lh, int* lk, int* nleaf) {
   const int D = a.bs_depth;
   const int64_t total = (int64_t)1 << D;
@@ -363,7 +395,7 @@ struct StepVals {
 // Eqs. 10-12, below rc_ij^2), then the groups: every lane takes the smallest
 // label of its neighbours until nothing changes (the components of the
 // encounter graph, labelled by their smallest member).
-__device__ int groups(const HArgs& a, const Sys& S, unsigned long long cand, const double xa[3],
+__device__ __forceinline__ int groups(const HArgs& a, const Sys& S, unsigned long long cand, const double xa[3],
                       const double va[3], const double xb[3], const double vb[3], double rc) {
   unsigned long long E = 0ull;
   for (int j = 0; j < S.n; ++j) {
@@ -401,7 +433,7 @@ __device__ int groups(const HArgs& a, const Sys& S, unsigned long long cand, con
 }
 
 // The precheck (Sec. 2.2): partners j > i closer than pf rc_ij.
-__device__ unsigned long long precheck(const HArgs& a, const Sys& S, const double x[3], double rc) {
+__device__ __forceinline__ unsigned long long precheck(const HArgs& a, const Sys& S, const double x[3], double rc) {
   unsigned long long c = 0ull;
   for (int j = 0; j < S.n; ++j) {
     const double xj = readlane_d(x[0], j), yj = readlane_d(x[1], j), zj = readlane_d(x[2], j);
@@ -424,7 +456,7 @@ __device__ __forceinline__ double radius(const HArgs& a, const Sys& S, const dou
 
 // One hybrid step of the lane's system: x, v and the candidate bits in and
 // out; R keeps the intermediate values.
-__device__ void hyb_step(const HArgs& a, const Sys& S, double x[3], double v[3],
+__device__ __forceinline__ void hyb_step(const HArgs& a, const Sys& S, double x[3], double v[3],
                          unsigned long long& cand, StepVals& R, unsigned& fl) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -491,7 +523,7 @@ __device__ void hyb_step(const HArgs& a, const Sys& S, double x[3], double v[3],
 // the term of the first body sees it), so each term's radius adjoint goes
 // to the body whose radius it used.
 template <bool HA>
-__device__ void pair_vjp(const HArgs& a, const Sys& S, unsigned long long Pm, bool on, double rc,
+__device__ __forceinline__ void pair_vjp(const HArgs& a, const Sys& S, unsigned long long Pm, bool on, double rc,
                          const double x[3], const double w[3], double out[3], double& mb,
                          double& rcb) {
   for (unsigned long long q = Pm; q; q &= q - 1) {
@@ -502,11 +534,11 @@ __device__ void pair_vjp(const HArgs& a, const Sys& S, unsigned long long Pm, bo
     if (on && j != S.lane) {
       const double d0 = xj - x[0], d1 = yj - x[1], d2 = zj - x[2];
       const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-      const double r = sqrt(r2);
-      const double ir = 1.0 / r, ir2 = ir * ir, ir3 = ir2 * ir, ir4 = ir2 * ir2;
+      const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir2 * ir, ir4 = ir2 * ir2;
+      const double r = r2 * ir;
       const double rcij = rc > rcj ? rc : rcj;
       double K, Kr, Krr, Kc, Krc;
-      chg<true>(r, rcij, K, Kr, Krr, Kc, Krc);
+      chg2(r, rcij, K, Kr, Krr, Kc, Krc);
       double f = K * ir3 - Kr * ir2;
       double fr = 3.0 * Kr * ir3 - 3.0 * K * ir4 - Krr * ir2;
       double fc = Kc * ir3 - Krc * ir2;
@@ -533,13 +565,12 @@ __device__ void pair_vjp(const HArgs& a, const Sys& S, unsigned long long Pm, bo
 }
 
 // H_A acceleration adjoint of a group member: the star's term and the pairs.
-__device__ void ha_vjp(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
+__device__ __forceinline__ void ha_vjp(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
                        const double z[3], const double w[3], double out[3], double& mb,
                        double& rcb) {
   out[0] = out[1] = out[2] = 0.0;
   const double r2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
-  const double r = sqrt(r2);
-  const double ir = 1.0 / r, ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
+  const double ir = rsqrt_nr(r2), ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
   const double xw = z[0] * w[0] + z[1] * w[1] + z[2] * w[2];
   if (mem) {
 #pragma unroll
@@ -548,60 +579,55 @@ __device__ void ha_vjp(const HArgs& a, const Sys& S, unsigned long long M, bool 
   pair_vjp<true>(a, S, M, mem, rc, z, w, out, mb, rcb);
 }
 
-// yb += G^T ob for the Gragg sequence of nsub substeps over H from y0.
-__device__ void gragg_vjp(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
-                          const double y0[6], double H, int nsub, const double ob[6],
-                          double yb[6], double& mb, double& rcb) {
+// yb += G^T ob for the Gragg sequence of nsub substeps over H from y0: the
+// sequence recomputed keeping its positions, then reversed from the
+// smoothing step (out = (z_{n-1} + z_n + hs F(z_n)) / 2) through the
+// midpoint steps (z_{m+1} = z_{m-1} + 2 hs F(z_m)) to the first Euler step
+// (z_1 = z_0 + hs F(z_0)); P and Q hold the adjoints of z_{m+1} and z_m.
+__device__ __forceinline__ void gragg_vjp(const HArgs& a, const Sys& S, unsigned long long M,
+                                          bool mem, double rc, const double y0[6], double H,
+                                          int nsub, const double ob[6], double yb[6], double& mb,
+                                          double& rcb) {
   const double hs = H / nsub;
   double tmp[6];
   gragg(a, S, M, mem, rc, y0, H, nsub, tmp, true);
-  double z[3], w[3], o[3];
   double Pa[6], Qa[6];
-  // out = (z_{n-1} + z_n + hs F(z_n)) / 2
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    z[c] = a.zpos[((size_t)nsub * 3 + c) * a.nl + S.gl];
-    w[c] = 0.5 * hs * ob[3 + c];
-  }
-  ha_vjp(a, S, M, mem, rc, z, w, o, mb, rcb);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    Pa[c] = 0.5 * ob[c] + o[c];
-    Pa[3 + c] = 0.5 * ob[3 + c] + 0.5 * hs * ob[c];
-  }
-#pragma unroll
-  for (int c = 0; c < 6; ++c) Qa[c] = 0.5 * ob[c];
-  // z_{m+1} = z_{m-1} + 2 hs F(z_m), m = nsub - 1 .. 1
-  for (int m = nsub - 1; m >= 1; --m) {
+  for (int m = nsub; m >= 0; --m) {
+    double z[3], w[3], o[3];
+    const double cw = m == nsub ? 0.5 * hs : (m == 0 ? hs : 2.0 * hs);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       z[c] = a.zpos[((size_t)m * 3 + c) * a.nl + S.gl];
-      w[c] = 2.0 * hs * Pa[3 + c];
+      w[c] = cw * (m == nsub ? ob[3 + c] : Pa[3 + c]);
     }
     ha_vjp(a, S, M, mem, rc, z, w, o, mb, rcb);
+    if (m == nsub) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      Qa[c] += o[c];
-      Qa[3 + c] += 2.0 * hs * Pa[c];
+      for (int c = 0; c < 3; ++c) {
+        Pa[c] = 0.5 * ob[c] + o[c];
+        Pa[3 + c] = 0.5 * ob[3 + c] + 0.5 * hs * ob[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) Qa[c] = 0.5 * ob[c];
+    } else if (m > 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Qa[c] += o[c];
+        Qa[3 + c] += 2.0 * hs * Pa[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double t = Pa[c];
+        Pa[c] = Qa[c];
+        Qa[c] = t;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Qa[c] += Pa[c] + o[c];
+        Qa[3 + c] += Pa[3 + c] + hs * Pa[c];
+      }
     }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const double t = Pa[c];
-      Pa[c] = Qa[c];
-      Qa[c] = t;
-    }
-  }
-  // z_1 = z_0 + hs F(z_0)
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    z[c] = a.zpos[(size_t)c * a.nl + S.gl];
-    w[c] = hs * Pa[3 + c];
-  }
-  ha_vjp(a, S, M, mem, rc, z, w, o, mb, rcb);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    Qa[c] += Pa[c] + o[c];
-    Qa[3 + c] += Pa[3 + c] + hs * Pa[c];
   }
 #pragma unroll
   for (int c = 0; c < 6; ++c) yb[c] += Qa[c];
@@ -609,7 +635,7 @@ __device__ void gragg_vjp(const HArgs& a, const Sys& S, unsigned long long M, bo
 
 // Adjoint of one group's BS over tau from y1 (the members' pre-drift
 // state): yb holds the adjoint of the BS result in and that of y1 out.
-__device__ void bs_group_vjp(const HArgs& a, const Sys& S, unsigned long long M, bool mem,
+__device__ __forceinline__ void bs_group_vjp(const HArgs& a, const Sys& S, unsigned long long M, bool mem,
                              double rc, const double y1[6], double yb[6], double& mb, double& rcb,
                              double* lh, int* lk, unsigned& fl) {
   double y[6];
@@ -648,7 +674,7 @@ __device__ void bs_group_vjp(const HArgs& a, const Sys& S, unsigned long long M,
 }
 
 // Radius adjoint (Eq. 6, the branch taken) into x^, v^, m^.
-__device__ void radius_vjp(const HArgs& a, const Sys& S, const double x[3], const double v[3],
+__device__ __forceinline__ void radius_vjp(const HArgs& a, const Sys& S, const double x[3], const double v[3],
                            double rcb, double xb[3], double vb[3], double& mb) {
   if (!S.act) return;
   const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
@@ -762,28 +788,32 @@ __global__ __launch_bounds__(64) void k_hadj_bwd(HArgs a) {
       }
       cand = (unsigned long long)__double_as_longlong(cp[6 * a.nb + S.row]);
     }
-    // replay the segment, keeping every step's start
-    for (int t = t0; t < t1; ++t) {
+    // the segment replayed keeping every step's start, then its steps in
+    // reverse, each recomputed from its start (one loop, so that the step's
+    // code appears once)
+    const int ns = t1 - t0;
+    for (int it = 0; it < 2 * ns; ++it) {
+      const bool rev = it >= ns;
+      const int t = rev ? t1 - 1 - (it - ns) : t0 + it;
       double* tp = a.tape + (size_t)(t - t0) * 7 * a.nl;
+      if (!rev) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        tp[k * a.nl + S.gl] = x[k];
-        tp[(3 + k) * a.nl + S.gl] = v[k];
+        for (int k = 0; k < 3; ++k) {
+          tp[k * a.nl + S.gl] = x[k];
+          tp[(3 + k) * a.nl + S.gl] = v[k];
+        }
+        tp[6 * a.nl + S.gl] = __longlong_as_double((long long)cand);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          x[k] = tp[k * a.nl + S.gl];
+          v[k] = tp[(3 + k) * a.nl + S.gl];
+        }
+        cand = (unsigned long long)__double_as_longlong(tp[6 * a.nl + S.gl]);
       }
-      tp[6 * a.nl + S.gl] = __longlong_as_double((long long)cand);
       StepVals R;
       hyb_step(a, S, x, v, cand, R, fl);
-    }
-    for (int t = t1 - 1; t >= t0; --t) {
-      const double* tp = a.tape + (size_t)(t - t0) * 7 * a.nl;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        x[k] = tp[k * a.nl + S.gl];
-        v[k] = tp[(3 + k) * a.nl + S.gl];
-      }
-      cand = (unsigned long long)__double_as_longlong(tp[6 * a.nl + S.gl]);
-      StepVals R;
-      hyb_step(a, S, x, v, cand, R, fl);
+      if (!rev) continue;
       const double rc = R.rc;
       double rcb = 0.0;
       // closing kick: v4 = v2 + h a_B(x3)
