@@ -334,6 +334,169 @@ __device__ __forceinline__ int bs_attempt(const HArgs& a, const Sys& S, unsigned
   return -1;
 }
 
+// ---- column-parallel BS for groups of up to 8 members ----------------------
+// Lane L = 8 c + q holds column c (2 (c + 1) substeps) of member slot q (the
+// q-th member in body order), so the columns of an attempt run side by side:
+// an attempt takes as many derivative rounds as its longest column (17)
+// instead of the sum over its columns (up to 80).  The Aitken-Neville
+// tableau moves down the columns by lane reads from the column below (lane
+// - 8).  Every sum is formed in the order of the one-column-at-a-time form
+// above, so both give the same bits.
+constexpr int kHPar = 8;
+
+struct Par {
+  int c, q, sz, src;             // column, member slot, group size, body lane of the slot
+  bool on;                       // the slot holds a member
+  double m, rc;                  // its mass and radius
+  double pm[kHPar], prc[kHPar];  // every slot's mass and radius
+};
+
+__device__ __forceinline__ int nth_bit64(unsigned long long M, int b) {
+  for (int t = 0; t < b; ++t) M &= M - 1;
+  return __builtin_ctzll(M);
+}
+
+__device__ __forceinline__ Par par_of(const Sys& S, unsigned long long M, double rc) {
+  Par P;
+  P.c = S.lane >> 3;
+  P.q = S.lane & 7;
+  P.sz = __builtin_popcountll(M);
+  P.on = P.q < P.sz;
+  P.src = P.on ? nth_bit64(M, P.q) : 0;
+  P.m = __shfl(S.m, P.src, 64);
+  P.rc = __shfl(rc, P.src, 64);
+#pragma unroll
+  for (int t = 0; t < kHPar; ++t) {
+    const int bl = t < P.sz ? nth_bit64(M, t) : 0;
+    P.pm[t] = readlane_d(S.m, bl);
+    P.prc[t] = readlane_d(rc, bl);
+  }
+  return P;
+}
+
+// ha_deriv for the lane's slot, partners from the lanes of its column.
+__device__ __forceinline__ void ha_deriv_par(const HArgs& a, const Sys& S, const Par& P,
+                                             const double y[6], double dy[6]) {
+  const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+  const double r = sqrt(r2);
+  const double fs = -S.Gm0 / (r2 * r);
+  double a0 = fs * y[0], a1 = fs * y[1], a2 = fs * y[2];
+  const int base = S.lane & ~7;
+#pragma unroll
+  for (int t = 0; t < kHPar; ++t) {
+    const double xj = __shfl(y[0], base + t, 64), yj = __shfl(y[1], base + t, 64),
+                 zj = __shfl(y[2], base + t, 64);
+    if (t < P.sz && P.on && t != P.q) {
+      const double d0 = xj - y[0], d1 = yj - y[1], d2 = zj - y[2];
+      const double q2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const double qq = sqrt(q2);
+      const double rcij = P.rc > P.prc[t] ? P.rc : P.prc[t];
+      double K, dK;
+      chg(qq, rcij, K, dK);
+      const double f = (1.0 - K) / (q2 * qq) + dK / q2;
+      const double sj = a.G * P.pm[t] * f;
+      a0 += sj * d0;
+      a1 += sj * d1;
+      a2 += sj * d2;
+    }
+  }
+  dy[0] = y[3];
+  dy[1] = y[4];
+  dy[2] = y[5];
+  dy[3] = a0;
+  dy[4] = a1;
+  dy[5] = a2;
+}
+
+// The lane's column of Gragg's rule (2 (c + 1) substeps over H); 17 rounds,
+// a column idle once its sequence is done.  keep: positions to zpos.
+__device__ __forceinline__ void gragg_par(const HArgs& a, const Sys& S, const Par& P,
+                                          const double y0[6], double H, double out[6],
+                                          bool keep) {
+  const int nsub = 2 * (P.c + 1);
+  const double hs = H / nsub;
+  double d[6], ym[6], yn[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    yn[c] = y0[c];
+    ym[c] = y0[c];
+    out[c] = 0.0;
+  }
+  if (keep) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.zpos[(size_t)c * a.nl + S.gl] = y0[c];
+  }
+  for (int m = 0; m <= 2 * kHPar; ++m) {
+    ha_deriv_par(a, S, P, yn, d);
+    if (m == 0) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) yn[c] = y0[c] + hs * d[c];
+    } else if (m < nsub) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double t = ym[c] + 2.0 * hs * d[c];
+        ym[c] = yn[c];
+        yn[c] = t;
+      }
+    } else if (m == nsub) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) out[c] = 0.5 * (ym[c] + yn[c] + hs * d[c]);
+    }
+    if (keep && m < nsub) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.zpos[((size_t)(m + 1) * 3 + c) * a.nl + S.gl] = yn[c];
+    }
+  }
+}
+
+// bs_attempt with the columns side by side: y holds the members' state in
+// their body lanes; the accepted column (>= 1) with its value in yout (body
+// lanes of members), or -1.
+__device__ __forceinline__ int bs_attempt_par(const HArgs& a, const Sys& S,
+                                              unsigned long long M, const Par& P,
+                                              const double y[6], double H, double yout[6]) {
+  double y0[6], T[6], Td[6], Ts[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) y0[c] = __shfl(y[c], P.src, 64);
+  gragg_par(a, S, P, y0, H, T, false);  // T(c, 0)
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    Td[c] = T[c];
+    Ts[c] = 0.0;
+  }
+  for (int j = 1; j < kHPar; ++j) {
+    double up[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) up[c] = __shfl(T[c], S.lane - 8, 64);  // T(c - 1, j - 1)
+    if (P.c >= j) {
+      const double ratio = (double)(2 * (P.c + 1)) / (double)(2 * (P.c - j + 1));
+      const double den = ratio * ratio - 1.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double nw = T[c] + (T[c] - up[c]) / den;
+        if (P.c == j) {
+          Ts[c] = T[c];
+          Td[c] = nw;
+        }
+        T[c] = nw;
+      }
+    }
+  }
+  double err = 0.0;
+  if (P.on && P.c >= 1) err = fmax(vrel3(&Td[0], &Ts[0]), vrel3(&Td[3], &Ts[3]));
+  err = fmax(err, __shfl_xor(err, 1, 64));
+  err = fmax(err, __shfl_xor(err, 2, 64));
+  err = fmax(err, __shfl_xor(err, 4, 64));
+  const unsigned long long ok =
+      __builtin_amdgcn_ballot_w64(P.q == 0 && P.c >= 1 && err <= a.bs_tol);
+  if (ok == 0ull) return -1;
+  const int k = __builtin_ctzll(ok) >> 3;
+  const int qi = __builtin_popcountll(M & ((1ull << S.lane) - 1ull));  // the body lane's slot
+#pragma unroll
+  for (int c = 0; c < 6; ++c) yout[c] = __shfl(Td[c], 8 * k + (qi & 7), 64);
+  return k;
+}
+
 // BS of one group over tau with binary refinement (as the main mode): y is
 // the members' state in and out.  With REC the start of every accepted
 // substep goes to the lane's leaf slots and its length and column to lh, lk
@@ -342,6 +505,7 @@ __device__ __forceinline__ int bs_attempt(const HArgs& a, const Sys& S, unsigned
 template <bool REC>
 __device__ __forceinline__ int bs_group(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
                         double y[6], double* lh, int* lk, int* nleaf) {
+  const Par P = par_of(S, M, rc);
   const int D = a.bs_depth;
   const int64_t total = (int64_t)1 << D;
   int64_t pos = 0;
@@ -349,7 +513,8 @@ __device__ __forceinline__ int bs_group(const HArgs& a, const Sys& S, unsigned l
   while (pos < total) {
     const double hh = ldexp(a.dt, -d);
     double yn[6];
-    const int k = bs_attempt(a, S, M, mem, rc, y, hh, yn);
+    const int k = P.sz <= kHPar ? bs_attempt_par(a, S, M, P, y, hh, yn)
+                                : bs_attempt(a, S, M, mem, rc, y, hh, yn);
     if (k >= 1) {
       if (REC) {
         if (nl < kHLeaf) {
@@ -633,6 +798,110 @@ __device__ __forceinline__ void gragg_vjp(const HArgs& a, const Sys& S, unsigned
   for (int c = 0; c < 6; ++c) yb[c] += Qa[c];
 }
 
+// ha_vjp for the lane's slot of the column-parallel layout (partners from
+// the lanes of its column, in slot order).
+__device__ __forceinline__ void ha_vjp_par(const HArgs& a, const Sys& S, const Par& P,
+                                           const double z[3], const double w[3], double out[3],
+                                           double& mb, double& rcb) {
+  out[0] = out[1] = out[2] = 0.0;
+  const double r2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+  const double ir = rsqrt_nr(r2), ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
+  const double xw = z[0] * w[0] + z[1] * w[1] + z[2] * w[2];
+  if (P.on) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c] = -S.Gm0 * (w[c] * ir3 - 3.0 * xw * z[c] * ir5);
+  }
+  const int base = S.lane & ~7;
+#pragma unroll
+  for (int t = 0; t < kHPar; ++t) {
+    const double xj = __shfl(z[0], base + t, 64), yj = __shfl(z[1], base + t, 64),
+                 zj = __shfl(z[2], base + t, 64);
+    const double wx = __shfl(w[0], base + t, 64), wy = __shfl(w[1], base + t, 64),
+                 wz = __shfl(w[2], base + t, 64);
+    if (t < P.sz && P.on && t != P.q) {
+      const double mj = P.pm[t], rcj = P.prc[t];
+      const double d0 = xj - z[0], d1 = yj - z[1], d2 = zj - z[2];
+      const double q2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const double iq = rsqrt_nr(q2), iq2 = iq * iq, iq3 = iq2 * iq, iq4 = iq2 * iq2;
+      const double q = q2 * iq;
+      const double rcij = P.rc > rcj ? P.rc : rcj;
+      double K, Kr, Krr, Kc, Krc;
+      chg2(q, rcij, K, Kr, Krr, Kc, Krc);
+      const double f = iq3 - (K * iq3 - Kr * iq2);
+      const double fr = -3.0 * iq4 - (3.0 * Kr * iq3 - 3.0 * K * iq4 - Krr * iq2);
+      const double fc = -(Kc * iq3 - Krc * iq2);
+      const double u0 = P.m * wx - mj * w[0], u1 = P.m * wy - mj * w[1], u2 = P.m * wz - mj * w[2];
+      const double du = d0 * u0 + d1 * u1 + d2 * u2;
+      const double cc = fr * iq * du;
+      out[0] += a.G * (f * u0 + cc * d0);
+      out[1] += a.G * (f * u1 + cc * d1);
+      out[2] += a.G * (f * u2 + cc * d2);
+      mb -= a.G * f * (d0 * wx + d1 * wy + d2 * wz);
+      const double tl = a.G * fc * mj * (d0 * w[0] + d1 * w[1] + d2 * w[2]);
+      const double tp = -a.G * fc * P.m * (d0 * wx + d1 * wy + d2 * wz);
+      if (P.rc > rcj) rcb += tl;
+      if (P.rc >= rcj) rcb += tp;
+    }
+  }
+}
+
+// gragg_vjp for the lane's column of the column-parallel layout: 17 reverse
+// rounds, a column idle above its own sequence.
+__device__ __forceinline__ void gragg_vjp_par(const HArgs& a, const Sys& S, const Par& P,
+                                              const double y0[6], double H, const double ob[6],
+                                              double yb[6], double& mb, double& rcb) {
+  const int nsub = 2 * (P.c + 1);
+  const double hs = H / nsub;
+  double tmp[6];
+  gragg_par(a, S, P, y0, H, tmp, true);
+  double Pa[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Qa[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int m = 2 * kHPar; m >= 0; --m) {
+    const bool act = m <= nsub;
+    const int mz = act ? m : nsub;
+    double z[3], w[3], o[3];
+    const double cw = m == nsub ? 0.5 * hs : (m == 0 ? hs : 2.0 * hs);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      z[c] = a.zpos[((size_t)mz * 3 + c) * a.nl + S.gl];
+      w[c] = act ? cw * (m == nsub ? ob[3 + c] : Pa[3 + c]) : 0.0;
+    }
+    double mbl = 0.0, rcbl = 0.0;
+    ha_vjp_par(a, S, P, z, w, o, mbl, rcbl);
+    if (!act) continue;
+    mb += mbl;
+    rcb += rcbl;
+    if (m == nsub) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Pa[c] = 0.5 * ob[c] + o[c];
+        Pa[3 + c] = 0.5 * ob[3 + c] + 0.5 * hs * ob[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) Qa[c] = 0.5 * ob[c];
+    } else if (m > 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Qa[c] += o[c];
+        Qa[3 + c] += 2.0 * hs * Pa[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double t = Pa[c];
+        Pa[c] = Qa[c];
+        Qa[c] = t;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Qa[c] += Pa[c] + o[c];
+        Qa[3 + c] += Pa[3 + c] + hs * Pa[c];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) yb[c] += Qa[c];
+}
+
 // Adjoint of one group's BS over tau from y1 (the members' pre-drift
 // state): yb holds the adjoint of the BS result in and that of y1 out.
 __device__ __forceinline__ void bs_group_vjp(const HArgs& a, const Sys& S, unsigned long long M, bool mem,
@@ -652,12 +921,46 @@ __device__ __forceinline__ void bs_group_vjp(const HArgs& a, const Sys& S, unsig
     fl |= F_ADJ_LEAF;
     return;
   }
+  const Par P = par_of(S, M, rc);
+  const int qi = __builtin_popcountll(M & ((1ull << S.lane) - 1ull)) & 7;  // body lane's slot
   for (int l = nleaf - 1; l >= 0; --l) {
     const double hh = lh[l];
     const int kk = lk[l];
     double yin[6], acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < 6; ++c) yin[c] = a.leaf[((size_t)l * 6 + c) * a.nl + S.gl];
+    if (P.sz <= kHPar) {
+      // the columns side by side, then each member's columns added in order
+      double y0[6], ob[6], col[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      const double wq = P.c <= kk ? kNW.w[kk][P.c] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        y0[c] = __shfl(yin[c], P.src, 64);
+        ob[c] = wq * __shfl(yb[c], P.src, 64);
+      }
+      double mbl = 0.0, rcbl = 0.0;
+      gragg_vjp_par(a, S, P, y0, hh, ob, col, mbl, rcbl);
+      double msum = 0.0, rsum = 0.0;
+      for (int c8 = 0; c8 < kHPar; ++c8) {
+        double v[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = __shfl(col[c], 8 * c8 + qi, 64);
+        const double mv = __shfl(mbl, 8 * c8 + qi, 64), rv = __shfl(rcbl, 8 * c8 + qi, 64);
+        if (c8 <= kk) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) acc[c] += v[c];
+          msum += mv;
+          rsum += rv;
+        }
+      }
+      if (mem) {
+        mb += msum;
+        rcb += rsum;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) yb[c] = acc[c];
+      }
+      continue;
+    }
     for (int q = 0; q <= kk; ++q) {
       const double wq = kNW.w[kk][q];
       double ob[6];
