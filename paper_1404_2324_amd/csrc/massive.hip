@@ -110,7 +110,7 @@ struct PairArgs {
 
 enum { KICK_CLOSE = 0, KICK_INIT = 1, KICK_ACC = 2 };
 
-// Workgroup (b, s) takes the 64 bodies i = 64 b + lane and the partners of
+// Workgroup (s, b) takes the 64 bodies i = 64 b + lane and the partners of
 // split s; each of its 16 waves a contiguous range of L = np / (16 njs)
 // partners j (L is even: np is a multiple of 32 njs), the same j for every lane, so the partner data
 // (x, y, z, m) comes through the scalar cache into SGPRs, two partners ahead
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_part(PairArgs a,
   __shared__ double red[6][kPairW][kPairBlock];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int ib = blockIdx.x, sp = blockIdx.y;
+  const int ib = blockIdx.y, sp = blockIdx.x;
   // a context's step: a stopped run appends nothing (its partial sums are
   // written and ignored by the finishing kernel), and rows past the live
   // count are padding (bodies that left); the acceleration form has no
@@ -1909,8 +1909,10 @@ PairArgs pair_args(const MassiveWs& w, const StepConsts& c) {
   return a;
 }
 
-// Workgroups of the pair kernel: 64-body blocks x splits.
-inline dim3 pair_grid(const MassiveWs& w) { return dim3(w.np / kPairBlock, w.njs); }
+// Workgroups of the pair kernel: splits x 64-body blocks, the split fastest,
+// so that consecutive workgroups (dispatched to the 8 XCDs in turn) take
+// different splits: with 8 splits each XCD's L2 holds one split's partners.
+inline dim3 pair_grid(const MassiveWs& w) { return dim3(w.njs, w.np / kPairBlock); }
 
 }  // namespace
 
