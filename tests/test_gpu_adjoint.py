@@ -1,9 +1,10 @@
 """GPU reverse-mode gradient of the encounter-free map (K = 1) against the
 oracle: its forward map, its adjoint (built from its tangent-linear model),
-the dot-product identity with that model, and central finite differences
-through the GPU forward map.  Gradients: 1e-9 of the largest component
-(the two sides accumulate thousands of rounding steps in different orders);
-states: 1e-12 relative."""
+the dot-product identity with that model (2e-12 relative; observed at most
+7e-13), and central finite differences through the GPU forward map.
+Gradients: 1e-9 of the largest component (the two sides accumulate
+thousands of rounding steps in different orders; observed 2e-13); states:
+1e-12 relative."""
 import numpy as np
 import pytest
 import torch
@@ -76,7 +77,7 @@ def test_adjoint_dot_product_with_oracle_tlm():
         rhs = np.sum(dx[a:b] * gx0[a:b]) + np.sum(dv[a:b] * gv0[a:b]) + np.sum(dm[a:b] * gm[a:b])
         rel = abs(lhs - rhs) / max(abs(lhs), 1e-300)
         _say("dot product system", s, "relative difference", rel)
-        assert rel <= 1e-10, (s, lhs, rhs)
+        assert rel <= 2e-12, (s, lhs, rhs)
 
 
 def test_autograd_loss_against_finite_differences():
