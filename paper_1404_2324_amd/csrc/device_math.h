@@ -94,7 +94,10 @@ __device__ __forceinline__ void changeover(double r, double rc, double& K,
     dKdr = 0.0;
     return;
   }
-  const double inv = 1.0 / (0.9 * rc);
+  // the reciprocals by rcp_nr (correctly rounded for these well-scaled
+  // arguments, as the division; 0.9 rc is a length of order 1e-4..1, D is in
+  // [1/2, 1])
+  const double inv = rcp_nr(0.9 * rc);
   const double y = (r - 0.1 * rc) * inv;
   if (y <= 0.0) {
     K = 0.0;
@@ -104,7 +107,7 @@ __device__ __forceinline__ void changeover(double r, double rc, double& K,
     dKdr = 0.0;
   } else {
     const double D = 2.0 * y * y - 2.0 * y + 1.0;
-    const double iD = 1.0 / D;
+    const double iD = rcp_nr(D);
     K = y * y * iD;
     dKdr = 2.0 * y * (1.0 - y) * iD * iD * inv;
   }
