@@ -179,3 +179,39 @@ def test_hybrid_adjoint_full_workload_sampled():
         _say("system", s, "encounters", st["enc_total"], "BS substeps", st["bs_substeps"],
              "relative", rel)
         assert rel <= 1e-9, (s, lhs, rhs)
+
+
+def test_hybrid_ragged_systems_and_groups_over_eight():
+    """Systems of 3, 12, 7 and 10 planets in one context, groups of up to 12
+    members (over 8: the one-column-at-a-time BS path; up to 8: the
+    column-parallel one), 12 steps with a checkpoint every 5: states and
+    every gradient component against the oracle."""
+    sizes, T, K = (3, 12, 7, 10), 12, 5
+    p = O.params()
+    ms, xs, vs = [], [], []
+    for npl in sizes:
+        m, x, u = W.encounter_systems(nsys=1, nplanets=npl, seed_index=20)
+        ms.append(m[0])
+        xs.append(x[0])
+        vs.append(O.helio_to_dem(p, m[0], u[0]))
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    m, x, v = np.concatenate(ms), np.concatenate(xs), np.concatenate(vs)
+    rng = np.random.default_rng(65)
+    gxT, gvT = rng.standard_normal(x.shape), rng.standard_normal(v.shape)
+    sim = _sim(off, np.ones(len(sizes)), m, x, v)
+    sim.adj_forward(T, K)
+    xT, vT = [t.cpu().numpy() for t in sim.state("dem")]
+    gx0, gv0, gm = [t.cpu().numpy() for t in sim.adj_backward(gxT, gvT)]
+    sim.check()
+    big = 0
+    for s in range(len(sizes)):
+        a, b = off[s], off[s + 1]
+        ox, ov, _, _, st = O.cs_massive(p, m[a:b], x[a:b], v[a:b], None, None, None, T)
+        big = max(big, st["max_group"])
+        assert _rel(xT[a:b], ox) <= 1e-12 and _rel(vT[a:b], ov) <= 1e-12, s
+        cx, cv, cm = O.cs_gradient(p, m[a:b], x[a:b], v[a:b], T, gxT[a:b], gvT[a:b])
+        for g, o, what in ((gx0[a:b], cx, "x"), (gv0[a:b], cv, "v"), (gm[a:b], cm, "m")):
+            err = _rel(g, o)
+            _say("system", s, "size", sizes[s], "d/d" + what, err)
+            assert err <= 1e-9, (s, what, err)
+    assert big > 8
