@@ -444,7 +444,7 @@ int genga_accel(const genga_params *p, int n, const double *d_m,
  * kernels and the same bits as genga_accel, for 1 <= n <=
  * GENGA_ACCEL_NOALLOC_MAX bodies (EINVAL beyond).  The library keeps the
  * packed bodies, radii and thresholds in a fixed device array of its own,
- * about 2.7 MB, one per GPU, held until the process ends; the first call on
+ * about 5.0 MB, one per GPU, held until the process ends; the first call on
  * a device looks up that device's copy (on the device current at the call,
  * which must be the stream's).  Calls that overlap on one GPU (concurrent
  * streams or threads) share that array and race: serialise them.

@@ -68,7 +68,7 @@ constexpr int kVecBlock = 256;         // threads of the per-body kernels
 // Views into the caller's workspace for main mode (also the massive part of
 // test-particle mode).  Bodies are padded to np (a multiple of 256).
 struct MassiveWs {
-  int n, np, njs, nblk;            // njs: partner splits of the pair kernel
+  int n, np, njs, pw, nblk;        // njs: partner splits of the pair kernel, pw: its waves per workgroup
   int cpb;              // candidate slots per body
   int enc_cap;
   double4* xm;          // x, y, z, m          (democratic: heliocentric x)

@@ -83,11 +83,18 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 // the prechecker (Sec. 2.2), as per-split partial sums; a second kernel
 // adds the splits of each body in a fixed order and applies the per-body
 // epilogue.
-constexpr int kPairW = 16;                     // waves per workgroup
-constexpr int kPairThreads = kPairW * 64;
+// Two shapes (waves per workgroup, splits x padded bodies aimed for), chosen
+// by size (measured): below kPairBigN 16 waves and 16384 (2048 bodies: 8
+// splits, 4096 waves; the launch floor dominates there), from kPairBigN on 8
+// waves and 65536 (16384 bodies: 4 splits, 1024 workgroups of 8 waves,
+// 21.1 against 18.6 TFLOP/s with the small-system shape).
+constexpr int kPairW = 16;                     // waves per workgroup, small systems
+constexpr int kPairTarget = 16384;
+constexpr int kPairWBig = 8;                   // waves per workgroup, large systems
+constexpr int kPairTargetBig = 65536;
+constexpr int kPairBigN = 8192;                // padded bodies from which the large shape runs
 constexpr int kPairBlock = 64;                 // i-bodies per workgroup (one per lane)
 constexpr int kPairU = 2;                      // partners per prefetched batch
-constexpr int kPairTarget = 16384;             // splits x padded bodies aimed for
 constexpr int kFinThreads = 64;                // threads of the finishing kernel
 
 struct PairArgs {
@@ -126,13 +133,13 @@ enum { KICK_CLOSE = 0, KICK_INIT = 1, KICK_ACC = 2 };
 // threshold T (over its 64 bodies and its partner range, from the 64-body
 // chunk maxima): below it the term is held out of the far sum by a select,
 // and a wave with any such lane takes the exact test for those lanes.  The
-// 16 waves' sums are added in LDS in wave order; the split's sums go to pp.
-template <int MODE>
-__global__ __launch_bounds__(kPairThreads) void k_pair_part(PairArgs a,
+// W waves' sums are added in LDS in wave order; the split's sums go to pp.
+template <int MODE, int W>
+__global__ __launch_bounds__(W * 64) void k_pair_part(PairArgs a,
                                                             const double4* __restrict__ x,
                                                             const double* __restrict__ thr,
                                                             const double* __restrict__ tmx) {
-  __shared__ double red[6][kPairW][kPairBlock];
+  __shared__ double red[6][W][kPairBlock];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ib = blockIdx.y, sp = blockIdx.x;
@@ -149,7 +156,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_part(PairArgs a,
   }
   const int i = ib * kPairBlock + lane;
   const int L = a.jl;
-  const int j0 = __builtin_amdgcn_readfirstlane((sp * kPairW + wave) * L);
+  const int j0 = __builtin_amdgcn_readfirstlane((sp * W + wave) * L);
   const double4* xj = x + j0;
   double4 cur[kPairU], nxt[kPairU];
 #pragma unroll
@@ -243,7 +250,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_part(PairArgs a,
     const int cpt = threadIdx.x >> 6, q = threadIdx.x & 63;
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < kPairW; ++w) t += red[cpt][w][q];
+    for (int w = 0; w < W; ++w) t += red[cpt][w][q];
     a.pp[((size_t)sp * 6 + cpt) * a.np + ib * kPairBlock + q] = t;
   }
 }
@@ -1884,7 +1891,7 @@ PairArgs pair_args(const MassiveWs& w, const StepConsts& c) {
   a.cr2 = w.cr2;
   a.pp = w.pp;
   a.njs = w.njs;
-  a.jl = w.np / (w.njs * kPairW);
+  a.jl = w.np / (w.njs * w.pw);
   a.xs = w.xs;
   a.vv = w.vv;
   a.afar = w.afar;
@@ -1908,6 +1915,13 @@ PairArgs pair_args(const MassiveWs& w, const StepConsts& c) {
   a.pf = c.pf;
   return a;
 }
+
+// The pair kernel of the workspace's shape, and its workgroup size.
+template <int MODE>
+inline auto pair_kernel(const MassiveWs& w) {
+  return w.pw == kPairWBig ? k_pair_part<MODE, kPairWBig> : k_pair_part<MODE, kPairW>;
+}
+inline dim3 pair_block(const MassiveWs& w) { return dim3(w.pw * 64); }
 
 // Workgroups of the pair kernel: splits x 64-body blocks, the split fastest,
 // so that consecutive workgroups (dispatched to the 8 XCDs in turn) take
@@ -1980,22 +1994,30 @@ size_t massive_ws_bytes(int n, const genga_params& p, bool snap) {
 
 // Lay the main-mode arrays out in the workspace starting at base (nullptr:
 // only size the layout).  Returns the bytes used.
-// Splits of the partner range per 64-body block of the pair kernel: the
-// largest divisor of np / (16 waves x 2 partners) with splits x np at most
-// kPairTarget, so that small systems still spread over the whole chip
-// (2048 bodies: 8 splits, 4096 waves) and every wave takes whole batches.
-int pair_splits(int np) {
-  const int q = np / (kPairW * kPairU);
+// Splits of the partner range per 64-body block of the pair kernel with W
+// waves per workgroup: the largest divisor of np / (W waves x 2 partners)
+// with splits x np at most target, so that small systems still spread over
+// the whole chip (2048 bodies: 8 splits, 4096 waves) and every wave takes
+// whole batches.
+int pair_splits(int np, int W, int target) {
+  const int q = np / (W * kPairU);
   int best = 1;
   for (int d = 1; d <= q; ++d)
-    if (q % d == 0 && (size_t)d * np <= (size_t)kPairTarget) best = d;
+    if (q % d == 0 && (size_t)d * np <= (size_t)target) best = d;
   return best;
+}
+
+// The pair kernel's shape for np padded bodies: waves per workgroup, splits.
+void pair_shape(int np, int* pw, int* njs) {
+  const bool big = np >= kPairBigN;
+  *pw = big ? kPairWBig : kPairW;
+  *njs = pair_splits(np, *pw, big ? kPairTargetBig : kPairTarget);
 }
 
 size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base, bool snap) {
   w.n = n;
   w.np = ceil_div(n, 256) * 256;
-  w.njs = pair_splits(w.np);
+  pair_shape(w.np, &w.pw, &w.njs);
   w.nblk = ceil_div(n, kVecBlock);
   w.cpb = p.cand_per_body;
   w.enc_cap = p.enc_cap;
@@ -2078,7 +2100,7 @@ hipError_t massive_prime(const MassiveWs& w, const StepConsts& c, hipStream_t s)
                      w.rc_cur, w.thr, w.tmax64, w.ccnt, w.n, c.mu, c.m0, c.n1, c.n2, fabs(c.dt),
                      c.pf2, c.encounter_free);
   PairArgs a = pair_args(w, c);
-  hipLaunchKernelGGL(k_pair_part<KICK_INIT>, pair_grid(w), dim3(kPairThreads), 0, s, a,
+  hipLaunchKernelGGL(pair_kernel<KICK_INIT>(w), pair_grid(w), pair_block(w), 0, s, a,
                      (const double4*)w.xm, (const double*)w.thr, (const double*)w.tmax64);
   hipLaunchKernelGGL(k_pair_finish<KICK_INIT>, dim3(ceil_div(w.n, kFinThreads)), dim3(kFinThreads),
                      0, s, a, (const double4*)w.xm);
@@ -2092,7 +2114,7 @@ hipError_t massive_accel(const MassiveWs& w, const StepConsts& c, const double4*
                          double* acc, hipStream_t s) {
   PairArgs a = pair_args(w, c);
   a.acc_out = acc;
-  hipLaunchKernelGGL(k_pair_part<KICK_ACC>, pair_grid(w), dim3(kPairThreads), 0, s, a, x,
+  hipLaunchKernelGGL(pair_kernel<KICK_ACC>(w), pair_grid(w), pair_block(w), 0, s, a, x,
                      (const double*)w.thr, (const double*)w.tmax64);
   hipLaunchKernelGGL(k_pair_finish<KICK_ACC>, dim3(ceil_div(w.n, kFinThreads)), dim3(kFinThreads),
                      0, s, a, x);
@@ -2228,7 +2250,8 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
   }
 
   PairArgs a = pair_args(w, c);
-  STEP_LAUNCH(4, k_pair_part<KICK_CLOSE>, pair_grid(w), dim3(kPairThreads), a,
+  const auto kpair = pair_kernel<KICK_CLOSE>(w);
+  STEP_LAUNCH(4, kpair, pair_grid(w), pair_block(w), a,
               (const double4*)w.xm, (const double*)w.thr, (const double*)w.tmax64);
   STEP_LAUNCH(5, k_pair_finish<KICK_CLOSE>, dim3(ceil_div(w.n, kFinThreads)), dim3(kFinThreads), a,
               (const double4*)w.xm);
@@ -2271,15 +2294,16 @@ hipError_t accel_run(const MassiveWs& w, const StepConsts& c, const double* m, c
 // and candidate counts of up to kNoAllocBodies bodies (116 bytes per padded
 // body), the 64-body chunks' largest thresholds and the pair kernel's partial sums
 // (6 doubles x splits x padded bodies, splits x padded bodies <=
-// kPairTarget): 2.7 MB.  Each GPU holds its own copy until the process ends;
+// kPairTargetBig, the pair kernel's shape being the workspace path's): 5.0 MB.  Each GPU holds its own copy until the process ends;
 // every call on a GPU uses that GPU's copy, so calls that overlap on one GPU
 // race.  Every byte a call reads is written earlier in the same call.
 constexpr int kNoAllocBodies = kAccelNoAllocMax;
 static_assert(kNoAllocBodies % 256 == 0, "bodies are padded to multiples of 256");
-static_assert(kNoAllocBodies <= kPairTarget, "partial sums sized by kPairTarget");
+static_assert(kNoAllocBodies <= kPairTarget && kPairTarget <= kPairTargetBig,
+              "partial sums sized by kPairTargetBig");
 constexpr size_t kNoAllocBytes =
     (size_t)kNoAllocBodies * (3 * sizeof(double4) + 2 * sizeof(double) + sizeof(int)) +
-    (size_t)kNoAllocBodies / 64 * sizeof(double) + (size_t)kPairTarget * 6 * sizeof(double);
+    (size_t)kNoAllocBodies / 64 * sizeof(double) + (size_t)kPairTargetBig * 6 * sizeof(double);
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
@@ -2319,7 +2343,7 @@ hipError_t accel_noalloc_run(const StepConsts& c, int n, const double* m, const 
   MassiveWs w{};
   w.n = n;
   w.np = ceil_div(n, 256) * 256;
-  w.njs = pair_splits(w.np);
+  pair_shape(w.np, &w.pw, &w.njs);  // as the workspace path, so both give the same bits
   w.nblk = ceil_div(n, kVecBlock);
   const size_t np = (size_t)w.np;
   char* q = static_cast<char*>(base);
