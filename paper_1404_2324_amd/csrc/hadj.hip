@@ -18,7 +18,9 @@
 // state with its own radii.
 //
 // One wave per system, one lane per body; partner data by lane reads in
-// wave-uniform loops.  Forward: the state and the candidate set every k
+// wave-uniform loops.  BS of a group of up to 8 members runs its columns
+// side by side (lane 8 c + q: column c of member slot q), larger groups one
+// column after another.  Forward: the state and the candidate set every k
 // steps.  Backward, per segment from the last: the segment replayed keeping
 // each step's start (the tape), then per step in reverse the step
 // recomputed and its pieces reversed:
