@@ -371,6 +371,8 @@ def main():
                     help="steps of the 16-body energy-error run reported under extra (0: skip)")
     ap.add_argument("--adj-steps", type=int, default=1000,
                     help="steps of the 1024 x 8 adjoint run reported under extra (0: skip)")
+    ap.add_argument("--energy-long-steps", type=int, default=10000,
+                    help="steps of the 2048-body disk after the timing, |dE/E| every 1000 (0: skip)")
     ap.add_argument("--hadj-steps", type=int, default=64,
                     help="steps of the 1024 x 8 hybrid (encounter) adjoint run under extra (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -391,6 +393,7 @@ def main():
     sim = G.Simulation(s.m, s.x, s.u, gp, coords="helio")
     n = sim.n
     stream = torch.cuda.current_stream()
+    E_init, L_init = sim.energy()
 
     sim.step(args.warmup)
     sim.check()
@@ -415,6 +418,27 @@ def main():
     # events recorded by the dispatches, on the context's stream)
     split = sim.step_kernel_us(min(args.kick_steps, 512))
     tot_us = sum(split.values())
+    # energy and angular momentum of the disk over a longer run (outside the
+    # timed region): |dE/E| (Sec. 4.1) every 1000 steps
+    energy_long = None
+    if args.energy_long_steps > 0:
+        done = args.warmup + args.steps + min(args.kick_steps, 512)
+        errs, failure = [], None
+        try:
+            for _ in range(args.energy_long_steps // 1000):
+                sim.step(1000)
+                sim.check()
+                E, L = sim.energy()
+                done += 1000
+                errs.append(abs((E - E_init) / E_init))
+        except G.GengaError as err:  # reported, not hidden: the run stops there
+            failure = str(err)
+        _, L = sim.energy()
+        energy_long = {"workload": "planetesimals_n2048", "steps": done,
+                       "dE_rel_every_1000": [float(e) for e in errs],
+                       "dE_rel_max": float(max(errs)) if errs else None,
+                       "L_rel_drift": float(np.linalg.norm(L - L_init) / np.linalg.norm(L_init)),
+                       "enc_total": sim.stats()["enc_total"], "failure": failure}
     dominant = max(split, key=split.get)
     kick_us = split["k_pair_part"]
     kick_s = kick_us * 1e-6
@@ -433,6 +457,8 @@ def main():
         simb.close()
 
     extra = {}
+    if energy_long is not None:
+        extra["energy_n2048"] = energy_long
     if args.energy_steps > 0:
         extra["energy"] = energy_measure(G, W, torch, args.energy_steps)
     if args.tp_steps > 0:
