@@ -215,3 +215,37 @@ def test_hybrid_ragged_systems_and_groups_over_eight():
             _say("system", s, "size", sizes[s], "d/d" + what, err)
             assert err <= 1e-9, (s, what, err)
     assert big > 8
+
+
+def test_hybrid_small_systems():
+    """Systems of 1, 2 (one encounter pair) and 5 planets: the single body
+    (no pairs: the Kepler drift and Sun kicks alone), the pair's BS, and a
+    group of five, each against the oracle's full gradient."""
+    p = O.params()
+    parts = ((1, 30), (2, 38), (5, 30))
+    ms, xs, vs = [], [], []
+    for npl, seed in parts:
+        m, x, u = W.encounter_systems(nsys=1, nplanets=npl, seed_index=seed)
+        ms.append(m[0])
+        xs.append(x[0])
+        vs.append(O.helio_to_dem(p, m[0], u[0]))
+    sizes = [q[0] for q in parts]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    m, x, v = np.concatenate(ms), np.concatenate(xs), np.concatenate(vs)
+    T, K = 12, 4
+    rng = np.random.default_rng(66)
+    gxT, gvT = rng.standard_normal(x.shape), rng.standard_normal(v.shape)
+    sim = _sim(off, np.ones(len(sizes)), m, x, v)
+    sim.adj_forward(T, K)
+    xT, vT = [t.cpu().numpy() for t in sim.state("dem")]
+    gx0, gv0, gm = [t.cpu().numpy() for t in sim.adj_backward(gxT, gvT)]
+    sim.check()
+    for s in range(len(sizes)):
+        a, b = off[s], off[s + 1]
+        ox, ov, _, _, st = O.cs_massive(p, m[a:b], x[a:b], v[a:b], None, None, None, T)
+        assert _rel(xT[a:b], ox) <= 1e-12 and _rel(vT[a:b], ov) <= 1e-12, s
+        cx, cv, cm = O.cs_gradient(p, m[a:b], x[a:b], v[a:b], T, gxT[a:b], gvT[a:b])
+        for g, o, what in ((gx0[a:b], cx, "x"), (gv0[a:b], cv, "v"), (gm[a:b], cm, "m")):
+            err = _rel(g, o)
+            _say("system of", sizes[s], "encounters", st["enc_total"], "d/d" + what, err)
+            assert err <= 1e-9, (s, what, err)
