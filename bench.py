@@ -371,6 +371,9 @@ def main():
                     help="steps of the 16-body energy-error run reported under extra (0: skip)")
     ap.add_argument("--adj-steps", type=int, default=1000,
                     help="steps of the 1024 x 8 adjoint run reported under extra (0: skip)")
+    ap.add_argument("--hist-steps", type=int, default=100,
+                    help="steps of the 2048-body disk after the timing for the candidate, "
+                         "encounter and group-size statistics (0: skip)")
     ap.add_argument("--energy-long-steps", type=int, default=10000,
                     help="steps of the 2048-body disk after the timing, |dE/E| every 1000 (0: skip)")
     ap.add_argument("--hadj-steps", type=int, default=64,
@@ -418,11 +421,45 @@ def main():
     # events recorded by the dispatches, on the context's stream)
     split = sim.step_kernel_us(min(args.kick_steps, 512))
     tot_us = sum(split.values())
+    # candidates, encounters and group sizes over 100 further steps, one at a
+    # time (outside the timed region): the per-step counts and the histogram
+    # of group sizes (connected components of each step's encounter pairs)
+    per_step = None
+    if args.hist_steps > 0:
+        nc, ne, sizes = [], [], {}
+        for _ in range(args.hist_steps):
+            sim.step(1)
+            ij = sim.encounters()[0]
+            nc.append(sim.stats()["n_cand"])
+            ne.append(len(ij))
+            parent = {}
+
+            def root(a):
+                while parent.setdefault(a, a) != a:
+                    parent[a] = parent[parent[a]]
+                    a = parent[a]
+                return a
+
+            for i, j in ij:
+                ri, rj = root(int(i)), root(int(j))
+                if ri != rj:
+                    parent[max(ri, rj)] = min(ri, rj)
+            comp = {}
+            for b in parent:
+                r = root(b)
+                comp[r] = comp.get(r, 0) + 1
+            for c in comp.values():
+                sizes[c] = sizes.get(c, 0) + 1
+        sim.check()
+        per_step = {"steps": args.hist_steps,
+                    "candidates_mean": float(np.mean(nc)), "candidates_max": int(max(nc)),
+                    "encounters_mean": float(np.mean(ne)), "encounters_max": int(max(ne)),
+                    "group_size_hist": {str(k): sizes[k] for k in sorted(sizes)}}
     # energy and angular momentum of the disk over a longer run (outside the
     # timed region): |dE/E| (Sec. 4.1) every 1000 steps
     energy_long = None
     if args.energy_long_steps > 0:
-        done = args.warmup + args.steps + min(args.kick_steps, 512)
+        done = args.warmup + args.steps + min(args.kick_steps, 512) + max(args.hist_steps, 0)
         errs, failure = [], None
         try:
             for _ in range(args.energy_long_steps // 1000):
@@ -457,6 +494,8 @@ def main():
         simb.close()
 
     extra = {}
+    if per_step is not None:
+        extra["encounters_n2048"] = per_step
     if energy_long is not None:
         extra["energy_n2048"] = energy_long
     if args.energy_steps > 0:
