@@ -575,19 +575,13 @@ __device__ __forceinline__ int bs_integrate_par(int sz, double y[6], double H,
   return 0;
 }
 
-// One group of sz members over H, P the smallest of 2, 4, 8 not below sz
-// (so P/2 < sz <= P; the pair terms rely on it).  Every lane of member b =
-// par_memb<P>(lane) holds the member's start state in y (dummy state for
-// b >= sz); mm[] and mrc[] (any memory) give every member's mass and critical
-// radius.  On return y holds member b's state after H in each of its lanes
-// (par_lane<P>(0, 0, b) among them).
-template <int P, bool TP>
-__device__ __forceinline__ int bs_group(int sz, double y[6], const double* mm,
-                                        const double* mrc, double H, double G,
-                                        double Gm0, double tol, int D,
-                                        long long* nsub, double R2 = -1.0,
-                                        int* cb = nullptr, long long* cpos = nullptr,
-                                        const double* mR = nullptr) {
+// The per-lane view of a group of sz members (P the smallest of 2, 4, 8
+// not below sz) that the force evaluations use: each partner's lane, mass,
+// critical radius and changeover constants, and the member whose reaction
+// this lane receives; mm[] and mrc[] (any memory) hold every member's mass
+// and critical radius.
+template <int P>
+__device__ __forceinline__ ParBody<P> par_body(int sz, const double* mm, const double* mrc) {
   const int lane = threadIdx.x & 63;
   const int b = par_memb<P>(lane);
   const double rcb = b < sz ? mrc[b] : 0.0;
@@ -612,6 +606,23 @@ __device__ __forceinline__ int bs_group(int sz, double y[6], const double* mm,
       Q.near2[q] = Q.rcij[q] > 0.0 ? Q.rcij[q] * Q.rcij[q] * (1.0 + 1e-12) : 0.0;
     }
   }
+  return Q;
+}
+
+// One group of sz members over H, P the smallest of 2, 4, 8 not below sz
+// (so P/2 < sz <= P; the pair terms rely on it).  Every lane of member b =
+// par_memb<P>(lane) holds the member's start state in y (dummy state for
+// b >= sz); mm[] and mrc[] (any memory) give every member's mass and critical
+// radius.  On return y holds member b's state after H in each of its lanes
+// (par_lane<P>(0, 0, b) among them).
+template <int P, bool TP>
+__device__ __forceinline__ int bs_group(int sz, double y[6], const double* mm,
+                                        const double* mrc, double H, double G,
+                                        double Gm0, double tol, int D,
+                                        long long* nsub, double R2 = -1.0,
+                                        int* cb = nullptr, long long* cpos = nullptr,
+                                        const double* mR = nullptr) {
+  const ParBody<P> Q = par_body<P>(sz, mm, mrc);
   return bs_integrate_par<P, TP>(sz, y, H, Q, G, Gm0, tol, D, nsub, R2, cb, cpos, mR);
 }
 

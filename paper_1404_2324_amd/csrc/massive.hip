@@ -955,6 +955,20 @@ struct BsArgs {
   int max_depth, coll, ev_cap;
 };
 
+// k_bs runs kBsWaves waves per workgroup.  Groups of up to kBsPar members
+// without collisions take all of them (speculative depths spread over the
+// waves); every other group is integrated by wave 0 alone while the others
+// wait at the group's closing barrier.  The lanes of that one wave order
+// their LDS and global accesses with wsync: the release and acquire fences
+// of a workgroup barrier around a wave barrier, without the workgroup-wide
+// s_barrier the waiting waves would have to join.
+constexpr int kBsWaves = 4;
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // ---- groups of more than 64 members ------------------------------------------
 // One wave integrates the group with the BS scheme of the smaller paths (the
 // same column sequence, Aitken-Neville tableau, error norm and halving), each
@@ -1008,7 +1022,7 @@ __device__ __forceinline__ void big_publish(const BsArgs& a, const int* mem, int
     const double* r = a.big + (size_t)id * kBigRec + off;
     a.bpos[id] = make_double4(r[0], r[1], r[2], a.xm[id].w);
   }
-  __syncthreads();
+  wsync();
 }
 
 // One attempt over H (columns n_k = 2k, k = 1..8, accepted at the first
@@ -1036,7 +1050,7 @@ __device__ bool big_attempt(const BsArgs& a, const int* mem, int sz, double H) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) r[kBigZc + c] = r[kBigZp + c] + hs * d[c];
     }
-    __syncthreads();
+    wsync();
     big_publish(a, mem, sz, kBigZc);
     // z_{s+1} = z_{s-1} + 2 hs f(z_s), s = 1 .. nk - 1
     for (int st = 1; st < nk; ++st) {
@@ -1056,7 +1070,7 @@ __device__ bool big_attempt(const BsArgs& a, const int* mem, int sz, double H) {
           r[kBigZc + c] = t;
         }
       }
-      __syncthreads();
+      wsync();
       big_publish(a, mem, sz, kBigZc);
     }
     // T_k0 = (z_{n-1} + z_n + hs f(z_n)) / 2, then the tableau row
@@ -1089,14 +1103,14 @@ __device__ bool big_attempt(const BsArgs& a, const int* mem, int sz, double H) {
                                    relerr3(R + 6 * k + 3, R + 6 * (k - 1) + 3)));
     }
     e = wave_max(e);
-    __syncthreads();
+    wsync();
     if (k >= 1 && e <= a.tol) {
       for (int m = threadIdx.x; m < sz; m += 64) {
         double* r = a.big + (size_t)mem[m] * kBigRec;
 #pragma unroll
         for (int c = 0; c < 6; ++c) r[kBigY0 + c] = r[kBigR + 6 * k + c];
       }
-      __syncthreads();
+      wsync();
       return true;
     }
   }
@@ -1118,7 +1132,7 @@ __device__ int bs_group_big(const BsArgs& a, int o, int sz, long long* nsub, dou
     for (int q = 0; q < sz; ++q) rank += gm[q] < id ? 1 : 0;
     mem[rank] = id;
   }
-  __syncthreads();
+  wsync();
   for (int m = lane; m < sz; m += 64) {
     const int id = mem[m];
     const double4 p = a.xpre[id], q = a.vpre[id];
@@ -1130,7 +1144,7 @@ __device__ int bs_group_big(const BsArgs& a, int o, int sz, long long* nsub, dou
     r[kBigY0 + 4] = q.y;
     r[kBigY0 + 5] = q.z;
   }
-  __syncthreads();
+  wsync();
   const int D = a.max_depth;
   const long long total = 1ll << D;
   long long pos = 0;
@@ -1167,14 +1181,81 @@ __device__ int bs_group_big(const BsArgs& a, int o, int sz, long long* nsub, dou
   return status;
 }
 
-// Main-mode group of sz <= P members (sorted indices in mem, masses and radii
-// in mm, mrc): start from the pre-drift copy, integrate, write back; returns
-// the BS status and, per member lane, its momentum change m (v_BS - v_drift).
+// Depth-slot exchange of the waves integrating one group.
+struct BsXchg {
+  int gs[kBsWaves];         // each wave's first accepted slot (INT_MAX: none)
+  double y[kBsPar][6];      // the winning slot's state per member
+};
+
+// Binary refinement over [0, H] of a group of sz <= P members by the
+// kBsWaves waves of the workgroup: in each round wave w tries the depths
+// d + w S .. d + w S + S - 1 (S = kBsPar / P per wave, as bs_round_par lays
+// them out), so that kBsWaves S halvings of the substep are attempted at
+// once from the same start.  The first accepted slot in sequential order
+// wins; its state reaches every wave through LDS, and the waves, holding the
+// same state, position and depth, go on together.  The substeps taken and
+// their results are those of the one-wave bs_integrate_par.
+template <int P>
+__device__ __forceinline__ int bs_integrate_mw(int sz, double y[6], double H,
+                                               const ParBody<P>& Q, double G, double Gm0,
+                                               double tol, int D, long long* nsub, BsXchg& X) {
+  constexpr int S = kBsPar / P;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int b = par_memb<P>(lane);
+  long long pos = 0;
+  const long long total = 1ll << D;
+  int d = 0, attempts = 0;
+  while (pos < total) {
+    if (++attempts > kBsMaxAttempts) return -1;
+    const int smax = min(kBsWaves * S, D - d + 1);  // never beyond the depth limit
+    double yt[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) yt[q] = y[q];
+    int gs = INT_MAX;
+    if (wave * S < smax) {
+      const int sa = bs_round_par<P, false>(sz, yt, ldexp(H, -(d + wave * S)), Q, G, Gm0, tol);
+      if (sa >= 0 && wave * S + sa < smax) gs = wave * S + sa;
+    }
+    if (lane == 0) X.gs[wave] = gs;
+    __syncthreads();
+    int best = X.gs[0];
+#pragma unroll
+    for (int w = 1; w < kBsWaves; ++w) best = min(best, X.gs[w]);
+    if (best != INT_MAX) {
+      if (wave == best / S && lane == par_lane<P>(0, 0, b)) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) X.y[b][q] = yt[q];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 6; ++q) y[q] = X.y[b][q];
+      d += best;
+      ++*nsub;
+      pos += 1ll << (D - d);
+      while (d > 0 && (pos % (1ll << (D - d + 1))) == 0) --d;
+    } else {
+      d += smax;
+    }
+    // X is written again only after every wave has read it
+    __syncthreads();
+    if (d > D) return -1;
+  }
+  return 0;
+}
+
+// Main-mode group of sz <= P members without collisions (sorted indices in
+// mem; masses and radii staged in mm, mrc), on all waves of the workgroup:
+// start from the pre-drift copy, integrate, wave 0 writes back; returns the
+// BS status and, in wave 0, per member lane, its momentum change
+// m (v_BS - v_drift).
 template <int P>
 __device__ __forceinline__ int bs_member_group(const BsArgs& a, int sz, const int* mem,
-                                               double* mm, double* mrc, long long* nsub,
-                                               double& dpx, double& dpy, double& dpz) {
+                                               double* mm, double* mrc, BsXchg& X,
+                                               long long* nsub, double& dpx, double& dpy,
+                                               double& dpz) {
   const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b = par_memb<P>(lane);
   const int id = b < sz ? mem[b] : -1;
   // every load the group needs is issued at once: the members' masses and
@@ -1197,14 +1278,15 @@ __device__ __forceinline__ int bs_member_group(const BsArgs& a, int sz, const in
     y[4] = q.y;
     y[5] = q.z;
   }
-  if (ml >= 0) {
+  if (ml >= 0 && wave == 0) {
     mm[lane] = mw;
     mrc[lane] = rcw;
   }
   __syncthreads();
-  const int r = bs_group<P, false>(sz, y, mm, mrc, a.dt, a.G, a.Gm0, a.tol, a.max_depth, nsub);
+  const ParBody<P> Q = par_body<P>(sz, mm, mrc);
+  const int r = bs_integrate_mw<P>(sz, y, a.dt, Q, a.G, a.Gm0, a.tol, a.max_depth, nsub, X);
   dpx = dpy = dpz = 0.0;
-  if (lane == par_lane<P>(0, 0, b) && id >= 0) {  // one lane per member writes
+  if (wave == 0 && lane == par_lane<P>(0, 0, b) && id >= 0) {  // one lane per member writes
     const double m = mm[b];
     dpx = m * (y[3] - vo.x);
     dpy = m * (y[4] - vo.y);
@@ -1239,13 +1321,13 @@ __device__ __forceinline__ int coll_par(const BsArgs& a, int sz, double pre[6], 
     y[0] = 1.0;
     y[1] = y[2] = y[3] = y[4] = y[5] = 0.0;
   }
-  __syncthreads();
+  wsync();
   if (lane < sz) {
     mm[lane] = m;
     mrc[lane] = rc;
     mR[lane] = Rd;
   }
-  __syncthreads();
+  wsync();
   const int r = bs_group<P, false>(sz, y, mm, mrc, H, a.G, a.Gm0, a.tol, a.max_depth, nsub, -1.0,
                                    key, cpos, mR);
 #pragma unroll
@@ -1403,61 +1485,31 @@ __device__ int bs_group_coll(const BsArgs& a, int g, int sz, const int* mem, dou
   return status;
 }
 
-// One wave per encounter group (grid-stride over the device-side count):
-// members sorted ascending, state reset to the pre-drift copy, H_A integrated
-// over tau by BS, result written back.  Groups of up to 8 members take the
-// all-columns path with speculative depths, larger ones (up to 64) one lane
-// per member with the columns in sequence.
-__global__ __launch_bounds__(64) void k_bs(BsArgs a) {
-  __shared__ double R[kBsCols][6][64];
-  __shared__ int mem[64];
-  __shared__ double mm[kBsPar], mrc[kBsPar], mR[kBsPar];
-  const int lane = threadIdx.x;
-  if (a.st->flags & F_NMIN) return;  // the run stopped below nmin bodies
-  const int ng = __builtin_amdgcn_readfirstlane(a.st->ngroups);
-  long long nsub = 0;
-  for (int g = blockIdx.x; g < ng; g += gridDim.x) {
-    const int o = a.goff[g];
-    const int sz = a.goff[g + 1] - o;
-    if (a.coll && sz > kBsMaxGroup) {
-      // collisions are tested in groups of up to 64 members only
-      if (lane == 0) atomicOr(&a.st->flags, F_GROUP);
-      continue;
-    }
-    if (sz > kBsMaxGroup) {
-      double dpx, dpy, dpz;
-      const int r = bs_group_big(a, o, sz, &nsub, dpx, dpy, dpz);
-      if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
-      dpx = wave_sum(dpx);
-      dpy = wave_sum(dpy);
-      dpz = wave_sum(dpz);
-      if (lane == 0) {
-        a.dP[4 * g + 0] = dpx;
-        a.dP[4 * g + 1] = dpy;
-        a.dP[4 * g + 2] = dpz;
-        a.dP[4 * g + 3] = 0.0;
-      }
-      __syncthreads();
-      continue;
-    }
+// A group that wave 0 integrates alone (wave 0 only): members that can
+// collide, or more than kBsPar members (one lane per member; more than 64
+// in the per-body records).  Writes the group's momentum change and merger
+// energy to dP.
+__device__ __forceinline__ void bs_group_one(const BsArgs& a, int g, int o, int sz, int* mem,
+                                             double* mm, double* mrc, double* mR,
+                                             double (*R)[6][64], long long* nsub) {
+  const int lane = threadIdx.x & 63;
+  if (a.coll && sz > kBsMaxGroup) {
+    // collisions are tested in groups of up to 64 members only
+    if (lane == 0) atomicOr(&a.st->flags, F_GROUP);
+    return;
+  }
+  double dpx = 0.0, dpy = 0.0, dpz = 0.0, Ug = 0.0;
+  if (sz > kBsMaxGroup) {
+    const int r = bs_group_big(a, o, sz, nsub, dpx, dpy, dpz);
+    if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
+  } else {
     const int my = lane < sz ? a.gmem[o + lane] : INT_MAX;
     int rank = 0;
     for (int q = 0; q < sz; ++q) rank += (__builtin_amdgcn_readlane(my, q) < my) ? 1 : 0;
-    __syncthreads();
     if (lane < sz) mem[rank] = my;
-    __syncthreads();
-    double dpx = 0.0, dpy = 0.0, dpz = 0.0, Ug = 0.0;
+    wsync();
     if (a.coll) {
-      const int r = bs_group_coll(a, g, sz, mem, mm, mrc, mR, R, &nsub, dpx, dpy, dpz, Ug);
-      if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
-    } else if (sz <= kBsPar) {
-      int r;
-      if (sz <= 2)
-        r = bs_member_group<2>(a, sz, mem, mm, mrc, &nsub, dpx, dpy, dpz);
-      else if (sz <= 4)
-        r = bs_member_group<4>(a, sz, mem, mm, mrc, &nsub, dpx, dpy, dpz);
-      else
-        r = bs_member_group<8>(a, sz, mem, mm, mrc, &nsub, dpx, dpy, dpz);
+      const int r = bs_group_coll(a, g, sz, mem, mm, mrc, mR, R, nsub, dpx, dpy, dpz, Ug);
       if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
     } else {
       const int bb = lane < sz ? mem[lane] : -1;
@@ -1475,7 +1527,7 @@ __global__ __launch_bounds__(64) void k_bs(BsArgs a) {
         rc = a.rc[bb];
       }
       const int r = bs_integrate(sz, lane, y, a.dt, m, rc, a.G, a.Gm0, a.tol,
-                                 a.max_depth, R, &nsub);
+                                 a.max_depth, R, nsub);
       if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
       if (bb >= 0) {
         const double4 vo = a.vv[bb];
@@ -1486,19 +1538,73 @@ __global__ __launch_bounds__(64) void k_bs(BsArgs a) {
         a.vv[bb] = make_double4(y[3], y[4], y[5], 0.0);
       }
     }
-    // the group's momentum change for the second Sun kick (fixed lane order)
-    dpx = wave_sum(dpx);
-    dpy = wave_sum(dpy);
-    dpz = wave_sum(dpz);
-    if (lane == 0) {
-      a.dP[4 * g + 0] = dpx;
-      a.dP[4 * g + 1] = dpy;
-      a.dP[4 * g + 2] = dpz;
-      a.dP[4 * g + 3] = Ug;  // internal energy of the group's mergers
+  }
+  // the group's momentum change for the second Sun kick (fixed lane order)
+  dpx = wave_sum(dpx);
+  dpy = wave_sum(dpy);
+  dpz = wave_sum(dpz);
+  if (lane == 0) {
+    a.dP[4 * g + 0] = dpx;
+    a.dP[4 * g + 1] = dpy;
+    a.dP[4 * g + 2] = dpz;
+    a.dP[4 * g + 3] = Ug;  // internal energy of the group's mergers
+  }
+}
+
+// One workgroup of kBsWaves waves per encounter group (grid-stride over the
+// device-side count): members sorted ascending, state reset to the
+// pre-drift copy, H_A integrated over tau by BS, result written back.
+// Groups of up to 8 members take the all-columns path with speculative
+// depths over every wave; the others take wave 0 alone (one lane per
+// member with the columns in sequence, or the collision path).
+__global__ __launch_bounds__(64 * kBsWaves) void k_bs(BsArgs a) {
+  __shared__ double R[kBsCols][6][64];
+  __shared__ int mem[64];
+  __shared__ double mm[kBsPar], mrc[kBsPar], mR[kBsPar];
+  __shared__ BsXchg X;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (a.st->flags & F_NMIN) return;  // the run stopped below nmin bodies
+  const int ng = __builtin_amdgcn_readfirstlane(a.st->ngroups);
+  long long nsub = 0;
+  for (int g = blockIdx.x; g < ng; g += gridDim.x) {
+    const int o = a.goff[g];
+    const int sz = a.goff[g + 1] - o;
+    if (!a.coll && sz <= kBsPar) {
+      // every wave ranks the members; wave 0 writes them in order
+      const int my = lane < sz ? a.gmem[o + lane] : INT_MAX;
+      int rank = 0;
+      for (int q = 0; q < sz; ++q) rank += (__builtin_amdgcn_readlane(my, q) < my) ? 1 : 0;
+      if (wave == 0 && lane < sz) mem[rank] = my;
+      __syncthreads();
+      double dpx, dpy, dpz;
+      int r;
+      if (sz <= 2)
+        r = bs_member_group<2>(a, sz, mem, mm, mrc, X, &nsub, dpx, dpy, dpz);
+      else if (sz <= 4)
+        r = bs_member_group<4>(a, sz, mem, mm, mrc, X, &nsub, dpx, dpy, dpz);
+      else
+        r = bs_member_group<8>(a, sz, mem, mm, mrc, X, &nsub, dpx, dpy, dpz);
+      if (wave == 0) {
+        if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
+        // the group's momentum change for the second Sun kick (fixed lane order)
+        dpx = wave_sum(dpx);
+        dpy = wave_sum(dpy);
+        dpz = wave_sum(dpz);
+        if (lane == 0) {
+          a.dP[4 * g + 0] = dpx;
+          a.dP[4 * g + 1] = dpy;
+          a.dP[4 * g + 2] = dpz;
+          a.dP[4 * g + 3] = 0.0;
+        }
+      }
+    } else if (wave == 0) {
+      bs_group_one(a, g, o, sz, mem, mm, mrc, mR, R, &nsub);
     }
+    // the group's LDS (mem, mm, mrc, mR, R, X) is free for the next one
     __syncthreads();
   }
-  if (lane == 0 && nsub > 0) atomicAdd(&a.st->bs_sub, (unsigned long long)nsub);
+  if (threadIdx.x == 0 && nsub > 0) atomicAdd(&a.st->bs_sub, (unsigned long long)nsub);
 }
 
 // ---- bodies leaving the system (Sec. 3.2.7, 3.2.8, 3.4.6) ------------------
@@ -2222,7 +2328,7 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
     b.max_depth = c.bs_max_depth;
     b.coll = c.coll;
     b.ev_cap = w.ev_cap;
-    STEP_LAUNCH(3, k_bs, dim3(std::max(1, std::min(256, w.n / 2))), dim3(64), b);
+    STEP_LAUNCH(3, k_bs, dim3(std::max(1, std::min(256, w.n / 2))), dim3(64 * kBsWaves), b);
     if (c.phys) {
       // bodies that merged or crossed rcut / rcut_sun leave (not timed per
       // kernel: the measurement forms run without these limits)
