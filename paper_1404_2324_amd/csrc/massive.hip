@@ -10,7 +10,8 @@
 //   k_encounter    Hermite test of every candidate (Eqs. 10-12), ballot
 //                  compaction of the confirmed pairs
 //   k_group        equivalence classes of the pairs in LDS (App. A)
-//   k_bs           Bulirsch-Stoer integration of H_A per group, one wave each
+//   k_bs           Bulirsch-Stoer integration of H_A per group, one workgroup
+//                  of four waves each (speculative halving depths)
 //   k_pair_part    closing kick: all pairs and the prechecker, partial sums
 //                  per split of the partners
 //   k_pair_finish  per body: the splits added, the second Sun kick tau/2,
