@@ -482,6 +482,24 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
   __shared__ double sh[3 * (kVecBlock / 64)];
   __shared__ unsigned kh[kKepBins];  // this block's drifts by iteration count
   double tloc = kTiny;               // the lane's candidate threshold
+  const int i = blockIdx.x * kVecBlock + threadIdx.x;  // < np: every per-body array has np rows
+  // Every load that does not depend on the status word is issued before the
+  // word is read: the body's state, cached far sum and radius, its row count
+  // and the first kPre entries of its candidate row (entries past the count
+  // are read and dropped), this block's Kepler histogram row, and the
+  // running iteration maximum.
+  const double4 p0 = a.xs[i];
+  const double rc0 = a.rc_next[i];
+  const double4 af0 = a.afar[i];
+  const double4 v0 = a.vv[i];
+  const int cnt0 = a.ccnt[i];
+  const int* row = a.ctab + (size_t)i * a.cpb;
+  int r8[kPre];
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) r8[u] = u < a.cpb ? row[u] : INT_MAX;
+  const unsigned long long kh0 =
+      threadIdx.x < kKepBins ? a.khist[(size_t)blockIdx.x * kKepBins + threadIdx.x] : 0ull;
+  const int itmax0 = a.st->kep_itmax;
   if (threadIdx.x < kKepBins) kh[threadIdx.x] = 0u;
   __syncthreads();
   if (a.st->flags & F_NMIN) {
@@ -489,7 +507,6 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) a.st->stopped = 1;
     return;
   }
-  const int i = blockIdx.x * kVecBlock + threadIdx.x;
   const bool iv = i < a.st->nlive;
   const bool full = (__builtin_amdgcn_readfirstlane(a.st->ctl) & C_FULLKICK) != 0;
   const double Ps = a.h / a.m0;
@@ -497,8 +514,8 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
   double m = 0.0, kx = 0.0, ky = 0.0, kz = 0.0, dx = 0.0, dy = 0.0, dz = 0.0;
   int it = 0;
   if (iv) {
-    const double4 p = a.xs[i];
-    const double rci = a.rc_next[i];
+    const double4 p = p0;
+    const double rci = rc0;
     if (a.xstart) a.xstart[i] = p;
     double ax = 0.0, ay = 0.0, az = 0.0;
     if (full) {
@@ -508,9 +525,8 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
       ay *= a.G;
       az *= a.G;
     } else {
-      const double4 af = a.afar[i];
-      const int cnt = min(a.ccnt[i], a.cpb);
-      const int* row = a.ctab + (size_t)i * a.cpb;
+      const double4 af = af0;
+      const int cnt = min(cnt0, a.cpb);
       double cx = 0.0, cy = 0.0, cz = 0.0;
       // Partners are summed in ascending order (deterministic).  Rows of up
       // to 8 (nearly all), 16 or kRowSort partners are sorted by a bitonic
@@ -520,7 +536,7 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
       if (cnt <= kPre) {
         int jj[kPre];
 #pragma unroll
-        for (int u = 0; u < kPre; ++u) jj[u] = u < cnt ? row[u] : INT_MAX;
+        for (int u = 0; u < kPre; ++u) jj[u] = u < cnt ? r8[u] : INT_MAX;
         bitonic_sort(jj);
         sum_partners<kPre>(jj, 0, cnt, i, p, rci, a, cx, cy, cz);
       } else if (cnt <= 2 * kPre) {
@@ -557,7 +573,7 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
       ay = af.y + a.G * cy;
       az = af.z + a.G * cz;
     }
-    double4 v = a.vv[i];
+    double4 v = v0;
     v.x += a.h * ax;
     v.y += a.h * ay;
     v.z += a.h * az;
@@ -587,13 +603,13 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
   // the running maximum rarely grows: read it first, so that waves do not
   // queue on one address every step
   const int itm = wave_max_i(abs(it));
-  if ((threadIdx.x & 63) == 0 && itm > a.st->kep_itmax) atomicMax(&a.st->kep_itmax, itm);
+  if ((threadIdx.x & 63) == 0 && itm > itmax0) atomicMax(&a.st->kep_itmax, itm);
   double Px = m * kx, Py = m * ky, Pz = m * kz;
   block_sum3<kVecBlock>(Px, Py, Pz, sh);
   double Qx = m * dx, Qy = m * dy, Qz = m * dz;
   block_sum3<kVecBlock>(Qx, Qy, Qz, sh);  // its barriers also order kh
   if (threadIdx.x < kKepBins)
-    a.khist[(size_t)blockIdx.x * kKepBins + threadIdx.x] += kh[threadIdx.x];
+    a.khist[(size_t)blockIdx.x * kKepBins + threadIdx.x] = kh0 + kh[threadIdx.x];
   chunk_tmax(tloc, i & ~63, a.tmax64);
   if (threadIdx.x == 0) {
     a.partP[4 * blockIdx.x + 0] = Px;
