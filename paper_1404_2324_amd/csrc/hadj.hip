@@ -337,17 +337,24 @@ __device__ __forceinline__ int bs_attempt(const HArgs& a, const Sys& S, unsigned
 }
 
 // ---- column-parallel BS for groups of up to 8 members ----------------------
-// Lane L = 8 c + q holds column c (2 (c + 1) substeps) of member slot q (the
-// q-th member in body order), so the columns of an attempt run side by side:
-// an attempt takes as many derivative rounds as its longest column (17)
-// instead of the sum over its columns (up to 80).  The Aitken-Neville
-// tableau moves down the columns by lane reads from the column below (lane
-// - 8).  Every sum is formed in the order of the one-column-at-a-time form
-// above, so both give the same bits.
+// Lane L = 8 c + l holds column c (2 (c + 1) substeps); inside the column's
+// eight lanes, l = w s + q: member slot q (the q-th member in body order) of
+// depth slot s, w the smallest of 2, 4, 8 not below the group size.  Depth
+// slot s attempts the substep of length H / 2^s from the same start (the
+// attempts the sequential refinement makes after s failures), so a group of
+// two tries four halvings at once and one of three or four two; the first
+// slot in sequential order with an accepted column is taken.  The columns
+// of an attempt run side by side: it takes as many derivative rounds as its
+// longest column (17) instead of the sum over its columns (up to 80).  The
+// Aitken-Neville tableau moves down the columns by lane reads from the
+// column below (lane - 8).  Every sum is formed in the order of the
+// one-column-at-a-time form above, so both give the same bits.  The reverse
+// pass uses the layout with one depth slot (w = 8).
 constexpr int kHPar = 8;
 
 struct Par {
   int c, q, sz, src;             // column, member slot, group size, body lane of the slot
+  int s, w, ns;                  // depth slot, slot width, depth slots per attempt
   bool on;                       // the slot holds a member
   double m, rc;                  // its mass and radius
   double pm[kHPar], prc[kHPar];  // every slot's mass and radius
@@ -358,11 +365,15 @@ __device__ __forceinline__ int nth_bit64(unsigned long long M, int b) {
   return __builtin_ctzll(M);
 }
 
-__device__ __forceinline__ Par par_of(const Sys& S, unsigned long long M, double rc) {
+__device__ __forceinline__ Par par_of(const Sys& S, unsigned long long M, double rc,
+                                      bool depths = false) {
   Par P;
   P.c = S.lane >> 3;
-  P.q = S.lane & 7;
   P.sz = __builtin_popcountll(M);
+  P.w = !depths || P.sz > 4 ? kHPar : P.sz > 2 ? 4 : 2;
+  P.ns = kHPar / P.w;
+  P.s = (S.lane & 7) / P.w;
+  P.q = (S.lane & 7) - P.s * P.w;
   P.on = P.q < P.sz;
   P.src = P.on ? nth_bit64(M, P.q) : 0;
   P.m = __shfl(S.m, P.src, 64);
@@ -383,9 +394,10 @@ __device__ __forceinline__ void ha_deriv_par(const HArgs& a, const Sys& S, const
   const double r = sqrt(r2);
   const double fs = -S.Gm0 / (r2 * r);
   double a0 = fs * y[0], a1 = fs * y[1], a2 = fs * y[2];
-  const int base = S.lane & ~7;
+  const int base = (S.lane & ~7) + P.s * P.w;
 #pragma unroll
   for (int t = 0; t < kHPar; ++t) {
+    if (t >= P.w) break;  // the slot's lanes only (wave-uniform)
     const double xj = __shfl(y[0], base + t, 64), yj = __shfl(y[1], base + t, 64),
                  zj = __shfl(y[2], base + t, 64);
     if (t < P.sz && P.on && t != P.q) {
@@ -416,7 +428,7 @@ __device__ __forceinline__ void gragg_par(const HArgs& a, const Sys& S, const Pa
                                           const double y0[6], double H, double out[6],
                                           bool keep) {
   const int nsub = 2 * (P.c + 1);
-  const double hs = H / nsub;
+  const double hs = ldexp(H, -P.s) / nsub;  // the lane's depth slot (exact scaling)
   double d[6], ym[6], yn[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
@@ -451,12 +463,15 @@ __device__ __forceinline__ void gragg_par(const HArgs& a, const Sys& S, const Pa
   }
 }
 
-// bs_attempt with the columns side by side: y holds the members' state in
-// their body lanes; the accepted column (>= 1) with its value in yout (body
-// lanes of members), or -1.
+// bs_attempt with the columns side by side and P.ns depth slots (slots from
+// smax on are past the depth limit and not taken): y holds the members'
+// state in their body lanes; the accepted column (>= 1) of the first slot
+// that has one, its slot in *sa and its value in yout (body lanes of
+// members), or -1.
 __device__ __forceinline__ int bs_attempt_par(const HArgs& a, const Sys& S,
                                               unsigned long long M, const Par& P,
-                                              const double y[6], double H, double yout[6]) {
+                                              const double y[6], double H, double yout[6],
+                                              int smax, int* sa) {
   double y0[6], T[6], Td[6], Ts[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) y0[c] = __shfl(y[c], P.src, 64);
@@ -486,16 +501,25 @@ __device__ __forceinline__ int bs_attempt_par(const HArgs& a, const Sys& S,
   }
   double err = 0.0;
   if (P.on && P.c >= 1) err = fmax(vrel3(&Td[0], &Ts[0]), vrel3(&Td[3], &Ts[3]));
+  // the largest error over the slot's members (its w adjacent lanes)
   err = fmax(err, __shfl_xor(err, 1, 64));
-  err = fmax(err, __shfl_xor(err, 2, 64));
-  err = fmax(err, __shfl_xor(err, 4, 64));
+  if (P.w >= 4) err = fmax(err, __shfl_xor(err, 2, 64));
+  if (P.w >= 8) err = fmax(err, __shfl_xor(err, 4, 64));
   const unsigned long long ok =
-      __builtin_amdgcn_ballot_w64(P.q == 0 && P.c >= 1 && err <= a.bs_tol);
+      __builtin_amdgcn_ballot_w64(P.q == 0 && P.c >= 1 && P.s < smax && err <= a.bs_tol);
   if (ok == 0ull) return -1;
-  const int k = __builtin_ctzll(ok) >> 3;
+  // the first slot with an accepted column: slot s leads at lanes 8 c + w s
+  int s = 0;
+  unsigned long long oks = 0ull;
+  for (; s < P.ns; ++s) {
+    oks = ok & (0x0101010101010101ull << (P.w * s));
+    if (oks) break;
+  }
+  const int k = __builtin_ctzll(oks) >> 3;
+  *sa = s;
   const int qi = __builtin_popcountll(M & ((1ull << S.lane) - 1ull));  // the body lane's slot
 #pragma unroll
-  for (int c = 0; c < 6; ++c) yout[c] = __shfl(Td[c], 8 * k + (qi & 7), 64);
+  for (int c = 0; c < 6; ++c) yout[c] = __shfl(Td[c], 8 * k + ((P.w * s + qi) & 7), 64);
   return k;
 }
 
@@ -507,17 +531,22 @@ __device__ __forceinline__ int bs_attempt_par(const HArgs& a, const Sys& S,
 template <bool REC>
 __device__ __forceinline__ int bs_group(const HArgs& a, const Sys& S, unsigned long long M, bool mem, double rc,
                         double y[6], double* lh, int* lk, int* nleaf) {
-  const Par P = par_of(S, M, rc);
+  const Par P = par_of(S, M, rc, true);
   const int D = a.bs_depth;
   const int64_t total = (int64_t)1 << D;
   int64_t pos = 0;
   int d = 0, nl = 0;
   while (pos < total) {
-    const double hh = ldexp(a.dt, -d);
     double yn[6];
-    const int k = P.sz <= kHPar ? bs_attempt_par(a, S, M, P, y, hh, yn)
-                                : bs_attempt(a, S, M, mem, rc, y, hh, yn);
+    int k, sa = 0;
+    const int smax = P.sz <= kHPar ? min(P.ns, D - d + 1) : 1;  // depths tried at once
+    if (P.sz <= kHPar)
+      k = bs_attempt_par(a, S, M, P, y, ldexp(a.dt, -d), yn, smax, &sa);
+    else
+      k = bs_attempt(a, S, M, mem, rc, y, ldexp(a.dt, -d), yn);
     if (k >= 1) {
+      d += sa;
+      const double hh = ldexp(a.dt, -d);  // the accepted substep's length
       if (REC) {
         if (nl < kHLeaf) {
 #pragma unroll
@@ -536,7 +565,7 @@ __device__ __forceinline__ int bs_group(const HArgs& a, const Sys& S, unsigned l
       pos += (int64_t)1 << (D - d);
       while (d > 0 && (pos % ((int64_t)1 << (D - d + 1))) == 0) --d;
     } else {
-      ++d;
+      d += smax;
       if (d > D) {
         if (nleaf) *nleaf = nl;
         return -1;
