@@ -349,7 +349,7 @@ __device__ __forceinline__ int bs_attempt(const HArgs& a, const Sys& S, unsigned
 // Aitken-Neville tableau moves down the columns by lane reads from the
 // column below (lane - 8).  Every sum is formed in the order of the
 // one-column-at-a-time form above, so both give the same bits.  The reverse
-// pass uses the layout with one depth slot (w = 8).
+// pass uses one depth slot (lanes w .. 7 of a column idle).
 constexpr int kHPar = 8;
 
 struct Par {
@@ -370,9 +370,9 @@ __device__ __forceinline__ Par par_of(const Sys& S, unsigned long long M, double
   Par P;
   P.c = S.lane >> 3;
   P.sz = __builtin_popcountll(M);
-  P.w = !depths || P.sz > 4 ? kHPar : P.sz > 2 ? 4 : 2;
-  P.ns = kHPar / P.w;
-  P.s = (S.lane & 7) / P.w;
+  P.w = P.sz > 4 ? kHPar : P.sz > 2 ? 4 : 2;
+  P.ns = depths ? kHPar / P.w : 1;
+  P.s = depths ? (S.lane & 7) / P.w : 0;
   P.q = (S.lane & 7) - P.s * P.w;
   P.on = P.q < P.sz;
   P.src = P.on ? nth_bit64(M, P.q) : 0;
@@ -845,6 +845,7 @@ __device__ __forceinline__ void ha_vjp_par(const HArgs& a, const Sys& S, const P
   const int base = S.lane & ~7;
 #pragma unroll
   for (int t = 0; t < kHPar; ++t) {
+    if (t >= P.w) break;  // the group's lanes only (wave-uniform)
     const double xj = __shfl(z[0], base + t, 64), yj = __shfl(z[1], base + t, 64),
                  zj = __shfl(z[2], base + t, 64);
     const double wx = __shfl(w[0], base + t, 64), wy = __shfl(w[1], base + t, 64),
