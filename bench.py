@@ -550,8 +550,9 @@ def main():
             "us": split,
             "share": {k: v / tot_us for k, v in split.items()},
             "dominant": dominant,
-            "dominant_bound": ("latency: one wave per encounter group, and the step waits "
-                               "for the group with the most sequential BS substeps"
+            "dominant_bound": ("latency: one workgroup per encounter group (its waves try "
+                               "several halving depths at once), and the step waits for the "
+                               "group with the most sequential BS substeps"
                                if dominant == "k_bs" else "see roofline"),
         },
         "stats": {k: st[k] for k in ("n_cand", "n_enc", "n_groups", "max_group",
