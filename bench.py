@@ -553,7 +553,7 @@ def main():
             "dominant_bound": ("latency: one workgroup per encounter group (its waves try "
                                "several halving depths at once), and the step waits for the "
                                "group with the most sequential BS substeps"
-                               if dominant == "k_bs" else "see roofline"),
+                               if dominant == "k_group_bs" else "see roofline"),
         },
         "stats": {k: st[k] for k in ("n_cand", "n_enc", "n_groups", "max_group",
                                       "kepler_iter_max", "bs_substeps", "enc_total",

@@ -201,18 +201,18 @@ int genga_step(genga_ctx *ctx, int64_t nsteps);
 int genga_step_profiled(genga_ctx *ctx, int64_t nsteps, double *h_kick_us);
 
 /* Number of kernels of one main-mode step, and their order. */
-#define GENGA_STEP_KERNELS 6
+#define GENGA_STEP_KERNELS 5
 /* Run nsteps (1..512) main-mode steps (in test-particle mode followed by the
  * particle kernels, untimed) with a HIP event pair around every kernel of
  * the step, launched so that the events take the dispatch's own start and
  * end timestamps.  h_us[GENGA_STEP_KERNELS] (host, caller-owned) receives
  * each kernel's average duration in microseconds, in launch order: opening
  * kick with Sun kick and Kepler drift, encounter search (Eqs. 10-12),
- * grouping (App. A), Bulirsch-Stoer of the groups (Sec. 3.2.6), pair kernel
- * of the closing kick (partial sums with the prechecker), the closing
- * kick's per-body epilogue (the partial sums added, second Sun kick,
- * velocity update, next critical radii); the second to fourth are 0 with
- * encounter_free.  The
+ * grouping (App. A) with Bulirsch-Stoer of the groups (Sec. 3.2.6) in one
+ * kernel, pair kernel of the closing kick (partial sums with the
+ * prechecker), the closing kick's per-body epilogue (the partial sums
+ * added, second Sun kick, velocity update, next critical radii); the second
+ * and third are 0 with encounter_free.  The
  * breakdown behind a step's time, not a faster step.  Synchronising; returns
  * the latched status (GENGA_EINVAL for a batched context, a null pointer or
  * nsteps out of range). */

@@ -195,12 +195,13 @@ hipError_t massive_prime(const MassiveWs& w, const StepConsts& c,
 // with clear_radii).
 hipError_t massive_reset_bodies(const MassiveWs& w, bool clear_radii, hipStream_t s);
 // Kernels of one main-mode step in launch order: opening kick and drift,
-// encounter search, grouping, BS, pair kernel (partial sums), the closing
-// kick's per-body epilogue (the middle three only with encounters).  With
+// encounter search, grouping with BS, pair kernel (partial sums), the
+// closing kick's per-body epilogue (the second and third only with
+// encounters).  With
 // kev (2 kStepKernels events), the events of slot k take the start and end
 // timestamps of kernel k's dispatch.
-constexpr int kStepKernels = 6;
-constexpr int kSlotPairs = 4;  // the pair kernel's slot
+constexpr int kStepKernels = 5;
+constexpr int kSlotPairs = 3;  // the pair kernel's slot
 hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
                         const hipEvent_t* kev = nullptr);
 hipError_t massive_energy(const MassiveWs& w, const StepConsts& c, double* dE,

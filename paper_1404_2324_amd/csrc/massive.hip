@@ -1,17 +1,18 @@
 // Main-mode kernels of the hybrid symplectic step (Grimm & Stadel,
 // arXiv:1404.2324, Sec. 2.2 step recipe and Sec. 3.2 kernels), for gfx950.
 //
-// One step is six launches on one stream (captured once into a HIP graph;
-// a seventh, the compaction, when bodies can leave):
+// One step is five launches on one stream (captured once into a HIP graph;
+// a sixth, the compaction, when bodies can leave):
 //   k_open_drift   opening kick: cached non-candidate acceleration + candidate
 //                  pairs recomputed with the new radii (KickA/KickB, Sec 3.2.3);
 //                  Sun kick tau/2 (Eq. 3) + pre-drift copy + Kepler drift
 //                  (Eq. 9) + momentum partials for the second Sun kick
 //   k_encounter    Hermite test of every candidate (Eqs. 10-12), ballot
 //                  compaction of the confirmed pairs
-//   k_group        equivalence classes of the pairs in LDS (App. A)
-//   k_bs           Bulirsch-Stoer integration of H_A per group, one workgroup
-//                  of four waves each (speculative halving depths)
+//   k_group_bs     equivalence classes of the pairs in LDS (App. A), formed
+//                  by every workgroup for itself, then Bulirsch-Stoer
+//                  integration of H_A per group, one workgroup of four waves
+//                  each (speculative halving depths)
 //   k_pair_part    closing kick: all pairs and the prechecker, partial sums
 //                  per split of the partners
 //   k_pair_finish  per body: the splits added, the second Sun kick tau/2,
@@ -650,8 +651,9 @@ struct EncArgs {
 
 constexpr int kEncThreads = 1024;
 
-// Exclusive scan over a block of 1024 threads; returns the prefix and puts the
+// Exclusive scan over a block of NT threads; returns the prefix and puts the
 // total in *total.
+template <int NT>
 __device__ __forceinline__ int block_excl_scan(int v, int* shw, int* total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int incl = v;
@@ -663,7 +665,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int* shw, int* total) {
   if (lane == 63) shw[w] = incl;
   __syncthreads();
   int base = 0, tot = 0;
-  for (int k = 0; k < kEncThreads / 64; ++k) {
+  for (int k = 0; k < NT / 64; ++k) {
     if (k < w) base += shw[k];
     tot += shw[k];
   }
@@ -793,33 +795,47 @@ __global__ __launch_bounds__(256) void k_encounter_all(EncArgs a) {
 }
 
 // Equivalence classes of the encounter pairs (App. A), one workgroup: LINK
-// starts as the identity, every pair lowers both ends to the smaller link
-// (LDS atomic min), links are shortened by LINK[i] = LINK[LINK[i]], and both
-// sweeps repeat until nothing changes.  Groups are numbered by their smallest
-// member; offsets and members go to global memory for the BS kernel.  Also
-// clears the candidate table for the closing kick and counts its pairs.
+// starts as the identity on the pairs' bodies, every pair lowers both ends
+// to the smaller link (LDS atomic min), links are shortened by LINK[i] =
+// LINK[LINK[i]], and both sweeps repeat until nothing changes.  Groups are
+// numbered by their smallest member (the rank of each component's root
+// among the roots); offsets and members go to global memory for the BS
+// kernel (and, with gm, to LDS).  Every loop runs over the pairs or their
+// ends, not over the bodies: a step has tens of pairs among thousands of
+// bodies.  The writing workgroup also clears the candidate table for the
+// closing kick, counts its pairs and sets the step's group statistics.
 // The first kEncLds pairs are held in LDS; pairs beyond (many-pair regimes,
 // up to the list capacity) are read from the encounter list in place, so
 // the workgroup's LINK array, not the pair count, bounds the grouping.
+template <int NT>
 struct GroupLds {
   int link[kGroupMaxN];
-  int gid[kGroupMaxN];
+  int first[kGroupMaxN];  // the first end (2 e or 2 e + 1) naming each body
+  int gid[kGroupMaxN];    // group of each root
   int2 pr[kEncLds];
   int gsz[kGroupMaxN / 2 + 1];
-  int gof[kGroupMaxN / 2 + 1];
-  unsigned char inp[kGroupMaxN];
-  int shw[kEncThreads / 64];
+  int gof[kGroupMaxN / 2 + 1];  // group offsets, gof[ng] = the member count
+  int roots[kGroupMaxN / 2];
+  int nroot;
+  int shw[NT / 64];
   int s_changed;
 };
 
-// The grouping of ne_all encounter pairs by one workgroup of kEncThreads.
-__device__ __forceinline__ void group_phase(const EncArgs& a, int ne_all, GroupLds& L) {
+// The grouping of ne_all encounter pairs by one workgroup of NT threads;
+// returns the number of groups.  gm (LDS, or null): the members by group at
+// the offsets gof.  writer: this workgroup writes the global results.  pf
+// (or null): the list's entries tid + k NT, k < kEncLds / NT, already loaded
+// by the caller.
+template <int NT>
+__device__ __forceinline__ int group_phase(const EncArgs& a, int ne_all, GroupLds<NT>& L,
+                                           int* gm, bool writer,
+                                           const int2* pf = nullptr) {
   int* link = L.link;
+  int* first = L.first;
   int* gid = L.gid;
   int2* pr = L.pr;
   int* gsz = L.gsz;
   int* gof = L.gof;
-  unsigned char* inp = L.inp;
   int* shw = L.shw;
   int& s_changed = L.s_changed;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -827,33 +843,41 @@ __device__ __forceinline__ void group_phase(const EncArgs& a, int ne_all, GroupL
   const int ne = min(ne_all, a.enc_cap);
   const int nl = min(ne, kEncLds);  // pairs held in LDS
   auto pair_at = [&](int e) { return e < nl ? pr[e] : a.encij[e]; };
+  auto end_at = [&](int t) {  // end t of the pairs: pair t / 2, first or second body
+    const int2 q = pair_at(t >> 1);
+    return (t & 1) ? q.y : q.x;
+  };
   // the opening kick has read the reuse flag; this step's closing kick sets
   // it again for the next one
-  if (tid == 0) a.st->ctl = 0u;
-  for (int i = tid; i < n; i += kEncThreads) {
-    link[i] = i;
-    inp[i] = 0;
+  if (writer && tid == 0) a.st->ctl = 0u;
+  if (tid == 0) L.nroot = 0;
+  if (pf) {
+#pragma unroll
+    for (int k = 0; k < kEncLds / NT; ++k)
+      if (tid + k * NT < nl) pr[tid + k * NT] = pf[k];
+  } else {
+    for (int e = tid; e < nl; e += NT) pr[e] = a.encij[e];
   }
-  for (int e = tid; e < nl; e += kEncThreads) pr[e] = a.encij[e];
   __syncthreads();
   // candidate pairs i < j: every pair sits in both rows (the test is
   // symmetric), so half the sum of the row lengths
   int rows = 0;
-  for (int i = tid; i < n; i += kEncThreads) {
-    rows += min(a.ccnt[i], a.cpb);
-    a.ccnt[i] = 0;
-  }
-  for (int e = tid; e < ne; e += kEncThreads) {
-    const int2 q = pair_at(e);
-    inp[q.x] = 1;
-    inp[q.y] = 1;
+  if (writer)
+    for (int i = tid; i < n; i += NT) {
+      rows += min(a.ccnt[i], a.cpb);
+      a.ccnt[i] = 0;
+    }
+  for (int t = tid; t < 2 * ne; t += NT) {
+    const int i = end_at(t);
+    link[i] = i;
+    first[i] = INT_MAX;
   }
   // equivalence classes
   while (true) {
     if (tid == 0) s_changed = 0;
     __syncthreads();
     bool ch = false;
-    for (int e = tid; e < ne; e += kEncThreads) {
+    for (int e = tid; e < ne; e += NT) {
       const int2 q = pair_at(e);
       const int p1 = q.x, p2 = q.y;
       const int l1 = link[p1], l2 = link[p2];
@@ -864,7 +888,9 @@ __device__ __forceinline__ void group_phase(const EncArgs& a, int ne_all, GroupL
       }
     }
     __syncthreads();
-    for (int i = tid; i < n; i += kEncThreads) {
+    // pointer jumping over the pairs' ends (links only ever name such bodies)
+    for (int t = tid; t < 2 * ne; t += NT) {
+      const int i = end_at(t);
       const int l = link[i];
       const int ll = link[l];
       if (ll < l) {
@@ -877,26 +903,31 @@ __device__ __forceinline__ void group_phase(const EncArgs& a, int ne_all, GroupL
     if (!s_changed) break;
     __syncthreads();
   }
-  // consecutive group ids in order of the smallest member
-  constexpr int PER = kGroupMaxN / kEncThreads;
-  int cntr = 0;
-  for (int k = 0; k < PER; ++k) {
-    const int i = tid * PER + k;
-    if (i < n && inp[i] && link[i] == i) ++cntr;
-  }
-  int ng = 0;
-  int off = block_excl_scan(cntr, shw, &ng);
-  for (int k = 0; k < PER; ++k) {
-    const int i = tid * PER + k;
-    if (i < n && inp[i] && link[i] == i) gid[i] = off++;
-  }
-  for (int g = tid; g <= ng; g += kEncThreads) gsz[g] = 0;
+  // each body once (at its first end), each root once
+  for (int t = tid; t < 2 * ne; t += NT) atomicMin(&first[end_at(t)], t);
   __syncthreads();
-  for (int i = tid; i < n; i += kEncThreads)
-    if (inp[i]) atomicAdd(&gsz[gid[link[i]]], 1);
+  for (int t = tid; t < 2 * ne; t += NT) {
+    const int i = end_at(t);
+    if (first[i] == t && link[i] == i) L.roots[atomicAdd(&L.nroot, 1)] = i;
+  }
+  __syncthreads();
+  const int ng = L.nroot;
+  // group ids in order of the smallest member: the rank among the roots
+  for (int r = tid; r < ng; r += NT) {
+    const int ri = L.roots[r];
+    int rank = 0;
+    for (int u = 0; u < ng; ++u) rank += L.roots[u] < ri ? 1 : 0;
+    gid[ri] = rank;
+  }
+  for (int g = tid; g <= ng; g += NT) gsz[g] = 0;
+  __syncthreads();
+  for (int t = tid; t < 2 * ne; t += NT) {
+    const int i = end_at(t);
+    if (first[i] == t) atomicAdd(&gsz[gid[link[i]]], 1);
+  }
   __syncthreads();
   // offsets: exclusive scan of the sizes
-  constexpr int GPER = (kGroupMaxN / 2 + kEncThreads - 1) / kEncThreads;
+  constexpr int GPER = (kGroupMaxN / 2 + NT - 1) / NT;
   int loc = 0, mx = 0;
   for (int k = 0; k < GPER; ++k) {
     const int g = tid * GPER + k;
@@ -906,45 +937,52 @@ __device__ __forceinline__ void group_phase(const EncArgs& a, int ne_all, GroupL
     }
   }
   int tot = 0;
-  int o2 = block_excl_scan(loc, shw, &tot);
+  int o2 = block_excl_scan<NT>(loc, shw, &tot);
   for (int k = 0; k < GPER; ++k) {
     const int g = tid * GPER + k;
     if (g < ng) {
       gof[g] = o2;
-      a.goff[g] = o2;
+      if (writer) a.goff[g] = o2;
       o2 += gsz[g];
     }
   }
-  if (tid == 0) a.goff[ng] = tot;
+  if (tid == 0) {
+    gof[ng] = tot;
+    if (writer) a.goff[ng] = tot;
+  }
   int nrow = 0;
-  (void)block_excl_scan(rows, shw, &nrow);
+  (void)block_excl_scan<NT>(rows, shw, &nrow);
   mx = wave_max_i(mx);
   __syncthreads();
   if (lane == 0) shw[tid >> 6] = mx;
-  for (int g = tid; g < ng; g += kEncThreads) gsz[g] = 0;
+  for (int g = tid; g < ng; g += NT) gsz[g] = 0;
   __syncthreads();
-  if (tid == 0) {
+  if (writer && tid == 0) {
     int m2 = 0;
-    for (int k = 0; k < kEncThreads / 64; ++k) m2 = max(m2, shw[k]);
+    for (int k = 0; k < NT / 64; ++k) m2 = max(m2, shw[k]);
     a.st->maxg = m2;
     a.st->ngroups = ng;
     a.st->ncand = nrow / 2;
     a.st->enc_total += (unsigned long long)ne_all;
     if (ne_all > a.enc_cap) atomicOr(&a.st->flags, F_ENC_OVF);
   }
-  for (int i = tid; i < n; i += kEncThreads) {
-    if (inp[i]) {
+  for (int t = tid; t < 2 * ne; t += NT) {
+    const int i = end_at(t);
+    if (first[i] == t) {
       const int g = gid[link[i]];
       const int pos = gof[g] + atomicAdd(&gsz[g], 1);
-      a.gmem[pos] = i;
+      if (writer) a.gmem[pos] = i;
+      if (gm) gm[pos] = i;
     }
   }
+  __syncthreads();  // gof and gm for every thread
+  return ng;
 }
 
 __global__ __launch_bounds__(kEncThreads) void k_group(EncArgs a) {
-  __shared__ GroupLds L;
+  __shared__ GroupLds<kEncThreads> L;
   if (a.st->flags & F_NMIN) return;  // the run stopped below nmin bodies
-  group_phase(a, a.st->nenc, L);
+  (void)group_phase<kEncThreads>(a, a.st->nenc, L, nullptr, true);
 }
 
 
@@ -1134,14 +1172,14 @@ __device__ bool big_attempt(const BsArgs& a, const int* mem, int sz, double H) {
   return false;
 }
 
-// Group g of sz > 64 members at offset o: members sorted into bmem, state
-// from the pre-drift copy, binary refinement over tau as bs_integrate does,
-// result written back; returns the BS status (0, or -1 when the depth or
-// the attempt cap is exhausted) and the group's momentum change.
-__device__ int bs_group_big(const BsArgs& a, int o, int sz, long long* nsub, double& dpx,
-                            double& dpy, double& dpz) {
+// Group g of sz > 64 members gm[0 .. sz - 1] at offset o: members sorted
+// into bmem, state from the pre-drift copy, binary refinement over tau as
+// bs_integrate does, result written back; returns the BS status (0, or -1
+// when the depth or the attempt cap is exhausted) and the group's momentum
+// change.
+__device__ int bs_group_big(const BsArgs& a, const int* gm, int o, int sz, long long* nsub,
+                            double& dpx, double& dpy, double& dpz) {
   const int lane = threadIdx.x;
-  const int* gm = a.gmem + o;
   int* mem = a.bmem + o;
   for (int m = lane; m < sz; m += 64) {
     const int id = gm[m];
@@ -1506,9 +1544,9 @@ __device__ int bs_group_coll(const BsArgs& a, int g, int sz, const int* mem, dou
 // collide, or more than kBsPar members (one lane per member; more than 64
 // in the per-body records).  Writes the group's momentum change and merger
 // energy to dP.
-__device__ __forceinline__ void bs_group_one(const BsArgs& a, int g, int o, int sz, int* mem,
-                                             double* mm, double* mrc, double* mR,
-                                             double (*R)[6][64], long long* nsub) {
+__device__ __forceinline__ void bs_group_one(const BsArgs& a, const int* gmem, int g, int o,
+                                             int sz, int* mem, double* mm, double* mrc,
+                                             double* mR, double (*R)[6][64], long long* nsub) {
   const int lane = threadIdx.x & 63;
   if (a.coll && sz > kBsMaxGroup) {
     // collisions are tested in groups of up to 64 members only
@@ -1517,10 +1555,10 @@ __device__ __forceinline__ void bs_group_one(const BsArgs& a, int g, int o, int 
   }
   double dpx = 0.0, dpy = 0.0, dpz = 0.0, Ug = 0.0;
   if (sz > kBsMaxGroup) {
-    const int r = bs_group_big(a, o, sz, nsub, dpx, dpy, dpz);
+    const int r = bs_group_big(a, gmem + o, o, sz, nsub, dpx, dpy, dpz);
     if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
   } else {
-    const int my = lane < sz ? a.gmem[o + lane] : INT_MAX;
+    const int my = lane < sz ? gmem[o + lane] : INT_MAX;
     int rank = 0;
     for (int q = 0; q < sz; ++q) rank += (__builtin_amdgcn_readlane(my, q) < my) ? 1 : 0;
     if (lane < sz) mem[rank] = my;
@@ -1568,40 +1606,44 @@ __device__ __forceinline__ void bs_group_one(const BsArgs& a, int g, int o, int 
   }
 }
 
-// One workgroup of kBsWaves waves per encounter group (grid-stride over the
-// device-side count): members sorted ascending, state reset to the
+// LDS of one workgroup's BS.
+struct BsLds {
+  double R[kBsCols][6][64];
+  int mem[64];
+  double mm[kBsPar], mrc[kBsPar], mR[kBsPar];
+  BsXchg X;
+};
+
+// The ng groups (offsets goff[0 .. ng], members gmem at those offsets, in
+// global memory or LDS) on the workgroups of the grid, one group at a time
+// per workgroup (grid-stride): members sorted ascending, state reset to the
 // pre-drift copy, H_A integrated over tau by BS, result written back.
 // Groups of up to 8 members take the all-columns path with speculative
 // depths over every wave; the others take wave 0 alone (one lane per
 // member with the columns in sequence, or the collision path).
-__global__ __launch_bounds__(64 * kBsWaves) void k_bs(BsArgs a) {
-  __shared__ double R[kBsCols][6][64];
-  __shared__ int mem[64];
-  __shared__ double mm[kBsPar], mrc[kBsPar], mR[kBsPar];
-  __shared__ BsXchg X;
+__device__ __forceinline__ void bs_groups(const BsArgs& a, int ng, const int* goff,
+                                          const int* gmem, BsLds& L) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (a.st->flags & F_NMIN) return;  // the run stopped below nmin bodies
-  const int ng = __builtin_amdgcn_readfirstlane(a.st->ngroups);
   long long nsub = 0;
   for (int g = blockIdx.x; g < ng; g += gridDim.x) {
-    const int o = a.goff[g];
-    const int sz = a.goff[g + 1] - o;
+    const int o = goff[g];
+    const int sz = goff[g + 1] - o;
     if (!a.coll && sz <= kBsPar) {
       // every wave ranks the members; wave 0 writes them in order
-      const int my = lane < sz ? a.gmem[o + lane] : INT_MAX;
+      const int my = lane < sz ? gmem[o + lane] : INT_MAX;
       int rank = 0;
       for (int q = 0; q < sz; ++q) rank += (__builtin_amdgcn_readlane(my, q) < my) ? 1 : 0;
-      if (wave == 0 && lane < sz) mem[rank] = my;
+      if (wave == 0 && lane < sz) L.mem[rank] = my;
       __syncthreads();
       double dpx, dpy, dpz;
       int r;
       if (sz <= 2)
-        r = bs_member_group<2>(a, sz, mem, mm, mrc, X, &nsub, dpx, dpy, dpz);
+        r = bs_member_group<2>(a, sz, L.mem, L.mm, L.mrc, L.X, &nsub, dpx, dpy, dpz);
       else if (sz <= 4)
-        r = bs_member_group<4>(a, sz, mem, mm, mrc, X, &nsub, dpx, dpy, dpz);
+        r = bs_member_group<4>(a, sz, L.mem, L.mm, L.mrc, L.X, &nsub, dpx, dpy, dpz);
       else
-        r = bs_member_group<8>(a, sz, mem, mm, mrc, X, &nsub, dpx, dpy, dpz);
+        r = bs_member_group<8>(a, sz, L.mem, L.mm, L.mrc, L.X, &nsub, dpx, dpy, dpz);
       if (wave == 0) {
         if (r != 0 && lane == 0) atomicOr(&a.st->flags, F_BS);
         // the group's momentum change for the second Sun kick (fixed lane order)
@@ -1616,12 +1658,51 @@ __global__ __launch_bounds__(64 * kBsWaves) void k_bs(BsArgs a) {
         }
       }
     } else if (wave == 0) {
-      bs_group_one(a, g, o, sz, mem, mm, mrc, mR, R, &nsub);
+      bs_group_one(a, gmem, g, o, sz, L.mem, L.mm, L.mrc, L.mR, L.R, &nsub);
     }
     // the group's LDS (mem, mm, mrc, mR, R, X) is free for the next one
     __syncthreads();
   }
   if (threadIdx.x == 0 && nsub > 0) atomicAdd(&a.st->bs_sub, (unsigned long long)nsub);
+}
+
+// BS of the groups that the grouping kernel left in global memory.
+__global__ __launch_bounds__(64 * kBsWaves) void k_bs(BsArgs a) {
+  __shared__ BsLds L;
+  if (a.st->flags & F_NMIN) return;  // the run stopped below nmin bodies
+  const int ng = __builtin_amdgcn_readfirstlane(a.st->ngroups);
+  bs_groups(a, ng, a.goff, a.gmem, L);
+}
+
+// Grouping (App. A) and BS (Sec. 3.2.6) in one launch: every workgroup
+// forms the groups of the step's encounter pairs in its own LDS (the same
+// groups, offsets and member sets in each: the labels and offsets come from
+// the pairs alone), so no workgroup waits for another before its BS; one
+// also writes the groups, the counts and the cleared candidate table to
+// global memory.
+struct GroupBsLds {
+  GroupLds<64 * kBsWaves> g;
+  int gm[kGroupMaxN];
+  BsLds b;
+};
+__global__ __launch_bounds__(64 * kBsWaves) void k_group_bs(EncArgs e, BsArgs a) {
+  constexpr int NT = 64 * kBsWaves;
+  __shared__ GroupBsLds L;
+  // the status word, the pair count and the list's first kEncLds entries
+  // are loaded together (entries past the count are dropped)
+  const unsigned fl = a.st->flags;
+  const int ne_all = e.st->nenc;
+  int2 pf[kEncLds / NT];
+#pragma unroll
+  for (int k = 0; k < kEncLds / NT; ++k) {
+    const int idx = threadIdx.x + k * NT;
+    pf[k] = idx < e.enc_cap ? e.encij[idx] : make_int2(0, 0);
+  }
+  if (fl & F_NMIN) return;  // the run stopped below nmin bodies
+  // the last workgroup, which rarely has a group of its own, writes the
+  // global results
+  const int ng = group_phase<NT>(e, ne_all, L.g, L.gm, blockIdx.x == gridDim.x - 1, pf);
+  bs_groups(a, ng, L.g.gof, L.gm, L.b);
 }
 
 // ---- bodies leaving the system (Sec. 3.2.7, 3.2.8, 3.4.6) ------------------
@@ -2308,17 +2389,6 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
     e.cpb = w.cpb;
     e.enc_cap = w.enc_cap;
     e.dt = c.dt;
-    if (c.all_pairs) {
-      // composed steps (not timed per kernel): every pair tested, then the
-      // grouping on its own
-      const int nt = ceil_div(w.n, kEncTile);
-      hipLaunchKernelGGL(k_encounter_all, dim3(nt, nt), dim3(256), 0, s, e);
-      hipLaunchKernelGGL(k_group, dim3(1), dim3(kEncThreads), 0, s, e);
-    } else {
-      STEP_LAUNCH(1, k_encounter, dim3(ceil_div(w.n * w.cpb, kVecBlock)), dim3(kVecBlock), e);
-      STEP_LAUNCH(2, k_group, dim3(1), dim3(kEncThreads), e);
-    }
-
     BsArgs b;
     b.xm = w.xm;
     b.vv = w.vv;
@@ -2345,7 +2415,18 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
     b.max_depth = c.bs_max_depth;
     b.coll = c.coll;
     b.ev_cap = w.ev_cap;
-    STEP_LAUNCH(3, k_bs, dim3(std::max(1, std::min(256, w.n / 2))), dim3(64 * kBsWaves), b);
+    const dim3 bs_grid(std::max(1, std::min(256, w.n / 2)));
+    if (c.all_pairs) {
+      // composed steps (not timed per kernel): every pair tested, then the
+      // grouping and BS on their own
+      const int nt = ceil_div(w.n, kEncTile);
+      hipLaunchKernelGGL(k_encounter_all, dim3(nt, nt), dim3(256), 0, s, e);
+      hipLaunchKernelGGL(k_group, dim3(1), dim3(kEncThreads), 0, s, e);
+      hipLaunchKernelGGL(k_bs, bs_grid, dim3(64 * kBsWaves), 0, s, b);
+    } else {
+      STEP_LAUNCH(1, k_encounter, dim3(ceil_div(w.n * w.cpb, kVecBlock)), dim3(kVecBlock), e);
+      STEP_LAUNCH(2, k_group_bs, bs_grid, dim3(64 * kBsWaves), e, b);
+    }
     if (c.phys) {
       // bodies that merged or crossed rcut / rcut_sun leave (not timed per
       // kernel: the measurement forms run without these limits)
@@ -2374,9 +2455,9 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
 
   PairArgs a = pair_args(w, c);
   const auto kpair = pair_kernel<KICK_CLOSE>(w);
-  STEP_LAUNCH(4, kpair, pair_grid(w), pair_block(w), a,
+  STEP_LAUNCH(3, kpair, pair_grid(w), pair_block(w), a,
               (const double4*)w.xm, (const double*)w.thr, (const double*)w.tmax64);
-  STEP_LAUNCH(5, k_pair_finish<KICK_CLOSE>, dim3(ceil_div(w.n, kFinThreads)), dim3(kFinThreads), a,
+  STEP_LAUNCH(4, k_pair_finish<KICK_CLOSE>, dim3(ceil_div(w.n, kFinThreads)), dim3(kFinThreads), a,
               (const double4*)w.xm);
   return hipGetLastError();
 }

@@ -195,7 +195,7 @@ class Simulation:
                "genga_step_profiled")
         return us.value
 
-    STEP_KERNELS = ("k_open_drift", "k_encounter", "k_group", "k_bs", "k_pair_part",
+    STEP_KERNELS = ("k_open_drift", "k_encounter", "k_group_bs", "k_pair_part",
                     "k_pair_finish")
 
     def step_kernel_us(self, nsteps: int) -> dict:

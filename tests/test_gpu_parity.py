@@ -393,7 +393,7 @@ def test_kernel_timed_steps_match_graph_steps():
     assert torch.equal(xa, xb) and torch.equal(va, vb)
     f = G.Simulation(s.m, s.x, s.u, _gparams(encounter_free=1), coords="helio")
     uf = f.step_kernel_us(3)
-    assert uf["k_encounter"] == uf["k_group"] == uf["k_bs"] == 0.0
+    assert uf["k_encounter"] == uf["k_group_bs"] == 0.0
     assert uf["k_pair_part"] > 0.0 and uf["k_pair_finish"] > 0.0 and uf["k_open_drift"] > 0.0
     with pytest.raises(G.GengaError):
         f.step_kernel_us(513)
