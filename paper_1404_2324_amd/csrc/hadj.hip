@@ -422,11 +422,13 @@ __device__ __forceinline__ void ha_deriv_par(const HArgs& a, const Sys& S, const
   dy[5] = a2;
 }
 
-// The lane's column of Gragg's rule (2 (c + 1) substeps over H); 17 rounds,
-// a column idle once its sequence is done.  keep: positions to zpos.
+// The lane's column of Gragg's rule (2 (c + 1) substeps over H); rounds 0 ..
+// mtop (17 for every column; fewer when only the columns with 2 (c + 1) <=
+// mtop are wanted), a column idle once its sequence is done.  keep:
+// positions to zpos.
 __device__ __forceinline__ void gragg_par(const HArgs& a, const Sys& S, const Par& P,
                                           const double y0[6], double H, double out[6],
-                                          bool keep) {
+                                          bool keep, int mtop = 2 * kHPar) {
   const int nsub = 2 * (P.c + 1);
   const double hs = ldexp(H, -P.s) / nsub;  // the lane's depth slot (exact scaling)
   double d[6], ym[6], yn[6];
@@ -440,7 +442,7 @@ __device__ __forceinline__ void gragg_par(const HArgs& a, const Sys& S, const Pa
 #pragma unroll
     for (int c = 0; c < 3; ++c) a.zpos[(size_t)c * a.nl + S.gl] = y0[c];
   }
-  for (int m = 0; m <= 2 * kHPar; ++m) {
+  for (int m = 0; m <= mtop; ++m) {
     ha_deriv_par(a, S, P, yn, d);
     if (m == 0) {
 #pragma unroll
@@ -877,17 +879,19 @@ __device__ __forceinline__ void ha_vjp_par(const HArgs& a, const Sys& S, const P
   }
 }
 
-// gragg_vjp for the lane's column of the column-parallel layout: 17 reverse
-// rounds, a column idle above its own sequence.
+// gragg_vjp for the lane's column of the column-parallel layout: reverse
+// rounds from mtop = 2 (kk + 1) down, kk the last column with a weight (the
+// columns past it have a zero adjoint and are left out), a column idle
+// above its own sequence.
 __device__ __forceinline__ void gragg_vjp_par(const HArgs& a, const Sys& S, const Par& P,
                                               const double y0[6], double H, const double ob[6],
-                                              double yb[6], double& mb, double& rcb) {
+                                              double yb[6], double& mb, double& rcb, int mtop) {
   const int nsub = 2 * (P.c + 1);
   const double hs = H / nsub;
   double tmp[6];
-  gragg_par(a, S, P, y0, H, tmp, true);
+  gragg_par(a, S, P, y0, H, tmp, true, mtop);
   double Pa[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Qa[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int m = 2 * kHPar; m >= 0; --m) {
+  for (int m = mtop; m >= 0; --m) {
     const bool act = m <= nsub;
     const int mz = act ? m : nsub;
     double z[3], w[3], o[3];
@@ -971,7 +975,7 @@ __device__ __forceinline__ void bs_group_vjp(const HArgs& a, const Sys& S, unsig
         ob[c] = wq * __shfl(yb[c], P.src, 64);
       }
       double mbl = 0.0, rcbl = 0.0;
-      gragg_vjp_par(a, S, P, y0, hh, ob, col, mbl, rcbl);
+      gragg_vjp_par(a, S, P, y0, hh, ob, col, mbl, rcbl, 2 * (kk + 1));
       double msum = 0.0, rsum = 0.0;
       for (int c8 = 0; c8 < kHPar; ++c8) {
         double v[6];
