@@ -422,27 +422,16 @@ __device__ __forceinline__ void ha_deriv_par(const HArgs& a, const Sys& S, const
   dy[5] = a2;
 }
 
-// The lane's column of Gragg's rule (2 (c + 1) substeps over H); rounds 0 ..
-// mtop (17 for every column; fewer when only the columns with 2 (c + 1) <=
-// mtop are wanted), a column idle once its sequence is done.  keep:
+// Rounds mfrom .. mto of the lane's column of Gragg's rule (nsub = 2 (c + 1)
+// substeps of hs from y0; ym, yn: the last two points; out: the result once
+// round nsub is done), a column idle once its sequence is done.  keep:
 // positions to zpos.
-__device__ __forceinline__ void gragg_par(const HArgs& a, const Sys& S, const Par& P,
-                                          const double y0[6], double H, double out[6],
-                                          bool keep, int mtop = 2 * kHPar) {
-  const int nsub = 2 * (P.c + 1);
-  const double hs = ldexp(H, -P.s) / nsub;  // the lane's depth slot (exact scaling)
-  double d[6], ym[6], yn[6];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    yn[c] = y0[c];
-    ym[c] = y0[c];
-    out[c] = 0.0;
-  }
-  if (keep) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) a.zpos[(size_t)c * a.nl + S.gl] = y0[c];
-  }
-  for (int m = 0; m <= mtop; ++m) {
+__device__ __forceinline__ void gragg_rounds(const HArgs& a, const Sys& S, const Par& P,
+                                             const double y0[6], double hs, int nsub,
+                                             double ym[6], double yn[6], double out[6],
+                                             bool keep, int mfrom, int mto) {
+  double d[6];
+  for (int m = mfrom; m <= mto; ++m) {
     ha_deriv_par(a, S, P, yn, d);
     if (m == 0) {
 #pragma unroll
@@ -465,25 +454,43 @@ __device__ __forceinline__ void gragg_par(const HArgs& a, const Sys& S, const Pa
   }
 }
 
-// bs_attempt with the columns side by side and P.ns depth slots (slots from
-// smax on are past the depth limit and not taken): y holds the members'
-// state in their body lanes; the accepted column (>= 1) of the first slot
-// that has one, its slot in *sa and its value in yout (body lanes of
-// members), or -1.
-__device__ __forceinline__ int bs_attempt_par(const HArgs& a, const Sys& S,
-                                              unsigned long long M, const Par& P,
-                                              const double y[6], double H, double yout[6],
-                                              int smax, int* sa) {
-  double y0[6], T[6], Td[6], Ts[6];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) y0[c] = __shfl(y[c], P.src, 64);
-  gragg_par(a, S, P, y0, H, T, false);  // T(c, 0)
+// The lane's column of Gragg's rule (2 (c + 1) substeps over H); rounds 0 ..
+// mtop (17 for every column; fewer when only the columns with 2 (c + 1) <=
+// mtop are wanted).  keep: positions to zpos.
+__device__ __forceinline__ void gragg_par(const HArgs& a, const Sys& S, const Par& P,
+                                          const double y0[6], double H, double out[6],
+                                          bool keep, int mtop = 2 * kHPar) {
+  const int nsub = 2 * (P.c + 1);
+  const double hs = ldexp(H, -P.s) / nsub;  // the lane's depth slot (exact scaling)
+  double ym[6], yn[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    Td[c] = T[c];
+    yn[c] = y0[c];
+    ym[c] = y0[c];
+    out[c] = 0.0;
+  }
+  if (keep) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.zpos[(size_t)c * a.nl + S.gl] = y0[c];
+  }
+  gragg_rounds(a, S, P, y0, hs, nsub, ym, yn, out, keep, 0, mtop);
+}
+
+// The Aitken-Neville tableau of the columns 0 .. kmax from their Gragg
+// results T0 (T(c, 0) in the lanes of column c): T(c, j) = T(c, j-1) +
+// (T(c, j-1) - T(c-1, j-1)) / ((n_c / n_{c-j})^2 - 1), the column below read
+// from lane - 8; Td, Ts receive T(c, c) and T(c, c-1) in the lanes of every
+// column c <= kmax.  The same operations in the same order for any kmax.
+__device__ __forceinline__ void neville_par(const Sys& S, const Par& P, const double T0[6],
+                                            int kmax, double Td[6], double Ts[6]) {
+  double T[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    T[c] = T0[c];
+    Td[c] = T0[c];
     Ts[c] = 0.0;
   }
-  for (int j = 1; j < kHPar; ++j) {
+  for (int j = 1; j <= kmax; ++j) {
     double up[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) up[c] = __shfl(T[c], S.lane - 8, 64);  // T(c - 1, j - 1)
@@ -501,21 +508,65 @@ __device__ __forceinline__ int bs_attempt_par(const HArgs& a, const Sys& S,
       }
     }
   }
+}
+
+// Ballot of the leading lanes (member slot 0) of the columns 1 .. kmax of
+// the depth slots below smax whose largest relative change over the slot's
+// members is within tol (lane bit 8 c + w s).
+__device__ __forceinline__ unsigned long long accepted_par(const HArgs& a, const Par& P,
+                                                           const double Td[6],
+                                                           const double Ts[6], int kmax,
+                                                           int smax) {
   double err = 0.0;
   if (P.on && P.c >= 1) err = fmax(vrel3(&Td[0], &Ts[0]), vrel3(&Td[3], &Ts[3]));
   // the largest error over the slot's members (its w adjacent lanes)
   err = fmax(err, __shfl_xor(err, 1, 64));
   if (P.w >= 4) err = fmax(err, __shfl_xor(err, 2, 64));
   if (P.w >= 8) err = fmax(err, __shfl_xor(err, 4, 64));
-  const unsigned long long ok =
-      __builtin_amdgcn_ballot_w64(P.q == 0 && P.c >= 1 && P.s < smax && err <= a.bs_tol);
-  if (ok == 0ull) return -1;
-  // the first slot with an accepted column: slot s leads at lanes 8 c + w s
+  return __builtin_amdgcn_ballot_w64(P.q == 0 && P.c >= 1 && P.c <= kmax && P.s < smax &&
+                                     err <= a.bs_tol);
+}
+
+// bs_attempt with the columns side by side and P.ns depth slots (slots from
+// smax on are past the depth limit and not taken): y holds the members'
+// state in their body lanes; the accepted column (>= 1) of the first slot
+// that has one, its slot in *sa and its value in yout (body lanes of
+// members), or -1.  The columns up to kHMid are tested when they are done
+// (after round 2 (kHMid + 1)): when the first slot has an accepted column
+// among them the attempt ends there; otherwise the rest of the rounds run
+// and every column is tested.  Either way the result is that of testing
+// every column at the end.
+constexpr int kHMid = 4;
+__device__ __forceinline__ int bs_attempt_par(const HArgs& a, const Sys& S,
+                                              unsigned long long M, const Par& P,
+                                              const double y[6], double H, double yout[6],
+                                              int smax, int* sa) {
+  double y0[6], ym[6], yn[6], T0[6], Td[6], Ts[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    y0[c] = __shfl(y[c], P.src, 64);
+    ym[c] = y0[c];
+    yn[c] = y0[c];
+    T0[c] = 0.0;
+  }
+  const int nsub = 2 * (P.c + 1);
+  const double hs = ldexp(H, -P.s) / nsub;  // the lane's depth slot (exact scaling)
+  gragg_rounds(a, S, P, y0, hs, nsub, ym, yn, T0, false, 0, 2 * (kHMid + 1));  // T(c, 0), c <= kHMid
+  neville_par(S, P, T0, kHMid, Td, Ts);
+  unsigned long long ok = accepted_par(a, P, Td, Ts, kHMid, smax);
+  const unsigned long long slot0 = 0x0101010101010101ull;  // slot 0 leads at lanes 8 c
   int s = 0;
-  unsigned long long oks = 0ull;
-  for (; s < P.ns; ++s) {
-    oks = ok & (0x0101010101010101ull << (P.w * s));
-    if (oks) break;
+  unsigned long long oks = ok & slot0;
+  if (oks == 0ull) {
+    gragg_rounds(a, S, P, y0, hs, nsub, ym, yn, T0, false, 2 * (kHMid + 1) + 1, 2 * kHPar);
+    neville_par(S, P, T0, kHPar - 1, Td, Ts);
+    ok = accepted_par(a, P, Td, Ts, kHPar - 1, smax);
+    if (ok == 0ull) return -1;
+    // the first slot with an accepted column: slot s leads at lanes 8 c + w s
+    for (; s < P.ns; ++s) {
+      oks = ok & (slot0 << (P.w * s));
+      if (oks) break;
+    }
   }
   const int k = __builtin_ctzll(oks) >> 3;
   *sa = s;
