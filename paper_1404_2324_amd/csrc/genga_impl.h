@@ -64,6 +64,7 @@ constexpr int kBsMaxGroup = 64;        // members of the lane-per-member BS path
 constexpr int kGroupMaxN = 2048;       // bodies the one-workgroup grouping holds
 constexpr int kEncLds = 2048;          // encounter pairs grouped in LDS
 constexpr int kVecBlock = 256;         // threads of the per-body kernels
+constexpr int kOpenBlock = 64;         // threads of the opening-kick-and-drift kernel (one wave)
 
 // Views into the caller's workspace for main mode (also the massive part of
 // test-particle mode).  Bodies are padded to np (a multiple of 256).

@@ -479,11 +479,11 @@ __device__ __forceinline__ void sum_partners(const int (&jj)[N], int c0, int cnt
 // after this opening kick up to rounding.  Also installs the step's radii
 // and thresholds, leaves per-block momentum partials after the kick and
 // after the drift, and resets the step's encounter counters.
-__global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
-  __shared__ double sh[3 * (kVecBlock / 64)];
+__global__ __launch_bounds__(kOpenBlock) void k_open_drift(OpenArgs a) {
+  __shared__ double sh[3 * (kOpenBlock / 64)];
   __shared__ unsigned kh[kKepBins];  // this block's drifts by iteration count
   double tloc = kTiny;               // the lane's candidate threshold
-  const int i = blockIdx.x * kVecBlock + threadIdx.x;  // < np: every per-body array has np rows
+  const int i = blockIdx.x * kOpenBlock + threadIdx.x;  // < np: every per-body array has np rows
   // Every load that does not depend on the status word is issued before the
   // word is read: the body's state, cached far sum and radius, its row count
   // and the first kPre entries of its candidate row (entries past the count
@@ -606,9 +606,9 @@ __global__ __launch_bounds__(kVecBlock) void k_open_drift(OpenArgs a) {
   const int itm = wave_max_i(abs(it));
   if ((threadIdx.x & 63) == 0 && itm > itmax0) atomicMax(&a.st->kep_itmax, itm);
   double Px = m * kx, Py = m * ky, Pz = m * kz;
-  block_sum3<kVecBlock>(Px, Py, Pz, sh);
+  block_sum3<kOpenBlock>(Px, Py, Pz, sh);
   double Qx = m * dx, Qy = m * dy, Qz = m * dz;
-  block_sum3<kVecBlock>(Qx, Qy, Qz, sh);  // its barriers also order kh
+  block_sum3<kOpenBlock>(Qx, Qy, Qz, sh);  // its barriers also order kh
   if (threadIdx.x < kKepBins)
     a.khist[(size_t)blockIdx.x * kKepBins + threadIdx.x] = kh0 + kh[threadIdx.x];
   chunk_tmax(tloc, i & ~63, a.tmax64);
@@ -2222,7 +2222,7 @@ size_t massive_carve(MassiveWs& w, int n, const genga_params& p, void* base, boo
   w.n = n;
   w.np = ceil_div(n, 256) * 256;
   pair_shape(w.np, &w.pw, &w.njs);
-  w.nblk = ceil_div(n, kVecBlock);
+  w.nblk = ceil_div(n, kOpenBlock);
   w.cpb = p.cand_per_body;
   w.enc_cap = p.enc_cap;
   const size_t np = (size_t)w.np;
@@ -2368,7 +2368,7 @@ hipError_t massive_step(const MassiveWs& w, const StepConsts& c, hipStream_t s,
   o.m0 = c.m0;
   o.mu = c.mu;
   o.dt = c.dt;
-  STEP_LAUNCH(0, k_open_drift, dim3(w.nblk), dim3(kVecBlock), o);
+  STEP_LAUNCH(0, k_open_drift, dim3(w.nblk), dim3(kOpenBlock), o);
 
   if (!c.encounter_free) {
     EncArgs e;
@@ -2548,7 +2548,7 @@ hipError_t accel_noalloc_run(const StepConsts& c, int n, const double* m, const 
   w.n = n;
   w.np = ceil_div(n, 256) * 256;
   pair_shape(w.np, &w.pw, &w.njs);  // as the workspace path, so both give the same bits
-  w.nblk = ceil_div(n, kVecBlock);
+  w.nblk = ceil_div(n, kOpenBlock);
   const size_t np = (size_t)w.np;
   char* q = static_cast<char*>(base);
   w.xm = reinterpret_cast<double4*>(q);
