@@ -824,8 +824,7 @@ struct GroupLds {
 // The grouping of ne_all encounter pairs by one workgroup of NT threads;
 // returns the number of groups.  gm (LDS, or null): the members by group at
 // the offsets gof.  writer: this workgroup writes the global results.  pf
-// (or null): the list's entries tid + k NT, k < kEncLds / NT, already loaded
-// by the caller.
+// (or null): the list's entry tid, already loaded by the caller.
 template <int NT>
 __device__ __forceinline__ int group_phase(const EncArgs& a, int ne_all, GroupLds<NT>& L,
                                            int* gm, bool writer,
@@ -851,13 +850,7 @@ __device__ __forceinline__ int group_phase(const EncArgs& a, int ne_all, GroupLd
   // it again for the next one
   if (writer && tid == 0) a.st->ctl = 0u;
   if (tid == 0) L.nroot = 0;
-  if (pf) {
-#pragma unroll
-    for (int k = 0; k < kEncLds / NT; ++k)
-      if (tid + k * NT < nl) pr[tid + k * NT] = pf[k];
-  } else {
-    for (int e = tid; e < nl; e += NT) pr[e] = a.encij[e];
-  }
+  for (int e = tid; e < nl; e += NT) pr[e] = (pf && e == tid) ? *pf : a.encij[e];
   __syncthreads();
   // candidate pairs i < j: every pair sits in both rows (the test is
   // symmetric), so half the sum of the row lengths
@@ -1688,20 +1681,16 @@ struct GroupBsLds {
 __global__ __launch_bounds__(64 * kBsWaves) void k_group_bs(EncArgs e, BsArgs a) {
   constexpr int NT = 64 * kBsWaves;
   __shared__ GroupBsLds L;
-  // the status word, the pair count and the list's first kEncLds entries
-  // are loaded together (entries past the count are dropped)
+  // the status word, the pair count and the list's first NT entries (a
+  // step's pairs are fewer, as a rule) are loaded together; entries past the
+  // count are dropped, and any beyond NT are read once the count is known
   const unsigned fl = a.st->flags;
   const int ne_all = e.st->nenc;
-  int2 pf[kEncLds / NT];
-#pragma unroll
-  for (int k = 0; k < kEncLds / NT; ++k) {
-    const int idx = threadIdx.x + k * NT;
-    pf[k] = idx < e.enc_cap ? e.encij[idx] : make_int2(0, 0);
-  }
+  const int2 pf = (int)threadIdx.x < e.enc_cap ? e.encij[threadIdx.x] : make_int2(0, 0);
   if (fl & F_NMIN) return;  // the run stopped below nmin bodies
   // the last workgroup, which rarely has a group of its own, writes the
   // global results
-  const int ng = group_phase<NT>(e, ne_all, L.g, L.gm, blockIdx.x == gridDim.x - 1, pf);
+  const int ng = group_phase<NT>(e, ne_all, L.g, L.gm, blockIdx.x == gridDim.x - 1, &pf);
   bs_groups(a, ng, L.g.gof, L.gm, L.b);
 }
 
