@@ -818,7 +818,7 @@ struct GroupLds {
   int roots[kGroupMaxN / 2];
   int nroot;
   int shw[NT / 64];
-  int s_changed;
+  int chg[2];
 };
 
 // The grouping of ne_all encounter pairs by one workgroup of NT threads;
@@ -836,7 +836,7 @@ __device__ __forceinline__ int group_phase(const EncArgs& a, int ne_all, GroupLd
   int* gsz = L.gsz;
   int* gof = L.gof;
   int* shw = L.shw;
-  int& s_changed = L.s_changed;
+  int* chg = L.chg;
   const int tid = threadIdx.x, lane = tid & 63;
   const int n = a.n;
   const int ne = min(ne_all, a.enc_cap);
@@ -849,7 +849,10 @@ __device__ __forceinline__ int group_phase(const EncArgs& a, int ne_all, GroupLd
   // the opening kick has read the reuse flag; this step's closing kick sets
   // it again for the next one
   if (writer && tid == 0) a.st->ctl = 0u;
-  if (tid == 0) L.nroot = 0;
+  if (tid == 0) {
+    L.nroot = 0;
+    chg[0] = chg[1] = 0;
+  }
   for (int e = tid; e < nl; e += NT) pr[e] = (pf && e == tid) ? *pf : a.encij[e];
   __syncthreads();
   // candidate pairs i < j: every pair sits in both rows (the test is
@@ -865,10 +868,12 @@ __device__ __forceinline__ int group_phase(const EncArgs& a, int ne_all, GroupLd
     link[i] = i;
     first[i] = INT_MAX;
   }
-  // equivalence classes
-  while (true) {
-    if (tid == 0) s_changed = 0;
-    __syncthreads();
+  // equivalence classes; the change flag of sweep k is chg[k & 1], the
+  // other one cleared for the next sweep once every thread is past the
+  // barrier before which it was last read.  The first sweep also notes each
+  // body's first end.
+  __syncthreads();
+  for (int it = 0;; ++it) {
     bool ch = false;
     for (int e = tid; e < ne; e += NT) {
       const int2 q = pair_at(e);
@@ -884,6 +889,7 @@ __device__ __forceinline__ int group_phase(const EncArgs& a, int ne_all, GroupLd
     // pointer jumping over the pairs' ends (links only ever name such bodies)
     for (int t = tid; t < 2 * ne; t += NT) {
       const int i = end_at(t);
+      if (it == 0) atomicMin(&first[i], t);
       const int l = link[i];
       const int ll = link[l];
       if (ll < l) {
@@ -891,14 +897,12 @@ __device__ __forceinline__ int group_phase(const EncArgs& a, int ne_all, GroupLd
         ch = true;
       }
     }
-    if (ch) s_changed = 1;
+    if (ch) chg[it & 1] = 1;
+    if (tid == 0) chg[(it & 1) ^ 1] = 0;
     __syncthreads();
-    if (!s_changed) break;
-    __syncthreads();
+    if (!chg[it & 1]) break;
   }
   // each body once (at its first end), each root once
-  for (int t = tid; t < 2 * ne; t += NT) atomicMin(&first[end_at(t)], t);
-  __syncthreads();
   for (int t = tid; t < 2 * ne; t += NT) {
     const int i = end_at(t);
     if (first[i] == t && link[i] == i) L.roots[atomicAdd(&L.nroot, 1)] = i;
@@ -944,7 +948,7 @@ __device__ __forceinline__ int group_phase(const EncArgs& a, int ne_all, GroupLd
     if (writer) a.goff[ng] = tot;
   }
   int nrow = 0;
-  (void)block_excl_scan<NT>(rows, shw, &nrow);
+  if (writer) (void)block_excl_scan<NT>(rows, shw, &nrow);  // writer: the same for every thread
   mx = wave_max_i(mx);
   __syncthreads();
   if (lane == 0) shw[tid >> 6] = mx;
