@@ -1007,8 +1007,7 @@ struct BsArgs {
   int max_depth, coll, ev_cap;
 };
 
-// The BS kernels (k_group_bs, and k_bs for the composed steps) run kBsWaves
-// waves per workgroup.  Groups of up to kBsPar members
+// k_bs runs kBsWaves waves per workgroup.  Groups of up to kBsPar members
 // without collisions take all of them (speculative depths spread over the
 // waves); every other group is integrated by wave 0 alone while the others
 // wait at the group's closing barrier.  The lanes of that one wave order
