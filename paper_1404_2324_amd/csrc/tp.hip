@@ -5,11 +5,12 @@
 //              the planets' momentum, Kepler drift, Hermite test against the
 //              particle's candidate planets; particles without an encounter
 //              finish the step here (second Sun kick, closing kick, new
-//              candidate mask); the others are compacted into a list
+//              candidate mask); the others are compacted into a list.  One
+//              more block, beside the particles' blocks: each planet's
+//              Gragg sequences and extrapolation over the whole step (it
+//              feels only the star inside a particle's group), the same for
+//              every particle that meets it
 //   k_tp_scan  offsets of each block's listed particles (one workgroup)
-//   k_tp_plan  a planet's Gragg sequences and extrapolation over the whole
-//              step (it feels only the star inside a particle's group), the
-//              same for every particle that meets it
 //   k_tp_bs1   eight lanes (one per extrapolation column) per particle
 //              meeting one planet: the BS attempt over the whole step with
 //              the planet taken from that table; most passages end here
@@ -141,8 +142,12 @@ __device__ __forceinline__ void tp_finish(const TpArgs& a, const double4* __rest
   a.mask[k] = msk;
 }
 
+__device__ void tp_plan(const TpArgs& a);
+
 // The planets' arrays come as kernel arguments of their own: as noalias
-// parameters their wave-uniform loads become scalar loads.
+// parameters their wave-uniform loads become scalar loads.  A block past
+// the particles' nb blocks (launched with encounters) builds the planets'
+// whole-step table instead, beside the particles' work.
 __global__ __launch_bounds__(256) void k_tp_main(TpArgs a, const double4* __restrict__ px0,
                                                  const double4* __restrict__ pfin,
                                                  const double4* __restrict__ ppre,
@@ -150,6 +155,10 @@ __global__ __launch_bounds__(256) void k_tp_main(TpArgs a, const double4* __rest
                                                  const double4* __restrict__ ppost,
                                                  const double4* __restrict__ vpost,
                                                  const double* __restrict__ prc) {
+  if ((int64_t)blockIdx.x >= a.nb) {  // the extra block (uniform over the workgroup)
+    tp_plan(a);
+    return;
+  }
   __shared__ unsigned kh[kKepBins];  // this block's drifts by iteration count
   if (threadIdx.x < kKepBins) kh[threadIdx.x] = 0u;
   __syncthreads();
@@ -373,7 +382,7 @@ __device__ __forceinline__ void star_acc(double Gm0, double x, double y, double 
 
 // One thread per (planet, column): the planet's Gragg sequence over the whole
 // step from its pre-drift state; then one thread per planet extrapolates.
-__global__ __launch_bounds__(256) void k_tp_plan(TpArgs a) {
+__device__ void tp_plan(const TpArgs& a) {
   __shared__ double sT0[kTpMaxPlanets * 8][6];
   const int j = threadIdx.x >> 3, k = threadIdx.x & 7;
   if (j < a.nm) {
@@ -965,13 +974,13 @@ hipError_t tp_prime(const MassiveWs& w, const TpWs& t, const StepConsts& c, hipS
 hipError_t tp_step(const MassiveWs& w, const TpWs& t, const StepConsts& c, hipStream_t s) {
   if (t.ntp <= 0) return hipSuccess;
   TpArgs a = tp_args(w, t, c);
-  hipLaunchKernelGGL(k_tp_main, dim3((unsigned)t.nb), dim3(256), 0, s, a,
+  // with encounters, one block more: the planets' whole-step table
+  hipLaunchKernelGGL(k_tp_main, dim3((unsigned)(t.nb + (c.encounter_free ? 0 : 1))), dim3(256), 0, s, a,
                      (const double4*)a.px0, (const double4*)a.pfin, (const double4*)a.ppre,
                      (const double4*)a.vpre, (const double4*)a.ppost, (const double4*)a.vpost,
                      (const double*)a.rc);
   if (!c.encounter_free) {
     hipLaunchKernelGGL(k_tp_scan, dim3(1), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(k_tp_plan, dim3(1), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_tp_bs1, dim3(kTpBs1Grid), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_tp_bs, dim3(kTpBsGrid), dim3(64), 0, s, a);
   }
