@@ -800,10 +800,11 @@ __global__ __launch_bounds__(256) void k_encounter_all(EncArgs a) {
 // LINK[LINK[i]], and both sweeps repeat until nothing changes.  Groups are
 // numbered by their smallest member (the rank of each component's root
 // among the roots); offsets and members go to global memory for the BS
-// kernel (and, with gm, to LDS).  Every loop runs over the pairs or their
-// ends, not over the bodies: a step has tens of pairs among thousands of
-// bodies.  The writing workgroup also clears the candidate table for the
-// closing kick, counts its pairs and sets the step's group statistics.
+// kernel (and, with gm, to LDS).  Every loop of the grouping runs over the
+// pairs or their ends, not over the bodies: a step has tens of pairs among
+// thousands of bodies.  The writing workgroup also clears the candidate
+// table for the closing kick (a loop over the bodies), counts its pairs and
+// sets the step's group statistics.
 // The first kEncLds pairs are held in LDS; pairs beyond (many-pair regimes,
 // up to the list capacity) are read from the encounter list in place, so
 // the workgroup's LINK array, not the pair count, bounds the grouping.
@@ -1007,7 +1008,8 @@ struct BsArgs {
   int max_depth, coll, ev_cap;
 };
 
-// k_bs runs kBsWaves waves per workgroup.  Groups of up to kBsPar members
+// The BS kernels (k_group_bs, and k_bs for the composed steps) run kBsWaves
+// waves per workgroup.  Groups of up to kBsPar members
 // without collisions take all of them (speculative depths spread over the
 // waves); every other group is integrated by wave 0 alone while the others
 // wait at the group's closing barrier.  The lanes of that one wave order
