@@ -32,12 +32,29 @@ FLOPS_PER_PAIR = 18              # 3 sub, 5 for r^2, sqrt, r^2 r, div, m/r^3, 3 
 N_BODIES = 2048
 
 
-def _kernel_source_hash() -> str:
+def _kernel_source_hash(files=("device_math.h", "massive.hip", "genga_impl.h")) -> str:
     h = hashlib.sha256()
-    for f in ("device_math.h", "massive.hip", "genga_impl.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1404_2324_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+TP_SOURCES = ("device_math.h", "bs_device.h", "tp.hip", "genga_impl.h")
+
+
+def _tp_traffic_per_step():
+    """HBM bytes per test-particle step (the particle kernels) and per
+    k_tp_main launch from the committed counter summary, or None when their
+    source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "tp_step_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != _kernel_source_hash(TP_SOURCES):
+        return None
+    return d
 
 
 def _traffic_per_launch():
@@ -126,7 +143,18 @@ def tp_measure(G, W, torch, steps: int, ntp: int = 1_000_000):
             "algorithmic_GBps": TP_BYTES * ntp * steps / sec / 1e9,
             "hbm_frac": TP_BYTES * ntp * steps / sec / 1e9 / HBM_PEAK_GBS,
             "tp_enc_last_step": st["tp_enc"], "bs_substeps": st["bs_substeps"],
-            "removed": st["tp_removed"]}
+            "removed": st["tp_removed"], "counters": _tp_counter_rates(sec / steps)}
+
+
+def _tp_counter_rates(step_s: float):
+    """HBM traffic of the particle kernels from rocprofv3 FETCH_SIZE and
+    WRITE_SIZE (profiles/tp_step_traffic.json), over this run's step time."""
+    d = _tp_traffic_per_step()
+    if d is None:
+        return None
+    return {"bytes_per_step": d["bytes_per_step"], "k_tp_main_bytes": d["k_tp_main_bytes"],
+            "GBps": d["bytes_per_step"] / step_s / 1e9,
+            "hbm_frac": d["bytes_per_step"] / step_s / 1e9 / HBM_PEAK_GBS}
 
 
 def energy_measure(G, W, torch, steps: int = 1000, every: int = 10):
